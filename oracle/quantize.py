@@ -1,0 +1,121 @@
+"""Error bound -> level-wise quantisation bins; quantiser; symbols (oracle).
+
+TEST INFRASTRUCTURE ONLY.
+
+The paper quantises the multilevel coefficients linearly with a different bin
+size per level (Section IV-A) so that the user's error bound holds after
+reconstruction; it gives no constants.  The bins used here come from the
+linearity of recomposition: with quantisation errors delta_l (|delta| <= q_l/2
+per entry), the reconstruction error is R(delta) = delta_0 +
+sum_{l>=1} (I - Q_{l-1}) delta_l, with Q_{l-1} the L2 projection onto level l-1.
+
+* L-infinity: ||(I - Q_{l-1}) d||_inf <= (1 + 3^D) ||d||_inf because, per axis,
+  ||M_{l-1}^{-1} P^T M_l||_inf <= 3 for any spacing (the diagonal part of
+  M_{l-1} dominates its off-diagonal part 2:1, and each row of P^T M_l sums
+  to 3/2 of that diagonal) and interpolation never increases a maximum.  One
+  bin for all levels:  q = 2 tau' / (1 + L (1 + 3^D)).
+* L2 (discrete, over all nodes): the terms of R(delta) are L2-orthogonal
+  across levels, projections do not increase the L2 norm, the input-grid mass
+  matrix has lambda_min >= 6^-D and level l's has lambda_max <= prod_d h_max.
+  Giving each of the L + 1 levels an equal share of tau'^2:
+  q_l = 2 tau' / sqrt(6^D (L+1) prod_d hmax_{l,d} m_l), m_l = entries of level l.
+
+``tau`` is the absolute bound: for a relative L-inf bound rel * (max - min),
+for a relative L2 bound rel * ||u||_2.  ``tau'`` keeps a margin for rounding
+the result to the output type (unit roundoff eps_out) and for FP64 arithmetic:
+tau' = tau - (eps_out + 2^-36) (A + tau) with A = max|u| (L-inf) or
+sqrt(N) max|u| (L2).  Bins are computed in FP64 with the operation order
+written in ``level_bins``; quantisation is k = rint(c * (1/q_l)) in FP64, round
+half to even; dequantisation is k * q_l in FP64.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .hierarchy import Hierarchy
+from .transform import level_slices
+
+EPS_OUT = {np.dtype(np.float32): 2.0 ** -24, np.dtype(np.float64): 2.0 ** -53}
+FP64_MARGIN = 2.0 ** -36
+S_DEFAULT = 65536
+
+
+def error_budget(u: np.ndarray, bound: float, norm: str, mode: str):
+    """Return (tau, tau_eff) for input ``u``.  norm in {linf, l2}; mode in {rel, abs}."""
+    u = np.asarray(u)
+    eps = EPS_OUT[np.dtype(u.dtype)]
+    x = u.astype(np.float64).ravel()
+    if x.size == 0:
+        return 0.0, 0.0
+    amax = float(max(abs(float(x.max())), abs(float(x.min()))))
+    if norm == "linf":
+        tau = bound * (float(x.max()) - float(x.min())) if mode == "rel" else float(bound)
+        A = amax
+    elif norm == "l2":
+        tau = bound * float(np.sqrt(np.dot(x, x))) if mode == "rel" else float(bound)
+        A = float(np.sqrt(np.float64(x.size))) * amax
+    else:
+        raise ValueError(norm)
+    tau_eff = tau - (eps + FP64_MARGIN) * (A + tau)
+    return float(tau), float(tau_eff)
+
+
+def level_bins(h: Hierarchy, tau_eff: float, norm: str):
+    """q_l for l = 0..L (FP64, fixed operation order)."""
+    D, L = h.D, h.L
+    q = []
+    for l in range(L + 1):
+        if norm == "linf":
+            K = 2.0 / float(1 + L * (1 + 3 ** D))
+        else:
+            den = float(6 ** D) * float(L + 1)
+            for hm in h.max_spacing(l):
+                den = den * hm
+            den = den * float(h.level_count(l))
+            K = 2.0 / float(np.sqrt(den))
+        q.append(tau_eff * K)
+    return np.asarray(q, dtype=np.float64)
+
+
+def quantize(stream: np.ndarray, h: Hierarchy, q: np.ndarray) -> np.ndarray:
+    """k = rint(c * r_l) per level, r_l = 1 / q_l; int64."""
+    k = np.empty(len(stream), dtype=np.int64)
+    for l, (a, b) in enumerate(level_slices(h)):
+        r = 1.0 / q[l]
+        t = np.rint(stream[a:b] * r)
+        if t.size and np.max(np.abs(t)) >= 2.0 ** 62:
+            raise OverflowError("quantised value out of range")
+        k[a:b] = t.astype(np.int64)
+    return k
+
+
+def dequantize(k: np.ndarray, h: Hierarchy, q: np.ndarray) -> np.ndarray:
+    out = np.empty(len(k), dtype=np.float64)
+    for l, (a, b) in enumerate(level_slices(h)):
+        out[a:b] = k[a:b].astype(np.float64) * q[l]
+    return out
+
+
+def to_symbols(k: np.ndarray, S: int = S_DEFAULT):
+    """Dictionary symbols and outliers.
+
+    |k| < S/2 -> symbol k + S/2 (1 .. S-1); otherwise escape symbol 0 plus an
+    outlier record (stream position, k), records in ascending position.
+    """
+    half = S // 2
+    esc = np.abs(k) >= half
+    sym = np.where(esc, 0, k + half).astype(np.uint16 if S <= 65536 else np.uint32)
+    pos = np.nonzero(esc)[0].astype(np.uint64)
+    return sym, pos, k[esc].astype(np.int64)
+
+
+def from_symbols(sym: np.ndarray, pos: np.ndarray, vals: np.ndarray, S: int = S_DEFAULT):
+    half = S // 2
+    k = sym.astype(np.int64) - half
+    if len(pos):
+        if np.any(sym[pos.astype(np.int64)] != 0):
+            raise ValueError("outlier position does not hold the escape symbol")
+        k[pos.astype(np.int64)] = vals
+    if np.any(sym == 0) and np.count_nonzero(sym == 0) != len(pos):
+        raise ValueError("escape symbols without outlier records")
+    return k
