@@ -143,8 +143,12 @@ def decode_tables(lengths: np.ndarray):
 
 
 def decode_chunks(words: np.ndarray, offsets: np.ndarray, lengths: np.ndarray,
-                  N: int, C: int) -> np.ndarray:
-    """Decode N symbols; all chunks advance together, one symbol per step."""
+                  N: int, C: int, chunks=None) -> np.ndarray:
+    """Decode N symbols; all chunks advance together, one symbol per step.
+
+    With ``chunks`` (chunk indices) only those chunks are decoded; the other
+    entries of the result stay 0.
+    """
     out = np.zeros(N, dtype=np.int64)
     if N == 0:
         return out
@@ -153,6 +157,10 @@ def decode_chunks(words: np.ndarray, offsets: np.ndarray, lengths: np.ndarray,
     w = np.concatenate([words.astype(np.uint64), np.zeros(2, dtype=np.uint64)])
     bitpos = offsets[:n_chunks].astype(np.int64) * 32
     chunk_len = np.minimum(C, N - np.arange(n_chunks) * C)
+    if chunks is not None:
+        keep = np.zeros(n_chunks, dtype=bool)
+        keep[np.asarray(chunks, dtype=np.int64)] = True
+        chunk_len = np.where(keep, chunk_len, 0)
     for s in range(C):
         act = np.nonzero(chunk_len > s)[0]
         if len(act) == 0:

@@ -154,8 +154,11 @@ def compress(u: np.ndarray, bound: float, norm: str = "linf", mode: str = "rel",
     return bytes(out)
 
 
-def decode_symbols(buf: bytes, hd: dict | None = None):
-    """The stream's symbols and outliers (no dequantisation)."""
+def decode_symbols(buf: bytes, hd: dict | None = None, chunks=None):
+    """The stream's symbols and outliers (no dequantisation).
+
+    With ``chunks`` only those chunks of symbols are decoded (others read 0).
+    """
     hd = hd or parse_header(buf)
     cb, off, o_pos, o_val, w_off, end = section_offsets(
         hd["L"], hd["n_codes"], hd["n_chunks"], hd["n_outliers"], hd["n_words"])
@@ -170,7 +173,7 @@ def decode_symbols(buf: bytes, hd: dict | None = None):
     opos = np.frombuffer(buf, "<u8", hd["n_outliers"], o_pos)
     oval = np.frombuffer(buf, "<i8", hd["n_outliers"], o_val)
     words = np.frombuffer(buf, "<u4", hd["n_words"], w_off)
-    sym = decode_chunks(words, offsets, lengths, hd["N"], hd["C"])
+    sym = decode_chunks(words, offsets, lengths, hd["N"], hd["C"], chunks)
     return sym, opos, oval
 
 

@@ -198,3 +198,57 @@ def recompose_adjoint(grad_u: np.ndarray, h: Hierarchy) -> np.ndarray:
         g = gc
     per_level[0] = np.asarray(g, dtype=np.float64).ravel()
     return np.concatenate(per_level) if h.N else np.zeros(0)
+
+
+def finest_coefficients_at(u: np.ndarray, h: Hierarchy, flat_idx):
+    """Finest-level coefficients at the given flat input indices, one by one.
+
+    For each index that is a new node of the input grid: the value minus the
+    multilinear interpolant from its nearest coarse neighbours on each axis
+    where it is new (the lerp step), and its stream position.  Indices of
+    coarse nodes are skipped.  Returns (stream positions, coefficients).
+    """
+    sizes = h.sizes[h.L]
+    ua = np.asarray(u).reshape(sizes)
+    l = h.L
+    sl = level_slices(h)
+    sub_sets = {}
+    sub_off = {}
+    acc = sl[l][0]
+    for m in range(1, 1 << h.D):
+        sets = _subband_index_sets(sizes, m)
+        sub_sets[m] = sets
+        sub_off[m] = acc
+        acc += int(np.prod([len(x) for x in sets], dtype=np.int64))
+    cpos = [coarse_positions(n) for n in sizes]
+    pos_out, c_out = [], []
+    for fi in flat_idx:
+        idx = np.unravel_index(int(fi), sizes)
+        m = 0
+        taps = []
+        for d, i in enumerate(idx):
+            x = h.coords[l][d]
+            if i in set(cpos[d].tolist()):
+                taps.append([(i, 1.0)])
+            else:
+                m |= 1 << d
+                k = int(np.searchsorted(cpos[d], i))
+                a, b = int(cpos[d][k - 1]), int(cpos[d][k])
+                taps.append([(a, (x[b] - x[i]) / (x[b] - x[a])), (b, (x[i] - x[a]) / (x[b] - x[a]))])
+        if m == 0:
+            continue
+        interp = 0.0
+        for corner in np.ndindex(*[len(t) for t in taps]):
+            w = 1.0
+            where = []
+            for d, c in enumerate(corner):
+                where.append(taps[d][c][0])
+                w *= taps[d][c][1]
+            interp += w * float(ua[tuple(where)])
+        c = float(ua[idx]) - interp
+        sets = sub_sets[m]
+        loc = [int(np.searchsorted(sets[d], idx[d])) for d in range(h.D)]
+        pos = sub_off[m] + int(np.ravel_multi_index(loc, [len(x) for x in sets]))
+        pos_out.append(pos)
+        c_out.append(c)
+    return np.asarray(pos_out, dtype=np.int64), np.asarray(c_out)

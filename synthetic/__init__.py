@@ -108,12 +108,13 @@ def sinusoids(shape, seed: int, n_waves: int = 64, kmax: int = 200,
     ph = rng.uniform(0.0, 2 * np.pi, size=n_waves)
     y = _axis_coords(ny)
     x = _axis_coords(nx)
-    u = np.zeros((ny, nx), dtype=np.float64)
-    for m in range(n_waves):
-        a = 2 * np.pi * ks[m] * np.cos(th[m]) * y + ph[m]
-        b = 2 * np.pi * ks[m] * np.sin(th[m]) * x
-        u += (1.0 / ks[m]) * (np.outer(np.sin(a), np.cos(b)) + np.outer(np.cos(a), np.sin(b)))
-    return u.astype(dtype)
+    a = 2 * np.pi * ks[None, :] * np.cos(th)[None, :] * y[:, None] + ph[None, :]
+    b = 2 * np.pi * ks[None, :] * np.sin(th)[None, :] * x[:, None]
+    amp = 1.0 / ks
+    # sum_m amp_m (sin a_m cos b_m + cos a_m sin b_m) as one matrix product
+    left = np.concatenate([np.sin(a) * amp, np.cos(a) * amp], axis=1)
+    right = np.concatenate([np.cos(b), np.sin(b)], axis=1)
+    return (left @ right.T).astype(dtype)
 
 
 def batch_specs(n_arrays: int = 256, seed: int = 5,

@@ -9,3 +9,15 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+import pytest  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name each GPU test on the real stderr before it touches the device."""
+    if request.node.get_closest_marker("gpu") is not None:
+        sys.__stderr__.write("\n[gpu case] %s\n" % request.node.nodeid)
+        sys.__stderr__.flush()
+    yield
