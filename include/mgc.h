@@ -1,0 +1,170 @@
+/*
+ * mgc.h - C ABI of the MI355X multigrid error-bounded lossy compressor.
+ *
+ * The library implements the MGARD reduction pipeline described in Section
+ * IV-A and Algorithm 1 of "HPDR: High-Performance Portable Scientific Data
+ * Reduction Framework" (arXiv 2503.06322): a multilevel decomposition
+ * (interpolation coefficients, a transfer/mass-matrix product and
+ * tridiagonal correction solves along each dimension, the add), level-wise
+ * linear quantisation, and Huffman entropy coding (Section IV-B, Algorithm 2).
+ * Decompression runs the inverse.  Every stage runs in HIP kernels on one
+ * gfx950 GPU.
+ *
+ * Conventions (all entry points):
+ *  - Every function returns an mgc_status; nothing throws across the ABI.
+ *    A failure leaves a thread-local message readable with mgc_last_error().
+ *  - Pointers named d_* are device pointers; h_* are host pointers.  All
+ *    device memory (inputs, outputs, workspaces) is owned by the caller; the
+ *    library never frees it.  A context owns only its cached plan tables
+ *    (small device tables, freed by mgc_destroy) and a small pinned buffer.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Kernels are enqueued on it in order.  Entry points marked BLOCKING
+ *    synchronise that stream before returning.
+ *  - Arrays are dense, row-major (last axis fastest), 1 to 3 axes; axes of
+ *    length 1 are squeezed out.  dtype is float32 or float64.  Arithmetic is
+ *    FP64 throughout (inputs are read and outputs written in their dtype).
+ *  - Sizes: at most 2^32 - 1 values per array.
+ *  - Calls on one context from several host threads must be serialised by
+ *    the caller; distinct contexts are independent.
+ */
+#ifndef MGC_H
+#define MGC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MGC_OK = 0,
+  MGC_EINVAL = 1,       /* bad argument: shape, dtype, bound, NaN/Inf input */
+  MGC_EUNSUPPORTED = 2, /* valid request this build does not handle (ndim > 3, N >= 2^32) */
+  MGC_ENOSPC = 3,       /* output or workspace too small (see mgc_last_error) */
+  MGC_EFORMAT = 4,      /* truncated or corrupt compressed stream */
+  MGC_EDEVICE = 5,      /* a HIP runtime call failed */
+  MGC_ERANGE = 6        /* bound too small for the data (quantised value >= 2^62,
+                           or the budget vanishes below the output precision) */
+} mgc_status;
+
+typedef enum { MGC_F32 = 0, MGC_F64 = 1 } mgc_dtype;
+typedef enum { MGC_LINF = 0, MGC_L2 = 1 } mgc_norm;
+typedef enum { MGC_REL = 0, MGC_ABS = 1 } mgc_mode;
+
+typedef struct mgc_ctx_s* mgc_ctx;
+
+/* Context = per-device plan cache (the paper's context-memory cache,
+ * Section III-B: reduction contexts are built once per shape and reused).
+ * `device` is the HIP device ordinal; it is made current by every call. */
+mgc_status mgc_create(int device, mgc_ctx* out);
+mgc_status mgc_destroy(mgc_ctx ctx);
+const char* mgc_last_error(void);
+int mgc_version(void);
+
+/* ------------------------------------------------------------------------
+ * Compression (Algorithm 1 end to end: hierarchy, decomposition, level-wise
+ * quantisation, Huffman).
+ *
+ * mgc_compress_query: workspace and worst-case output bytes for an array of
+ *   `shape` (ndim entries) and dtype, with room for `outlier_cap` escaped
+ *   values (0 = default, max(65536, N/4)).
+ * mgc_compress (BLOCKING): compresses d_in into d_out and stores the stream
+ *   length in *h_out_size.  error_bound > 0 is relative (to max - min for
+ *   L-inf, to ||u||_2 for L2) when mode == MGC_REL, absolute otherwise; the
+ *   reconstruction error in that norm is at most the bound.  out_cap and
+ *   ws_bytes must be at least the queried sizes for the same outlier_cap
+ *   (MGC_ENOSPC otherwise).  If more values escape the dictionary than
+ *   outlier_cap, MGC_ENOSPC is returned and *h_out_size holds the number of
+ *   escaped values needed; calling again with that capacity succeeds.
+ *   Errors: MGC_EINVAL (shape, dtype, bound, NaN/Inf in the data),
+ *   MGC_ERANGE, MGC_ENOSPC, MGC_EDEVICE.
+ *
+ * Stream layout (little-endian): a 128-byte header, the per-level bins
+ * q_0..q_L (f64), then, unless the array is constant or empty, the codebook
+ * (u16 symbols ascending, then u8 code lengths), the chunk word offsets
+ * (u64, n_chunks + 1), the escaped values' stream positions (u64, ascending)
+ * and values (i64), and the coded 32-bit words; each section starts at a
+ * multiple of 8 bytes.
+ * ---------------------------------------------------------------------- */
+mgc_status mgc_compress_query(int ndim, const uint64_t* shape, mgc_dtype dtype,
+                              uint64_t outlier_cap, size_t* ws_bytes,
+                              size_t* max_out_bytes);
+mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                        mgc_dtype dtype, double error_bound, mgc_norm norm,
+                        mgc_mode mode, uint64_t outlier_cap, void* d_out,
+                        size_t out_cap, void* d_ws, size_t ws_bytes, void* stream,
+                        uint64_t* h_out_size);
+
+/* ------------------------------------------------------------------------
+ * Decompression (inverse of the above).
+ *
+ * mgc_header_info: parses a host copy of the first bytes of a stream (at least
+ *   128 + 8 * (L + 1); 1024 always suffices) and returns the array's ndim,
+ *   shape (3 entries, unused = 0), dtype, the stream length and the
+ *   decompression workspace size.  Errors: MGC_EFORMAT.
+ * mgc_decompress (BLOCKING: it reads the header from the device): writes the
+ *   reconstructed array (dtype and shape of the header) to d_out.
+ *   Errors: MGC_EFORMAT, MGC_ENOSPC (out_cap/ws_bytes), MGC_EDEVICE.
+ * ---------------------------------------------------------------------- */
+mgc_status mgc_header_info(const void* h_prefix, size_t n, int* ndim, uint64_t* shape3,
+                           mgc_dtype* dtype, uint64_t* stream_bytes, size_t* ws_bytes);
+mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* d_out,
+                          size_t out_cap, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Transform only (Algorithm 1 without quantisation): the multilevel
+ * coefficients as FP64 values in stream order - the coarsest level's nodal
+ * values row-major, then for each finer level its 2^D - 1 subbands (subband
+ * m holds the level's new nodes along active axis d when bit d of m is set,
+ * its coarse nodes otherwise; axis 0 is the slowest), each row-major.
+ * d_coeffs holds N doubles.  Asynchronous on `stream`.
+ * Errors: MGC_EINVAL, MGC_ENOSPC (ws_bytes), MGC_EDEVICE.
+ * ---------------------------------------------------------------------- */
+mgc_status mgc_transform_query(int ndim, const uint64_t* shape, size_t* ws_bytes);
+mgc_status mgc_decompose(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                         mgc_dtype dtype, double* d_coeffs, void* d_ws, size_t ws_bytes,
+                         void* stream);
+mgc_status mgc_recompose(mgc_ctx ctx, const double* d_coeffs, int ndim,
+                         const uint64_t* shape, mgc_dtype out_dtype, void* d_out,
+                         void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Huffman stage alone (Algorithm 2) on n 16-bit symbols, chunk size C
+ * (multiple of 64, 64..65536).  Stream: u32 magic 0x3148474D, u32 C,
+ * u64 N, n_codes, n_chunks, n_words, total bytes (48-byte header), then the
+ * codebook, chunk offsets and words sections laid out as in the compressed
+ * stream.  Code lengths come from the two-queue construction with ties taken
+ * from the leaf queue (length limit 32 by halving frequencies), codes are
+ * canonical, and codes are packed most-significant bit first into 32-bit
+ * words, each chunk starting on a word boundary.
+ * mgc_huffman_encode is BLOCKING (returns the length in *h_out_size).
+ * mgc_huffman_decode writes n symbols to d_sym (asynchronous after a
+ * blocking read of the 48-byte header).
+ * Errors: MGC_EINVAL, MGC_ENOSPC, MGC_EFORMAT, MGC_EDEVICE.
+ * ---------------------------------------------------------------------- */
+mgc_status mgc_huffman_query(uint64_t n, uint32_t C, size_t* ws_bytes, size_t* max_out_bytes);
+mgc_status mgc_huffman_encode(mgc_ctx ctx, const uint16_t* d_sym, uint64_t n, uint32_t C,
+                              void* d_out, size_t out_cap, void* d_ws, size_t ws_bytes,
+                              void* stream, uint64_t* h_out_size);
+mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes,
+                              uint16_t* d_sym, uint64_t n, void* d_ws, size_t ws_bytes,
+                              void* stream);
+
+/* ------------------------------------------------------------------------
+ * Stage timing.  When enabled, every entry point records HIP events around
+ * each kernel launch on its stream; mgc_profile_read returns, per stage
+ * name, the number of launches and their total GPU milliseconds accumulated
+ * since the last reset (reading synchronises the recorded events).
+ * `names` receives a '\n'-separated list (at most names_cap bytes); counts
+ * and ms receive up to `cap` entries in the same order.
+ * ---------------------------------------------------------------------- */
+mgc_status mgc_profile_enable(mgc_ctx ctx, int enable);
+mgc_status mgc_profile_reset(mgc_ctx ctx);
+mgc_status mgc_profile_read(mgc_ctx ctx, char* names, size_t names_cap, uint64_t* counts,
+                            double* ms, int cap, int* n_stages);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGC_H */

@@ -1,0 +1,327 @@
+"""MI355X multigrid error-bounded lossy compressor: Python binding of libmgc.
+
+Thin ctypes layer over the C ABI declared in ``include/mgc.h``.  It only
+marshals arguments: every stage runs in the HIP kernels of ``libmgc.so``;
+PyTorch provides device memory and the current stream.  There is no CPU
+fallback: calling any entry point without the built library or with tensors
+that are not on a GPU raises.
+
+Entry points (same names as the C functions, without the ``mgc_`` prefix):
+
+``compress(x, error_bound, norm="linf", mode="rel")``  -> uint8 device tensor
+``decompress(stream)``                                   -> device tensor
+``decompose(x)`` / ``recompose(coeffs, shape, dtype)``   (FP64 coefficients)
+``huffman_encode(symbols, C=1024)`` / ``huffman_decode(stream, n)``
+``header_info(stream)``, ``profile_enable / profile_reset / profile_read``
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = ["MgcError", "library_path", "compress", "decompress", "decompose", "recompose",
+           "huffman_encode", "huffman_decode", "header_info", "profile_enable",
+           "profile_reset", "profile_read", "compress_query", "transform_query"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmgc.so")
+_lib = None
+_lock = threading.Lock()
+_ctxs = {}
+
+_STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSUPPORTED", 3: "ENOSPC", 4: "EFORMAT",
+           5: "EDEVICE", 6: "ERANGE"}
+_NORM = {"linf": 0, "l2": 1}
+_MODE = {"rel": 0, "abs": 1}
+HEADER_PREFIX = 128 + 8 * 63
+
+
+class MgcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), message))
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError("libmgc.so is not built; run `python -m paper_2503_06322_amd.build`")
+        lib = ctypes.CDLL(_LIB_PATH)
+        c_u64p = ctypes.POINTER(ctypes.c_uint64)
+        c_szp = ctypes.POINTER(ctypes.c_size_t)
+        vp = ctypes.c_void_p
+        sig = {
+            "mgc_create": [ctypes.c_int, ctypes.POINTER(vp)],
+            "mgc_destroy": [vp],
+            "mgc_compress_query": [ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_uint64, c_szp, c_szp],
+            "mgc_compress": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_double,
+                             ctypes.c_int, ctypes.c_int, ctypes.c_uint64, vp, ctypes.c_size_t,
+                             vp, ctypes.c_size_t, vp, c_u64p],
+            "mgc_header_info": [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), c_u64p,
+                                ctypes.POINTER(ctypes.c_int), c_u64p, c_szp],
+            "mgc_decompress": [vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp],
+            "mgc_transform_query": [ctypes.c_int, c_u64p, c_szp],
+            "mgc_decompose": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, vp, vp, ctypes.c_size_t, vp],
+            "mgc_recompose": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, vp, vp, ctypes.c_size_t, vp],
+            "mgc_huffman_query": [ctypes.c_uint64, ctypes.c_uint32, c_szp, c_szp],
+            "mgc_huffman_encode": [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_size_t,
+                                   vp, ctypes.c_size_t, vp, c_u64p],
+            "mgc_huffman_decode": [vp, vp, ctypes.c_size_t, vp, ctypes.c_uint64, vp,
+                                   ctypes.c_size_t, vp],
+            "mgc_profile_enable": [vp, ctypes.c_int],
+            "mgc_profile_reset": [vp],
+            "mgc_profile_read": [vp, ctypes.c_char_p, ctypes.c_size_t, c_u64p,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_int)],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.mgc_last_error.restype = ctypes.c_char_p
+        lib.mgc_last_error.argtypes = []
+        lib.mgc_version.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _check(st: int):
+    if st != 0:
+        msg = _load().mgc_last_error()
+        raise MgcError(st, msg.decode() if msg else "")
+
+
+def _ctx(device: int):
+    lib = _load()
+    with _lock:
+        h = _ctxs.get(device)
+        if h is None:
+            h = ctypes.c_void_p()
+            _check(lib.mgc_create(device, ctypes.byref(h)))
+            _ctxs[device] = h
+        return h
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _shape_arg(shape):
+    arr = (ctypes.c_uint64 * max(len(shape), 1))(*[int(s) for s in shape])
+    return arr
+
+
+def _dtype_code(dt) -> int:
+    torch = _torch()
+    if dt == torch.float32:
+        return 0
+    if dt == torch.float64:
+        return 1
+    raise TypeError("only float32 and float64 tensors are supported")
+
+
+def _require_gpu(t, what):
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor (no CPU path exists)" % what)
+
+
+def _empty(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def compress_query(shape, dtype, outlier_cap: int = 0):
+    ws = ctypes.c_size_t()
+    mx = ctypes.c_size_t()
+    _check(_load().mgc_compress_query(len(shape), _shape_arg(shape), _dtype_code(dtype),
+                                      outlier_cap, ctypes.byref(ws), ctypes.byref(mx)))
+    return ws.value, mx.value
+
+
+def compress(x, error_bound: float, norm: str = "linf", mode: str = "rel",
+             outlier_cap: int = 0, workspace=None, out=None):
+    """Compress a 1-3D float32/float64 GPU tensor; returns a uint8 GPU tensor.
+
+    The reconstruction error is at most ``error_bound`` in the chosen norm
+    (relative to max-min for L-inf or to ||x||_2 for L2 when mode="rel").
+    ``workspace``/``out`` may be preallocated uint8 tensors of the queried
+    sizes; the returned tensor is a view into ``out``.
+    """
+    _require_gpu(x, "input")
+    x = x.contiguous()
+    dev = x.device.index if x.device.index is not None else _torch().cuda.current_device()
+    lib = _load()
+    ctx = _ctx(dev)
+    shape = tuple(x.shape)
+    for _ in range(2):
+        ws_n, out_n = compress_query(shape, x.dtype, outlier_cap)
+        ws = workspace if workspace is not None and workspace.numel() >= ws_n else _empty(ws_n, x.device)
+        ob = out if out is not None and out.numel() >= out_n else _empty(out_n, x.device)
+        size = ctypes.c_uint64()
+        st = lib.mgc_compress(ctx, ctypes.c_void_p(x.data_ptr()), len(shape), _shape_arg(shape),
+                              _dtype_code(x.dtype), float(error_bound), _NORM[norm], _MODE[mode],
+                              outlier_cap, ctypes.c_void_p(ob.data_ptr()), ob.numel(),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(dev),
+                              ctypes.byref(size))
+        if st == 3 and size.value > outlier_cap and size.value > 0:
+            outlier_cap = int(size.value)   # more escaped values than room: retry once
+            continue
+        _check(st)
+        return ob[: size.value]
+    _check(st)
+
+
+def header_info(stream):
+    """Shape, dtype and sizes of a compressed stream (reads its header)."""
+    import numpy as np
+    n = min(int(stream.numel()), HEADER_PREFIX)
+    host = stream[:n].cpu().numpy() if stream.is_cuda else np.asarray(stream[:n])
+    buf = np.ascontiguousarray(host, dtype=np.uint8)
+    ndim = ctypes.c_int()
+    shp = (ctypes.c_uint64 * 3)()
+    dt = ctypes.c_int()
+    total = ctypes.c_uint64()
+    ws = ctypes.c_size_t()
+    _check(_load().mgc_header_info(buf.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(ndim), shp,
+                                   ctypes.byref(dt), ctypes.byref(total), ctypes.byref(ws)))
+    torch = _torch()
+    return {"shape": tuple(int(shp[i]) for i in range(ndim.value)),
+            "dtype": torch.float32 if dt.value == 0 else torch.float64,
+            "stream_bytes": int(total.value), "workspace_bytes": int(ws.value)}
+
+
+def decompress(stream, workspace=None, out=None):
+    """Reconstruct the array held in a compressed GPU stream."""
+    _require_gpu(stream, "stream")
+    torch = _torch()
+    dev = stream.device.index if stream.device.index is not None else torch.cuda.current_device()
+    info = header_info(stream)
+    res = out if out is not None else torch.empty(info["shape"], dtype=info["dtype"], device=stream.device)
+    ws = workspace if workspace is not None and workspace.numel() >= info["workspace_bytes"] \
+        else _empty(info["workspace_bytes"], stream.device)
+    stream = stream.contiguous()
+    _check(_load().mgc_decompress(_ctx(dev), ctypes.c_void_p(stream.data_ptr()), stream.numel(),
+                                  ctypes.c_void_p(res.data_ptr()), res.numel() * res.element_size(),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(dev)))
+    return res
+
+
+def transform_query(shape) -> int:
+    ws = ctypes.c_size_t()
+    _check(_load().mgc_transform_query(len(shape), _shape_arg(shape), ctypes.byref(ws)))
+    return ws.value
+
+
+def decompose(x, workspace=None):
+    """Multilevel coefficients (FP64, stream order) of a 1-3D GPU tensor."""
+    _require_gpu(x, "input")
+    torch = _torch()
+    x = x.contiguous()
+    dev = x.device.index if x.device.index is not None else torch.cuda.current_device()
+    shape = tuple(x.shape)
+    ws_n = transform_query(shape)
+    ws = workspace if workspace is not None and workspace.numel() >= ws_n else _empty(ws_n, x.device)
+    out = torch.empty(x.numel(), dtype=torch.float64, device=x.device)
+    _check(_load().mgc_decompose(_ctx(dev), ctypes.c_void_p(x.data_ptr()), len(shape),
+                                 _shape_arg(shape), _dtype_code(x.dtype),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), _stream_ptr(dev)))
+    return out
+
+
+def recompose(coeffs, shape, dtype=None, workspace=None):
+    """Inverse of decompose: nodal values of ``shape`` from FP64 coefficients."""
+    _require_gpu(coeffs, "coefficients")
+    torch = _torch()
+    dtype = dtype or torch.float64
+    coeffs = coeffs.contiguous()
+    if coeffs.dtype != torch.float64:
+        raise TypeError("coefficients must be float64")
+    dev = coeffs.device.index if coeffs.device.index is not None else torch.cuda.current_device()
+    shape = tuple(int(s) for s in shape)
+    ws_n = transform_query(shape)
+    ws = workspace if workspace is not None and workspace.numel() >= ws_n else _empty(ws_n, coeffs.device)
+    out = torch.empty(shape, dtype=dtype, device=coeffs.device)
+    _check(_load().mgc_recompose(_ctx(dev), ctypes.c_void_p(coeffs.data_ptr()), len(shape),
+                                 _shape_arg(shape), _dtype_code(dtype),
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), _stream_ptr(dev)))
+    return out
+
+
+def huffman_encode(symbols, C: int = 1024):
+    """Huffman-code 16-bit symbols (an int16/uint16/int32 GPU tensor of values 0..65535)."""
+    _require_gpu(symbols, "symbols")
+    torch = _torch()
+    if symbols.dtype == torch.int32 or symbols.dtype == torch.int64:
+        symbols = symbols.to(torch.int32).to(torch.int16)
+    symbols = symbols.contiguous()
+    if symbols.element_size() != 2:
+        raise TypeError("symbols must be 16-bit")
+    dev = symbols.device.index if symbols.device.index is not None else torch.cuda.current_device()
+    n = symbols.numel()
+    ws_n = ctypes.c_size_t()
+    out_n = ctypes.c_size_t()
+    _check(_load().mgc_huffman_query(n, C, ctypes.byref(ws_n), ctypes.byref(out_n)))
+    ws = _empty(ws_n.value, symbols.device)
+    out = _empty(out_n.value, symbols.device)
+    size = ctypes.c_uint64()
+    _check(_load().mgc_huffman_encode(_ctx(dev), ctypes.c_void_p(symbols.data_ptr()), n, C,
+                                      ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(dev),
+                                      ctypes.byref(size)))
+    return out[: size.value]
+
+
+def huffman_decode(stream, n: int):
+    """Decode n symbols; returns an int16 GPU tensor holding the 16-bit patterns."""
+    _require_gpu(stream, "stream")
+    torch = _torch()
+    dev = stream.device.index if stream.device.index is not None else torch.cuda.current_device()
+    stream = stream.contiguous()
+    ws_n = ctypes.c_size_t()
+    _check(_load().mgc_huffman_query(n, 64, ctypes.byref(ws_n), None))
+    ws = _empty(ws_n.value, stream.device)
+    out = torch.empty(max(n, 1), dtype=torch.int16, device=stream.device)
+    _check(_load().mgc_huffman_decode(_ctx(dev), ctypes.c_void_p(stream.data_ptr()), stream.numel(),
+                                      ctypes.c_void_p(out.data_ptr()), n,
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(dev)))
+    return out[:n]
+
+
+def profile_enable(flag: bool = True, device: int = 0):
+    _check(_load().mgc_profile_enable(_ctx(device), 1 if flag else 0))
+
+
+def profile_reset(device: int = 0):
+    _check(_load().mgc_profile_reset(_ctx(device)))
+
+
+def profile_read(device: int = 0):
+    """{stage: (launches, total GPU ms)} accumulated since the last reset."""
+    lib = _load()
+    cap = 64
+    names = ctypes.create_string_buffer(8192)
+    counts = (ctypes.c_uint64 * cap)()
+    ms = (ctypes.c_double * cap)()
+    n = ctypes.c_int()
+    _check(lib.mgc_profile_read(_ctx(device), names, 8192, counts, ms, cap, ctypes.byref(n)))
+    keys = names.value.decode().split("\n") if n.value else []
+    return {k: (int(counts[i]), float(ms[i])) for i, k in enumerate(keys[:cap])}

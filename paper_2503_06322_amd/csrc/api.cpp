@@ -1,0 +1,806 @@
+// C-ABI entry points and host orchestration of the kernels.
+//
+// compress runs Algorithm 1 of the paper end to end on one stream: a range
+// pre-pass (min, max, sum of squares) for the relative bound, then for each
+// level from the finest the fused lerp/quantise/mass_trans kernel and the
+// tridiagonal sweeps, the coarsest block, and the Huffman stage of Algorithm
+// 2.  The host reads back 32 bytes after the pre-pass (to turn the relative
+// bound into bins and reject NaN/Inf or constant data) and 24 bytes at the
+// end (status, escaped-value count and stream length).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mgc {
+
+thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+void fail(mgc_status st, const std::string& msg) {
+  g_err = msg;
+  throw Fail{st};
+}
+
+struct Profiler {
+  bool enabled = false;
+  std::vector<std::string> names;
+  std::map<std::string, int> slot_of;
+  std::vector<double> ms;
+  std::vector<uint64_t> counts;
+  struct Pending {
+    int slot;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+
+  int slot(const char* name) {
+    auto it = slot_of.find(name);
+    if (it != slot_of.end()) return it->second;
+    int s = (int)names.size();
+    names.push_back(name);
+    slot_of[name] = s;
+    ms.push_back(0.0);
+    counts.push_back(0);
+    return s;
+  }
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    MGC_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void flush() {
+    for (auto& p : pending) {
+      MGC_HIP(hipEventSynchronize(p.b));
+      float t = 0.f;
+      MGC_HIP(hipEventElapsedTime(&t, p.a, p.b));
+      ms[p.slot] += t;
+      counts[p.slot] += 1;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  ~Profiler() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+StageScope::StageScope(Profiler* prof, const char* name, hipStream_t stream)
+    : p(prof && prof->enabled ? prof : nullptr), slot(-1), s(stream), a(nullptr) {
+  if (!p) return;
+  slot = p->slot(name);
+  a = p->get();
+  MGC_HIP(hipEventRecord(a, s));
+}
+StageScope::~StageScope() {
+  if (!p) return;
+  hipEvent_t b = p->get();
+  if (hipEventRecord(b, s) == hipSuccess) p->pending.push_back({slot, a, b});
+}
+
+// bump allocator over a caller workspace (measure-only when base is null)
+struct Carver {
+  uint8_t* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<uint8_t*>(b)) {}
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+constexpr uint32_t kChunk = 1024;
+
+uint64_t default_outlier_cap(int64_t N) {
+  return std::max<uint64_t>(65536, (uint64_t)N / 16);
+}
+
+int key_bits(int64_t N) {
+  if (N <= 1) return 1;
+  uint64_t v = (uint64_t)(N - 1);
+  int b = 0;
+  while (v) {
+    ++b;
+    v >>= 1;
+  }
+  return b;
+}
+
+struct CompressWs {
+  uint16_t* sym;
+  double *gA, *gB, *part, *range;
+  unsigned* status;
+  unsigned long long* n_out;
+  Layout* lay;
+  unsigned* hist;
+  uint32_t* code;
+  uint8_t* clen;
+  void* cbs;
+  uint32_t* cw;
+  uint32_t* opos;
+  int64_t* oval;
+  uint32_t *okA, *ovA, *okB, *ovB;
+  unsigned long long* info;
+};
+
+CompressWs carve_compress(Carver& c, const Plan& p, uint64_t cap) {
+  CompressWs w;
+  const int64_t n_coarse = p.L >= 1 ? p.points(p.L - 1) : 1;
+  const int64_t n_chunks = (p.N + kChunk - 1) / kChunk;
+  w.sym = c.take<uint16_t>(std::max<int64_t>(p.N, 1));
+  w.gA = c.take<double>(n_coarse);
+  w.gB = c.take<double>(n_coarse);
+  w.part = c.take<double>(4 * kRangeBlocks);
+  w.range = c.take<double>(4);
+  w.status = c.take<unsigned>(4);
+  w.n_out = c.take<unsigned long long>(1);
+  w.lay = c.take<Layout>(1);
+  w.hist = c.take<unsigned>(kDict);
+  w.code = c.take<uint32_t>(kDict);
+  w.clen = c.take<uint8_t>(kDict);
+  w.cbs = c.take<uint8_t>(codebook_scratch_bytes());
+  w.cw = c.take<uint32_t>(std::max<int64_t>(n_chunks, 1));
+  w.opos = c.take<uint32_t>(cap);
+  w.oval = c.take<int64_t>(cap);
+  w.okA = c.take<uint32_t>(cap);
+  w.ovA = c.take<uint32_t>(cap);
+  w.okB = c.take<uint32_t>(cap);
+  w.ovB = c.take<uint32_t>(cap);
+  w.info = c.take<unsigned long long>(4);
+  return w;
+}
+
+size_t max_stream_bytes(const Plan& p, uint64_t cap) {
+  const uint64_t n_chunks = (p.N + kChunk - 1) / kChunk;
+  return kHeaderBytes + 8 * (p.L + 1) + pad8(3 * kDict) + 8 * (n_chunks + 1) + 16 * cap +
+         4 * ((uint64_t)p.N + n_chunks) + 8;
+}
+
+struct DecompressWs {
+  uint16_t* sym;
+  double *gA, *gB;
+  void* tables;
+  unsigned* status;
+};
+
+DecompressWs carve_decompress(Carver& c, const Plan& p) {
+  DecompressWs w;
+  const int64_t n_coarse = p.L >= 1 ? p.points(p.L - 1) : 1;
+  w.sym = c.take<uint16_t>(std::max<int64_t>(p.N, 1));
+  w.gA = c.take<double>(n_coarse);
+  w.gB = c.take<double>(n_coarse);
+  w.tables = c.take<uint8_t>(decode_tables_bytes());
+  w.status = c.take<unsigned>(4);
+  return w;
+}
+
+size_t dtype_size(mgc_dtype d) { return d == MGC_F32 ? 4 : 8; }
+
+// Parses and validates a stream header held in host memory.
+void parse_header(const uint8_t* b, size_t n, Header* h, std::vector<double>* q) {
+  if (n < (size_t)kHeaderBytes) fail(MGC_EFORMAT, "stream shorter than its header");
+  std::memcpy(h, b, kHeaderBytes);
+  if (h->magic != kMagic || h->version != kVersion) fail(MGC_EFORMAT, "bad magic or version");
+  if (h->dtype > 1 || h->norm > 1 || h->mode > 1 || h->ndim < 1 || h->ndim > 3 ||
+      h->L > (uint32_t)kMaxLevels || (h->flags & ~3u))
+    fail(MGC_EFORMAT, "bad header field");
+  if (n < (size_t)kHeaderBytes + 8 * (h->L + 1)) fail(MGC_EFORMAT, "truncated bins");
+  q->resize(h->L + 1);
+  std::memcpy(q->data(), b + kHeaderBytes, 8 * (h->L + 1));
+}
+
+}  // namespace mgc
+
+using namespace mgc;
+
+struct mgc_ctx_s {
+  int device = 0;
+  std::map<std::vector<uint64_t>, Plan> plans;
+  Profiler prof;
+  uint8_t* pinned = nullptr;  // 4 KiB host staging
+};
+
+namespace {
+
+template <typename F>
+mgc_status guard(F&& f) {
+  try {
+    f();
+    return MGC_OK;
+  } catch (const Fail& e) {
+    return e.st;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return MGC_EDEVICE;
+  }
+}
+
+void check_ctx(mgc_ctx ctx) {
+  if (!ctx) fail(MGC_EINVAL, "null context");
+  MGC_HIP(hipSetDevice(ctx->device));
+}
+
+Plan& get_plan(mgc_ctx ctx, int ndim, const uint64_t* shape) {
+  if (ndim < 1) fail(MGC_EINVAL, "ndim must be at least 1");
+  if (ndim > 3) fail(MGC_EUNSUPPORTED, "ndim above 3 is not supported");
+  std::vector<uint64_t> key(shape, shape + ndim);
+  key.insert(key.begin(), (uint64_t)ndim);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) return it->second;
+  Plan p = build_plan(ndim, shape);
+  upload_plan(p);
+  return ctx->plans.emplace(key, std::move(p)).first->second;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+void sync_read(mgc_ctx ctx, void* host, const void* dev, size_t n, hipStream_t s) {
+  MGC_HIP(hipMemcpyAsync(host, dev, n, hipMemcpyDeviceToHost, s));
+  MGC_HIP(hipStreamSynchronize(s));
+  (void)ctx;
+}
+
+// header of a constant or empty array (no sections)
+uint64_t write_trivial_stream(mgc_ctx ctx, Header h, void* d_out, hipStream_t s) {
+  h.L = 0;
+  h.total = kHeaderBytes + 8;
+  std::memcpy(ctx->pinned, &h, kHeaderBytes);
+  std::memset(ctx->pinned + kHeaderBytes, 0, 8);
+  MGC_HIP(hipMemcpyAsync(d_out, ctx->pinned, kHeaderBytes + 8, hipMemcpyHostToDevice, s));
+  MGC_HIP(hipStreamSynchronize(s));
+  return h.total;
+}
+
+void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_f32,
+                          double* gA, double* gB, uint16_t* sym, double* raw,
+                          const std::vector<double>& r, const OutlierBuf& ob, unsigned* status,
+                          hipStream_t s) {
+  const void* Gcur = d_in;
+  bool cur_f32 = in_f32;
+  for (int l = p.L; l >= 1; --l) {
+    double* Gnext = ((p.L - l) % 2 == 0) ? gA : gB;
+    const LevelGeom g = p.geom(l);
+    {
+      StageScope sc(&ctx->prof, l == p.L ? "dec_level[finest]" : "dec_level", s);
+      launch_dec_level(Gcur, cur_f32, g, Gnext, sym, raw, sym ? r[l] : 0.0, ob, status, s);
+    }
+    for (int axis = 2; axis >= 0; --axis) {
+      if (p.bit[axis] < 0) continue;
+      StageScope sc(&ctx->prof, l == p.L ? "thomas[finest]" : "thomas", s);
+      launch_thomas(axis, Gnext, g.nc, g.ax[axis], nullptr, s);
+    }
+    Gcur = Gnext;
+    cur_f32 = false;
+  }
+  StageScope sc(&ctx->prof, "level0", s);
+  launch_level0(Gcur, cur_f32, p.points(0), sym, raw, sym ? r[0] : 0.0, ob, status, s);
+}
+
+void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
+                          const std::vector<double>& q, double* gA, double* gB, void* d_out,
+                          bool out_f32, hipStream_t s) {
+  if (p.L == 0) {
+    StageScope sc(&ctx->prof, "rec_level0", s);
+    launch_rec_level0(src, p.points(0), q[0], d_out, out_f32, s);
+    return;
+  }
+  {
+    StageScope sc(&ctx->prof, "rec_level0", s);
+    launch_rec_level0(src, p.points(0), q[0], gA, false, s);
+  }
+  double* Gprev = gA;
+  double* F = gB;
+  int last = -1;
+  for (int axis = 0; axis <= 2; ++axis)
+    if (p.bit[axis] >= 0) {
+      last = axis;
+      break;
+    }
+  for (int l = 1; l <= p.L; ++l) {
+    const LevelGeom g = p.geom(l);
+    const bool fin = l == p.L;
+    {
+      StageScope sc(&ctx->prof, fin ? "rec_restrict[finest]" : "rec_restrict", s);
+      launch_rec_restrict(g, src, q[l], F, s);
+    }
+    for (int axis = 2; axis >= 0; --axis) {
+      if (p.bit[axis] < 0) continue;
+      StageScope sc(&ctx->prof, fin ? "thomas[finest]" : "thomas", s);
+      launch_thomas(axis, F, g.nc, g.ax[axis], axis == last ? Gprev : nullptr, s);
+    }
+    {
+      StageScope sc(&ctx->prof, fin ? "rec_interp[finest]" : "rec_interp", s);
+      launch_rec_interp(F, g, src, q[l], fin ? d_out : (void*)Gprev, fin && out_f32, s);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgc_version(void) { return 1; }
+
+const char* mgc_last_error(void) { return g_err.c_str(); }
+
+mgc_status mgc_create(int device, mgc_ctx* out) {
+  return guard([&] {
+    if (!out) fail(MGC_EINVAL, "null output");
+    int n = 0;
+    MGC_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) fail(MGC_EINVAL, "device ordinal out of range");
+    MGC_HIP(hipSetDevice(device));
+    auto* c = new mgc_ctx_s;
+    c->device = device;
+    if (hipHostMalloc((void**)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+      delete c;
+      fail(MGC_EDEVICE, "hipHostMalloc failed");
+    }
+    *out = c;
+  });
+}
+
+mgc_status mgc_destroy(mgc_ctx ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->plans) free_plan(kv.second);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+  });
+}
+
+mgc_status mgc_compress_query(int ndim, const uint64_t* shape, mgc_dtype dtype,
+                              uint64_t outlier_cap, size_t* ws_bytes, size_t* max_out_bytes) {
+  return guard([&] {
+    if (dtype != MGC_F32 && dtype != MGC_F64) fail(MGC_EINVAL, "dtype must be f32 or f64");
+    Plan p = build_plan(ndim, shape);
+    const uint64_t cap = outlier_cap ? outlier_cap : default_outlier_cap(p.N);
+    Carver c(nullptr);
+    carve_compress(c, p, cap);
+    if (ws_bytes) *ws_bytes = c.off;
+    if (max_out_bytes) *max_out_bytes = max_stream_bytes(p, cap);
+  });
+}
+
+mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                        mgc_dtype dtype, double error_bound, mgc_norm norm, mgc_mode mode,
+                        uint64_t outlier_cap, void* d_out, size_t out_cap, void* d_ws,
+                        size_t ws_bytes, void* stream, uint64_t* h_out_size) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (dtype != MGC_F32 && dtype != MGC_F64) fail(MGC_EINVAL, "dtype must be f32 or f64");
+    if (norm != MGC_LINF && norm != MGC_L2) fail(MGC_EINVAL, "norm must be L-inf or L2");
+    if (mode != MGC_REL && mode != MGC_ABS) fail(MGC_EINVAL, "mode must be rel or abs");
+    if (!(error_bound > 0.0) || !std::isfinite(error_bound))
+      fail(MGC_EINVAL, "error bound must be positive and finite");
+    if (!h_out_size) fail(MGC_EINVAL, "null size output");
+    const Plan& p = get_plan(ctx, ndim, shape);
+    const uint64_t cap = outlier_cap ? outlier_cap : default_outlier_cap(p.N);
+    Carver meas(nullptr);
+    carve_compress(meas, p, cap);
+    if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
+    if (out_cap < max_stream_bytes(p, cap)) fail(MGC_ENOSPC, "output capacity too small");
+    if (p.N > 0 && (!d_in || !d_out || !d_ws)) fail(MGC_EINVAL, "null device pointer");
+    hipStream_t s = as_stream(stream);
+    Carver c(d_ws);
+    CompressWs w = carve_compress(c, p, cap);
+
+    Header h{};
+    h.magic = kMagic;
+    h.version = kVersion;
+    h.dtype = (uint8_t)dtype;
+    h.norm = (uint8_t)norm;
+    h.mode = (uint8_t)mode;
+    h.ndim = (uint8_t)ndim;
+    h.D = (uint8_t)p.D;
+    h.L = (uint32_t)p.L;
+    for (int d = 0; d < ndim; ++d) h.shape[d] = shape[d];
+    h.bound = error_bound;
+    h.S = kDict;
+    h.C = kChunk;
+    h.N = (uint64_t)p.N;
+    h.n_chunks = (p.N + kChunk - 1) / kChunk;
+    if (p.N == 0) {
+      h.flags = FLAG_EMPTY;
+      h.n_chunks = 0;
+      *h_out_size = write_trivial_stream(ctx, h, d_out, s);
+      return;
+    }
+    {
+      StageScope sc(&ctx->prof, "range", s);
+      launch_range(d_in, dtype, p.N, w.part, w.range, s);
+    }
+    double rng[4];
+    sync_read(ctx, ctx->pinned, w.range, sizeof(rng), s);
+    std::memcpy(rng, ctx->pinned, sizeof(rng));
+    if (rng[3] != 0.0) fail(MGC_EINVAL, "input holds NaN or Inf");
+    if (rng[0] == rng[1]) {
+      h.flags = FLAG_CONSTANT;
+      h.const_value = rng[0];
+      h.n_chunks = 0;
+      *h_out_size = write_trivial_stream(ctx, h, d_out, s);
+      return;
+    }
+    double tau, tau_eff;
+    error_budget(dtype, norm, mode, error_bound, rng[0], rng[1], rng[2], p.N, &tau, &tau_eff);
+    if (!(tau_eff > 0.0)) fail(MGC_ERANGE, "error bound below the resolution of the output type");
+    h.tau = tau;
+    h.tau_eff = tau_eff;
+    const std::vector<double> K = p.bin_factors(norm);
+    std::vector<double> q(p.L + 1), r(p.L + 1);
+    for (int l = 0; l <= p.L; ++l) {
+      q[l] = tau_eff * K[l];
+      r[l] = 1.0 / q[l];
+    }
+    MGC_HIP(hipMemsetAsync(w.status, 0, 4 * sizeof(unsigned), s));
+    MGC_HIP(hipMemsetAsync(w.n_out, 0, sizeof(unsigned long long), s));
+    MGC_HIP(hipMemsetAsync(w.lay, 0, sizeof(Layout), s));
+    MGC_HIP(hipMemsetAsync(w.hist, 0, kDict * sizeof(unsigned), s));
+    OutlierBuf ob{w.opos, w.oval, w.n_out, cap};
+    run_levels_decompose(ctx, p, d_in, dtype == MGC_F32, w.gA, w.gB, w.sym, nullptr, r, ob,
+                         w.status, s);
+    uint8_t* out = static_cast<uint8_t*>(d_out);
+    const uint64_t cb_off = kHeaderBytes + 8 * (p.L + 1);
+    const CodebookScratch sc = carve_codebook_scratch(w.cbs);
+    {
+      StageScope st(&ctx->prof, "histogram", s);
+      launch_histogram(w.sym, p.N, w.hist, s);
+    }
+    {
+      StageScope st(&ctx->prof, "codebook", s);
+      launch_codebook(w.hist, sc, w.code, w.clen, out, cb_off, w.lay, s);
+    }
+    {
+      StageScope st(&ctx->prof, "chunk_words", s);
+      launch_chunk_words(w.sym, p.N, kChunk, w.clen, w.cw, w.lay, s);
+    }
+    {
+      StageScope st(&ctx->prof, "layout_scan", s);
+      launch_layout_scan(w.cw, (int64_t)h.n_chunks, out, cb_off, w.lay, w.n_out, cap, false, s);
+    }
+    {
+      StageScope st(&ctx->prof, "outlier_sort", s);
+      launch_outlier_sort(ob, w.okA, w.ovA, w.okB, w.ovB, key_bits(p.N), out, w.lay, s);
+    }
+    {
+      StageScope st(&ctx->prof, "encode", s);
+      launch_encode(w.sym, p.N, kChunk, w.code, w.clen, out, w.lay, s);
+    }
+    {
+      StageScope st(&ctx->prof, "header", s);
+      launch_header(out, h, q.data(), p.L + 1, w.lay, w.status, w.info, s);
+    }
+    MGC_HIP(hipGetLastError());
+    unsigned long long info[3];
+    sync_read(ctx, ctx->pinned, w.info, sizeof(info), s);
+    std::memcpy(info, ctx->pinned, sizeof(info));
+    if (info[0] & ST_OVERFLOW) {
+      *h_out_size = info[1];
+      fail(MGC_ENOSPC, "more escaped values than the outlier capacity; retry with capacity " +
+                           std::to_string(info[1]));
+    }
+    if (info[0] & ST_RANGE) fail(MGC_ERANGE, "quantised value out of range (bound too small)");
+    if (info[0]) fail(MGC_EDEVICE, "device status " + std::to_string(info[0]));
+    *h_out_size = info[2];
+  });
+}
+
+mgc_status mgc_header_info(const void* h_prefix, size_t n, int* ndim, uint64_t* shape3,
+                           mgc_dtype* dtype, uint64_t* stream_bytes, size_t* ws_bytes) {
+  return guard([&] {
+    if (!h_prefix) fail(MGC_EINVAL, "null prefix");
+    Header h;
+    std::vector<double> q;
+    parse_header(static_cast<const uint8_t*>(h_prefix), n, &h, &q);
+    if (ndim) *ndim = h.ndim;
+    if (shape3)
+      for (int d = 0; d < 3; ++d) shape3[d] = d < h.ndim ? h.shape[d] : 0;
+    if (dtype) *dtype = (mgc_dtype)h.dtype;
+    if (stream_bytes) *stream_bytes = h.total;
+    if (ws_bytes) {
+      Plan p = build_plan(h.ndim, h.shape);
+      Carver c(nullptr);
+      carve_decompress(c, p);
+      *ws_bytes = c.off;
+    }
+  });
+}
+
+mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* d_out,
+                          size_t out_cap, void* d_ws, size_t ws_bytes, void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (!d_in) fail(MGC_EINVAL, "null input");
+    hipStream_t s = as_stream(stream);
+    const size_t pre = std::min<size_t>(in_bytes, kHeaderBytes + 8 * (kMaxLevels + 1));
+    if (pre < (size_t)kHeaderBytes) fail(MGC_EFORMAT, "stream shorter than its header");
+    sync_read(ctx, ctx->pinned, d_in, pre, s);
+    Header h;
+    std::vector<double> q;
+    parse_header(ctx->pinned, pre, &h, &q);
+    const Plan& p = get_plan(ctx, h.ndim, h.shape);
+    const mgc_dtype dt = (mgc_dtype)h.dtype;
+    if ((uint64_t)p.N != h.N) fail(MGC_EFORMAT, "header size inconsistent with its shape");
+    if (h.total > in_bytes) fail(MGC_EFORMAT, "truncated stream");
+    if (out_cap < (size_t)p.N * dtype_size(dt)) fail(MGC_ENOSPC, "output capacity too small");
+    if (h.flags & FLAG_EMPTY) return;
+    if (h.flags & FLAG_CONSTANT) {
+      launch_fill(d_out, dt == MGC_F32, p.N, h.const_value, s);
+      MGC_HIP(hipGetLastError());
+      return;
+    }
+    if (h.L != (uint32_t)p.L || h.S != kDict || h.C < 1 || h.C > (1u << 20) ||
+        h.n_chunks != (h.N + h.C - 1) / h.C || h.n_codes > kDict || h.n_codes < 1 ||
+        h.n_outliers > h.N)
+      fail(MGC_EFORMAT, "inconsistent header counts");
+    const uint64_t cb = kHeaderBytes + 8 * (h.L + 1);
+    const uint64_t off = pad8(cb + 3 * h.n_codes);
+    const uint64_t opos = off + 8 * (h.n_chunks + 1);
+    const uint64_t oval = opos + 8 * h.n_outliers;
+    const uint64_t words = oval + 8 * h.n_outliers;
+    const uint64_t end = pad8(words + 4 * h.n_words);
+    if (end != h.total) fail(MGC_EFORMAT, "section sizes disagree with the stream length");
+    Carver meas(nullptr);
+    carve_decompress(meas, p);
+    if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
+    Carver c(d_ws);
+    DecompressWs w = carve_decompress(c, p);
+    const uint8_t* in = static_cast<const uint8_t*>(d_in);
+    MGC_HIP(hipMemsetAsync(w.status, 0, 4 * sizeof(unsigned), s));
+    {
+      StageScope st(&ctx->prof, "decode_tables", s);
+      launch_decode_tables(in + cb, h.n_codes, static_cast<DecodeTables*>(w.tables), w.status, s);
+    }
+    {
+      StageScope st(&ctx->prof, "decode", s);
+      launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, p.N,
+                    static_cast<const DecodeTables*>(w.tables), w.sym, w.status, s);
+    }
+    CoeffSrc src{w.sym, nullptr, reinterpret_cast<const uint64_t*>(in + opos),
+                 reinterpret_cast<const int64_t*>(in + oval), (int64_t)h.n_outliers};
+    run_levels_recompose(ctx, p, src, q, w.gA, w.gB, d_out, dt == MGC_F32, s);
+    MGC_HIP(hipGetLastError());
+    unsigned st = 0;
+    sync_read(ctx, ctx->pinned, w.status, sizeof(unsigned), s);
+    std::memcpy(&st, ctx->pinned, sizeof(unsigned));
+    if (st & ST_FORMAT) fail(MGC_EFORMAT, "corrupt coded data");
+  });
+}
+
+mgc_status mgc_transform_query(int ndim, const uint64_t* shape, size_t* ws_bytes) {
+  return guard([&] {
+    Plan p = build_plan(ndim, shape);
+    const int64_t n_coarse = p.L >= 1 ? p.points(p.L - 1) : 1;
+    Carver c(nullptr);
+    c.take<double>(n_coarse);
+    c.take<double>(n_coarse);
+    c.take<unsigned>(4);
+    if (ws_bytes) *ws_bytes = c.off;
+  });
+}
+
+mgc_status mgc_decompose(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                         mgc_dtype dtype, double* d_coeffs, void* d_ws, size_t ws_bytes,
+                         void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (dtype != MGC_F32 && dtype != MGC_F64) fail(MGC_EINVAL, "dtype must be f32 or f64");
+    const Plan& p = get_plan(ctx, ndim, shape);
+    if (p.N == 0) return;
+    const int64_t n_coarse = p.L >= 1 ? p.points(p.L - 1) : 1;
+    Carver c(d_ws);
+    double* gA = c.take<double>(n_coarse);
+    double* gB = c.take<double>(n_coarse);
+    unsigned* status = c.take<unsigned>(4);
+    if (ws_bytes < c.off) fail(MGC_ENOSPC, "workspace too small");
+    hipStream_t s = as_stream(stream);
+    OutlierBuf ob{nullptr, nullptr, nullptr, 0};
+    run_levels_decompose(ctx, p, d_in, dtype == MGC_F32, gA, gB, nullptr, d_coeffs,
+                         std::vector<double>(p.L + 1, 0.0), ob, status, s);
+    MGC_HIP(hipGetLastError());
+  });
+}
+
+mgc_status mgc_recompose(mgc_ctx ctx, const double* d_coeffs, int ndim, const uint64_t* shape,
+                         mgc_dtype out_dtype, void* d_out, void* d_ws, size_t ws_bytes,
+                         void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (out_dtype != MGC_F32 && out_dtype != MGC_F64) fail(MGC_EINVAL, "dtype must be f32 or f64");
+    const Plan& p = get_plan(ctx, ndim, shape);
+    if (p.N == 0) return;
+    const int64_t n_coarse = p.L >= 1 ? p.points(p.L - 1) : 1;
+    Carver c(d_ws);
+    double* gA = c.take<double>(n_coarse);
+    double* gB = c.take<double>(n_coarse);
+    c.take<unsigned>(4);
+    if (ws_bytes < c.off) fail(MGC_ENOSPC, "workspace too small");
+    hipStream_t s = as_stream(stream);
+    CoeffSrc src{nullptr, d_coeffs, nullptr, nullptr, 0};
+    run_levels_recompose(ctx, p, src, std::vector<double>(p.L + 1, 1.0), gA, gB, d_out,
+                         out_dtype == MGC_F32, s);
+    MGC_HIP(hipGetLastError());
+  });
+}
+
+mgc_status mgc_huffman_query(uint64_t n, uint32_t C, size_t* ws_bytes, size_t* max_out_bytes) {
+  return guard([&] {
+    if (C < 64 || C > 65536 || C % 64) fail(MGC_EINVAL, "chunk size must be a multiple of 64 in [64, 65536]");
+    const uint64_t n_chunks = (n + C - 1) / C;
+    Carver c(nullptr);
+    c.take<unsigned>(kDict);
+    c.take<uint32_t>(kDict);
+    c.take<uint8_t>(kDict);
+    c.take<uint8_t>(codebook_scratch_bytes());
+    c.take<uint32_t>(std::max<uint64_t>(n_chunks, 1));
+    c.take<Layout>(1);
+    c.take<unsigned long long>(4);
+    c.take<uint8_t>(decode_tables_bytes());
+    c.take<unsigned>(4);
+    if (ws_bytes) *ws_bytes = c.off;
+    if (max_out_bytes)
+      *max_out_bytes = kHuffHeaderBytes + pad8(3 * kDict) + 8 * (n_chunks + 1) + 4 * (n + n_chunks) + 8;
+  });
+}
+
+mgc_status mgc_huffman_encode(mgc_ctx ctx, const uint16_t* d_sym, uint64_t n, uint32_t C,
+                              void* d_out, size_t out_cap, void* d_ws, size_t ws_bytes,
+                              void* stream, uint64_t* h_out_size) {
+  return guard([&] {
+    check_ctx(ctx);
+    size_t need_ws = 0, need_out = 0;
+    if (mgc_huffman_query(n, C, &need_ws, &need_out) != MGC_OK) throw Fail{MGC_EINVAL};
+    if (ws_bytes < need_ws || out_cap < need_out) fail(MGC_ENOSPC, "workspace or output too small");
+    if (n >= (1ull << 32)) fail(MGC_EUNSUPPORTED, "2^32 or more symbols");
+    if (!h_out_size) fail(MGC_EINVAL, "null size output");
+    hipStream_t s = as_stream(stream);
+    const uint64_t n_chunks = (n + C - 1) / C;
+    Carver c(d_ws);
+    unsigned* hist = c.take<unsigned>(kDict);
+    uint32_t* code = c.take<uint32_t>(kDict);
+    uint8_t* clen = c.take<uint8_t>(kDict);
+    void* cbs = c.take<uint8_t>(codebook_scratch_bytes());
+    uint32_t* cw = c.take<uint32_t>(std::max<uint64_t>(n_chunks, 1));
+    Layout* lay = c.take<Layout>(1);
+    unsigned long long* info = c.take<unsigned long long>(4);
+    uint8_t* out = static_cast<uint8_t*>(d_out);
+    MGC_HIP(hipMemsetAsync(hist, 0, kDict * sizeof(unsigned), s));
+    MGC_HIP(hipMemsetAsync(lay, 0, sizeof(Layout), s));
+    if (n > 0) {
+      StageScope st(&ctx->prof, "histogram", s);
+      launch_histogram(d_sym, (int64_t)n, hist, s);
+    }
+    {
+      StageScope st(&ctx->prof, "codebook", s);
+      launch_codebook(hist, carve_codebook_scratch(cbs), code, clen, out, kHuffHeaderBytes, lay, s);
+    }
+    if (n > 0) {
+      StageScope st(&ctx->prof, "chunk_words", s);
+      launch_chunk_words(d_sym, (int64_t)n, (int)C, clen, cw, lay, s);
+    }
+    {
+      StageScope st(&ctx->prof, "layout_scan", s);
+      launch_layout_scan(cw, (int64_t)n_chunks, out, kHuffHeaderBytes, lay, nullptr, 0, true, s);
+    }
+    if (n > 0) {
+      StageScope st(&ctx->prof, "encode", s);
+      launch_encode(d_sym, (int64_t)n, (int)C, code, clen, out, lay, s);
+    }
+    launch_huff_header(out, C, n, n_chunks, lay, info, s);
+    MGC_HIP(hipGetLastError());
+    unsigned long long inf[3];
+    sync_read(ctx, ctx->pinned, info, sizeof(inf), s);
+    std::memcpy(inf, ctx->pinned, sizeof(inf));
+    if (inf[0]) fail(MGC_EDEVICE, "huffman encode failed");
+    *h_out_size = inf[2];
+  });
+}
+
+mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes, uint16_t* d_sym,
+                              uint64_t n, void* d_ws, size_t ws_bytes, void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (in_bytes < (size_t)kHuffHeaderBytes) fail(MGC_EFORMAT, "stream shorter than its header");
+    hipStream_t s = as_stream(stream);
+    sync_read(ctx, ctx->pinned, d_in, kHuffHeaderBytes, s);
+    HuffHeader h;
+    std::memcpy(&h, ctx->pinned, kHuffHeaderBytes);
+    if (h.magic != kHuffMagic || h.N != n || h.C < 1 || h.C > (1u << 20) ||
+        h.n_chunks != (h.N + h.C - 1) / h.C || h.n_codes > kDict || (n > 0 && h.n_codes < 1))
+      fail(MGC_EFORMAT, "bad huffman header");
+    const uint64_t off = pad8(kHuffHeaderBytes + 3 * h.n_codes);
+    const uint64_t words = off + 8 * (h.n_chunks + 1);
+    const uint64_t end = pad8(words + 4 * h.n_words);
+    if (end != h.total || h.total > in_bytes) fail(MGC_EFORMAT, "truncated huffman stream");
+    Carver meas(nullptr);
+    meas.take<uint8_t>(decode_tables_bytes());
+    meas.take<unsigned>(4);
+    if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
+    if (n == 0) return;
+    Carver c(d_ws);
+    void* tables = c.take<uint8_t>(decode_tables_bytes());
+    unsigned* status = c.take<unsigned>(4);
+    const uint8_t* in = static_cast<const uint8_t*>(d_in);
+    MGC_HIP(hipMemsetAsync(status, 0, 4 * sizeof(unsigned), s));
+    {
+      StageScope st(&ctx->prof, "decode_tables", s);
+      launch_decode_tables(in + kHuffHeaderBytes, h.n_codes, static_cast<DecodeTables*>(tables),
+                           status, s);
+    }
+    {
+      StageScope st(&ctx->prof, "decode", s);
+      launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, (int64_t)n,
+                    static_cast<const DecodeTables*>(tables), d_sym, status, s);
+    }
+    MGC_HIP(hipGetLastError());
+    unsigned st = 0;
+    sync_read(ctx, ctx->pinned, status, sizeof(unsigned), s);
+    std::memcpy(&st, ctx->pinned, sizeof(unsigned));
+    if (st & ST_FORMAT) fail(MGC_EFORMAT, "corrupt coded data");
+  });
+}
+
+mgc_status mgc_profile_enable(mgc_ctx ctx, int enable) {
+  return guard([&] {
+    if (!ctx) fail(MGC_EINVAL, "null context");
+    ctx->prof.enabled = enable != 0;
+  });
+}
+
+mgc_status mgc_profile_reset(mgc_ctx ctx) {
+  return guard([&] {
+    if (!ctx) fail(MGC_EINVAL, "null context");
+    MGC_HIP(hipSetDevice(ctx->device));
+    ctx->prof.flush();
+    std::fill(ctx->prof.ms.begin(), ctx->prof.ms.end(), 0.0);
+    std::fill(ctx->prof.counts.begin(), ctx->prof.counts.end(), 0);
+  });
+}
+
+mgc_status mgc_profile_read(mgc_ctx ctx, char* names, size_t names_cap, uint64_t* counts,
+                            double* ms, int cap, int* n_stages) {
+  return guard([&] {
+    if (!ctx) fail(MGC_EINVAL, "null context");
+    MGC_HIP(hipSetDevice(ctx->device));
+    ctx->prof.flush();
+    const int n = (int)ctx->prof.names.size();
+    if (n_stages) *n_stages = n;
+    std::string all;
+    for (int i = 0; i < n; ++i) {
+      if (i) all += '\n';
+      all += ctx->prof.names[i];
+      if (i < cap) {
+        if (counts) counts[i] = ctx->prof.counts[i];
+        if (ms) ms[i] = ctx->prof.ms[i];
+      }
+    }
+    if (names && names_cap) {
+      const size_t k = std::min(all.size(), names_cap - 1);
+      std::memcpy(names, all.data(), k);
+      names[k] = 0;
+    }
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,875 @@
+// Huffman stage for gfx950 (Algorithm 2 and Section IV-B of the paper):
+// histogram -> sort by frequency -> drop zero keys -> code construction ->
+// encode -> serialise, plus the inverse decode.
+//
+//  * histogram: LDS-privatised counts for a central window of symbols (the
+//    quantised coefficients cluster around the dictionary centre), global
+//    atomics for the rest.
+//  * codebook: one workgroup of 1024 threads.  The non-zero keys are
+//    compacted in symbol order and sorted by frequency with a stable LSD
+//    radix sort (wave ballots rank equal digits), giving the (frequency,
+//    symbol) order.  Code lengths follow the two-queue construction (leaves in
+//    that order, internal nodes in creation order, ties to the leaf), computed
+//    in rounds: with m nodes already taken, no node created later can weigh
+//    less than t = (the next node to be paired) + (the smallest remaining),
+//    so every available node of weight <= t is taken in this round by a
+//    parallel merge of the two sorted queues.  The threshold at least doubles
+//    every two rounds, so the round count is logarithmic in the total weight.
+//    Depths come from pointer jumping; lengths above 32 halve the
+//    frequencies and rebuild.  Codes are canonical (RFC 1951 construction).
+//  * encode: one wavefront per chunk of C symbols; a wave prefix scan of code
+//    lengths gives each lane its bit offset; codes are OR-ed MSB-first into
+//    the chunk's 32-bit words in LDS, then stored coalesced.
+//  * decode: one thread per chunk; an LDS lookup table resolves codes of up
+//    to 11 bits, longer codes use the canonical limit table.
+#include "kernels.hpp"
+
+namespace mgc {
+
+constexpr int kLutBits = 11;
+
+struct DecodeTables {
+  uint32_t first[34];
+  uint32_t count[34];
+  uint32_t base[34];
+  uint64_t limit[34];   // left-justified exclusive upper bound of each length
+  uint32_t maxlen;
+  uint32_t lut[1 << kLutBits];  // symbol | length << 16 (length 0: longer code)
+  uint16_t sorted[kDict];       // symbols in (length, symbol) order
+};
+
+size_t decode_tables_bytes() { return sizeof(DecodeTables); }
+
+size_t codebook_scratch_bytes() { return (size_t)kDict * 4 * 14; }
+
+CodebookScratch carve_codebook_scratch(void* base) {
+  uint32_t* p = static_cast<uint32_t*>(base);
+  CodebookScratch s;
+  s.keyA = p; p += kDict;
+  s.valA = p; p += kDict;
+  s.keyB = p; p += kDict;
+  s.valB = p; p += kDict;
+  s.symAsc = p; p += kDict;
+  s.freqAsc = p; p += kDict;
+  s.Iw = p; p += kDict;
+  s.Sw = p; p += 2 * kDict;
+  s.leafPar = p; p += kDict;
+  s.parA = p; p += kDict;
+  s.parB = p; p += kDict;
+  s.dstA = p; p += kDict;
+  s.dstB = p; p += kDict;
+  return s;
+}
+
+namespace {
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Lanes of the wave whose `digit` (nbits bits) equals this lane's, among the
+// lanes with valid set.
+__device__ __forceinline__ uint64_t match_digit(unsigned digit, int nbits, bool valid) {
+  uint64_t peers = __ballot(valid);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (digit >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// ---------------------------------------------------------------- histogram
+constexpr int kHistWin = 16384;
+
+__global__ __launch_bounds__(1024) void k_histogram(const uint16_t* __restrict__ sym, int64_t n,
+                                                     unsigned* __restrict__ hist) {
+  __shared__ unsigned h[kHistWin];
+  for (int i = threadIdx.x; i < kHistWin; i += 1024) h[i] = 0;
+  __syncthreads();
+  const unsigned lo = kHalf - kHistWin / 2;
+  const int64_t stride = (int64_t)gridDim.x * 1024;
+  for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride) {
+    const unsigned s = sym[i];
+    const unsigned d = s - lo;
+    if (d < (unsigned)kHistWin) atomicAdd(&h[d], 1u);
+    else atomicAdd(&hist[s], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kHistWin; i += 1024)
+    if (h[i]) atomicAdd(&hist[lo + i], h[i]);
+}
+
+// ---------------------------------------------------- single-block helpers
+struct SortSmem {
+  unsigned hist[256];
+  unsigned base[256];
+  unsigned total[256];
+  unsigned wcnt[16][256];
+};
+
+// Stable LSD radix sort by the low `bits` bits of the keys, 8 bits a pass,
+// one 1024-thread block.  Returns true when the result is in (k1, v1).
+__device__ bool block_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+                                 uint32_t n, int bits, SortSmem& sm) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int passes = (bits + 7) / 8;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 8 * pass;
+    if (tid < 256) sm.hist[tid] = 0;
+    for (int w = 0; w < 16; ++w)
+      if (tid < 256) sm.wcnt[w][tid] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < n; i += 1024) atomicAdd(&sm.hist[(k0[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    if (tid == 0) {
+      unsigned run = 0;
+      for (int d = 0; d < 256; ++d) {
+        sm.base[d] = run;
+        run += sm.hist[d];
+      }
+    }
+    __syncthreads();
+    for (uint32_t t0 = 0; t0 < n; t0 += 1024) {
+      const uint32_t i = t0 + tid;
+      const bool valid = i < n;
+      const uint32_t key = valid ? k0[i] : 0u;
+      const uint32_t val = valid ? v0[i] : 0u;
+      const unsigned d = (key >> shift) & 255u;
+      const uint64_t peers = match_digit(d, 8, valid);
+      const unsigned rank = __popcll(peers & lanemask_lt());
+      if (valid && rank == 0) sm.wcnt[wave][d] = __popcll(peers);
+      __syncthreads();
+      if (tid < 256) {
+        unsigned run = 0;
+        for (int w = 0; w < 16; ++w) {
+          const unsigned c = sm.wcnt[w][tid];
+          sm.wcnt[w][tid] = run;
+          run += c;
+        }
+        sm.total[tid] = run;
+      }
+      __syncthreads();
+      if (valid) {
+        const unsigned pos = sm.base[d] + sm.wcnt[wave][d] + rank;
+        k1[pos] = key;
+        v1[pos] = val;
+      }
+      __syncthreads();
+      if (tid < 256) {
+        sm.base[tid] += sm.total[tid];
+        for (int w = 0; w < 16; ++w) sm.wcnt[w][tid] = 0;
+      }
+      __syncthreads();
+    }
+    uint32_t* t;
+    t = k0; k0 = k1; k1 = t;
+    t = v0; v0 = v1; v1 = t;
+    (void)lane;
+  }
+  return passes & 1;
+}
+
+__device__ unsigned block_max(unsigned v, unsigned* sm32) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sm32[wave] = v;
+  __syncthreads();
+  unsigned r = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = max(r, sm32[w]);
+  __syncthreads();
+  return r;
+}
+
+// Exclusive scan of one value per thread over the 1024-thread block.
+__device__ unsigned block_excl_scan(unsigned v, unsigned* sm32, unsigned* total) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  unsigned x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = (unsigned)__shfl_up((int)x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) sm32[wave] = x;
+  __syncthreads();
+  unsigned before = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) before += sm32[w];
+    tot += sm32[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return before + x - v;
+}
+
+// ---------------------------------------------------------------- codebook
+struct CbSmem {
+  SortSmem sort;
+  unsigned sm32[16];
+  unsigned m, li, ii, nI, la, ib, n, flag;
+  unsigned long long t;
+  unsigned lcount[34];
+  unsigned lfirst[34];
+  unsigned lbase[34];
+  unsigned wl[16][34];
+};
+
+// count of a[0..n) that are < w (strict) or <= w, a ascending
+__device__ __forceinline__ unsigned lower_count(const uint32_t* a, unsigned n, uint32_t w) {
+  unsigned lo = 0, hi = n;
+  while (lo < hi) {
+    const unsigned mid = (lo + hi) >> 1;
+    if (a[mid] < w) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ unsigned upper_count(const uint32_t* a, unsigned n, uint32_t w) {
+  unsigned lo = 0, hi = n;
+  while (lo < hi) {
+    const unsigned mid = (lo + hi) >> 1;
+    if (a[mid] <= w) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Stable rank of each item among items with the same small digit (< 34), in
+// item order, processed in tiles of 1024.  For every valid item calls
+// fn(i, digit, rank) where rank counts earlier items with that digit.
+template <typename DigitFn, typename Fn>
+__device__ void stable_digit_ranks(unsigned n, DigitFn digit_of, Fn fn, CbSmem& sm) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  if (tid < 34) sm.lbase[tid] = 0;
+  for (int w = 0; w < 16; ++w)
+    if (tid < 34) sm.wl[w][tid] = 0;
+  __syncthreads();
+  for (unsigned t0 = 0; t0 < n; t0 += 1024) {
+    const unsigned i = t0 + tid;
+    const bool valid = i < n;
+    const unsigned d = valid ? digit_of(i) : 0u;
+    const uint64_t peers = match_digit(d, 6, valid);
+    const unsigned rank = __popcll(peers & lanemask_lt());
+    if (valid && rank == 0) sm.wl[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (tid < 34) {
+      unsigned run = 0;
+      for (int w = 0; w < 16; ++w) {
+        const unsigned c = sm.wl[w][tid];
+        sm.wl[w][tid] = run;
+        run += c;
+      }
+      sm.lcount[tid] = run;  // per-tile total (reused below)
+    }
+    __syncthreads();
+    if (valid) fn(i, d, sm.lbase[d] + sm.wl[wave][d] + rank);
+    __syncthreads();
+    if (tid < 34) {
+      sm.lbase[tid] += sm.lcount[tid];
+      for (int w = 0; w < 16; ++w) sm.wl[w][tid] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ hist,
+                                                    CodebookScratch s, uint32_t* __restrict__ code,
+                                                    uint8_t* __restrict__ clen,
+                                                    uint8_t* __restrict__ cb_out,
+                                                    Layout* __restrict__ lay) {
+  __shared__ CbSmem sm;
+  const int tid = threadIdx.x;
+  for (unsigned i = tid; i < kDict; i += 1024) {
+    clen[i] = 0;
+    code[i] = 0;
+  }
+  // 1. non-zero keys in ascending symbol order (each thread owns 64 symbols)
+  unsigned cnt = 0;
+  for (int k = 0; k < 64; ++k) cnt += hist[tid * 64 + k] != 0;
+  unsigned total;
+  unsigned off = block_excl_scan(cnt, sm.sm32, &total);
+  for (int k = 0; k < 64; ++k) {
+    const unsigned sy = tid * 64 + k;
+    const unsigned f = hist[sy];
+    if (f) {
+      s.symAsc[off] = sy;
+      s.freqAsc[off] = f;
+      ++off;
+    }
+  }
+  const unsigned n = total;
+  __syncthreads();
+  if (n == 0) {
+    if (tid == 0) lay->n_codes = 0;
+    return;
+  }
+  if (n == 1) {
+    if (tid == 0) {
+      const unsigned sy = s.symAsc[0];
+      clen[sy] = 1;
+      code[sy] = 0;
+      reinterpret_cast<uint16_t*>(cb_out)[0] = (uint16_t)sy;
+      cb_out[2] = 1;
+      lay->n_codes = 1;
+    }
+    return;
+  }
+  const uint32_t root = n - 2;
+  for (int flatten = 0;; ++flatten) {
+    if (flatten > 40) {  // 33 halvings bring every frequency to 1
+      if (tid == 0) lay->status |= ST_INTERNAL;
+      return;
+    }
+    // 2. sort leaves by (frequency, symbol): stable radix sort of indices
+    //    into the ascending-symbol list, keyed by frequency
+    unsigned fmax = 0;
+    for (unsigned i = tid; i < n; i += 1024) {
+      s.keyA[i] = s.freqAsc[i];
+      s.valA[i] = i;
+      fmax = max(fmax, s.freqAsc[i]);
+    }
+    fmax = block_max(fmax, sm.sm32);
+    const int bits = 32 - __clz(fmax);
+    __syncthreads();
+    const bool inB = block_radix_sort(s.keyA, s.valA, s.keyB, s.valB, n, bits, sm.sort);
+    const uint32_t* Lw = inB ? s.keyB : s.keyA;   // leaf weights, ascending
+    const uint32_t* Lx = inB ? s.valB : s.valA;   // leaf -> index into symAsc
+    __syncthreads();
+    // 3. two-queue merge in rounds
+    if (tid == 0) {
+      sm.m = 0;
+      sm.li = 0;
+      sm.ii = 0;
+      sm.nI = 0;
+    }
+    __syncthreads();
+    while (true) {
+      const unsigned m = sm.m, li = sm.li, ii = sm.ii, nI = sm.nI;
+      if (m == 2 * n - 2) break;
+      if (tid == 0) {
+        const unsigned long long INF = ~0ull;
+        const unsigned long long l0 = li < n ? Lw[li] : INF;
+        const unsigned long long l1 = li + 1 < n ? Lw[li + 1] : INF;
+        const unsigned long long i0 = ii < nI ? s.Iw[ii] : INF;
+        const unsigned long long i1 = ii + 1 < nI ? s.Iw[ii + 1] : INF;
+        unsigned long long t;
+        if (m & 1) {
+          t = (unsigned long long)s.Sw[m - 1] + (l0 < i0 ? l0 : i0);
+        } else {
+          // two smallest of the queue fronts
+          unsigned long long a = l0 < i0 ? l0 : i0;
+          unsigned long long b;
+          if (l0 < i0) b = l1 < i0 ? l1 : i0;
+          else b = l0 < i1 ? l0 : i1;
+          t = a + b;
+        }
+        sm.t = t;
+      }
+      __syncthreads();
+      const unsigned long long t = sm.t;
+      // leaves and internal nodes of weight <= t (prefixes of sorted queues)
+      unsigned la = li;
+      while (true) {
+        const unsigned idx = la + tid;
+        const bool ok = idx < n && (unsigned long long)Lw[idx] <= t;
+        const int c = __syncthreads_count(ok);
+        la += c;
+        if (c < 1024) break;
+      }
+      unsigned ib = ii;
+      while (true) {
+        const unsigned idx = ib + tid;
+        const bool ok = idx < nI && (unsigned long long)s.Iw[idx] <= t;
+        const int c = __syncthreads_count(ok);
+        ib += c;
+        if (c < 1024) break;
+      }
+      // merge: ties go to the leaf
+      for (unsigned x = li + tid; x < la; x += 1024) {
+        const uint32_t w = Lw[x];
+        const unsigned pos = m + (x - li) + lower_count(s.Iw + ii, ib - ii, w);
+        s.Sw[pos] = w;
+        s.leafPar[x] = pos >> 1;
+      }
+      for (unsigned y = ii + tid; y < ib; y += 1024) {
+        const uint32_t w = s.Iw[y];
+        const unsigned pos = m + (y - ii) + upper_count(Lw + li, la - li, w);
+        s.Sw[pos] = w;
+        s.parA[y] = pos >> 1;
+      }
+      __syncthreads();
+      const unsigned m_new = m + (la - li) + (ib - ii);
+      if (m_new == m) {  // every round takes at least the smallest node
+        if (tid == 0) lay->status |= ST_INTERNAL;
+        return;
+      }
+      for (unsigned j = nI + tid; j < m_new / 2; j += 1024) s.Iw[j] = s.Sw[2 * j] + s.Sw[2 * j + 1];
+      __syncthreads();
+      if (tid == 0) {
+        sm.m = m_new;
+        sm.li = la;
+        sm.ii = ib;
+        sm.nI = m_new / 2;
+      }
+      __syncthreads();
+    }
+    // 4. depths of internal nodes by pointer jumping towards the root
+    for (unsigned y = tid; y <= root; y += 1024) {
+      if (y == root) s.parA[y] = root;
+      s.dstA[y] = y == root ? 0u : 1u;
+    }
+    __syncthreads();
+    uint32_t *pa = s.parA, *pb = s.parB, *da = s.dstA, *db = s.dstB;
+    for (int jump = 0;; ++jump) {
+      if (jump > 40) {  // depth <= n - 1 < 2^17: 18 jumps suffice
+        if (tid == 0) lay->status |= ST_INTERNAL;
+        return;
+      }
+      bool more = false;
+      for (unsigned y = tid; y <= root; y += 1024) {
+        const uint32_t p = pa[y];
+        db[y] = da[y] + da[p];
+        pb[y] = pa[p];
+        more |= pa[p] != root;
+      }
+      const int any = __syncthreads_or(more);
+      uint32_t* tmp;
+      tmp = pa; pa = pb; pb = tmp;
+      tmp = da; da = db; db = tmp;
+      if (!any) break;
+    }
+    // 5. leaf lengths
+    unsigned lmax = 0;
+    for (unsigned x = tid; x < n; x += 1024) lmax = max(lmax, da[s.leafPar[x]] + 1u);
+    lmax = block_max(lmax, sm.sm32);
+    if (lmax <= (unsigned)kMaxCodeLen) {
+      for (unsigned x = tid; x < n; x += 1024) clen[s.symAsc[Lx[x]]] = (uint8_t)(da[s.leafPar[x]] + 1u);
+      __syncthreads();
+      break;
+    }
+    for (unsigned i = tid; i < n; i += 1024) s.freqAsc[i] = (s.freqAsc[i] + 1u) >> 1;
+    __syncthreads();
+  }
+  // 6. canonical codes: count per length, first code per length, then the
+  //    rank of each symbol among equal lengths in ascending symbol order
+  if (tid < 34) sm.lfirst[tid] = 0;
+  __syncthreads();
+  for (unsigned i = tid; i < n; i += 1024) atomicAdd(&sm.lfirst[clen[s.symAsc[i]]], 1u);
+  __syncthreads();
+  if (tid == 0) {
+    unsigned c = 0;
+    for (int l = 1; l <= kMaxCodeLen; ++l) {
+      const unsigned cntl = sm.lfirst[l];
+      sm.lfirst[l] = c;
+      c = (c + cntl) << 1;
+    }
+  }
+  __syncthreads();
+  stable_digit_ranks(
+      n, [&](unsigned i) { return (unsigned)clen[s.symAsc[i]]; },
+      [&](unsigned i, unsigned d, unsigned rank) { code[s.symAsc[i]] = sm.lfirst[d] + rank; },
+      sm);
+  // 7. codebook section: symbols ascending, then their lengths
+  uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
+  for (unsigned i = tid; i < n; i += 1024) {
+    const unsigned sy = s.symAsc[i];
+    cs[i] = (uint16_t)sy;
+    cb_out[2 * n + i] = clen[sy];
+  }
+  if (tid == 0) lay->n_codes = n;
+}
+
+// ---------------------------------------------------------------- encoding
+__global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict__ sym, int64_t N,
+                                                      int C, const uint8_t* __restrict__ clen,
+                                                      uint32_t* __restrict__ cw,
+                                                      const Layout* __restrict__ lay) {
+  if (lay->status) return;
+  const int64_t n_chunks = (N + C - 1) / C;
+  const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (chunk >= n_chunks) return;
+  const int64_t start = chunk * C;
+  const int64_t end = min<int64_t>(start + C, N);
+  unsigned bits = 0;
+  for (int64_t i = start + lane; i < end; i += 64) bits += clen[sym[i]];
+  for (int o = 32; o > 0; o >>= 1) bits += (unsigned)__shfl_xor((int)bits, o, 64);
+  if (lane == 0) cw[chunk] = (bits + 31u) >> 5;
+}
+
+__global__ __launch_bounds__(1024) void k_layout_scan(const uint32_t* __restrict__ cw,
+                                                       int64_t n_chunks, uint8_t* __restrict__ out,
+                                                       uint64_t cb_off, Layout* __restrict__ lay,
+                                                       const unsigned long long* n_out,
+                                                       uint64_t out_cap_n, int huff_only) {
+  __shared__ unsigned sm32[16];
+  __shared__ unsigned long long carry;
+  const int tid = threadIdx.x;
+  const unsigned long long n_codes = lay->n_codes;
+  const unsigned long long no = huff_only ? 0ull : *n_out;
+  if (no > out_cap_n) {
+    if (tid == 0) {
+      lay->n_outliers = no;
+      lay->status |= ST_OVERFLOW;
+    }
+    return;
+  }
+  const unsigned long long off = pad8(cb_off + 3 * n_codes);
+  const unsigned long long opos = off + 8ull * (n_chunks + 1);
+  const unsigned long long oval = opos + 8ull * no;
+  const unsigned long long words = oval + 8ull * no;
+  uint64_t* offs = reinterpret_cast<uint64_t*>(out + off);
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  // chunk-parallel exclusive scan in tiles of 1024 chunks
+  for (int64_t t0 = 0; t0 < n_chunks; t0 += 1024) {
+    const int64_t c = t0 + tid;
+    const unsigned v = c < n_chunks ? cw[c] : 0u;
+    unsigned tot;
+    const unsigned ex = block_excl_scan(v, sm32, &tot);
+    const unsigned long long base = carry;
+    if (c < n_chunks) offs[c] = base + ex;
+    __syncthreads();
+    if (tid == 0) carry = base + tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const unsigned long long nw = carry;
+    offs[n_chunks] = nw;
+    lay->n_outliers = no;
+    lay->n_words = nw;
+    lay->cb = cb_off;
+    lay->off = off;
+    lay->opos = opos;
+    lay->oval = oval;
+    lay->words = words;
+    lay->end = pad8(words + 4ull * nw);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_outlier_sort(const OutlierBuf ob, uint32_t* keyA,
+                                                        uint32_t* valA, uint32_t* keyB,
+                                                        uint32_t* valB, int key_bits,
+                                                        uint8_t* __restrict__ out,
+                                                        const Layout* __restrict__ lay) {
+  __shared__ SortSmem sm;
+  if (lay->status) return;
+  const uint32_t n = (uint32_t)lay->n_outliers;
+  if (n == 0) return;
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) {
+    keyA[i] = ob.pos[i];
+    valA[i] = i;
+  }
+  __syncthreads();
+  const bool inB = block_radix_sort(keyA, valA, keyB, valB, n, key_bits, sm);
+  const uint32_t* ks = inB ? keyB : keyA;
+  const uint32_t* vs = inB ? valB : valA;
+  uint64_t* op = reinterpret_cast<uint64_t*>(out + lay->opos);
+  int64_t* ov = reinterpret_cast<int64_t*>(out + lay->oval);
+  for (uint32_t i = threadIdx.x; i < n; i += 1024) {
+    op[i] = ks[i];
+    ov[i] = ob.val[vs[i]];
+  }
+}
+
+// One wavefront per chunk, four chunks per block; LDS holds each chunk's
+// words while codes are OR-ed into place.
+__global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym, int64_t N, int C,
+                                                 const uint32_t* __restrict__ code,
+                                                 const uint8_t* __restrict__ clen,
+                                                 uint8_t* __restrict__ out,
+                                                 const Layout* __restrict__ lay) {
+  extern __shared__ uint32_t wbuf[];  // 4 * C words
+  if (lay->status) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t n_chunks = (N + C - 1) / C;
+  const int64_t chunk = (int64_t)blockIdx.x * 4 + wave;
+  uint32_t* w = wbuf + wave * C;
+  for (int i = lane; i < C; i += 64) w[i] = 0;
+  __syncthreads();
+  const uint64_t* offs = reinterpret_cast<const uint64_t*>(out + lay->off);
+  uint32_t* words = reinterpret_cast<uint32_t*>(out + lay->words);
+  const bool live = chunk < n_chunks;
+  const int per = C / 64;
+  int64_t start = 0, end = 0;
+  unsigned my_bits = 0;
+  if (live) {
+    start = chunk * C;
+    end = min<int64_t>(start + C, N);
+    const int64_t a = start + (int64_t)lane * per;
+    for (int k = 0; k < per; ++k)
+      if (a + k < end) my_bits += clen[sym[a + k]];
+  }
+  // exclusive prefix over lanes
+  unsigned x = my_bits;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = (unsigned)__shfl_up((int)x, o, 64);
+    if (lane >= o) x += y;
+  }
+  unsigned bitpos = x - my_bits;
+  if (live) {
+    const int64_t a = start + (int64_t)lane * per;
+    for (int k = 0; k < per; ++k) {
+      if (a + k >= end) break;
+      const unsigned sy = sym[a + k];
+      const unsigned l = clen[sy];
+      const uint32_t c = code[sy];
+      const unsigned wi = bitpos >> 5, o = bitpos & 31u;
+      if (o + l <= 32u) {
+        atomicOr(&w[wi], c << (32u - o - l));
+      } else {
+        atomicOr(&w[wi], c >> (o + l - 32u));
+        atomicOr(&w[wi + 1], c << (64u - o - l));
+      }
+      bitpos += l;
+    }
+  }
+  __syncthreads();
+  if (live) {
+    const uint64_t w0 = offs[chunk], nw = offs[chunk + 1] - w0;
+    for (uint64_t i = lane; i < nw; i += 64) words[w0 + i] = w[i];
+  }
+}
+
+struct QArgs {
+  double q[kMaxLevels + 1];
+};
+
+__global__ void k_header(uint8_t* __restrict__ out, Header h, const QArgs qa, int nq,
+                         const Layout* __restrict__ lay, const unsigned* status,
+                         unsigned long long* info) {
+  if (threadIdx.x != 0) return;
+  const unsigned st = lay->status | (status ? *status : 0u);
+  info[0] = st;
+  info[1] = lay->n_outliers;
+  info[2] = lay->end;
+  if (st) return;
+  h.n_codes = lay->n_codes;
+  h.n_outliers = lay->n_outliers;
+  h.n_words = lay->n_words;
+  h.total = lay->end;
+  const uint8_t* src = reinterpret_cast<const uint8_t*>(&h);
+  for (int i = 0; i < kHeaderBytes; ++i) out[i] = src[i];
+  double* q = reinterpret_cast<double*>(out + kHeaderBytes);
+  for (int i = 0; i < nq; ++i) q[i] = qa.q[i];
+  // zero the padding bytes after the codebook and after the words
+  for (uint64_t i = lay->cb + 3 * lay->n_codes; i < lay->off; ++i) out[i] = 0;
+  for (uint64_t i = lay->words + 4 * lay->n_words; i < lay->end; ++i) out[i] = 0;
+}
+
+__global__ void k_huff_header(uint8_t* __restrict__ out, uint32_t C, uint64_t N, uint64_t n_chunks,
+                              const Layout* __restrict__ lay, unsigned long long* info) {
+  if (threadIdx.x != 0) return;
+  info[0] = lay->status;
+  info[1] = 0;
+  info[2] = lay->end;
+  HuffHeader h;
+  h.magic = kHuffMagic;
+  h.C = C;
+  h.N = N;
+  h.n_codes = lay->n_codes;
+  h.n_chunks = n_chunks;
+  h.n_words = lay->n_words;
+  h.total = lay->end;
+  const uint8_t* src = reinterpret_cast<const uint8_t*>(&h);
+  for (int i = 0; i < kHuffHeaderBytes; ++i) out[i] = src[i];
+  for (uint64_t i = lay->cb + 3 * lay->n_codes; i < lay->off; ++i) out[i] = 0;
+  for (uint64_t i = lay->words + 4 * lay->n_words; i < lay->end; ++i) out[i] = 0;
+}
+
+// ---------------------------------------------------------------- decoding
+__global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restrict__ cb,
+                                                         uint64_t n_codes,
+                                                         DecodeTables* __restrict__ t,
+                                                         unsigned* status) {
+  __shared__ CbSmem sm;
+  const int tid = threadIdx.x;
+  const uint16_t* syms = reinterpret_cast<const uint16_t*>(cb);
+  const uint8_t* lens = cb + 2 * n_codes;
+  const unsigned n = (unsigned)n_codes;
+  if (tid < 34) sm.lcount[tid] = 0;
+  if (tid == 0) sm.flag = 0;
+  for (unsigned i = tid; i < (1u << kLutBits); i += 1024) t->lut[i] = 0;
+  __syncthreads();
+  for (unsigned i = tid; i < n; i += 1024) {
+    const unsigned l = lens[i];
+    if (l < 1 || l > (unsigned)kMaxCodeLen || (i > 0 && syms[i] <= syms[i - 1])) sm.flag = 1;
+    else atomicAdd(&sm.lcount[l], 1u);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned c = 0, idx = 0, maxlen = 0;
+    unsigned long long kraft = 0;
+    for (int l = 1; l <= kMaxCodeLen; ++l) {
+      const unsigned cnt = sm.lcount[l];
+      t->first[l] = c;
+      t->count[l] = cnt;
+      t->base[l] = idx;
+      t->limit[l] = ((unsigned long long)c + cnt) << (32 - l);
+      sm.lfirst[l] = c;
+      sm.lbase[l] = idx;
+      kraft += (unsigned long long)cnt << (32 - l);
+      idx += cnt;
+      c = (c + cnt) << 1;
+      if (cnt) maxlen = l;
+    }
+    t->maxlen = maxlen;
+    if (kraft > (1ull << 32) || (n >= 2 && kraft != (1ull << 32))) sm.flag = 1;
+  }
+  __syncthreads();
+  if (sm.flag) {
+    if (tid == 0) atomicOr(status, ST_FORMAT);
+    return;
+  }
+  __shared__ unsigned lfirst[34], lbase[34];
+  if (tid < 34) {
+    lfirst[tid] = sm.lfirst[tid];
+    lbase[tid] = sm.lbase[tid];
+  }
+  __syncthreads();
+  stable_digit_ranks(
+      n, [&](unsigned i) { return (unsigned)lens[i]; },
+      [&](unsigned i, unsigned d, unsigned rank) {
+        const unsigned sy = syms[i];
+        t->sorted[lbase[d] + rank] = (uint16_t)sy;
+        if (d <= (unsigned)kLutBits) {
+          const unsigned c = lfirst[d] + rank;
+          const unsigned a = c << (kLutBits - d), b = (c + 1) << (kLutBits - d);
+          for (unsigned e = a; e < b; ++e) t->lut[e] = sy | (d << 16);
+        }
+      },
+      sm);
+}
+
+__global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, uint64_t off_sec,
+                                                 uint64_t words_sec, uint64_t n_chunks,
+                                                 uint64_t n_words, int C, int64_t N,
+                                                 const DecodeTables* __restrict__ t,
+                                                 uint16_t* __restrict__ sym, unsigned* status) {
+  __shared__ uint32_t lut[1 << kLutBits];
+  __shared__ uint32_t first[34], base[34];
+  __shared__ uint64_t limit[34];
+  __shared__ uint32_t maxlen;
+  for (int i = threadIdx.x; i < (1 << kLutBits); i += 256) lut[i] = t->lut[i];
+  if (threadIdx.x < 34) {
+    first[threadIdx.x] = t->first[threadIdx.x];
+    base[threadIdx.x] = t->base[threadIdx.x];
+    limit[threadIdx.x] = t->limit[threadIdx.x];
+  }
+  if (threadIdx.x == 0) maxlen = t->maxlen;
+  __syncthreads();
+  const uint64_t chunk = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (chunk >= n_chunks) return;
+  const uint64_t* offs = reinterpret_cast<const uint64_t*>(in + off_sec);
+  const uint32_t* words = reinterpret_cast<const uint32_t*>(in + words_sec);
+  const uint64_t w0 = offs[chunk], w1 = offs[chunk + 1];
+  if (w0 > w1 || w1 > n_words) {
+    atomicOr(status, ST_FORMAT);
+    return;
+  }
+  const int64_t start = (int64_t)chunk * C;
+  const int cnt = (int)min<int64_t>(C, N - start);
+  uint64_t buf = 0;
+  int nb = 0;
+  uint64_t wi = w0;
+  bool bad = false;
+  for (int k = 0; k < cnt; ++k) {
+    while (nb <= 32) {
+      const uint32_t w = wi < w1 ? words[wi] : 0u;
+      ++wi;
+      buf |= (uint64_t)w << (32 - nb);
+      nb += 32;
+    }
+    const uint32_t peek = (uint32_t)(buf >> 32);
+    const uint32_t e = lut[peek >> (32 - kLutBits)];
+    unsigned len = e >> 16;
+    uint32_t s;
+    if (len) {
+      s = e & 0xFFFFu;
+    } else {
+      len = kLutBits + 1;
+      while (len <= maxlen && (uint64_t)peek >= limit[len]) ++len;
+      if (len > maxlen) {
+        bad = true;
+        break;
+      }
+      s = t->sorted[base[len] + ((peek >> (32 - len)) - first[len])];
+    }
+    buf <<= len;
+    nb -= (int)len;
+    sym[start + k] = (uint16_t)s;
+  }
+  if (bad || (int64_t)(wi - w0) * 32 - nb > (int64_t)(w1 - w0) * 32) atomicOr(status, ST_FORMAT);
+}
+
+}  // namespace
+
+void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s) {
+  int64_t blocks = (n + 1024 * 32 - 1) / (1024 * 32);
+  if (blocks < 1) blocks = 1;
+  if (blocks > 512) blocks = 512;
+  hipLaunchKernelGGL(k_histogram, dim3((unsigned)blocks), dim3(1024), 0, s, sym, n, hist);
+}
+
+void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
+                     uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, s, hist, sc, code, clen,
+                     cb_out_base + cb_off, lay);
+}
+
+void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
+                        uint32_t* cw, Layout* lay, hipStream_t s) {
+  const int64_t n_chunks = (N + C - 1) / C;
+  hipLaunchKernelGGL(k_chunk_words, dim3((unsigned)((n_chunks + 3) / 4)), dim3(256), 0, s, sym,
+                     N, C, clen, cw, lay);
+}
+
+void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint64_t cb_off,
+                        Layout* lay, const unsigned long long* n_out, uint64_t out_cap_n,
+                        bool huff_only, hipStream_t s) {
+  hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(1024), 0, s, cw, n_chunks, out, cb_off, lay,
+                     n_out, out_cap_n, huff_only ? 1 : 0);
+}
+
+void launch_outlier_sort(const OutlierBuf& ob, uint32_t* keyA, uint32_t* valA, uint32_t* keyB,
+                         uint32_t* valB, int key_bits, uint8_t* out, Layout* lay,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_outlier_sort, dim3(1), dim3(1024), 0, s, ob, keyA, valA, keyB, valB,
+                     key_bits, out, lay);
+}
+
+void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
+                   const uint8_t* clen, uint8_t* out, const Layout* lay, hipStream_t s) {
+  const int64_t n_chunks = (N + C - 1) / C;
+  hipLaunchKernelGGL(k_encode, dim3((unsigned)((n_chunks + 3) / 4)), dim3(256),
+                     (size_t)4 * C * sizeof(uint32_t), s, sym, N, C, code, clen, out, lay);
+}
+
+void launch_header(uint8_t* out, const Header& h, const double* q, int nq, const Layout* lay,
+                   const unsigned* status, unsigned long long* info, hipStream_t s) {
+  QArgs qa{};
+  for (int i = 0; i < nq && i <= kMaxLevels; ++i) qa.q[i] = q[i];
+  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, out, h, qa, nq, lay, status, info);
+}
+
+void launch_huff_header(uint8_t* out, uint32_t C, uint64_t N, uint64_t n_chunks,
+                        const Layout* lay, unsigned long long* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_huff_header, dim3(1), dim3(64), 0, s, out, C, N, n_chunks, lay, info);
+}
+
+void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
+                          unsigned* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(1024), 0, s, cb, n_codes, t, status);
+}
+
+void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
+                   uint64_t n_words, int C, int64_t N, const DecodeTables* t, uint16_t* sym,
+                   unsigned* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_decode, dim3((unsigned)((n_chunks + 255) / 256)), dim3(256), 0, s, in,
+                     off_sec, words_sec, n_chunks, n_words, C, N, t, sym, status);
+}
+
+}  // namespace mgc

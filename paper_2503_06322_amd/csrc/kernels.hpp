@@ -1,0 +1,77 @@
+// Launch wrappers of the HIP kernels (defined in transform.hip and
+// huffman.hip), called by the host orchestration in api.cpp.
+#pragma once
+
+#include "common.hpp"
+
+namespace mgc {
+
+// ---- transform.hip -------------------------------------------------------
+constexpr int kRangeBlocks = 1024;
+// min, max, sum of squares and non-finite count of u (dtype dt) -> out[4].
+void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, double* out,
+                  hipStream_t s);
+// One decomposition level: coefficients of the level's new nodes (quantised
+// to symbols when sym != nullptr, else FP64 into raw) and the restriction
+// f = (P^T M_l) G_l onto the coarse grid (fout, FP64).
+void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* fout,
+                      uint16_t* sym, double* raw, double r, const OutlierBuf& ob,
+                      unsigned* status, hipStream_t s);
+// Solve the coarse mass matrix along internal axis `axis` for every line of
+// x (coarse grid nc).  When sub != nullptr, x <- sub - solution.
+void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
+                   const double* sub, hipStream_t s);
+// Level-0 block: values of G0 (m0 entries) quantised (sym) or copied (raw).
+void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
+                   double r, const OutlierBuf& ob, unsigned* status, hipStream_t s);
+// Recomposition: f = (P^T M_l) c_l on the coarse grid from the coefficients.
+void launch_rec_restrict(const LevelGeom& g, const CoeffSrc& src, double q, double* fout,
+                         hipStream_t s);
+// Recomposition: G_l = P Gc + c_l (out in FP32 or FP64).
+void launch_rec_interp(const double* Gc, const LevelGeom& g, const CoeffSrc& src, double q,
+                       void* out, bool out_f32, hipStream_t s);
+void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, bool out_f32,
+                       hipStream_t s);
+void launch_fill(void* out, bool out_f32, int64_t N, double v, hipStream_t s);
+
+// ---- huffman.hip ---------------------------------------------------------
+struct CodebookScratch {
+  uint32_t *keyA, *valA, *keyB, *valB, *symAsc, *freqAsc, *Iw, *Sw, *leafPar, *parA, *parB,
+      *dstA, *dstB;
+};
+size_t codebook_scratch_bytes();
+CodebookScratch carve_codebook_scratch(void* base);
+
+struct DecodeTables;
+size_t decode_tables_bytes();
+
+void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s);
+void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
+                     uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
+                     hipStream_t s);
+void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
+                        uint32_t* cw, Layout* lay, hipStream_t s);
+// Section layout + exclusive scan of the chunk word counts into the stream's
+// offsets section.  huff_only selects the Huffman-only stream layout.
+void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint64_t cb_off,
+                        Layout* lay, const unsigned long long* n_out, uint64_t out_cap_n,
+                        bool huff_only, hipStream_t s);
+void launch_outlier_sort(const OutlierBuf& ob, uint32_t* keyA, uint32_t* valA, uint32_t* keyB,
+                         uint32_t* valB, int key_bits, uint8_t* out, Layout* lay,
+                         hipStream_t s);
+void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
+                   const uint8_t* clen, uint8_t* out, const Layout* lay, hipStream_t s);
+// Writes the header and bins (q holds nq <= kMaxLevels + 1 host values) once
+// the layout is known; info <- {status bits, outliers, stream bytes}.
+void launch_header(uint8_t* out, const Header& h, const double* q, int nq, const Layout* lay,
+                   const unsigned* status, unsigned long long* info, hipStream_t s);
+void launch_huff_header(uint8_t* out, uint32_t C, uint64_t N, uint64_t n_chunks,
+                        const Layout* lay, unsigned long long* info, hipStream_t s);
+
+void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
+                          unsigned* status, hipStream_t s);
+void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
+                   uint64_t n_words, int C, int64_t N, const DecodeTables* t, uint16_t* sym,
+                   unsigned* status, hipStream_t s);
+
+}  // namespace mgc

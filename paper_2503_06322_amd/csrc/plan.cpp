@@ -1,0 +1,278 @@
+// Host plan: the level hierarchy and per-axis operator tables of one shape.
+//
+// Hierarchy (Algorithm 1 builds it from the input; the coarsening rule for
+// sizes other than 2^k + 1 is not given in the paper): axis coordinates are
+// the grid indices; a coarsening step keeps the even positions of a level and,
+// when its node count is even, also its last node; all axes longer than 1
+// coarsen together until the shortest has 2 nodes.
+//
+// Operators (Section IV-A: the data is the piecewise linear function through
+// the nodal values; lerp, mass_trans and tridiag of Algorithm 1): P is the
+// prolongation of coarse hat functions into the fine basis, M the mass matrix
+// of the hats on one level.  Per coarse node j the restriction row of
+// P^T M_l has five taps at fine positions p(j)-2 .. p(j)+2; the tridiagonal
+// coarse mass matrix is pre-factored for the Thomas sweeps.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+#pragma clang fp contract(off)
+
+namespace mgc {
+
+namespace {
+
+inline int64_t cpos(int64_t j, int64_t nf) { return std::min<int64_t>(2 * j, nf - 1); }
+inline bool is_new(int64_t i, int64_t nf) { return (i & 1) && !(i == nf - 1); }
+
+std::vector<double> coarse_coords(const std::vector<double>& x) {
+  const int64_t n = (int64_t)x.size();
+  std::vector<double> out;
+  for (int64_t i = 0; i < n; i += 2) out.push_back(x[i]);
+  if (n % 2 == 0) out.push_back(x[n - 1]);
+  return out;
+}
+
+// Mass-matrix entry M(f, g) of the hats on nodes x.
+double mass_entry(const std::vector<double>& x, int64_t f, int64_t g) {
+  const int64_t n = (int64_t)x.size();
+  if (g < 0 || g >= n) return 0.0;
+  if (f == g) {
+    double hl = f > 0 ? x[f] - x[f - 1] : 0.0;
+    double hr = f < n - 1 ? x[f + 1] - x[f] : 0.0;
+    return (hl + hr) / 3.0;
+  }
+  if (f - g == 1 || g - f == 1) return (x[std::max(f, g)] - x[std::min(f, g)]) / 6.0;
+  return 0.0;
+}
+
+}  // namespace
+
+Plan build_plan(int ndim, const uint64_t* shape) {
+  Plan p;
+  if (ndim < 1) fail(MGC_EINVAL, "ndim must be at least 1");
+  if (ndim > 3) fail(MGC_EUNSUPPORTED, "ndim above 3 is not supported");
+  if (!shape) fail(MGC_EINVAL, "null shape");
+  p.ndim = ndim;
+  unsigned __int128 N = 1;
+  std::vector<int64_t> act;
+  for (int d = 0; d < ndim; ++d) {
+    p.shape[d] = shape[d];
+    N *= shape[d];
+    if (shape[d] > 1) act.push_back((int64_t)shape[d]);
+  }
+  if (N >= ((unsigned __int128)1 << 32)) fail(MGC_EUNSUPPORTED, "arrays of 2^32 or more values");
+  p.N = (int64_t)N;
+  if (p.N == 0) act.clear();
+  p.D = (int)act.size();
+  for (int k = 0; k < 3; ++k) {
+    int d = k - (3 - p.D);
+    p.n[k] = d >= 0 ? act[d] : 1;
+    p.bit[k] = d >= 0 ? d : -1;
+  }
+  // hierarchy: collect levels finest first
+  std::vector<std::array<int64_t, 3>> fine_first{{p.n[0], p.n[1], p.n[2]}};
+  std::vector<std::array<std::vector<double>, 3>> coords(1);
+  for (int k = 0; k < 3; ++k) {
+    coords[0][k].resize(p.n[k]);
+    for (int64_t i = 0; i < p.n[k]; ++i) coords[0][k][i] = (double)i;
+  }
+  if (p.D > 0 && p.N > 0) {
+    while (true) {
+      auto cur = fine_first.back();
+      int64_t mn = INT64_MAX;
+      for (int k = 0; k < 3; ++k)
+        if (p.bit[k] >= 0) mn = std::min(mn, cur[k]);
+      if (mn <= 2) break;
+      std::array<int64_t, 3> nxt;
+      std::array<std::vector<double>, 3> c;
+      for (int k = 0; k < 3; ++k) {
+        if (p.bit[k] >= 0) {
+          c[k] = coarse_coords(coords.back()[k]);
+          nxt[k] = (int64_t)c[k].size();
+        } else {
+          c[k] = coords.back()[k];
+          nxt[k] = cur[k];
+        }
+      }
+      fine_first.push_back(nxt);
+      coords.push_back(c);
+      if ((int)fine_first.size() > kMaxLevels) fail(MGC_EUNSUPPORTED, "too many levels");
+    }
+  }
+  p.L = (int)fine_first.size() - 1;
+  p.sizes.assign(fine_first.rbegin(), fine_first.rend());
+  std::reverse(coords.begin(), coords.end());  // coords[l], l = 0..L
+
+  p.lv.resize(p.L + 1);
+  int64_t off = 0;
+  for (int l = 0; l <= p.L; ++l) {
+    PlanLevel& v = p.lv[l];
+    for (int k = 0; k < 3; ++k) {
+      v.nf[k] = p.sizes[l][k];
+      v.nc[k] = l > 0 ? p.sizes[l - 1][k] : p.sizes[l][k];
+      const auto& x = coords[l][k];
+      double hm = 1.0;
+      if (p.bit[k] >= 0 && x.size() > 1) {
+        hm = 0.0;
+        for (size_t i = 0; i + 1 < x.size(); ++i) hm = std::max(hm, x[i + 1] - x[i]);
+      }
+      v.hmax[k] = hm;
+    }
+    v.off = off;
+    v.count = l == 0 ? p.points(0) : p.points(l) - p.points(l - 1);
+    off += v.count;
+    for (int m = 0; m < 8; ++m) v.sub_off[m] = 0;
+    if (l >= 1) {
+      int64_t acc = 0;
+      for (int m = 1; m < (1 << p.D); ++m) {
+        v.sub_off[m] = acc;
+        int64_t sz = 1;
+        for (int k = 0; k < 3; ++k) {
+          bool nw = p.bit[k] >= 0 && ((m >> p.bit[k]) & 1);
+          sz *= nw ? (v.nf[k] - v.nc[k]) : v.nc[k];
+        }
+        acc += sz;
+      }
+      // tables
+      for (int k = 0; k < 3; ++k) {
+        const int64_t nf = v.nf[k], nc = v.nc[k];
+        const auto& xf = coords[l][k];
+        const auto& xc = coords[l - 1][k];
+        v.t_wl[k] = p.tab.size();
+        p.tab.resize(p.tab.size() + nf, 0.0);
+        v.t_wr[k] = p.tab.size();
+        p.tab.resize(p.tab.size() + nf, 0.0);
+        v.t_W[k] = p.tab.size();
+        p.tab.resize(p.tab.size() + 5 * nc, 0.0);
+        v.t_ta[k] = p.tab.size();
+        p.tab.resize(p.tab.size() + nc, 0.0);
+        v.t_tm[k] = p.tab.size();
+        p.tab.resize(p.tab.size() + nc, 0.0);
+        v.t_tc[k] = p.tab.size();
+        p.tab.resize(p.tab.size() + nc, 0.0);
+        double* wl = &p.tab[v.t_wl[k]];
+        double* wr = &p.tab[v.t_wr[k]];
+        double* W = &p.tab[v.t_W[k]];
+        double* ta = &p.tab[v.t_ta[k]];
+        double* tm = &p.tab[v.t_tm[k]];
+        double* tc = &p.tab[v.t_tc[k]];
+        if (p.bit[k] < 0) {  // inactive axis: identity operators
+          W[2] = 1.0;
+          tm[0] = 1.0;
+          continue;
+        }
+        for (int64_t i = 0; i < nf; ++i) {
+          if (!is_new(i, nf)) continue;
+          const double xa = xf[i - 1], xb = xf[i + 1], xi = xf[i];
+          wl[i] = (xb - xi) / (xb - xa);
+          wr[i] = (xi - xa) / (xb - xa);
+        }
+        for (int64_t j = 0; j < nc; ++j) {
+          const int64_t pj = cpos(j, nf);
+          for (int d = -2; d <= 2; ++d) {
+            double acc2 = 0.0;
+            for (int64_t f = pj - 1; f <= pj + 1; ++f) {
+              if (f < 0 || f >= nf) continue;
+              double pf;
+              if (f == pj) pf = 1.0;
+              else if (is_new(f, nf) && f - 1 == pj) pf = wl[f];
+              else if (is_new(f, nf) && f + 1 == pj) pf = wr[f];
+              else pf = 0.0;
+              if (pf != 0.0) acc2 += pf * mass_entry(xf, f, pj + d);
+            }
+            W[5 * j + d + 2] = acc2;
+          }
+        }
+        // Thomas factors of the coarse mass matrix
+        double cprev = 0.0;
+        for (int64_t j = 0; j < nc; ++j) {
+          const double Hl = j > 0 ? xc[j] - xc[j - 1] : 0.0;
+          const double Hr = j < nc - 1 ? xc[j + 1] - xc[j] : 0.0;
+          const double a = Hl / 6.0, b = (Hl + Hr) / 3.0, s = Hr / 6.0;
+          const double den = j > 0 ? b - a * cprev : b;
+          const double mj = 1.0 / den;
+          ta[j] = a;
+          tm[j] = mj;
+          tc[j] = s * mj;
+          cprev = tc[j];
+        }
+      }
+    }
+  }
+  return p;
+}
+
+void upload_plan(Plan& p) {
+  if (p.d_tab || p.tab.empty()) return;
+  MGC_HIP(hipMalloc(&p.d_tab, p.tab.size() * sizeof(double)));
+  MGC_HIP(hipMemcpy(p.d_tab, p.tab.data(), p.tab.size() * sizeof(double),
+                    hipMemcpyHostToDevice));
+}
+
+void free_plan(Plan& p) {
+  if (p.d_tab) (void)hipFree(p.d_tab);
+  p.d_tab = nullptr;
+}
+
+LevelGeom Plan::geom(int l) const {
+  LevelGeom g{};
+  const PlanLevel& v = lv[l];
+  for (int k = 0; k < 3; ++k) {
+    g.nf[k] = v.nf[k];
+    g.nc[k] = v.nc[k];
+    g.bit[k] = bit[k];
+    if (l >= 1) {
+      g.ax[k].wl = d_tab + v.t_wl[k];
+      g.ax[k].wr = d_tab + v.t_wr[k];
+      g.ax[k].W = d_tab + v.t_W[k];
+      g.ax[k].ta = d_tab + v.t_ta[k];
+      g.ax[k].tm = d_tab + v.t_tm[k];
+      g.ax[k].tc = d_tab + v.t_tc[k];
+    }
+  }
+  g.level_off = v.off;
+  for (int m = 0; m < 8; ++m) g.sub_off[m] = v.sub_off[m];
+  return g;
+}
+
+std::vector<double> Plan::bin_factors(mgc_norm norm) const {
+  std::vector<double> K(L + 1);
+  int64_t pow3 = 1, pow6 = 1;
+  for (int d = 0; d < D; ++d) {
+    pow3 *= 3;
+    pow6 *= 6;
+  }
+  for (int l = 0; l <= L; ++l) {
+    if (norm == MGC_LINF) {
+      K[l] = 2.0 / (double)(1 + (int64_t)L * (1 + pow3));
+    } else {
+      double den = (double)pow6 * (double)(L + 1);
+      for (int k = 0; k < 3; ++k)
+        if (bit[k] >= 0) den = den * lv[l].hmax[k];
+      den = den * (double)lv[l].count;
+      K[l] = 2.0 / std::sqrt(den);
+    }
+  }
+  return K;
+}
+
+void error_budget(mgc_dtype dt, mgc_norm norm, mgc_mode mode, double bound, double umin,
+                  double umax, double sumsq, int64_t N, double* tau, double* tau_eff) {
+  const double eps = dt == MGC_F32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+  const double margin = std::ldexp(1.0, -36);
+  const double amax = std::max(std::fabs(umax), std::fabs(umin));
+  double t, A;
+  if (norm == MGC_LINF) {
+    t = mode == MGC_REL ? bound * (umax - umin) : bound;
+    A = amax;
+  } else {
+    t = mode == MGC_REL ? bound * std::sqrt(sumsq) : bound;
+    A = std::sqrt((double)N) * amax;
+  }
+  *tau = t;
+  *tau_eff = t - (eps + margin) * (A + t);
+}
+
+}  // namespace mgc

@@ -1,0 +1,80 @@
+"""GPU Huffman stage: bit-exact against the oracle on identical symbols."""
+import struct
+
+import numpy as np
+import pytest
+
+from oracle import huffman
+from tests.gpu_common import gpu, oracle_huffman_stream, to_bytes
+
+pytestmark = pytest.mark.gpu
+
+
+def _laplace_symbols(n, scale, seed):
+    rng = np.random.default_rng(seed)
+    k = np.round(rng.laplace(0, scale, size=n)).astype(np.int64)
+    return np.clip(k + 32768, 0, 65535).astype(np.int64)
+
+
+CASES = [  # (n, scale, C)
+    (1, 3.0, 1024), (1000, 3.0, 1024), (1024, 3.0, 1024), (5000, 0.2, 1024),
+    (100003, 40.0, 1024), (300000, 3000.0, 1024), (70000, 5.0, 64), (4097, 2.0, 128),
+    (2_000_000, 9000.0, 1024),
+]
+
+
+@pytest.mark.parametrize("n,scale,C", CASES)
+def test_encode_bit_exact(n, scale, C):
+    torch, mgc = gpu()
+    sym = _laplace_symbols(n, scale, n)
+    t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
+    got = to_bytes(mgc.huffman_encode(t, C))
+    ref = oracle_huffman_stream(sym, C)
+    assert len(got) == len(ref)
+    assert got == ref
+    back = mgc.huffman_decode(mgc.huffman_encode(t, C), n).cpu().numpy().view(np.uint16)
+    assert np.array_equal(back.astype(np.int64), sym)
+
+
+def test_single_symbol_and_all_symbols():
+    torch, mgc = gpu()
+    for sym in (np.full(5000, 7, dtype=np.int64), np.arange(65536, dtype=np.int64),
+                np.repeat(np.arange(65536, dtype=np.int64), 3)):
+        t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
+        got = to_bytes(mgc.huffman_encode(t, 1024))
+        assert got == oracle_huffman_stream(sym, 1024)
+        back = mgc.huffman_decode(mgc.huffman_encode(t, 1024), len(sym)).cpu().numpy().view(np.uint16)
+        assert np.array_equal(back.astype(np.int64), sym)
+
+
+def test_length_limit_flattening_matches_oracle():
+    torch, mgc = gpu()
+    fib = [1, 1]
+    while len(fib) < 40:
+        fib.append(fib[-1] + fib[-2])
+    sym = np.repeat(np.arange(40, dtype=np.int64) * 7 + 100, fib)
+    rng = np.random.default_rng(3)
+    rng.shuffle(sym)
+    ln = huffman.code_lengths(huffman.histogram(sym, 65536))
+    assert ln.max() <= 32
+    t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
+    assert to_bytes(mgc.huffman_encode(t, 1024)) == oracle_huffman_stream(sym, 1024)
+
+
+def test_gpu_decodes_oracle_stream_and_rejects_corruption():
+    torch, mgc = gpu()
+    sym = _laplace_symbols(50000, 30.0, 5)
+    ref = oracle_huffman_stream(sym, 1024)
+    dev = torch.from_numpy(np.frombuffer(ref, dtype=np.uint8).copy()).cuda()
+    back = mgc.huffman_decode(dev, len(sym)).cpu().numpy().view(np.uint16)
+    assert np.array_equal(back.astype(np.int64), sym)
+    bad = bytearray(ref)
+    n_codes = struct.unpack_from("<Q", ref, 16)[0]
+    bad[48 + 2 * n_codes] = 0    # the first code length becomes 0
+    with pytest.raises(mgc.MgcError) as e:
+        mgc.huffman_decode(torch.from_numpy(np.frombuffer(bytes(bad), dtype=np.uint8).copy()).cuda(),
+                           len(sym))
+    assert e.value.name == "EFORMAT"
+    with pytest.raises(mgc.MgcError) as e:
+        mgc.huffman_decode(dev[: len(ref) - 64], len(sym))
+    assert e.value.name == "EFORMAT"
