@@ -424,6 +424,8 @@ mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t*
     if (p.N == 0) {
       h.flags = FLAG_EMPTY;
       h.n_chunks = 0;
+      h.D = 0;  // number of axes longer than 1, as given
+      for (int d = 0; d < ndim; ++d) h.D += shape[d] > 1;
       *h_out_size = write_trivial_stream(ctx, h, d_out, s);
       return;
     }

@@ -34,6 +34,7 @@ struct DecodeTables {
   uint32_t base[34];
   uint64_t limit[34];   // left-justified exclusive upper bound of each length
   uint32_t maxlen;
+  uint32_t valid;               // 1 only after a codebook passed validation
   uint32_t lut[1 << kLutBits];  // symbol | length << 16 (length 0: longer code)
   uint16_t sorted[kDict];       // symbols in (length, symbol) order
 };
@@ -690,7 +691,10 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
   const uint8_t* lens = cb + 2 * n_codes;
   const unsigned n = (unsigned)n_codes;
   if (tid < 34) sm.lcount[tid] = 0;
-  if (tid == 0) sm.flag = 0;
+  if (tid == 0) {
+    sm.flag = 0;
+    t->valid = 0;
+  }
   for (unsigned i = tid; i < (1u << kLutBits); i += 1024) t->lut[i] = 0;
   __syncthreads();
   for (unsigned i = tid; i < n; i += 1024) {
@@ -741,6 +745,7 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
         }
       },
       sm);
+  if (tid == 0) t->valid = 1;
 }
 
 __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, uint64_t off_sec,
@@ -749,16 +754,20 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
                                                  const DecodeTables* __restrict__ t,
                                                  uint16_t* __restrict__ sym, unsigned* status) {
   __shared__ uint32_t lut[1 << kLutBits];
-  __shared__ uint32_t first[34], base[34];
+  __shared__ uint32_t first[34], count[34], base[34];
   __shared__ uint64_t limit[34];
-  __shared__ uint32_t maxlen;
+  __shared__ uint32_t maxlen, valid;
+  if (threadIdx.x == 0) valid = t->valid;
+  __syncthreads();
+  if (!valid) return;  // table build rejected the codebook (status already set)
   for (int i = threadIdx.x; i < (1 << kLutBits); i += 256) lut[i] = t->lut[i];
   if (threadIdx.x < 34) {
     first[threadIdx.x] = t->first[threadIdx.x];
+    count[threadIdx.x] = t->count[threadIdx.x];
     base[threadIdx.x] = t->base[threadIdx.x];
     limit[threadIdx.x] = t->limit[threadIdx.x];
   }
-  if (threadIdx.x == 0) maxlen = t->maxlen;
+  if (threadIdx.x == 0) maxlen = t->maxlen > (uint32_t)kMaxCodeLen ? kMaxCodeLen : t->maxlen;
   __syncthreads();
   const uint64_t chunk = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (chunk >= n_chunks) return;
@@ -795,7 +804,13 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
         bad = true;
         break;
       }
-      s = t->sorted[base[len] + ((peek >> (32 - len)) - first[len])];
+      const uint32_t v = peek >> (32 - len);
+      if (v < first[len] || v - first[len] >= count[len] ||
+          base[len] + (v - first[len]) >= (uint32_t)kDict) {
+        bad = true;
+        break;
+      }
+      s = t->sorted[base[len] + (v - first[len])];
     }
     buf <<= len;
     nb -= (int)len;
