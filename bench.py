@@ -76,7 +76,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--n", type=int, default=513)
-    ap.add_argument("--cpu-edge", type=int, default=193)
+    ap.add_argument("--cpu-edge", type=int, default=257)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -105,7 +105,7 @@ def main():
     log("warmup %d steps" % args.warmup)
     for _ in range(args.warmup):
         blob = mgc.compress(x, args.rel, workspace=ws, out=out)
-        mgc.decompress(blob, workspace=ws_d, out=y)
+        mgc.decompress(blob, workspace=ws_d, out=y, info=info)
     torch.cuda.synchronize()
 
     mgc.profile_enable(True)
@@ -119,7 +119,7 @@ def main():
         ev[i][0].record(stream)
         blob = mgc.compress(x, args.rel, workspace=ws, out=out)
         ev[i][1].record(stream)
-        mgc.decompress(blob, workspace=ws_d, out=y)
+        mgc.decompress(blob, workspace=ws_d, out=y, info=info)
         ev[i][2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0

@@ -207,12 +207,16 @@ def header_info(stream):
             "stream_bytes": int(total.value), "workspace_bytes": int(ws.value)}
 
 
-def decompress(stream, workspace=None, out=None):
-    """Reconstruct the array held in a compressed GPU stream."""
+def decompress(stream, workspace=None, out=None, info=None):
+    """Reconstruct the array held in a compressed GPU stream.
+
+    ``info`` may pass a header_info() result for this stream's shape to skip
+    reading the header from the device here (the library reads it anyway).
+    """
     _require_gpu(stream, "stream")
     torch = _torch()
     dev = stream.device.index if stream.device.index is not None else torch.cuda.current_device()
-    info = header_info(stream)
+    info = info or header_info(stream)
     res = out if out is not None else torch.empty(info["shape"], dtype=info["dtype"], device=stream.device)
     ws = workspace if workspace is not None and workspace.numel() >= info["workspace_bytes"] \
         else _empty(info["workspace_bytes"], stream.device)

@@ -82,24 +82,40 @@ __device__ __forceinline__ uint64_t match_digit(unsigned digit, int nbits, bool 
 }
 
 // ---------------------------------------------------------------- histogram
-constexpr int kHistWin = 16384;
+// One 1024-thread block per CU.  A window of 32768 bins around the
+// dictionary centre (|k| < 16384) is counted in LDS; symbols outside it and
+// the escape symbol go to global atomics.  Symbols are read 8 at a time.
+constexpr int kHistWin = 32768;
+
+__device__ __forceinline__ void hist_add(unsigned s, unsigned* h, unsigned* hist) {
+  const unsigned d = s - (kHalf - kHistWin / 2);
+  if (d < (unsigned)kHistWin) atomicAdd(&h[d], 1u);
+  else atomicAdd(&hist[s], 1u);
+}
 
 __global__ __launch_bounds__(1024) void k_histogram(const uint16_t* __restrict__ sym, int64_t n,
                                                      unsigned* __restrict__ hist) {
   __shared__ unsigned h[kHistWin];
   for (int i = threadIdx.x; i < kHistWin; i += 1024) h[i] = 0;
   __syncthreads();
-  const unsigned lo = kHalf - kHistWin / 2;
   const int64_t stride = (int64_t)gridDim.x * 1024;
-  for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride) {
-    const unsigned s = sym[i];
-    const unsigned d = s - lo;
-    if (d < (unsigned)kHistWin) atomicAdd(&h[d], 1u);
-    else atomicAdd(&hist[s], 1u);
+  const bool vec = (reinterpret_cast<uintptr_t>(sym) & 15) == 0;
+  const int64_t nvec = vec ? n / 8 : 0;
+  const uint4* sv = reinterpret_cast<const uint4*>(sym);
+  for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < nvec; i += stride) {
+    const uint4 w = sv[i];
+    const unsigned a[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      hist_add(a[k] & 0xFFFFu, h, hist);
+      hist_add(a[k] >> 16, h, hist);
+    }
   }
+  for (int64_t i = nvec * 8 + (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride)
+    hist_add(sym[i], h, hist);
   __syncthreads();
   for (int i = threadIdx.x; i < kHistWin; i += 1024)
-    if (h[i]) atomicAdd(&hist[lo + i], h[i]);
+    if (h[i]) atomicAdd(&hist[kHalf - kHistWin / 2 + i], h[i]);
 }
 
 // ---------------------------------------------------- single-block helpers
@@ -748,6 +764,12 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
   if (tid == 0) t->valid = 1;
 }
 
+// One thread per chunk, 64 chunks per wavefront.  Coded words are fetched
+// four at a time into a 128-bit register queue feeding a 64-bit bit buffer;
+// decoded symbols are staged in LDS, SB per lane, and each wave then stores
+// its 64 chunks' segments contiguously.
+constexpr int kDecSB = 32;
+
 __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, uint64_t off_sec,
                                                  uint64_t words_sec, uint64_t n_chunks,
                                                  uint64_t n_words, int C, int64_t N,
@@ -757,6 +779,7 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
   __shared__ uint32_t first[34], count[34], base[34];
   __shared__ uint64_t limit[34];
   __shared__ uint32_t maxlen, valid;
+  __shared__ uint16_t stage[4][64][kDecSB + 2];
   if (threadIdx.x == 0) valid = t->valid;
   __syncthreads();
   if (!valid) return;  // table build rejected the codebook (status already set)
@@ -769,62 +792,91 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
   }
   if (threadIdx.x == 0) maxlen = t->maxlen > (uint32_t)kMaxCodeLen ? kMaxCodeLen : t->maxlen;
   __syncthreads();
-  const uint64_t chunk = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (chunk >= n_chunks) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t wave_chunk0 = (uint64_t)blockIdx.x * 256 + wave * 64;
+  const uint64_t chunk = wave_chunk0 + lane;
   const uint64_t* offs = reinterpret_cast<const uint64_t*>(in + off_sec);
   const uint32_t* words = reinterpret_cast<const uint32_t*>(in + words_sec);
-  const uint64_t w0 = offs[chunk], w1 = offs[chunk + 1];
-  if (w0 > w1 || w1 > n_words) {
-    atomicOr(status, ST_FORMAT);
-    return;
+  bool live = chunk < n_chunks;
+  uint64_t w0 = 0, w1 = 0;
+  if (live) {
+    w0 = offs[chunk];
+    w1 = offs[chunk + 1];
+    if (w0 > w1 || w1 > n_words) {
+      atomicOr(status, ST_FORMAT);
+      live = false;
+    }
   }
   const int64_t start = (int64_t)chunk * C;
-  const int cnt = (int)min<int64_t>(C, N - start);
-  uint64_t buf = 0;
-  int nb = 0;
+  const int cnt = live ? (int)min<int64_t>(C, N - start) : 0;
+  uint64_t buf = 0, qa = 0, qb = 0;
+  int nb = 0, qn = 0;
   uint64_t wi = w0;
   bool bad = false;
-  for (int k = 0; k < cnt; ++k) {
-    while (nb <= 32) {
-      const uint32_t w = wi < w1 ? words[wi] : 0u;
-      ++wi;
-      buf |= (uint64_t)w << (32 - nb);
-      nb += 32;
-    }
-    const uint32_t peek = (uint32_t)(buf >> 32);
-    const uint32_t e = lut[peek >> (32 - kLutBits)];
-    unsigned len = e >> 16;
-    uint32_t s;
-    if (len) {
-      s = e & 0xFFFFu;
-    } else {
-      len = kLutBits + 1;
-      while (len <= maxlen && (uint64_t)peek >= limit[len]) ++len;
-      if (len > maxlen) {
-        bad = true;
-        break;
+  for (int k0 = 0; k0 < C; k0 += kDecSB) {
+    const int kn = min(kDecSB, C - k0);
+    for (int k = 0; k < kn; ++k) {
+      if (k0 + k >= cnt || bad) break;
+      while (nb <= 32) {
+        if (qn == 0) {
+          uint32_t v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = wi + u < w1 ? words[wi + u] : 0u;
+          wi += 4;
+          qa = ((uint64_t)v[0] << 32) | v[1];
+          qb = ((uint64_t)v[2] << 32) | v[3];
+          qn = 4;
+        }
+        const uint32_t w = (uint32_t)(qa >> 32);
+        qa = (qa << 32) | (qb >> 32);
+        qb <<= 32;
+        --qn;
+        buf |= (uint64_t)w << (32 - nb);
+        nb += 32;
       }
-      const uint32_t v = peek >> (32 - len);
-      if (v < first[len] || v - first[len] >= count[len] ||
-          base[len] + (v - first[len]) >= (uint32_t)kDict) {
-        bad = true;
-        break;
+      const uint32_t peek = (uint32_t)(buf >> 32);
+      const uint32_t e = lut[peek >> (32 - kLutBits)];
+      unsigned len = e >> 16;
+      uint32_t s;
+      if (len) {
+        s = e & 0xFFFFu;
+      } else {
+        len = kLutBits + 1;
+        while (len <= maxlen && (uint64_t)peek >= limit[len]) ++len;
+        const uint32_t v = len <= maxlen ? peek >> (32 - len) : 0u;
+        if (len > maxlen || v < first[len] || v - first[len] >= count[len] ||
+            base[len] + (v - first[len]) >= (uint32_t)kDict) {
+          bad = true;
+          break;
+        }
+        s = t->sorted[base[len] + (v - first[len])];
       }
-      s = t->sorted[base[len] + (v - first[len])];
+      buf <<= len;
+      nb -= (int)len;
+      stage[wave][lane][k] = (uint16_t)s;
     }
-    buf <<= len;
-    nb -= (int)len;
-    sym[start + k] = (uint16_t)s;
+    __syncthreads();
+    // store: rows of kn symbols, two rows per pass of the wave
+    for (int r = 0; r < 64; r += 2) {
+      const int row = r + (lane >> 5), col = lane & 31;
+      const uint64_t c = wave_chunk0 + row;
+      if (c < n_chunks && col < kn) {
+        const int64_t pos = (int64_t)c * C + k0 + col;
+        if (pos < N && k0 + col < C) sym[pos] = stage[wave][row][col];
+      }
+    }
+    __syncthreads();
   }
-  if (bad || (int64_t)(wi - w0) * 32 - nb > (int64_t)(w1 - w0) * 32) atomicOr(status, ST_FORMAT);
+  const int64_t used = (int64_t)(wi - w0) * 32 - (int64_t)qn * 32 - nb;
+  if (live && (bad || used > (int64_t)(w1 - w0) * 32)) atomicOr(status, ST_FORMAT);
 }
 
 }  // namespace
 
 void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s) {
-  int64_t blocks = (n + 1024 * 32 - 1) / (1024 * 32);
+  int64_t blocks = (n + 1024 * 64 - 1) / (1024 * 64);
   if (blocks < 1) blocks = 1;
-  if (blocks > 512) blocks = 512;
+  if (blocks > 256) blocks = 256;
   hipLaunchKernelGGL(k_histogram, dim3((unsigned)blocks), dim3(1024), 0, s, sym, n, hist);
 }
 

@@ -18,34 +18,11 @@
 #include "kernels.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace mgc {
 
 namespace {
-
-__device__ __forceinline__ int64_t cpos(int64_t j, int64_t nf) {
-  int64_t p = 2 * j;
-  return p < nf ? p : nf - 1;
-}
-__device__ __forceinline__ bool is_new(int64_t i, int64_t nf) {
-  return (i & 1) && i != nf - 1;
-}
-__device__ __forceinline__ int64_t coarse_idx(int64_t i, int64_t nf) {
-  return (i == nf - 1 && !(nf & 1)) ? (nf >> 1) : (i >> 1);
-}
-
-// Stream position of fine point (i0,i1,i2) with new-node flags n0,n1,n2.
-__device__ __forceinline__ int64_t stream_index(const LevelGeom& g, int64_t i0, int64_t i1,
-                                                int64_t i2, bool n0, bool n1, bool n2) {
-  int m = (n0 ? (1 << g.bit[0]) : 0) | (n1 ? (1 << g.bit[1]) : 0) |
-          (n2 ? (1 << g.bit[2]) : 0);
-  const int64_t e1 = n1 ? g.nf[1] - g.nc[1] : g.nc[1];
-  const int64_t e2 = n2 ? g.nf[2] - g.nc[2] : g.nc[2];
-  const int64_t j0 = n0 ? (i0 >> 1) : coarse_idx(i0, g.nf[0]);
-  const int64_t j1 = n1 ? (i1 >> 1) : coarse_idx(i1, g.nf[1]);
-  const int64_t j2 = n2 ? (i2 >> 1) : coarse_idx(i2, g.nf[2]);
-  return g.level_off + g.sub_off[m] + (j0 * e1 + j1) * e2 + j2;
-}
 
 // Linear quantisation of one coefficient: k = rint(c * r) in FP64 (round
 // half to even).  |k| < S/2 -> symbol k + S/2; otherwise the escape symbol 0
@@ -89,28 +66,44 @@ __device__ __forceinline__ double coeff_at(const CoeffSrc& s, int64_t pos, doubl
   return (double)k * q;
 }
 
-template <typename T>
-__device__ __forceinline__ double wave_sum(T v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // ------------------------------------------------------------ range pass
 template <typename T>
+__device__ __forceinline__ void range_acc(double v, double& mn, double& mx, double& ss,
+                                          double& bad) {
+  if (!isfinite(v)) {
+    bad = 1.0;
+  } else {
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+    ss += v * v;
+  }
+}
+
+// Each thread reads 16-byte vectors in a grid-stride loop (the tail, fewer
+// than one vector per thread of the grid, is read element by element).
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_range_partial(const T* __restrict__ u, int64_t N,
                                                         double* __restrict__ part) {
+  constexpr int V = VEC ? 16 / sizeof(T) : 1;
+  using Vec = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   double mn = INFINITY, mx = -INFINITY, ss = 0.0, bad = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
-    const double v = (double)u[i];
-    if (!isfinite(v)) {
-      bad = 1.0;
+  const int64_t nvec = VEC ? N / V : 0;
+  const Vec* uv = reinterpret_cast<const Vec*>(u);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+    const Vec w = uv[i];
+    if constexpr (sizeof(T) == 4) {
+      range_acc<T>(w.x, mn, mx, ss, bad);
+      range_acc<T>(w.y, mn, mx, ss, bad);
+      range_acc<T>(w.z, mn, mx, ss, bad);
+      range_acc<T>(w.w, mn, mx, ss, bad);
     } else {
-      mn = fmin(mn, v);
-      mx = fmax(mx, v);
-      ss += v * v;
+      range_acc<T>(w.x, mn, mx, ss, bad);
+      range_acc<T>(w.y, mn, mx, ss, bad);
     }
   }
+  for (int64_t i = nvec * V + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride)
+    range_acc<T>((double)u[i], mn, mx, ss, bad);
   for (int o = 32; o > 0; o >>= 1) {
     mn = fmin(mn, __shfl_xor(mn, o, 64));
     mx = fmax(mx, __shfl_xor(mx, o, 64));
@@ -153,157 +146,397 @@ __global__ __launch_bounds__(64) void k_range_final(const double* __restrict__ p
   out[3] = bad;
 }
 
-// ----------------------------------------------- decomposition of one level
-// Coarse output tile TZ x TY x TX (an extent of 1 marks an inactive axis).
+// ------------------------------------------------------------- tile helpers
+// Coarse output tile TZ x TY x TX; an extent of 1 marks an inactive axis.
 template <int T>
 struct Ext {
   static constexpr int v = T == 1 ? 1 : 2 * T + 3;
 };
 
+__device__ __forceinline__ uint32_t cpos32(uint32_t j, uint32_t nf) {
+  const uint32_t p = 2 * j;
+  return p < nf ? p : nf - 1;
+}
+__device__ __forceinline__ bool is_new32(uint32_t i, uint32_t nf) {
+  return (i & 1u) && i != nf - 1;
+}
+__device__ __forceinline__ uint32_t cidx32(uint32_t i, uint32_t nf) {
+  return (i == nf - 1 && !(nf & 1u)) ? (nf >> 1) : (i >> 1);
+}
+// floor(r / d) for r < 2^16 with m = ceil(2^32 / d)
+__device__ __forceinline__ uint32_t div_small(uint32_t r, uint32_t m) { return __umulhi(r, m); }
+__device__ __forceinline__ uint32_t div_magic(uint32_t d) {
+  return (uint32_t)((0xFFFFFFFFull + d) / d);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; giving each XCD a
+// contiguous range of tiles keeps neighbouring tiles (which share halos) in
+// the same L2.  grid = n_tiles rounded up to a multiple of 8.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t grid) {
+  return (b & 7u) * (grid >> 3) + (b >> 3);
+}
+
+// Geometry of one tile of level l, uniform over the block.
+struct Tile {
+  uint32_t nf[3], nc[3];
+  uint32_t c0[3];   // first coarse index per axis
+  int tk[3];        // coarse outputs per axis
+  uint32_t lo[3];   // first fine index loaded (halo of two nodes)
+  int ext[3];       // fine nodes loaded
+  int olo[3];       // first owned fine node, relative to lo
+  int oext[3];      // owned fine nodes
+};
+
+template <int TZ, int TY, int TX>
+__device__ __forceinline__ bool make_tile(const LevelGeom& g, uint32_t t, uint32_t tiles_x,
+                                          uint32_t tiles_y, Tile& tl) {
+  const uint32_t tx = t % tiles_x, rest = t / tiles_x;
+  const uint32_t ty = rest % tiles_y, tz = rest / tiles_y;
+  const uint32_t cc[3] = {tz * TZ, ty * TY, tx * TX};
+  const int T[3] = {TZ, TY, TX};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint32_t nf = (uint32_t)g.nf[k], nc = (uint32_t)g.nc[k];
+    tl.nf[k] = nf;
+    tl.nc[k] = nc;
+    tl.c0[k] = cc[k];
+    if (cc[k] >= nc) return false;
+    tl.tk[k] = (int)min<uint32_t>(T[k], nc - cc[k]);
+    const uint32_t p0 = cpos32(cc[k], nf);
+    tl.lo[k] = p0 >= 2 ? p0 - 2 : 0;
+    const uint32_t hi = min<uint32_t>(cpos32(cc[k] + tl.tk[k] - 1, nf) + 2, nf - 1);
+    tl.ext[k] = (int)(hi - tl.lo[k] + 1);
+    const uint32_t olo = 2 * cc[k];
+    const uint32_t ohi = (cc[k] + tl.tk[k] >= nc) ? nf : 2 * (cc[k] + tl.tk[k]);
+    tl.olo[k] = (int)(olo - tl.lo[k]);
+    tl.oext[k] = ohi > olo ? (int)(ohi - olo) : 0;
+  }
+  return true;
+}
+
+// Per-tile operator tables in LDS: interpolation weights of the loaded fine
+// nodes, restriction taps of the tile's coarse outputs and the tile-relative
+// position of each output's centre tap; subband offsets of the level.
+template <int E0, int E1, int E2, int TZ, int TY, int TX>
+struct TileTabs {
+  double wl0[E0], wr0[E0], wl1[E1], wr1[E1], wl2[E2], wr2[E2];
+  double W0[TZ][5], W1[TY][5], W2[TX][5];
+  int P0[TZ], P1[TY], P2[TX];
+  uint32_t soff[8];
+};
+
+template <int E0, int E1, int E2, int TZ, int TY, int TX>
+__device__ void load_tabs(const LevelGeom& g, const Tile& tl, TileTabs<E0, E1, E2, TZ, TY, TX>& tb,
+                          bool need_w) {
+  const int tid = threadIdx.x;
+  if (need_w) {
+    for (int i = tid; i < tl.ext[0]; i += 256) { tb.wl0[i] = g.ax[0].wl[tl.lo[0] + i]; tb.wr0[i] = g.ax[0].wr[tl.lo[0] + i]; }
+    for (int i = tid; i < tl.ext[1]; i += 256) { tb.wl1[i] = g.ax[1].wl[tl.lo[1] + i]; tb.wr1[i] = g.ax[1].wr[tl.lo[1] + i]; }
+    for (int i = tid; i < tl.ext[2]; i += 256) { tb.wl2[i] = g.ax[2].wl[tl.lo[2] + i]; tb.wr2[i] = g.ax[2].wr[tl.lo[2] + i]; }
+  }
+  for (int i = tid; i < 5 * tl.tk[0]; i += 256) tb.W0[i / 5][i % 5] = g.ax[0].W[5 * tl.c0[0] + i];
+  for (int i = tid; i < 5 * tl.tk[1]; i += 256) tb.W1[i / 5][i % 5] = g.ax[1].W[5 * tl.c0[1] + i];
+  for (int i = tid; i < 5 * tl.tk[2]; i += 256) tb.W2[i / 5][i % 5] = g.ax[2].W[5 * tl.c0[2] + i];
+  for (int i = tid; i < tl.tk[0]; i += 256) tb.P0[i] = (int)(cpos32(tl.c0[0] + i, tl.nf[0]) - tl.lo[0]);
+  for (int i = tid; i < tl.tk[1]; i += 256) tb.P1[i] = (int)(cpos32(tl.c0[1] + i, tl.nf[1]) - tl.lo[1]);
+  for (int i = tid; i < tl.tk[2]; i += 256) tb.P2[i] = (int)(cpos32(tl.c0[2] + i, tl.nf[2]) - tl.lo[2]);
+  if (tid < 8) tb.soff[tid] = (uint32_t)(tid == 0 ? 0 : g.sub_off[tid]);
+}
+
+// Stream position of a fine node with new-node flags n0..n2 (32-bit: N < 2^32).
+__device__ __forceinline__ uint32_t stream_pos(const LevelGeom& g, const Tile& tl,
+                                               const uint32_t* soff, uint32_t i0, uint32_t i1,
+                                               uint32_t i2, bool n0, bool n1, bool n2) {
+  const int m = (n0 ? (1 << g.bit[0]) : 0) | (n1 ? (1 << g.bit[1]) : 0) | (n2 ? (1 << g.bit[2]) : 0);
+  const uint32_t e1 = n1 ? tl.nf[1] - tl.nc[1] : tl.nc[1];
+  const uint32_t e2 = n2 ? tl.nf[2] - tl.nc[2] : tl.nc[2];
+  const uint32_t j0 = n0 ? (i0 >> 1) : cidx32(i0, tl.nf[0]);
+  const uint32_t j1 = n1 ? (i1 >> 1) : cidx32(i1, tl.nf[1]);
+  const uint32_t j2 = n2 ? (i2 >> 1) : cidx32(i2, tl.nf[2]);
+  return (uint32_t)g.level_off + soff[m] + (j0 * e1 + j1) * e2 + j2;
+}
+
+// The separable restriction (P^T M_l along x, then y, then z) of a fine tile
+// held in LDS (element type V, row pitch E2, plane pitch E1*E2) to the tile's
+// coarse outputs, written to fout (coarse grid).  A and B are LDS scratch.
+template <typename V, int E0, int E1, int E2, int TZ, int TY, int TX>
+__device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& tl,
+                              const TileTabs<E0, E1, E2, TZ, TY, TX>& tb, double* __restrict__ fout) {
+  const int tid = threadIdx.x;
+  constexpr int CW = TX < 64 ? TX : 64;        // lanes per output row
+  constexpr int RS = 256 / CW;                  // rows per block step
+  const int col0 = tid % CW, rsub = tid / CW;
+  // x: A[z][y][cx], rows (z, y)
+  {
+    const int rows = tl.ext[0] * tl.ext[1];
+    const uint32_t m1 = div_magic((uint32_t)tl.ext[1]);
+    for (int rw = rsub; rw < rows; rw += RS) {
+      const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
+      const V* row = tile + (z * E1 + y) * E2;
+      for (int cx = col0; cx < tl.tk[2]; cx += CW) {
+        const int p = tb.P2[cx];
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+          const int f = p + d - 2;
+          const bool in = f >= 0 && f < tl.ext[2];
+          acc += tb.W2[cx][d] * (in ? (double)row[in ? f : 0] : 0.0);
+        }
+        A[(z * E1 + y) * TX + cx] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  // y: B[z][cy][cx], rows (z, cy)
+  {
+    const int rows = tl.ext[0] * tl.tk[1];
+    const uint32_t m1 = div_magic((uint32_t)tl.tk[1]);
+    for (int rw = rsub; rw < rows; rw += RS) {
+      const int z = (int)div_small((uint32_t)rw, m1), cy = rw - z * tl.tk[1];
+      const int p = tb.P1[cy];
+      for (int cx = col0; cx < tl.tk[2]; cx += CW) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+          const int f = p + d - 2;
+          const bool in = f >= 0 && f < tl.ext[1];
+          acc += tb.W1[cy][d] * (in ? A[(z * E1 + (in ? f : 0)) * TX + cx] : 0.0);
+        }
+        B[(z * TY + cy) * TX + cx] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  // z: coarse outputs, rows (cz, cy)
+  {
+    const int rows = tl.tk[0] * tl.tk[1];
+    const uint32_t m1 = div_magic((uint32_t)tl.tk[1]);
+    for (int rw = rsub; rw < rows; rw += RS) {
+      const int cz = (int)div_small((uint32_t)rw, m1), cy = rw - cz * tl.tk[1];
+      const int p = tb.P0[cz];
+      double* orow = fout + ((size_t)(tl.c0[0] + cz) * tl.nc[1] + tl.c0[1] + cy) * tl.nc[2] + tl.c0[2];
+      for (int cx = col0; cx < tl.tk[2]; cx += CW) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+          const int f = p + d - 2;
+          const bool in = f >= 0 && f < tl.ext[0];
+          acc += tb.W0[cz][d] * (in ? B[((in ? f : 0) * TY + cy) * TX + cx] : 0.0);
+        }
+        orow[cx] = acc;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------- decomposition of one level
 template <typename Tin, int TZ, int TY, int TX, bool QUANT>
 __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, const LevelGeom g,
                                                     double* __restrict__ fout,
                                                     uint16_t* __restrict__ sym,
                                                     double* __restrict__ raw, const double r,
                                                     const OutlierBuf ob,
-                                                    unsigned* __restrict__ status) {
+                                                    unsigned* __restrict__ status,
+                                                    const uint32_t n_tiles, const uint32_t tiles_x,
+                                                    const uint32_t tiles_y) {
   constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
   constexpr int TILE_BYTES = E0 * E1 * E2 * (int)sizeof(Tin);
-  constexpr int B_BYTES = E0 * TY * TX * (int)sizeof(double);
-  static_assert(B_BYTES <= TILE_BYTES, "B aliases the tile");
+  static_assert(E0 * TY * TX * (int)sizeof(double) <= TILE_BYTES, "B aliases the tile");
   __shared__ __align__(16) unsigned char smem[TILE_BYTES];
   __shared__ double A[E0 * E1 * TX];
+  __shared__ TileTabs<E0, E1, E2, TZ, TY, TX> tb;
   Tin* tile = reinterpret_cast<Tin*>(smem);
-  double* B = reinterpret_cast<double*>(smem);
 
+  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= n_tiles) return;
+  Tile tl;
+  if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
+  load_tabs(g, tl, tb, true);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // load the fine tile: one row (z, y) per wavefront step, lanes along x
+  {
+    const int rows = tl.ext[0] * tl.ext[1];
+    const uint32_t m1 = div_magic((uint32_t)tl.ext[1]);
+    for (int rw = wave; rw < rows; rw += 4) {
+      const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
+      const Tin* src = G + ((size_t)(tl.lo[0] + z) * tl.nf[1] + tl.lo[1] + y) * tl.nf[2] + tl.lo[2];
+      Tin* dst = tile + (z * E1 + y) * E2;
+      for (int x = lane; x < tl.ext[2]; x += 64) dst[x] = src[x];
+    }
+  }
+  __syncthreads();
+
+  // lerp + quantise the owned new nodes
+  {
+    constexpr int OX = 2 * TX;
+    constexpr int CW = OX < 64 ? OX : 64;
+    constexpr int RS = 256 / CW;
+    const int col0 = tid % CW, rsub = tid / CW;
+    const int rows = tl.oext[0] * tl.oext[1];
+    const uint32_t m1 = div_magic((uint32_t)max(tl.oext[1], 1));
+    for (int rw = rsub; rw < rows; rw += RS) {
+      const int a = (int)div_small((uint32_t)rw, m1), b = rw - a * tl.oext[1];
+      const int z = tl.olo[0] + a, y = tl.olo[1] + b;
+      const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y;
+      const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]);
+      const double wz0 = n0 ? tb.wl0[z] : 1.0, wz1 = n0 ? tb.wr0[z] : 0.0;
+      const double wy0 = n1 ? tb.wl1[y] : 1.0, wy1 = n1 ? tb.wr1[y] : 0.0;
+      const int zl = n0 ? z - 1 : z, zh = n0 ? z + 1 : z;
+      const int yl = n1 ? y - 1 : y, yh = n1 ? y + 1 : y;
+      const Tin* r00 = tile + (zl * E1 + yl) * E2;
+      const Tin* r01 = tile + (zl * E1 + yh) * E2;
+      const Tin* r10 = tile + (zh * E1 + yl) * E2;
+      const Tin* r11 = tile + (zh * E1 + yh) * E2;
+      const Tin* rc = tile + (z * E1 + y) * E2;
+      for (int c = col0; c < tl.oext[2]; c += CW) {
+        const int x = tl.olo[2] + c;
+        const uint32_t i2 = tl.lo[2] + x;
+        const bool n2 = is_new32(i2, tl.nf[2]);
+        if (!(n0 || n1 || n2)) continue;
+        const double wx0 = n2 ? tb.wl2[x] : 1.0, wx1 = n2 ? tb.wr2[x] : 0.0;
+        const int xl = n2 ? x - 1 : x, xh = n2 ? x + 1 : x;
+        const double i00 = wx0 * (double)r00[xl] + wx1 * (double)r00[xh];
+        const double i01 = wx0 * (double)r01[xl] + wx1 * (double)r01[xh];
+        const double i10 = wx0 * (double)r10[xl] + wx1 * (double)r10[xh];
+        const double i11 = wx0 * (double)r11[xl] + wx1 * (double)r11[xh];
+        const double interp = wz0 * (wy0 * i00 + wy1 * i01) + wz1 * (wy0 * i10 + wy1 * i11);
+        const double cval = (double)rc[x] - interp;
+        const uint32_t pos = stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2);
+        if (QUANT) emit_q(pos, cval, r, sym, ob, status);
+        else raw[pos] = cval;
+      }
+    }
+  }
+  // mass_trans: separable restriction of G_l to the coarse outputs
+  restrict_tile(tile, A, reinterpret_cast<double*>(smem), tl, tb, fout);
+}
+
+// --------------------------------------------- recomposition of one level
+// f = (P^T M_l) c_l: the tile holds the dequantised coefficients (zero at the
+// coarse nodes); then the same separable restriction.
+template <int TZ, int TY, int TX, bool RAW>
+__global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const CoeffSrc src,
+                                                       const double q, double* __restrict__ fout,
+                                                       const uint32_t n_tiles,
+                                                       const uint32_t tiles_x,
+                                                       const uint32_t tiles_y) {
+  constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
+  static_assert(E0 * TY * TX <= E0 * E1 * E2, "B aliases the tile");
+  __shared__ double tile[E0 * E1 * E2];
+  __shared__ double A[E0 * E1 * TX];
+  __shared__ TileTabs<E0, E1, E2, TZ, TY, TX> tb;
+  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= n_tiles) return;
+  Tile tl;
+  if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
+  load_tabs(g, tl, tb, false);
+  __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    const int rows = tl.ext[0] * tl.ext[1];
+    const uint32_t m1 = div_magic((uint32_t)tl.ext[1]);
+    for (int rw = wave; rw < rows; rw += 4) {
+      const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
+      const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y;
+      const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]);
+      double* dst = tile + (z * E1 + y) * E2;
+      for (int x = lane; x < tl.ext[2]; x += 64) {
+        const uint32_t i2 = tl.lo[2] + x;
+        const bool n2 = is_new32(i2, tl.nf[2]);
+        double v = 0.0;
+        if (n0 || n1 || n2) v = coeff_at<RAW>(src, stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2), q);
+        dst[x] = v;
+      }
+    }
+  }
+  __syncthreads();
+  restrict_tile(tile, A, tile, tl, tb, fout);
+}
+
+// G_l = P Gc + c_l on the tile's owned fine nodes; the coarse values the tile
+// needs (its coarse outputs plus one more per axis) are staged in LDS.
+template <typename Tout, int TZ, int TY, int TX, bool RAW>
+__global__ __launch_bounds__(256) void k_rec_interp(const double* __restrict__ Gc,
+                                                     const LevelGeom g, const CoeffSrc src,
+                                                     const double q, Tout* __restrict__ out,
+                                                     const uint32_t n_tiles,
+                                                     const uint32_t tiles_x,
+                                                     const uint32_t tiles_y) {
+  constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
+  constexpr int C0 = TZ == 1 ? 1 : TZ + 1, C1 = TY == 1 ? 1 : TY + 1, C2 = TX == 1 ? 1 : TX + 1;
+  __shared__ double gc[C0 * C1 * C2];
+  __shared__ TileTabs<E0, E1, E2, TZ, TY, TX> tb;
+  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= n_tiles) return;
+  Tile tl;
+  if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
+  load_tabs(g, tl, tb, true);
   const int tid = threadIdx.x;
-  const int T[3] = {TZ, TY, TX};
-  const int64_t c0[3] = {(int64_t)blockIdx.z * TZ, (int64_t)blockIdx.y * TY,
-                         (int64_t)blockIdx.x * TX};
-  int tk[3], ext[3], olo_rel[3], oext[3];
-  int64_t lo[3];
-  for (int k = 0; k < 3; ++k) {
-    const int64_t nf = g.nf[k], nc = g.nc[k];
-    tk[k] = (int)min<int64_t>(T[k], nc - c0[k]);
-    lo[k] = max<int64_t>(cpos(c0[k], nf) - 2, 0);
-    const int64_t hi = min<int64_t>(cpos(c0[k] + tk[k] - 1, nf) + 2, nf - 1);
-    ext[k] = (int)(hi - lo[k] + 1);
-    const int64_t olo = 2 * c0[k];
-    const int64_t ohi = (c0[k] + tk[k] >= nc) ? nf : 2 * (c0[k] + tk[k]);
-    olo_rel[k] = (int)(olo - lo[k]);
-    oext[k] = (int)(ohi - olo);
-  }
-  // load the fine tile with its halo
-  const int n_ld = ext[0] * ext[1] * ext[2];
-  const int e12 = ext[1] * ext[2];
-  for (int i = tid; i < n_ld; i += 256) {
-    const int z = i / e12, rem = i - z * e12, y = rem / ext[2], x = rem - y * ext[2];
-    tile[(z * E1 + y) * E2 + x] =
-        G[((lo[0] + z) * g.nf[1] + (lo[1] + y)) * g.nf[2] + lo[2] + x];
+  int ce[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ce[k] = (int)min<uint32_t>(tl.tk[k] + 1, tl.nc[k] - tl.c0[k]);
+  for (int i = tid; i < ce[0] * ce[1] * ce[2]; i += 256) {
+    const int a = i / (ce[1] * ce[2]), rem = i - a * ce[1] * ce[2], b = rem / ce[2], c = rem - b * ce[2];
+    gc[(a * C1 + b) * C2 + c] =
+        Gc[((size_t)(tl.c0[0] + a) * tl.nc[1] + tl.c0[1] + b) * tl.nc[2] + tl.c0[2] + c];
   }
   __syncthreads();
-
-  // lerp: coefficients of the owned new nodes
-  const int n_own = oext[0] * oext[1] * oext[2];
-  const int o12 = oext[1] * oext[2];
-  for (int i = tid; i < n_own; i += 256) {
-    const int a = i / o12, rem = i - a * o12, b = rem / oext[2], c = rem - b * oext[2];
-    const int z = olo_rel[0] + a, y = olo_rel[1] + b, x = olo_rel[2] + c;
-    const int64_t i0 = lo[0] + z, i1 = lo[1] + y, i2 = lo[2] + x;
-    const bool n0 = is_new(i0, g.nf[0]), n1 = is_new(i1, g.nf[1]), n2 = is_new(i2, g.nf[2]);
-    if (!(n0 || n1 || n2)) continue;
-    double w0[2] = {1.0, 0.0}, w1[2] = {1.0, 0.0}, w2[2] = {1.0, 0.0};
-    int d0[2] = {0, 0}, d1[2] = {0, 0}, d2[2] = {0, 0};
-    int k0 = 1, k1 = 1, k2 = 1;
-    if (n0) { w0[0] = g.ax[0].wl[i0]; w0[1] = g.ax[0].wr[i0]; d0[0] = -1; d0[1] = 1; k0 = 2; }
-    if (n1) { w1[0] = g.ax[1].wl[i1]; w1[1] = g.ax[1].wr[i1]; d1[0] = -1; d1[1] = 1; k1 = 2; }
-    if (n2) { w2[0] = g.ax[2].wl[i2]; w2[1] = g.ax[2].wr[i2]; d2[0] = -1; d2[1] = 1; k2 = 2; }
-    double interp = 0.0;
-    for (int p = 0; p < k0; ++p)
-      for (int q = 0; q < k1; ++q) {
-        double acc = 0.0;
-        for (int s = 0; s < k2; ++s)
-          acc += w2[s] * (double)tile[((z + d0[p]) * E1 + y + d1[q]) * E2 + x + d2[s]];
-        interp += w0[p] * w1[q] * acc;
-      }
-    const double cval = (double)tile[(z * E1 + y) * E2 + x] - interp;
-    const int64_t pos = stream_index(g, i0, i1, i2, n0, n1, n2);
-    if (QUANT) emit_q(pos, cval, r, sym, ob, status);
-    else raw[pos] = cval;
-  }
-
-  // mass_trans along axis 2 (contiguous)
-  {
-    const double* W = g.ax[2].W;
-    const int n = ext[0] * ext[1] * tk[2];
-    const int per = ext[1] * tk[2];
-    for (int i = tid; i < n; i += 256) {
-      const int z = i / per, rem = i - z * per, y = rem / tk[2], cx = rem - y * tk[2];
-      const int64_t j = c0[2] + cx, p = cpos(j, g.nf[2]);
-      double acc = 0.0;
-#pragma unroll
-      for (int d = -2; d <= 2; ++d) {
-        const int64_t f = p + d;
-        if (f >= 0 && f < g.nf[2])
-          acc += W[5 * j + d + 2] * (double)tile[(z * E1 + y) * E2 + (int)(f - lo[2])];
-      }
-      A[(z * E1 + y) * TX + cx] = acc;
-    }
-  }
-  __syncthreads();
-  // along axis 1
-  {
-    const double* W = g.ax[1].W;
-    const int n = ext[0] * tk[1] * tk[2];
-    const int per = tk[1] * tk[2];
-    for (int i = tid; i < n; i += 256) {
-      const int z = i / per, rem = i - z * per, cy = rem / tk[2], cx = rem - cy * tk[2];
-      const int64_t j = c0[1] + cy, p = cpos(j, g.nf[1]);
-      double acc = 0.0;
-#pragma unroll
-      for (int d = -2; d <= 2; ++d) {
-        const int64_t f = p + d;
-        if (f >= 0 && f < g.nf[1]) acc += W[5 * j + d + 2] * A[(z * E1 + (int)(f - lo[1])) * TX + cx];
-      }
-      B[(z * TY + cy) * TX + cx] = acc;
-    }
-  }
-  __syncthreads();
-  // along axis 0, to global memory
-  {
-    const double* W = g.ax[0].W;
-    const int n = tk[0] * tk[1] * tk[2];
-    const int per = tk[1] * tk[2];
-    for (int i = tid; i < n; i += 256) {
-      const int cz = i / per, rem = i - cz * per, cy = rem / tk[2], cx = rem - cy * tk[2];
-      const int64_t j = c0[0] + cz, p = cpos(j, g.nf[0]);
-      double acc = 0.0;
-#pragma unroll
-      for (int d = -2; d <= 2; ++d) {
-        const int64_t f = p + d;
-        if (f >= 0 && f < g.nf[0]) acc += W[5 * j + d + 2] * B[((int)(f - lo[0]) * TY + cy) * TX + cx];
-      }
-      fout[((c0[0] + cz) * g.nc[1] + c0[1] + cy) * g.nc[2] + c0[2] + cx] = acc;
+  constexpr int OX = 2 * TX;
+  constexpr int CW = OX < 64 ? OX : 64;
+  constexpr int RS = 256 / CW;
+  const int col0 = tid % CW, rsub = tid / CW;
+  const int rows = tl.oext[0] * tl.oext[1];
+  const uint32_t m1 = div_magic((uint32_t)max(tl.oext[1], 1));
+  for (int rw = rsub; rw < rows; rw += RS) {
+    const int a = (int)div_small((uint32_t)rw, m1), b = rw - a * tl.oext[1];
+    const uint32_t i0 = 2 * tl.c0[0] + a, i1 = 2 * tl.c0[1] + b;
+    const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]);
+    const int z = tl.olo[0] + a, y = tl.olo[1] + b;   // fine index relative to lo (weights)
+    const int j0 = (int)((n0 ? (i0 >> 1) : cidx32(i0, tl.nf[0])) - tl.c0[0]);
+    const int j1 = (int)((n1 ? (i1 >> 1) : cidx32(i1, tl.nf[1])) - tl.c0[1]);
+    const double wz0 = n0 ? tb.wl0[z] : 1.0, wz1 = n0 ? tb.wr0[z] : 0.0;
+    const double wy0 = n1 ? tb.wl1[y] : 1.0, wy1 = n1 ? tb.wr1[y] : 0.0;
+    const int jz1 = n0 ? j0 + 1 : j0, jy1 = n1 ? j1 + 1 : j1;
+    const double* g00 = gc + (j0 * C1 + j1) * C2;
+    const double* g01 = gc + (j0 * C1 + jy1) * C2;
+    const double* g10 = gc + (jz1 * C1 + j1) * C2;
+    const double* g11 = gc + (jz1 * C1 + jy1) * C2;
+    Tout* orow = out + ((size_t)i0 * tl.nf[1] + i1) * tl.nf[2] + 2 * tl.c0[2];
+    for (int c = col0; c < tl.oext[2]; c += CW) {
+      const uint32_t i2 = 2 * tl.c0[2] + c;
+      const bool n2 = is_new32(i2, tl.nf[2]);
+      const int x = tl.olo[2] + c;
+      const int j2 = (int)((n2 ? (i2 >> 1) : cidx32(i2, tl.nf[2])) - tl.c0[2]);
+      const int jx1 = n2 ? j2 + 1 : j2;
+      const double wx0 = n2 ? tb.wl2[x] : 1.0, wx1 = n2 ? tb.wr2[x] : 0.0;
+      const double v00 = wx0 * g00[j2] + wx1 * g00[jx1];
+      const double v01 = wx0 * g01[j2] + wx1 * g01[jx1];
+      const double v10 = wx0 * g10[j2] + wx1 * g10[jx1];
+      const double v11 = wx0 * g11[j2] + wx1 * g11[jx1];
+      double v = wz0 * (wy0 * v00 + wy1 * v01) + wz1 * (wy0 * v10 + wy1 * v11);
+      if (n0 || n1 || n2) v += coeff_at<RAW>(src, stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2), q);
+      orow[c] = (Tout)v;
     }
   }
 }
 
 // ------------------------------------------------------------- tridiagonal
-// One thread per line; lines of the strided axes are adjacent across lanes.
-template <int AXIS>
-__global__ __launch_bounds__(256) void k_thomas(double* __restrict__ x, int64_t n0, int64_t n1,
-                                                 int64_t n2, const double* __restrict__ ta,
-                                                 const double* __restrict__ tm,
-                                                 const double* __restrict__ tc,
-                                                 const double* __restrict__ sub) {
+// Thomas sweeps with the pre-factored coarse mass matrix: forward
+// y_i = (f_i - a_i y_{i-1}) m_i, backward x_i = y_i - c_i x_{i+1}.
+//
+// Strided axes: one thread per line, adjacent lanes on adjacent lines (the
+// contiguous index), so every access is coalesced; values are moved in blocks
+// of U so that U loads are in flight before the recurrence consumes them.
+template <int AXIS, int U>
+__global__ __launch_bounds__(256) void k_thomas_strided(double* __restrict__ x, int64_t n0,
+                                                         int64_t n1, int64_t n2,
+                                                         const double* __restrict__ ta,
+                                                         const double* __restrict__ tm,
+                                                         const double* __restrict__ tc,
+                                                         const double* __restrict__ sub) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t len, stride, base;
-  if (AXIS == 2) {
-    if (t >= n0 * n1) return;
-    len = n2;
-    stride = 1;
-    base = t * n2;
-  } else if (AXIS == 1) {
+  if (AXIS == 1) {
     if (t >= n0 * n2) return;
     const int64_t i0 = t / n2, i2 = t - i0 * n2;
     len = n1;
@@ -316,19 +549,107 @@ __global__ __launch_bounds__(256) void k_thomas(double* __restrict__ x, int64_t 
     base = t;
   }
   double* p = x + base;
-  double prev = p[0] * tm[0];
-  p[0] = prev;
-  for (int64_t i = 1; i < len; ++i) {
-    const double v = (p[i * stride] - ta[i] * prev) * tm[i];
-    p[i * stride] = v;
-    prev = v;
+  double prev = 0.0;
+  for (int64_t i0 = 0; i0 < len; i0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u < len) v[u] = p[(i0 + u) * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u;
+      if (i < len) {
+        v[u] = (i == 0 ? v[u] : v[u] - ta[i] * prev) * tm[i];
+        prev = v[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u < len) p[(i0 + u) * stride] = v[u];
   }
-  double nxt = prev;
-  if (sub) p[(len - 1) * stride] = sub[base + (len - 1) * stride] - nxt;
-  for (int64_t i = len - 2; i >= 0; --i) {
-    const double v = p[i * stride] - tc[i] * nxt;
-    p[i * stride] = sub ? sub[base + i * stride] - v : v;
-    nxt = v;
+  double nxt = 0.0;
+  for (int64_t hi = len - 1; hi >= 0; hi -= U) {
+    double v[U], sv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = hi - u;
+      if (i >= 0) {
+        v[u] = p[i * stride];
+        if (sub) sv[u] = sub[base + i * stride];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = hi - u;
+      if (i >= 0) {
+        if (i < len - 1) v[u] = v[u] - tc[i] * nxt;
+        nxt = v[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = hi - u;
+      if (i >= 0) p[i * stride] = sub ? sv[u] - v[u] : v[u];
+    }
+  }
+}
+
+// Contiguous axis: one wavefront per 64 rows.  Segments of SEG elements of
+// the 64 rows are staged through LDS with coalesced loads and stores; each
+// lane then runs the recurrence along its own row inside LDS.
+template <int SEG>
+__global__ __launch_bounds__(64) void k_thomas_rows(double* __restrict__ x, int64_t nrows,
+                                                     int64_t n, const double* __restrict__ ta,
+                                                     const double* __restrict__ tm,
+                                                     const double* __restrict__ tc,
+                                                     const double* __restrict__ sub) {
+  __shared__ double buf[64][SEG + 1];
+  const int lane = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int nr = (int)min<int64_t>(64, nrows - r0);
+  double prev = 0.0;
+  for (int64_t s0 = 0; s0 < n; s0 += SEG) {
+    const int ns = (int)min<int64_t>(SEG, n - s0);
+    for (int j = 0; j < nr; ++j)
+      if (lane < ns) buf[j][lane] = x[(r0 + j) * n + s0 + lane];
+    __syncthreads();
+    if (lane < nr) {
+      for (int i = 0; i < ns; ++i) {
+        const int64_t gi = s0 + i;
+        const double f = buf[lane][i];
+        const double v = (gi == 0 ? f : f - ta[gi] * prev) * tm[gi];
+        buf[lane][i] = v;
+        prev = v;
+      }
+    }
+    __syncthreads();
+    for (int j = 0; j < nr; ++j)
+      if (lane < ns) x[(r0 + j) * n + s0 + lane] = buf[j][lane];
+    __syncthreads();
+  }
+  double nxt = 0.0;
+  for (int64_t s0 = ((n - 1) / SEG) * SEG; s0 >= 0; s0 -= SEG) {
+    const int ns = (int)min<int64_t>(SEG, n - s0);
+    for (int j = 0; j < nr; ++j)
+      if (lane < ns) buf[j][lane] = x[(r0 + j) * n + s0 + lane];
+    __syncthreads();
+    if (lane < nr) {
+      for (int i = ns - 1; i >= 0; --i) {
+        const int64_t gi = s0 + i;
+        double v = buf[lane][i];
+        if (gi < n - 1) v = v - tc[gi] * nxt;
+        buf[lane][i] = v;
+        nxt = v;
+      }
+    }
+    __syncthreads();
+    for (int j = 0; j < nr; ++j) {
+      if (lane < ns) {
+        const int64_t gi = (r0 + j) * n + s0 + lane;
+        x[gi] = sub ? sub[gi] - buf[j][lane] : buf[j][lane];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -342,140 +663,6 @@ __global__ __launch_bounds__(256) void k_level0(const Tin* __restrict__ G0, int6
     const double c = (double)G0[i];
     if (QUANT) emit_q(i, c, r, sym, ob, status);
     else raw[i] = c;
-  }
-}
-
-// --------------------------------------------- recomposition of one level
-template <int TZ, int TY, int TX, bool RAW>
-__global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const CoeffSrc src,
-                                                       const double q,
-                                                       double* __restrict__ fout) {
-  constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
-  __shared__ double tile[E0 * E1 * E2];
-  __shared__ double A[E0 * E1 * TX];
-  double* B = tile;
-  static_assert(E0 * TY * TX <= E0 * E1 * E2, "B aliases the tile");
-  const int tid = threadIdx.x;
-  const int T[3] = {TZ, TY, TX};
-  const int64_t c0[3] = {(int64_t)blockIdx.z * TZ, (int64_t)blockIdx.y * TY,
-                         (int64_t)blockIdx.x * TX};
-  int tk[3], ext[3];
-  int64_t lo[3];
-  for (int k = 0; k < 3; ++k) {
-    const int64_t nf = g.nf[k], nc = g.nc[k];
-    tk[k] = (int)min<int64_t>(T[k], nc - c0[k]);
-    lo[k] = max<int64_t>(cpos(c0[k], nf) - 2, 0);
-    const int64_t hi = min<int64_t>(cpos(c0[k] + tk[k] - 1, nf) + 2, nf - 1);
-    ext[k] = (int)(hi - lo[k] + 1);
-  }
-  const int n_ld = ext[0] * ext[1] * ext[2];
-  const int e12 = ext[1] * ext[2];
-  for (int i = tid; i < n_ld; i += 256) {
-    const int z = i / e12, rem = i - z * e12, y = rem / ext[2], x = rem - y * ext[2];
-    const int64_t i0 = lo[0] + z, i1 = lo[1] + y, i2 = lo[2] + x;
-    const bool n0 = is_new(i0, g.nf[0]), n1 = is_new(i1, g.nf[1]), n2 = is_new(i2, g.nf[2]);
-    double v = 0.0;
-    if (n0 || n1 || n2) v = coeff_at<RAW>(src, stream_index(g, i0, i1, i2, n0, n1, n2), q);
-    tile[(z * E1 + y) * E2 + x] = v;
-  }
-  __syncthreads();
-  {
-    const double* W = g.ax[2].W;
-    const int n = ext[0] * ext[1] * tk[2];
-    const int per = ext[1] * tk[2];
-    for (int i = tid; i < n; i += 256) {
-      const int z = i / per, rem = i - z * per, y = rem / tk[2], cx = rem - y * tk[2];
-      const int64_t j = c0[2] + cx, p = cpos(j, g.nf[2]);
-      double acc = 0.0;
-#pragma unroll
-      for (int d = -2; d <= 2; ++d) {
-        const int64_t f = p + d;
-        if (f >= 0 && f < g.nf[2]) acc += W[5 * j + d + 2] * tile[(z * E1 + y) * E2 + (int)(f - lo[2])];
-      }
-      A[(z * E1 + y) * TX + cx] = acc;
-    }
-  }
-  __syncthreads();
-  {
-    const double* W = g.ax[1].W;
-    const int n = ext[0] * tk[1] * tk[2];
-    const int per = tk[1] * tk[2];
-    for (int i = tid; i < n; i += 256) {
-      const int z = i / per, rem = i - z * per, cy = rem / tk[2], cx = rem - cy * tk[2];
-      const int64_t j = c0[1] + cy, p = cpos(j, g.nf[1]);
-      double acc = 0.0;
-#pragma unroll
-      for (int d = -2; d <= 2; ++d) {
-        const int64_t f = p + d;
-        if (f >= 0 && f < g.nf[1]) acc += W[5 * j + d + 2] * A[(z * E1 + (int)(f - lo[1])) * TX + cx];
-      }
-      B[(z * TY + cy) * TX + cx] = acc;
-    }
-  }
-  __syncthreads();
-  {
-    const double* W = g.ax[0].W;
-    const int n = tk[0] * tk[1] * tk[2];
-    const int per = tk[1] * tk[2];
-    for (int i = tid; i < n; i += 256) {
-      const int cz = i / per, rem = i - cz * per, cy = rem / tk[2], cx = rem - cy * tk[2];
-      const int64_t j = c0[0] + cz, p = cpos(j, g.nf[0]);
-      double acc = 0.0;
-#pragma unroll
-      for (int d = -2; d <= 2; ++d) {
-        const int64_t f = p + d;
-        if (f >= 0 && f < g.nf[0]) acc += W[5 * j + d + 2] * B[((int)(f - lo[0]) * TY + cy) * TX + cx];
-      }
-      fout[((c0[0] + cz) * g.nc[1] + c0[1] + cy) * g.nc[2] + c0[2] + cx] = acc;
-    }
-  }
-}
-
-template <typename Tout, bool RAW>
-__global__ __launch_bounds__(256) void k_rec_interp(const double* __restrict__ Gc,
-                                                     const LevelGeom g, const CoeffSrc src,
-                                                     const double q, Tout* __restrict__ out) {
-  const int64_t i2 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i2 >= g.nf[2]) return;
-  const int64_t rows = g.nf[0] * g.nf[1];
-  const bool n2 = is_new(i2, g.nf[2]);
-  int64_t j2[2];
-  double w2[2];
-  int k2 = 1;
-  if (n2) {
-    j2[0] = i2 >> 1;
-    j2[1] = (i2 >> 1) + 1;
-    w2[0] = g.ax[2].wl[i2];
-    w2[1] = g.ax[2].wr[i2];
-    k2 = 2;
-  } else {
-    j2[0] = coarse_idx(i2, g.nf[2]);
-    w2[0] = 1.0;
-  }
-  for (int64_t row = blockIdx.y; row < rows; row += gridDim.y) {
-    const int64_t i0 = row / g.nf[1], i1 = row - i0 * g.nf[1];
-    const bool n0 = is_new(i0, g.nf[0]), n1 = is_new(i1, g.nf[1]);
-    int64_t j0[2], j1[2];
-    double w0[2], w1[2];
-    int k0 = 1, k1 = 1;
-    if (n0) { j0[0] = i0 >> 1; j0[1] = (i0 >> 1) + 1; w0[0] = g.ax[0].wl[i0]; w0[1] = g.ax[0].wr[i0]; k0 = 2; }
-    else { j0[0] = coarse_idx(i0, g.nf[0]); w0[0] = 1.0; }
-    if (n1) { j1[0] = i1 >> 1; j1[1] = (i1 >> 1) + 1; w1[0] = g.ax[1].wl[i1]; w1[1] = g.ax[1].wr[i1]; k1 = 2; }
-    else { j1[0] = coarse_idx(i1, g.nf[1]); w1[0] = 1.0; }
-    double v;
-    if (!(n0 || n1 || n2)) {
-      v = Gc[(j0[0] * g.nc[1] + j1[0]) * g.nc[2] + j2[0]];
-    } else {
-      double interp = 0.0;
-      for (int a = 0; a < k0; ++a)
-        for (int b = 0; b < k1; ++b) {
-          double acc = 0.0;
-          for (int c = 0; c < k2; ++c) acc += w2[c] * Gc[(j0[a] * g.nc[1] + j1[b]) * g.nc[2] + j2[c]];
-          interp += w0[a] * w1[b] * acc;
-        }
-      v = interp + coeff_at<RAW>(src, stream_index(g, i0, i1, i2, n0, n1, n2), q);
-    }
-    out[row * g.nf[2] + i2] = (Tout)v;
   }
 }
 
@@ -500,59 +687,101 @@ inline unsigned grid_for(int64_t n, int block = 256, int64_t cap = 65536) {
   return (unsigned)(b < cap ? b : cap);
 }
 
-// Tile shapes per number of active axes (an extent of 1 = inactive axis).
+struct TileGrid {
+  uint32_t n_tiles, tiles_x, tiles_y;
+  unsigned grid;
+};
+
+TileGrid tile_grid(const LevelGeom& g, int tz, int ty, int tx) {
+  TileGrid t;
+  t.tiles_x = (uint32_t)((g.nc[2] + tx - 1) / tx);
+  t.tiles_y = (uint32_t)((g.nc[1] + ty - 1) / ty);
+  const uint32_t tiles_z = (uint32_t)((g.nc[0] + tz - 1) / tz);
+  t.n_tiles = t.tiles_x * t.tiles_y * tiles_z;
+  t.grid = (t.n_tiles + 7) & ~7u;
+  return t;
+}
+
+int active_axes(const LevelGeom& g) {
+  return (g.bit[0] >= 0) + (g.bit[1] >= 0) + (g.bit[2] >= 0);
+}
+
 template <typename Tin, bool QUANT>
 void dec_dispatch(const void* G, const LevelGeom& g, double* fout, uint16_t* sym, double* raw,
                   double r, const OutlierBuf& ob, unsigned* status, hipStream_t s) {
   const Tin* Gp = static_cast<const Tin*>(G);
-  const int D = (g.bit[0] >= 0) + (g.bit[1] >= 0) + (g.bit[2] >= 0);
-  auto grid = [&](int tz, int ty, int tx) {
-    return dim3((unsigned)((g.nc[2] + tx - 1) / tx), (unsigned)((g.nc[1] + ty - 1) / ty),
-                (unsigned)((g.nc[0] + tz - 1) / tz));
-  };
+  const int D = active_axes(g);
   if (D == 3) {
     constexpr int TX = sizeof(Tin) == 4 ? 16 : 8;
-    hipLaunchKernelGGL((k_dec_level<Tin, 4, 8, TX, QUANT>), grid(4, 8, TX), dim3(256), 0, s, Gp,
-                       g, fout, sym, raw, r, ob, status);
+    const TileGrid t = tile_grid(g, 4, 8, TX);
+    hipLaunchKernelGGL((k_dec_level<Tin, 4, 8, TX, QUANT>), dim3(t.grid), dim3(256), 0, s, Gp, g,
+                       fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
   } else if (D == 2) {
     constexpr int TY = sizeof(Tin) == 4 ? 16 : 8;
-    hipLaunchKernelGGL((k_dec_level<Tin, 1, TY, 32, QUANT>), grid(1, TY, 32), dim3(256), 0, s,
-                       Gp, g, fout, sym, raw, r, ob, status);
+    const TileGrid t = tile_grid(g, 1, TY, 32);
+    hipLaunchKernelGGL((k_dec_level<Tin, 1, TY, 32, QUANT>), dim3(t.grid), dim3(256), 0, s, Gp, g,
+                       fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
   } else {
-    hipLaunchKernelGGL((k_dec_level<Tin, 1, 1, 256, QUANT>), grid(1, 1, 256), dim3(256), 0, s,
-                       Gp, g, fout, sym, raw, r, ob, status);
+    const TileGrid t = tile_grid(g, 1, 1, 256);
+    hipLaunchKernelGGL((k_dec_level<Tin, 1, 1, 256, QUANT>), dim3(t.grid), dim3(256), 0, s, Gp,
+                       g, fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
   }
 }
 
 template <bool RAW>
 void rec_restrict_dispatch(const LevelGeom& g, const CoeffSrc& src, double q, double* fout,
                            hipStream_t s) {
-  const int D = (g.bit[0] >= 0) + (g.bit[1] >= 0) + (g.bit[2] >= 0);
-  auto grid = [&](int tz, int ty, int tx) {
-    return dim3((unsigned)((g.nc[2] + tx - 1) / tx), (unsigned)((g.nc[1] + ty - 1) / ty),
-                (unsigned)((g.nc[0] + tz - 1) / tz));
-  };
-  if (D == 3)
-    hipLaunchKernelGGL((k_rec_restrict<4, 8, 8, RAW>), grid(4, 8, 8), dim3(256), 0, s, g, src, q,
-                       fout);
-  else if (D == 2)
-    hipLaunchKernelGGL((k_rec_restrict<1, 8, 32, RAW>), grid(1, 8, 32), dim3(256), 0, s, g, src,
-                       q, fout);
-  else
-    hipLaunchKernelGGL((k_rec_restrict<1, 1, 256, RAW>), grid(1, 1, 256), dim3(256), 0, s, g,
-                       src, q, fout);
+  const int D = active_axes(g);
+  if (D == 3) {
+    const TileGrid t = tile_grid(g, 4, 8, 8);
+    hipLaunchKernelGGL((k_rec_restrict<4, 8, 8, RAW>), dim3(t.grid), dim3(256), 0, s, g, src, q,
+                       fout, t.n_tiles, t.tiles_x, t.tiles_y);
+  } else if (D == 2) {
+    const TileGrid t = tile_grid(g, 1, 8, 32);
+    hipLaunchKernelGGL((k_rec_restrict<1, 8, 32, RAW>), dim3(t.grid), dim3(256), 0, s, g, src, q,
+                       fout, t.n_tiles, t.tiles_x, t.tiles_y);
+  } else {
+    const TileGrid t = tile_grid(g, 1, 1, 256);
+    hipLaunchKernelGGL((k_rec_restrict<1, 1, 256, RAW>), dim3(t.grid), dim3(256), 0, s, g, src,
+                       q, fout, t.n_tiles, t.tiles_x, t.tiles_y);
+  }
+}
+
+template <typename Tout, bool RAW>
+void rec_interp_dispatch(const double* Gc, const LevelGeom& g, const CoeffSrc& src, double q,
+                         Tout* out, hipStream_t s) {
+  const int D = active_axes(g);
+  if (D == 3) {
+    const TileGrid t = tile_grid(g, 4, 8, 16);
+    hipLaunchKernelGGL((k_rec_interp<Tout, 4, 8, 16, RAW>), dim3(t.grid), dim3(256), 0, s, Gc, g,
+                       src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
+  } else if (D == 2) {
+    const TileGrid t = tile_grid(g, 1, 16, 32);
+    hipLaunchKernelGGL((k_rec_interp<Tout, 1, 16, 32, RAW>), dim3(t.grid), dim3(256), 0, s, Gc, g,
+                       src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
+  } else {
+    const TileGrid t = tile_grid(g, 1, 1, 256);
+    hipLaunchKernelGGL((k_rec_interp<Tout, 1, 1, 256, RAW>), dim3(t.grid), dim3(256), 0, s, Gc,
+                       g, src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
+  }
 }
 
 }  // namespace
 
 void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, double* out,
                   hipStream_t s) {
-  if (dt == MGC_F32)
-    hipLaunchKernelGGL(k_range_partial<float>, dim3(kRangeBlocks), dim3(256), 0, s,
-                       static_cast<const float*>(u), N, part);
-  else
-    hipLaunchKernelGGL(k_range_partial<double>, dim3(kRangeBlocks), dim3(256), 0, s,
-                       static_cast<const double*>(u), N, part);
+  const bool vec = (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  if (dt == MGC_F32) {
+    if (vec) hipLaunchKernelGGL((k_range_partial<float, true>), dim3(kRangeBlocks), dim3(256), 0, s,
+                                static_cast<const float*>(u), N, part);
+    else hipLaunchKernelGGL((k_range_partial<float, false>), dim3(kRangeBlocks), dim3(256), 0, s,
+                            static_cast<const float*>(u), N, part);
+  } else {
+    if (vec) hipLaunchKernelGGL((k_range_partial<double, true>), dim3(kRangeBlocks), dim3(256), 0,
+                                s, static_cast<const double*>(u), N, part);
+    else hipLaunchKernelGGL((k_range_partial<double, false>), dim3(kRangeBlocks), dim3(256), 0, s,
+                            static_cast<const double*>(u), N, part);
+  }
   hipLaunchKernelGGL(k_range_final, dim3(1), dim3(64), 0, s, part, kRangeBlocks, out);
 }
 
@@ -570,17 +799,20 @@ void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* 
 
 void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
                    const double* sub, hipStream_t s) {
-  int64_t lines = axis == 2 ? nc[0] * nc[1] : axis == 1 ? nc[0] * nc[2] : nc[1] * nc[2];
-  unsigned blocks = (unsigned)((lines + 255) / 256);
-  if (axis == 2)
-    hipLaunchKernelGGL(k_thomas<2>, dim3(blocks), dim3(256), 0, s, x, nc[0], nc[1], nc[2], t.ta,
-                       t.tm, t.tc, sub);
-  else if (axis == 1)
-    hipLaunchKernelGGL(k_thomas<1>, dim3(blocks), dim3(256), 0, s, x, nc[0], nc[1], nc[2], t.ta,
-                       t.tm, t.tc, sub);
+  if (axis == 2) {
+    const int64_t rows = nc[0] * nc[1];
+    hipLaunchKernelGGL(k_thomas_rows<32>, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, s, x,
+                       rows, nc[2], t.ta, t.tm, t.tc, sub);
+    return;
+  }
+  const int64_t lines = axis == 1 ? nc[0] * nc[2] : nc[1] * nc[2];
+  const unsigned blocks = (unsigned)((lines + 255) / 256);
+  if (axis == 1)
+    hipLaunchKernelGGL((k_thomas_strided<1, 8>), dim3(blocks), dim3(256), 0, s, x, nc[0], nc[1],
+                       nc[2], t.ta, t.tm, t.tc, sub);
   else
-    hipLaunchKernelGGL(k_thomas<0>, dim3(blocks), dim3(256), 0, s, x, nc[0], nc[1], nc[2], t.ta,
-                       t.tm, t.tc, sub);
+    hipLaunchKernelGGL((k_thomas_strided<0, 8>), dim3(blocks), dim3(256), 0, s, x, nc[0], nc[1],
+                       nc[2], t.ta, t.tm, t.tc, sub);
 }
 
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
@@ -607,18 +839,12 @@ void launch_rec_restrict(const LevelGeom& g, const CoeffSrc& src, double q, doub
 
 void launch_rec_interp(const double* Gc, const LevelGeom& g, const CoeffSrc& src, double q,
                        void* out, bool out_f32, hipStream_t s) {
-  const int64_t rows = g.nf[0] * g.nf[1];
-  dim3 grid((unsigned)((g.nf[2] + 255) / 256), (unsigned)(rows < 65535 ? rows : 65535));
   if (out_f32) {
-    if (src.raw) hipLaunchKernelGGL((k_rec_interp<float, true>), grid, dim3(256), 0, s, Gc, g, src,
-                                    q, static_cast<float*>(out));
-    else hipLaunchKernelGGL((k_rec_interp<float, false>), grid, dim3(256), 0, s, Gc, g, src, q,
-                            static_cast<float*>(out));
+    if (src.raw) rec_interp_dispatch<float, true>(Gc, g, src, q, static_cast<float*>(out), s);
+    else rec_interp_dispatch<float, false>(Gc, g, src, q, static_cast<float*>(out), s);
   } else {
-    if (src.raw) hipLaunchKernelGGL((k_rec_interp<double, true>), grid, dim3(256), 0, s, Gc, g,
-                                    src, q, static_cast<double*>(out));
-    else hipLaunchKernelGGL((k_rec_interp<double, false>), grid, dim3(256), 0, s, Gc, g, src, q,
-                            static_cast<double*>(out));
+    if (src.raw) rec_interp_dispatch<double, true>(Gc, g, src, q, static_cast<double*>(out), s);
+    else rec_interp_dispatch<double, false>(Gc, g, src, q, static_cast<double*>(out), s);
   }
 }
 
