@@ -222,10 +222,13 @@ __device__ unsigned block_excl_scan(unsigned v, unsigned* sm32, unsigned* total)
 }
 
 // ---------------------------------------------------------------- codebook
+constexpr int kMergeCap = 4096;
+
 struct CbSmem {
   SortSmem sort;
+  uint32_t runL[kMergeCap], runI[kMergeCap], runS[kMergeCap];
   unsigned sm32[16];
-  unsigned m, li, ii, nI, la, ib, n, flag;
+  unsigned m, li, ii, nI, la, ib, n, flag, lastw;
   unsigned long long t;
   unsigned lcount[34];
   unsigned lfirst[34];
@@ -354,12 +357,15 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
     const uint32_t* Lw = inB ? s.keyB : s.keyA;   // leaf weights, ascending
     const uint32_t* Lx = inB ? s.valB : s.valA;   // leaf -> index into symAsc
     __syncthreads();
-    // 3. two-queue merge in rounds
+    // 3. two-queue merge in rounds.  A round's two runs are staged in LDS
+    //    when they fit (binary searches and the new internal weights then
+    //    stay in LDS); larger rounds use global memory.
     if (tid == 0) {
       sm.m = 0;
       sm.li = 0;
       sm.ii = 0;
       sm.nI = 0;
+      sm.lastw = 0;
     }
     __syncthreads();
     while (true) {
@@ -373,7 +379,8 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
         const unsigned long long i1 = ii + 1 < nI ? s.Iw[ii + 1] : INF;
         unsigned long long t;
         if (m & 1) {
-          t = (unsigned long long)s.Sw[m - 1] + (l0 < i0 ? l0 : i0);
+          // the pending first child (weight lastw) pairs with the next node
+          t = (unsigned long long)sm.lastw + (l0 < i0 ? l0 : i0);
         } else {
           // two smallest of the queue fronts
           unsigned long long a = l0 < i0 ? l0 : i0;
@@ -387,43 +394,68 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
       __syncthreads();
       const unsigned long long t = sm.t;
       // leaves and internal nodes of weight <= t (prefixes of sorted queues)
-      unsigned la = li;
-      while (true) {
-        const unsigned idx = la + tid;
-        const bool ok = idx < n && (unsigned long long)Lw[idx] <= t;
-        const int c = __syncthreads_count(ok);
-        la += c;
-        if (c < 1024) break;
+      unsigned la = li, ib = ii;
+      bool more_l = true, more_i = true;
+      while (more_l || more_i) {
+        const unsigned xl = la + tid, xi = ib + tid;
+        const bool okl = more_l && xl < n && (unsigned long long)Lw[xl] <= t;
+        const bool oki = more_i && xi < nI && (unsigned long long)s.Iw[xi] <= t;
+        const int cl = __syncthreads_count(okl);
+        const int ci = __syncthreads_count(oki);
+        la += cl;
+        ib += ci;
+        more_l = more_l && cl == 1024;
+        more_i = more_i && ci == 1024;
       }
-      unsigned ib = ii;
-      while (true) {
-        const unsigned idx = ib + tid;
-        const bool ok = idx < nI && (unsigned long long)s.Iw[idx] <= t;
-        const int c = __syncthreads_count(ok);
-        ib += c;
-        if (c < 1024) break;
-      }
-      // merge: ties go to the leaf
-      for (unsigned x = li + tid; x < la; x += 1024) {
-        const uint32_t w = Lw[x];
-        const unsigned pos = m + (x - li) + lower_count(s.Iw + ii, ib - ii, w);
-        s.Sw[pos] = w;
-        s.leafPar[x] = pos >> 1;
-      }
-      for (unsigned y = ii + tid; y < ib; y += 1024) {
-        const uint32_t w = s.Iw[y];
-        const unsigned pos = m + (y - ii) + upper_count(Lw + li, la - li, w);
-        s.Sw[pos] = w;
-        s.parA[y] = pos >> 1;
-      }
-      __syncthreads();
-      const unsigned m_new = m + (la - li) + (ib - ii);
+      const unsigned nl = la - li, ni = ib - ii;
+      const unsigned m_new = m + nl + ni;
       if (m_new == m) {  // every round takes at least the smallest node
         if (tid == 0) lay->status |= ST_INTERNAL;
         return;
       }
-      for (unsigned j = nI + tid; j < m_new / 2; j += 1024) s.Iw[j] = s.Sw[2 * j] + s.Sw[2 * j + 1];
-      __syncthreads();
+      if (nl + ni <= (unsigned)kMergeCap) {
+        for (unsigned k = tid; k < nl; k += 1024) sm.runL[k] = Lw[li + k];
+        for (unsigned k = tid; k < ni; k += 1024) sm.runI[k] = s.Iw[ii + k];
+        __syncthreads();
+        // merge: ties go to the leaf
+        for (unsigned k = tid; k < nl; k += 1024) {
+          const uint32_t w = sm.runL[k];
+          const unsigned r = k + lower_count(sm.runI, ni, w);
+          sm.runS[r] = w;
+          s.leafPar[li + k] = (m + r) >> 1;
+        }
+        for (unsigned k = tid; k < ni; k += 1024) {
+          const uint32_t w = sm.runI[k];
+          const unsigned r = k + upper_count(sm.runL, nl, w);
+          sm.runS[r] = w;
+          s.parA[ii + k] = (m + r) >> 1;
+        }
+        __syncthreads();
+        for (unsigned j = nI + tid; j < m_new / 2; j += 1024) {
+          const int r = (int)(2 * j) - (int)m;   // -1: first child placed last round
+          s.Iw[j] = (r < 0 ? sm.lastw : sm.runS[r]) + sm.runS[r + 1];
+        }
+        __syncthreads();
+        if (tid == 0) sm.lastw = sm.runS[nl + ni - 1];
+      } else {
+        for (unsigned x = li + tid; x < la; x += 1024) {
+          const uint32_t w = Lw[x];
+          const unsigned pos = m + (x - li) + lower_count(s.Iw + ii, ni, w);
+          s.Sw[pos] = w;
+          s.leafPar[x] = pos >> 1;
+        }
+        for (unsigned y = ii + tid; y < ib; y += 1024) {
+          const uint32_t w = s.Iw[y];
+          const unsigned pos = m + (y - ii) + upper_count(Lw + li, nl, w);
+          s.Sw[pos] = w;
+          s.parA[y] = pos >> 1;
+        }
+        __syncthreads();
+        for (unsigned j = nI + tid; j < m_new / 2; j += 1024)
+          s.Iw[j] = (2 * j + 1 == m ? sm.lastw : s.Sw[2 * j]) + s.Sw[2 * j + 1];
+        __syncthreads();
+        if (tid == 0) sm.lastw = s.Sw[m_new - 1];
+      }
       if (tid == 0) {
         sm.m = m_new;
         sm.li = la;

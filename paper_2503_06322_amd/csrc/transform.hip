@@ -163,11 +163,11 @@ __device__ __forceinline__ bool is_new32(uint32_t i, uint32_t nf) {
 __device__ __forceinline__ uint32_t cidx32(uint32_t i, uint32_t nf) {
   return (i == nf - 1 && !(nf & 1u)) ? (nf >> 1) : (i >> 1);
 }
-// floor(r / d) for r < 2^16 with m = ceil(2^32 / d)
-__device__ __forceinline__ uint32_t div_small(uint32_t r, uint32_t m) { return __umulhi(r, m); }
-__device__ __forceinline__ uint32_t div_magic(uint32_t d) {
-  return (uint32_t)((0xFFFFFFFFull + d) / d);
+// floor(r / d) for r < 2^16 with m = ceil(2^32 / d) (2^32 itself for d = 1)
+__device__ __forceinline__ uint32_t div_small(uint32_t r, uint64_t m) {
+  return (uint32_t)(((uint64_t)r * m) >> 32);
 }
+__device__ __forceinline__ uint64_t div_magic(uint32_t d) { return (0xFFFFFFFFull + d) / d; }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; giving each XCD a
 // contiguous range of tiles keeps neighbouring tiles (which share halos) in
@@ -269,7 +269,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
   // x: A[z][y][cx], rows (z, y)
   {
     const int rows = tl.ext[0] * tl.ext[1];
-    const uint32_t m1 = div_magic((uint32_t)tl.ext[1]);
+    const uint64_t m1 = div_magic((uint32_t)tl.ext[1]);
     for (int rw = rsub; rw < rows; rw += RS) {
       const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
       const V* row = tile + (z * E1 + y) * E2;
@@ -290,7 +290,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
   // y: B[z][cy][cx], rows (z, cy)
   {
     const int rows = tl.ext[0] * tl.tk[1];
-    const uint32_t m1 = div_magic((uint32_t)tl.tk[1]);
+    const uint64_t m1 = div_magic((uint32_t)tl.tk[1]);
     for (int rw = rsub; rw < rows; rw += RS) {
       const int z = (int)div_small((uint32_t)rw, m1), cy = rw - z * tl.tk[1];
       const int p = tb.P1[cy];
@@ -310,7 +310,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
   // z: coarse outputs, rows (cz, cy)
   {
     const int rows = tl.tk[0] * tl.tk[1];
-    const uint32_t m1 = div_magic((uint32_t)tl.tk[1]);
+    const uint64_t m1 = div_magic((uint32_t)tl.tk[1]);
     for (int rw = rsub; rw < rows; rw += RS) {
       const int cz = (int)div_small((uint32_t)rw, m1), cy = rw - cz * tl.tk[1];
       const int p = tb.P0[cz];
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
   // load the fine tile: one row (z, y) per wavefront step, lanes along x
   {
     const int rows = tl.ext[0] * tl.ext[1];
-    const uint32_t m1 = div_magic((uint32_t)tl.ext[1]);
+    const uint64_t m1 = div_magic((uint32_t)tl.ext[1]);
     for (int rw = wave; rw < rows; rw += 4) {
       const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
       const Tin* src = G + ((size_t)(tl.lo[0] + z) * tl.nf[1] + tl.lo[1] + y) * tl.nf[2] + tl.lo[2];
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
     constexpr int RS = 256 / CW;
     const int col0 = tid % CW, rsub = tid / CW;
     const int rows = tl.oext[0] * tl.oext[1];
-    const uint32_t m1 = div_magic((uint32_t)max(tl.oext[1], 1));
+    const uint64_t m1 = div_magic((uint32_t)max(tl.oext[1], 1));
     for (int rw = rsub; rw < rows; rw += RS) {
       const int a = (int)div_small((uint32_t)rw, m1), b = rw - a * tl.oext[1];
       const int z = tl.olo[0] + a, y = tl.olo[1] + b;
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const C
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   {
     const int rows = tl.ext[0] * tl.ext[1];
-    const uint32_t m1 = div_magic((uint32_t)tl.ext[1]);
+    const uint64_t m1 = div_magic((uint32_t)tl.ext[1]);
     for (int rw = wave; rw < rows; rw += 4) {
       const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
       const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y;
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(256) void k_rec_interp(const double* __restrict__ G
   constexpr int RS = 256 / CW;
   const int col0 = tid % CW, rsub = tid / CW;
   const int rows = tl.oext[0] * tl.oext[1];
-  const uint32_t m1 = div_magic((uint32_t)max(tl.oext[1], 1));
+  const uint64_t m1 = div_magic((uint32_t)max(tl.oext[1], 1));
   for (int rw = rsub; rw < rows; rw += RS) {
     const int a = (int)div_small((uint32_t)rw, m1), b = rw - a * tl.oext[1];
     const uint32_t i0 = 2 * tl.c0[0] + a, i1 = 2 * tl.c0[1] + b;

@@ -13,7 +13,7 @@ from tests.gpu_common import gpu
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(65, 65, 65), (9, 5, 4), (6, 6, 6), (30, 41, 12), (33, 20), (17,), (1, 7, 1),
+SHAPES = [(65, 65, 65), (9, 5, 4), (6, 6, 6), (30, 41, 12), (33, 20), (17,), (1, 7, 1), (17, 17, 17),
           (2, 2, 2), (3, 5), (100, 3), (40, 33, 17), (257,), (5, 129)]
 
 
