@@ -216,7 +216,8 @@ struct mgc_ctx_s {
   int device = 0;
   std::map<std::vector<uint64_t>, Plan> plans;
   Profiler prof;
-  uint8_t* pinned = nullptr;  // 4 KiB host staging
+  uint8_t* pinned = nullptr;      // 4 KiB host staging (pinned, mapped)
+  uint8_t* pinned_dev = nullptr;  // the same memory as seen by the device
 };
 
 namespace {
@@ -253,10 +254,13 @@ Plan& get_plan(mgc_ctx ctx, int ndim, const uint64_t* shape) {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// Reads n bytes of device memory into ctx->pinned (n <= 4 KiB): a one-block
+// copy into the mapped staging buffer, then a stream synchronisation.
 void sync_read(mgc_ctx ctx, void* host, const void* dev, size_t n, hipStream_t s) {
-  MGC_HIP(hipMemcpyAsync(host, dev, n, hipMemcpyDeviceToHost, s));
+  if (host != ctx->pinned || n > 4096) fail(MGC_EINVAL, "staging read too large");
+  launch_copy_bytes(ctx->pinned_dev, dev, n, s);
+  MGC_HIP(hipGetLastError());
   MGC_HIP(hipStreamSynchronize(s));
-  (void)ctx;
 }
 
 // header of a constant or empty array (no sections)
@@ -354,6 +358,11 @@ mgc_status mgc_create(int device, mgc_ctx* out) {
     if (hipHostMalloc((void**)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
       delete c;
       fail(MGC_EDEVICE, "hipHostMalloc failed");
+    }
+    if (hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0) != hipSuccess) {
+      (void)hipHostFree(c->pinned);
+      delete c;
+      fail(MGC_EDEVICE, "hipHostGetDevicePointer failed");
     }
     *out = c;
   });
@@ -576,7 +585,7 @@ mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* 
     }
     {
       StageScope st(&ctx->prof, "decode", s);
-      launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, p.N,
+      launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, p.N, h.n_codes,
                     static_cast<const DecodeTables*>(w.tables), w.sym, w.status, s);
     }
     CoeffSrc src{w.sym, nullptr, reinterpret_cast<const uint64_t*>(in + opos),
@@ -752,7 +761,7 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes, ui
     }
     {
       StageScope st(&ctx->prof, "decode", s);
-      launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, (int64_t)n,
+      launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, (int64_t)n, h.n_codes,
                     static_cast<const DecodeTables*>(tables), d_sym, status, s);
     }
     MGC_HIP(hipGetLastError());

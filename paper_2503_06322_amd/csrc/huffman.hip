@@ -26,7 +26,8 @@
 
 namespace mgc {
 
-constexpr int kLutBits = 11;
+constexpr int kLutBits = 12;
+constexpr uint32_t kLutLong = 1u << 31;   // LUT entry flag: a longer code, length field = minimum
 
 struct DecodeTables {
   uint32_t first[34];
@@ -35,7 +36,9 @@ struct DecodeTables {
   uint64_t limit[34];   // left-justified exclusive upper bound of each length
   uint32_t maxlen;
   uint32_t valid;               // 1 only after a codebook passed validation
-  uint32_t lut[1 << kLutBits];  // symbol | length << 16 (length 0: longer code)
+  // symbol | length << 16 for codes of <= kLutBits bits; for a prefix of
+  // longer codes kLutLong | (shortest length with that prefix) << 16
+  uint32_t lut[1 << kLutBits];
   uint16_t sorted[kDict];       // symbols in (length, symbol) order
 };
 
@@ -223,12 +226,14 @@ __device__ unsigned block_excl_scan(unsigned v, unsigned* sm32, unsigned* total)
 
 // ---------------------------------------------------------------- codebook
 constexpr int kMergeCap = 4096;
+constexpr int kMaxRounds = 256;
 
 struct CbSmem {
   SortSmem sort;
   uint32_t runL[kMergeCap], runI[kMergeCap], runS[kMergeCap];
+  unsigned round_lo[kMaxRounds];
   unsigned sm32[16];
-  unsigned m, li, ii, nI, la, ib, n, flag, lastw;
+  unsigned m, li, ii, nI, la, ib, n, flag, lastw, rounds;
   unsigned long long t;
   unsigned lcount[34];
   unsigned lfirst[34];
@@ -305,18 +310,28 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
     clen[i] = 0;
     code[i] = 0;
   }
-  // 1. non-zero keys in ascending symbol order (each thread owns 64 symbols)
+  // 1. non-zero keys in ascending symbol order (each thread owns 64 symbols,
+  //    read as sixteen 16-byte vectors kept in registers)
+  uint4 hv[16];
+  const uint4* h4 = reinterpret_cast<const uint4*>(hist) + tid * 16;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) hv[k] = h4[k];
   unsigned cnt = 0;
-  for (int k = 0; k < 64; ++k) cnt += hist[tid * 64 + k] != 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    cnt += (hv[k].x != 0) + (hv[k].y != 0) + (hv[k].z != 0) + (hv[k].w != 0);
   unsigned total;
   unsigned off = block_excl_scan(cnt, sm.sm32, &total);
-  for (int k = 0; k < 64; ++k) {
-    const unsigned sy = tid * 64 + k;
-    const unsigned f = hist[sy];
-    if (f) {
-      s.symAsc[off] = sy;
-      s.freqAsc[off] = f;
-      ++off;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const unsigned f4[4] = {hv[k].x, hv[k].y, hv[k].z, hv[k].w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (f4[q]) {
+        s.symAsc[off] = tid * 64 + 4 * k + q;
+        s.freqAsc[off] = f4[q];
+        ++off;
+      }
     }
   }
   const unsigned n = total;
@@ -366,11 +381,16 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
       sm.ii = 0;
       sm.nI = 0;
       sm.lastw = 0;
+      sm.rounds = 0;
     }
     __syncthreads();
     while (true) {
       const unsigned m = sm.m, li = sm.li, ii = sm.ii, nI = sm.nI;
       if (m == 2 * n - 2) break;
+      if (tid == 0) {
+        // internal nodes created in this round: [nI, m_new / 2), recorded below
+        if (sm.rounds < kMaxRounds) sm.round_lo[sm.rounds] = nI;
+      }
       if (tid == 0) {
         const unsigned long long INF = ~0ull;
         const unsigned long long l0 = li < n ? Lw[li] : INF;
@@ -461,40 +481,81 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
         sm.li = la;
         sm.ii = ib;
         sm.nI = m_new / 2;
+        ++sm.rounds;
       }
       __syncthreads();
     }
-    // 4. depths of internal nodes by pointer jumping towards the root
-    for (unsigned y = tid; y <= root; y += 1024) {
-      if (y == root) s.parA[y] = root;
-      s.dstA[y] = y == root ? 0u : 1u;
-    }
-    __syncthreads();
-    uint32_t *pa = s.parA, *pb = s.parB, *da = s.dstA, *db = s.dstB;
-    for (int jump = 0;; ++jump) {
-      if (jump > 40) {  // depth <= n - 1 < 2^17: 18 jumps suffice
-        if (tid == 0) lay->status |= ST_INTERNAL;
-        return;
+    // 4. depths of internal nodes.  A node created in round r is taken in a
+    //    later round, so its parent is created later still: walking the
+    //    rounds backwards, each round's nodes are resolved in parallel.
+    uint32_t* da;
+    const unsigned rounds = sm.rounds;
+    if (rounds <= (unsigned)kMaxRounds) {
+      da = s.dstA;
+      for (int r = (int)rounds - 1; r >= 0; --r) {
+        const unsigned lo = sm.round_lo[r];
+        const unsigned hi = r + 1 < (int)rounds ? sm.round_lo[r + 1] : root + 1;
+        for (unsigned y = lo + tid; y < hi; y += 1024)
+          da[y] = y == root ? 0u : da[s.parA[y]] + 1u;
+        __syncthreads();
       }
-      bool more = false;
+    } else {
+      // pointer jumping towards the root
       for (unsigned y = tid; y <= root; y += 1024) {
-        const uint32_t p = pa[y];
-        db[y] = da[y] + da[p];
-        pb[y] = pa[p];
-        more |= pa[p] != root;
+        if (y == root) s.parA[y] = root;
+        s.dstA[y] = y == root ? 0u : 1u;
       }
-      const int any = __syncthreads_or(more);
-      uint32_t* tmp;
-      tmp = pa; pa = pb; pb = tmp;
-      tmp = da; da = db; db = tmp;
-      if (!any) break;
+      __syncthreads();
+      uint32_t *pa = s.parA, *pb = s.parB, *db = s.dstB;
+      da = s.dstA;
+      for (int jump = 0;; ++jump) {
+        if (jump > 40) {  // depth <= n - 1 < 2^17: 18 jumps suffice
+          if (tid == 0) lay->status |= ST_INTERNAL;
+          return;
+        }
+        bool more = false;
+        for (unsigned y = tid; y <= root; y += 1024) {
+          const uint32_t p = pa[y];
+          db[y] = da[y] + da[p];
+          pb[y] = pa[p];
+          more |= pa[p] != root;
+        }
+        const int any = __syncthreads_or(more);
+        uint32_t* tmp;
+        tmp = pa; pa = pb; pb = tmp;
+        tmp = da; da = db; db = tmp;
+        if (!any) break;
+      }
     }
-    // 5. leaf lengths
+    // 5. leaf lengths (four items per thread in flight)
+    uint32_t* lenx = s.parB;  // free after step 4
     unsigned lmax = 0;
-    for (unsigned x = tid; x < n; x += 1024) lmax = max(lmax, da[s.leafPar[x]] + 1u);
+    for (unsigned x0 = tid; x0 < n; x0 += 4096) {
+      uint32_t par[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) par[u] = x0 + 1024 * u < n ? s.leafPar[x0 + 1024 * u] : root;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned x = x0 + 1024 * u;
+        if (x < n) {
+          const unsigned l = da[par[u]] + 1u;
+          lenx[x] = l;
+          lmax = max(lmax, l);
+        }
+      }
+    }
     lmax = block_max(lmax, sm.sm32);
     if (lmax <= (unsigned)kMaxCodeLen) {
-      for (unsigned x = tid; x < n; x += 1024) clen[s.symAsc[Lx[x]]] = (uint8_t)(da[s.leafPar[x]] + 1u);
+      for (unsigned x0 = tid; x0 < n; x0 += 4096) {
+        uint32_t li4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) li4[u] = x0 + 1024 * u < n ? Lx[x0 + 1024 * u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned x = x0 + 1024 * u;
+          if (x < n) clen[s.symAsc[li4[u]]] = (uint8_t)lenx[x];
+        }
+      }
       __syncthreads();
       break;
     }
@@ -531,6 +592,9 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
 }
 
 // ---------------------------------------------------------------- encoding
+// Lane l of the chunk's wavefront owns symbols [l*per, (l+1)*per) of the
+// chunk; symbols and their code lengths are fetched in groups of 8 with all
+// loads in flight before use.
 __global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict__ sym, int64_t N,
                                                       int C, const uint8_t* __restrict__ clen,
                                                       uint32_t* __restrict__ cw,
@@ -540,10 +604,17 @@ __global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict_
   const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (chunk >= n_chunks) return;
-  const int64_t start = chunk * C;
-  const int64_t end = min<int64_t>(start + C, N);
+  const int per = C / 64;
+  const int64_t a = chunk * C + (int64_t)lane * per;
+  const int64_t end = min<int64_t>(chunk * C + C, N);
   unsigned bits = 0;
-  for (int64_t i = start + lane; i < end; i += 64) bits += clen[sym[i]];
+  for (int k0 = 0; k0 < per; k0 += 8) {
+    unsigned sy[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sy[u] = (k0 + u < per && a + k0 + u < end) ? sym[a + k0 + u] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bits += sy[u] != 0xFFFFFFFFu ? clen[sy[u]] : 0u;
+  }
   for (int o = 32; o > 0; o >>= 1) bits += (unsigned)__shfl_xor((int)bits, o, 64);
   if (lane == 0) cw[chunk] = (bits + 31u) >> 5;
 }
@@ -642,14 +713,16 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym
   uint32_t* words = reinterpret_cast<uint32_t*>(out + lay->words);
   const bool live = chunk < n_chunks;
   const int per = C / 64;
-  int64_t start = 0, end = 0;
+  const int64_t a = live ? chunk * C + (int64_t)lane * per : 0;
+  const int64_t end = live ? min<int64_t>(chunk * C + C, N) : 0;
+  // pass 1: bit count of this lane's symbols
   unsigned my_bits = 0;
-  if (live) {
-    start = chunk * C;
-    end = min<int64_t>(start + C, N);
-    const int64_t a = start + (int64_t)lane * per;
-    for (int k = 0; k < per; ++k)
-      if (a + k < end) my_bits += clen[sym[a + k]];
+  for (int k0 = 0; k0 < per; k0 += 8) {
+    unsigned sy[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sy[u] = (k0 + u < per && a + k0 + u < end) ? sym[a + k0 + u] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) my_bits += sy[u] != 0xFFFFFFFFu ? clen[sy[u]] : 0u;
   }
   // exclusive prefix over lanes
   unsigned x = my_bits;
@@ -658,13 +731,23 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym
     if (lane >= o) x += y;
   }
   unsigned bitpos = x - my_bits;
-  if (live) {
-    const int64_t a = start + (int64_t)lane * per;
-    for (int k = 0; k < per; ++k) {
-      if (a + k >= end) break;
-      const unsigned sy = sym[a + k];
-      const unsigned l = clen[sy];
-      const uint32_t c = code[sy];
+  // pass 2: OR the codes into the chunk's words
+  for (int k0 = 0; k0 < per; k0 += 8) {
+    unsigned sy[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sy[u] = (k0 + u < per && a + k0 + u < end) ? sym[a + k0 + u] : 0xFFFFFFFFu;
+    uint32_t cd[8];
+    unsigned ln[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      cd[u] = sy[u] != 0xFFFFFFFFu ? code[sy[u]] : 0u;
+      ln[u] = sy[u] != 0xFFFFFFFFu ? clen[sy[u]] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const unsigned l = ln[u];
+      if (l == 0) continue;
+      const uint32_t c = cd[u];
       const unsigned wi = bitpos >> 5, o = bitpos & 31u;
       if (o + l <= 32u) {
         atomicOr(&w[wi], c << (32u - o - l));
@@ -743,7 +826,6 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     sm.flag = 0;
     t->valid = 0;
   }
-  for (unsigned i = tid; i < (1u << kLutBits); i += 1024) t->lut[i] = 0;
   __syncthreads();
   for (unsigned i = tid; i < n; i += 1024) {
     const unsigned l = lens[i];
@@ -781,15 +863,21 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     lbase[tid] = sm.lbase[tid];
   }
   __syncthreads();
+  for (unsigned i = tid; i < (1u << kLutBits); i += 1024) t->lut[i] = kLutLong | (63u << 16);
+  __syncthreads();
   stable_digit_ranks(
       n, [&](unsigned i) { return (unsigned)lens[i]; },
       [&](unsigned i, unsigned d, unsigned rank) {
         const unsigned sy = syms[i];
         t->sorted[lbase[d] + rank] = (uint16_t)sy;
+        const unsigned c = lfirst[d] + rank;
         if (d <= (unsigned)kLutBits) {
-          const unsigned c = lfirst[d] + rank;
           const unsigned a = c << (kLutBits - d), b = (c + 1) << (kLutBits - d);
           for (unsigned e = a; e < b; ++e) t->lut[e] = sy | (d << 16);
+        } else {
+          // canonical order: lengths grow with the code, so the first code
+          // under a prefix has the prefix's shortest length
+          atomicMin(&t->lut[c >> (d - kLutBits)], kLutLong | (d << 16));
         }
       },
       sm);
@@ -797,14 +885,20 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
 }
 
 // One thread per chunk, 64 chunks per wavefront.  Coded words are fetched
-// four at a time into a 128-bit register queue feeding a 64-bit bit buffer;
-// decoded symbols are staged in LDS, SB per lane, and each wave then stores
+// four at a time into a 128-bit register queue feeding a 64-bit bit buffer.
+// A 12-bit prefix table resolves short codes directly and gives the shortest
+// possible length for long ones (then at most a few comparisons against the
+// canonical limits); the (length, symbol) table is staged in LDS when it fits.
+// Decoded symbols are staged in LDS, SB per lane, and each wave then stores
 // its 64 chunks' segments contiguously.
-constexpr int kDecSB = 32;
+constexpr int kDecSB = 16;
+constexpr int kSortedLds = 24576;
 
+template <bool SORTED_LDS>
 __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, uint64_t off_sec,
                                                  uint64_t words_sec, uint64_t n_chunks,
                                                  uint64_t n_words, int C, int64_t N,
+                                                 uint32_t n_codes,
                                                  const DecodeTables* __restrict__ t,
                                                  uint16_t* __restrict__ sym, unsigned* status) {
   __shared__ uint32_t lut[1 << kLutBits];
@@ -812,6 +906,7 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
   __shared__ uint64_t limit[34];
   __shared__ uint32_t maxlen, valid;
   __shared__ uint16_t stage[4][64][kDecSB + 2];
+  __shared__ uint16_t sorted_l[SORTED_LDS ? kSortedLds : 1];
   if (threadIdx.x == 0) valid = t->valid;
   __syncthreads();
   if (!valid) return;  // table build rejected the codebook (status already set)
@@ -823,7 +918,10 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
     limit[threadIdx.x] = t->limit[threadIdx.x];
   }
   if (threadIdx.x == 0) maxlen = t->maxlen > (uint32_t)kMaxCodeLen ? kMaxCodeLen : t->maxlen;
+  if (SORTED_LDS)
+    for (uint32_t i = threadIdx.x; i < n_codes; i += 256) sorted_l[i] = t->sorted[i];
   __syncthreads();
+  const uint16_t* sorted = SORTED_LDS ? sorted_l : t->sorted;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t wave_chunk0 = (uint64_t)blockIdx.x * 256 + wave * 64;
   const uint64_t chunk = wave_chunk0 + lane;
@@ -868,33 +966,32 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
       }
       const uint32_t peek = (uint32_t)(buf >> 32);
       const uint32_t e = lut[peek >> (32 - kLutBits)];
-      unsigned len = e >> 16;
+      unsigned len = (e >> 16) & 63u;
       uint32_t s;
-      if (len) {
+      if (!(e & kLutLong)) {
         s = e & 0xFFFFu;
       } else {
-        len = kLutBits + 1;
         while (len <= maxlen && (uint64_t)peek >= limit[len]) ++len;
         const uint32_t v = len <= maxlen ? peek >> (32 - len) : 0u;
         if (len > maxlen || v < first[len] || v - first[len] >= count[len] ||
-            base[len] + (v - first[len]) >= (uint32_t)kDict) {
+            base[len] + (v - first[len]) >= n_codes) {
           bad = true;
           break;
         }
-        s = t->sorted[base[len] + (v - first[len])];
+        s = sorted[base[len] + (v - first[len])];
       }
       buf <<= len;
       nb -= (int)len;
       stage[wave][lane][k] = (uint16_t)s;
     }
     __syncthreads();
-    // store: rows of kn symbols, two rows per pass of the wave
-    for (int r = 0; r < 64; r += 2) {
-      const int row = r + (lane >> 5), col = lane & 31;
+    // store: rows of kn symbols, four rows per pass of the wave
+    for (int r = 0; r < 64; r += 4) {
+      const int row = r + (lane >> 4), col = lane & 15;
       const uint64_t c = wave_chunk0 + row;
       if (c < n_chunks && col < kn) {
         const int64_t pos = (int64_t)c * C + k0 + col;
-        if (pos < N && k0 + col < C) sym[pos] = stage[wave][row][col];
+        if (pos < N) sym[pos] = stage[wave][row][col];
       }
     }
     __syncthreads();
@@ -965,10 +1062,15 @@ void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
 }
 
 void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
-                   uint64_t n_words, int C, int64_t N, const DecodeTables* t, uint16_t* sym,
-                   unsigned* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_decode, dim3((unsigned)((n_chunks + 255) / 256)), dim3(256), 0, s, in,
-                     off_sec, words_sec, n_chunks, n_words, C, N, t, sym, status);
+                   uint64_t n_words, int C, int64_t N, uint64_t n_codes, const DecodeTables* t,
+                   uint16_t* sym, unsigned* status, hipStream_t s) {
+  const dim3 grid((unsigned)((n_chunks + 255) / 256));
+  if (n_codes <= (uint64_t)kSortedLds)
+    hipLaunchKernelGGL(k_decode<true>, grid, dim3(256), 0, s, in, off_sec, words_sec, n_chunks,
+                       n_words, C, N, (uint32_t)n_codes, t, sym, status);
+  else
+    hipLaunchKernelGGL(k_decode<false>, grid, dim3(256), 0, s, in, off_sec, words_sec, n_chunks,
+                       n_words, C, N, (uint32_t)n_codes, t, sym, status);
 }
 
 }  // namespace mgc

@@ -33,6 +33,8 @@ void launch_rec_interp(const double* Gc, const LevelGeom& g, const CoeffSrc& src
 void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, bool out_f32,
                        hipStream_t s);
 void launch_fill(void* out, bool out_f32, int64_t N, double v, hipStream_t s);
+// Copies n (<= a few KiB) bytes with one block, e.g. into mapped host memory.
+void launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 
 // ---- huffman.hip ---------------------------------------------------------
 struct CodebookScratch {
@@ -71,7 +73,7 @@ void launch_huff_header(uint8_t* out, uint32_t C, uint64_t N, uint64_t n_chunks,
 void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
                           unsigned* status, hipStream_t s);
 void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
-                   uint64_t n_words, int C, int64_t N, const DecodeTables* t, uint16_t* sym,
-                   unsigned* status, hipStream_t s);
+                   uint64_t n_words, int C, int64_t N, uint64_t n_codes, const DecodeTables* t,
+                   uint16_t* sym, unsigned* status, hipStream_t s);
 
 }  // namespace mgc

@@ -130,20 +130,33 @@ __global__ __launch_bounds__(256) void k_range_partial(const T* __restrict__ u, 
   }
 }
 
-__global__ __launch_bounds__(64) void k_range_final(const double* __restrict__ part, int nb,
-                                                     double* __restrict__ out) {
-  if (threadIdx.x != 0) return;
+// Reduces the per-block partials in a fixed tree order (deterministic).
+__global__ __launch_bounds__(256) void k_range_final(const double* __restrict__ part, int nb,
+                                                      double* __restrict__ out) {
+  __shared__ double sm[4][256];
+  const int t = threadIdx.x;
   double mn = INFINITY, mx = -INFINITY, ss = 0.0, bad = 0.0;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = t; b < nb; b += 256) {
     mn = fmin(mn, part[4 * b + 0]);
     mx = fmax(mx, part[4 * b + 1]);
     ss += part[4 * b + 2];
     bad = fmax(bad, part[4 * b + 3]);
   }
-  out[0] = mn;
-  out[1] = mx;
-  out[2] = ss;
-  out[3] = bad;
+  sm[0][t] = mn;
+  sm[1][t] = mx;
+  sm[2][t] = ss;
+  sm[3][t] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      sm[0][t] = fmin(sm[0][t], sm[0][t + w]);
+      sm[1][t] = fmax(sm[1][t], sm[1][t + w]);
+      sm[2][t] += sm[2][t + w];
+      sm[3][t] = fmax(sm[3][t], sm[3][t + w]);
+    }
+    __syncthreads();
+  }
+  if (t < 4) out[t] = sm[t][0];
 }
 
 // ------------------------------------------------------------- tile helpers
@@ -353,15 +366,29 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
   load_tabs(g, tl, tb, true);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // load the fine tile: one row (z, y) per wavefront step, lanes along x
+  // load the fine tile: flattened over the block, eight loads in flight per thread
   {
-    const int rows = tl.ext[0] * tl.ext[1];
-    const uint64_t m1 = div_magic((uint32_t)tl.ext[1]);
-    for (int rw = wave; rw < rows; rw += 4) {
-      const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
-      const Tin* src = G + ((size_t)(tl.lo[0] + z) * tl.nf[1] + tl.lo[1] + y) * tl.nf[2] + tl.lo[2];
-      Tin* dst = tile + (z * E1 + y) * E2;
-      for (int x = lane; x < tl.ext[2]; x += 64) dst[x] = src[x];
+    const int e12 = tl.ext[1] * tl.ext[2], n_ld = tl.ext[0] * e12;
+    const uint64_t m12 = div_magic((uint32_t)e12), m2 = div_magic((uint32_t)tl.ext[2]);
+    const Tin* base = G + ((size_t)tl.lo[0] * tl.nf[1] + tl.lo[1]) * tl.nf[2] + tl.lo[2];
+    const size_t pz = (size_t)tl.nf[1] * tl.nf[2], py = tl.nf[2];
+    for (int e0 = 0; e0 < n_ld; e0 += 256 * 8) {
+      Tin v[8];
+      int dst[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + tid;
+        dst[u] = -1;
+        if (e < n_ld) {
+          const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
+          const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
+          v[u] = base[z * pz + y * py + x];
+          dst[u] = (z * E1 + y) * E2 + x;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (dst[u] >= 0) tile[dst[u]] = v[u];
     }
   }
   __syncthreads();
@@ -431,22 +458,36 @@ __global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const C
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
   load_tabs(g, tl, tb, false);
   __syncthreads();
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
+  // dequantised coefficients of the loaded region (zero at coarse nodes),
+  // flattened over the block with eight symbol loads in flight per thread
   {
-    const int rows = tl.ext[0] * tl.ext[1];
-    const uint64_t m1 = div_magic((uint32_t)tl.ext[1]);
-    for (int rw = wave; rw < rows; rw += 4) {
-      const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
-      const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y;
-      const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]);
-      double* dst = tile + (z * E1 + y) * E2;
-      for (int x = lane; x < tl.ext[2]; x += 64) {
-        const uint32_t i2 = tl.lo[2] + x;
-        const bool n2 = is_new32(i2, tl.nf[2]);
-        double v = 0.0;
-        if (n0 || n1 || n2) v = coeff_at<RAW>(src, stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2), q);
-        dst[x] = v;
+    const int e12 = tl.ext[1] * tl.ext[2], n_ld = tl.ext[0] * e12;
+    const uint64_t m12 = div_magic((uint32_t)e12), m2 = div_magic((uint32_t)tl.ext[2]);
+    for (int e0 = 0; e0 < n_ld; e0 += 256 * 8) {
+      uint32_t pos[8];
+      int dst[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + tid;
+        dst[u] = -1;
+        pos[u] = 0xFFFFFFFFu;
+        if (e < n_ld) {
+          const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
+          const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
+          const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y, i2 = tl.lo[2] + x;
+          const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]),
+                     n2 = is_new32(i2, tl.nf[2]);
+          dst[u] = (z * E1 + y) * E2 + x;
+          if (n0 || n1 || n2) pos[u] = stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2);
+        }
       }
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pos[u] != 0xFFFFFFFFu ? coeff_at<RAW>(src, pos[u], q) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (dst[u] >= 0) tile[dst[u]] = v[u];
     }
   }
   __syncthreads();
@@ -674,6 +715,13 @@ __global__ __launch_bounds__(256) void k_rec_level0(const CoeffSrc src, int64_t 
     out[i] = (Tout)coeff_at<RAW>(src, i, q);
 }
 
+// Small device-to-host transfers: one block copies n bytes into mapped
+// pinned host memory (cheaper than a runtime copy for a few hundred bytes).
+__global__ __launch_bounds__(256) void k_copy_bytes(uint8_t* __restrict__ dst,
+                                                     const uint8_t* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += 256) dst[i] = src[i];
+}
+
 template <typename Tout>
 __global__ __launch_bounds__(256) void k_fill(Tout* __restrict__ out, int64_t N, double v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -782,7 +830,7 @@ void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, double* 
     else hipLaunchKernelGGL((k_range_partial<double, false>), dim3(kRangeBlocks), dim3(256), 0, s,
                             static_cast<const double*>(u), N, part);
   }
-  hipLaunchKernelGGL(k_range_final, dim3(1), dim3(64), 0, s, part, kRangeBlocks, out);
+  hipLaunchKernelGGL(k_range_final, dim3(1), dim3(256), 0, s, part, kRangeBlocks, out);
 }
 
 void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* fout,
@@ -862,6 +910,11 @@ void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, boo
     else hipLaunchKernelGGL((k_rec_level0<double, false>), dim3(b), dim3(256), 0, s, src, m0, q,
                             static_cast<double*>(out));
   }
+}
+
+void launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_bytes, dim3(1), dim3(256), 0, s, static_cast<uint8_t*>(dst),
+                     static_cast<const uint8_t*>(src), (int)n);
 }
 
 void launch_fill(void* out, bool out_f32, int64_t N, double v, hipStream_t s) {
