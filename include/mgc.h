@@ -68,7 +68,7 @@ int mgc_version(void);
  *
  * mgc_compress_query: workspace and worst-case output bytes for an array of
  *   `shape` (ndim entries) and dtype, with room for `outlier_cap` escaped
- *   values (0 = default, max(65536, N/4)).
+ *   values (0 = default, max(65536, N/16)).
  * mgc_compress (BLOCKING): compresses d_in into d_out and stores the stream
  *   length in *h_out_size.  error_bound > 0 is relative (to max - min for
  *   L-inf, to ||u||_2 for L2) when mode == MGC_REL, absolute otherwise; the
@@ -128,6 +128,33 @@ mgc_status mgc_decompose(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t
 mgc_status mgc_recompose(mgc_ctx ctx, const double* d_coeffs, int ndim,
                          const uint64_t* shape, mgc_dtype out_dtype, void* d_out,
                          void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Differentiation form.  Recomposition is linear in the coefficients, so the
+ * gradient of any quantity of interest J(u) with respect to the multilevel
+ * coefficients c is R^T (dJ/du), R = recompose.  mgc_recompose_adjoint applies
+ * R^T level by level from the finest: Gbar = P^T g, v = M_{l-1}^{-1} Gbar,
+ * cbar_l = (g - M_l P v) at the level's new nodes, then g = Gbar; finally
+ * cbar_0 = g.  d_grad_u holds N doubles on the input grid (row-major) and
+ * d_grad_coeffs receives N doubles in stream order.  Quantisation has no
+ * useful derivative; treating it as the identity (straight-through) makes
+ * this also the gradient with respect to the unquantised coefficients.
+ *
+ * mgc_recompose_levels is mgc_recompose that also stores every coarse level's
+ * nodal grid G_0 .. G_{L-1} (FP64, level after level, row-major) in d_levels
+ * (levels_bytes >= 8 * sum of their sizes; see mgc_levels_query), the
+ * per-level checkpoints of a forward pass.
+ * Asynchronous on `stream`.  Errors: MGC_EINVAL, MGC_ENOSPC, MGC_EDEVICE.
+ * ---------------------------------------------------------------------- */
+mgc_status mgc_adjoint_query(int ndim, const uint64_t* shape, size_t* ws_bytes);
+mgc_status mgc_recompose_adjoint(mgc_ctx ctx, const double* d_grad_u, int ndim,
+                                 const uint64_t* shape, double* d_grad_coeffs, void* d_ws,
+                                 size_t ws_bytes, void* stream);
+mgc_status mgc_levels_query(int ndim, const uint64_t* shape, size_t* levels_bytes);
+mgc_status mgc_recompose_levels(mgc_ctx ctx, const double* d_coeffs, int ndim,
+                                const uint64_t* shape, mgc_dtype out_dtype, void* d_out,
+                                double* d_levels, size_t levels_bytes, void* d_ws,
+                                size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Huffman stage alone (Algorithm 2) on n 16-bit symbols, chunk size C

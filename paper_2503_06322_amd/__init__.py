@@ -21,8 +21,9 @@ import os
 import threading
 
 __all__ = ["MgcError", "library_path", "compress", "decompress", "decompose", "recompose",
-           "huffman_encode", "huffman_decode", "header_info", "profile_enable",
-           "profile_reset", "profile_read", "compress_query", "transform_query"]
+           "recompose_adjoint", "recompose_levels", "Recompose", "huffman_encode",
+           "huffman_decode", "header_info", "profile_enable", "profile_reset", "profile_read",
+           "compress_query", "transform_query"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmgc.so")
@@ -74,6 +75,11 @@ def _load():
             "mgc_transform_query": [ctypes.c_int, c_u64p, c_szp],
             "mgc_decompose": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, vp, vp, ctypes.c_size_t, vp],
             "mgc_recompose": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, vp, vp, ctypes.c_size_t, vp],
+            "mgc_adjoint_query": [ctypes.c_int, c_u64p, c_szp],
+            "mgc_recompose_adjoint": [vp, vp, ctypes.c_int, c_u64p, vp, vp, ctypes.c_size_t, vp],
+            "mgc_levels_query": [ctypes.c_int, c_u64p, c_szp],
+            "mgc_recompose_levels": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, vp, vp,
+                                     ctypes.c_size_t, vp, ctypes.c_size_t, vp],
             "mgc_huffman_query": [ctypes.c_uint64, ctypes.c_uint32, c_szp, c_szp],
             "mgc_huffman_encode": [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_size_t,
                                    vp, ctypes.c_size_t, vp, c_u64p],
@@ -268,6 +274,93 @@ def recompose(coeffs, shape, dtype=None, workspace=None):
                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel(), _stream_ptr(dev)))
     return out
+
+
+def recompose_adjoint(grad_u, workspace=None):
+    """R^T grad_u: gradient with respect to the multilevel coefficients (FP64,
+    stream order) of a quantity whose gradient on the grid is ``grad_u``."""
+    _require_gpu(grad_u, "gradient")
+    torch = _torch()
+    g = grad_u.contiguous().to(torch.float64)
+    dev = g.device.index if g.device.index is not None else torch.cuda.current_device()
+    shape = tuple(g.shape)
+    ws_n = ctypes.c_size_t()
+    _check(_load().mgc_adjoint_query(len(shape), _shape_arg(shape), ctypes.byref(ws_n)))
+    ws = workspace if workspace is not None and workspace.numel() >= ws_n.value \
+        else _empty(ws_n.value, g.device)
+    out = torch.empty(g.numel(), dtype=torch.float64, device=g.device)
+    _check(_load().mgc_recompose_adjoint(_ctx(dev), ctypes.c_void_p(g.data_ptr()), len(shape),
+                                         _shape_arg(shape), ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream_ptr(dev)))
+    return out
+
+
+def recompose_levels(coeffs, shape, dtype=None):
+    """recompose() that also returns every coarse level's grid G_0..G_{L-1}
+    (FP64) as one flat tensor, level after level (per-level checkpoints)."""
+    _require_gpu(coeffs, "coefficients")
+    torch = _torch()
+    dtype = dtype or torch.float64
+    coeffs = coeffs.contiguous()
+    dev = coeffs.device.index if coeffs.device.index is not None else torch.cuda.current_device()
+    shape = tuple(int(x) for x in shape)
+    lv = ctypes.c_size_t()
+    _check(_load().mgc_levels_query(len(shape), _shape_arg(shape), ctypes.byref(lv)))
+    levels = torch.empty(lv.value // 8, dtype=torch.float64, device=coeffs.device)
+    ws = _empty(transform_query(shape), coeffs.device)
+    out = torch.empty(shape, dtype=dtype, device=coeffs.device)
+    _check(_load().mgc_recompose_levels(_ctx(dev), ctypes.c_void_p(coeffs.data_ptr()), len(shape),
+                                        _shape_arg(shape), _dtype_code(dtype),
+                                        ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(levels.data_ptr()), levels.numel() * 8,
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream_ptr(dev)))
+    return out, levels
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class Recompose(torch.autograd.Function):
+        """u = R c with the GPU recomposition; backward applies the GPU adjoint.
+
+        ``Recompose.apply(coeffs, shape, keep_levels)``: coeffs is the FP64
+        coefficient vector in stream order.  With keep_levels the forward pass
+        also stores the coarse levels' grids (checkpoints), available as
+        ``ctx.levels`` during backward; recomposition being linear, the
+        gradient does not need them.  Quantisation, if the coefficients came
+        from a compressed stream, is treated as the identity (straight-through).
+        """
+
+        @staticmethod
+        def forward(ctx, coeffs, shape, keep_levels=False):
+            shape = tuple(int(x) for x in shape)
+            ctx.shape = shape
+            if keep_levels:
+                u, levels = recompose_levels(coeffs.detach(), shape, torch.float64)
+                ctx.save_for_backward(levels)
+            else:
+                u = recompose(coeffs.detach(), shape, torch.float64)
+            return u
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            return recompose_adjoint(grad_u), None, None
+
+    return Recompose
+
+
+class _LazyRecompose:
+    _cls = None
+
+    def apply(self, *args):
+        if _LazyRecompose._cls is None:
+            _LazyRecompose._cls = _autograd_function()
+        return _LazyRecompose._cls.apply(*args)
+
+
+Recompose = _LazyRecompose()
 
 
 def huffman_encode(symbols, C: int = 1024):

@@ -299,19 +299,28 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
   launch_level0(Gcur, cur_f32, p.points(0), sym, raw, sym ? r[0] : 0.0, ob, status, s);
 }
 
+// levels (optional) receives G_0 .. G_{L-1}, level after level.
 void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
                           const std::vector<double>& q, double* gA, double* gB, void* d_out,
-                          bool out_f32, hipStream_t s) {
+                          bool out_f32, hipStream_t s, double* levels = nullptr) {
   if (p.L == 0) {
     StageScope sc(&ctx->prof, "rec_level0", s);
     launch_rec_level0(src, p.points(0), q[0], d_out, out_f32, s);
     return;
   }
+  std::vector<double*> slot(p.L + 1, gA);
+  if (levels) {
+    size_t off = 0;
+    for (int l = 0; l < p.L; ++l) {
+      slot[l] = levels + off;
+      off += (size_t)p.points(l);
+    }
+  }
   {
     StageScope sc(&ctx->prof, "rec_level0", s);
-    launch_rec_level0(src, p.points(0), q[0], gA, false, s);
+    launch_rec_level0(src, p.points(0), q[0], slot[0], false, s);
   }
-  double* Gprev = gA;
+  double* Gprev = slot[0];
   double* F = gB;
   int last = -1;
   for (int axis = 0; axis <= 2; ++axis)
@@ -333,7 +342,9 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
     }
     {
       StageScope sc(&ctx->prof, fin ? "rec_interp[finest]" : "rec_interp", s);
-      launch_rec_interp(F, g, src, q[l], fin ? d_out : (void*)Gprev, fin && out_f32, s);
+      double* dst = levels ? slot[l] : Gprev;
+      launch_rec_interp(F, g, src, q[l], fin ? d_out : (void*)dst, fin && out_f32, s);
+      if (!fin) Gprev = dst;
     }
   }
 }
@@ -651,6 +662,108 @@ mgc_status mgc_recompose(mgc_ctx ctx, const double* d_coeffs, int ndim, const ui
     CoeffSrc src{nullptr, d_coeffs, nullptr, nullptr, 0};
     run_levels_recompose(ctx, p, src, std::vector<double>(p.L + 1, 1.0), gA, gB, d_out,
                          out_dtype == MGC_F32, s);
+    MGC_HIP(hipGetLastError());
+  });
+}
+
+namespace {
+struct AdjointWs {
+  double *gA, *gB, *Y, *T;
+};
+AdjointWs carve_adjoint(Carver& c, const Plan& p) {
+  const int64_t n_coarse = p.L >= 1 ? p.points(p.L - 1) : 1;
+  AdjointWs w;
+  w.gA = c.take<double>(n_coarse);
+  w.gB = c.take<double>(n_coarse);
+  w.Y = c.take<double>(n_coarse);
+  w.T = c.take<double>(std::max<int64_t>(p.N, 1));
+  return w;
+}
+size_t levels_bytes_of(const Plan& p) {
+  size_t n = 0;
+  for (int l = 0; l < p.L; ++l) n += (size_t)p.points(l);
+  return 8 * std::max<size_t>(n, 1);
+}
+}  // namespace
+
+mgc_status mgc_adjoint_query(int ndim, const uint64_t* shape, size_t* ws_bytes) {
+  return guard([&] {
+    Plan p = build_plan(ndim, shape);
+    Carver c(nullptr);
+    carve_adjoint(c, p);
+    if (ws_bytes) *ws_bytes = c.off;
+  });
+}
+
+mgc_status mgc_recompose_adjoint(mgc_ctx ctx, const double* d_grad_u, int ndim,
+                                 const uint64_t* shape, double* d_grad_coeffs, void* d_ws,
+                                 size_t ws_bytes, void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    const Plan& p = get_plan(ctx, ndim, shape);
+    if (p.N == 0) return;
+    if (!d_grad_u || !d_grad_coeffs || !d_ws) fail(MGC_EINVAL, "null device pointer");
+    Carver meas(nullptr);
+    carve_adjoint(meas, p);
+    if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
+    Carver c(d_ws);
+    AdjointWs w = carve_adjoint(c, p);
+    hipStream_t s = as_stream(stream);
+    const double* g = d_grad_u;
+    for (int l = p.L; l >= 1; --l) {
+      const LevelGeom geom = p.geom(l);
+      double* Gc = (g == w.gA) ? w.gB : w.gA;
+      {
+        StageScope sc(&ctx->prof, "adj_restrict", s);
+        launch_adj_restrict(g, geom, Gc, w.Y, s);
+      }
+      for (int axis = 2; axis >= 0; --axis) {
+        if (p.bit[axis] < 0) continue;
+        StageScope sc(&ctx->prof, "thomas", s);
+        launch_thomas(axis, w.Y, geom.nc, geom.ax[axis], nullptr, s);
+      }
+      {
+        StageScope sc(&ctx->prof, "adj_prolong", s);
+        launch_prolong(w.Y, geom, w.T, s);
+      }
+      {
+        StageScope sc(&ctx->prof, "adj_mass", s);
+        launch_adj_mass(w.T, g, geom, d_grad_coeffs, s);
+      }
+      g = Gc;
+    }
+    OutlierBuf ob{nullptr, nullptr, nullptr, 0};
+    launch_level0(g, false, p.points(0), nullptr, d_grad_coeffs, 0.0, ob, nullptr, s);
+    MGC_HIP(hipGetLastError());
+  });
+}
+
+mgc_status mgc_levels_query(int ndim, const uint64_t* shape, size_t* levels_bytes) {
+  return guard([&] {
+    Plan p = build_plan(ndim, shape);
+    if (levels_bytes) *levels_bytes = levels_bytes_of(p);
+  });
+}
+
+mgc_status mgc_recompose_levels(mgc_ctx ctx, const double* d_coeffs, int ndim,
+                                const uint64_t* shape, mgc_dtype out_dtype, void* d_out,
+                                double* d_levels, size_t levels_bytes, void* d_ws,
+                                size_t ws_bytes, void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (out_dtype != MGC_F32 && out_dtype != MGC_F64) fail(MGC_EINVAL, "dtype must be f32 or f64");
+    const Plan& p = get_plan(ctx, ndim, shape);
+    if (p.N == 0) return;
+    if (levels_bytes < levels_bytes_of(p)) fail(MGC_ENOSPC, "level buffer too small");
+    const int64_t n_coarse = p.L >= 1 ? p.points(p.L - 1) : 1;
+    Carver c(d_ws);
+    double* gA = c.take<double>(n_coarse);
+    double* gB = c.take<double>(n_coarse);
+    c.take<unsigned>(4);
+    if (ws_bytes < c.off) fail(MGC_ENOSPC, "workspace too small");
+    CoeffSrc src{nullptr, d_coeffs, nullptr, nullptr, 0};
+    run_levels_recompose(ctx, p, src, std::vector<double>(p.L + 1, 1.0), gA, gB, d_out,
+                         out_dtype == MGC_F32, as_stream(stream), d_levels);
     MGC_HIP(hipGetLastError());
   });
 }

@@ -37,6 +37,8 @@ struct AxisTab {
   const double* ta;  // [nc] Thomas: sub-diagonal of the coarse mass matrix
   const double* tm;  // [nc] Thomas: reciprocal pivots
   const double* tc;  // [nc] Thomas: super-diagonal times reciprocal pivot
+  const double* WP;  // [nc*5] taps of P^T at fine p(j)-2 .. p(j)+2 (adjoint)
+  const double* Mt;  // [nf*3] fine mass-matrix row (i-1, i, i+1) (adjoint)
 };
 
 // Geometry of level l (fine grid = level l, coarse grid = level l-1) in the

@@ -863,7 +863,8 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     lbase[tid] = sm.lbase[tid];
   }
   __syncthreads();
-  for (unsigned i = tid; i < (1u << kLutBits); i += 1024) t->lut[i] = kLutLong | (63u << 16);
+  __shared__ uint32_t lut[1 << kLutBits];
+  for (unsigned i = tid; i < (1u << kLutBits); i += 1024) lut[i] = kLutLong | (63u << 16);
   __syncthreads();
   stable_digit_ranks(
       n, [&](unsigned i) { return (unsigned)lens[i]; },
@@ -873,44 +874,44 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
         const unsigned c = lfirst[d] + rank;
         if (d <= (unsigned)kLutBits) {
           const unsigned a = c << (kLutBits - d), b = (c + 1) << (kLutBits - d);
-          for (unsigned e = a; e < b; ++e) t->lut[e] = sy | (d << 16);
+          for (unsigned e = a; e < b; ++e) lut[e] = sy | (d << 16);
         } else {
-          // canonical order: lengths grow with the code, so the first code
-          // under a prefix has the prefix's shortest length
-          atomicMin(&t->lut[c >> (d - kLutBits)], kLutLong | (d << 16));
+          // the shortest length among the codes under this prefix
+          atomicMin(&lut[c >> (d - kLutBits)], kLutLong | (d << 16));
         }
       },
       sm);
+  for (unsigned i = tid; i < (1u << kLutBits); i += 1024) t->lut[i] = lut[i];
+  __syncthreads();
   if (tid == 0) t->valid = 1;
 }
 
-// One thread per chunk, 64 chunks per wavefront.  Coded words are fetched
-// four at a time into a 128-bit register queue feeding a 64-bit bit buffer.
-// A 12-bit prefix table resolves short codes directly and gives the shortest
-// possible length for long ones (then at most a few comparisons against the
-// canonical limits); the (length, symbol) table is staged in LDS when it fits.
-// Decoded symbols are staged in LDS, SB per lane, and each wave then stores
-// its 64 chunks' segments contiguously.
-constexpr int kDecSB = 16;
-constexpr int kSortedLds = 24576;
+// One thread per chunk, 64 chunks per wavefront, eight wavefronts per block.
+// Coded words are fetched four at a time into a 128-bit register queue that
+// feeds a 64-bit bit buffer.  A 12-bit prefix table resolves short codes
+// directly and gives the shortest possible length for long ones (then a few
+// comparisons against the canonical limits); the (length, symbol) table is
+// held in LDS (dynamic size: the codebook's).  Decoded symbols are staged in
+// LDS, SB per lane, and each wave then stores its chunks' segments
+// contiguously.
+constexpr int kDecSB = 8;
+constexpr int kDecWaves = 8;
 
-template <bool SORTED_LDS>
-__global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, uint64_t off_sec,
-                                                 uint64_t words_sec, uint64_t n_chunks,
-                                                 uint64_t n_words, int C, int64_t N,
-                                                 uint32_t n_codes,
-                                                 const DecodeTables* __restrict__ t,
-                                                 uint16_t* __restrict__ sym, unsigned* status) {
+__global__ __launch_bounds__(64 * kDecWaves) void k_decode(
+    const uint8_t* __restrict__ in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
+    uint64_t n_words, int C, int64_t N, uint32_t n_codes, const DecodeTables* __restrict__ t,
+    uint16_t* __restrict__ sym, unsigned* status) {
+  extern __shared__ uint16_t sorted[];  // n_codes entries
   __shared__ uint32_t lut[1 << kLutBits];
   __shared__ uint32_t first[34], count[34], base[34];
   __shared__ uint64_t limit[34];
   __shared__ uint32_t maxlen, valid;
-  __shared__ uint16_t stage[4][64][kDecSB + 2];
-  __shared__ uint16_t sorted_l[SORTED_LDS ? kSortedLds : 1];
+  __shared__ uint16_t stage[kDecWaves][64][kDecSB + 2];
+  const int nthr = 64 * kDecWaves;
   if (threadIdx.x == 0) valid = t->valid;
   __syncthreads();
   if (!valid) return;  // table build rejected the codebook (status already set)
-  for (int i = threadIdx.x; i < (1 << kLutBits); i += 256) lut[i] = t->lut[i];
+  for (int i = threadIdx.x; i < (1 << kLutBits); i += nthr) lut[i] = t->lut[i];
   if (threadIdx.x < 34) {
     first[threadIdx.x] = t->first[threadIdx.x];
     count[threadIdx.x] = t->count[threadIdx.x];
@@ -918,12 +919,10 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
     limit[threadIdx.x] = t->limit[threadIdx.x];
   }
   if (threadIdx.x == 0) maxlen = t->maxlen > (uint32_t)kMaxCodeLen ? kMaxCodeLen : t->maxlen;
-  if (SORTED_LDS)
-    for (uint32_t i = threadIdx.x; i < n_codes; i += 256) sorted_l[i] = t->sorted[i];
+  for (uint32_t i = threadIdx.x; i < n_codes; i += nthr) sorted[i] = t->sorted[i];
   __syncthreads();
-  const uint16_t* sorted = SORTED_LDS ? sorted_l : t->sorted;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const uint64_t wave_chunk0 = (uint64_t)blockIdx.x * 256 + wave * 64;
+  const uint64_t wave_chunk0 = (uint64_t)blockIdx.x * nthr + wave * 64;
   const uint64_t chunk = wave_chunk0 + lane;
   const uint64_t* offs = reinterpret_cast<const uint64_t*>(in + off_sec);
   const uint32_t* words = reinterpret_cast<const uint32_t*>(in + words_sec);
@@ -985,9 +984,9 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ in, 
       stage[wave][lane][k] = (uint16_t)s;
     }
     __syncthreads();
-    // store: rows of kn symbols, four rows per pass of the wave
-    for (int r = 0; r < 64; r += 4) {
-      const int row = r + (lane >> 4), col = lane & 15;
+    // store: rows of kn symbols, eight rows per pass of the wave
+    for (int r = 0; r < 64; r += 8) {
+      const int row = r + (lane >> 3), col = lane & 7;
       const uint64_t c = wave_chunk0 + row;
       if (c < n_chunks && col < kn) {
         const int64_t pos = (int64_t)c * C + k0 + col;
@@ -1064,13 +1063,18 @@ void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
 void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
                    uint64_t n_words, int C, int64_t N, uint64_t n_codes, const DecodeTables* t,
                    uint16_t* sym, unsigned* status, hipStream_t s) {
-  const dim3 grid((unsigned)((n_chunks + 255) / 256));
-  if (n_codes <= (uint64_t)kSortedLds)
-    hipLaunchKernelGGL(k_decode<true>, grid, dim3(256), 0, s, in, off_sec, words_sec, n_chunks,
-                       n_words, C, N, (uint32_t)n_codes, t, sym, status);
-  else
-    hipLaunchKernelGGL(k_decode<false>, grid, dim3(256), 0, s, in, off_sec, words_sec, n_chunks,
-                       n_words, C, N, (uint32_t)n_codes, t, sym, status);
+  const int nthr = 64 * kDecWaves;
+  const dim3 grid((unsigned)((n_chunks + nthr - 1) / nthr));
+  const size_t dyn = ((size_t)n_codes * sizeof(uint16_t) + 15) & ~size_t(15);
+  static bool attr_set = false;
+  if (!attr_set) {
+    // allow the full 128 KiB table on top of the static LDS
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_decode),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_decode, grid, dim3(nthr), dyn, s, in, off_sec, words_sec, n_chunks, n_words,
+                     C, N, (uint32_t)n_codes, t, sym, status);
 }
 
 }  // namespace mgc

@@ -32,6 +32,14 @@ void launch_rec_interp(const double* Gc, const LevelGeom& g, const CoeffSrc& src
                        void* out, bool out_f32, hipStream_t s);
 void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, bool out_f32,
                        hipStream_t s);
+// Adjoint of recomposition, one level: Gc = P^T g (also copied to Gc_copy,
+// which the Thomas sweeps then turn into v = M_{l-1}^{-1} Gc); Pv on the fine
+// grid; cbar (stream order) = g - M_l P v at the level's new nodes.
+void launch_adj_restrict(const double* gl, const LevelGeom& g, double* Gc, double* Gc_copy,
+                         hipStream_t s);
+void launch_prolong(const double* v, const LevelGeom& g, double* out, hipStream_t s);
+void launch_adj_mass(const double* Pv, const double* gl, const LevelGeom& g, double* cbar,
+                     hipStream_t s);
 void launch_fill(void* out, bool out_f32, int64_t N, double v, hipStream_t s);
 // Copies n (<= a few KiB) bytes with one block, e.g. into mapped host memory.
 void launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);

@@ -152,15 +152,23 @@ Plan build_plan(int ndim, const uint64_t* shape) {
         p.tab.resize(p.tab.size() + nc, 0.0);
         v.t_tc[k] = p.tab.size();
         p.tab.resize(p.tab.size() + nc, 0.0);
+        v.t_WP[k] = p.tab.size();
+        p.tab.resize(p.tab.size() + 5 * nc, 0.0);
+        v.t_Mt[k] = p.tab.size();
+        p.tab.resize(p.tab.size() + 3 * nf, 0.0);
         double* wl = &p.tab[v.t_wl[k]];
         double* wr = &p.tab[v.t_wr[k]];
         double* W = &p.tab[v.t_W[k]];
         double* ta = &p.tab[v.t_ta[k]];
         double* tm = &p.tab[v.t_tm[k]];
         double* tc = &p.tab[v.t_tc[k]];
+        double* WP = &p.tab[v.t_WP[k]];
+        double* Mt = &p.tab[v.t_Mt[k]];
         if (p.bit[k] < 0) {  // inactive axis: identity operators
           W[2] = 1.0;
           tm[0] = 1.0;
+          WP[2] = 1.0;
+          Mt[1] = 1.0;
           continue;
         }
         for (int64_t i = 0; i < nf; ++i) {
@@ -184,6 +192,19 @@ Plan build_plan(int ndim, const uint64_t* shape) {
             }
             W[5 * j + d + 2] = acc2;
           }
+        }
+        // P^T row of coarse node j: its own fine node and the new nodes beside it
+        for (int64_t j = 0; j < nc; ++j) {
+          const int64_t pj = cpos(j, nf);
+          WP[5 * j + 2] = 1.0;
+          if (pj - 1 >= 0 && is_new(pj - 1, nf)) WP[5 * j + 1] = wr[pj - 1];
+          if (pj + 1 < nf && is_new(pj + 1, nf)) WP[5 * j + 3] = wl[pj + 1];
+        }
+        // fine mass-matrix rows
+        for (int64_t i = 0; i < nf; ++i) {
+          Mt[3 * i + 0] = mass_entry(xf, i, i - 1);
+          Mt[3 * i + 1] = mass_entry(xf, i, i);
+          Mt[3 * i + 2] = mass_entry(xf, i, i + 1);
         }
         // Thomas factors of the coarse mass matrix
         double cprev = 0.0;
@@ -230,6 +251,8 @@ LevelGeom Plan::geom(int l) const {
       g.ax[k].ta = d_tab + v.t_ta[k];
       g.ax[k].tm = d_tab + v.t_tm[k];
       g.ax[k].tc = d_tab + v.t_tc[k];
+      g.ax[k].WP = d_tab + v.t_WP[k];
+      g.ax[k].Mt = d_tab + v.t_Mt[k];
     }
   }
   g.level_off = v.off;

@@ -15,7 +15,7 @@ struct PlanLevel {
   int64_t count;          // entries contributed (level 0: all nodes)
   int64_t sub_off[8];
   double hmax[3];         // largest spacing on each internal axis at level l
-  size_t t_wl[3], t_wr[3], t_W[3], t_ta[3], t_tm[3], t_tc[3];  // table offsets
+  size_t t_wl[3], t_wr[3], t_W[3], t_ta[3], t_tm[3], t_tc[3], t_WP[3], t_Mt[3];  // table offsets
 };
 
 struct Plan {

@@ -240,16 +240,19 @@ struct TileTabs {
 
 template <int E0, int E1, int E2, int TZ, int TY, int TX>
 __device__ void load_tabs(const LevelGeom& g, const Tile& tl, TileTabs<E0, E1, E2, TZ, TY, TX>& tb,
-                          bool need_w) {
+                          bool need_w, bool transpose_p = false) {
   const int tid = threadIdx.x;
   if (need_w) {
     for (int i = tid; i < tl.ext[0]; i += 256) { tb.wl0[i] = g.ax[0].wl[tl.lo[0] + i]; tb.wr0[i] = g.ax[0].wr[tl.lo[0] + i]; }
     for (int i = tid; i < tl.ext[1]; i += 256) { tb.wl1[i] = g.ax[1].wl[tl.lo[1] + i]; tb.wr1[i] = g.ax[1].wr[tl.lo[1] + i]; }
     for (int i = tid; i < tl.ext[2]; i += 256) { tb.wl2[i] = g.ax[2].wl[tl.lo[2] + i]; tb.wr2[i] = g.ax[2].wr[tl.lo[2] + i]; }
   }
-  for (int i = tid; i < 5 * tl.tk[0]; i += 256) tb.W0[i / 5][i % 5] = g.ax[0].W[5 * tl.c0[0] + i];
-  for (int i = tid; i < 5 * tl.tk[1]; i += 256) tb.W1[i / 5][i % 5] = g.ax[1].W[5 * tl.c0[1] + i];
-  for (int i = tid; i < 5 * tl.tk[2]; i += 256) tb.W2[i / 5][i % 5] = g.ax[2].W[5 * tl.c0[2] + i];
+  const double* W0 = transpose_p ? g.ax[0].WP : g.ax[0].W;
+  const double* W1 = transpose_p ? g.ax[1].WP : g.ax[1].W;
+  const double* W2 = transpose_p ? g.ax[2].WP : g.ax[2].W;
+  for (int i = tid; i < 5 * tl.tk[0]; i += 256) tb.W0[i / 5][i % 5] = W0[5 * tl.c0[0] + i];
+  for (int i = tid; i < 5 * tl.tk[1]; i += 256) tb.W1[i / 5][i % 5] = W1[5 * tl.c0[1] + i];
+  for (int i = tid; i < 5 * tl.tk[2]; i += 256) tb.W2[i / 5][i % 5] = W2[5 * tl.c0[2] + i];
   for (int i = tid; i < tl.tk[0]; i += 256) tb.P0[i] = (int)(cpos32(tl.c0[0] + i, tl.nf[0]) - tl.lo[0]);
   for (int i = tid; i < tl.tk[1]; i += 256) tb.P1[i] = (int)(cpos32(tl.c0[1] + i, tl.nf[1]) - tl.lo[1]);
   for (int i = tid; i < tl.tk[2]; i += 256) tb.P2[i] = (int)(cpos32(tl.c0[2] + i, tl.nf[2]) - tl.lo[2]);
@@ -274,7 +277,8 @@ __device__ __forceinline__ uint32_t stream_pos(const LevelGeom& g, const Tile& t
 // coarse outputs, written to fout (coarse grid).  A and B are LDS scratch.
 template <typename V, int E0, int E1, int E2, int TZ, int TY, int TX>
 __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& tl,
-                              const TileTabs<E0, E1, E2, TZ, TY, TX>& tb, double* __restrict__ fout) {
+                              const TileTabs<E0, E1, E2, TZ, TY, TX>& tb, double* __restrict__ fout,
+                              double* __restrict__ fout2 = nullptr) {
   const int tid = threadIdx.x;
   constexpr int CW = TX < 64 ? TX : 64;        // lanes per output row
   constexpr int RS = 256 / CW;                  // rows per block step
@@ -327,7 +331,8 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
     for (int rw = rsub; rw < rows; rw += RS) {
       const int cz = (int)div_small((uint32_t)rw, m1), cy = rw - cz * tl.tk[1];
       const int p = tb.P0[cz];
-      double* orow = fout + ((size_t)(tl.c0[0] + cz) * tl.nc[1] + tl.c0[1] + cy) * tl.nc[2] + tl.c0[2];
+      const size_t ro = ((size_t)(tl.c0[0] + cz) * tl.nc[1] + tl.c0[1] + cy) * tl.nc[2] + tl.c0[2];
+      double* orow = fout + ro;
       for (int cx = col0; cx < tl.tk[2]; cx += CW) {
         double acc = 0.0;
 #pragma unroll
@@ -337,13 +342,16 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
           acc += tb.W0[cz][d] * (in ? B[((in ? f : 0) * TY + cy) * TX + cx] : 0.0);
         }
         orow[cx] = acc;
+        if (fout2) fout2[ro + cx] = acc;
       }
     }
   }
 }
 
 // ----------------------------------------------- decomposition of one level
-template <typename Tin, int TZ, int TY, int TX, bool QUANT>
+// MODE: 0 quantise the coefficients, 1 write them as FP64, 2 adjoint (no
+// coefficients; restriction with the P^T taps written to fout and fout2).
+template <typename Tin, int TZ, int TY, int TX, int MODE>
 __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, const LevelGeom g,
                                                     double* __restrict__ fout,
                                                     uint16_t* __restrict__ sym,
@@ -364,37 +372,37 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
   if (t >= n_tiles) return;
   Tile tl;
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
-  load_tabs(g, tl, tb, true);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // load the fine tile: flattened over the block, eight loads in flight per thread
+  load_tabs(g, tl, tb, MODE != 2, MODE == 2);
+  const int tid = threadIdx.x;
+  // load the fine tile: flattened over the block, every load of a thread in
+  // flight before the first LDS store
   {
+    constexpr int NLD = (E0 * E1 * E2 + 255) / 256;
     const int e12 = tl.ext[1] * tl.ext[2], n_ld = tl.ext[0] * e12;
     const uint64_t m12 = div_magic((uint32_t)e12), m2 = div_magic((uint32_t)tl.ext[2]);
     const Tin* base = G + ((size_t)tl.lo[0] * tl.nf[1] + tl.lo[1]) * tl.nf[2] + tl.lo[2];
     const size_t pz = (size_t)tl.nf[1] * tl.nf[2], py = tl.nf[2];
-    for (int e0 = 0; e0 < n_ld; e0 += 256 * 8) {
-      Tin v[8];
-      int dst[8];
+    Tin v[NLD];
+    int dst[NLD];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + tid;
-        dst[u] = -1;
-        if (e < n_ld) {
-          const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
-          const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
-          v[u] = base[z * pz + y * py + x];
-          dst[u] = (z * E1 + y) * E2 + x;
-        }
+    for (int u = 0; u < NLD; ++u) {
+      const int e = u * 256 + tid;
+      dst[u] = -1;
+      if (e < n_ld) {
+        const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
+        const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
+        v[u] = base[z * pz + y * py + x];
+        dst[u] = (z * E1 + y) * E2 + x;
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (dst[u] >= 0) tile[dst[u]] = v[u];
     }
+#pragma unroll
+    for (int u = 0; u < NLD; ++u)
+      if (dst[u] >= 0) tile[dst[u]] = v[u];
   }
   __syncthreads();
 
   // lerp + quantise the owned new nodes
-  {
+  if (MODE != 2) {
     constexpr int OX = 2 * TX;
     constexpr int CW = OX < 64 ? OX : 64;
     constexpr int RS = 256 / CW;
@@ -429,13 +437,13 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
         const double interp = wz0 * (wy0 * i00 + wy1 * i01) + wz1 * (wy0 * i10 + wy1 * i11);
         const double cval = (double)rc[x] - interp;
         const uint32_t pos = stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2);
-        if (QUANT) emit_q(pos, cval, r, sym, ob, status);
+        if (MODE == 0) emit_q(pos, cval, r, sym, ob, status);
         else raw[pos] = cval;
       }
     }
   }
-  // mass_trans: separable restriction of G_l to the coarse outputs
-  restrict_tile(tile, A, reinterpret_cast<double*>(smem), tl, tb, fout);
+  // mass_trans (or P^T for the adjoint): separable restriction to the coarse outputs
+  restrict_tile(tile, A, reinterpret_cast<double*>(smem), tl, tb, fout, MODE == 2 ? raw : nullptr);
 }
 
 // --------------------------------------------- recomposition of one level
@@ -460,35 +468,34 @@ __global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const C
   __syncthreads();
   const int tid = threadIdx.x;
   // dequantised coefficients of the loaded region (zero at coarse nodes),
-  // flattened over the block with eight symbol loads in flight per thread
+  // flattened over the block with every symbol load of a thread in flight
   {
+    constexpr int NLD = (E0 * E1 * E2 + 255) / 256;
     const int e12 = tl.ext[1] * tl.ext[2], n_ld = tl.ext[0] * e12;
     const uint64_t m12 = div_magic((uint32_t)e12), m2 = div_magic((uint32_t)tl.ext[2]);
-    for (int e0 = 0; e0 < n_ld; e0 += 256 * 8) {
-      uint32_t pos[8];
-      int dst[8];
+    uint32_t pos[NLD];
+    int dst[NLD];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + tid;
-        dst[u] = -1;
-        pos[u] = 0xFFFFFFFFu;
-        if (e < n_ld) {
-          const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
-          const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
-          const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y, i2 = tl.lo[2] + x;
-          const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]),
-                     n2 = is_new32(i2, tl.nf[2]);
-          dst[u] = (z * E1 + y) * E2 + x;
-          if (n0 || n1 || n2) pos[u] = stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2);
-        }
+    for (int u = 0; u < NLD; ++u) {
+      const int e = u * 256 + tid;
+      dst[u] = -1;
+      pos[u] = 0xFFFFFFFFu;
+      if (e < n_ld) {
+        const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
+        const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
+        const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y, i2 = tl.lo[2] + x;
+        const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]),
+                   n2 = is_new32(i2, tl.nf[2]);
+        dst[u] = (z * E1 + y) * E2 + x;
+        if (n0 || n1 || n2) pos[u] = stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2);
       }
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = pos[u] != 0xFFFFFFFFu ? coeff_at<RAW>(src, pos[u], q) : 0.0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (dst[u] >= 0) tile[dst[u]] = v[u];
     }
+    double v[NLD];
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) v[u] = pos[u] != 0xFFFFFFFFu ? coeff_at<RAW>(src, pos[u], q) : 0.0;
+#pragma unroll
+    for (int u = 0; u < NLD; ++u)
+      if (dst[u] >= 0) tile[dst[u]] = v[u];
   }
   __syncthreads();
   restrict_tile(tile, A, tile, tl, tb, fout);
@@ -496,7 +503,8 @@ __global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const C
 
 // G_l = P Gc + c_l on the tile's owned fine nodes; the coarse values the tile
 // needs (its coarse outputs plus one more per axis) are staged in LDS.
-template <typename Tout, int TZ, int TY, int TX, bool RAW>
+// SRC: 0 dequantised symbols, 1 FP64 coefficients, 2 none (plain P Gc).
+template <typename Tout, int TZ, int TY, int TX, int SRC>
 __global__ __launch_bounds__(256) void k_rec_interp(const double* __restrict__ Gc,
                                                      const LevelGeom g, const CoeffSrc src,
                                                      const double q, Tout* __restrict__ out,
@@ -555,9 +563,57 @@ __global__ __launch_bounds__(256) void k_rec_interp(const double* __restrict__ G
       const double v10 = wx0 * g10[j2] + wx1 * g10[jx1];
       const double v11 = wx0 * g11[j2] + wx1 * g11[jx1];
       double v = wz0 * (wy0 * v00 + wy1 * v01) + wz1 * (wy0 * v10 + wy1 * v11);
-      if (n0 || n1 || n2) v += coeff_at<RAW>(src, stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2), q);
+      if (SRC != 2 && (n0 || n1 || n2))
+        v += coeff_at<SRC == 1>(src, stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2), q);
       orow[c] = (Tout)v;
     }
+  }
+}
+
+// --------------------------------------------------------- adjoint pieces
+// cbar at the new nodes of level l: g - (M_l Pv), the fine mass matrix applied
+// as a 3x3x3 stencil to the prolongated coarse solution Pv.
+__global__ __launch_bounds__(256) void k_adj_mass(const double* __restrict__ Pv,
+                                                   const double* __restrict__ gl,
+                                                   const LevelGeom g, double* __restrict__ cbar) {
+  const uint32_t nf0 = (uint32_t)g.nf[0], nf1 = (uint32_t)g.nf[1], nf2 = (uint32_t)g.nf[2];
+  const uint32_t i2 = blockIdx.x * 256 + threadIdx.x;
+  if (i2 >= nf2) return;
+  Tile tl;
+  for (int k = 0; k < 3; ++k) {
+    tl.nf[k] = (uint32_t)g.nf[k];
+    tl.nc[k] = (uint32_t)g.nc[k];
+  }
+  uint32_t soff[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) soff[m] = (uint32_t)(m == 0 ? 0 : g.sub_off[m]);
+  const bool n2 = is_new32(i2, nf2);
+  const uint32_t rows = nf0 * nf1;
+  for (uint32_t row = blockIdx.y; row < rows; row += gridDim.y) {
+    const uint32_t i0 = row / nf1, i1 = row - i0 * nf1;
+    const bool n0 = is_new32(i0, nf0), n1 = is_new32(i1, nf1);
+    if (!(n0 || n1 || n2)) continue;
+    double acc = 0.0;
+    for (int a = -1; a <= 1; ++a) {
+      const int64_t j0 = (int64_t)i0 + a;
+      if (j0 < 0 || j0 >= nf0) continue;
+      const double w0 = g.ax[0].Mt[3 * i0 + a + 1];
+      for (int b = -1; b <= 1; ++b) {
+        const int64_t j1 = (int64_t)i1 + b;
+        if (j1 < 0 || j1 >= nf1) continue;
+        const double w1 = g.ax[1].Mt[3 * i1 + b + 1];
+        const double* prow = Pv + ((size_t)j0 * nf1 + j1) * nf2;
+        double s2 = 0.0;
+        for (int c = -1; c <= 1; ++c) {
+          const int64_t j2 = (int64_t)i2 + c;
+          if (j2 < 0 || j2 >= nf2) continue;
+          s2 += g.ax[2].Mt[3 * i2 + c + 1] * prow[j2];
+        }
+        acc += w0 * w1 * s2;
+      }
+    }
+    const uint32_t pos = stream_pos(g, tl, soff, i0, i1, i2, n0, n1, n2);
+    cbar[pos] = gl[((size_t)i0 * nf1 + i1) * nf2 + i2] - acc;
   }
 }
 
@@ -754,7 +810,7 @@ int active_axes(const LevelGeom& g) {
   return (g.bit[0] >= 0) + (g.bit[1] >= 0) + (g.bit[2] >= 0);
 }
 
-template <typename Tin, bool QUANT>
+template <typename Tin, int MODE>
 void dec_dispatch(const void* G, const LevelGeom& g, double* fout, uint16_t* sym, double* raw,
                   double r, const OutlierBuf& ob, unsigned* status, hipStream_t s) {
   const Tin* Gp = static_cast<const Tin*>(G);
@@ -762,16 +818,16 @@ void dec_dispatch(const void* G, const LevelGeom& g, double* fout, uint16_t* sym
   if (D == 3) {
     constexpr int TX = sizeof(Tin) == 4 ? 16 : 8;
     const TileGrid t = tile_grid(g, 4, 8, TX);
-    hipLaunchKernelGGL((k_dec_level<Tin, 4, 8, TX, QUANT>), dim3(t.grid), dim3(256), 0, s, Gp, g,
+    hipLaunchKernelGGL((k_dec_level<Tin, 4, 8, TX, MODE>), dim3(t.grid), dim3(256), 0, s, Gp, g,
                        fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
   } else if (D == 2) {
     constexpr int TY = sizeof(Tin) == 4 ? 16 : 8;
     const TileGrid t = tile_grid(g, 1, TY, 32);
-    hipLaunchKernelGGL((k_dec_level<Tin, 1, TY, 32, QUANT>), dim3(t.grid), dim3(256), 0, s, Gp, g,
+    hipLaunchKernelGGL((k_dec_level<Tin, 1, TY, 32, MODE>), dim3(t.grid), dim3(256), 0, s, Gp, g,
                        fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
   } else {
     const TileGrid t = tile_grid(g, 1, 1, 256);
-    hipLaunchKernelGGL((k_dec_level<Tin, 1, 1, 256, QUANT>), dim3(t.grid), dim3(256), 0, s, Gp,
+    hipLaunchKernelGGL((k_dec_level<Tin, 1, 1, 256, MODE>), dim3(t.grid), dim3(256), 0, s, Gp,
                        g, fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
   }
 }
@@ -795,21 +851,21 @@ void rec_restrict_dispatch(const LevelGeom& g, const CoeffSrc& src, double q, do
   }
 }
 
-template <typename Tout, bool RAW>
+template <typename Tout, int SRC>
 void rec_interp_dispatch(const double* Gc, const LevelGeom& g, const CoeffSrc& src, double q,
                          Tout* out, hipStream_t s) {
   const int D = active_axes(g);
   if (D == 3) {
     const TileGrid t = tile_grid(g, 4, 8, 16);
-    hipLaunchKernelGGL((k_rec_interp<Tout, 4, 8, 16, RAW>), dim3(t.grid), dim3(256), 0, s, Gc, g,
+    hipLaunchKernelGGL((k_rec_interp<Tout, 4, 8, 16, SRC>), dim3(t.grid), dim3(256), 0, s, Gc, g,
                        src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
   } else if (D == 2) {
     const TileGrid t = tile_grid(g, 1, 16, 32);
-    hipLaunchKernelGGL((k_rec_interp<Tout, 1, 16, 32, RAW>), dim3(t.grid), dim3(256), 0, s, Gc, g,
+    hipLaunchKernelGGL((k_rec_interp<Tout, 1, 16, 32, SRC>), dim3(t.grid), dim3(256), 0, s, Gc, g,
                        src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
   } else {
     const TileGrid t = tile_grid(g, 1, 1, 256);
-    hipLaunchKernelGGL((k_rec_interp<Tout, 1, 1, 256, RAW>), dim3(t.grid), dim3(256), 0, s, Gc,
+    hipLaunchKernelGGL((k_rec_interp<Tout, 1, 1, 256, SRC>), dim3(t.grid), dim3(256), 0, s, Gc,
                        g, src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
   }
 }
@@ -837,11 +893,11 @@ void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* 
                       uint16_t* sym, double* raw, double r, const OutlierBuf& ob,
                       unsigned* status, hipStream_t s) {
   if (sym) {
-    if (g_is_f32) dec_dispatch<float, true>(G, g, fout, sym, raw, r, ob, status, s);
-    else dec_dispatch<double, true>(G, g, fout, sym, raw, r, ob, status, s);
+    if (g_is_f32) dec_dispatch<float, 0>(G, g, fout, sym, raw, r, ob, status, s);
+    else dec_dispatch<double, 0>(G, g, fout, sym, raw, r, ob, status, s);
   } else {
-    if (g_is_f32) dec_dispatch<float, false>(G, g, fout, sym, raw, r, ob, status, s);
-    else dec_dispatch<double, false>(G, g, fout, sym, raw, r, ob, status, s);
+    if (g_is_f32) dec_dispatch<float, 1>(G, g, fout, sym, raw, r, ob, status, s);
+    else dec_dispatch<double, 1>(G, g, fout, sym, raw, r, ob, status, s);
   }
 }
 
@@ -888,12 +944,30 @@ void launch_rec_restrict(const LevelGeom& g, const CoeffSrc& src, double q, doub
 void launch_rec_interp(const double* Gc, const LevelGeom& g, const CoeffSrc& src, double q,
                        void* out, bool out_f32, hipStream_t s) {
   if (out_f32) {
-    if (src.raw) rec_interp_dispatch<float, true>(Gc, g, src, q, static_cast<float*>(out), s);
-    else rec_interp_dispatch<float, false>(Gc, g, src, q, static_cast<float*>(out), s);
+    if (src.raw) rec_interp_dispatch<float, 1>(Gc, g, src, q, static_cast<float*>(out), s);
+    else rec_interp_dispatch<float, 0>(Gc, g, src, q, static_cast<float*>(out), s);
   } else {
-    if (src.raw) rec_interp_dispatch<double, true>(Gc, g, src, q, static_cast<double*>(out), s);
-    else rec_interp_dispatch<double, false>(Gc, g, src, q, static_cast<double*>(out), s);
+    if (src.raw) rec_interp_dispatch<double, 1>(Gc, g, src, q, static_cast<double*>(out), s);
+    else rec_interp_dispatch<double, 0>(Gc, g, src, q, static_cast<double*>(out), s);
   }
+}
+
+void launch_adj_restrict(const double* gl, const LevelGeom& g, double* Gc, double* Gc_copy,
+                         hipStream_t s) {
+  dec_dispatch<double, 2>(gl, g, Gc, nullptr, Gc_copy, 0.0, OutlierBuf{nullptr, nullptr, nullptr, 0},
+                          nullptr, s);
+}
+
+void launch_prolong(const double* v, const LevelGeom& g, double* out, hipStream_t s) {
+  const CoeffSrc none{nullptr, nullptr, nullptr, nullptr, 0};
+  rec_interp_dispatch<double, 2>(v, g, none, 0.0, out, s);
+}
+
+void launch_adj_mass(const double* Pv, const double* gl, const LevelGeom& g, double* cbar,
+                     hipStream_t s) {
+  const int64_t rows = g.nf[0] * g.nf[1];
+  const dim3 grid((unsigned)((g.nf[2] + 255) / 256), (unsigned)(rows < 65535 ? rows : 65535));
+  hipLaunchKernelGGL(k_adj_mass, grid, dim3(256), 0, s, Pv, gl, g, cbar);
 }
 
 void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, bool out_f32,
