@@ -9,7 +9,10 @@ before timing starts.  ``value`` is the round-trip throughput
 
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (per-launch algorithmic bytes over its HIP-event-timed duration) and a
-CPU baseline (the FP64 oracle on a bounded sub-cube, one core).
+CPU baseline (the FP64 oracle on a bounded sub-cube, one core).  Two more
+objects ride on the same line: "batched" (256 uneven arrays in one graph
+launch against 256 plain calls) and "differentiation" (gradient of a
+sub-box quantity of interest through the adjoint recomposition).
 """
 from __future__ import annotations
 
@@ -42,7 +45,9 @@ def stage_bytes(N: int, Nc: int, in_size: int, stream_bytes: int):
     return {
         "range": in_size * N,
         "dec_level[finest]": in_size * N + 2 * new + 8 * Nc,
-        "thomas[finest]": 2 * 8 * Nc,
+        "thomas_ax0[finest]": 2 * 8 * Nc,
+        "thomas_ax1[finest]": 2 * 8 * Nc,
+        "thomas_ax2[finest]": 2 * 8 * Nc,
         "histogram": 2 * N,
         "chunk_words": 2 * N,
         "encode": 2 * N + stream_bytes,
@@ -69,6 +74,126 @@ def cpu_baseline(u: np.ndarray, rel: float, edge: int):
                       % (edge, t1 - t0, t2 - t1)}
 
 
+def batched_leg(torch, mgc, synthetic, reps: int):
+    """The batched form against plain calls on 256 uneven arrays.
+
+    Axes from {33, 65, 129, 257}, relative L-inf bounds from {1e-2, 1e-3,
+    1e-4}, bump and |k|^-3 fields (seed 5).  Plain: one mgc.compress per array
+    (each call blocks until its stream size is known), buffers preallocated.
+    Batched: one graph launch for all arrays; the first call (autotuning and
+    graph capture) is untimed.  Throughput = total input bytes / time.
+    """
+    from concurrent.futures import ThreadPoolExecutor
+    specs = synthetic.batch_specs(256, seed=5)
+    log("batched leg: generating 256 arrays")
+    with ThreadPoolExecutor(8) as ex:
+        fields = list(ex.map(synthetic.field_from_spec, specs))
+    xs = [torch.from_numpy(u).cuda() for u in fields]
+    del fields
+    bounds = [sp["bound"] for sp in specs]
+    total = sum(x.numel() * x.element_size() for x in xs)
+    # plain calls with reused buffers
+    need = [mgc.compress_query(tuple(x.shape), x.dtype) for x in xs]
+    ws = torch.empty(max(w for w, _ in need), dtype=torch.uint8, device="cuda")
+    out = torch.empty(max(o for _, o in need), dtype=torch.uint8, device="cuda")
+    plain_bytes = 0
+    for x, b in zip(xs, bounds):
+        plain_bytes += mgc.compress(x, b, workspace=ws, out=out).numel()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for x, b in zip(xs, bounds):
+            mgc.compress(x, b, workspace=ws, out=out)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / reps
+    # batched
+    bt = mgc.Batch([x.shape for x in xs], [x.dtype for x in xs])
+    t0 = time.perf_counter()
+    bt.run(xs, bounds)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    bt.run(xs, bounds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bt.run(xs, bounds)
+    torch.cuda.synchronize()
+    batched_ms = (time.perf_counter() - t0) * 1e3 / reps
+    streams = bt.streams()
+    batched_bytes = sum(int(st.numel()) for st in streams)
+    tuning = {k: mgc.tuning_info(k)[1] for k in mgc.TUNE_KINDS}
+    res = {
+        "arrays": len(xs), "input_bytes": total, "reps": reps,
+        "plain_ms": round(plain_ms, 3), "plain_GBps": round(total / (plain_ms * 1e-3) / 1e9, 2),
+        "batched_ms": round(batched_ms, 3),
+        "batched_GBps": round(total / (batched_ms * 1e-3) / 1e9, 2),
+        "batched_frac_of_hbm_peak": round(total / (batched_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 5),
+        "speedup_vs_plain": round(plain_ms / batched_ms, 3),
+        "first_call_ms": round(first_ms, 1),
+        "compression_ratio": round(total / batched_bytes, 3),
+        "same_bytes_as_plain": batched_bytes == plain_bytes,
+        "tuning": tuning,
+    }
+    log("batched leg: plain %.2f ms (%.1f GB/s), batched %.2f ms (%.1f GB/s), x%.2f"
+        % (plain_ms, res["plain_GBps"], batched_ms, res["batched_GBps"], res["speedup_vs_plain"]))
+    return res
+
+
+def differentiation_leg(torch, mgc, synthetic, reps: int = 3):
+    """Gradient of J(c) = mean over a random 64^3 sub-box of u^2, u = R c.
+
+    257^3 FP32 |k|^-3 field (seed 6), decomposed on the GPU; the gradient over
+    all coefficients comes from the hand-written adjoint (backward of
+    mgc.Recompose).  Reported: forward + backward time, the adjoint alone, and
+    peak device memory of forward + backward with and without the per-level
+    checkpoints (coarse grids kept by the forward pass).
+    """
+    shape = (257, 257, 257)
+    u = synthetic.grf(shape, 6)
+    x = torch.from_numpy(u).cuda()
+    c = mgc.decompose(x)
+    o = np.random.default_rng(6).integers(0, 194, size=3)
+    box = tuple(slice(int(a), int(a) + 64) for a in o)
+
+    def run(keep):
+        cc = c.detach().clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        uu = mgc.Recompose.apply(cc, shape, keep)
+        J = torch.mean(uu[box] ** 2)
+        J.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dt, torch.cuda.max_memory_allocated() - base
+
+    res = {"workload": "grf257_f32_qoi_subbox64", "coefficients": int(c.numel())}
+    for keep in (False, True):
+        run(keep)
+        ts, peaks = [], []
+        for _ in range(reps):
+            dt, pk = run(keep)
+            ts.append(dt)
+            peaks.append(pk)
+        tag = "with_checkpoints" if keep else "without_checkpoints"
+        res[tag] = {"fwd_bwd_ms": round(1e3 * float(np.median(ts)), 3),
+                    "peak_bytes": int(max(peaks))}
+    du = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    du[box] = 1.0
+    mgc.recompose_adjoint(du)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        mgc.recompose_adjoint(du)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    res["adjoint_ms"] = round(e0.elapsed_time(e1) / reps, 3)
+    log("differentiation leg: %s" % json.dumps(res))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +203,12 @@ def main():
     ap.add_argument("--n", type=int, default=513)
     ap.add_argument("--cpu-edge", type=int, default=257)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="also copy the input once on the device (a kernel of known "
+                         "traffic, the scale for hardware byte counters)")
+    ap.add_argument("--batched-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -131,6 +262,13 @@ def main():
     log("timed %d steps: %.3f ms/step (compress %.3f ms, decompress %.3f ms)"
         % (args.steps, ms_step, c_ms, d_ms))
 
+    if args.copy_reference:
+        ref = torch.empty_like(x)
+        ref.copy_(x)
+        torch.cuda.synchronize()
+        log("copy reference: %d bytes read, %d written" % (x.numel() * 4, x.numel() * 4))
+        del ref
+
     stream_bytes = int(blob.numel())
     yu = y.cpu().numpy().astype(np.float64)
     tau = args.rel * (float(u.max()) - float(u.min()))
@@ -155,6 +293,15 @@ def main():
                 "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                 "traffic": None, "bytes_per_launch": int(sb[dom["stage"]])}
 
+    batched = None
+    if not args.no_batched:
+        del ws, out, ws_d
+        batched = batched_leg(torch, mgc, synthetic, args.batched_reps)
+
+    diff = None
+    if not args.no_diff:
+        diff = differentiation_leg(torch, mgc, synthetic)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on a %d^3 sub-cube" % args.cpu_edge)
@@ -175,7 +322,7 @@ def main():
         "compress_ms": round(c_ms, 4), "decompress_ms": round(d_ms, 4),
         "compression_ratio": round(in_bytes / stream_bytes, 3),
         "max_err_over_tau": round(err / tau, 4),
-        "roofline": roofline, "cpu_baseline": cpu, "stages": stages,
+        "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "differentiation": diff, "stages": stages,
     }
     print(json.dumps(res), flush=True)
 

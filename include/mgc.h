@@ -179,6 +179,59 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes,
                               void* stream);
 
 /* ------------------------------------------------------------------------
+ * Batched form: n arrays (uneven shapes, dtypes and bounds; one norm and
+ * mode) compressed together.  Each stage of Algorithm 1 and Algorithm 2 runs
+ * as one launch over the blocks of every array, with the per-array error
+ * budget derived on the device, so the call makes no host round trip; the
+ * launch sequence is captured into a HIP graph on first use and replayed by
+ * one graph launch afterwards.  Array j's stream is bit-identical to what
+ * mgc_compress writes for it with the same outlier capacity.
+ *
+ * Shapes are passed as n rows of 3 (row j: ndims[j] entries, the rest 0).
+ * mgc_batch_query: total workspace bytes, total output bytes, and the byte
+ *   offset of each array's output slot (h_out_offsets, n entries, optional).
+ * mgc_compress_batched (asynchronous on `stream`): d_in[j] holds array j
+ *   (device).  Stream j is written at d_out + offset j; d_sizes[j] (device,
+ *   u64) receives its length and d_status[j] (device, i32) an mgc_status:
+ *   MGC_EINVAL (NaN/Inf), MGC_ERANGE, or MGC_ENOSPC with d_sizes[j] = the
+ *   escaped values needed (then compress that array alone with that
+ *   capacity).  Constant and empty arrays get their trivial streams.  Host
+ *   errors (bad arguments, small buffers) are returned directly.
+ *   flags: MGC_BATCH_EAGER launches the stages directly instead of the
+ *   graph; MGC_BATCH_NO_TUNE skips the autotuner (defaults are used for
+ *   kinds not forced).  The first call for a batch signature (shapes,
+ *   dtypes, outlier_cap) builds per-array plans, block maps and, unless
+ *   disabled, runs the autotuner: every candidate of each tuning kind is
+ *   timed on the call's own data and the fastest kept.  Calls on one context
+ *   must not overlap; the buffers of a call must stay valid until it ends.
+ * mgc_set_tuning forces candidate `candidate` of tuning kind `kind` for later
+ *   batched calls of the context (-1 = autotune again).  Candidates:
+ *   MGC_TUNE_DEC_F32 / MGC_TUNE_DEC_F64 - tile shape (coarse outputs, z y x)
+ *   of the three-axis decomposition kernel on FP32 / FP64 input: f32
+ *   {4x8x16, 8x8x8, 4x4x16, 2x8x32}, f64 {4x8x8, 4x4x16, 2x8x16, 8x8x8};
+ *   MGC_TUNE_THOMAS_STRIDED - values in flight per line {8, 4, 16};
+ *   MGC_TUNE_THOMAS_ROWS - LDS segment of the contiguous sweep {32, 16, 64}.
+ *   Every candidate gives bit-identical output.
+ * mgc_tuning_info: the candidate count of a kind and the choice used by the
+ *   context's most recent batched call (-1 before any).
+ * ---------------------------------------------------------------------- */
+#define MGC_BATCH_EAGER 1
+#define MGC_BATCH_NO_TUNE 2
+enum { MGC_TUNE_DEC_F32 = 0, MGC_TUNE_DEC_F64 = 1, MGC_TUNE_THOMAS_STRIDED = 2,
+       MGC_TUNE_THOMAS_ROWS = 3 };
+mgc_status mgc_batch_query(int n, const int* ndims, const uint64_t* shapes,
+                           const mgc_dtype* dtypes, uint64_t outlier_cap, size_t* ws_bytes,
+                           size_t* out_bytes, uint64_t* h_out_offsets);
+mgc_status mgc_compress_batched(mgc_ctx ctx, int n, const void* const* d_in, const int* ndims,
+                                const uint64_t* shapes, const mgc_dtype* dtypes,
+                                const double* bounds, mgc_norm norm, mgc_mode mode,
+                                uint64_t outlier_cap, void* d_out, size_t out_cap, void* d_ws,
+                                size_t ws_bytes, uint64_t* d_sizes, int32_t* d_status,
+                                int flags, void* stream);
+mgc_status mgc_set_tuning(mgc_ctx ctx, int kind, int candidate);
+mgc_status mgc_tuning_info(mgc_ctx ctx, int kind, int* n_candidates, int* last_choice);
+
+/* ------------------------------------------------------------------------
  * Stage timing.  When enabled, every entry point records HIP events around
  * each kernel launch on its stream; mgc_profile_read returns, per stage
  * name, the number of launches and their total GPU milliseconds accumulated

@@ -11,6 +11,7 @@ Entry points (same names as the C functions, without the ``mgc_`` prefix):
 ``compress(x, error_bound, norm="linf", mode="rel")``  -> uint8 device tensor
 ``decompress(stream)``                                   -> device tensor
 ``decompose(x)`` / ``recompose(coeffs, shape, dtype)``   (FP64 coefficients)
+``compress_batched(tensors, bounds)`` / ``Batch`` (one graph launch for many arrays)
 ``huffman_encode(symbols, C=1024)`` / ``huffman_decode(stream, n)``
 ``header_info(stream)``, ``profile_enable / profile_reset / profile_read``
 """
@@ -23,7 +24,8 @@ import threading
 __all__ = ["MgcError", "library_path", "compress", "decompress", "decompose", "recompose",
            "recompose_adjoint", "recompose_levels", "Recompose", "huffman_encode",
            "huffman_decode", "header_info", "profile_enable", "profile_reset", "profile_read",
-           "compress_query", "transform_query"]
+           "compress_query", "transform_query", "batch_query", "Batch", "compress_batched",
+           "set_tuning", "tuning_info"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmgc.so")
@@ -85,6 +87,18 @@ def _load():
                                    vp, ctypes.c_size_t, vp, c_u64p],
             "mgc_huffman_decode": [vp, vp, ctypes.c_size_t, vp, ctypes.c_uint64, vp,
                                    ctypes.c_size_t, vp],
+            "mgc_batch_query": [ctypes.c_int, ctypes.POINTER(ctypes.c_int), c_u64p,
+                                ctypes.POINTER(ctypes.c_int), ctypes.c_uint64, c_szp, c_szp,
+                                c_u64p],
+            "mgc_compress_batched": [vp, ctypes.c_int, ctypes.POINTER(vp),
+                                     ctypes.POINTER(ctypes.c_int), c_u64p,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_uint64, vp,
+                                     ctypes.c_size_t, vp, ctypes.c_size_t, vp, vp, ctypes.c_int,
+                                     vp],
+            "mgc_set_tuning": [vp, ctypes.c_int, ctypes.c_int],
+            "mgc_tuning_info": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)],
             "mgc_profile_enable": [vp, ctypes.c_int],
             "mgc_profile_reset": [vp],
             "mgc_profile_read": [vp, ctypes.c_char_p, ctypes.c_size_t, c_u64p,
@@ -192,6 +206,126 @@ def compress(x, error_bound: float, norm: str = "linf", mode: str = "rel",
         _check(st)
         return ob[: size.value]
     _check(st)
+
+
+BATCH_EAGER = 1
+BATCH_NO_TUNE = 2
+TUNE_KINDS = {"dec_f32": 0, "dec_f64": 1, "thomas_strided": 2, "thomas_rows": 3}
+
+
+def _batch_desc(shapes, dtypes):
+    n = len(shapes)
+    ndims = (ctypes.c_int * n)(*[len(s) for s in shapes])
+    flat = []
+    for s in shapes:
+        if not 1 <= len(s) <= 3:
+            raise ValueError("arrays of 1 to 3 axes")
+        flat += [int(v) for v in s] + [0] * (3 - len(s))
+    shp = (ctypes.c_uint64 * (3 * n))(*flat)
+    dts = (ctypes.c_int * n)(*[_dtype_code(d) for d in dtypes])
+    return n, ndims, shp, dts
+
+
+def batch_query(shapes, dtypes, outlier_cap: int = 0):
+    """(workspace bytes, output bytes, per-array output offsets) of a batch."""
+    n, ndims, shp, dts = _batch_desc(shapes, dtypes)
+    ws = ctypes.c_size_t()
+    ob = ctypes.c_size_t()
+    offs = (ctypes.c_uint64 * n)()
+    _check(_load().mgc_batch_query(n, ndims, shp, dts, outlier_cap, ctypes.byref(ws),
+                                   ctypes.byref(ob), offs))
+    return ws.value, ob.value, [int(v) for v in offs]
+
+
+class Batch:
+    """Buffers of a batched compression of fixed shapes and dtypes.
+
+    ``run`` enqueues the compression of one list of tensors (asynchronous);
+    ``streams`` waits for it and returns one uint8 GPU tensor per array (views
+    into the shared output buffer; an array whose escaped values overflowed
+    the capacity is compressed again alone with the capacity it needs).
+    """
+
+    def __init__(self, shapes, dtypes, outlier_cap: int = 0, device=None):
+        torch = _torch()
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.dtypes = list(dtypes)
+        self.outlier_cap = int(outlier_cap)
+        self.device = torch.device("cuda", device if device is not None else torch.cuda.current_device())
+        self.ws_bytes, self.out_bytes, self.offsets = batch_query(self.shapes, self.dtypes,
+                                                                  self.outlier_cap)
+        n = len(self.shapes)
+        self.workspace = _empty(self.ws_bytes, self.device)
+        self.out = _empty(self.out_bytes, self.device)
+        self.sizes = torch.zeros(n, dtype=torch.int64, device=self.device)
+        self.status = torch.zeros(n, dtype=torch.int32, device=self.device)
+        self._desc = _batch_desc(self.shapes, self.dtypes)
+        self._last = None
+
+    def run(self, tensors, bounds, norm: str = "linf", mode: str = "rel", flags: int = 0):
+        n, ndims, shp, dts = self._desc
+        if len(tensors) != n or len(bounds) != n:
+            raise ValueError("one tensor and one bound per array")
+        for j, t in enumerate(tensors):
+            _require_gpu(t, "input %d" % j)
+            if tuple(t.shape) != self.shapes[j] or t.dtype != self.dtypes[j] or not t.is_contiguous():
+                raise ValueError("input %d does not match the batch description" % j)
+        ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in tensors])
+        bnd = (ctypes.c_double * n)(*[float(b) for b in bounds])
+        dev = self.device.index
+        _check(_load().mgc_compress_batched(
+            _ctx(dev), n, ptrs, ndims, shp, dts, bnd, _NORM[norm], _MODE[mode], self.outlier_cap,
+            ctypes.c_void_p(self.out.data_ptr()), self.out.numel(),
+            ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+            ctypes.c_void_p(self.sizes.data_ptr()), ctypes.c_void_p(self.status.data_ptr()),
+            int(flags), _stream_ptr(dev)))
+        self._last = (list(tensors), list(bounds), norm, mode)
+
+    def streams(self):
+        if self._last is None:
+            raise RuntimeError("run() has not been called")
+        sizes = self.sizes.cpu().tolist()
+        status = self.status.cpu().tolist()
+        tensors, bounds, norm, mode = self._last
+        res = []
+        for j, (st, sz) in enumerate(zip(status, sizes)):
+            if st == 3:   # escaped values overflowed: this array alone, with the room it needs
+                res.append(compress(tensors[j], bounds[j], norm, mode, outlier_cap=int(sz)))
+            elif st != 0:
+                raise MgcError(st, "array %d of the batch" % j)
+            else:
+                res.append(self.out[self.offsets[j]: self.offsets[j] + sz])
+        return res
+
+
+def compress_batched(tensors, bounds, norm: str = "linf", mode: str = "rel",
+                     outlier_cap: int = 0, flags: int = 0):
+    """Compress a list of GPU tensors (uneven shapes, per-array bounds) in one
+    batched call; returns one uint8 GPU tensor per array."""
+    tensors = [t.contiguous() for t in tensors]
+    b = Batch([t.shape for t in tensors], [t.dtype for t in tensors], outlier_cap,
+              device=tensors[0].device.index)
+    b.run(tensors, bounds, norm, mode, flags)
+    return b.streams()
+
+
+def set_tuning(kind: str, candidate: int, device=None):
+    """Force candidate ``candidate`` of a tuning kind for later batched calls
+    (-1: autotune)."""
+    torch = _torch()
+    dev = device if device is not None else torch.cuda.current_device()
+    _check(_load().mgc_set_tuning(_ctx(dev), TUNE_KINDS[kind], int(candidate)))
+
+
+def tuning_info(kind: str, device=None):
+    """(number of candidates, candidate used by the latest batched call)."""
+    torch = _torch()
+    dev = device if device is not None else torch.cuda.current_device()
+    n = ctypes.c_int()
+    last = ctypes.c_int()
+    _check(_load().mgc_tuning_info(_ctx(dev), TUNE_KINDS[kind], ctypes.byref(n),
+                                   ctypes.byref(last)))
+    return n.value, last.value
 
 
 def header_info(stream):

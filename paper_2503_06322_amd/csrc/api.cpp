@@ -13,8 +13,7 @@
 #include <map>
 #include <vector>
 
-#include "kernels.hpp"
-#include "plan.hpp"
+#include "host.hpp"
 
 #pragma clang fp contract(off)
 
@@ -26,60 +25,6 @@ void fail(mgc_status st, const std::string& msg) {
   g_err = msg;
   throw Fail{st};
 }
-
-struct Profiler {
-  bool enabled = false;
-  std::vector<std::string> names;
-  std::map<std::string, int> slot_of;
-  std::vector<double> ms;
-  std::vector<uint64_t> counts;
-  struct Pending {
-    int slot;
-    hipEvent_t a, b;
-  };
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> pool;
-
-  int slot(const char* name) {
-    auto it = slot_of.find(name);
-    if (it != slot_of.end()) return it->second;
-    int s = (int)names.size();
-    names.push_back(name);
-    slot_of[name] = s;
-    ms.push_back(0.0);
-    counts.push_back(0);
-    return s;
-  }
-  hipEvent_t get() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e;
-    MGC_HIP(hipEventCreate(&e));
-    return e;
-  }
-  void flush() {
-    for (auto& p : pending) {
-      MGC_HIP(hipEventSynchronize(p.b));
-      float t = 0.f;
-      MGC_HIP(hipEventElapsedTime(&t, p.a, p.b));
-      ms[p.slot] += t;
-      counts[p.slot] += 1;
-      pool.push_back(p.a);
-      pool.push_back(p.b);
-    }
-    pending.clear();
-  }
-  ~Profiler() {
-    for (auto& p : pending) {
-      (void)hipEventDestroy(p.a);
-      (void)hipEventDestroy(p.b);
-    }
-    for (auto e : pool) (void)hipEventDestroy(e);
-  }
-};
 
 StageScope::StageScope(Profiler* prof, const char* name, hipStream_t stream)
     : p(prof && prof->enabled ? prof : nullptr), slot(-1), s(stream), a(nullptr) {
@@ -93,22 +38,6 @@ StageScope::~StageScope() {
   hipEvent_t b = p->get();
   if (hipEventRecord(b, s) == hipSuccess) p->pending.push_back({slot, a, b});
 }
-
-// bump allocator over a caller workspace (measure-only when base is null)
-struct Carver {
-  uint8_t* base;
-  size_t off = 0;
-  explicit Carver(void* b) : base(static_cast<uint8_t*>(b)) {}
-  template <typename T>
-  T* take(size_t n) {
-    off = (off + 255) & ~size_t(255);
-    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
-    off += n * sizeof(T);
-    return p;
-  }
-};
-
-constexpr uint32_t kChunk = 1024;
 
 uint64_t default_outlier_cap(int64_t N) {
   return std::max<uint64_t>(65536, (uint64_t)N / 16);
@@ -125,22 +54,31 @@ int key_bits(int64_t N) {
   return b;
 }
 
-struct CompressWs {
-  uint16_t* sym;
-  double *gA, *gB, *part, *range;
-  unsigned* status;
-  unsigned long long* n_out;
-  Layout* lay;
-  unsigned* hist;
-  uint32_t* code;
-  uint8_t* clen;
-  void* cbs;
-  uint32_t* cw;
-  uint32_t* opos;
-  int64_t* oval;
-  uint32_t *okA, *ovA, *okB, *ovB;
-  unsigned long long* info;
-};
+Header make_header(const Plan& p, int ndim, const uint64_t* shape, mgc_dtype dtype,
+                   double bound, mgc_norm norm, mgc_mode mode) {
+  Header h{};
+  h.magic = kMagic;
+  h.version = kVersion;
+  h.dtype = (uint8_t)dtype;
+  h.norm = (uint8_t)norm;
+  h.mode = (uint8_t)mode;
+  h.ndim = (uint8_t)ndim;
+  h.D = (uint8_t)p.D;
+  h.L = (uint32_t)p.L;
+  for (int d = 0; d < ndim; ++d) h.shape[d] = shape[d];
+  h.bound = bound;
+  h.S = kDict;
+  h.C = kChunk;
+  h.N = (uint64_t)p.N;
+  h.n_chunks = (p.N + kChunk - 1) / kChunk;
+  if (p.N == 0) {
+    h.flags = FLAG_EMPTY;
+    h.n_chunks = 0;
+    h.D = 0;  // number of axes longer than 1, as given
+    for (int d = 0; d < ndim; ++d) h.D += shape[d] > 1;
+  }
+  return h;
+}
 
 CompressWs carve_compress(Carver& c, const Plan& p, uint64_t cap) {
   CompressWs w;
@@ -150,7 +88,7 @@ CompressWs carve_compress(Carver& c, const Plan& p, uint64_t cap) {
   w.gA = c.take<double>(n_coarse);
   w.gB = c.take<double>(n_coarse);
   w.part = c.take<double>(4 * kRangeBlocks);
-  w.range = c.take<double>(4);
+  w.bud = c.take<double>(kBudDoubles);
   w.status = c.take<unsigned>(4);
   w.n_out = c.take<unsigned long long>(1);
   w.lay = c.take<Layout>(1);
@@ -212,35 +150,13 @@ void parse_header(const uint8_t* b, size_t n, Header* h, std::vector<double>* q)
 
 using namespace mgc;
 
-struct mgc_ctx_s {
-  int device = 0;
-  std::map<std::vector<uint64_t>, Plan> plans;
-  Profiler prof;
-  uint8_t* pinned = nullptr;      // 4 KiB host staging (pinned, mapped)
-  uint8_t* pinned_dev = nullptr;  // the same memory as seen by the device
-};
-
-namespace {
-
-template <typename F>
-mgc_status guard(F&& f) {
-  try {
-    f();
-    return MGC_OK;
-  } catch (const Fail& e) {
-    return e.st;
-  } catch (const std::exception& e) {
-    set_error(e.what());
-    return MGC_EDEVICE;
-  }
-}
-
+namespace mgc {
 void check_ctx(mgc_ctx ctx) {
   if (!ctx) fail(MGC_EINVAL, "null context");
   MGC_HIP(hipSetDevice(ctx->device));
 }
 
-Plan& get_plan(mgc_ctx ctx, int ndim, const uint64_t* shape) {
+const Plan& get_plan(mgc_ctx ctx, int ndim, const uint64_t* shape) {
   if (ndim < 1) fail(MGC_EINVAL, "ndim must be at least 1");
   if (ndim > 3) fail(MGC_EUNSUPPORTED, "ndim above 3 is not supported");
   std::vector<uint64_t> key(shape, shape + ndim);
@@ -251,8 +167,15 @@ Plan& get_plan(mgc_ctx ctx, int ndim, const uint64_t* shape) {
   upload_plan(p);
   return ctx->plans.emplace(key, std::move(p)).first->second;
 }
+}  // namespace mgc
+
+namespace {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// stage names of the finest level's sweeps, per internal axis
+const char* const kThomasFinest[3] = {"thomas_ax0[finest]", "thomas_ax1[finest]",
+                                      "thomas_ax2[finest]"};
 
 // Reads n bytes of device memory into ctx->pinned (n <= 4 KiB): a one-block
 // copy into the mapped staging buffer, then a stream synchronisation.
@@ -289,7 +212,7 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
     }
     for (int axis = 2; axis >= 0; --axis) {
       if (p.bit[axis] < 0) continue;
-      StageScope sc(&ctx->prof, l == p.L ? "thomas[finest]" : "thomas", s);
+      StageScope sc(&ctx->prof, l == p.L ? kThomasFinest[axis] : "thomas", s);
       launch_thomas(axis, Gnext, g.nc, g.ax[axis], nullptr, s);
     }
     Gcur = Gnext;
@@ -337,7 +260,7 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
     }
     for (int axis = 2; axis >= 0; --axis) {
       if (p.bit[axis] < 0) continue;
-      StageScope sc(&ctx->prof, fin ? "thomas[finest]" : "thomas", s);
+      StageScope sc(&ctx->prof, fin ? kThomasFinest[axis] : "thomas", s);
       launch_thomas(axis, F, g.nc, g.ax[axis], axis == last ? Gprev : nullptr, s);
     }
     {
@@ -384,6 +307,8 @@ mgc_status mgc_destroy(mgc_ctx ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->batches) free_batch_plan(kv.second);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto& kv : ctx->plans) free_plan(kv.second);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
@@ -426,59 +351,41 @@ mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t*
     Carver c(d_ws);
     CompressWs w = carve_compress(c, p, cap);
 
-    Header h{};
-    h.magic = kMagic;
-    h.version = kVersion;
-    h.dtype = (uint8_t)dtype;
-    h.norm = (uint8_t)norm;
-    h.mode = (uint8_t)mode;
-    h.ndim = (uint8_t)ndim;
-    h.D = (uint8_t)p.D;
-    h.L = (uint32_t)p.L;
-    for (int d = 0; d < ndim; ++d) h.shape[d] = shape[d];
-    h.bound = error_bound;
-    h.S = kDict;
-    h.C = kChunk;
-    h.N = (uint64_t)p.N;
-    h.n_chunks = (p.N + kChunk - 1) / kChunk;
+    Header h = make_header(p, ndim, shape, dtype, error_bound, norm, mode);
     if (p.N == 0) {
-      h.flags = FLAG_EMPTY;
-      h.n_chunks = 0;
-      h.D = 0;  // number of axes longer than 1, as given
-      for (int d = 0; d < ndim; ++d) h.D += shape[d] > 1;
       *h_out_size = write_trivial_stream(ctx, h, d_out, s);
       return;
-    }
-    {
-      StageScope sc(&ctx->prof, "range", s);
-      launch_range(d_in, dtype, p.N, w.part, w.range, s);
-    }
-    double rng[4];
-    sync_read(ctx, ctx->pinned, w.range, sizeof(rng), s);
-    std::memcpy(rng, ctx->pinned, sizeof(rng));
-    if (rng[3] != 0.0) fail(MGC_EINVAL, "input holds NaN or Inf");
-    if (rng[0] == rng[1]) {
-      h.flags = FLAG_CONSTANT;
-      h.const_value = rng[0];
-      h.n_chunks = 0;
-      *h_out_size = write_trivial_stream(ctx, h, d_out, s);
-      return;
-    }
-    double tau, tau_eff;
-    error_budget(dtype, norm, mode, error_bound, rng[0], rng[1], rng[2], p.N, &tau, &tau_eff);
-    if (!(tau_eff > 0.0)) fail(MGC_ERANGE, "error bound below the resolution of the output type");
-    h.tau = tau;
-    h.tau_eff = tau_eff;
-    const std::vector<double> K = p.bin_factors(norm);
-    std::vector<double> q(p.L + 1), r(p.L + 1);
-    for (int l = 0; l <= p.L; ++l) {
-      q[l] = tau_eff * K[l];
-      r[l] = 1.0 / q[l];
     }
     MGC_HIP(hipMemsetAsync(w.status, 0, 4 * sizeof(unsigned), s));
     MGC_HIP(hipMemsetAsync(w.n_out, 0, sizeof(unsigned long long), s));
     MGC_HIP(hipMemsetAsync(w.lay, 0, sizeof(Layout), s));
     MGC_HIP(hipMemsetAsync(w.hist, 0, kDict * sizeof(unsigned), s));
+    {
+      StageScope sc(&ctx->prof, "range", s);
+      const BudgetIn bi{(int)dtype, (int)norm, (int)mode, p.L, error_bound, p.N,
+                        p.d_K[norm == MGC_LINF ? 0 : 1]};
+      launch_range(d_in, dtype, p.N, w.part, bi, w.bud, w.status, s);
+    }
+    const int nbud = 6 + 2 * (p.L + 1);
+    std::vector<double> bud(nbud);
+    sync_read(ctx, ctx->pinned, w.bud, nbud * sizeof(double), s);
+    std::memcpy(bud.data(), ctx->pinned, nbud * sizeof(double));
+    if (bud[3] != 0.0) fail(MGC_EINVAL, "input holds NaN or Inf");
+    if (bud[0] == bud[1]) {
+      h.flags = FLAG_CONSTANT;
+      h.const_value = bud[0];
+      h.n_chunks = 0;
+      *h_out_size = write_trivial_stream(ctx, h, d_out, s);
+      return;
+    }
+    if (!(bud[5] > 0.0)) fail(MGC_ERANGE, "error bound below the resolution of the output type");
+    h.tau = bud[4];
+    h.tau_eff = bud[5];
+    std::vector<double> q(p.L + 1), r(p.L + 1);
+    for (int l = 0; l <= p.L; ++l) {
+      q[l] = bud[bud_q(l)];
+      r[l] = bud[bud_r(p.L, l)];
+    }
     OutlierBuf ob{w.opos, w.oval, w.n_out, cap};
     run_levels_decompose(ctx, p, d_in, dtype == MGC_F32, w.gA, w.gB, w.sym, nullptr, r, ob,
                          w.status, s);

@@ -27,6 +27,27 @@ enum : uint32_t {
   ST_OVERFLOW = 2u,   // more escaped values than the outlier capacity
   ST_FORMAT = 4u,     // corrupt code or table in a stream being decoded
   ST_INTERNAL = 8u,   // a bounded device loop hit its iteration guard
+  ST_NONFINITE = 16u, // the input holds NaN or Inf
+  ST_CONST = 32u,     // the input is constant (trivial stream)
+  ST_BUDGET = 64u,    // the error budget vanishes below the output precision
+  ST_EMPTY = 128u,    // the array has no values (trivial stream)
+  ST_SKIP = ST_NONFINITE | ST_CONST | ST_BUDGET | ST_EMPTY,
+};
+
+// Error-budget block of a compression (device, doubles): [0..3] min, max, sum
+// of squares, non-finite flag; [4] tau; [5] tau'; [6 .. 6+L] bins q_l;
+// [7+L .. 7+2L] their reciprocals.
+constexpr int kBudDoubles = 6 + 2 * (kMaxLevels + 1);
+__host__ __device__ inline int bud_q(int l) { return 6 + l; }
+__host__ __device__ inline int bud_r(int L, int l) { return 7 + L + l; }
+
+// Inputs of the error budget: the request and the per-level bin factors K_l
+// (q_l = tau' K_l; device table of L + 1 doubles).
+struct BudgetIn {
+  int dtype, norm, mode, L;
+  double bound;
+  int64_t N;
+  const double* K;
 };
 
 // Per-axis tables of one level (device pointers into the plan's table block).
@@ -69,6 +90,12 @@ struct CoeffSrc {
   int64_t n_out;
 };
 
+// Scratch of the single-block codebook construction (65536 entries each).
+struct CodebookScratch {
+  uint32_t *keyA, *valA, *keyB, *valB, *symAsc, *freqAsc, *Iw, *Sw, *leafPar, *parA, *parB,
+      *dstA, *dstB;
+};
+
 // Stream layout computed on the device once counts are known.
 struct Layout {
   unsigned long long n_codes;
@@ -101,6 +128,45 @@ static_assert(sizeof(Header) == kHeaderBytes, "header layout");
 static_assert(sizeof(HuffHeader) == kHuffHeaderBytes, "huffman header layout");
 
 enum : uint8_t { FLAG_CONSTANT = 1, FLAG_EMPTY = 2 };
+
+// ------------------------------------------------------------ batched form
+// One array of a batched compression: a device table entry written by the
+// host (pointers into the caller's buffers and the plan's tables).  Work
+// buffers are those of a plain compression of the same array.
+struct Job {
+  const void* in;
+  uint8_t* out;             // this array's output slot
+  int64_t N;
+  int32_t L, dtype;
+  uint64_t cap;             // outlier capacity
+  uint64_t n_chunks;
+  int32_t key_bits, pad0;
+  const LevelGeom* geo;     // geo[l], l = 0..L
+  BudgetIn bi;
+  double *part, *bud;
+  uint16_t* sym;
+  double *gA, *gB;
+  unsigned* status;
+  unsigned long long* n_out;
+  Layout* lay;
+  unsigned* hist;
+  uint32_t* code;
+  uint8_t* clen;
+  CodebookScratch cbs;
+  uint32_t* cw;
+  uint32_t* opos;
+  int64_t* oval;
+  uint32_t *okA, *ovA, *okB, *ovB;
+  uint64_t* size_out;       // result tables of the call (device)
+  int32_t* status_out;
+  Header hdr;               // template: request and shape fields
+};
+
+// Block of a flattened batched launch: its array, its index among that
+// array's blocks of the launch and their count.
+struct JobBlock {
+  uint32_t job, local, count;
+};
 
 __host__ __device__ inline uint64_t pad8(uint64_t n) { return (n + 7) & ~uint64_t(7); }
 

@@ -90,22 +90,26 @@ __device__ __forceinline__ uint64_t match_digit(unsigned digit, int nbits, bool 
 // the escape symbol go to global atomics.  Symbols are read 8 at a time.
 constexpr int kHistWin = 32768;
 
+// h[kHistWin] counts the escape symbol 0 (frequent when many values escape
+// the dictionary, and then too contended for one global counter).
 __device__ __forceinline__ void hist_add(unsigned s, unsigned* h, unsigned* hist) {
   const unsigned d = s - (kHalf - kHistWin / 2);
   if (d < (unsigned)kHistWin) atomicAdd(&h[d], 1u);
+  else if (s == 0) atomicAdd(&h[kHistWin], 1u);
   else atomicAdd(&hist[s], 1u);
 }
 
-__global__ __launch_bounds__(1024) void k_histogram(const uint16_t* __restrict__ sym, int64_t n,
-                                                     unsigned* __restrict__ hist) {
-  __shared__ unsigned h[kHistWin];
-  for (int i = threadIdx.x; i < kHistWin; i += 1024) h[i] = 0;
+__device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ sym, int64_t n,
+                                               unsigned* __restrict__ hist, uint32_t blk,
+                                               uint32_t nblk) {
+  __shared__ unsigned h[kHistWin + 1];
+  for (int i = threadIdx.x; i <= kHistWin; i += 1024) h[i] = 0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * 1024;
+  const int64_t stride = (int64_t)nblk * 1024;
   const bool vec = (reinterpret_cast<uintptr_t>(sym) & 15) == 0;
   const int64_t nvec = vec ? n / 8 : 0;
   const uint4* sv = reinterpret_cast<const uint4*>(sym);
-  for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < nvec; i += stride) {
+  for (int64_t i = (int64_t)blk * 1024 + threadIdx.x; i < nvec; i += stride) {
     const uint4 w = sv[i];
     const unsigned a[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -114,11 +118,17 @@ __global__ __launch_bounds__(1024) void k_histogram(const uint16_t* __restrict__
       hist_add(a[k] >> 16, h, hist);
     }
   }
-  for (int64_t i = nvec * 8 + (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride)
+  for (int64_t i = nvec * 8 + (int64_t)blk * 1024 + threadIdx.x; i < n; i += stride)
     hist_add(sym[i], h, hist);
   __syncthreads();
   for (int i = threadIdx.x; i < kHistWin; i += 1024)
     if (h[i]) atomicAdd(&hist[kHalf - kHistWin / 2 + i], h[i]);
+  if (threadIdx.x == 0 && h[kHistWin]) atomicAdd(&hist[0], h[kHistWin]);
+}
+
+__global__ __launch_bounds__(1024) void k_histogram(const uint16_t* __restrict__ sym, int64_t n,
+                                                     unsigned* __restrict__ hist) {
+  histogram_body(sym, n, hist, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------- single-block helpers
@@ -299,11 +309,12 @@ __device__ void stable_digit_ranks(unsigned n, DigitFn digit_of, Fn fn, CbSmem& 
   }
 }
 
-__global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ hist,
-                                                    CodebookScratch s, uint32_t* __restrict__ code,
-                                                    uint8_t* __restrict__ clen,
-                                                    uint8_t* __restrict__ cb_out,
-                                                    Layout* __restrict__ lay) {
+__device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
+                                              const CodebookScratch& s,
+                                              uint32_t* __restrict__ code,
+                                              uint8_t* __restrict__ clen,
+                                              uint8_t* __restrict__ cb_out,
+                                              Layout* __restrict__ lay) {
   __shared__ CbSmem sm;
   const int tid = threadIdx.x;
   for (unsigned i = tid; i < kDict; i += 1024) {
@@ -591,17 +602,25 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
   if (tid == 0) lay->n_codes = n;
 }
 
+__global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ hist,
+                                                    CodebookScratch s, uint32_t* __restrict__ code,
+                                                    uint8_t* __restrict__ clen,
+                                                    uint8_t* __restrict__ cb_out,
+                                                    Layout* __restrict__ lay) {
+  codebook_body(hist, s, code, clen, cb_out, lay);
+}
+
 // ---------------------------------------------------------------- encoding
 // Lane l of the chunk's wavefront owns symbols [l*per, (l+1)*per) of the
 // chunk; symbols and their code lengths are fetched in groups of 8 with all
 // loads in flight before use.
-__global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict__ sym, int64_t N,
-                                                      int C, const uint8_t* __restrict__ clen,
-                                                      uint32_t* __restrict__ cw,
-                                                      const Layout* __restrict__ lay) {
+__device__ __forceinline__ void chunk_words_body(const uint16_t* __restrict__ sym, int64_t N,
+                                                 int C, const uint8_t* __restrict__ clen,
+                                                 uint32_t* __restrict__ cw,
+                                                 const Layout* __restrict__ lay, uint32_t blk) {
   if (lay->status) return;
   const int64_t n_chunks = (N + C - 1) / C;
-  const int64_t chunk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t chunk = (int64_t)blk * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (chunk >= n_chunks) return;
   const int per = C / 64;
@@ -619,11 +638,18 @@ __global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict_
   if (lane == 0) cw[chunk] = (bits + 31u) >> 5;
 }
 
-__global__ __launch_bounds__(1024) void k_layout_scan(const uint32_t* __restrict__ cw,
-                                                       int64_t n_chunks, uint8_t* __restrict__ out,
-                                                       uint64_t cb_off, Layout* __restrict__ lay,
-                                                       const unsigned long long* n_out,
-                                                       uint64_t out_cap_n, int huff_only) {
+__global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict__ sym, int64_t N,
+                                                      int C, const uint8_t* __restrict__ clen,
+                                                      uint32_t* __restrict__ cw,
+                                                      const Layout* __restrict__ lay) {
+  chunk_words_body(sym, N, C, clen, cw, lay, blockIdx.x);
+}
+
+__device__ __forceinline__ void layout_scan_body(const uint32_t* __restrict__ cw,
+                                                 int64_t n_chunks, uint8_t* __restrict__ out,
+                                                 uint64_t cb_off, Layout* __restrict__ lay,
+                                                 const unsigned long long* n_out,
+                                                 uint64_t out_cap_n, int huff_only) {
   __shared__ unsigned sm32[16];
   __shared__ unsigned long long carry;
   const int tid = threadIdx.x;
@@ -669,11 +695,19 @@ __global__ __launch_bounds__(1024) void k_layout_scan(const uint32_t* __restrict
   }
 }
 
-__global__ __launch_bounds__(1024) void k_outlier_sort(const OutlierBuf ob, uint32_t* keyA,
-                                                        uint32_t* valA, uint32_t* keyB,
-                                                        uint32_t* valB, int key_bits,
-                                                        uint8_t* __restrict__ out,
-                                                        const Layout* __restrict__ lay) {
+__global__ __launch_bounds__(1024) void k_layout_scan(const uint32_t* __restrict__ cw,
+                                                       int64_t n_chunks, uint8_t* __restrict__ out,
+                                                       uint64_t cb_off, Layout* __restrict__ lay,
+                                                       const unsigned long long* n_out,
+                                                       uint64_t out_cap_n, int huff_only) {
+  layout_scan_body(cw, n_chunks, out, cb_off, lay, n_out, out_cap_n, huff_only);
+}
+
+__device__ __forceinline__ void outlier_sort_body(const OutlierBuf& ob, uint32_t* keyA,
+                                                  uint32_t* valA, uint32_t* keyB,
+                                                  uint32_t* valB, int key_bits,
+                                                  uint8_t* __restrict__ out,
+                                                  const Layout* __restrict__ lay) {
   __shared__ SortSmem sm;
   if (lay->status) return;
   const uint32_t n = (uint32_t)lay->n_outliers;
@@ -694,18 +728,27 @@ __global__ __launch_bounds__(1024) void k_outlier_sort(const OutlierBuf ob, uint
   }
 }
 
+__global__ __launch_bounds__(1024) void k_outlier_sort(const OutlierBuf ob, uint32_t* keyA,
+                                                        uint32_t* valA, uint32_t* keyB,
+                                                        uint32_t* valB, int key_bits,
+                                                        uint8_t* __restrict__ out,
+                                                        const Layout* __restrict__ lay) {
+  outlier_sort_body(ob, keyA, valA, keyB, valB, key_bits, out, lay);
+}
+
 // One wavefront per chunk, four chunks per block; LDS holds each chunk's
 // words while codes are OR-ed into place.
-__global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym, int64_t N, int C,
-                                                 const uint32_t* __restrict__ code,
-                                                 const uint8_t* __restrict__ clen,
-                                                 uint8_t* __restrict__ out,
-                                                 const Layout* __restrict__ lay) {
-  extern __shared__ uint32_t wbuf[];  // 4 * C words
+// wbuf: dynamic LDS of 4 * C words.
+__device__ __forceinline__ void encode_body(const uint16_t* __restrict__ sym, int64_t N, int C,
+                                            const uint32_t* __restrict__ code,
+                                            const uint8_t* __restrict__ clen,
+                                            uint8_t* __restrict__ out,
+                                            const Layout* __restrict__ lay, uint32_t blk,
+                                            uint32_t* wbuf) {
   if (lay->status) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t n_chunks = (N + C - 1) / C;
-  const int64_t chunk = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t chunk = (int64_t)blk * 4 + wave;
   uint32_t* w = wbuf + wave * C;
   for (int i = lane; i < C; i += 64) w[i] = 0;
   __syncthreads();
@@ -763,6 +806,15 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym
     const uint64_t w0 = offs[chunk], nw = offs[chunk + 1] - w0;
     for (uint64_t i = lane; i < nw; i += 64) words[w0 + i] = w[i];
   }
+}
+
+__global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym, int64_t N, int C,
+                                                 const uint32_t* __restrict__ code,
+                                                 const uint8_t* __restrict__ clen,
+                                                 uint8_t* __restrict__ out,
+                                                 const Layout* __restrict__ lay) {
+  extern __shared__ uint32_t wbuf[];  // 4 * C words
+  encode_body(sym, N, C, code, clen, out, lay, blockIdx.x, wbuf);
 }
 
 struct QArgs {
@@ -887,15 +939,70 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
 }
 
 // One thread per chunk, 64 chunks per wavefront, eight wavefronts per block.
-// Coded words are fetched four at a time into a 128-bit register queue that
-// feeds a 64-bit bit buffer.  A 12-bit prefix table resolves short codes
-// directly and gives the shortest possible length for long ones (then a few
-// comparisons against the canonical limits); the (length, symbol) table is
-// held in LDS (dynamic size: the codebook's).  Decoded symbols are staged in
-// LDS, SB per lane, and each wave then stores its chunks' segments
-// contiguously.
+//
+// Coded words flow through a 64-bit bit buffer fed by a queue of up to eight
+// words in registers, behind which the next four words are always in flight.
+// The queue is topped up at fixed symbol counts (every four symbols, when it
+// holds four words or fewer), the same points for every lane, so a wavefront
+// only waits for loads issued a refill period earlier; a lane whose queue
+// runs dry in between (possible only with codes near the 32-bit limit) tops
+// up on the spot.  A 12-bit prefix table resolves short codes directly.  For
+// a longer code the length is the number of canonical limits the left-aligned
+// 32-bit window reaches (the limits grow with the length; those of lengths
+// 13..31 sit in registers), then the symbol comes from the (length,
+// symbol)-ordered table in LDS (dynamic size: the codebook's).  Decoded
+// symbols are staged in LDS, eight per lane, and stored at the next batch's
+// start, four rows of 16 bytes per wave instruction.
 constexpr int kDecSB = 8;
 constexpr int kDecWaves = 8;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Register queue of coded words: q0..q3 hold up to eight 32-bit words,
+// first word in the high half of q0, unused words zero; p0, p1 the four
+// words that follow (in flight); wi the next word to request.
+struct WordQueue {
+  uint64_t q0, q1, q2, q3, p0, p1;
+  int qn;
+  uint64_t wi;
+
+  __device__ __forceinline__ void request(const uint32_t* __restrict__ words, uint64_t w1) {
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = wi + u < w1 ? words[wi + u] : 0u;
+    p0 = ((uint64_t)v[0] << 32) | v[1];
+    p1 = ((uint64_t)v[2] << 32) | v[3];
+    wi += 4;
+  }
+  // append the four pending words at word qn (qn <= 4), then request more
+  __device__ __forceinline__ void top_up(const uint32_t* __restrict__ words, uint64_t w1) {
+    const bool odd = qn & 1;
+    const int half = qn >> 1;
+    const uint64_t x0 = odd ? (p0 >> 32) : p0;
+    const uint64_t x1 = odd ? ((p0 << 32) | (p1 >> 32)) : p1;
+    const uint64_t x2 = odd ? (p1 << 32) : 0ull;
+    q0 |= half == 0 ? x0 : 0ull;
+    q1 |= half == 0 ? x1 : (half == 1 ? x0 : 0ull);
+    q2 |= half == 0 ? x2 : (half == 1 ? x1 : x0);
+    q3 |= half == 1 ? x2 : (half == 2 ? x1 : 0ull);
+    qn += 4;
+    request(words, w1);
+  }
+  __device__ __forceinline__ uint32_t pull(const uint32_t* __restrict__ words, uint64_t w1) {
+    if (qn == 0) top_up(words, w1);
+    const uint32_t w = (uint32_t)(q0 >> 32);
+    q0 = (q0 << 32) | (q1 >> 32);
+    q1 = (q1 << 32) | (q2 >> 32);
+    q2 = (q2 << 32) | (q3 >> 32);
+    q3 <<= 32;
+    --qn;
+    return w;
+  }
+};
 
 __global__ __launch_bounds__(64 * kDecWaves) void k_decode(
     const uint8_t* __restrict__ in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
@@ -904,8 +1011,7 @@ __global__ __launch_bounds__(64 * kDecWaves) void k_decode(
   extern __shared__ uint16_t sorted[];  // n_codes entries
   __shared__ uint32_t lut[1 << kLutBits];
   __shared__ uint32_t first[34], count[34], base[34];
-  __shared__ uint64_t limit[34];
-  __shared__ uint32_t maxlen, valid;
+  __shared__ uint32_t valid;
   __shared__ uint16_t stage[kDecWaves][64][kDecSB + 2];
   const int nthr = 64 * kDecWaves;
   if (threadIdx.x == 0) valid = t->valid;
@@ -916,10 +1022,16 @@ __global__ __launch_bounds__(64 * kDecWaves) void k_decode(
     first[threadIdx.x] = t->first[threadIdx.x];
     count[threadIdx.x] = t->count[threadIdx.x];
     base[threadIdx.x] = t->base[threadIdx.x];
-    limit[threadIdx.x] = t->limit[threadIdx.x];
   }
-  if (threadIdx.x == 0) maxlen = t->maxlen > (uint32_t)kMaxCodeLen ? kMaxCodeLen : t->maxlen;
   for (uint32_t i = threadIdx.x; i < n_codes; i += nthr) sorted[i] = t->sorted[i];
+  // uniform: longest length and the limits of lengths kLutBits+1 .. 31
+  // (below the longest length a limit is under 2^32: the longest length's
+  // own codes lie above it)
+  const uint32_t maxlen = t->maxlen > (uint32_t)kMaxCodeLen ? kMaxCodeLen : t->maxlen;
+  uint32_t lim[kMaxCodeLen];
+#pragma unroll
+  for (int l = kLutBits + 1; l < kMaxCodeLen; ++l)
+    lim[l] = (uint32_t)min<uint64_t>(t->limit[l], 0xFFFFFFFFull);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t wave_chunk0 = (uint64_t)blockIdx.x * nthr + wave * 64;
@@ -938,42 +1050,61 @@ __global__ __launch_bounds__(64 * kDecWaves) void k_decode(
   }
   const int64_t start = (int64_t)chunk * C;
   const int cnt = live ? (int)min<int64_t>(C, N - start) : 0;
-  uint64_t buf = 0, qa = 0, qb = 0;
-  int nb = 0, qn = 0;
-  uint64_t wi = w0;
+  WordQueue wq;
+  wq.q2 = wq.q3 = 0;
+  wq.wi = w0;
+  wq.request(words, w1);
+  wq.q0 = wq.p0;
+  wq.q1 = wq.p1;
+  wq.request(words, w1);
+  wq.q2 = wq.p0;
+  wq.q3 = wq.p1;
+  wq.qn = 8;
+  wq.request(words, w1);
+  uint64_t buf = 0;
+  int nb = 0;
   bool bad = false;
+  uint16_t(*stw)[kDecSB + 2] = stage[wave];
+  // stores of a staged batch: lane l writes row r + l/8, column l%8
+  auto store_batch = [&](int kb) {
+    uint16_t v[64 / (64 / kDecSB)];
+#pragma unroll
+    for (int i = 0; i < kDecSB; ++i) v[i] = stw[i * (64 / kDecSB) + lane / kDecSB][lane % kDecSB];
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < kDecSB; ++i) {
+      const int row = i * (64 / kDecSB) + lane / kDecSB, col = lane % kDecSB;
+      const uint64_t c = wave_chunk0 + row;
+      const int64_t pos = (int64_t)c * C + kb + col;
+      if (c < n_chunks && kb + col < C && pos < N) sym[pos] = v[i];
+    }
+  };
   for (int k0 = 0; k0 < C; k0 += kDecSB) {
-    const int kn = min(kDecSB, C - k0);
-    for (int k = 0; k < kn; ++k) {
+    if (wq.qn <= 4) wq.top_up(words, w1);
+    if (k0 > 0) store_batch(k0 - kDecSB);
+    for (int k = 0; k < kDecSB; ++k) {
+      if (k == kDecSB / 2 && wq.qn <= 4) wq.top_up(words, w1);
       if (k0 + k >= cnt || bad) break;
       while (nb <= 32) {
-        if (qn == 0) {
-          uint32_t v[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) v[u] = wi + u < w1 ? words[wi + u] : 0u;
-          wi += 4;
-          qa = ((uint64_t)v[0] << 32) | v[1];
-          qb = ((uint64_t)v[2] << 32) | v[3];
-          qn = 4;
-        }
-        const uint32_t w = (uint32_t)(qa >> 32);
-        qa = (qa << 32) | (qb >> 32);
-        qb <<= 32;
-        --qn;
+        const uint32_t w = wq.pull(words, w1);
         buf |= (uint64_t)w << (32 - nb);
         nb += 32;
       }
       const uint32_t peek = (uint32_t)(buf >> 32);
       const uint32_t e = lut[peek >> (32 - kLutBits)];
-      unsigned len = (e >> 16) & 63u;
+      unsigned len;
       uint32_t s;
       if (!(e & kLutLong)) {
+        len = (e >> 16) & 63u;
         s = e & 0xFFFFu;
       } else {
-        while (len <= maxlen && (uint64_t)peek >= limit[len]) ++len;
+        len = kLutBits + 1;
+#pragma unroll
+        for (int l = kLutBits + 1; l < kMaxCodeLen; ++l)
+          if ((uint32_t)l < maxlen) len += peek >= lim[l] ? 1u : 0u;
         const uint32_t v = len <= maxlen ? peek >> (32 - len) : 0u;
-        if (len > maxlen || v < first[len] || v - first[len] >= count[len] ||
-            base[len] + (v - first[len]) >= n_codes) {
+        if (len > maxlen || ((e >> 16) & 63u) > maxlen || v < first[len] ||
+            v - first[len] >= count[len] || base[len] + (v - first[len]) >= n_codes) {
           bad = true;
           break;
         }
@@ -981,31 +1112,166 @@ __global__ __launch_bounds__(64 * kDecWaves) void k_decode(
       }
       buf <<= len;
       nb -= (int)len;
-      stage[wave][lane][k] = (uint16_t)s;
+      stw[lane][k] = (uint16_t)s;
     }
-    __syncthreads();
-    // store: rows of kn symbols, eight rows per pass of the wave
-    for (int r = 0; r < 64; r += 8) {
-      const int row = r + (lane >> 3), col = lane & 7;
-      const uint64_t c = wave_chunk0 + row;
-      if (c < n_chunks && col < kn) {
-        const int64_t pos = (int64_t)c * C + k0 + col;
-        if (pos < N) sym[pos] = stage[wave][row][col];
-      }
-    }
-    __syncthreads();
+    wave_lds_sync();
   }
-  const int64_t used = (int64_t)(wi - w0) * 32 - (int64_t)qn * 32 - nb;
+  store_batch(((C - 1) / kDecSB) * kDecSB);
+  const uint64_t wi = wq.wi;
+  const int qn = wq.qn;
+  // words taken into the bit buffer: all fetched but the prefetched group and
+  // the qn still queued
+  const int64_t used = ((int64_t)(wi - w0) - 4 - qn) * 32 - nb;
   if (live && (bad || used > (int64_t)(w1 - w0) * 32)) atomicOr(status, ST_FORMAT);
+}
+
+// ------------------------------------------------------------ batched form
+// Same bodies as the plain kernels; the array comes from the block map (or
+// the block index for one block per array).  Skipped arrays (constant, empty,
+// non-finite, no budget) only get their trivial stream or status in kb_header.
+__device__ __forceinline__ bool job_skipped_h(const Job& J) { return (*J.status & ST_SKIP) != 0; }
+__device__ __forceinline__ uint64_t job_cb_off(const Job& J) {
+  return kHeaderBytes + 8ull * (J.L + 1);
+}
+
+__global__ __launch_bounds__(1024) void kb_histogram(const Job* __restrict__ jobs,
+                                                      const JobBlock* __restrict__ map,
+                                                      uint32_t nb) {
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  if (job_skipped_h(J)) return;
+  histogram_body(J.sym, J.N, J.hist, jb.local, jb.count);
+}
+
+__global__ __launch_bounds__(1024) void kb_codebook(const Job* __restrict__ jobs) {
+  const Job& J = jobs[blockIdx.x];
+  if (job_skipped_h(J)) return;
+  codebook_body(J.hist, J.cbs, J.code, J.clen, J.out + job_cb_off(J), J.lay);
+}
+
+__global__ __launch_bounds__(256) void kb_chunk_words(const Job* __restrict__ jobs,
+                                                       const JobBlock* __restrict__ map,
+                                                       uint32_t nb) {
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  if (job_skipped_h(J)) return;
+  chunk_words_body(J.sym, J.N, (int)kChunkSyms, J.clen, J.cw, J.lay, jb.local);
+}
+
+__global__ __launch_bounds__(1024) void kb_layout_scan(const Job* __restrict__ jobs) {
+  const Job& J = jobs[blockIdx.x];
+  if (job_skipped_h(J)) return;
+  layout_scan_body(J.cw, (int64_t)J.n_chunks, J.out, job_cb_off(J), J.lay, J.n_out, J.cap, 0);
+}
+
+__global__ __launch_bounds__(1024) void kb_outlier_sort(const Job* __restrict__ jobs) {
+  const Job& J = jobs[blockIdx.x];
+  if (job_skipped_h(J)) return;
+  const OutlierBuf ob{J.opos, J.oval, J.n_out, J.cap};
+  outlier_sort_body(ob, J.okA, J.ovA, J.okB, J.ovB, J.key_bits, J.out, J.lay);
+}
+
+__global__ __launch_bounds__(256) void kb_encode(const Job* __restrict__ jobs,
+                                                  const JobBlock* __restrict__ map,
+                                                  uint32_t nb) {
+  extern __shared__ uint32_t wbuf[];  // 4 * C words
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  if (job_skipped_h(J)) return;
+  encode_body(J.sym, J.N, (int)kChunkSyms, J.code, J.clen, J.out, J.lay, jb.local, wbuf);
+}
+
+// Header, bins and result-table entries of one array (thread 0).  Constant
+// and empty arrays get the 136-byte trivial stream of the plain path.
+__global__ void kb_header(const Job* __restrict__ jobs) {
+  if (threadIdx.x != 0) return;
+  const Job& J = jobs[blockIdx.x];
+  const unsigned st = *J.status;
+  Header h = J.hdr;
+  uint8_t* out = J.out;
+  if (st & (ST_EMPTY | ST_CONST)) {
+    h.flags = (st & ST_EMPTY) ? FLAG_EMPTY : FLAG_CONSTANT;
+    if (!(st & ST_EMPTY)) h.const_value = J.bud[0];
+    h.L = 0;
+    h.n_chunks = 0;
+    h.total = kHeaderBytes + 8;
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(&h);
+    for (int i = 0; i < kHeaderBytes; ++i) out[i] = src[i];
+    for (int i = 0; i < 8; ++i) out[kHeaderBytes + i] = 0;
+    *J.size_out = h.total;
+    *J.status_out = MGC_OK;
+    return;
+  }
+  if (st & ST_NONFINITE) {
+    *J.size_out = 0;
+    *J.status_out = MGC_EINVAL;
+    return;
+  }
+  if (st & ST_BUDGET) {
+    *J.size_out = 0;
+    *J.status_out = MGC_ERANGE;
+    return;
+  }
+  const Layout* lay = J.lay;
+  const unsigned all = st | lay->status;
+  if (all) {
+    *J.size_out = (all & ST_OVERFLOW) ? lay->n_outliers : 0;
+    *J.status_out = (all & ST_OVERFLOW) ? MGC_ENOSPC : (all & ST_RANGE) ? MGC_ERANGE : MGC_EDEVICE;
+    return;
+  }
+  h.tau = J.bud[4];
+  h.tau_eff = J.bud[5];
+  h.n_codes = lay->n_codes;
+  h.n_outliers = lay->n_outliers;
+  h.n_words = lay->n_words;
+  h.total = lay->end;
+  const uint8_t* src = reinterpret_cast<const uint8_t*>(&h);
+  for (int i = 0; i < kHeaderBytes; ++i) out[i] = src[i];
+  double* q = reinterpret_cast<double*>(out + kHeaderBytes);
+  for (int l = 0; l <= J.L; ++l) q[l] = J.bud[bud_q(l)];
+  for (uint64_t i = lay->cb + 3 * lay->n_codes; i < lay->off; ++i) out[i] = 0;
+  for (uint64_t i = lay->words + 4 * lay->n_words; i < lay->end; ++i) out[i] = 0;
+  *J.size_out = lay->end;
+  *J.status_out = MGC_OK;
 }
 
 }  // namespace
 
-void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s) {
+uint32_t hist_blocks(int64_t n) {
   int64_t blocks = (n + 1024 * 64 - 1) / (1024 * 64);
   if (blocks < 1) blocks = 1;
   if (blocks > 256) blocks = 256;
-  hipLaunchKernelGGL(k_histogram, dim3((unsigned)blocks), dim3(1024), 0, s, sym, n, hist);
+  return (uint32_t)blocks;
+}
+
+void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_histogram, dim3(hist_blocks(n)), dim3(1024), 0, s, sym, n, hist);
+}
+
+void launch_b_histogram(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s) {
+  hipLaunchKernelGGL(kb_histogram, dim3(nb), dim3(1024), 0, s, jobs, map, nb);
+}
+void launch_b_codebook(const Job* jobs, int n, hipStream_t s) {
+  hipLaunchKernelGGL(kb_codebook, dim3((unsigned)n), dim3(1024), 0, s, jobs);
+}
+void launch_b_chunk_words(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s) {
+  hipLaunchKernelGGL(kb_chunk_words, dim3(nb), dim3(256), 0, s, jobs, map, nb);
+}
+void launch_b_layout_scan(const Job* jobs, int n, hipStream_t s) {
+  hipLaunchKernelGGL(kb_layout_scan, dim3((unsigned)n), dim3(1024), 0, s, jobs);
+}
+void launch_b_outlier_sort(const Job* jobs, int n, hipStream_t s) {
+  hipLaunchKernelGGL(kb_outlier_sort, dim3((unsigned)n), dim3(1024), 0, s, jobs);
+}
+void launch_b_encode(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s) {
+  hipLaunchKernelGGL(kb_encode, dim3(nb), dim3(256), (size_t)4 * kChunkSyms * sizeof(uint32_t),
+                     s, jobs, map, nb);
+}
+void launch_b_header(const Job* jobs, int n, hipStream_t s) {
+  hipLaunchKernelGGL(kb_header, dim3((unsigned)n), dim3(64), 0, s, jobs);
 }
 
 void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
@@ -1066,13 +1332,17 @@ void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint
   const int nthr = 64 * kDecWaves;
   const dim3 grid((unsigned)((n_chunks + nthr - 1) / nthr));
   const size_t dyn = ((size_t)n_codes * sizeof(uint16_t) + 15) & ~size_t(15);
-  static bool attr_set = false;
-  if (!attr_set) {
-    // allow the full 128 KiB table on top of the static LDS
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_decode),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
-    attr_set = true;
+  static size_t dyn_max = 0;
+  if (dyn_max == 0) {
+    // allow the full 128 KiB table on top of the static LDS (160 KiB per CU)
+    hipFuncAttributes fa;
+    MGC_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_decode)));
+    const size_t room = 163840 - fa.sharedSizeBytes;
+    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_decode),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)room));
+    dyn_max = room;
   }
+  if (dyn > dyn_max) fail(MGC_EDEVICE, "decode table does not fit in LDS");
   hipLaunchKernelGGL(k_decode, grid, dim3(nthr), dyn, s, in, off_sec, words_sec, n_chunks, n_words,
                      C, N, (uint32_t)n_codes, t, sym, status);
 }

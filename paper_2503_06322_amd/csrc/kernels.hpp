@@ -6,11 +6,43 @@
 
 namespace mgc {
 
+// ---- tile shapes ---------------------------------------------------------
+// Coarse outputs per tile of the decomposition kernel.  Three-axis levels
+// have candidates (the batched form's autotuner picks one per input type;
+// every candidate gives bit-identical results); entry 0 is the plain default.
+struct TileShape {
+  int z, y, x;
+};
+constexpr int kDecCands = 4;
+constexpr TileShape kDecTiles3F32[kDecCands] = {{4, 8, 16}, {8, 8, 8}, {4, 4, 16}, {2, 8, 32}};
+constexpr TileShape kDecTiles3F64[kDecCands] = {{4, 8, 8}, {4, 4, 16}, {2, 8, 16}, {8, 8, 8}};
+constexpr TileShape kDecTile2F32 = {1, 16, 32}, kDecTile2F64 = {1, 8, 32};
+constexpr TileShape kDecTile1 = {1, 1, 256};
+inline TileShape dec_tile(int D, bool f32, int cand) {
+  if (cand < 0 || cand >= kDecCands) cand = 0;
+  if (D == 3) return f32 ? kDecTiles3F32[cand] : kDecTiles3F64[cand];
+  if (D == 2) return f32 ? kDecTile2F32 : kDecTile2F64;
+  return kDecTile1;
+}
+// Thomas sweeps: values in flight per thread on strided axes, and the LDS
+// segment length on the contiguous axis (entry 0 is the plain default).
+constexpr int kThomasCands = 3;
+constexpr int kThomasU[kThomasCands] = {8, 4, 16};
+constexpr int kThomasSeg[kThomasCands] = {32, 16, 64};
+
 // ---- transform.hip -------------------------------------------------------
+// Blocks of the range pre-pass: a function of N alone, so that the sum of
+// squares is reduced in the same order by every entry point.
 constexpr int kRangeBlocks = 1024;
-// min, max, sum of squares and non-finite count of u (dtype dt) -> out[4].
-void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, double* out,
-                  hipStream_t s);
+__host__ __device__ inline unsigned range_blocks(int64_t N) {
+  const int64_t b = (N + 16383) / 16384;
+  return (unsigned)(b < 1 ? 1 : (b > kRangeBlocks ? kRangeBlocks : b));
+}
+// Range pre-pass and error budget: bud[0..3] <- min, max, sum of squares and
+// a non-finite flag of u (dtype dt); then tau, tau' and the bins (see Bud).
+// part holds 4 * kRangeBlocks doubles.
+void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, const BudgetIn& b,
+                  double* bud, unsigned* status, hipStream_t s);
 // One decomposition level: coefficients of the level's new nodes (quantised
 // to symbols when sym != nullptr, else FP64 into raw) and the restriction
 // f = (P^T M_l) G_l onto the coarse grid (fout, FP64).
@@ -44,11 +76,29 @@ void launch_fill(void* out, bool out_f32, int64_t N, double v, hipStream_t s);
 // Copies n (<= a few KiB) bytes with one block, e.g. into mapped host memory.
 void launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 
+// ---- batched form (one launch per stage over every array of a batch) ----
+// Map-driven launches take nb = number of map entries (grid covers them).
+void launch_b_zero(const Job* jobs, int n, hipStream_t s);
+void launch_b_range(const Job* jobs, const JobBlock* map, uint32_t nb, bool f32, hipStream_t s);
+void launch_b_budget(const Job* jobs, int n, hipStream_t s);
+void launch_b_dec_level(const Job* jobs, const JobBlock* map, uint32_t nb, int step, int D,
+                        bool f32, int cand, hipStream_t s);
+void launch_b_thomas(int axis, const Job* jobs, const JobBlock* map, uint32_t nb, int step,
+                     int cand, hipStream_t s);
+void launch_b_level0(const Job* jobs, const JobBlock* map, uint32_t nb, bool f32,
+                     hipStream_t s);
+void launch_b_histogram(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s);
+void launch_b_codebook(const Job* jobs, int n, hipStream_t s);
+void launch_b_chunk_words(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s);
+void launch_b_layout_scan(const Job* jobs, int n, hipStream_t s);
+void launch_b_outlier_sort(const Job* jobs, int n, hipStream_t s);
+void launch_b_encode(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s);
+void launch_b_header(const Job* jobs, int n, hipStream_t s);
+// Blocks per array of the map-driven Huffman launches.
+uint32_t hist_blocks(int64_t N);
+constexpr uint32_t kChunkSyms = 1024;   // symbols per coded chunk (C)
+
 // ---- huffman.hip ---------------------------------------------------------
-struct CodebookScratch {
-  uint32_t *keyA, *valA, *keyB, *valB, *symAsc, *freqAsc, *Iw, *Sw, *leafPar, *parA, *parB,
-      *dstA, *dstB;
-};
 size_t codebook_scratch_bytes();
 CodebookScratch carve_codebook_scratch(void* base);
 

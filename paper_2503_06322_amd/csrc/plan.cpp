@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #pragma clang fp contract(off)
 
@@ -225,11 +226,32 @@ Plan build_plan(int ndim, const uint64_t* shape) {
   return p;
 }
 
+// Device block: the operator tables, the bin factors K_l of both norms, then
+// the per-level geometry records (whose table pointers point into the block).
 void upload_plan(Plan& p) {
-  if (p.d_tab || p.tab.empty()) return;
-  MGC_HIP(hipMalloc(&p.d_tab, p.tab.size() * sizeof(double)));
-  MGC_HIP(hipMemcpy(p.d_tab, p.tab.data(), p.tab.size() * sizeof(double),
-                    hipMemcpyHostToDevice));
+  if (p.d_tab) return;
+  const size_t n_tab = p.tab.size();
+  const size_t k_off = n_tab, k_len = (size_t)p.L + 1;
+  const size_t geo_bytes = sizeof(LevelGeom) * ((size_t)p.L + 1);
+  const size_t geo_off = ((n_tab + 2 * k_len) * sizeof(double) + 255) & ~size_t(255);
+  const size_t total = geo_off + geo_bytes;
+  void* mem = nullptr;
+  MGC_HIP(hipMalloc(&mem, total));
+  p.d_tab = static_cast<double*>(mem);
+  std::vector<uint8_t> host(total, 0);
+  if (n_tab) std::memcpy(host.data(), p.tab.data(), n_tab * sizeof(double));
+  for (int nrm = 0; nrm < 2; ++nrm) {
+    const std::vector<double> K = p.bin_factors(nrm == 0 ? MGC_LINF : MGC_L2);
+    std::memcpy(host.data() + (k_off + nrm * k_len) * sizeof(double), K.data(),
+                k_len * sizeof(double));
+    p.d_K[nrm] = p.d_tab + k_off + nrm * k_len;
+  }
+  p.d_geo = reinterpret_cast<const LevelGeom*>(static_cast<uint8_t*>(mem) + geo_off);
+  for (int l = 0; l <= p.L; ++l) {
+    const LevelGeom g = p.geom(l);
+    std::memcpy(host.data() + geo_off + l * sizeof(LevelGeom), &g, sizeof(LevelGeom));
+  }
+  MGC_HIP(hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice));
 }
 
 void free_plan(Plan& p) {
@@ -279,23 +301,6 @@ std::vector<double> Plan::bin_factors(mgc_norm norm) const {
     }
   }
   return K;
-}
-
-void error_budget(mgc_dtype dt, mgc_norm norm, mgc_mode mode, double bound, double umin,
-                  double umax, double sumsq, int64_t N, double* tau, double* tau_eff) {
-  const double eps = dt == MGC_F32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
-  const double margin = std::ldexp(1.0, -36);
-  const double amax = std::max(std::fabs(umax), std::fabs(umin));
-  double t, A;
-  if (norm == MGC_LINF) {
-    t = mode == MGC_REL ? bound * (umax - umin) : bound;
-    A = amax;
-  } else {
-    t = mode == MGC_REL ? bound * std::sqrt(sumsq) : bound;
-    A = std::sqrt((double)N) * amax;
-  }
-  *tau = t;
-  *tau_eff = t - (eps + margin) * (A + t);
 }
 
 }  // namespace mgc

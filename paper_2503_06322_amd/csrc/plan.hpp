@@ -29,7 +29,9 @@ struct Plan {
   std::vector<std::array<int64_t, 3>> sizes;  // sizes[l], l = 0..L
   std::vector<PlanLevel> lv;                   // lv[l], l = 0..L
   std::vector<double> tab;                     // host copy of every table
-  double* d_tab = nullptr;                     // device copy (owned)
+  double* d_tab = nullptr;                     // device block (owned): tables, K, geometry
+  const double* d_K[2] = {nullptr, nullptr};   // bin factors (L-inf, L2), L + 1 each
+  const LevelGeom* d_geo = nullptr;            // d_geo[l], l = 0..L
 
   int64_t points(int l) const { return sizes[l][0] * sizes[l][1] * sizes[l][2]; }
   LevelGeom geom(int l) const;
@@ -42,9 +44,5 @@ Plan build_plan(int ndim, const uint64_t* shape);
 void upload_plan(Plan& p);
 void free_plan(Plan& p);
 
-// Error budget: tau (absolute bound) and tau' (budget the bins are derived
-// for), from the data's min, max and sum of squares.
-void error_budget(mgc_dtype dt, mgc_norm norm, mgc_mode mode, double bound, double umin,
-                  double umax, double sumsq, int64_t N, double* tau, double* tau_eff);
 
 }  // namespace mgc

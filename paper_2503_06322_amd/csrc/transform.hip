@@ -26,22 +26,30 @@ namespace {
 
 // Linear quantisation of one coefficient: k = rint(c * r) in FP64 (round
 // half to even).  |k| < S/2 -> symbol k + S/2; otherwise the escape symbol 0
-// and an (position, k) record.
+// and an (position, k) record.  The escaping lanes of a wavefront reserve
+// their records with one atomic (the records are sorted by position later,
+// so their order here does not matter).
 __device__ __forceinline__ void emit_q(int64_t pos, double c, double r, uint16_t* sym,
                                        const OutlierBuf& ob, unsigned* status) {
   const double t = rint(c * r);
-  if (fabs(t) < 32768.0) {
-    sym[pos] = (uint16_t)(int)(t + 32768.0);
-    return;
-  }
-  sym[pos] = 0;
-  int64_t k = 0;
-  if (fabs(t) < 4611686018427387904.0) k = (int64_t)t;
-  else atomicOr(status, ST_RANGE);
-  unsigned long long i = atomicAdd(ob.count, 1ull);
-  if (i < ob.cap) {
-    ob.pos[i] = (uint32_t)pos;
-    ob.val[i] = k;
+  const bool esc = !(fabs(t) < 32768.0);
+  sym[pos] = (uint16_t)(int)((esc ? -32768.0 : t) + 32768.0);
+  const uint64_t m = __ballot(esc);
+  if (m == 0) return;
+  if (esc) {
+    int64_t k = 0;
+    if (fabs(t) < 4611686018427387904.0) k = (int64_t)t;
+    else atomicOr(status, ST_RANGE);
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(ob.count, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, 64);
+    const unsigned long long i = base + (unsigned long long)__popcll(m & ((1ull << lane) - 1));
+    if (i < ob.cap) {
+      ob.pos[i] = (uint32_t)pos;
+      ob.val[i] = k;
+    }
   }
 }
 
@@ -79,18 +87,20 @@ __device__ __forceinline__ void range_acc(double v, double& mn, double& mx, doub
   }
 }
 
-// Each thread reads 16-byte vectors in a grid-stride loop (the tail, fewer
-// than one vector per thread of the grid, is read element by element).
+// Block `blk` of `nblk` reads 16-byte vectors in a grid-stride loop (the
+// tail, fewer than one vector per thread of the grid, element by element) and
+// writes its (min, max, sum of squares, non-finite flag) to part4.
 template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void k_range_partial(const T* __restrict__ u, int64_t N,
-                                                        double* __restrict__ part) {
+__device__ __forceinline__ void range_partial_body(const T* __restrict__ u, int64_t N,
+                                                   double* __restrict__ part4, uint32_t blk,
+                                                   uint32_t nblk) {
   constexpr int V = VEC ? 16 / sizeof(T) : 1;
   using Vec = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   double mn = INFINITY, mx = -INFINITY, ss = 0.0, bad = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)nblk * 256;
   const int64_t nvec = VEC ? N / V : 0;
   const Vec* uv = reinterpret_cast<const Vec*>(u);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+  for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < nvec; i += stride) {
     const Vec w = uv[i];
     if constexpr (sizeof(T) == 4) {
       range_acc<T>(w.x, mn, mx, ss, bad);
@@ -102,7 +112,7 @@ __global__ __launch_bounds__(256) void k_range_partial(const T* __restrict__ u, 
       range_acc<T>(w.y, mn, mx, ss, bad);
     }
   }
-  for (int64_t i = nvec * V + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride)
+  for (int64_t i = nvec * V + (int64_t)blk * 256 + threadIdx.x; i < N; i += stride)
     range_acc<T>((double)u[i], mn, mx, ss, bad);
   for (int o = 32; o > 0; o >>= 1) {
     mn = fmin(mn, __shfl_xor(mn, o, 64));
@@ -126,13 +136,20 @@ __global__ __launch_bounds__(256) void k_range_partial(const T* __restrict__ u, 
       sm[0][2] += sm[k][2];
       sm[0][3] = fmax(sm[0][3], sm[k][3]);
     }
-    for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = sm[0][k];
+    for (int k = 0; k < 4; ++k) part4[k] = sm[0][k];
   }
 }
 
-// Reduces the per-block partials in a fixed tree order (deterministic).
-__global__ __launch_bounds__(256) void k_range_final(const double* __restrict__ part, int nb,
-                                                      double* __restrict__ out) {
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_range_partial(const T* __restrict__ u, int64_t N,
+                                                        double* __restrict__ part) {
+  range_partial_body<T, VEC>(u, N, part + 4 * blockIdx.x, blockIdx.x, gridDim.x);
+}
+
+// Reduces the per-block partials in a fixed tree order (deterministic) into
+// out[0..3]; thread 0 also receives them in r4.
+__device__ __forceinline__ void range_final_body(const double* __restrict__ part, int nb,
+                                                 double* __restrict__ out, double* r4) {
   __shared__ double sm[4][256];
   const int t = threadIdx.x;
   double mn = INFINITY, mx = -INFINITY, ss = 0.0, bad = 0.0;
@@ -157,6 +174,58 @@ __global__ __launch_bounds__(256) void k_range_final(const double* __restrict__ 
     __syncthreads();
   }
   if (t < 4) out[t] = sm[t][0];
+  if (t == 0)
+    for (int k = 0; k < 4; ++k) r4[k] = sm[k][0];
+}
+
+// Error budget of the quantiser from the data range (thread 0): the absolute
+// bound tau (relative bounds scale by max - min for L-inf, by ||u||_2 for
+// L2), the budget tau' left after the rounding of the output type, and the
+// per-level bins q_l = tau' K_l with their reciprocals.  Sets ST_NONFINITE,
+// ST_CONST or ST_BUDGET (tau' not positive) instead when they apply.
+__device__ __forceinline__ void budget_from_range(const BudgetIn& b, const double* r4,
+                                                  double* __restrict__ bud,
+                                                  unsigned* __restrict__ status) {
+  const double mn = r4[0], mx = r4[1], ss = r4[2], bad = r4[3];
+  if (bad != 0.0) {
+    atomicOr(status, ST_NONFINITE);
+    return;
+  }
+  if (mn == mx) {
+    atomicOr(status, ST_CONST);
+    return;
+  }
+  const double eps = b.dtype == MGC_F32 ? 0x1p-24 : 0x1p-53;
+  const double margin = 0x1p-36;
+  const double amax = fmax(fabs(mx), fabs(mn));
+  double t, A;
+  if (b.norm == MGC_LINF) {
+    t = b.mode == MGC_REL ? b.bound * (mx - mn) : b.bound;
+    A = amax;
+  } else {
+    t = b.mode == MGC_REL ? b.bound * sqrt(ss) : b.bound;
+    A = sqrt((double)b.N) * amax;
+  }
+  const double te = t - (eps + margin) * (A + t);
+  bud[4] = t;
+  bud[5] = te;
+  if (!(te > 0.0)) {
+    atomicOr(status, ST_BUDGET);
+    return;
+  }
+  for (int l = 0; l <= b.L; ++l) {
+    const double q = te * b.K[l];
+    bud[6 + l] = q;
+    bud[6 + b.L + 1 + l] = 1.0 / q;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_budget(const double* __restrict__ part, int nb,
+                                                 const BudgetIn b, double* __restrict__ bud,
+                                                 unsigned* __restrict__ status) {
+  double r4[4];
+  range_final_body(part, nb, bud, r4);
+  if (threadIdx.x == 0) budget_from_range(b, r4, bud, status);
 }
 
 // ------------------------------------------------------------- tile helpers
@@ -275,6 +344,13 @@ __device__ __forceinline__ uint32_t stream_pos(const LevelGeom& g, const Tile& t
 // The separable restriction (P^T M_l along x, then y, then z) of a fine tile
 // held in LDS (element type V, row pitch E2, plane pitch E1*E2) to the tile's
 // coarse outputs, written to fout (coarse grid).  A and B are LDS scratch.
+//
+// A tap that falls outside the loaded region lies outside the grid, where the
+// operator's weight is exactly zero; such taps read the nearest loaded node
+// (clamped index) instead of being skipped, which adds a signed zero and
+// leaves every sum unchanged.  Each thread keeps one output column (x) or one
+// (y, x) pair for all its rows, so the taps' positions and weights are read
+// from LDS once per thread.
 template <typename V, int E0, int E1, int E2, int TZ, int TY, int TX>
 __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& tl,
                               const TileTabs<E0, E1, E2, TZ, TY, TX>& tb, double* __restrict__ fout,
@@ -287,62 +363,103 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
   {
     const int rows = tl.ext[0] * tl.ext[1];
     const uint64_t m1 = div_magic((uint32_t)tl.ext[1]);
-    for (int rw = rsub; rw < rows; rw += RS) {
-      const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
-      const V* row = tile + (z * E1 + y) * E2;
-      for (int cx = col0; cx < tl.tk[2]; cx += CW) {
-        const int p = tb.P2[cx];
+    const int last = tl.ext[2] - 1;
+    for (int cx = col0; cx < tl.tk[2]; cx += CW) {
+      const int p = tb.P2[cx];
+      int f[5];
+      double w[5];
+#pragma unroll
+      for (int d = 0; d < 5; ++d) {
+        f[d] = min(max(p + d - 2, 0), last);
+        w[d] = tb.W2[cx][d];
+      }
+      for (int rw = rsub; rw < rows; rw += RS) {
+        const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
+        const V* row = tile + (z * E1 + y) * E2;
         double acc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 5; ++d) {
-          const int f = p + d - 2;
-          const bool in = f >= 0 && f < tl.ext[2];
-          acc += tb.W2[cx][d] * (in ? (double)row[in ? f : 0] : 0.0);
-        }
+        for (int d = 0; d < 5; ++d) acc += w[d] * (double)row[f[d]];
         A[(z * E1 + y) * TX + cx] = acc;
       }
     }
   }
   __syncthreads();
-  // y: B[z][cy][cx], rows (z, cy)
-  {
+  constexpr int PAIRS = TY * TX;
+  constexpr bool FIXED = PAIRS <= 256 && 256 % PAIRS == 0;
+  // y: B[z][cy][cx]
+  if constexpr (FIXED) {
+    constexpr int G = 256 / PAIRS;   // threads sharing a (cy, cx) pair, over z
+    const int pair = tid % PAIRS, z0 = tid / PAIRS;
+    const int cy = pair / TX, cx = pair % TX;
+    if (cy < tl.tk[1] && cx < tl.tk[2]) {
+      const int p = tb.P1[cy], last = tl.ext[1] - 1;
+      int f[5];
+      double w[5];
+#pragma unroll
+      for (int d = 0; d < 5; ++d) {
+        f[d] = min(max(p + d - 2, 0), last);
+        w[d] = tb.W1[cy][d];
+      }
+      for (int z = z0; z < tl.ext[0]; z += G) {
+        const double* col = A + z * E1 * TX + cx;
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) acc += w[d] * col[f[d] * TX];
+        B[(z * TY + cy) * TX + cx] = acc;
+      }
+    }
+  } else {
     const int rows = tl.ext[0] * tl.tk[1];
     const uint64_t m1 = div_magic((uint32_t)tl.tk[1]);
+    const int last = tl.ext[1] - 1;
     for (int rw = rsub; rw < rows; rw += RS) {
       const int z = (int)div_small((uint32_t)rw, m1), cy = rw - z * tl.tk[1];
       const int p = tb.P1[cy];
       for (int cx = col0; cx < tl.tk[2]; cx += CW) {
         double acc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 5; ++d) {
-          const int f = p + d - 2;
-          const bool in = f >= 0 && f < tl.ext[1];
-          acc += tb.W1[cy][d] * (in ? A[(z * E1 + (in ? f : 0)) * TX + cx] : 0.0);
-        }
+        for (int d = 0; d < 5; ++d)
+          acc += tb.W1[cy][d] * A[(z * E1 + min(max(p + d - 2, 0), last)) * TX + cx];
         B[(z * TY + cy) * TX + cx] = acc;
       }
     }
   }
   __syncthreads();
-  // z: coarse outputs, rows (cz, cy)
+  // z: coarse outputs (cz, cy, cx)
   {
-    const int rows = tl.tk[0] * tl.tk[1];
-    const uint64_t m1 = div_magic((uint32_t)tl.tk[1]);
-    for (int rw = rsub; rw < rows; rw += RS) {
-      const int cz = (int)div_small((uint32_t)rw, m1), cy = rw - cz * tl.tk[1];
-      const int p = tb.P0[cz];
-      const size_t ro = ((size_t)(tl.c0[0] + cz) * tl.nc[1] + tl.c0[1] + cy) * tl.nc[2] + tl.c0[2];
-      double* orow = fout + ro;
-      for (int cx = col0; cx < tl.tk[2]; cx += CW) {
-        double acc = 0.0;
+    const int last = tl.ext[0] - 1;
+    if constexpr (FIXED) {
+      constexpr int G = 256 / PAIRS;
+      const int pair = tid % PAIRS, c0 = tid / PAIRS;
+      const int cy = pair / TX, cx = pair % TX;
+      if (cy < tl.tk[1] && cx < tl.tk[2]) {
+        for (int cz = c0; cz < tl.tk[0]; cz += G) {
+          const int p = tb.P0[cz];
+          double acc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 5; ++d) {
-          const int f = p + d - 2;
-          const bool in = f >= 0 && f < tl.ext[0];
-          acc += tb.W0[cz][d] * (in ? B[((in ? f : 0) * TY + cy) * TX + cx] : 0.0);
+          for (int d = 0; d < 5; ++d)
+            acc += tb.W0[cz][d] * B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx];
+          const size_t o = ((size_t)(tl.c0[0] + cz) * tl.nc[1] + tl.c0[1] + cy) * tl.nc[2] +
+                           tl.c0[2] + cx;
+          fout[o] = acc;
+          if (fout2) fout2[o] = acc;
         }
-        orow[cx] = acc;
-        if (fout2) fout2[ro + cx] = acc;
+      }
+    } else {
+      const int rows = tl.tk[0] * tl.tk[1];
+      const uint64_t m1 = div_magic((uint32_t)tl.tk[1]);
+      for (int rw = rsub; rw < rows; rw += RS) {
+        const int cz = (int)div_small((uint32_t)rw, m1), cy = rw - cz * tl.tk[1];
+        const int p = tb.P0[cz];
+        const size_t ro = ((size_t)(tl.c0[0] + cz) * tl.nc[1] + tl.c0[1] + cy) * tl.nc[2] + tl.c0[2];
+        for (int cx = col0; cx < tl.tk[2]; cx += CW) {
+          double acc = 0.0;
+#pragma unroll
+          for (int d = 0; d < 5; ++d)
+            acc += tb.W0[cz][d] * B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx];
+          fout[ro + cx] = acc;
+          if (fout2) fout2[ro + cx] = acc;
+        }
       }
     }
   }
@@ -351,15 +468,14 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
 // ----------------------------------------------- decomposition of one level
 // MODE: 0 quantise the coefficients, 1 write them as FP64, 2 adjoint (no
 // coefficients; restriction with the P^T taps written to fout and fout2).
+// Tile t (row-major over the level's coarse grid in tiles of TZ x TY x TX).
 template <typename Tin, int TZ, int TY, int TX, int MODE>
-__global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, const LevelGeom g,
-                                                    double* __restrict__ fout,
-                                                    uint16_t* __restrict__ sym,
-                                                    double* __restrict__ raw, const double r,
-                                                    const OutlierBuf ob,
-                                                    unsigned* __restrict__ status,
-                                                    const uint32_t n_tiles, const uint32_t tiles_x,
-                                                    const uint32_t tiles_y) {
+__device__ __forceinline__ void dec_level_body(const Tin* __restrict__ G, const LevelGeom& g,
+                                               double* __restrict__ fout,
+                                               uint16_t* __restrict__ sym,
+                                               double* __restrict__ raw, const double r,
+                                               const OutlierBuf& ob,
+                                               unsigned* __restrict__ status, uint32_t t) {
   constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
   constexpr int TILE_BYTES = E0 * E1 * E2 * (int)sizeof(Tin);
   static_assert(E0 * TY * TX * (int)sizeof(double) <= TILE_BYTES, "B aliases the tile");
@@ -368,8 +484,8 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
   __shared__ TileTabs<E0, E1, E2, TZ, TY, TX> tb;
   Tin* tile = reinterpret_cast<Tin*>(smem);
 
-  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= n_tiles) return;
+  const uint32_t tiles_x = (uint32_t)((g.nc[2] + TX - 1) / TX);
+  const uint32_t tiles_y = (uint32_t)((g.nc[1] + TY - 1) / TY);
   Tile tl;
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
   load_tabs(g, tl, tb, MODE != 2, MODE == 2);
@@ -446,22 +562,33 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
   restrict_tile(tile, A, reinterpret_cast<double*>(smem), tl, tb, fout, MODE == 2 ? raw : nullptr);
 }
 
+template <typename Tin, int TZ, int TY, int TX, int MODE>
+__global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, const LevelGeom g,
+                                                    double* __restrict__ fout,
+                                                    uint16_t* __restrict__ sym,
+                                                    double* __restrict__ raw, const double r,
+                                                    const OutlierBuf ob,
+                                                    unsigned* __restrict__ status,
+                                                    const uint32_t n_tiles) {
+  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= n_tiles) return;
+  dec_level_body<Tin, TZ, TY, TX, MODE>(G, g, fout, sym, raw, r, ob, status, t);
+}
+
 // --------------------------------------------- recomposition of one level
 // f = (P^T M_l) c_l: the tile holds the dequantised coefficients (zero at the
 // coarse nodes); then the same separable restriction.
 template <int TZ, int TY, int TX, bool RAW>
-__global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const CoeffSrc src,
-                                                       const double q, double* __restrict__ fout,
-                                                       const uint32_t n_tiles,
-                                                       const uint32_t tiles_x,
-                                                       const uint32_t tiles_y) {
+__device__ __forceinline__ void rec_restrict_body(const LevelGeom& g, const CoeffSrc& src,
+                                                  const double q, double* __restrict__ fout,
+                                                  uint32_t t) {
   constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
   static_assert(E0 * TY * TX <= E0 * E1 * E2, "B aliases the tile");
   __shared__ double tile[E0 * E1 * E2];
   __shared__ double A[E0 * E1 * TX];
   __shared__ TileTabs<E0, E1, E2, TZ, TY, TX> tb;
-  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= n_tiles) return;
+  const uint32_t tiles_x = (uint32_t)((g.nc[2] + TX - 1) / TX);
+  const uint32_t tiles_y = (uint32_t)((g.nc[1] + TY - 1) / TY);
   Tile tl;
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
   load_tabs(g, tl, tb, false);
@@ -501,22 +628,28 @@ __global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const C
   restrict_tile(tile, A, tile, tl, tb, fout);
 }
 
+template <int TZ, int TY, int TX, bool RAW>
+__global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const CoeffSrc src,
+                                                       const double q, double* __restrict__ fout,
+                                                       const uint32_t n_tiles) {
+  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= n_tiles) return;
+  rec_restrict_body<TZ, TY, TX, RAW>(g, src, q, fout, t);
+}
+
 // G_l = P Gc + c_l on the tile's owned fine nodes; the coarse values the tile
 // needs (its coarse outputs plus one more per axis) are staged in LDS.
 // SRC: 0 dequantised symbols, 1 FP64 coefficients, 2 none (plain P Gc).
 template <typename Tout, int TZ, int TY, int TX, int SRC>
-__global__ __launch_bounds__(256) void k_rec_interp(const double* __restrict__ Gc,
-                                                     const LevelGeom g, const CoeffSrc src,
-                                                     const double q, Tout* __restrict__ out,
-                                                     const uint32_t n_tiles,
-                                                     const uint32_t tiles_x,
-                                                     const uint32_t tiles_y) {
+__device__ __forceinline__ void rec_interp_body(const double* __restrict__ Gc, const LevelGeom& g,
+                                                const CoeffSrc& src, const double q,
+                                                Tout* __restrict__ out, uint32_t t) {
   constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
   constexpr int C0 = TZ == 1 ? 1 : TZ + 1, C1 = TY == 1 ? 1 : TY + 1, C2 = TX == 1 ? 1 : TX + 1;
   __shared__ double gc[C0 * C1 * C2];
   __shared__ TileTabs<E0, E1, E2, TZ, TY, TX> tb;
-  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= n_tiles) return;
+  const uint32_t tiles_x = (uint32_t)((g.nc[2] + TX - 1) / TX);
+  const uint32_t tiles_y = (uint32_t)((g.nc[1] + TY - 1) / TY);
   Tile tl;
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
   load_tabs(g, tl, tb, true);
@@ -568,6 +701,16 @@ __global__ __launch_bounds__(256) void k_rec_interp(const double* __restrict__ G
       orow[c] = (Tout)v;
     }
   }
+}
+
+template <typename Tout, int TZ, int TY, int TX, int SRC>
+__global__ __launch_bounds__(256) void k_rec_interp(const double* __restrict__ Gc,
+                                                     const LevelGeom g, const CoeffSrc src,
+                                                     const double q, Tout* __restrict__ out,
+                                                     const uint32_t n_tiles) {
+  const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= n_tiles) return;
+  rec_interp_body<Tout, TZ, TY, TX, SRC>(Gc, g, src, q, out, t);
 }
 
 // --------------------------------------------------------- adjoint pieces
@@ -624,14 +767,14 @@ __global__ __launch_bounds__(256) void k_adj_mass(const double* __restrict__ Pv,
 // Strided axes: one thread per line, adjacent lanes on adjacent lines (the
 // contiguous index), so every access is coalesced; values are moved in blocks
 // of U so that U loads are in flight before the recurrence consumes them.
+// Line t of the axis (lines ordered by their contiguous index).
 template <int AXIS, int U>
-__global__ __launch_bounds__(256) void k_thomas_strided(double* __restrict__ x, int64_t n0,
-                                                         int64_t n1, int64_t n2,
-                                                         const double* __restrict__ ta,
-                                                         const double* __restrict__ tm,
-                                                         const double* __restrict__ tc,
-                                                         const double* __restrict__ sub) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void thomas_strided_body(double* __restrict__ x, int64_t n0,
+                                                    int64_t n1, int64_t n2,
+                                                    const double* __restrict__ ta,
+                                                    const double* __restrict__ tm,
+                                                    const double* __restrict__ tc,
+                                                    const double* __restrict__ sub, int64_t t) {
   int64_t len, stride, base;
   if (AXIS == 1) {
     if (t >= n0 * n2) return;
@@ -691,18 +834,29 @@ __global__ __launch_bounds__(256) void k_thomas_strided(double* __restrict__ x, 
   }
 }
 
+template <int AXIS, int U>
+__global__ __launch_bounds__(256) void k_thomas_strided(double* __restrict__ x, int64_t n0,
+                                                         int64_t n1, int64_t n2,
+                                                         const double* __restrict__ ta,
+                                                         const double* __restrict__ tm,
+                                                         const double* __restrict__ tc,
+                                                         const double* __restrict__ sub) {
+  thomas_strided_body<AXIS, U>(x, n0, n1, n2, ta, tm, tc, sub,
+                               (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Contiguous axis: one wavefront per 64 rows.  Segments of SEG elements of
 // the 64 rows are staged through LDS with coalesced loads and stores; each
 // lane then runs the recurrence along its own row inside LDS.
 template <int SEG>
-__global__ __launch_bounds__(64) void k_thomas_rows(double* __restrict__ x, int64_t nrows,
-                                                     int64_t n, const double* __restrict__ ta,
-                                                     const double* __restrict__ tm,
-                                                     const double* __restrict__ tc,
-                                                     const double* __restrict__ sub) {
+__device__ __forceinline__ void thomas_rows_body(double* __restrict__ x, int64_t nrows,
+                                                 int64_t n, const double* __restrict__ ta,
+                                                 const double* __restrict__ tm,
+                                                 const double* __restrict__ tc,
+                                                 const double* __restrict__ sub, int64_t blk) {
   __shared__ double buf[64][SEG + 1];
   const int lane = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int64_t r0 = blk * 64;
   const int nr = (int)min<int64_t>(64, nrows - r0);
   double prev = 0.0;
   for (int64_t s0 = 0; s0 < n; s0 += SEG) {
@@ -750,17 +904,34 @@ __global__ __launch_bounds__(64) void k_thomas_rows(double* __restrict__ x, int6
   }
 }
 
+template <int SEG>
+__global__ __launch_bounds__(64) void k_thomas_rows(double* __restrict__ x, int64_t nrows,
+                                                     int64_t n, const double* __restrict__ ta,
+                                                     const double* __restrict__ tm,
+                                                     const double* __restrict__ tc,
+                                                     const double* __restrict__ sub) {
+  thomas_rows_body<SEG>(x, nrows, n, ta, tm, tc, sub, blockIdx.x);
+}
+
+template <typename Tin, bool QUANT>
+__device__ __forceinline__ void level0_body(const Tin* __restrict__ G0, int64_t m0,
+                                            uint16_t* __restrict__ sym, double* __restrict__ raw,
+                                            double r, const OutlierBuf& ob, unsigned* status,
+                                            uint32_t blk, uint32_t nblk) {
+  const int64_t stride = (int64_t)nblk * 256;
+  for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < m0; i += stride) {
+    const double c = (double)G0[i];
+    if (QUANT) emit_q(i, c, r, sym, ob, status);
+    else raw[i] = c;
+  }
+}
+
 template <typename Tin, bool QUANT>
 __global__ __launch_bounds__(256) void k_level0(const Tin* __restrict__ G0, int64_t m0,
                                                  uint16_t* __restrict__ sym,
                                                  double* __restrict__ raw, double r,
                                                  const OutlierBuf ob, unsigned* status) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m0; i += stride) {
-    const double c = (double)G0[i];
-    if (QUANT) emit_q(i, c, r, sym, ob, status);
-    else raw[i] = c;
-  }
+  level0_body<Tin, QUANT>(G0, m0, sym, raw, r, ob, status, blockIdx.x, gridDim.x);
 }
 
 template <typename Tout, bool RAW>
@@ -783,6 +954,113 @@ __global__ __launch_bounds__(256) void k_fill(Tout* __restrict__ out, int64_t N,
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride)
     out[i] = (Tout)v;
+}
+
+// ------------------------------------------------------------ batched form
+// Each batched kernel finds its array through the launch's block map (or its
+// block index, for one block per array), reads the array's pointers and level
+// geometry from the job table, and runs the same body as the plain kernel.
+// Arrays whose range pass flagged them (constant, empty, non-finite, no
+// budget) are skipped.  Step s of the level loop works on level L - s of each
+// array; level outputs alternate between the gA (even steps) and gB buffers.
+__device__ __forceinline__ bool job_skipped(const Job& J) { return (*J.status & ST_SKIP) != 0; }
+
+__global__ __launch_bounds__(256) void kb_zero(const Job* __restrict__ jobs) {
+  const Job& J = jobs[blockIdx.y];
+  const uint32_t b = blockIdx.x;
+  if (b < 16) {
+    for (uint32_t i = threadIdx.x; i < 4096; i += 256) J.hist[b * 4096 + i] = 0;
+    return;
+  }
+  if (threadIdx.x < 4) J.status[threadIdx.x] = 0;
+  if (threadIdx.x == 4) *J.n_out = 0;
+  unsigned* lw = reinterpret_cast<unsigned*>(J.lay);
+  for (uint32_t i = threadIdx.x; i < sizeof(Layout) / 4; i += 256) lw[i] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_range(const Job* __restrict__ jobs,
+                                                 const JobBlock* __restrict__ map, uint32_t nb) {
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  const T* u = static_cast<const T*>(J.in);
+  if ((reinterpret_cast<uintptr_t>(u) & 15) == 0)
+    range_partial_body<T, true>(u, J.N, J.part + 4 * jb.local, jb.local, jb.count);
+  else
+    range_partial_body<T, false>(u, J.N, J.part + 4 * jb.local, jb.local, jb.count);
+}
+
+__global__ __launch_bounds__(256) void kb_budget(const Job* __restrict__ jobs) {
+  const Job& J = jobs[blockIdx.x];
+  if (J.N == 0) {
+    if (threadIdx.x == 0) atomicOr(J.status, ST_EMPTY);
+    return;
+  }
+  double r4[4];
+  range_final_body(J.part, (int)range_blocks(J.N), J.bud, r4);
+  if (threadIdx.x == 0) budget_from_range(J.bi, r4, J.bud, J.status);
+}
+
+template <typename Tin, int TZ, int TY, int TX>
+__global__ __launch_bounds__(256) void kb_dec_level(const Job* __restrict__ jobs,
+                                                     const JobBlock* __restrict__ map,
+                                                     uint32_t nb, int step) {
+  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+  if (b >= nb) return;
+  const JobBlock jb = map[b];
+  const Job& J = jobs[jb.job];
+  if (job_skipped(J)) return;
+  const int l = J.L - step;
+  const Tin* G = step == 0 ? static_cast<const Tin*>(J.in)
+                           : reinterpret_cast<const Tin*>((step & 1) ? J.gA : J.gB);
+  double* F = (step & 1) ? J.gB : J.gA;
+  const OutlierBuf ob{J.opos, J.oval, J.n_out, J.cap};
+  dec_level_body<Tin, TZ, TY, TX, 0>(G, J.geo[l], F, J.sym, nullptr, J.bud[bud_r(J.L, l)], ob,
+                                     J.status, jb.local);
+}
+
+template <int SEG>
+__global__ __launch_bounds__(64) void kb_thomas_rows(const Job* __restrict__ jobs,
+                                                      const JobBlock* __restrict__ map,
+                                                      uint32_t nb, int step) {
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  if (job_skipped(J)) return;
+  const LevelGeom& g = J.geo[J.L - step];
+  const AxisTab& t = g.ax[2];
+  thomas_rows_body<SEG>((step & 1) ? J.gB : J.gA, g.nc[0] * g.nc[1], g.nc[2], t.ta, t.tm, t.tc,
+                        nullptr, jb.local);
+}
+
+template <int AXIS, int U>
+__global__ __launch_bounds__(256) void kb_thomas_strided(const Job* __restrict__ jobs,
+                                                          const JobBlock* __restrict__ map,
+                                                          uint32_t nb, int step) {
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  if (job_skipped(J)) return;
+  const LevelGeom& g = J.geo[J.L - step];
+  const AxisTab& t = g.ax[AXIS];
+  thomas_strided_body<AXIS, U>((step & 1) ? J.gB : J.gA, g.nc[0], g.nc[1], g.nc[2], t.ta, t.tm,
+                               t.tc, nullptr, (int64_t)jb.local * 256 + threadIdx.x);
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(256) void kb_level0(const Job* __restrict__ jobs,
+                                                  const JobBlock* __restrict__ map, uint32_t nb) {
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  if (job_skipped(J)) return;
+  const Tin* G0 = J.L == 0 ? static_cast<const Tin*>(J.in)
+                           : reinterpret_cast<const Tin*>(((J.L - 1) & 1) ? J.gB : J.gA);
+  const LevelGeom& g = J.geo[0];
+  const OutlierBuf ob{J.opos, J.oval, J.n_out, J.cap};
+  level0_body<Tin, true>(G0, g.nf[0] * g.nf[1] * g.nf[2], J.sym, nullptr,
+                         J.bud[bud_r(J.L, 0)], ob, J.status, jb.local, jb.count);
 }
 
 inline unsigned grid_for(int64_t n, int block = 256, int64_t cap = 65536) {
@@ -816,19 +1094,20 @@ void dec_dispatch(const void* G, const LevelGeom& g, double* fout, uint16_t* sym
   const Tin* Gp = static_cast<const Tin*>(G);
   const int D = active_axes(g);
   if (D == 3) {
-    constexpr int TX = sizeof(Tin) == 4 ? 16 : 8;
-    const TileGrid t = tile_grid(g, 4, 8, TX);
-    hipLaunchKernelGGL((k_dec_level<Tin, 4, 8, TX, MODE>), dim3(t.grid), dim3(256), 0, s, Gp, g,
-                       fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
+    constexpr TileShape ts = sizeof(Tin) == 4 ? kDecTiles3F32[0] : kDecTiles3F64[0];
+    const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
+    hipLaunchKernelGGL((k_dec_level<Tin, ts.z, ts.y, ts.x, MODE>), dim3(t.grid), dim3(256), 0, s,
+                       Gp, g, fout, sym, raw, r, ob, status, t.n_tiles);
   } else if (D == 2) {
-    constexpr int TY = sizeof(Tin) == 4 ? 16 : 8;
-    const TileGrid t = tile_grid(g, 1, TY, 32);
-    hipLaunchKernelGGL((k_dec_level<Tin, 1, TY, 32, MODE>), dim3(t.grid), dim3(256), 0, s, Gp, g,
-                       fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
+    constexpr TileShape ts = sizeof(Tin) == 4 ? kDecTile2F32 : kDecTile2F64;
+    const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
+    hipLaunchKernelGGL((k_dec_level<Tin, ts.z, ts.y, ts.x, MODE>), dim3(t.grid), dim3(256), 0, s,
+                       Gp, g, fout, sym, raw, r, ob, status, t.n_tiles);
   } else {
-    const TileGrid t = tile_grid(g, 1, 1, 256);
-    hipLaunchKernelGGL((k_dec_level<Tin, 1, 1, 256, MODE>), dim3(t.grid), dim3(256), 0, s, Gp,
-                       g, fout, sym, raw, r, ob, status, t.n_tiles, t.tiles_x, t.tiles_y);
+    constexpr TileShape ts = kDecTile1;
+    const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
+    hipLaunchKernelGGL((k_dec_level<Tin, ts.z, ts.y, ts.x, MODE>), dim3(t.grid), dim3(256), 0, s,
+                       Gp, g, fout, sym, raw, r, ob, status, t.n_tiles);
   }
 }
 
@@ -839,15 +1118,15 @@ void rec_restrict_dispatch(const LevelGeom& g, const CoeffSrc& src, double q, do
   if (D == 3) {
     const TileGrid t = tile_grid(g, 4, 8, 8);
     hipLaunchKernelGGL((k_rec_restrict<4, 8, 8, RAW>), dim3(t.grid), dim3(256), 0, s, g, src, q,
-                       fout, t.n_tiles, t.tiles_x, t.tiles_y);
+                       fout, t.n_tiles);
   } else if (D == 2) {
     const TileGrid t = tile_grid(g, 1, 8, 32);
     hipLaunchKernelGGL((k_rec_restrict<1, 8, 32, RAW>), dim3(t.grid), dim3(256), 0, s, g, src, q,
-                       fout, t.n_tiles, t.tiles_x, t.tiles_y);
+                       fout, t.n_tiles);
   } else {
     const TileGrid t = tile_grid(g, 1, 1, 256);
     hipLaunchKernelGGL((k_rec_restrict<1, 1, 256, RAW>), dim3(t.grid), dim3(256), 0, s, g, src,
-                       q, fout, t.n_tiles, t.tiles_x, t.tiles_y);
+                       q, fout, t.n_tiles);
   }
 }
 
@@ -858,35 +1137,36 @@ void rec_interp_dispatch(const double* Gc, const LevelGeom& g, const CoeffSrc& s
   if (D == 3) {
     const TileGrid t = tile_grid(g, 4, 8, 16);
     hipLaunchKernelGGL((k_rec_interp<Tout, 4, 8, 16, SRC>), dim3(t.grid), dim3(256), 0, s, Gc, g,
-                       src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
+                       src, q, out, t.n_tiles);
   } else if (D == 2) {
     const TileGrid t = tile_grid(g, 1, 16, 32);
     hipLaunchKernelGGL((k_rec_interp<Tout, 1, 16, 32, SRC>), dim3(t.grid), dim3(256), 0, s, Gc, g,
-                       src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
+                       src, q, out, t.n_tiles);
   } else {
     const TileGrid t = tile_grid(g, 1, 1, 256);
     hipLaunchKernelGGL((k_rec_interp<Tout, 1, 1, 256, SRC>), dim3(t.grid), dim3(256), 0, s, Gc,
-                       g, src, q, out, t.n_tiles, t.tiles_x, t.tiles_y);
+                       g, src, q, out, t.n_tiles);
   }
 }
 
 }  // namespace
 
-void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, double* out,
-                  hipStream_t s) {
+void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, const BudgetIn& b,
+                  double* bud, unsigned* status, hipStream_t s) {
   const bool vec = (reinterpret_cast<uintptr_t>(u) & 15) == 0;
+  const unsigned nb = range_blocks(N);
   if (dt == MGC_F32) {
-    if (vec) hipLaunchKernelGGL((k_range_partial<float, true>), dim3(kRangeBlocks), dim3(256), 0, s,
+    if (vec) hipLaunchKernelGGL((k_range_partial<float, true>), dim3(nb), dim3(256), 0, s,
                                 static_cast<const float*>(u), N, part);
-    else hipLaunchKernelGGL((k_range_partial<float, false>), dim3(kRangeBlocks), dim3(256), 0, s,
+    else hipLaunchKernelGGL((k_range_partial<float, false>), dim3(nb), dim3(256), 0, s,
                             static_cast<const float*>(u), N, part);
   } else {
-    if (vec) hipLaunchKernelGGL((k_range_partial<double, true>), dim3(kRangeBlocks), dim3(256), 0,
-                                s, static_cast<const double*>(u), N, part);
-    else hipLaunchKernelGGL((k_range_partial<double, false>), dim3(kRangeBlocks), dim3(256), 0, s,
+    if (vec) hipLaunchKernelGGL((k_range_partial<double, true>), dim3(nb), dim3(256), 0, s,
+                                static_cast<const double*>(u), N, part);
+    else hipLaunchKernelGGL((k_range_partial<double, false>), dim3(nb), dim3(256), 0, s,
                             static_cast<const double*>(u), N, part);
   }
-  hipLaunchKernelGGL(k_range_final, dim3(1), dim3(256), 0, s, part, kRangeBlocks, out);
+  hipLaunchKernelGGL(k_budget, dim3(1), dim3(256), 0, s, part, (int)nb, b, bud, status);
 }
 
 void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* fout,
@@ -905,18 +1185,18 @@ void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
                    const double* sub, hipStream_t s) {
   if (axis == 2) {
     const int64_t rows = nc[0] * nc[1];
-    hipLaunchKernelGGL(k_thomas_rows<32>, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, s, x,
-                       rows, nc[2], t.ta, t.tm, t.tc, sub);
+    hipLaunchKernelGGL(k_thomas_rows<kThomasSeg[0]>, dim3((unsigned)((rows + 63) / 64)), dim3(64),
+                       0, s, x, rows, nc[2], t.ta, t.tm, t.tc, sub);
     return;
   }
   const int64_t lines = axis == 1 ? nc[0] * nc[2] : nc[1] * nc[2];
   const unsigned blocks = (unsigned)((lines + 255) / 256);
   if (axis == 1)
-    hipLaunchKernelGGL((k_thomas_strided<1, 8>), dim3(blocks), dim3(256), 0, s, x, nc[0], nc[1],
-                       nc[2], t.ta, t.tm, t.tc, sub);
+    hipLaunchKernelGGL((k_thomas_strided<1, kThomasU[0]>), dim3(blocks), dim3(256), 0, s, x,
+                       nc[0], nc[1], nc[2], t.ta, t.tm, t.tc, sub);
   else
-    hipLaunchKernelGGL((k_thomas_strided<0, 8>), dim3(blocks), dim3(256), 0, s, x, nc[0], nc[1],
-                       nc[2], t.ta, t.tm, t.tc, sub);
+    hipLaunchKernelGGL((k_thomas_strided<0, kThomasU[0]>), dim3(blocks), dim3(256), 0, s, x,
+                       nc[0], nc[1], nc[2], t.ta, t.tm, t.tc, sub);
 }
 
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
@@ -984,6 +1264,88 @@ void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, boo
     else hipLaunchKernelGGL((k_rec_level0<double, false>), dim3(b), dim3(256), 0, s, src, m0, q,
                             static_cast<double*>(out));
   }
+}
+
+// ---- batched launchers
+void launch_b_zero(const Job* jobs, int n, hipStream_t s) {
+  hipLaunchKernelGGL(kb_zero, dim3(17, (unsigned)n), dim3(256), 0, s, jobs);
+}
+
+void launch_b_range(const Job* jobs, const JobBlock* map, uint32_t nb, bool f32, hipStream_t s) {
+  if (f32) hipLaunchKernelGGL(kb_range<float>, dim3(nb), dim3(256), 0, s, jobs, map, nb);
+  else hipLaunchKernelGGL(kb_range<double>, dim3(nb), dim3(256), 0, s, jobs, map, nb);
+}
+
+void launch_b_budget(const Job* jobs, int n, hipStream_t s) {
+  hipLaunchKernelGGL(kb_budget, dim3((unsigned)n), dim3(256), 0, s, jobs);
+}
+
+namespace {
+template <typename Tin, int TZ, int TY, int TX>
+void b_dec(const Job* jobs, const JobBlock* map, uint32_t nb, int step, hipStream_t s) {
+  const unsigned grid = (nb + 7) & ~7u;
+  hipLaunchKernelGGL((kb_dec_level<Tin, TZ, TY, TX>), dim3(grid), dim3(256), 0, s, jobs, map, nb,
+                     step);
+}
+template <typename Tin, int C>
+void b_dec_3(const Job* jobs, const JobBlock* map, uint32_t nb, int step, hipStream_t s) {
+  constexpr TileShape t = sizeof(Tin) == 4 ? kDecTiles3F32[C] : kDecTiles3F64[C];
+  b_dec<Tin, t.z, t.y, t.x>(jobs, map, nb, step, s);
+}
+template <typename Tin>
+void b_dec_cand(const Job* jobs, const JobBlock* map, uint32_t nb, int step, int D, int cand,
+                hipStream_t s) {
+  if (D == 3) {
+    switch (cand) {
+      case 1: b_dec_3<Tin, 1>(jobs, map, nb, step, s); break;
+      case 2: b_dec_3<Tin, 2>(jobs, map, nb, step, s); break;
+      case 3: b_dec_3<Tin, 3>(jobs, map, nb, step, s); break;
+      default: b_dec_3<Tin, 0>(jobs, map, nb, step, s);
+    }
+  } else if (D == 2) {
+    constexpr TileShape t = sizeof(Tin) == 4 ? kDecTile2F32 : kDecTile2F64;
+    b_dec<Tin, t.z, t.y, t.x>(jobs, map, nb, step, s);
+  } else {
+    b_dec<Tin, kDecTile1.z, kDecTile1.y, kDecTile1.x>(jobs, map, nb, step, s);
+  }
+}
+}  // namespace
+
+void launch_b_dec_level(const Job* jobs, const JobBlock* map, uint32_t nb, int step, int D,
+                        bool f32, int cand, hipStream_t s) {
+  if (f32) b_dec_cand<float>(jobs, map, nb, step, D, cand, s);
+  else b_dec_cand<double>(jobs, map, nb, step, D, cand, s);
+}
+
+namespace {
+template <int C>
+void b_thomas(int axis, const Job* jobs, const JobBlock* map, uint32_t nb, int step,
+              hipStream_t s) {
+  if (axis == 2)
+    hipLaunchKernelGGL(kb_thomas_rows<kThomasSeg[C]>, dim3(nb), dim3(64), 0, s, jobs, map, nb,
+                       step);
+  else if (axis == 1)
+    hipLaunchKernelGGL((kb_thomas_strided<1, kThomasU[C]>), dim3(nb), dim3(256), 0, s, jobs, map,
+                       nb, step);
+  else
+    hipLaunchKernelGGL((kb_thomas_strided<0, kThomasU[C]>), dim3(nb), dim3(256), 0, s, jobs, map,
+                       nb, step);
+}
+}  // namespace
+
+void launch_b_thomas(int axis, const Job* jobs, const JobBlock* map, uint32_t nb, int step,
+                     int cand, hipStream_t s) {
+  switch (cand) {
+    case 1: b_thomas<1>(axis, jobs, map, nb, step, s); break;
+    case 2: b_thomas<2>(axis, jobs, map, nb, step, s); break;
+    default: b_thomas<0>(axis, jobs, map, nb, step, s);
+  }
+}
+
+void launch_b_level0(const Job* jobs, const JobBlock* map, uint32_t nb, bool f32,
+                     hipStream_t s) {
+  if (f32) hipLaunchKernelGGL(kb_level0<float>, dim3(nb), dim3(256), 0, s, jobs, map, nb);
+  else hipLaunchKernelGGL(kb_level0<double>, dim3(nb), dim3(256), 0, s, jobs, map, nb);
 }
 
 void launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s) {

@@ -77,3 +77,26 @@ def test_gpu_entry_points_refuse_cpu_tensors():
     _lib()
     with pytest.raises(ValueError):
         mgc.compress(torch.zeros(8, 8), 1e-3)
+
+
+def test_batch_query_lays_out_plain_slots():
+    """Batched output slots are the plain worst-case sizes, 256-byte aligned."""
+    import torch
+    import paper_2503_06322_amd as mgc
+    _lib()
+    shapes = [(33, 65, 17), (257,), (0, 5), (9, 9), (65, 65, 65)]
+    dtypes = [torch.float32, torch.float64, torch.float32, torch.float64, torch.float32]
+    ws, total, offs = mgc.batch_query(shapes, dtypes)
+    pos = 0
+    wsum = 0
+    for shp, dt, off in zip(shapes, dtypes, offs):
+        w1, m1 = mgc.compress_query(shp, dt)
+        assert off == pos
+        pos += (m1 + 255) // 256 * 256
+        wsum += (w1 + 255) // 256 * 256
+    assert total == pos and ws == wsum
+    with pytest.raises(ValueError):
+        mgc.batch_query([(4, 4, 4, 4)], [torch.float32])
+    with pytest.raises(mgc.MgcError) as e:
+        mgc.batch_query([], [])
+    assert e.value.name == "EINVAL"

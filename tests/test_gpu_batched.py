@@ -1,0 +1,183 @@
+"""Batched form: one graph launch compresses many arrays of uneven shapes.
+
+* every array's stream is bit-identical to the plain mgc_compress stream of
+  the same array and outlier capacity, in graph and in eager mode, for every
+  candidate of every autotuner kind (outputs may not depend on tile shapes);
+* graph replays with new data and new bounds stay identical to plain calls;
+* constant, empty, non-finite and overflowing arrays get the plain path's
+  trivial streams or statuses; an overflowing array is compressed again with
+  the capacity the batch reported;
+* the 256-array batch (axes from {33, 65, 129, 257}, relative L-inf bounds
+  from {1e-2, 1e-3, 1e-4}, bump and |k|^-3 fields) matches plain calls array
+  by array and every reconstruction holds its bound;
+* small arrays of the batch decode with the FP64 oracle's decoder too.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+from tests.gpu_common import gpu, to_bytes
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [  # (shape, dtype, kind, bound)
+    ((33, 17, 20), np.float32, "bumps", 1e-3),
+    ((65, 65, 65), np.float32, "grf", 1e-2),
+    ((40, 33, 17), np.float64, "grf", 1e-4),
+    ((17, 17, 17), np.float64, "bumps", 1e-3),
+    ((100, 3), np.float32, "grf", 1e-3),
+    ((257,), np.float64, "grf", 1e-4),
+    ((9, 5, 4), np.float32, "bumps", 1e-2),
+    ((2, 2, 2), np.float32, "grf", 1e-3),
+    ((33, 20), np.float32, "bumps", 1e-4),
+    ((1, 30, 1), np.float64, "grf", 1e-3),
+]
+
+
+def _field(shape, dtype, kind, seed):
+    if kind == "bumps":
+        return synthetic.bumps(shape, seed, dtype=dtype)
+    return synthetic.grf(shape, seed, dtype=dtype)
+
+
+def _inputs(torch, seed=11):
+    return [torch.from_numpy(_field(s, d, k, seed + i)).cuda() for i, (s, d, k, _) in enumerate(SMALL)]
+
+
+def _assert_same_as_plain(mgc, xs, bounds, streams, norm="linf", mode="rel", cap=0):
+    for j, (x, b, got) in enumerate(zip(xs, bounds, streams)):
+        ref = mgc.compress(x, b, norm, mode, outlier_cap=cap)
+        assert got.numel() == ref.numel(), "array %d: %d vs %d bytes" % (j, got.numel(), ref.numel())
+        assert bool((got == ref).all()), "array %d differs from the plain stream" % j
+
+
+@pytest.mark.parametrize("norm,mode", [("linf", "rel"), ("l2", "rel"), ("linf", "abs")])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_batched_equals_plain(norm, mode, flags):
+    torch, mgc = gpu()
+    xs = _inputs(torch)
+    bounds = [b for (_, _, _, b) in SMALL]
+    out = mgc.compress_batched(xs, bounds, norm, mode, flags=flags)
+    _assert_same_as_plain(mgc, xs, bounds, out, norm, mode)
+
+
+def test_every_tuning_candidate_gives_the_same_streams():
+    torch, mgc = gpu()
+    xs = _inputs(torch, seed=21)
+    bounds = [b for (_, _, _, b) in SMALL]
+    ref = [mgc.compress(x, b) for x, b in zip(xs, bounds)]
+    b = mgc.Batch([x.shape for x in xs], [x.dtype for x in xs])
+    try:
+        for kind in mgc.TUNE_KINDS:
+            n_cand, _ = mgc.tuning_info(kind)
+            for c in range(n_cand):
+                mgc.set_tuning(kind, c)
+                b.run(xs, bounds)
+                got = b.streams()
+                assert mgc.tuning_info(kind)[1] == c
+                for j in range(len(xs)):
+                    assert bool((got[j] == ref[j]).all()), "kind %s candidate %d array %d" % (kind, c, j)
+            mgc.set_tuning(kind, -1)
+    finally:
+        for kind in mgc.TUNE_KINDS:
+            mgc.set_tuning(kind, -1)
+
+
+def test_graph_replay_with_new_data_and_bounds():
+    torch, mgc = gpu()
+    shapes = [s for (s, _, _, _) in SMALL]
+    dtypes = [torch.float32 if d == np.float32 else torch.float64 for (_, d, _, _) in SMALL]
+    b = mgc.Batch(shapes, dtypes)
+    for rep, seed in enumerate([31, 32, 33]):
+        xs = _inputs(torch, seed)
+        bounds = [bd * (1 + rep) for (_, _, _, bd) in SMALL]
+        b.run(xs, bounds)
+        got = b.streams()
+        _assert_same_as_plain(mgc, xs, bounds, [g.clone() for g in got])
+
+
+def test_trivial_and_failing_arrays():
+    torch, mgc = gpu()
+    good = torch.from_numpy(synthetic.grf((33, 33, 33), 5)).cuda()
+    const = torch.full((9, 9, 9), 1.5, dtype=torch.float32, device="cuda")
+    empty = torch.empty((0, 5), dtype=torch.float32, device="cuda")
+    bad = torch.from_numpy(synthetic.bumps((17, 17), 6)).cuda()
+    bad[3, 4] = float("nan")
+    xs = [good, const, empty, bad]
+    bounds = [1e-3, 1e-3, 1e-3, 1e-3]
+    b = mgc.Batch([x.shape for x in xs], [x.dtype for x in xs])
+    b.run(xs, bounds)
+    torch.cuda.synchronize()
+    status = b.status.cpu().tolist()
+    assert status == [0, 0, 0, 1]
+    sizes = b.sizes.cpu().tolist()
+    for j in range(3):
+        got = b.out[b.offsets[j]: b.offsets[j] + sizes[j]]
+        ref = mgc.compress(xs[j], bounds[j])
+        assert bool((got == ref).all()), "array %d" % j
+    with pytest.raises(mgc.MgcError):
+        b.streams()
+
+
+def test_overflow_is_reported_and_recompressed():
+    torch, mgc = gpu()
+    x_over = torch.from_numpy(synthetic.grf((65, 65, 65), 7)).cuda()
+    x_ok = torch.from_numpy(synthetic.bumps((33, 33, 33), 8)).cuda()
+    xs = [x_ok, x_over]
+    bounds = [1e-2, 1e-6]
+    b = mgc.Batch([x.shape for x in xs], [x.dtype for x in xs], outlier_cap=16)
+    b.run(xs, bounds)
+    torch.cuda.synchronize()
+    status = b.status.cpu().tolist()
+    sizes = b.sizes.cpu().tolist()
+    assert status[1] == 3 and sizes[1] > 16
+    got = b.streams()
+    assert bool((got[0] == mgc.compress(x_ok, 1e-2, outlier_cap=16)).all())
+    assert bool((got[1] == mgc.compress(x_over, 1e-6, outlier_cap=int(sizes[1]))).all())
+
+
+def test_small_arrays_decode_with_the_oracle():
+    torch, mgc = gpu()
+    xs = _inputs(torch, seed=41)
+    bounds = [b for (_, _, _, b) in SMALL]
+    out = mgc.compress_batched(xs, bounds)
+    for j, (x, bd) in enumerate(zip(xs, bounds)):
+        if x.numel() > 40000:
+            continue
+        u = x.cpu().numpy().astype(np.float64)
+        back = oracle.decompress(to_bytes(out[j]))
+        tau = bd * (u.max() - u.min())
+        assert np.max(np.abs(back - u)) <= tau, "array %d" % j
+
+
+@pytest.fixture(scope="module")
+def batch256():
+    specs = synthetic.batch_specs(256, seed=5)
+    with ThreadPoolExecutor(8) as ex:
+        fields = list(ex.map(synthetic.field_from_spec, specs))
+    return specs, fields
+
+
+def test_batch_of_256_matches_plain_and_holds_bounds(batch256):
+    torch, mgc = gpu()
+    specs, fields = batch256
+    xs = [torch.from_numpy(u).cuda() for u in fields]
+    bounds = [s["bound"] for s in specs]
+    b = mgc.Batch([x.shape for x in xs], [x.dtype for x in xs])
+    b.run(xs, bounds)
+    got = b.streams()
+    info = None
+    worst = 0.0
+    for j, (x, u, bd) in enumerate(zip(xs, fields, bounds)):
+        ref = mgc.compress(x, bd)
+        assert got[j].numel() == ref.numel() and bool((got[j] == ref).all()), "array %d" % j
+        info = mgc.header_info(got[j])
+        y = mgc.decompress(got[j], info=info)
+        tau = bd * (float(u.max()) - float(u.min()))
+        err = torch.max(torch.abs(y.double() - x.double())).item()
+        worst = max(worst, err / tau)
+        assert err <= tau, "array %d: error %.3g above %.3g" % (j, err, tau)
+    print("256 arrays: worst error / bound = %.3f" % worst)

@@ -192,3 +192,48 @@ def _grf513():
     if "u" not in _CACHE:
         _CACHE["u"] = synthetic.grf((513, 513, 513), 2)
     return _CACHE["u"]
+
+
+def _cfg3(name):
+    key = "cfg3_" + name
+    if key not in _CACHE:
+        if name == "sin8193":
+            _CACHE[key] = synthetic.sinusoids((8193, 8193), 3)
+        else:
+            _CACHE[key] = synthetic.grf((300, 400, 500), 4)
+    return _CACHE[key]
+
+
+@pytest.mark.parametrize("name,norm,rel", [("sin8193", "linf", 1e-4), ("sin8193", "l2", 1e-3),
+                                           ("grf300", "linf", 1e-4), ("grf300", "l2", 1e-3)])
+def test_full_size_fp64_and_non_dyadic(name, norm, rel):
+    """8193^2 FP64 plane waves and a 300x400x500 FP32 |k|^-3 field."""
+    torch, mgc = gpu()
+    u = _cfg3(name)
+    x = torch.from_numpy(u).cuda()
+    blob = mgc.compress(x, rel, norm)
+    v = mgc.decompress(blob).cpu().numpy()
+    assert v.dtype == u.dtype and _bound_ok(u, v, rel, norm)
+    g = to_bytes(blob)
+    hd = parse_header(g)
+    h = Hierarchy(u.shape)
+    assert hd["L"] == h.L
+    _, tau_eff = oracle.error_budget(u, rel, norm, "rel")
+    q = oracle.level_bins(h, tau_eff, norm)
+    if norm == "linf":
+        assert np.array_equal(hd["q"], q)
+    else:
+        assert np.allclose(hd["q"], q, rtol=1e-13, atol=0)
+    # sampled finest-level integers (with the stream's own bins)
+    idx = np.random.default_rng(2).choice(u.size, 2000, replace=False)
+    pos, c = oracle.transform.finest_coefficients_at(u.astype(np.float64), h, idx)
+    k_ref = np.rint(c * (1.0 / hd["q"][h.L])).astype(np.int64)
+    chunks = np.unique(pos // hd["C"])
+    sym, opos, oval = decode_symbols(g, hd, chunks=chunks)
+    k = sym[pos] - 32768
+    esc = sym[pos] == 0
+    if np.any(esc):
+        where = np.searchsorted(opos.astype(np.int64), pos[esc])
+        k[esc] = oval[where]
+    assert np.count_nonzero(k != k_ref) <= 1e-6 * u.size
+    assert np.all(np.abs(k - k_ref) <= 1)
