@@ -35,6 +35,42 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_grf513_f32_linf_rel1e-3.txt")
+
+
+def source_digest() -> str:
+    """SHA-256 of the library sources (kernels, host code, C header)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2503_06322_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "mgc.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage: str):
+    """HBM bytes per launch of a stage from the committed hardware-counter
+    summary, or None when it is missing or the sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    digest, bytes_of = None, {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line.startswith("source_sha256:"):
+            digest = line.split(":", 1)[1].strip()
+        elif line.startswith("stage "):
+            name, rest = line[len("stage "):].split(":", 1)
+            f = dict(kv.split("=") for kv in rest.split())
+            bytes_of[name.strip()] = int(f["fetch"]) + int(f["write"])
+    if digest != source_digest():
+        return None
+    return bytes_of.get(stage)
+
+
 def stage_bytes(N: int, Nc: int, in_size: int, stream_bytes: int):
     """Algorithmic HBM bytes per launch of the finest-level / full-array stages.
 
@@ -291,7 +327,7 @@ def main():
     achieved = sb[dom["stage"]] / (dom["ms_per_launch"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom["stage"], "achieved": round(achieved, 1),
                 "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                "traffic": None, "bytes_per_launch": int(sb[dom["stage"]])}
+                "traffic": measured_traffic(dom["stage"]), "bytes_per_launch": int(sb[dom["stage"]])}
 
     batched = None
     if not args.no_batched:

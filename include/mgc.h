@@ -205,7 +205,8 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes,
  *   timed on the call's own data and the fastest kept.  Calls on one context
  *   must not overlap; the buffers of a call must stay valid until it ends.
  * mgc_set_tuning forces candidate `candidate` of tuning kind `kind` for later
- *   batched calls of the context (-1 = autotune again).  Candidates:
+ *   calls of the context, batched and plain (-1 = autotune again for batched
+ *   calls, the default candidate 0 for plain calls).  Candidates:
  *   MGC_TUNE_DEC_F32 / MGC_TUNE_DEC_F64 - tile shape (coarse outputs, z y x)
  *   of the three-axis decomposition kernel on FP32 / FP64 input: f32
  *   {4x8x16, 8x8x8, 4x4x16, 2x8x32}, f64 {4x8x8, 4x4x16, 2x8x16, 8x8x8};

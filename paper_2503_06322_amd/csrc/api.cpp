@@ -173,6 +173,13 @@ namespace {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
+// Candidate of a tuning kind for plain calls: the caller's forced choice, else
+// the default (entry 0).
+int tuned(mgc_ctx ctx, int kind) {
+  const int c = ctx->forced_tuning[kind];
+  return c >= 0 ? c : 0;
+}
+
 // stage names of the finest level's sweeps, per internal axis
 const char* const kThomasFinest[3] = {"thomas_ax0[finest]", "thomas_ax1[finest]",
                                       "thomas_ax2[finest]"};
@@ -208,12 +215,14 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
     const LevelGeom g = p.geom(l);
     {
       StageScope sc(&ctx->prof, l == p.L ? "dec_level[finest]" : "dec_level", s);
-      launch_dec_level(Gcur, cur_f32, g, Gnext, sym, raw, sym ? r[l] : 0.0, ob, status, s);
+      launch_dec_level(Gcur, cur_f32, g, Gnext, sym, raw, sym ? r[l] : 0.0, ob, status, s,
+                       tuned(ctx, cur_f32 ? MGC_TUNE_DEC_F32 : MGC_TUNE_DEC_F64));
     }
     for (int axis = 2; axis >= 0; --axis) {
       if (p.bit[axis] < 0) continue;
       StageScope sc(&ctx->prof, l == p.L ? kThomasFinest[axis] : "thomas", s);
-      launch_thomas(axis, Gnext, g.nc, g.ax[axis], nullptr, s);
+      launch_thomas(axis, Gnext, g.nc, g.ax[axis], nullptr, s,
+                    tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED));
     }
     Gcur = Gnext;
     cur_f32 = false;
@@ -261,7 +270,8 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
     for (int axis = 2; axis >= 0; --axis) {
       if (p.bit[axis] < 0) continue;
       StageScope sc(&ctx->prof, fin ? kThomasFinest[axis] : "thomas", s);
-      launch_thomas(axis, F, g.nc, g.ax[axis], axis == last ? Gprev : nullptr, s);
+      launch_thomas(axis, F, g.nc, g.ax[axis], axis == last ? Gprev : nullptr, s,
+                    tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED));
     }
     {
       StageScope sc(&ctx->prof, fin ? "rec_interp[finest]" : "rec_interp", s);
@@ -414,7 +424,7 @@ mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t*
     }
     {
       StageScope st(&ctx->prof, "encode", s);
-      launch_encode(w.sym, p.N, kChunk, w.code, w.clen, out, w.lay, s);
+      launch_encode(w.sym, p.N, kChunk, w.code, w.clen, sc.pk, out, w.lay, s);
     }
     {
       StageScope st(&ctx->prof, "header", s);
@@ -481,7 +491,7 @@ mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* 
     }
     if (h.L != (uint32_t)p.L || h.S != kDict || h.C < 1 || h.C > (1u << 20) ||
         h.n_chunks != (h.N + h.C - 1) / h.C || h.n_codes > kDict || h.n_codes < 1 ||
-        h.n_outliers > h.N)
+        h.n_outliers > h.N || h.n_words < 1)
       fail(MGC_EFORMAT, "inconsistent header counts");
     const uint64_t cb = kHeaderBytes + 8 * (h.L + 1);
     const uint64_t off = pad8(cb + 3 * h.n_codes);
@@ -712,6 +722,7 @@ mgc_status mgc_huffman_encode(mgc_ctx ctx, const uint16_t* d_sym, uint64_t n, ui
     uint32_t* code = c.take<uint32_t>(kDict);
     uint8_t* clen = c.take<uint8_t>(kDict);
     void* cbs = c.take<uint8_t>(codebook_scratch_bytes());
+    const CodebookScratch cbsc = carve_codebook_scratch(cbs);
     uint32_t* cw = c.take<uint32_t>(std::max<uint64_t>(n_chunks, 1));
     Layout* lay = c.take<Layout>(1);
     unsigned long long* info = c.take<unsigned long long>(4);
@@ -724,7 +735,7 @@ mgc_status mgc_huffman_encode(mgc_ctx ctx, const uint16_t* d_sym, uint64_t n, ui
     }
     {
       StageScope st(&ctx->prof, "codebook", s);
-      launch_codebook(hist, carve_codebook_scratch(cbs), code, clen, out, kHuffHeaderBytes, lay, s);
+      launch_codebook(hist, cbsc, code, clen, out, kHuffHeaderBytes, lay, s);
     }
     if (n > 0) {
       StageScope st(&ctx->prof, "chunk_words", s);
@@ -736,7 +747,7 @@ mgc_status mgc_huffman_encode(mgc_ctx ctx, const uint16_t* d_sym, uint64_t n, ui
     }
     if (n > 0) {
       StageScope st(&ctx->prof, "encode", s);
-      launch_encode(d_sym, (int64_t)n, (int)C, code, clen, out, lay, s);
+      launch_encode(d_sym, (int64_t)n, (int)C, code, clen, cbsc.pk, out, lay, s);
     }
     launch_huff_header(out, C, n, n_chunks, lay, info, s);
     MGC_HIP(hipGetLastError());
@@ -769,6 +780,7 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes, ui
     meas.take<unsigned>(4);
     if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
     if (n == 0) return;
+    if (h.n_words < 1) fail(MGC_EFORMAT, "huffman stream without coded words");
     Carver c(d_ws);
     void* tables = c.take<uint8_t>(decode_tables_bytes());
     unsigned* status = c.take<unsigned>(4);

@@ -224,7 +224,7 @@ void build_launches(BatchPlan& b, const int t[kTuneKinds], std::vector<JobBlock>
     BLaunch L;
     L.kind = BK::ChunkW;
     L.name = "b_chunk_words";
-    mapped(L, [&](int j) { return live(j) ? ceil_div(ceil_div(b.plans[j]->N, kChunk), 4) : 0u; });
+    mapped(L, [&](int j) { return live(j) ? chunk_words_blocks(b.plans[j]->N, kChunk) : 0u; });
   }
   per_job(BK::Scan, "b_layout_scan");
   per_job(BK::OSort, "b_outlier_sort");

@@ -94,6 +94,7 @@ struct CoeffSrc {
 struct CodebookScratch {
   uint32_t *keyA, *valA, *keyB, *valB, *symAsc, *freqAsc, *Iw, *Sw, *leafPar, *parA, *parB,
       *dstA, *dstB;
+  uint32_t* pk;  // per coded symbol: code << 6 | length (valid when max_len <= 26)
 };
 
 // Stream layout computed on the device once counts are known.
@@ -103,7 +104,7 @@ struct Layout {
   unsigned long long n_words;
   unsigned long long cb, off, opos, oval, words, end;
   unsigned int status;
-  unsigned int pad;
+  unsigned int max_len;   // longest code length (set with the codebook)
 };
 
 // Fixed 128-byte header of a compressed stream (little-endian on the host

@@ -24,10 +24,14 @@
 //    to 11 bits, longer codes use the canonical limit table.
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace mgc {
 
 constexpr int kLutBits = 12;
-constexpr uint32_t kLutLong = 1u << 31;   // LUT entry flag: a longer code, length field = minimum
+// Prefix-table entry flag: the prefix holds codes of several lengths
+// (lengths lo and hi in bits 16..21 and 22..27), or none (lo = 0).
+constexpr uint32_t kLutMixed = 1u << 31;
 
 struct DecodeTables {
   uint32_t first[34];
@@ -36,15 +40,18 @@ struct DecodeTables {
   uint64_t limit[34];   // left-justified exclusive upper bound of each length
   uint32_t maxlen;
   uint32_t valid;               // 1 only after a codebook passed validation
-  // symbol | length << 16 for codes of <= kLutBits bits; for a prefix of
-  // longer codes kLutLong | (shortest length with that prefix) << 16
+  // Entry of each kLutBits-bit prefix of the window.  When every window
+  // with that prefix starts with a code of one length d: d << 16 |
+  // ((base[d] - first[d]) mod 2^16), so that the code's index in sorted is
+  // (top d bits of the window + entry) mod 2^16.  Otherwise kLutMixed with
+  // the shortest and longest length under the prefix.
   uint32_t lut[1 << kLutBits];
   uint16_t sorted[kDict];       // symbols in (length, symbol) order
 };
 
 size_t decode_tables_bytes() { return sizeof(DecodeTables); }
 
-size_t codebook_scratch_bytes() { return (size_t)kDict * 4 * 14; }
+size_t codebook_scratch_bytes() { return (size_t)kDict * 4 * 15; }
 
 CodebookScratch carve_codebook_scratch(void* base) {
   uint32_t* p = static_cast<uint32_t*>(base);
@@ -62,6 +69,7 @@ CodebookScratch carve_codebook_scratch(void* base) {
   s.parB = p; p += kDict;
   s.dstA = p; p += kDict;
   s.dstB = p; p += kDict;
+  s.pk = p; p += kDict;
   return s;
 }
 
@@ -348,7 +356,10 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
   const unsigned n = total;
   __syncthreads();
   if (n == 0) {
-    if (tid == 0) lay->n_codes = 0;
+    if (tid == 0) {
+      lay->n_codes = 0;
+      lay->max_len = 0;
+    }
     return;
   }
   if (n == 1) {
@@ -356,9 +367,11 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       const unsigned sy = s.symAsc[0];
       clen[sy] = 1;
       code[sy] = 0;
+      s.pk[sy] = 1u;  // code 0, one bit
       reinterpret_cast<uint16_t*>(cb_out)[0] = (uint16_t)sy;
       cb_out[2] = 1;
       lay->n_codes = 1;
+      lay->max_len = 1;
     }
     return;
   }
@@ -580,24 +593,30 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
   for (unsigned i = tid; i < n; i += 1024) atomicAdd(&sm.lfirst[clen[s.symAsc[i]]], 1u);
   __syncthreads();
   if (tid == 0) {
-    unsigned c = 0;
+    unsigned c = 0, ml = 0;
     for (int l = 1; l <= kMaxCodeLen; ++l) {
       const unsigned cntl = sm.lfirst[l];
+      if (cntl) ml = l;
       sm.lfirst[l] = c;
       c = (c + cntl) << 1;
     }
+    lay->max_len = ml;
   }
   __syncthreads();
   stable_digit_ranks(
       n, [&](unsigned i) { return (unsigned)clen[s.symAsc[i]]; },
       [&](unsigned i, unsigned d, unsigned rank) { code[s.symAsc[i]] = sm.lfirst[d] + rank; },
       sm);
-  // 7. codebook section: symbols ascending, then their lengths
+  __syncthreads();
+  // 7. codebook section: symbols ascending, then their lengths; the packed
+  //    (code, length) word of each coded symbol for the encoder
   uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
   for (unsigned i = tid; i < n; i += 1024) {
     const unsigned sy = s.symAsc[i];
+    const unsigned l = clen[sy];
     cs[i] = (uint16_t)sy;
-    cb_out[2 * n + i] = clen[sy];
+    cb_out[2 * n + i] = (uint8_t)l;
+    s.pk[sy] = (code[sy] << 6) | l;
   }
   if (tid == 0) lay->n_codes = n;
 }
@@ -617,32 +636,49 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
 __device__ __forceinline__ void chunk_words_body(const uint16_t* __restrict__ sym, int64_t N,
                                                  int C, const uint8_t* __restrict__ clen,
                                                  uint32_t* __restrict__ cw,
-                                                 const Layout* __restrict__ lay, uint32_t blk) {
+                                                 const Layout* __restrict__ lay, uint32_t blk,
+                                                 uint32_t nblk) {
+  // the code lengths of all 65536 symbols in LDS (one 16-byte load per
+  // thread per 4 KiB), then chunk groups of four in a block-stride loop
+  __shared__ __align__(16) uint8_t ln[kDict];
   if (lay->status) return;
-  const int64_t n_chunks = (N + C - 1) / C;
-  const int64_t chunk = (int64_t)blk * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (chunk >= n_chunks) return;
-  const int per = C / 64;
-  const int64_t a = chunk * C + (int64_t)lane * per;
-  const int64_t end = min<int64_t>(chunk * C + C, N);
-  unsigned bits = 0;
-  for (int k0 = 0; k0 < per; k0 += 8) {
-    unsigned sy[8];
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(clen);
+    uint4* dst = reinterpret_cast<uint4*>(ln);
+    uint4 v[kDict / 16 / 256];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) sy[u] = (k0 + u < per && a + k0 + u < end) ? sym[a + k0 + u] : 0xFFFFFFFFu;
+    for (int u = 0; u < kDict / 16 / 256; ++u) v[u] = src[u * 256 + threadIdx.x];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) bits += sy[u] != 0xFFFFFFFFu ? clen[sy[u]] : 0u;
+    for (int u = 0; u < kDict / 16 / 256; ++u) dst[u * 256 + threadIdx.x] = v[u];
   }
-  for (int o = 32; o > 0; o >>= 1) bits += (unsigned)__shfl_xor((int)bits, o, 64);
-  if (lane == 0) cw[chunk] = (bits + 31u) >> 5;
+  __syncthreads();
+  const int64_t n_chunks = (N + C - 1) / C;
+  const int lane = threadIdx.x & 63;
+  const int per = C / 64;
+  for (int64_t chunk = (int64_t)blk * 4 + (threadIdx.x >> 6); chunk < n_chunks;
+       chunk += (int64_t)nblk * 4) {
+    const int64_t a = chunk * C + (int64_t)lane * per;
+    const int64_t end = min<int64_t>(chunk * C + C, N);
+    unsigned bits = 0;
+    if (per == 16 && a + 16 <= end && (reinterpret_cast<uintptr_t>(sym) & 15) == 0) {
+      const uint4* p = reinterpret_cast<const uint4*>(sym + a);
+      const uint4 x0 = p[0], x1 = p[1];
+      const unsigned w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) bits += (unsigned)ln[w[k] & 0xFFFFu] + ln[w[k] >> 16];
+    } else {
+      for (int64_t i = a; i < min<int64_t>(a + per, end); ++i) bits += ln[sym[i]];
+    }
+    for (int o = 32; o > 0; o >>= 1) bits += (unsigned)__shfl_xor((int)bits, o, 64);
+    if (lane == 0) cw[chunk] = (bits + 31u) >> 5;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict__ sym, int64_t N,
                                                       int C, const uint8_t* __restrict__ clen,
                                                       uint32_t* __restrict__ cw,
                                                       const Layout* __restrict__ lay) {
-  chunk_words_body(sym, N, C, clen, cw, lay, blockIdx.x);
+  chunk_words_body(sym, N, C, clen, cw, lay, blockIdx.x, gridDim.x);
 }
 
 __device__ __forceinline__ void layout_scan_body(const uint32_t* __restrict__ cw,
@@ -739,9 +775,21 @@ __global__ __launch_bounds__(1024) void k_outlier_sort(const OutlierBuf ob, uint
 // One wavefront per chunk, four chunks per block; LDS holds each chunk's
 // words while codes are OR-ed into place.
 // wbuf: dynamic LDS of 4 * C words.
+// OR code c of length l at bit position bitpos of the chunk's LDS words.
+__device__ __forceinline__ void put_code(uint32_t* w, unsigned bitpos, uint32_t c, unsigned l) {
+  const unsigned wi = bitpos >> 5, o = bitpos & 31u;
+  if (o + l <= 32u) {
+    atomicOr(&w[wi], c << (32u - o - l));
+  } else {
+    atomicOr(&w[wi], c >> (o + l - 32u));
+    atomicOr(&w[wi + 1], c << (64u - o - l));
+  }
+}
+
 __device__ __forceinline__ void encode_body(const uint16_t* __restrict__ sym, int64_t N, int C,
                                             const uint32_t* __restrict__ code,
                                             const uint8_t* __restrict__ clen,
+                                            const uint32_t* __restrict__ pk,
                                             uint8_t* __restrict__ out,
                                             const Layout* __restrict__ lay, uint32_t blk,
                                             uint32_t* wbuf) {
@@ -758,6 +806,46 @@ __device__ __forceinline__ void encode_body(const uint16_t* __restrict__ sym, in
   const int per = C / 64;
   const int64_t a = live ? chunk * C + (int64_t)lane * per : 0;
   const int64_t end = live ? min<int64_t>(chunk * C + C, N) : 0;
+  if (per == 16 && lay->max_len <= 26) {
+    // sixteen symbols per lane in two 16-byte loads (element loads at the
+    // array's end), one packed (code, length) word each
+    uint32_t cl[16];
+    if (a + 16 <= end && (reinterpret_cast<uintptr_t>(sym) & 15) == 0) {
+      const uint4* p = reinterpret_cast<const uint4*>(sym + a);
+      const uint4 x0 = p[0], x1 = p[1];
+      const unsigned v[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        cl[2 * k] = pk[v[k] & 0xFFFFu];
+        cl[2 * k + 1] = pk[v[k] >> 16];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) cl[k] = a + k < end ? pk[sym[a + k]] : 0u;
+    }
+    unsigned my_bits = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) my_bits += cl[k] & 63u;
+    unsigned x = my_bits;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned y = (unsigned)__shfl_up((int)x, o, 64);
+      if (lane >= o) x += y;
+    }
+    unsigned bitpos = x - my_bits;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const unsigned l = cl[k] & 63u;
+      if (l == 0) continue;
+      put_code(w, bitpos, cl[k] >> 6, l);
+      bitpos += l;
+    }
+    __syncthreads();
+    if (live) {
+      const uint64_t w0 = offs[chunk], nw = offs[chunk + 1] - w0;
+      for (uint64_t i = lane; i < nw; i += 64) words[w0 + i] = w[i];
+    }
+    return;
+  }
   // pass 1: bit count of this lane's symbols
   unsigned my_bits = 0;
   for (int k0 = 0; k0 < per; k0 += 8) {
@@ -790,14 +878,7 @@ __device__ __forceinline__ void encode_body(const uint16_t* __restrict__ sym, in
     for (int u = 0; u < 8; ++u) {
       const unsigned l = ln[u];
       if (l == 0) continue;
-      const uint32_t c = cd[u];
-      const unsigned wi = bitpos >> 5, o = bitpos & 31u;
-      if (o + l <= 32u) {
-        atomicOr(&w[wi], c << (32u - o - l));
-      } else {
-        atomicOr(&w[wi], c >> (o + l - 32u));
-        atomicOr(&w[wi + 1], c << (64u - o - l));
-      }
+      put_code(w, bitpos, cd[u], l);
       bitpos += l;
     }
   }
@@ -811,10 +892,11 @@ __device__ __forceinline__ void encode_body(const uint16_t* __restrict__ sym, in
 __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym, int64_t N, int C,
                                                  const uint32_t* __restrict__ code,
                                                  const uint8_t* __restrict__ clen,
+                                                 const uint32_t* __restrict__ pk,
                                                  uint8_t* __restrict__ out,
                                                  const Layout* __restrict__ lay) {
   extern __shared__ uint32_t wbuf[];  // 4 * C words
-  encode_body(sym, N, C, code, clen, out, lay, blockIdx.x, wbuf);
+  encode_body(sym, N, C, code, clen, pk, out, lay, blockIdx.x, wbuf);
 }
 
 struct QArgs {
@@ -885,6 +967,8 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     else atomicAdd(&sm.lcount[l], 1u);
   }
   __syncthreads();
+  __shared__ unsigned long long llim[34];
+  __shared__ unsigned lmax;
   if (tid == 0) {
     unsigned c = 0, idx = 0, maxlen = 0;
     unsigned long long kraft = 0;
@@ -894,6 +978,7 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
       t->count[l] = cnt;
       t->base[l] = idx;
       t->limit[l] = ((unsigned long long)c + cnt) << (32 - l);
+      llim[l] = ((unsigned long long)c + cnt) << (32 - l);
       sm.lfirst[l] = c;
       sm.lbase[l] = idx;
       kraft += (unsigned long long)cnt << (32 - l);
@@ -902,6 +987,7 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
       if (cnt) maxlen = l;
     }
     t->maxlen = maxlen;
+    lmax = maxlen;
     if (kraft > (1ull << 32) || (n >= 2 && kraft != (1ull << 32))) sm.flag = 1;
   }
   __syncthreads();
@@ -915,46 +1001,53 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     lbase[tid] = sm.lbase[tid];
   }
   __syncthreads();
-  __shared__ uint32_t lut[1 << kLutBits];
-  for (unsigned i = tid; i < (1u << kLutBits); i += 1024) lut[i] = kLutLong | (63u << 16);
-  __syncthreads();
+  // symbols in (length, symbol) order
   stable_digit_ranks(
       n, [&](unsigned i) { return (unsigned)lens[i]; },
-      [&](unsigned i, unsigned d, unsigned rank) {
-        const unsigned sy = syms[i];
-        t->sorted[lbase[d] + rank] = (uint16_t)sy;
-        const unsigned c = lfirst[d] + rank;
-        if (d <= (unsigned)kLutBits) {
-          const unsigned a = c << (kLutBits - d), b = (c + 1) << (kLutBits - d);
-          for (unsigned e = a; e < b; ++e) lut[e] = sy | (d << 16);
-        } else {
-          // the shortest length among the codes under this prefix
-          atomicMin(&lut[c >> (d - kLutBits)], kLutLong | (d << 16));
-        }
-      },
-      sm);
-  for (unsigned i = tid; i < (1u << kLutBits); i += 1024) t->lut[i] = lut[i];
+      [&](unsigned i, unsigned d, unsigned rank) { t->sorted[lbase[d] + rank] = syms[i]; }, sm);
+  // prefix table: the code length at a left-aligned 32-bit window W is one
+  // more than the number of lengths whose limit is <= W (limits do not
+  // decrease with the length); a prefix's windows span [lo, hi]
+  const unsigned maxlen = lmax;
+  for (unsigned p = tid; p < (1u << kLutBits); p += 1024) {
+    const uint64_t lo = (uint64_t)p << (32 - kLutBits);
+    const uint64_t hi = lo + (1ull << (32 - kLutBits)) - 1;
+    unsigned dlo = 1, dhi = 1;
+    for (unsigned l = 1; l <= maxlen; ++l) {
+      dlo += llim[l] <= lo ? 1u : 0u;
+      dhi += llim[l] <= hi ? 1u : 0u;
+    }
+    uint32_t e;
+    if (dhi > maxlen) e = kLutMixed;  // windows that start no code (one-symbol codebook)
+    else if (dlo == dhi) e = (dlo << 16) | ((lbase[dlo] - lfirst[dlo]) & 0xFFFFu);
+    else e = kLutMixed | (dlo << 16) | (dhi << 22);
+    t->lut[p] = e;
+  }
   __syncthreads();
   if (tid == 0) t->valid = 1;
 }
 
-// One thread per chunk, 64 chunks per wavefront, eight wavefronts per block.
+// One thread per chunk, 64 chunks per wavefront, blockDim/64 wavefronts per
+// block (sized by the launcher so that one pass of blocks covers the CUs).
 //
-// Coded words flow through a 64-bit bit buffer fed by a queue of up to eight
-// words in registers, behind which the next four words are always in flight.
-// The queue is topped up at fixed symbol counts (every four symbols, when it
-// holds four words or fewer), the same points for every lane, so a wavefront
-// only waits for loads issued a refill period earlier; a lane whose queue
-// runs dry in between (possible only with codes near the 32-bit limit) tops
-// up on the spot.  A 12-bit prefix table resolves short codes directly.  For
-// a longer code the length is the number of canonical limits the left-aligned
-// 32-bit window reaches (the limits grow with the length; those of lengths
-// 13..31 sit in registers), then the symbol comes from the (length,
-// symbol)-ordered table in LDS (dynamic size: the codebook's).  Decoded
-// symbols are staged in LDS, eight per lane, and stored at the next batch's
-// start, four rows of 16 bytes per wave instruction.
+// A symbol costs two LDS lookups and no branch on the common path: the
+// 12-bit prefix of the left-aligned window gives the code length d (and a
+// 16-bit offset), the top d bits of the window plus the offset give the
+// code's index in the (length, symbol)-ordered table.  Prefixes holding
+// codes of several lengths (at most one per length boundary) count the
+// canonical limits between their shortest and longest length.
+//
+// Coded words reach the 64-bit bit buffer through a ring of RW words per
+// lane in LDS.  At fixed symbol counts (every four symbols, the same points
+// for every lane) a lane whose ring has room for four more words writes the
+// group it loaded earlier and requests the group after next, so two groups
+// of loads are in flight behind the ring and a wavefront waits only for
+// loads issued two refills before.  Four symbols take at most four words
+// and each refill point leaves at least four in the ring, so the word a
+// symbol needs is always there.  Decoded symbols are staged in LDS, eight
+// per lane, and stored at the next batch's start, four rows of 16 bytes per
+// wave instruction.
 constexpr int kDecSB = 8;
-constexpr int kDecWaves = 8;
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -962,76 +1055,42 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Register queue of coded words: q0..q3 hold up to eight 32-bit words,
-// first word in the high half of q0, unused words zero; p0, p1 the four
-// words that follow (in flight); wi the next word to request.
-struct WordQueue {
-  uint64_t q0, q1, q2, q3, p0, p1;
-  int qn;
-  uint64_t wi;
+__host__ __device__ constexpr size_t dec_sorted_bytes(uint64_t n_codes) {
+  return ((size_t)n_codes * sizeof(uint16_t) + 15) & ~size_t(15);
+}
+// dynamic LDS per wavefront beyond the sorted table: ring and staging rows
+__host__ __device__ constexpr size_t dec_wave_bytes(int rw) {
+  return (size_t)64 * ((size_t)(rw + 1) * 4 + (kDecSB + 2) * 2);
+}
 
-  __device__ __forceinline__ void request(const uint32_t* __restrict__ words, uint64_t w1) {
-    uint32_t v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = wi + u < w1 ? words[wi + u] : 0u;
-    p0 = ((uint64_t)v[0] << 32) | v[1];
-    p1 = ((uint64_t)v[2] << 32) | v[3];
-    wi += 4;
-  }
-  // append the four pending words at word qn (qn <= 4), then request more
-  __device__ __forceinline__ void top_up(const uint32_t* __restrict__ words, uint64_t w1) {
-    const bool odd = qn & 1;
-    const int half = qn >> 1;
-    const uint64_t x0 = odd ? (p0 >> 32) : p0;
-    const uint64_t x1 = odd ? ((p0 << 32) | (p1 >> 32)) : p1;
-    const uint64_t x2 = odd ? (p1 << 32) : 0ull;
-    q0 |= half == 0 ? x0 : 0ull;
-    q1 |= half == 0 ? x1 : (half == 1 ? x0 : 0ull);
-    q2 |= half == 0 ? x2 : (half == 1 ? x1 : x0);
-    q3 |= half == 1 ? x2 : (half == 2 ? x1 : 0ull);
-    qn += 4;
-    request(words, w1);
-  }
-  __device__ __forceinline__ uint32_t pull(const uint32_t* __restrict__ words, uint64_t w1) {
-    if (qn == 0) top_up(words, w1);
-    const uint32_t w = (uint32_t)(q0 >> 32);
-    q0 = (q0 << 32) | (q1 >> 32);
-    q1 = (q1 << 32) | (q2 >> 32);
-    q2 = (q2 << 32) | (q3 >> 32);
-    q3 <<= 32;
-    --qn;
-    return w;
-  }
-};
-
-__global__ __launch_bounds__(64 * kDecWaves) void k_decode(
+template <int RW>
+__global__ __launch_bounds__(1024) void k_decode(
     const uint8_t* __restrict__ in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
     uint64_t n_words, int C, int64_t N, uint32_t n_codes, const DecodeTables* __restrict__ t,
     uint16_t* __restrict__ sym, unsigned* status) {
-  extern __shared__ uint16_t sorted[];  // n_codes entries
+  static_assert(RW % 4 == 0 && RW >= 8, "ring of whole groups with room for two");
+  constexpr int RS = RW + 1;  // ring row pitch in words (odd: rows start on different banks)
+  extern __shared__ __align__(16) unsigned char dsm[];
   __shared__ uint32_t lut[1 << kLutBits];
-  __shared__ uint32_t first[34], count[34], base[34];
+  __shared__ uint32_t lim[kMaxCodeLen + 1], offd[kMaxCodeLen + 1];
   __shared__ uint32_t valid;
-  __shared__ uint16_t stage[kDecWaves][64][kDecSB + 2];
-  const int nthr = 64 * kDecWaves;
+  const int nthr = blockDim.x;
+  uint16_t* sorted = reinterpret_cast<uint16_t*>(dsm);
+  uint32_t* ring = reinterpret_cast<uint32_t*>(dsm + dec_sorted_bytes(n_codes));
+  uint16_t* stage = reinterpret_cast<uint16_t*>(ring + (size_t)nthr * RS);
   if (threadIdx.x == 0) valid = t->valid;
   __syncthreads();
   if (!valid) return;  // table build rejected the codebook (status already set)
   for (int i = threadIdx.x; i < (1 << kLutBits); i += nthr) lut[i] = t->lut[i];
-  if (threadIdx.x < 34) {
-    first[threadIdx.x] = t->first[threadIdx.x];
-    count[threadIdx.x] = t->count[threadIdx.x];
-    base[threadIdx.x] = t->base[threadIdx.x];
+  const uint32_t maxlen = t->maxlen > (uint32_t)kMaxCodeLen ? kMaxCodeLen : t->maxlen;
+  if (threadIdx.x <= kMaxCodeLen) {
+    // limits below the longest length are under 2^32 (the longest length's
+    // codes lie above them)
+    const int l = threadIdx.x;
+    lim[l] = l >= 1 && (uint32_t)l < maxlen ? (uint32_t)t->limit[l] : 0xFFFFFFFFu;
+    offd[l] = ((uint32_t)l << 16) | ((t->base[l] - t->first[l]) & 0xFFFFu);
   }
   for (uint32_t i = threadIdx.x; i < n_codes; i += nthr) sorted[i] = t->sorted[i];
-  // uniform: longest length and the limits of lengths kLutBits+1 .. 31
-  // (below the longest length a limit is under 2^32: the longest length's
-  // own codes lie above it)
-  const uint32_t maxlen = t->maxlen > (uint32_t)kMaxCodeLen ? kMaxCodeLen : t->maxlen;
-  uint32_t lim[kMaxCodeLen];
-#pragma unroll
-  for (int l = kLutBits + 1; l < kMaxCodeLen; ++l)
-    lim[l] = (uint32_t)min<uint64_t>(t->limit[l], 0xFFFFFFFFull);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t wave_chunk0 = (uint64_t)blockIdx.x * nthr + wave * 64;
@@ -1050,26 +1109,72 @@ __global__ __launch_bounds__(64 * kDecWaves) void k_decode(
   }
   const int64_t start = (int64_t)chunk * C;
   const int cnt = live ? (int)min<int64_t>(C, N - start) : 0;
-  WordQueue wq;
-  wq.q2 = wq.q3 = 0;
-  wq.wi = w0;
-  wq.request(words, w1);
-  wq.q0 = wq.p0;
-  wq.q1 = wq.p1;
-  wq.request(words, w1);
-  wq.q2 = wq.p0;
-  wq.q3 = wq.p1;
-  wq.qn = 8;
-  wq.request(words, w1);
-  uint64_t buf = 0;
-  int nb = 0;
+  const uint64_t nwc = live ? w1 - w0 : 0;  // words of the chunk; later ones read as zero
+  const uint64_t last = n_words > 0 ? n_words - 1 : 0;
+  // loads from a clamped index, so that no load sits behind a branch
+  auto ld = [&](uint32_t i) -> uint32_t { return words[min<uint64_t>(w0 + i, last)]; };
+  auto msk = [&](uint32_t i, uint32_t v) -> uint32_t { return i < nwc ? v : 0u; };
+  uint32_t* rg = ring + (size_t)threadIdx.x * RS;
+  // prologue: the first RW words into the ring, the next two groups in flight
+  uint32_t g0, g1, g2, g3, h0, h1, h2, h3;
+  {
+    uint32_t pre[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) pre[i] = ld(i);
+    g0 = ld(RW);
+    g1 = ld(RW + 1);
+    g2 = ld(RW + 2);
+    g3 = ld(RW + 3);
+    h0 = ld(RW + 4);
+    h1 = ld(RW + 5);
+    h2 = ld(RW + 6);
+    h3 = ld(RW + 7);
+#pragma unroll
+    for (int i = 0; i < RW; ++i) rg[i] = msk(i, pre[i]);
+  }
+  uint64_t buf = ((uint64_t)rg[0] << 32) | rg[1];
+  int nb = 64;                // valid bits in buf (left-aligned)
+  uint32_t rd = 2, wt = RW;   // next word into buf; words written to the ring
+  uint32_t nextw = rg[rd % RW];
   bool bad = false;
-  uint16_t(*stw)[kDecSB + 2] = stage[wave];
+  auto top_up = [&]() {
+    if (wt - rd <= (uint32_t)(RW - 4)) {
+      rg[wt % RW] = msk(wt, g0);
+      rg[(wt + 1) % RW] = msk(wt + 1, g1);
+      rg[(wt + 2) % RW] = msk(wt + 2, g2);
+      rg[(wt + 3) % RW] = msk(wt + 3, g3);
+      wt += 4;
+      g0 = h0;
+      g1 = h1;
+      g2 = h2;
+      g3 = h3;
+      h0 = ld(wt + 4);
+      h1 = ld(wt + 5);
+      h2 = ld(wt + 6);
+      h3 = ld(wt + 7);
+    }
+    nextw = rg[rd % RW];
+  };
+  // a prefix with codes of several lengths: count the limits the window
+  // reaches; a window that starts no code marks the chunk bad
+  auto mixed = [&](uint32_t e, uint32_t peek) -> uint32_t {
+    unsigned d = (e >> 16) & 63u;
+    const unsigned dhi = (e >> 22) & 63u;
+    if (d == 0) {
+      bad = true;
+      return (1u << 16) | ((0u - (peek >> 31)) & 0xFFFFu);  // one bit, index 0
+    }
+    while (d < dhi && peek >= lim[d]) ++d;
+    return offd[d];
+  };
+  uint16_t* stw = stage + (size_t)wave * 64 * (kDecSB + 2);
+  uint16_t* mine = stw + lane * (kDecSB + 2);
   // stores of a staged batch: lane l writes row r + l/8, column l%8
   auto store_batch = [&](int kb) {
-    uint16_t v[64 / (64 / kDecSB)];
+    uint16_t v[kDecSB];
 #pragma unroll
-    for (int i = 0; i < kDecSB; ++i) v[i] = stw[i * (64 / kDecSB) + lane / kDecSB][lane % kDecSB];
+    for (int i = 0; i < kDecSB; ++i)
+      v[i] = stw[(i * (64 / kDecSB) + lane / kDecSB) * (kDecSB + 2) + lane % kDecSB];
     wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < kDecSB; ++i) {
@@ -1080,49 +1185,33 @@ __global__ __launch_bounds__(64 * kDecWaves) void k_decode(
     }
   };
   for (int k0 = 0; k0 < C; k0 += kDecSB) {
-    if (wq.qn <= 4) wq.top_up(words, w1);
+    top_up();
     if (k0 > 0) store_batch(k0 - kDecSB);
-    for (int k = 0; k < kDecSB; ++k) {
-      if (k == kDecSB / 2 && wq.qn <= 4) wq.top_up(words, w1);
-      if (k0 + k >= cnt || bad) break;
-      while (nb <= 32) {
-        const uint32_t w = wq.pull(words, w1);
-        buf |= (uint64_t)w << (32 - nb);
-        nb += 32;
-      }
-      const uint32_t peek = (uint32_t)(buf >> 32);
-      const uint32_t e = lut[peek >> (32 - kLutBits)];
-      unsigned len;
-      uint32_t s;
-      if (!(e & kLutLong)) {
-        len = (e >> 16) & 63u;
-        s = e & 0xFFFFu;
-      } else {
-        len = kLutBits + 1;
 #pragma unroll
-        for (int l = kLutBits + 1; l < kMaxCodeLen; ++l)
-          if ((uint32_t)l < maxlen) len += peek >= lim[l] ? 1u : 0u;
-        const uint32_t v = len <= maxlen ? peek >> (32 - len) : 0u;
-        if (len > maxlen || ((e >> 16) & 63u) > maxlen || v < first[len] ||
-            v - first[len] >= count[len] || base[len] + (v - first[len]) >= n_codes) {
-          bad = true;
-          break;
-        }
-        s = sorted[base[len] + (v - first[len])];
-      }
-      buf <<= len;
-      nb -= (int)len;
-      stw[lane][k] = (uint16_t)s;
+    for (int k = 0; k < kDecSB; ++k) {
+      if (k == kDecSB / 2) top_up();
+      const uint32_t peek = (uint32_t)(buf >> 32);
+      uint32_t e = lut[peek >> (32 - kLutBits)];
+      if (e & kLutMixed) e = mixed(e, peek);
+      unsigned d = (e >> 16) & 63u;
+      const uint32_t v = (uint32_t)(((uint64_t)peek << d) >> 32);  // top d bits
+      mine[k] = sorted[(v + e) & 0xFFFFu];
+      d = k0 + k < cnt ? d : 0u;  // past the chunk's last symbol nothing is consumed
+      buf <<= d;
+      nb -= (int)d;
+      const bool need = nb < 32;
+      buf |= (uint64_t)(need ? nextw : 0u) << ((32 - nb) & 63);
+      nb += need ? 32 : 0;
+      rd += need ? 1u : 0u;
+      nextw = rg[rd % RW];
     }
     wave_lds_sync();
   }
   store_batch(((C - 1) / kDecSB) * kDecSB);
-  const uint64_t wi = wq.wi;
-  const int qn = wq.qn;
-  // words taken into the bit buffer: all fetched but the prefetched group and
-  // the qn still queued
-  const int64_t used = ((int64_t)(wi - w0) - 4 - qn) * 32 - nb;
-  if (live && (bad || used > (int64_t)(w1 - w0) * 32)) atomicOr(status, ST_FORMAT);
+  // bits taken from the chunk: the words moved into the buffer less those
+  // still in it
+  const int64_t used = (int64_t)rd * 32 - nb;
+  if (live && (bad || used > (int64_t)nwc * 32)) atomicOr(status, ST_FORMAT);
 }
 
 // ------------------------------------------------------------ batched form
@@ -1157,7 +1246,7 @@ __global__ __launch_bounds__(256) void kb_chunk_words(const Job* __restrict__ jo
   const JobBlock jb = map[blockIdx.x];
   const Job& J = jobs[jb.job];
   if (job_skipped_h(J)) return;
-  chunk_words_body(J.sym, J.N, (int)kChunkSyms, J.clen, J.cw, J.lay, jb.local);
+  chunk_words_body(J.sym, J.N, (int)kChunkSyms, J.clen, J.cw, J.lay, jb.local, jb.count);
 }
 
 __global__ __launch_bounds__(1024) void kb_layout_scan(const Job* __restrict__ jobs) {
@@ -1181,7 +1270,8 @@ __global__ __launch_bounds__(256) void kb_encode(const Job* __restrict__ jobs,
   const JobBlock jb = map[blockIdx.x];
   const Job& J = jobs[jb.job];
   if (job_skipped_h(J)) return;
-  encode_body(J.sym, J.N, (int)kChunkSyms, J.code, J.clen, J.out, J.lay, jb.local, wbuf);
+  encode_body(J.sym, J.N, (int)kChunkSyms, J.code, J.clen, J.cbs.pk, J.out, J.lay, jb.local,
+              wbuf);
 }
 
 // Header, bins and result-table entries of one array (thread 0).  Constant
@@ -1281,11 +1371,17 @@ void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* 
                      cb_out_base + cb_off, lay);
 }
 
+// Each block first copies the 64 KiB length table, so it takes at least 16
+// groups of four chunks (128 KiB of symbols at C = 1024).
+uint32_t chunk_words_blocks(int64_t N, int C) {
+  const int64_t groups = ((N + C - 1) / C + 3) / 4;
+  return (uint32_t)std::max<int64_t>(1, std::min<int64_t>((groups + 15) / 16, 512));
+}
+
 void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
                         uint32_t* cw, Layout* lay, hipStream_t s) {
-  const int64_t n_chunks = (N + C - 1) / C;
-  hipLaunchKernelGGL(k_chunk_words, dim3((unsigned)((n_chunks + 3) / 4)), dim3(256), 0, s, sym,
-                     N, C, clen, cw, lay);
+  hipLaunchKernelGGL(k_chunk_words, dim3(chunk_words_blocks(N, C)), dim3(256), 0, s, sym, N, C,
+                     clen, cw, lay);
 }
 
 void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint64_t cb_off,
@@ -1303,10 +1399,11 @@ void launch_outlier_sort(const OutlierBuf& ob, uint32_t* keyA, uint32_t* valA, u
 }
 
 void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
-                   const uint8_t* clen, uint8_t* out, const Layout* lay, hipStream_t s) {
+                   const uint8_t* clen, const uint32_t* pk, uint8_t* out, const Layout* lay,
+                   hipStream_t s) {
   const int64_t n_chunks = (N + C - 1) / C;
   hipLaunchKernelGGL(k_encode, dim3((unsigned)((n_chunks + 3) / 4)), dim3(256),
-                     (size_t)4 * C * sizeof(uint32_t), s, sym, N, C, code, clen, out, lay);
+                     (size_t)4 * C * sizeof(uint32_t), s, sym, N, C, code, clen, pk, out, lay);
 }
 
 void launch_header(uint8_t* out, const Header& h, const double* q, int nq, const Layout* lay,
@@ -1326,25 +1423,49 @@ void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
   hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(1024), 0, s, cb, n_codes, t, status);
 }
 
+namespace {
+template <int RW>
+size_t decode_room() {
+  // the dynamic LDS the kernel can take on top of its static LDS (160 KiB per CU)
+  static size_t room = 0;
+  if (room == 0) {
+    hipFuncAttributes fa;
+    MGC_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_decode<RW>)));
+    const size_t r = 163840 - fa.sharedSizeBytes;
+    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_decode<RW>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)r));
+    room = r;
+  }
+  return room;
+}
+}  // namespace
+
 void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
                    uint64_t n_words, int C, int64_t N, uint64_t n_codes, const DecodeTables* t,
                    uint16_t* sym, unsigned* status, hipStream_t s) {
-  const int nthr = 64 * kDecWaves;
-  const dim3 grid((unsigned)((n_chunks + nthr - 1) / nthr));
-  const size_t dyn = ((size_t)n_codes * sizeof(uint16_t) + 15) & ~size_t(15);
-  static size_t dyn_max = 0;
-  if (dyn_max == 0) {
-    // allow the full 128 KiB table on top of the static LDS (160 KiB per CU)
-    hipFuncAttributes fa;
-    MGC_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_decode)));
-    const size_t room = 163840 - fa.sharedSizeBytes;
-    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_decode),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)room));
-    dyn_max = room;
+  // wavefronts per block: enough that one block per CU covers every chunk
+  // (one pass over the 256 CUs), at most 16; then the widest ring that fits
+  // in LDS beside the symbol table, else fewer wavefronts
+  constexpr uint64_t kCUs = 256;
+  int waves = (int)std::min<uint64_t>(16, std::max<uint64_t>(1, (n_chunks + 64 * kCUs - 1) / (64 * kCUs)));
+  const size_t tab = dec_sorted_bytes(n_codes);
+  int rw = 16;
+  while (true) {
+    const size_t room = rw == 16 ? decode_room<16>() : decode_room<8>();
+    if (tab + (size_t)waves * dec_wave_bytes(rw) <= room) break;
+    if (rw == 16) rw = 8;
+    else if (waves > 1) --waves;
+    else fail(MGC_EDEVICE, "decode table does not fit in LDS");
   }
-  if (dyn > dyn_max) fail(MGC_EDEVICE, "decode table does not fit in LDS");
-  hipLaunchKernelGGL(k_decode, grid, dim3(nthr), dyn, s, in, off_sec, words_sec, n_chunks, n_words,
-                     C, N, (uint32_t)n_codes, t, sym, status);
+  const int nthr = 64 * waves;
+  const dim3 grid((unsigned)((n_chunks + nthr - 1) / nthr));
+  const size_t dyn = tab + (size_t)waves * dec_wave_bytes(rw);
+  if (rw == 16)
+    hipLaunchKernelGGL(k_decode<16>, grid, dim3(nthr), dyn, s, in, off_sec, words_sec, n_chunks,
+                       n_words, C, N, (uint32_t)n_codes, t, sym, status);
+  else
+    hipLaunchKernelGGL(k_decode<8>, grid, dim3(nthr), dyn, s, in, off_sec, words_sec, n_chunks,
+                       n_words, C, N, (uint32_t)n_codes, t, sym, status);
 }
 
 }  // namespace mgc

@@ -46,13 +46,15 @@ void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, const Bu
 // One decomposition level: coefficients of the level's new nodes (quantised
 // to symbols when sym != nullptr, else FP64 into raw) and the restriction
 // f = (P^T M_l) G_l onto the coarse grid (fout, FP64).
+// cand: tile candidate for three-axis levels (kDecTiles3F32/F64), others fixed.
 void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* fout,
                       uint16_t* sym, double* raw, double r, const OutlierBuf& ob,
-                      unsigned* status, hipStream_t s);
+                      unsigned* status, hipStream_t s, int cand = 0);
 // Solve the coarse mass matrix along internal axis `axis` for every line of
 // x (coarse grid nc).  When sub != nullptr, x <- sub - solution.
+// cand: kThomasSeg (axis 2) or kThomasU (axes 0, 1) candidate.
 void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
-                   const double* sub, hipStream_t s);
+                   const double* sub, hipStream_t s, int cand = 0);
 // Level-0 block: values of G0 (m0 entries) quantised (sym) or copied (raw).
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
                    double r, const OutlierBuf& ob, unsigned* status, hipStream_t s);
@@ -96,6 +98,7 @@ void launch_b_encode(const Job* jobs, const JobBlock* map, uint32_t nb, hipStrea
 void launch_b_header(const Job* jobs, int n, hipStream_t s);
 // Blocks per array of the map-driven Huffman launches.
 uint32_t hist_blocks(int64_t N);
+uint32_t chunk_words_blocks(int64_t N, int C);
 constexpr uint32_t kChunkSyms = 1024;   // symbols per coded chunk (C)
 
 // ---- huffman.hip ---------------------------------------------------------
@@ -119,8 +122,11 @@ void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint
 void launch_outlier_sort(const OutlierBuf& ob, uint32_t* keyA, uint32_t* valA, uint32_t* keyB,
                          uint32_t* valB, int key_bits, uint8_t* out, Layout* lay,
                          hipStream_t s);
+// pk: packed (code << 6 | length) words from the codebook, used when the
+// longest code has at most 26 bits.
 void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
-                   const uint8_t* clen, uint8_t* out, const Layout* lay, hipStream_t s);
+                   const uint8_t* clen, const uint32_t* pk, uint8_t* out, const Layout* lay,
+                   hipStream_t s);
 // Writes the header and bins (q holds nq <= kMaxLevels + 1 host values) once
 // the layout is known; info <- {status bits, outliers, stream bytes}.
 void launch_header(uint8_t* out, const Header& h, const double* q, int nq, const Layout* lay,

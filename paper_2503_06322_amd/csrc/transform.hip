@@ -301,27 +301,68 @@ __device__ __forceinline__ bool make_tile(const LevelGeom& g, uint32_t t, uint32
 // position of each output's centre tap; subband offsets of the level.
 template <int E0, int E1, int E2, int TZ, int TY, int TX>
 struct TileTabs {
-  double wl0[E0], wr0[E0], wl1[E1], wr1[E1], wl2[E2], wr2[E2];
-  double W0[TZ][5], W1[TY][5], W2[TX][5];
+  // doubles: wl0[E0] wr0[E0] wl1[E1] wr1[E1] wl2[E2] wr2[E2] W0[TZ][5] W1[TY][5] W2[TX][5]
+  static constexpr int O_WL0 = 0, O_WR0 = E0, O_WL1 = 2 * E0, O_WR1 = 2 * E0 + E1,
+                       O_WL2 = 2 * (E0 + E1), O_WR2 = 2 * (E0 + E1) + E2,
+                       O_W0 = 2 * (E0 + E1 + E2), O_W1 = O_W0 + 5 * TZ, O_W2 = O_W1 + 5 * TY,
+                       ND = O_W2 + 5 * TX;
+  double d[ND];
   int P0[TZ], P1[TY], P2[TX];
   uint32_t soff[8];
+  __device__ double wl0(int i) const { return d[O_WL0 + i]; }
+  __device__ double wr0(int i) const { return d[O_WR0 + i]; }
+  __device__ double wl1(int i) const { return d[O_WL1 + i]; }
+  __device__ double wr1(int i) const { return d[O_WR1 + i]; }
+  __device__ double wl2(int i) const { return d[O_WL2 + i]; }
+  __device__ double wr2(int i) const { return d[O_WR2 + i]; }
+  __device__ double W0(int j, int t) const { return d[O_W0 + 5 * j + t]; }
+  __device__ double W1(int j, int t) const { return d[O_W1 + 5 * j + t]; }
+  __device__ double W2(int j, int t) const { return d[O_W2 + 5 * j + t]; }
 };
 
+// The tables are fetched as one flattened list (interpolation weights of
+// the loaded nodes when need_w, then the restriction taps of the outputs),
+// every load of a thread issued before any is used, so a tile pays one
+// memory latency for them.  (A loop of load-then-store would wait once per
+// table.)  The taps are those of P^T instead of P^T M when transpose_p.
 template <int E0, int E1, int E2, int TZ, int TY, int TX>
 __device__ void load_tabs(const LevelGeom& g, const Tile& tl, TileTabs<E0, E1, E2, TZ, TY, TX>& tb,
                           bool need_w, bool transpose_p = false) {
+  constexpr int MAXN = 2 * (E0 + E1 + E2) + 5 * (TZ + TY + TX);
+  constexpr int NT = (MAXN + 255) / 256;
   const int tid = threadIdx.x;
-  if (need_w) {
-    for (int i = tid; i < tl.ext[0]; i += 256) { tb.wl0[i] = g.ax[0].wl[tl.lo[0] + i]; tb.wr0[i] = g.ax[0].wr[tl.lo[0] + i]; }
-    for (int i = tid; i < tl.ext[1]; i += 256) { tb.wl1[i] = g.ax[1].wl[tl.lo[1] + i]; tb.wr1[i] = g.ax[1].wr[tl.lo[1] + i]; }
-    for (int i = tid; i < tl.ext[2]; i += 256) { tb.wl2[i] = g.ax[2].wl[tl.lo[2] + i]; tb.wr2[i] = g.ax[2].wr[tl.lo[2] + i]; }
+  const int n0 = tl.ext[0], n1 = tl.ext[1], n2 = tl.ext[2];
+  // segment sizes, sources and destinations (offsets in the doubles of tb)
+  const int sz[9] = {need_w ? n0 : 0, need_w ? n0 : 0, need_w ? n1 : 0, need_w ? n1 : 0,
+                     need_w ? n2 : 0, need_w ? n2 : 0, 5 * tl.tk[0], 5 * tl.tk[1], 5 * tl.tk[2]};
+  const double* src[9] = {g.ax[0].wl + tl.lo[0], g.ax[0].wr + tl.lo[0], g.ax[1].wl + tl.lo[1],
+                          g.ax[1].wr + tl.lo[1], g.ax[2].wl + tl.lo[2], g.ax[2].wr + tl.lo[2],
+                          (transpose_p ? g.ax[0].WP : g.ax[0].W) + 5 * tl.c0[0],
+                          (transpose_p ? g.ax[1].WP : g.ax[1].W) + 5 * tl.c0[1],
+                          (transpose_p ? g.ax[2].WP : g.ax[2].W) + 5 * tl.c0[2]};
+  using TT = TileTabs<E0, E1, E2, TZ, TY, TX>;
+  constexpr int dof[9] = {TT::O_WL0, TT::O_WR0, TT::O_WL1, TT::O_WR1, TT::O_WL2,
+                          TT::O_WR2, TT::O_W0, TT::O_W1, TT::O_W2};
+  double v[NT];
+  int dst[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    int i = tid + 256 * u;
+    dst[u] = -1;
+    const double* sp = src[8];  // a valid address for threads with no entry
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      if (dst[u] < 0 && i < sz[k]) {
+        dst[u] = dof[k] + i;
+        sp = src[k] + i;
+      }
+      if (dst[u] < 0) i -= sz[k];
+    }
+    v[u] = *sp;
   }
-  const double* W0 = transpose_p ? g.ax[0].WP : g.ax[0].W;
-  const double* W1 = transpose_p ? g.ax[1].WP : g.ax[1].W;
-  const double* W2 = transpose_p ? g.ax[2].WP : g.ax[2].W;
-  for (int i = tid; i < 5 * tl.tk[0]; i += 256) tb.W0[i / 5][i % 5] = W0[5 * tl.c0[0] + i];
-  for (int i = tid; i < 5 * tl.tk[1]; i += 256) tb.W1[i / 5][i % 5] = W1[5 * tl.c0[1] + i];
-  for (int i = tid; i < 5 * tl.tk[2]; i += 256) tb.W2[i / 5][i % 5] = W2[5 * tl.c0[2] + i];
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+    if (dst[u] >= 0) tb.d[dst[u]] = v[u];
   for (int i = tid; i < tl.tk[0]; i += 256) tb.P0[i] = (int)(cpos32(tl.c0[0] + i, tl.nf[0]) - tl.lo[0]);
   for (int i = tid; i < tl.tk[1]; i += 256) tb.P1[i] = (int)(cpos32(tl.c0[1] + i, tl.nf[1]) - tl.lo[1]);
   for (int i = tid; i < tl.tk[2]; i += 256) tb.P2[i] = (int)(cpos32(tl.c0[2] + i, tl.nf[2]) - tl.lo[2]);
@@ -339,6 +380,53 @@ __device__ __forceinline__ uint32_t stream_pos(const LevelGeom& g, const Tile& t
   const uint32_t j1 = n1 ? (i1 >> 1) : cidx32(i1, tl.nf[1]);
   const uint32_t j2 = n2 ? (i2 >> 1) : cidx32(i2, tl.nf[2]);
   return (uint32_t)g.level_off + soff[m] + (j0 * e1 + j1) * e2 + j2;
+}
+
+// Offset of subband m from eight uniform values (no indexing of a register
+// array, which would go through scratch memory).
+__device__ __forceinline__ uint32_t sel8(const uint32_t (&so)[8], int m) {
+  const uint32_t a = (m & 1) ? so[1] : so[0], b = (m & 1) ? so[3] : so[2];
+  const uint32_t c = (m & 1) ? so[5] : so[4], d = (m & 1) ? so[7] : so[6];
+  const uint32_t ab = (m & 2) ? b : a, cd = (m & 2) ? d : c;
+  return (m & 4) ? cd : ab;
+}
+
+// stream_pos with the subband offsets held in registers (no LDS table).
+__device__ __forceinline__ uint32_t stream_pos_r(const LevelGeom& g, const Tile& tl,
+                                                 const uint32_t (&so)[8], uint32_t i0,
+                                                 uint32_t i1, uint32_t i2, bool n0, bool n1,
+                                                 bool n2) {
+  const int m = (n0 ? (1 << g.bit[0]) : 0) | (n1 ? (1 << g.bit[1]) : 0) | (n2 ? (1 << g.bit[2]) : 0);
+  const uint32_t e1 = n1 ? tl.nf[1] - tl.nc[1] : tl.nc[1];
+  const uint32_t e2 = n2 ? tl.nf[2] - tl.nc[2] : tl.nc[2];
+  const uint32_t j0 = n0 ? (i0 >> 1) : cidx32(i0, tl.nf[0]);
+  const uint32_t j1 = n1 ? (i1 >> 1) : cidx32(i1, tl.nf[1]);
+  const uint32_t j2 = n2 ? (i2 >> 1) : cidx32(i2, tl.nf[2]);
+  return (uint32_t)g.level_off + sel8(so, m) + (j0 * e1 + j1) * e2 + j2;
+}
+
+__device__ __forceinline__ void subband_offsets(const LevelGeom& g, uint32_t (&so)[8]) {
+  so[0] = 0;
+#pragma unroll
+  for (int m = 1; m < 8; ++m) so[m] = (uint32_t)g.sub_off[m];
+}
+
+// Dequantised coefficient from an already loaded symbol v at stream position
+// pos (escaped values: binary search in the sorted outlier positions).
+__device__ __forceinline__ double dequant(const CoeffSrc& s, uint32_t v, uint32_t pos, double q) {
+  int64_t k;
+  if (v != 0) {
+    k = (int64_t)v - 32768;
+  } else {
+    int64_t lo = 0, hi = s.n_out;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (s.opos[mid] < (uint64_t)pos) lo = mid + 1;
+      else hi = mid;
+    }
+    k = (lo < s.n_out && s.opos[lo] == (uint64_t)pos) ? s.oval[lo] : 0;
+  }
+  return (double)k * q;
 }
 
 // The separable restriction (P^T M_l along x, then y, then z) of a fine tile
@@ -371,7 +459,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
 #pragma unroll
       for (int d = 0; d < 5; ++d) {
         f[d] = min(max(p + d - 2, 0), last);
-        w[d] = tb.W2[cx][d];
+        w[d] = tb.W2(cx, d);
       }
       for (int rw = rsub; rw < rows; rw += RS) {
         const int z = (int)div_small((uint32_t)rw, m1), y = rw - z * tl.ext[1];
@@ -398,7 +486,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
 #pragma unroll
       for (int d = 0; d < 5; ++d) {
         f[d] = min(max(p + d - 2, 0), last);
-        w[d] = tb.W1[cy][d];
+        w[d] = tb.W1(cy, d);
       }
       for (int z = z0; z < tl.ext[0]; z += G) {
         const double* col = A + z * E1 * TX + cx;
@@ -419,7 +507,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
         double acc = 0.0;
 #pragma unroll
         for (int d = 0; d < 5; ++d)
-          acc += tb.W1[cy][d] * A[(z * E1 + min(max(p + d - 2, 0), last)) * TX + cx];
+          acc += tb.W1(cy, d) * A[(z * E1 + min(max(p + d - 2, 0), last)) * TX + cx];
         B[(z * TY + cy) * TX + cx] = acc;
       }
     }
@@ -438,7 +526,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
           double acc = 0.0;
 #pragma unroll
           for (int d = 0; d < 5; ++d)
-            acc += tb.W0[cz][d] * B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx];
+            acc += tb.W0(cz, d) * B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx];
           const size_t o = ((size_t)(tl.c0[0] + cz) * tl.nc[1] + tl.c0[1] + cy) * tl.nc[2] +
                            tl.c0[2] + cx;
           fout[o] = acc;
@@ -456,12 +544,78 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
           double acc = 0.0;
 #pragma unroll
           for (int d = 0; d < 5; ++d)
-            acc += tb.W0[cz][d] * B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx];
+            acc += tb.W0(cz, d) * B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx];
           fout[ro + cx] = acc;
           if (fout2) fout2[ro + cx] = acc;
         }
       }
     }
+  }
+}
+
+// ------------------------------------------------------- lerp by cells
+// Cell J (coarse indices J0, J1, J2) owns the fine nodes at cpos(J) and, on
+// each axis where 2J+1 is a new node, 2J+1: up to seven new nodes, whose
+// coefficients are the value minus the multilinear interpolant from the
+// cell's corners cpos(J) and cpos(J+1) = 2J+2 (the coarse nodes around
+// them).  The interpolant nests the axes as x innermost, then y, then z;
+// along an axis where the node is not new the weights would be (1, 0), which
+// reproduces the same value, so those factors are simply left out.  The
+// seven stream positions share (J0*e1 + J1)*e2 + J2 with per-subband extents,
+// and consecutive threads take consecutive cells along x, so each subband's
+// stores are contiguous.
+template <typename Tin, int TZ, int TY, int TX, int E1, int E2, bool QUANT, typename TT>
+__device__ __forceinline__ void lerp_cells(const Tin* tile, const Tile& tl, const TT& tb,
+                                           const LevelGeom& g, uint16_t* __restrict__ sym,
+                                           double* __restrict__ raw, double r,
+                                           const OutlierBuf& ob, unsigned* __restrict__ status) {
+  constexpr int NC = TZ * TY * TX;
+  const uint32_t e1c = tl.nc[1], e1n = tl.nf[1] - tl.nc[1];
+  const uint32_t e2c = tl.nc[2], e2n = tl.nf[2] - tl.nc[2];
+  const uint32_t lvl = (uint32_t)g.level_off;
+  const int m0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, m1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
+            m2 = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
+  auto T = [&](int z, int y, int x) -> double { return (double)tile[(z * E1 + y) * E2 + x]; };
+  auto emit = [&](uint32_t pos, double v) {
+    if (QUANT) emit_q(pos, v, r, sym, ob, status);
+    else raw[pos] = v;
+  };
+  for (int e = threadIdx.x; e < NC; e += 256) {
+    const int cx = e % TX, rest = e / TX, cy = rest % TY, cz = rest / TY;
+    if (cz >= tl.tk[0] || cy >= tl.tk[1] || cx >= tl.tk[2]) continue;
+    const uint32_t J0 = tl.c0[0] + cz, J1 = tl.c0[1] + cy, J2 = tl.c0[2] + cx;
+    const bool h0 = 2 * J0 + 1 < tl.nf[0] - 1, h1 = 2 * J1 + 1 < tl.nf[1] - 1,
+               h2 = 2 * J2 + 1 < tl.nf[2] - 1;
+    if (!(h0 || h1 || h2)) continue;
+    // tile-relative fine positions: cell origin p, new node p+1, next corner
+    const int p0 = (int)(cpos32(J0, tl.nf[0]) - tl.lo[0]);
+    const int p1 = (int)(cpos32(J1, tl.nf[1]) - tl.lo[1]);
+    const int p2 = (int)(cpos32(J2, tl.nf[2]) - tl.lo[2]);
+    const int s0 = h0 ? p0 + 2 : p0, s1 = h1 ? p1 + 2 : p1, s2 = h2 ? p2 + 2 : p2;
+    const int q0 = h0 ? p0 + 1 : p0, q1 = h1 ? p1 + 1 : p1, q2 = h2 ? p2 + 1 : p2;
+    const double wz0 = tb.wl0(q0), wz1 = tb.wr0(q0);
+    const double wy0 = tb.wl1(q1), wy1 = tb.wr1(q1);
+    const double wx0 = tb.wl2(q2), wx1 = tb.wr2(q2);
+    const double c000 = T(p0, p1, p2), c001 = T(p0, p1, s2), c010 = T(p0, s1, p2),
+                 c011 = T(p0, s1, s2), c100 = T(s0, p1, p2), c101 = T(s0, p1, s2),
+                 c110 = T(s0, s1, p2), c111 = T(s0, s1, s2);
+    const double ix00 = wx0 * c000 + wx1 * c001, ix01 = wx0 * c010 + wx1 * c011;
+    const double ix10 = wx0 * c100 + wx1 * c101, ix11 = wx0 * c110 + wx1 * c111;
+    const uint32_t base_cc = (J0 * e1c + J1) * e2c + J2, base_cn = (J0 * e1c + J1) * e2n + J2;
+    const uint32_t base_nc = (J0 * e1n + J1) * e2c + J2, base_nn = (J0 * e1n + J1) * e2n + J2;
+    if (h2) emit(lvl + tb.soff[m2] + base_cn, T(p0, p1, q2) - ix00);
+    if (h1) emit(lvl + tb.soff[m1] + base_nc, T(p0, q1, p2) - (wy0 * c000 + wy1 * c010));
+    if (h1 && h2)
+      emit(lvl + tb.soff[m1 | m2] + base_nn, T(p0, q1, q2) - (wy0 * ix00 + wy1 * ix01));
+    if (h0) emit(lvl + tb.soff[m0] + base_cc, T(q0, p1, p2) - (wz0 * c000 + wz1 * c100));
+    if (h0 && h2)
+      emit(lvl + tb.soff[m0 | m2] + base_cn, T(q0, p1, q2) - (wz0 * ix00 + wz1 * ix10));
+    if (h0 && h1)
+      emit(lvl + tb.soff[m0 | m1] + base_nc,
+           T(q0, q1, p2) - (wz0 * (wy0 * c000 + wy1 * c010) + wz1 * (wy0 * c100 + wy1 * c110)));
+    if (h0 && h1 && h2)
+      emit(lvl + tb.soff[m0 | m1 | m2] + base_nn,
+           T(q0, q1, q2) - (wz0 * (wy0 * ix00 + wy1 * ix01) + wz1 * (wy0 * ix10 + wy1 * ix11)));
   }
 }
 
@@ -488,76 +642,36 @@ __device__ __forceinline__ void dec_level_body(const Tin* __restrict__ G, const 
   const uint32_t tiles_y = (uint32_t)((g.nc[1] + TY - 1) / TY);
   Tile tl;
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
-  load_tabs(g, tl, tb, MODE != 2, MODE == 2);
   const int tid = threadIdx.x;
   // load the fine tile: flattened over the block, every load of a thread in
-  // flight before the first LDS store
+  // flight (with the operator tables' loads behind them) before the first
+  // LDS store; offsets are 32-bit (arrays hold fewer than 2^32 values)
   {
     constexpr int NLD = (E0 * E1 * E2 + 255) / 256;
     const int e12 = tl.ext[1] * tl.ext[2], n_ld = tl.ext[0] * e12;
     const uint64_t m12 = div_magic((uint32_t)e12), m2 = div_magic((uint32_t)tl.ext[2]);
     const Tin* base = G + ((size_t)tl.lo[0] * tl.nf[1] + tl.lo[1]) * tl.nf[2] + tl.lo[2];
-    const size_t pz = (size_t)tl.nf[1] * tl.nf[2], py = tl.nf[2];
+    const uint32_t pz = tl.nf[1] * tl.nf[2], py = tl.nf[2];
     Tin v[NLD];
     int dst[NLD];
 #pragma unroll
     for (int u = 0; u < NLD; ++u) {
-      const int e = u * 256 + tid;
-      dst[u] = -1;
-      if (e < n_ld) {
-        const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
-        const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
-        v[u] = base[z * pz + y * py + x];
-        dst[u] = (z * E1 + y) * E2 + x;
-      }
+      const int e = min(u * 256 + tid, n_ld - 1);
+      const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
+      const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
+      v[u] = base[(uint32_t)z * pz + (uint32_t)y * py + (uint32_t)x];
+      dst[u] = u * 256 + tid < n_ld ? (z * E1 + y) * E2 + x : -1;
     }
+    load_tabs(g, tl, tb, MODE != 2, MODE == 2);
 #pragma unroll
     for (int u = 0; u < NLD; ++u)
       if (dst[u] >= 0) tile[dst[u]] = v[u];
   }
   __syncthreads();
 
-  // lerp + quantise the owned new nodes
-  if (MODE != 2) {
-    constexpr int OX = 2 * TX;
-    constexpr int CW = OX < 64 ? OX : 64;
-    constexpr int RS = 256 / CW;
-    const int col0 = tid % CW, rsub = tid / CW;
-    const int rows = tl.oext[0] * tl.oext[1];
-    const uint64_t m1 = div_magic((uint32_t)max(tl.oext[1], 1));
-    for (int rw = rsub; rw < rows; rw += RS) {
-      const int a = (int)div_small((uint32_t)rw, m1), b = rw - a * tl.oext[1];
-      const int z = tl.olo[0] + a, y = tl.olo[1] + b;
-      const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y;
-      const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]);
-      const double wz0 = n0 ? tb.wl0[z] : 1.0, wz1 = n0 ? tb.wr0[z] : 0.0;
-      const double wy0 = n1 ? tb.wl1[y] : 1.0, wy1 = n1 ? tb.wr1[y] : 0.0;
-      const int zl = n0 ? z - 1 : z, zh = n0 ? z + 1 : z;
-      const int yl = n1 ? y - 1 : y, yh = n1 ? y + 1 : y;
-      const Tin* r00 = tile + (zl * E1 + yl) * E2;
-      const Tin* r01 = tile + (zl * E1 + yh) * E2;
-      const Tin* r10 = tile + (zh * E1 + yl) * E2;
-      const Tin* r11 = tile + (zh * E1 + yh) * E2;
-      const Tin* rc = tile + (z * E1 + y) * E2;
-      for (int c = col0; c < tl.oext[2]; c += CW) {
-        const int x = tl.olo[2] + c;
-        const uint32_t i2 = tl.lo[2] + x;
-        const bool n2 = is_new32(i2, tl.nf[2]);
-        if (!(n0 || n1 || n2)) continue;
-        const double wx0 = n2 ? tb.wl2[x] : 1.0, wx1 = n2 ? tb.wr2[x] : 0.0;
-        const int xl = n2 ? x - 1 : x, xh = n2 ? x + 1 : x;
-        const double i00 = wx0 * (double)r00[xl] + wx1 * (double)r00[xh];
-        const double i01 = wx0 * (double)r01[xl] + wx1 * (double)r01[xh];
-        const double i10 = wx0 * (double)r10[xl] + wx1 * (double)r10[xh];
-        const double i11 = wx0 * (double)r11[xl] + wx1 * (double)r11[xh];
-        const double interp = wz0 * (wy0 * i00 + wy1 * i01) + wz1 * (wy0 * i10 + wy1 * i11);
-        const double cval = (double)rc[x] - interp;
-        const uint32_t pos = stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2);
-        if (MODE == 0) emit_q(pos, cval, r, sym, ob, status);
-        else raw[pos] = cval;
-      }
-    }
-  }
+  // lerp + quantise the owned new nodes, one coarse cell (the 2x2x2 fine
+  // nodes a coarse node owns) at a time
+  if (MODE != 2) lerp_cells<Tin, TZ, TY, TX, E1, E2, MODE == 0>(tile, tl, tb, g, sym, raw, r, ob, status);
   // mass_trans (or P^T for the adjoint): separable restriction to the coarse outputs
   restrict_tile(tile, A, reinterpret_cast<double*>(smem), tl, tb, fout, MODE == 2 ? raw : nullptr);
 }
@@ -578,12 +692,19 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
 // --------------------------------------------- recomposition of one level
 // f = (P^T M_l) c_l: the tile holds the dequantised coefficients (zero at the
 // coarse nodes); then the same separable restriction.
+// The tile of dequantised coefficients (zero at coarse nodes) is assembled by
+// coarse cells (see lerp_cells): the cells whose nodes meet the loaded region
+// are the tile's own plus one more on each side of each active axis.  Every
+// coefficient load of a thread (coalesced per subband: consecutive threads,
+// consecutive cells) and the tables' loads are in flight before any is used.
 template <int TZ, int TY, int TX, bool RAW>
 __device__ __forceinline__ void rec_restrict_body(const LevelGeom& g, const CoeffSrc& src,
                                                   const double q, double* __restrict__ fout,
                                                   uint32_t t) {
   constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
   static_assert(E0 * TY * TX <= E0 * E1 * E2, "B aliases the tile");
+  constexpr int X0 = TZ == 1 ? 1 : TZ + 2, X1 = TY == 1 ? 1 : TY + 2, X2 = TX == 1 ? 1 : TX + 2;
+  constexpr int NX = X0 * X1 * X2, NCR = (NX + 255) / 256;
   __shared__ double tile[E0 * E1 * E2];
   __shared__ double A[E0 * E1 * TX];
   __shared__ TileTabs<E0, E1, E2, TZ, TY, TX> tb;
@@ -591,38 +712,65 @@ __device__ __forceinline__ void rec_restrict_body(const LevelGeom& g, const Coef
   const uint32_t tiles_y = (uint32_t)((g.nc[1] + TY - 1) / TY);
   Tile tl;
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
-  load_tabs(g, tl, tb, false);
-  __syncthreads();
   const int tid = threadIdx.x;
-  // dequantised coefficients of the loaded region (zero at coarse nodes),
-  // flattened over the block with every symbol load of a thread in flight
-  {
-    constexpr int NLD = (E0 * E1 * E2 + 255) / 256;
-    const int e12 = tl.ext[1] * tl.ext[2], n_ld = tl.ext[0] * e12;
-    const uint64_t m12 = div_magic((uint32_t)e12), m2 = div_magic((uint32_t)tl.ext[2]);
-    uint32_t pos[NLD];
-    int dst[NLD];
+  uint32_t so[8];
+  subband_offsets(g, so);
+  const uint32_t e1c = tl.nc[1], e1n = tl.nf[1] - tl.nc[1];
+  const uint32_t e2c = tl.nc[2], e2n = tl.nf[2] - tl.nc[2];
+  const uint32_t lvl = (uint32_t)g.level_off;
+  const int m0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, m1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
+            m2 = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
+  uint32_t pos[NCR][8], sv[NCR][8];
+  double rv[NCR][8];
+  int dst[NCR][8];
 #pragma unroll
-    for (int u = 0; u < NLD; ++u) {
-      const int e = u * 256 + tid;
-      dst[u] = -1;
-      pos[u] = 0xFFFFFFFFu;
-      if (e < n_ld) {
-        const int z = (int)div_small((uint32_t)e, m12), r = e - z * e12;
-        const int y = (int)div_small((uint32_t)r, m2), x = r - y * tl.ext[2];
-        const uint32_t i0 = tl.lo[0] + z, i1 = tl.lo[1] + y, i2 = tl.lo[2] + x;
-        const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]),
-                   n2 = is_new32(i2, tl.nf[2]);
-        dst[u] = (z * E1 + y) * E2 + x;
-        if (n0 || n1 || n2) pos[u] = stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2);
+  for (int u = 0; u < NCR; ++u) {
+    const int eu = u * 256 + tid, e = min(eu, NX - 1);
+    const int ex = e % X2, rest = e / X2, ey = rest % X1, ez = rest / X1;
+    const int J0 = (int)tl.c0[0] + ez - (TZ == 1 ? 0 : 1);
+    const int J1 = (int)tl.c0[1] + ey - (TY == 1 ? 0 : 1);
+    const int J2 = (int)tl.c0[2] + ex - (TX == 1 ? 0 : 1);
+    const bool live = eu < NX && J0 >= 0 && J1 >= 0 && J2 >= 0 && J0 < (int)tl.nc[0] &&
+                      J1 < (int)tl.nc[1] && J2 < (int)tl.nc[2];
+    const uint32_t j0 = live ? J0 : 0, j1 = live ? J1 : 0, j2 = live ? J2 : 0;
+    const bool h0 = live && 2 * j0 + 1 < tl.nf[0] - 1, h1 = live && 2 * j1 + 1 < tl.nf[1] - 1,
+               h2 = live && 2 * j2 + 1 < tl.nf[2] - 1;
+    // tile-relative fine index of the cell origin and of its new node
+    const int p0 = (int)cpos32(j0, tl.nf[0]) - (int)tl.lo[0];
+    const int p1 = (int)cpos32(j1, tl.nf[1]) - (int)tl.lo[1];
+    const int p2 = (int)cpos32(j2, tl.nf[2]) - (int)tl.lo[2];
+    const bool iP0 = p0 >= 0 && p0 < tl.ext[0], iP1 = p1 >= 0 && p1 < tl.ext[1],
+               iP2 = p2 >= 0 && p2 < tl.ext[2];
+    const bool iN0 = h0 && p0 + 1 >= 0 && p0 + 1 < tl.ext[0];
+    const bool iN1 = h1 && p1 + 1 >= 0 && p1 + 1 < tl.ext[1];
+    const bool iN2 = h2 && p2 + 1 >= 0 && p2 + 1 < tl.ext[2];
+    const uint32_t bcc = (j0 * e1c + j1) * e2c + j2, bcn = (j0 * e1c + j1) * e2n + j2;
+    const uint32_t bnc = (j0 * e1n + j1) * e2c + j2, bnn = (j0 * e1n + j1) * e2n + j2;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool nx = k & 1, ny = k & 2, nz = k & 4;
+      const bool ok = live && (nx ? iN2 : iP2) && (ny ? iN1 : iP1) && (nz ? iN0 : iP0);
+      const int z = p0 + (nz ? 1 : 0), y = p1 + (ny ? 1 : 0), x = p2 + (nx ? 1 : 0);
+      dst[u][k] = ok ? (z * E1 + y) * E2 + x : -1;
+      const int m = (nz ? m0 : 0) | (ny ? m1 : 0) | (nx ? m2 : 0);
+      const uint32_t bse = ny ? (nx ? bnn : bnc) : (nx ? bcn : bcc);
+      pos[u][k] = k != 0 && ok ? lvl + sel8(so, m) + bse : 0u;
+      if (k != 0) {
+        if (RAW) rv[u][k] = src.raw[pos[u][k]];
+        else sv[u][k] = src.sym[pos[u][k]];
       }
     }
-    double v[NLD];
+  }
+  load_tabs(g, tl, tb, false);
 #pragma unroll
-    for (int u = 0; u < NLD; ++u) v[u] = pos[u] != 0xFFFFFFFFu ? coeff_at<RAW>(src, pos[u], q) : 0.0;
+  for (int u = 0; u < NCR; ++u) {
 #pragma unroll
-    for (int u = 0; u < NLD; ++u)
-      if (dst[u] >= 0) tile[dst[u]] = v[u];
+    for (int k = 0; k < 8; ++k) {
+      if (dst[u][k] < 0) continue;
+      double v = 0.0;
+      if (k != 0) v = RAW ? rv[u][k] : dequant(src, sv[u][k], pos[u][k], q);
+      tile[dst[u][k]] = v;
+    }
   }
   __syncthreads();
   restrict_tile(tile, A, tile, tl, tb, fout);
@@ -640,66 +788,122 @@ __global__ __launch_bounds__(256) void k_rec_restrict(const LevelGeom g, const C
 // G_l = P Gc + c_l on the tile's owned fine nodes; the coarse values the tile
 // needs (its coarse outputs plus one more per axis) are staged in LDS.
 // SRC: 0 dequantised symbols, 1 FP64 coefficients, 2 none (plain P Gc).
+// Per coarse cell (see lerp_cells): the cell's coarse value and, at its new
+// nodes, the multilinear interpolant of its corners plus the coefficient.
+// The coarse values the tile needs (its cells and one more per axis) are
+// staged in LDS; every global load (coarse values, coefficients, weights)
+// is issued before any is used.
 template <typename Tout, int TZ, int TY, int TX, int SRC>
 __device__ __forceinline__ void rec_interp_body(const double* __restrict__ Gc, const LevelGeom& g,
                                                 const CoeffSrc& src, const double q,
                                                 Tout* __restrict__ out, uint32_t t) {
   constexpr int E0 = Ext<TZ>::v, E1 = Ext<TY>::v, E2 = Ext<TX>::v;
   constexpr int C0 = TZ == 1 ? 1 : TZ + 1, C1 = TY == 1 ? 1 : TY + 1, C2 = TX == 1 ? 1 : TX + 1;
+  constexpr int NC = TZ * TY * TX, NCELL = (NC + 255) / 256;
   __shared__ double gc[C0 * C1 * C2];
   __shared__ TileTabs<E0, E1, E2, TZ, TY, TX> tb;
   const uint32_t tiles_x = (uint32_t)((g.nc[2] + TX - 1) / TX);
   const uint32_t tiles_y = (uint32_t)((g.nc[1] + TY - 1) / TY);
   Tile tl;
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
-  load_tabs(g, tl, tb, true);
   const int tid = threadIdx.x;
+  uint32_t so[8];
+  subband_offsets(g, so);
+  // 1. coarse values
+  constexpr int NGC = (C0 * C1 * C2 + 255) / 256;
   int ce[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) ce[k] = (int)min<uint32_t>(tl.tk[k] + 1, tl.nc[k] - tl.c0[k]);
-  for (int i = tid; i < ce[0] * ce[1] * ce[2]; i += 256) {
-    const int a = i / (ce[1] * ce[2]), rem = i - a * ce[1] * ce[2], b = rem / ce[2], c = rem - b * ce[2];
-    gc[(a * C1 + b) * C2 + c] =
-        Gc[((size_t)(tl.c0[0] + a) * tl.nc[1] + tl.c0[1] + b) * tl.nc[2] + tl.c0[2] + c];
+  const int c12 = ce[1] * ce[2], n_gc = ce[0] * c12;
+  const uint64_t mc12 = div_magic((uint32_t)c12), mc2 = div_magic((uint32_t)ce[2]);
+  double gv[NGC];
+  int gdst[NGC];
+#pragma unroll
+  for (int u = 0; u < NGC; ++u) {
+    const int iu = u * 256 + tid, i = min(iu, n_gc - 1);
+    const int a = (int)div_small((uint32_t)i, mc12), rem = i - a * c12;
+    const int b = (int)div_small((uint32_t)rem, mc2), c = rem - b * ce[2];
+    gv[u] = Gc[((tl.c0[0] + a) * tl.nc[1] + tl.c0[1] + b) * tl.nc[2] + tl.c0[2] + c];
+    gdst[u] = iu < n_gc ? (a * C1 + b) * C2 + c : -1;
   }
-  __syncthreads();
-  constexpr int OX = 2 * TX;
-  constexpr int CW = OX < 64 ? OX : 64;
-  constexpr int RS = 256 / CW;
-  const int col0 = tid % CW, rsub = tid / CW;
-  const int rows = tl.oext[0] * tl.oext[1];
-  const uint64_t m1 = div_magic((uint32_t)max(tl.oext[1], 1));
-  for (int rw = rsub; rw < rows; rw += RS) {
-    const int a = (int)div_small((uint32_t)rw, m1), b = rw - a * tl.oext[1];
-    const uint32_t i0 = 2 * tl.c0[0] + a, i1 = 2 * tl.c0[1] + b;
-    const bool n0 = is_new32(i0, tl.nf[0]), n1 = is_new32(i1, tl.nf[1]);
-    const int z = tl.olo[0] + a, y = tl.olo[1] + b;   // fine index relative to lo (weights)
-    const int j0 = (int)((n0 ? (i0 >> 1) : cidx32(i0, tl.nf[0])) - tl.c0[0]);
-    const int j1 = (int)((n1 ? (i1 >> 1) : cidx32(i1, tl.nf[1])) - tl.c0[1]);
-    const double wz0 = n0 ? tb.wl0[z] : 1.0, wz1 = n0 ? tb.wr0[z] : 0.0;
-    const double wy0 = n1 ? tb.wl1[y] : 1.0, wy1 = n1 ? tb.wr1[y] : 0.0;
-    const int jz1 = n0 ? j0 + 1 : j0, jy1 = n1 ? j1 + 1 : j1;
-    const double* g00 = gc + (j0 * C1 + j1) * C2;
-    const double* g01 = gc + (j0 * C1 + jy1) * C2;
-    const double* g10 = gc + (jz1 * C1 + j1) * C2;
-    const double* g11 = gc + (jz1 * C1 + jy1) * C2;
-    Tout* orow = out + ((size_t)i0 * tl.nf[1] + i1) * tl.nf[2] + 2 * tl.c0[2];
-    for (int c = col0; c < tl.oext[2]; c += CW) {
-      const uint32_t i2 = 2 * tl.c0[2] + c;
-      const bool n2 = is_new32(i2, tl.nf[2]);
-      const int x = tl.olo[2] + c;
-      const int j2 = (int)((n2 ? (i2 >> 1) : cidx32(i2, tl.nf[2])) - tl.c0[2]);
-      const int jx1 = n2 ? j2 + 1 : j2;
-      const double wx0 = n2 ? tb.wl2[x] : 1.0, wx1 = n2 ? tb.wr2[x] : 0.0;
-      const double v00 = wx0 * g00[j2] + wx1 * g00[jx1];
-      const double v01 = wx0 * g01[j2] + wx1 * g01[jx1];
-      const double v10 = wx0 * g10[j2] + wx1 * g10[jx1];
-      const double v11 = wx0 * g11[j2] + wx1 * g11[jx1];
-      double v = wz0 * (wy0 * v00 + wy1 * v01) + wz1 * (wy0 * v10 + wy1 * v11);
-      if (SRC != 2 && (n0 || n1 || n2))
-        v += coeff_at<SRC == 1>(src, stream_pos(g, tl, tb.soff, i0, i1, i2, n0, n1, n2), q);
-      orow[c] = (Tout)v;
+  // 2. coefficients of the cells' new nodes (node k: bit 0 x, bit 1 y, bit 2 z new)
+  const uint32_t e1c = tl.nc[1], e1n = tl.nf[1] - tl.nc[1];
+  const uint32_t e2c = tl.nc[2], e2n = tl.nf[2] - tl.nc[2];
+  const uint32_t lvl = (uint32_t)g.level_off;
+  const int m0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, m1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
+            m2 = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
+  uint32_t cpos[NCELL][8], csv[NCELL][8];
+  double crv[NCELL][8];
+#pragma unroll
+  for (int u = 0; u < NCELL; ++u) {
+    const int e = min(u * 256 + tid, NC - 1);
+    const int cx = e % TX, rest = e / TX, cy = rest % TY, cz = rest / TY;
+    const uint32_t J0 = tl.c0[0] + cz, J1 = tl.c0[1] + cy, J2 = tl.c0[2] + cx;
+    const bool live = u * 256 + tid < NC && cz < tl.tk[0] && cy < tl.tk[1] && cx < tl.tk[2];
+    const bool h0 = live && 2 * J0 + 1 < tl.nf[0] - 1, h1 = live && 2 * J1 + 1 < tl.nf[1] - 1,
+               h2 = live && 2 * J2 + 1 < tl.nf[2] - 1;
+    const uint32_t bcc = (J0 * e1c + J1) * e2c + J2, bcn = (J0 * e1c + J1) * e2n + J2;
+    const uint32_t bnc = (J0 * e1n + J1) * e2c + J2, bnn = (J0 * e1n + J1) * e2n + J2;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      const bool nx = k & 1, ny = k & 2, nz = k & 4;
+      const bool ok = (!nx || h2) && (!ny || h1) && (!nz || h0) && live;
+      const int m = (nz ? m0 : 0) | (ny ? m1 : 0) | (nx ? m2 : 0);
+      const uint32_t bse = ny ? (nx ? bnn : bnc) : (nx ? bcn : bcc);
+      cpos[u][k] = SRC != 2 && ok ? lvl + sel8(so, m) + bse : 0u;
+      if (SRC == 1) crv[u][k] = src.raw[cpos[u][k]];
+      if (SRC == 0) csv[u][k] = src.sym[cpos[u][k]];
     }
+  }
+  // 3. interpolation weights
+  load_tabs(g, tl, tb, true);
+#pragma unroll
+  for (int u = 0; u < NGC; ++u)
+    if (gdst[u] >= 0) gc[gdst[u]] = gv[u];
+  __syncthreads();
+  // 4. outputs
+  auto G = [&](int a, int b, int c) -> double { return gc[(a * C1 + b) * C2 + c]; };
+#pragma unroll
+  for (int u = 0; u < NCELL; ++u) {
+    const int e = u * 256 + tid;
+    if (e >= NC) break;
+    const int cx = e % TX, rest = e / TX, cy = rest % TY, cz = rest / TY;
+    if (cz >= tl.tk[0] || cy >= tl.tk[1] || cx >= tl.tk[2]) continue;
+    const uint32_t J0 = tl.c0[0] + cz, J1 = tl.c0[1] + cy, J2 = tl.c0[2] + cx;
+    const bool h0 = 2 * J0 + 1 < tl.nf[0] - 1, h1 = 2 * J1 + 1 < tl.nf[1] - 1,
+               h2 = 2 * J2 + 1 < tl.nf[2] - 1;
+    const uint32_t P0 = cpos32(J0, tl.nf[0]), P1 = cpos32(J1, tl.nf[1]), P2 = cpos32(J2, tl.nf[2]);
+    // weights of the new nodes (tile-relative fine index of 2J+1)
+    const int r0 = (int)(P0 - tl.lo[0]) + (h0 ? 1 : 0), r1 = (int)(P1 - tl.lo[1]) + (h1 ? 1 : 0),
+              r2 = (int)(P2 - tl.lo[2]) + (h2 ? 1 : 0);
+    const double wz0 = tb.wl0(r0), wz1 = tb.wr0(r0), wy0 = tb.wl1(r1), wy1 = tb.wr1(r1);
+    const double wx0 = tb.wl2(r2), wx1 = tb.wr2(r2);
+    const int a1 = h0 ? cz + 1 : cz, b1 = h1 ? cy + 1 : cy, c1 = h2 ? cx + 1 : cx;
+    const double c000 = G(cz, cy, cx), c001 = G(cz, cy, c1), c010 = G(cz, b1, cx),
+                 c011 = G(cz, b1, c1), c100 = G(a1, cy, cx), c101 = G(a1, cy, c1),
+                 c110 = G(a1, b1, cx), c111 = G(a1, b1, c1);
+    const double ix00 = wx0 * c000 + wx1 * c001, ix01 = wx0 * c010 + wx1 * c011;
+    const double ix10 = wx0 * c100 + wx1 * c101, ix11 = wx0 * c110 + wx1 * c111;
+    auto coef = [&](int k) -> double {
+      if (SRC == 2) return 0.0;
+      return SRC == 1 ? crv[u][k] : dequant(src, csv[u][k], cpos[u][k], q);
+    };
+    const uint32_t nf1 = tl.nf[1], nf2 = tl.nf[2];
+    auto put = [&](uint32_t i0, uint32_t i1, uint32_t i2, double v) {
+      out[(i0 * nf1 + i1) * nf2 + i2] = (Tout)v;
+    };
+    put(P0, P1, P2, c000);
+    if (h2) put(P0, P1, P2 + 1, ix00 + coef(1));
+    if (h1) put(P0, P1 + 1, P2, (wy0 * c000 + wy1 * c010) + coef(2));
+    if (h1 && h2) put(P0, P1 + 1, P2 + 1, (wy0 * ix00 + wy1 * ix01) + coef(3));
+    if (h0) put(P0 + 1, P1, P2, (wz0 * c000 + wz1 * c100) + coef(4));
+    if (h0 && h2) put(P0 + 1, P1, P2 + 1, (wz0 * ix00 + wz1 * ix10) + coef(5));
+    if (h0 && h1)
+      put(P0 + 1, P1 + 1, P2,
+          (wz0 * (wy0 * c000 + wy1 * c010) + wz1 * (wy0 * c100 + wy1 * c110)) + coef(6));
+    if (h0 && h1 && h2)
+      put(P0 + 1, P1 + 1, P2 + 1,
+          (wz0 * (wy0 * ix00 + wy1 * ix01) + wz1 * (wy0 * ix10 + wy1 * ix11)) + coef(7));
   }
 }
 
@@ -788,13 +992,22 @@ __device__ __forceinline__ void thomas_strided_body(double* __restrict__ x, int6
     stride = n1 * n2;
     base = t;
   }
+  // each sweep keeps the next batch's loads in flight while it runs the
+  // recurrence over the current batch (indices clamped: loads are never
+  // behind a branch); the batches a sweep reads ahead are not yet written
   double* p = x + base;
+  const double* ps = sub ? sub + base : nullptr;
+  const int64_t last = len - 1;
   double prev = 0.0;
-  for (int64_t i0 = 0; i0 < len; i0 += U) {
-    double v[U];
+  double v[U], nv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (i0 + u < len) v[u] = p[(i0 + u) * stride];
+  for (int u = 0; u < U; ++u) v[u] = p[min<int64_t>(u, last) * stride];
+  for (int64_t i0 = 0; i0 < len; i0 += U) {
+    const bool more = i0 + U < len;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) nv[u] = p[min<int64_t>(i0 + U + u, last) * stride];
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u;
@@ -806,16 +1019,27 @@ __device__ __forceinline__ void thomas_strided_body(double* __restrict__ x, int6
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (i0 + u < len) p[(i0 + u) * stride] = v[u];
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = nv[u];
+    }
   }
   double nxt = 0.0;
-  for (int64_t hi = len - 1; hi >= 0; hi -= U) {
-    double v[U], sv[U];
+  double sv[U], nsv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = hi - u;
-      if (i >= 0) {
-        v[u] = p[i * stride];
-        if (sub) sv[u] = sub[base + i * stride];
+  for (int u = 0; u < U; ++u) {
+    const int64_t i = max<int64_t>(last - u, 0);
+    v[u] = p[i * stride];
+    sv[u] = ps ? ps[i * stride] : 0.0;
+  }
+  for (int64_t hi = last; hi >= 0; hi -= U) {
+    const bool more = hi - U >= 0;
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = max<int64_t>(hi - U - u, 0);
+        nv[u] = p[i * stride];
+        nsv[u] = ps ? ps[i * stride] : 0.0;
       }
     }
 #pragma unroll
@@ -829,7 +1053,14 @@ __device__ __forceinline__ void thomas_strided_body(double* __restrict__ x, int6
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = hi - u;
-      if (i >= 0) p[i * stride] = sub ? sv[u] - v[u] : v[u];
+      if (i >= 0) p[i * stride] = ps ? sv[u] - v[u] : v[u];
+    }
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = nv[u];
+        sv[u] = nsv[u];
+      }
     }
   }
 }
@@ -848,56 +1079,94 @@ __global__ __launch_bounds__(256) void k_thomas_strided(double* __restrict__ x, 
 // Contiguous axis: one wavefront per 64 rows.  Segments of SEG elements of
 // the 64 rows are staged through LDS with coalesced loads and stores; each
 // lane then runs the recurrence along its own row inside LDS.
+// Value of lane l (uniform) of a double held by every lane of the wavefront.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 template <int SEG>
 __device__ __forceinline__ void thomas_rows_body(double* __restrict__ x, int64_t nrows,
                                                  int64_t n, const double* __restrict__ ta,
                                                  const double* __restrict__ tm,
                                                  const double* __restrict__ tc,
                                                  const double* __restrict__ sub, int64_t blk) {
+  static_assert(SEG <= 64 && 64 % SEG == 0, "segment divides the wavefront");
+  constexpr int RP = 64 / SEG;  // rows per wavefront load (SEG lanes per row)
+  constexpr int K = SEG;        // loads per lane per segment (64 rows)
   __shared__ double buf[64][SEG + 1];
   const int lane = threadIdx.x;
   const int64_t r0 = blk * 64;
   const int nr = (int)min<int64_t>(64, nrows - r0);
+  const int c = lane % SEG, jr = lane / SEG;
+  // a segment of the 64 rows: every load of a lane in flight at once, plus
+  // the segment's factors (lane c holds entry s0 + c; the recurrence reads
+  // them back with a uniform lane index).  The recurrence runs on all 64
+  // lanes, also past the last row (those LDS rows hold clamped copies of a
+  // real row and are never stored): under a lane-dependent branch the
+  // compiler may move the factor loads into it, and a lane read back by
+  // readlane would then be one that never loaded.
+  auto seg_load = [&](int64_t s0, int ns, double (&v)[K], double& fa, double& fm, double& fc,
+                      const double* src2, double (&w)[K]) {
+    const int64_t cc = s0 + min(c, ns - 1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = min(jr + k * RP, nr - 1);
+      v[k] = x[(r0 + j) * n + cc];
+      if (src2) w[k] = src2[(r0 + j) * n + cc];
+    }
+    fa = ta[cc];
+    fm = tm[cc];
+    fc = tc[cc];
+  };
   double prev = 0.0;
   for (int64_t s0 = 0; s0 < n; s0 += SEG) {
     const int ns = (int)min<int64_t>(SEG, n - s0);
-    for (int j = 0; j < nr; ++j)
-      if (lane < ns) buf[j][lane] = x[(r0 + j) * n + s0 + lane];
+    double v[K], w[K], fa, fm, fc;
+    seg_load(s0, ns, v, fa, fm, fc, nullptr, w);
+#pragma unroll
+    for (int k = 0; k < K; ++k) buf[jr + k * RP][c] = v[k];
     __syncthreads();
-    if (lane < nr) {
-      for (int i = 0; i < ns; ++i) {
-        const int64_t gi = s0 + i;
-        const double f = buf[lane][i];
-        const double v = (gi == 0 ? f : f - ta[gi] * prev) * tm[gi];
-        buf[lane][i] = v;
-        prev = v;
-      }
+    for (int i = 0; i < ns; ++i) {
+      const int64_t gi = s0 + i;
+      const double a = readlane_d(fa, i), m = readlane_d(fm, i);
+      const double f = buf[lane][i];
+      const double y = (gi == 0 ? f : f - a * prev) * m;
+      buf[lane][i] = y;
+      prev = y;
     }
     __syncthreads();
-    for (int j = 0; j < nr; ++j)
-      if (lane < ns) x[(r0 + j) * n + s0 + lane] = buf[j][lane];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = jr + k * RP;
+      if (j < nr && c < ns) x[(r0 + j) * n + s0 + c] = buf[j][c];
+    }
     __syncthreads();
   }
   double nxt = 0.0;
   for (int64_t s0 = ((n - 1) / SEG) * SEG; s0 >= 0; s0 -= SEG) {
     const int ns = (int)min<int64_t>(SEG, n - s0);
-    for (int j = 0; j < nr; ++j)
-      if (lane < ns) buf[j][lane] = x[(r0 + j) * n + s0 + lane];
+    double v[K], w[K], fa, fm, fc;
+    seg_load(s0, ns, v, fa, fm, fc, sub, w);
+#pragma unroll
+    for (int k = 0; k < K; ++k) buf[jr + k * RP][c] = v[k];
     __syncthreads();
-    if (lane < nr) {
-      for (int i = ns - 1; i >= 0; --i) {
-        const int64_t gi = s0 + i;
-        double v = buf[lane][i];
-        if (gi < n - 1) v = v - tc[gi] * nxt;
-        buf[lane][i] = v;
-        nxt = v;
-      }
+    for (int i = ns - 1; i >= 0; --i) {
+      const int64_t gi = s0 + i;
+      const double cf = readlane_d(fc, i);
+      double y = buf[lane][i];
+      if (gi < n - 1) y = y - cf * nxt;
+      buf[lane][i] = y;
+      nxt = y;
     }
     __syncthreads();
-    for (int j = 0; j < nr; ++j) {
-      if (lane < ns) {
-        const int64_t gi = (r0 + j) * n + s0 + lane;
-        x[gi] = sub ? sub[gi] - buf[j][lane] : buf[j][lane];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = jr + k * RP;
+      if (j < nr && c < ns) {
+        const int64_t gi = (r0 + j) * n + s0 + c;
+        x[gi] = sub ? w[k] - buf[j][c] : buf[j][c];
       }
     }
     __syncthreads();
@@ -1088,16 +1357,29 @@ int active_axes(const LevelGeom& g) {
   return (g.bit[0] >= 0) + (g.bit[1] >= 0) + (g.bit[2] >= 0);
 }
 
+template <typename Tin, int MODE, int C>
+void dec_3(const Tin* Gp, const LevelGeom& g, double* fout, uint16_t* sym, double* raw, double r,
+           const OutlierBuf& ob, unsigned* status, hipStream_t s) {
+  constexpr TileShape ts = sizeof(Tin) == 4 ? kDecTiles3F32[C] : kDecTiles3F64[C];
+  const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
+  hipLaunchKernelGGL((k_dec_level<Tin, ts.z, ts.y, ts.x, MODE>), dim3(t.grid), dim3(256), 0, s,
+                     Gp, g, fout, sym, raw, r, ob, status, t.n_tiles);
+}
+
 template <typename Tin, int MODE>
 void dec_dispatch(const void* G, const LevelGeom& g, double* fout, uint16_t* sym, double* raw,
-                  double r, const OutlierBuf& ob, unsigned* status, hipStream_t s) {
+                  double r, const OutlierBuf& ob, unsigned* status, hipStream_t s,
+                  int cand = 0) {
   const Tin* Gp = static_cast<const Tin*>(G);
   const int D = active_axes(g);
   if (D == 3) {
-    constexpr TileShape ts = sizeof(Tin) == 4 ? kDecTiles3F32[0] : kDecTiles3F64[0];
-    const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
-    hipLaunchKernelGGL((k_dec_level<Tin, ts.z, ts.y, ts.x, MODE>), dim3(t.grid), dim3(256), 0, s,
-                       Gp, g, fout, sym, raw, r, ob, status, t.n_tiles);
+    if (MODE == 2) cand = 0;
+    switch (cand) {
+      case 1: dec_3<Tin, MODE, 1>(Gp, g, fout, sym, raw, r, ob, status, s); break;
+      case 2: dec_3<Tin, MODE, 2>(Gp, g, fout, sym, raw, r, ob, status, s); break;
+      case 3: dec_3<Tin, MODE, 3>(Gp, g, fout, sym, raw, r, ob, status, s); break;
+      default: dec_3<Tin, MODE, 0>(Gp, g, fout, sym, raw, r, ob, status, s);
+    }
   } else if (D == 2) {
     constexpr TileShape ts = sizeof(Tin) == 4 ? kDecTile2F32 : kDecTile2F64;
     const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
@@ -1171,32 +1453,44 @@ void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, const Bu
 
 void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* fout,
                       uint16_t* sym, double* raw, double r, const OutlierBuf& ob,
-                      unsigned* status, hipStream_t s) {
+                      unsigned* status, hipStream_t s, int cand) {
   if (sym) {
-    if (g_is_f32) dec_dispatch<float, 0>(G, g, fout, sym, raw, r, ob, status, s);
-    else dec_dispatch<double, 0>(G, g, fout, sym, raw, r, ob, status, s);
+    if (g_is_f32) dec_dispatch<float, 0>(G, g, fout, sym, raw, r, ob, status, s, cand);
+    else dec_dispatch<double, 0>(G, g, fout, sym, raw, r, ob, status, s, cand);
   } else {
-    if (g_is_f32) dec_dispatch<float, 1>(G, g, fout, sym, raw, r, ob, status, s);
-    else dec_dispatch<double, 1>(G, g, fout, sym, raw, r, ob, status, s);
+    if (g_is_f32) dec_dispatch<float, 1>(G, g, fout, sym, raw, r, ob, status, s, cand);
+    else dec_dispatch<double, 1>(G, g, fout, sym, raw, r, ob, status, s, cand);
   }
 }
 
-void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
-                   const double* sub, hipStream_t s) {
+namespace {
+template <int C>
+void thomas_c(int axis, double* x, const int64_t nc[3], const AxisTab& t, const double* sub,
+              hipStream_t s) {
   if (axis == 2) {
     const int64_t rows = nc[0] * nc[1];
-    hipLaunchKernelGGL(k_thomas_rows<kThomasSeg[0]>, dim3((unsigned)((rows + 63) / 64)), dim3(64),
+    hipLaunchKernelGGL(k_thomas_rows<kThomasSeg[C]>, dim3((unsigned)((rows + 63) / 64)), dim3(64),
                        0, s, x, rows, nc[2], t.ta, t.tm, t.tc, sub);
     return;
   }
   const int64_t lines = axis == 1 ? nc[0] * nc[2] : nc[1] * nc[2];
   const unsigned blocks = (unsigned)((lines + 255) / 256);
   if (axis == 1)
-    hipLaunchKernelGGL((k_thomas_strided<1, kThomasU[0]>), dim3(blocks), dim3(256), 0, s, x,
+    hipLaunchKernelGGL((k_thomas_strided<1, kThomasU[C]>), dim3(blocks), dim3(256), 0, s, x,
                        nc[0], nc[1], nc[2], t.ta, t.tm, t.tc, sub);
   else
-    hipLaunchKernelGGL((k_thomas_strided<0, kThomasU[0]>), dim3(blocks), dim3(256), 0, s, x,
+    hipLaunchKernelGGL((k_thomas_strided<0, kThomasU[C]>), dim3(blocks), dim3(256), 0, s, x,
                        nc[0], nc[1], nc[2], t.ta, t.tm, t.tc, sub);
+}
+}  // namespace
+
+void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
+                   const double* sub, hipStream_t s, int cand) {
+  switch (cand) {
+    case 1: thomas_c<1>(axis, x, nc, t, sub, s); break;
+    case 2: thomas_c<2>(axis, x, nc, t, sub, s); break;
+    default: thomas_c<0>(axis, x, nc, t, sub, s);
+  }
 }
 
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,

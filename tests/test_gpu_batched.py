@@ -80,6 +80,10 @@ def test_every_tuning_candidate_gives_the_same_streams():
                 assert mgc.tuning_info(kind)[1] == c
                 for j in range(len(xs)):
                     assert bool((got[j] == ref[j]).all()), "kind %s candidate %d array %d" % (kind, c, j)
+                # plain calls use the forced candidate too
+                for j in (1, 2, 3):
+                    plain = mgc.compress(xs[j], bounds[j])
+                    assert bool((plain == ref[j]).all()), "plain: kind %s candidate %d" % (kind, c)
             mgc.set_tuning(kind, -1)
     finally:
         for kind in mgc.TUNE_KINDS:

@@ -58,7 +58,11 @@ def test_length_limit_flattening_matches_oracle():
     ln = huffman.code_lengths(huffman.histogram(sym, 65536))
     assert ln.max() <= 32
     t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
-    assert to_bytes(mgc.huffman_encode(t, 1024)) == oracle_huffman_stream(sym, 1024)
+    enc = mgc.huffman_encode(t, 1024)
+    assert to_bytes(enc) == oracle_huffman_stream(sym, 1024)
+    # codes up to the 32-bit limit, prefixes holding several lengths
+    back = mgc.huffman_decode(enc, len(sym))
+    assert bool((back == t).all())
 
 
 def test_gpu_decodes_oracle_stream_and_rejects_corruption():
