@@ -55,9 +55,9 @@ struct AxisTab {
   const double* wl;  // [nf] weight of the left coarse neighbour of new node i
   const double* wr;  // [nf] weight of the right coarse neighbour of new node i
   const double* W;   // [nc*5] restriction taps at fine p(j)-2 .. p(j)+2
-  const double* ta;  // [nc] Thomas: sub-diagonal of the coarse mass matrix
+  const double* ta;  // [nc] Thomas: sub-diagonal times reciprocal pivot (0 at j = 0)
   const double* tm;  // [nc] Thomas: reciprocal pivots
-  const double* tc;  // [nc] Thomas: super-diagonal times reciprocal pivot
+  const double* tc;  // [nc] Thomas: super-diagonal times reciprocal pivot (0 at the end)
   const double* WP;  // [nc*5] taps of P^T at fine p(j)-2 .. p(j)+2 (adjoint)
   const double* Mt;  // [nf*3] fine mass-matrix row (i-1, i, i+1) (adjoint)
 };

@@ -82,6 +82,12 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 // Lanes of the wave whose `digit` (nbits bits) equals this lane's, among the
 // lanes with valid set.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ uint64_t match_digit(unsigned digit, int nbits, bool valid) {
   uint64_t peers = __ballot(valid);
   for (int b = 0; b < nbits; ++b) {
@@ -149,62 +155,87 @@ struct SortSmem {
 
 // Stable LSD radix sort by the low `bits` bits of the keys, 8 bits a pass,
 // one 1024-thread block.  Returns true when the result is in (k1, v1).
+// Wavefront w owns a contiguous run of the items (tiles of 64; eight tiles'
+// loads in flight at once): per pass it counts its digits, one block scan
+// turns the per-wavefront counts into output offsets, and it scatters its
+// run in order (peers with the same digit found by ballots, ranked by lane),
+// so the sort is stable with three block barriers per pass.
 __device__ bool block_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                                  uint32_t n, int bits, SortSmem& sm) {
+  constexpr int B = 8;  // tiles per batch of loads
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int passes = (bits + 7) / 8;
+  const uint32_t run = ((n + 1023) / 1024) * 64;
+  const uint32_t i0 = min(n, (uint32_t)wave * run), i1 = min(n, i0 + run);
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = 8 * pass;
-    if (tid < 256) sm.hist[tid] = 0;
-    for (int w = 0; w < 16; ++w)
-      if (tid < 256) sm.wcnt[w][tid] = 0;
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += 1024) atomicAdd(&sm.hist[(k0[i] >> shift) & 255u], 1u);
-    __syncthreads();
-    if (tid == 0) {
-      unsigned run = 0;
-      for (int d = 0; d < 256; ++d) {
-        sm.base[d] = run;
-        run += sm.hist[d];
+    for (int d = lane; d < 256; d += 64) sm.wcnt[wave][d] = 0;
+    wave_lds_fence();
+    for (uint32_t t = i0; t < i1; t += 64 * B) {
+      uint32_t key[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) key[b] = k0[min(t + b * 64 + lane, i1 - 1)];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const bool valid = t + b * 64 + lane < i1;
+        const unsigned d = (key[b] >> shift) & 255u;
+        const uint64_t peers = match_digit(d, 8, valid);
+        if (valid && __popcll(peers & lanemask_lt()) == 0) sm.wcnt[wave][d] += __popcll(peers);
+        wave_lds_fence();
       }
     }
     __syncthreads();
-    for (uint32_t t0 = 0; t0 < n; t0 += 1024) {
-      const uint32_t i = t0 + tid;
-      const bool valid = i < n;
-      const uint32_t key = valid ? k0[i] : 0u;
-      const uint32_t val = valid ? v0[i] : 0u;
-      const unsigned d = (key >> shift) & 255u;
-      const uint64_t peers = match_digit(d, 8, valid);
-      const unsigned rank = __popcll(peers & lanemask_lt());
-      if (valid && rank == 0) sm.wcnt[wave][d] = __popcll(peers);
-      __syncthreads();
-      if (tid < 256) {
-        unsigned run = 0;
-        for (int w = 0; w < 16; ++w) {
-          const unsigned c = sm.wcnt[w][tid];
-          sm.wcnt[w][tid] = run;
-          run += c;
+    // offsets: digit d's output starts after all smaller digits, and wave
+    // w's items of digit d after those of the earlier wavefronts
+    unsigned tot = 0, incl = 0;
+    if (tid < 256) {
+      for (int w = 0; w < 16; ++w) tot += sm.wcnt[w][tid];
+      incl = tot;
+      for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = (unsigned)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      if (lane == 63) sm.total[wave] = incl;
+    }
+    __syncthreads();
+    if (tid < 256) {
+      unsigned acc = incl - tot;
+      for (int w = 0; w < wave; ++w) acc += sm.total[w];
+      for (int w = 0; w < 16; ++w) {
+        const unsigned c = sm.wcnt[w][tid];
+        sm.wcnt[w][tid] = acc;
+        acc += c;
+      }
+    }
+    __syncthreads();
+    for (uint32_t t = i0; t < i1; t += 64 * B) {
+      uint32_t key[B], val[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const uint32_t i = min(t + b * 64 + lane, i1 - 1);
+        key[b] = k0[i];
+        val[b] = v0[i];
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const bool valid = t + b * 64 + lane < i1;
+        const unsigned d = (key[b] >> shift) & 255u;
+        const uint64_t peers = match_digit(d, 8, valid);
+        const unsigned r = __popcll(peers & lanemask_lt());
+        const unsigned pos = valid ? sm.wcnt[wave][d] + r : 0u;
+        if (valid) {
+          k1[pos] = key[b];
+          v1[pos] = val[b];
         }
-        sm.total[tid] = run;
+        wave_lds_fence();
+        if (valid && r == 0) sm.wcnt[wave][d] = pos + __popcll(peers);
+        wave_lds_fence();
       }
-      __syncthreads();
-      if (valid) {
-        const unsigned pos = sm.base[d] + sm.wcnt[wave][d] + rank;
-        k1[pos] = key;
-        v1[pos] = val;
-      }
-      __syncthreads();
-      if (tid < 256) {
-        sm.base[tid] += sm.total[tid];
-        for (int w = 0; w < 16; ++w) sm.wcnt[w][tid] = 0;
-      }
-      __syncthreads();
     }
+    __syncthreads();
     uint32_t* t;
     t = k0; k0 = k1; k1 = t;
     t = v0; v0 = v1; v1 = t;
-    (void)lane;
   }
   return passes & 1;
 }
@@ -280,41 +311,50 @@ __device__ __forceinline__ unsigned upper_count(const uint32_t* a, unsigned n, u
 }
 
 // Stable rank of each item among items with the same small digit (< 34), in
-// item order, processed in tiles of 1024.  For every valid item calls
-// fn(i, digit, rank) where rank counts earlier items with that digit.
+// item order.  For every item calls fn(i, digit, rank) where rank counts
+// earlier items with that digit.  Wavefront w takes a contiguous run of the
+// items in tiles of 64 (peers with the same digit found by ballots, one
+// lane per digit updating the wave's counter): a counting pass, a scan of
+// the per-wave counts over the wavefronts, then the ranking pass; two block
+// barriers in all.
 template <typename DigitFn, typename Fn>
 __device__ void stable_digit_ranks(unsigned n, DigitFn digit_of, Fn fn, CbSmem& sm) {
-  const int tid = threadIdx.x, wave = tid >> 6;
-  if (tid < 34) sm.lbase[tid] = 0;
-  for (int w = 0; w < 16; ++w)
-    if (tid < 34) sm.wl[w][tid] = 0;
-  __syncthreads();
-  for (unsigned t0 = 0; t0 < n; t0 += 1024) {
-    const unsigned i = t0 + tid;
-    const bool valid = i < n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const unsigned run = ((n + 16 * 64 - 1) / (16 * 64)) * 64;  // items per wavefront
+  const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
+  for (int d = lane; d < 34; d += 64) sm.wl[wave][d] = 0;
+  wave_lds_fence();
+  for (unsigned t = i0; t < i1; t += 64) {
+    const unsigned i = t + lane;
+    const bool valid = i < i1;
     const unsigned d = valid ? digit_of(i) : 0u;
     const uint64_t peers = match_digit(d, 6, valid);
-    const unsigned rank = __popcll(peers & lanemask_lt());
-    if (valid && rank == 0) sm.wl[wave][d] = __popcll(peers);
-    __syncthreads();
-    if (tid < 34) {
-      unsigned run = 0;
-      for (int w = 0; w < 16; ++w) {
-        const unsigned c = sm.wl[w][tid];
-        sm.wl[w][tid] = run;
-        run += c;
-      }
-      sm.lcount[tid] = run;  // per-tile total (reused below)
-    }
-    __syncthreads();
-    if (valid) fn(i, d, sm.lbase[d] + sm.wl[wave][d] + rank);
-    __syncthreads();
-    if (tid < 34) {
-      sm.lbase[tid] += sm.lcount[tid];
-      for (int w = 0; w < 16; ++w) sm.wl[w][tid] = 0;
-    }
-    __syncthreads();
+    if (valid && __popcll(peers & lanemask_lt()) == 0) sm.wl[wave][d] += __popcll(peers);
+    wave_lds_fence();
   }
+  __syncthreads();
+  if (tid < 34) {
+    unsigned acc = 0;
+    for (int w = 0; w < 16; ++w) {
+      const unsigned c = sm.wl[w][tid];
+      sm.wl[w][tid] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  for (unsigned t = i0; t < i1; t += 64) {
+    const unsigned i = t + lane;
+    const bool valid = i < i1;
+    const unsigned d = valid ? digit_of(i) : 0u;
+    const uint64_t peers = match_digit(d, 6, valid);
+    const unsigned r = __popcll(peers & lanemask_lt());
+    const unsigned base = valid ? sm.wl[wave][d] : 0u;
+    if (valid) fn(i, d, base + r);
+    wave_lds_fence();
+    if (valid && r == 0) sm.wl[wave][d] = base + __popcll(peers);
+    wave_lds_fence();
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
@@ -686,7 +726,6 @@ __device__ __forceinline__ void layout_scan_body(const uint32_t* __restrict__ cw
                                                  uint64_t cb_off, Layout* __restrict__ lay,
                                                  const unsigned long long* n_out,
                                                  uint64_t out_cap_n, int huff_only) {
-  __shared__ unsigned sm32[16];
   __shared__ unsigned long long carry;
   const int tid = threadIdx.x;
   const unsigned long long n_codes = lay->n_codes;
@@ -703,20 +742,51 @@ __device__ __forceinline__ void layout_scan_body(const uint32_t* __restrict__ cw
   const unsigned long long oval = opos + 8ull * no;
   const unsigned long long words = oval + 8ull * no;
   uint64_t* offs = reinterpret_cast<uint64_t*>(out + off);
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  // chunk-parallel exclusive scan in tiles of 1024 chunks
-  for (int64_t t0 = 0; t0 < n_chunks; t0 += 1024) {
-    const int64_t c = t0 + tid;
-    const unsigned v = c < n_chunks ? cw[c] : 0u;
-    unsigned tot;
-    const unsigned ex = block_excl_scan(v, sm32, &tot);
-    const unsigned long long base = carry;
-    if (c < n_chunks) offs[c] = base + ex;
-    __syncthreads();
-    if (tid == 0) carry = base + tot;
-    __syncthreads();
+  // each thread owns a contiguous run of chunks: sum it (sixteen loads in
+  // flight, clamped indices), one block scan of the sums, then the run's
+  // offsets
+  const int64_t per = (n_chunks + 1023) / 1024;
+  const int64_t c0 = min<int64_t>(n_chunks, (int64_t)tid * per);
+  const int64_t c1 = min<int64_t>(n_chunks, c0 + per);
+  unsigned long long mine = 0;
+  for (int64_t j = c0; j < c1; j += 16) {
+    unsigned v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = cw[min<int64_t>(j + u, c1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) mine += j + u < c1 ? v[u] : 0u;
   }
+  // exclusive scan of the 64-bit run sums over the 1024 threads
+  unsigned long long incl = mine;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned lo = (unsigned)__shfl_up((int)(unsigned)incl, o, 64);
+    const unsigned hi = (unsigned)__shfl_up((int)(unsigned)(incl >> 32), o, 64);
+    if (lane >= o) incl += ((unsigned long long)hi << 32) | lo;
+  }
+  __shared__ unsigned long long wsum[16];
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  unsigned long long before = 0, total = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wave) before += wsum[w];
+    total += wsum[w];
+  }
+  unsigned long long run = before + incl - mine;
+  for (int64_t j = c0; j < c1; j += 16) {
+    unsigned v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = cw[min<int64_t>(j + u, c1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (j + u < c1) {
+        offs[j + u] = run;
+        run += v[u];
+      }
+    }
+  }
+  if (tid == 0) carry = total;
+  __syncthreads();
   if (tid == 0) {
     const unsigned long long nw = carry;
     offs[n_chunks] = nw;
@@ -899,6 +969,194 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym
   encode_body(sym, N, C, code, clen, pk, out, lay, blockIdx.x, wbuf);
 }
 
+// Encoder for large arrays (chunks of 1024 symbols): persistent blocks of
+// kEncWaves wavefronts, one chunk per wavefront at a time.  The packed
+// (code << 6 | length) words of the kEncWin symbols around the dictionary
+// centre (|k| < kEncWin/2, nearly all of them) are copied into LDS once per
+// block, so a symbol's code is an LDS read; the rest come from the global
+// table.  Symbols are loaded two chunks ahead and the global look-ups of
+// the next chunk are issued before the current chunk is coded, so neither
+// waits on memory in the steady state (a look-up of an in-window symbol
+// reads one shared, cached word instead).  Each wavefront ORs its chunk's
+// codes into its own LDS words and copies them out; no block barriers.
+constexpr int kEncWin = 32768;
+constexpr uint32_t kEncLo = kHalf - kEncWin / 2;
+constexpr int kEncWaves = 6;
+constexpr int kEncC = 1024;
+
+__host__ __device__ constexpr size_t enc_win_lds_bytes() {
+  return (size_t)(kEncWin + kEncWaves * kEncC) * sizeof(uint32_t);
+}
+
+struct EncSyms {
+  uint32_t v[8];  // 16 symbols, two per word (low half first)
+  int n;          // symbols of this lane inside the array
+};
+
+__global__ __launch_bounds__(64 * kEncWaves) void k_encode_win(
+    const uint16_t* __restrict__ sym, int64_t N, const uint32_t* __restrict__ code,
+    const uint8_t* __restrict__ clen, const uint32_t* __restrict__ pk, uint8_t* __restrict__ out,
+    const Layout* __restrict__ lay) {
+  extern __shared__ __align__(16) uint32_t esm[];
+  if (lay->status) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t* tab = esm;
+  uint32_t* w = esm + kEncWin + wave * kEncC;
+  const int64_t n_chunks = (N + kEncC - 1) / kEncC;
+  const uint64_t* offs = reinterpret_cast<const uint64_t*>(out + lay->off);
+  uint32_t* words = reinterpret_cast<uint32_t*>(out + lay->words);
+  const int64_t stride = (int64_t)gridDim.x * kEncWaves;
+  const bool fast = lay->max_len <= 26;
+  if (fast) {
+    const uint4* src = reinterpret_cast<const uint4*>(pk + kEncLo);
+    uint4* dst = reinterpret_cast<uint4*>(tab);
+    constexpr int NV = kEncWin / 4 / (64 * kEncWaves) + 1;
+    uint4 t[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int i = min<int>(u * 64 * kEncWaves + threadIdx.x, kEncWin / 4 - 1);
+      t[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int i = u * 64 * kEncWaves + threadIdx.x;
+      if (i < kEncWin / 4) dst[i] = t[u];
+    }
+  }
+  __syncthreads();
+  // 16 symbols of lane `lane` in chunk c (whole-vector loads inside the array)
+  auto load_syms = [&](int64_t c, EncSyms& e) {
+    const int64_t a = c * kEncC + lane * 16;
+    const int64_t cl = min<int64_t>(c, n_chunks - 1);
+    e.n = c < n_chunks ? (int)max<int64_t>(0, min<int64_t>(16, N - a)) : 0;
+    if (e.n == 16) {
+      const uint4* p = reinterpret_cast<const uint4*>(sym + a);
+      const uint4 x0 = p[0], x1 = p[1];
+      e.v[0] = x0.x; e.v[1] = x0.y; e.v[2] = x0.z; e.v[3] = x0.w;
+      e.v[4] = x1.x; e.v[5] = x1.y; e.v[6] = x1.z; e.v[7] = x1.w;
+    } else {
+      const int64_t b = cl * kEncC + lane * 16;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t lo = 2 * k < e.n ? sym[b + 2 * k] : 0u;
+        const uint32_t hi = 2 * k + 1 < e.n ? sym[b + 2 * k + 1] : 0u;
+        e.v[k] = lo | (hi << 16);
+      }
+    }
+  };
+  auto sym_at = [](const EncSyms& e, int k) -> uint32_t {
+    return (k & 1) ? (e.v[k >> 1] >> 16) : (e.v[k >> 1] & 0xFFFFu);
+  };
+  // global look-ups of the symbols outside the window (a shared word otherwise)
+  auto gather = [&](const EncSyms& e, uint32_t (&g)[16]) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t s = sym_at(e, k);
+      g[k] = pk[s - kEncLo < (uint32_t)kEncWin ? kHalf : s];
+    }
+  };
+  auto emit = [&](int64_t c, uint64_t w0, uint64_t nw) {
+    wave_lds_fence();
+    if (c < n_chunks)
+      for (uint64_t i = lane; i < nw; i += 64) words[w0 + i] = w[i];
+    wave_lds_fence();
+  };
+  auto zero_words = [&]() {
+    uint4* z = reinterpret_cast<uint4*>(w);
+#pragma unroll
+    for (int k = 0; k < kEncC / 4 / 64; ++k) z[k * 64 + lane] = make_uint4(0u, 0u, 0u, 0u);
+  };
+  auto scan_bits = [&](unsigned my_bits) -> unsigned {
+    unsigned x = my_bits;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned y = (unsigned)__shfl_up((int)x, o, 64);
+      if (lane >= o) x += y;
+    }
+    return x - my_bits;
+  };
+  int64_t c = (int64_t)blockIdx.x * kEncWaves + wave;
+  if (!fast) {
+    // codes longer than 26 bits: code and length tables in global memory
+    for (; c < n_chunks; c += stride) {
+      EncSyms e;
+      load_syms(c, e);
+      const uint64_t w0 = offs[c], nw = offs[c + 1] - w0;
+      uint32_t cd[16];
+      unsigned ln[16], my_bits = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t s = sym_at(e, k);
+        cd[k] = k < e.n ? code[s] : 0u;
+        ln[k] = k < e.n ? clen[s] : 0u;
+      }
+      zero_words();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) my_bits += ln[k];
+      unsigned bitpos = scan_bits(my_bits);
+      wave_lds_fence();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (ln[k] == 0) continue;
+        put_code(w, bitpos, cd[k], ln[k]);
+        bitpos += ln[k];
+      }
+      emit(c, w0, nw);
+    }
+    return;
+  }
+  if (c >= n_chunks) return;
+  EncSyms s0, s1, s2;
+  uint32_t g0[16], g1[16];
+  uint64_t o0a, o0b, o1a, o1b;
+  load_syms(c, s0);
+  load_syms(c + stride, s1);
+  o0a = offs[c];
+  o0b = offs[c + 1];
+  {
+    const int64_t cn = min<int64_t>(c + stride, n_chunks - 1);
+    o1a = offs[cn];
+    o1b = offs[cn + 1];
+  }
+  gather(s0, g0);
+  for (; c < n_chunks; c += stride) {
+    load_syms(c + 2 * stride, s2);
+    gather(s1, g1);
+    // code chunk c
+    zero_words();
+    uint32_t cl[16];
+    unsigned my_bits = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t d = sym_at(s0, k) - kEncLo;
+      const uint32_t e = d < (uint32_t)kEncWin ? tab[d] : g0[k];
+      cl[k] = k < s0.n ? e : 0u;
+      my_bits += cl[k] & 63u;
+    }
+    unsigned bitpos = scan_bits(my_bits);
+    wave_lds_fence();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const unsigned l = cl[k] & 63u;
+      if (l == 0) continue;
+      put_code(w, bitpos, cl[k] >> 6, l);
+      bitpos += l;
+    }
+    emit(c, o0a, o0b - o0a);
+    // rotate the pipeline
+    s0 = s1;
+    s1 = s2;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) g0[k] = g1[k];
+    o0a = o1a;
+    o0b = o1b;
+    {
+      const int64_t cn = min<int64_t>(c + 2 * stride, n_chunks - 1);
+      o1a = offs[cn];
+      o1b = offs[cn + 1];
+    }
+  }
+}
+
 struct QArgs {
   double q[kMaxLevels + 1];
 };
@@ -1049,12 +1307,6 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
 // wave instruction.
 constexpr int kDecSB = 8;
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __host__ __device__ constexpr size_t dec_sorted_bytes(uint64_t n_codes) {
   return ((size_t)n_codes * sizeof(uint16_t) + 15) & ~size_t(15);
 }
@@ -1175,7 +1427,7 @@ __global__ __launch_bounds__(1024) void k_decode(
 #pragma unroll
     for (int i = 0; i < kDecSB; ++i)
       v[i] = stw[(i * (64 / kDecSB) + lane / kDecSB) * (kDecSB + 2) + lane % kDecSB];
-    wave_lds_sync();
+    wave_lds_fence();
 #pragma unroll
     for (int i = 0; i < kDecSB; ++i) {
       const int row = i * (64 / kDecSB) + lane / kDecSB, col = lane % kDecSB;
@@ -1205,7 +1457,7 @@ __global__ __launch_bounds__(1024) void k_decode(
       rd += need ? 1u : 0u;
       nextw = rg[rd % RW];
     }
-    wave_lds_sync();
+    wave_lds_fence();
   }
   store_batch(((C - 1) / kDecSB) * kDecSB);
   // bits taken from the chunk: the words moved into the buffer less those
@@ -1402,6 +1654,24 @@ void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
                    const uint8_t* clen, const uint32_t* pk, uint8_t* out, const Layout* lay,
                    hipStream_t s) {
   const int64_t n_chunks = (N + C - 1) / C;
+  // large arrays: the persistent encoder with the code window in LDS (one
+  // block per CU); the window copy needs 16-byte aligned symbol and table
+  // arrays
+  constexpr int64_t kCUs = 256;
+  if (C == kEncC && n_chunks >= 8 * kCUs * kEncWaves &&
+      (reinterpret_cast<uintptr_t>(sym) & 15) == 0 && (reinterpret_cast<uintptr_t>(pk) & 15) == 0) {
+    static bool attr = false;
+    if (!attr) {
+      MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_encode_win),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)enc_win_lds_bytes()));
+      attr = true;
+    }
+    const int64_t blocks = std::min<int64_t>(kCUs, (n_chunks + kEncWaves - 1) / kEncWaves);
+    hipLaunchKernelGGL(k_encode_win, dim3((unsigned)blocks), dim3(64 * kEncWaves),
+                       enc_win_lds_bytes(), s, sym, N, code, clen, pk, out, lay);
+    return;
+  }
   hipLaunchKernelGGL(k_encode, dim3((unsigned)((n_chunks + 3) / 4)), dim3(256),
                      (size_t)4 * C * sizeof(uint32_t), s, sym, N, C, code, clen, pk, out, lay);
 }

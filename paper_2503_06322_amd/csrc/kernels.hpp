@@ -27,8 +27,8 @@ inline TileShape dec_tile(int D, bool f32, int cand) {
 // Thomas sweeps: values in flight per thread on strided axes, and the LDS
 // segment length on the contiguous axis (entry 0 is the plain default).
 constexpr int kThomasCands = 3;
-constexpr int kThomasU[kThomasCands] = {8, 4, 16};
-constexpr int kThomasSeg[kThomasCands] = {32, 16, 64};
+constexpr int kThomasU[kThomasCands] = {16, 8, 4};
+constexpr int kThomasSeg[kThomasCands] = {16, 32, 64};
 
 // ---- transform.hip -------------------------------------------------------
 // Blocks of the range pre-pass: a function of N alone, so that the sum of
@@ -52,7 +52,10 @@ void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* 
                       unsigned* status, hipStream_t s, int cand = 0);
 // Solve the coarse mass matrix along internal axis `axis` for every line of
 // x (coarse grid nc).  When sub != nullptr, x <- sub - solution.
-// cand: kThomasSeg (axis 2) or kThomasU (axes 0, 1) candidate.
+// cand: kThomasSeg (axis 2) or kThomasU (axes 0, 1) candidate; with cand 0,
+// grids of at most kThomasTilePoints points and lines of at most 540 values
+// use the LDS line tiles instead (all variants give identical results).
+constexpr int64_t kThomasTilePoints = int64_t(1) << 22;
 void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
                    const double* sub, hipStream_t s, int cand = 0);
 // Level-0 block: values of G0 (m0 entries) quantised (sym) or copied (raw).

@@ -215,9 +215,9 @@ Plan build_plan(int ndim, const uint64_t* shape) {
           const double a = Hl / 6.0, b = (Hl + Hr) / 3.0, s = Hr / 6.0;
           const double den = j > 0 ? b - a * cprev : b;
           const double mj = 1.0 / den;
-          ta[j] = a;
+          ta[j] = a * mj;  // zero at j = 0
           tm[j] = mj;
-          tc[j] = s * mj;
+          tc[j] = s * mj;  // zero at j = nc - 1
           cprev = tc[j];
         }
       }

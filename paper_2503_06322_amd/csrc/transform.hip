@@ -965,8 +965,18 @@ __global__ __launch_bounds__(256) void k_adj_mass(const double* __restrict__ Pv,
 }
 
 // ------------------------------------------------------------- tridiagonal
-// Thomas sweeps with the pre-factored coarse mass matrix: forward
-// y_i = (f_i - a_i y_{i-1}) m_i, backward x_i = y_i - c_i x_{i+1}.
+// Thomas sweeps with the pre-factored coarse mass matrix (pivot reciprocals
+// m_i, sub- and super-diagonal scaled by them, a_i and c_i): forward
+// y_i = m_i f_i - a_i y_{i-1}, backward x_i = y_i - c_i x_{i+1}, each one
+// fused multiply-add on the dependence chain (the same arithmetic in every
+// sweep kernel).  a_0 = c_{n-1} = 0 and the sweeps start from y_{-1} =
+// x_n = 0, which leave the first and last steps exact.
+__device__ __forceinline__ double thomas_fwd(double f, double a, double m, double prev) {
+  return fma(-a, prev, m * f);
+}
+__device__ __forceinline__ double thomas_bwd(double y, double c, double nxt) {
+  return fma(-c, nxt, y);
+}
 //
 // Strided axes: one thread per line, adjacent lanes on adjacent lines (the
 // contiguous index), so every access is coalesced; values are moved in blocks
@@ -1012,7 +1022,7 @@ __device__ __forceinline__ void thomas_strided_body(double* __restrict__ x, int6
     for (int u = 0; u < U; ++u) {
       const int64_t i = i0 + u;
       if (i < len) {
-        v[u] = (i == 0 ? v[u] : v[u] - ta[i] * prev) * tm[i];
+        v[u] = thomas_fwd(v[u], ta[i], tm[i], prev);
         prev = v[u];
       }
     }
@@ -1046,7 +1056,7 @@ __device__ __forceinline__ void thomas_strided_body(double* __restrict__ x, int6
     for (int u = 0; u < U; ++u) {
       const int64_t i = hi - u;
       if (i >= 0) {
-        if (i < len - 1) v[u] = v[u] - tc[i] * nxt;
+        v[u] = thomas_bwd(v[u], tc[i], nxt);
         nxt = v[u];
       }
     }
@@ -1129,10 +1139,8 @@ __device__ __forceinline__ void thomas_rows_body(double* __restrict__ x, int64_t
     for (int k = 0; k < K; ++k) buf[jr + k * RP][c] = v[k];
     __syncthreads();
     for (int i = 0; i < ns; ++i) {
-      const int64_t gi = s0 + i;
       const double a = readlane_d(fa, i), m = readlane_d(fm, i);
-      const double f = buf[lane][i];
-      const double y = (gi == 0 ? f : f - a * prev) * m;
+      const double y = thomas_fwd(buf[lane][i], a, m, prev);
       buf[lane][i] = y;
       prev = y;
     }
@@ -1153,10 +1161,8 @@ __device__ __forceinline__ void thomas_rows_body(double* __restrict__ x, int64_t
     for (int k = 0; k < K; ++k) buf[jr + k * RP][c] = v[k];
     __syncthreads();
     for (int i = ns - 1; i >= 0; --i) {
-      const int64_t gi = s0 + i;
       const double cf = readlane_d(fc, i);
-      double y = buf[lane][i];
-      if (gi < n - 1) y = y - cf * nxt;
+      const double y = thomas_bwd(buf[lane][i], cf, nxt);
       buf[lane][i] = y;
       nxt = y;
     }
@@ -1180,6 +1186,196 @@ __global__ __launch_bounds__(64) void k_thomas_rows(double* __restrict__ x, int6
                                                      const double* __restrict__ tc,
                                                      const double* __restrict__ sub) {
   thomas_rows_body<SEG>(x, nrows, n, ta, tm, tc, sub, blockIdx.x);
+}
+
+// Orders a wavefront's LDS accesses (its lanes exchange values through LDS).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Whole lines in LDS, one tile per wavefront.  Each wavefront holds 16
+// lines of the axis in its own part of LDS: lines adjacent along the
+// contiguous axis for the strided axes (the 16 values at one position are
+// 128 contiguous bytes), 16 consecutive rows for the contiguous axis (one
+// contiguous block).  It loads the tile with sixteen loads per lane in
+// flight, runs the forward and backward sweeps in LDS (one lane per line,
+// values and factors through registers in batches) and writes the tile back:
+// each value is read and written once per axis, where the segment-staged
+// sweeps read and write the forward pass's values a second time.  The
+// wavefronts of a block share only the factor tables, so one can sweep
+// while the others load or store.
+constexpr int kTileLines = 16;
+constexpr int kThomasTile4MaxL = 280;  // four tiles per block
+constexpr int kThomasTile2MaxL = 540;  // two tiles per block
+
+__host__ __device__ constexpr size_t thomas_tile_lds(int64_t L, int tiles) {
+  return ((size_t)L * ((size_t)tiles * (kTileLines + 1) + 3) + (size_t)tiles * kTileLines) *
+         sizeof(double);
+}
+
+template <int TILES, int AXIS>
+__global__ __launch_bounds__(64 * TILES) void k_thomas_tile(double* __restrict__ x, int64_t n0,
+                                                             int64_t n1, int64_t n2,
+                                                             const double* __restrict__ ta,
+                                                             const double* __restrict__ tm,
+                                                             const double* __restrict__ tc,
+                                                             const double* __restrict__ sub) {
+  constexpr int W = kTileLines, NB = 32;
+  extern __shared__ double tsm[];
+  const int L = (int)(AXIS == 0 ? n0 : (AXIS == 1 ? n1 : n2));
+  // strided axes: [position][line] with pitch W + 1; rows: [line][position]
+  // with pitch L + 1; room for either
+  const int tile_sz = L * (W + 1) + W;
+  double* fa = tsm;
+  double* fm = fa + L;
+  double* fc = fm + L;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* T = fc + L + wave * tile_sz;
+  for (int i = tid; i < L; i += 64 * TILES) {
+    fa[i] = ta[i];
+    fm[i] = tm[i];
+    fc[i] = tc[i];
+  }
+  const int64_t tile = (int64_t)blockIdx.x * TILES + wave;
+  // first value of the tile, lines in it, distance between positions
+  int64_t base0, estride;
+  int nl;
+  bool live = true;
+  if (AXIS == 2) {
+    const int64_t r0 = tile * W, rows = n0 * n1;
+    live = r0 < rows;
+    nl = live ? (int)min<int64_t>(W, rows - r0) : 0;
+    base0 = live ? r0 * n2 : 0;
+    estride = 1;
+  } else if (AXIS == 1) {
+    const int64_t gpp = (n2 + W - 1) / W;
+    const int64_t i0 = tile / gpp, x0 = (tile - i0 * gpp) * W;
+    live = i0 < n0;
+    nl = live ? (int)min<int64_t>(W, n2 - x0) : 0;
+    base0 = live ? i0 * n1 * n2 + x0 : 0;
+    estride = n2;
+  } else {
+    const int64_t t0 = tile * W, m = n1 * n2;
+    live = t0 < m;
+    nl = live ? (int)min<int64_t>(W, m - t0) : 0;
+    base0 = live ? t0 : 0;
+    estride = m;
+  }
+  __syncthreads();  // factor tables
+  if (!live) return;
+  const int total = L * nl;  // values in the tile
+  // lane's k-th value: global address and LDS slot
+  //   rows: value e = lane + 64k of the contiguous block, line e / L
+  //   strided: line lane % 16, position lane / 16 + 4k
+  const uint64_t mL = div_magic((uint32_t)L);
+  const int jl = lane & (W - 1), il = lane >> 4;
+  const bool lane_ok = AXIS == 2 || jl < nl;
+  double* gp = x + base0 + (AXIS == 2 ? 0 : (int64_t)min(jl, nl - 1) + (int64_t)il * estride);
+  const int n_k = AXIS == 2 ? (total + 63) / 64 : (L + 3) / 4;
+  auto slot = [&](int k, int& dst) -> int64_t {  // returns the global offset from gp
+    if (AXIS == 2) {
+      const int e = min(lane + 64 * k, total - 1);
+      const int j = (int)div_small((uint32_t)e, mL);
+      dst = lane + 64 * k < total ? e + j : -1;  // j * (L + 1) + (e - j * L)
+      return e;
+    } else {
+      const int i = min(il + 4 * k, L - 1);
+      dst = lane_ok && il + 4 * k < L ? i * (W + 1) + jl : -1;
+      return (int64_t)(i - il) * estride;
+    }
+  };
+  for (int k0 = 0; k0 < n_k; k0 += NB) {
+    double v[NB];
+    int dst[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) v[u] = gp[slot(k0 + u, dst[u])];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (dst[u] >= 0) T[dst[u]] = v[u];
+  }
+  wave_fence();
+  if (lane < nl) {
+    // one line per lane; values and factors move through registers in
+    // batches of U, the next batch's LDS reads issued before the current
+    // batch's recurrence
+    constexpr int U = 8;
+    const int pitch = AXIS == 2 ? 1 : W + 1;
+    double* c = AXIS == 2 ? T + lane * (L + 1) : T + lane;
+    double v[U], a[U], m[U], nv[U], na[U], nm[U];
+    auto fwd_load = [&](int i0, double (&pv)[U], double (&pa)[U], double (&pm)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = min(i0 + u, L - 1);
+        pv[u] = c[i * pitch];
+        pa[u] = fa[i];
+        pm[u] = fm[i];
+      }
+    };
+    double prev = 0.0;
+    fwd_load(0, v, a, m);
+    for (int i0 = 0; i0 < L; i0 += U) {
+      if (i0 + U < L) fwd_load(i0 + U, nv, na, nm);
+#pragma unroll
+      // past the line's end the factors are clamped and the values unused
+      for (int u = 0; u < U; ++u) {
+        v[u] = thomas_fwd(v[u], a[u], m[u], prev);
+        prev = v[u];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u < L) c[(i0 + u) * pitch] = v[u];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = nv[u];
+        a[u] = na[u];
+        m[u] = nm[u];
+      }
+    }
+    auto bwd_load = [&](int hi, double (&pv)[U], double (&pc)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = max(hi - u, 0);
+        pv[u] = c[i * pitch];
+        pc[u] = fc[i];
+      }
+    };
+    double nxt = 0.0;
+    bwd_load(L - 1, v, a);
+    for (int hi = L - 1; hi >= 0; hi -= U) {
+      if (hi - U >= 0) bwd_load(hi - U, nv, na);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = thomas_bwd(v[u], a[u], nxt);
+        nxt = v[u];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (hi - u >= 0) c[(hi - u) * pitch] = v[u];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        v[u] = nv[u];
+        a[u] = na[u];
+      }
+    }
+  }
+  wave_fence();
+  double* gq = gp;
+  const double* sp = sub ? sub + (gp - x) : nullptr;
+  for (int k0 = 0; k0 < n_k; k0 += NB) {
+    double sv[NB];
+    int64_t off[NB];
+    int src[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      off[u] = slot(k0 + u, src[u]);
+      sv[u] = sp ? sp[off[u]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (src[u] >= 0) gq[off[u]] = sp ? sv[u] - T[src[u]] : T[src[u]];
+  }
 }
 
 template <typename Tin, bool QUANT>
@@ -1484,8 +1680,44 @@ void thomas_c(int axis, double* x, const int64_t nc[3], const AxisTab& t, const 
 }
 }  // namespace
 
+namespace {
+template <int TILES, int AXIS>
+void thomas_tiles_axis(double* x, const int64_t nc[3], const AxisTab& t, const double* sub,
+                       hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_thomas_tile<TILES, AXIS>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)thomas_tile_lds(TILES == 4 ? kThomasTile4MaxL
+                                                                : kThomasTile2MaxL, TILES)));
+    attr = true;
+  }
+  int64_t tiles;
+  if (AXIS == 2) tiles = (nc[0] * nc[1] + kTileLines - 1) / kTileLines;
+  else if (AXIS == 1) tiles = nc[0] * ((nc[2] + kTileLines - 1) / kTileLines);
+  else tiles = (nc[1] * nc[2] + kTileLines - 1) / kTileLines;
+  const int64_t blocks = (tiles + TILES - 1) / TILES;
+  hipLaunchKernelGGL((k_thomas_tile<TILES, AXIS>), dim3((unsigned)blocks), dim3(64 * TILES),
+                     thomas_tile_lds(nc[AXIS], TILES), s, x, nc[0], nc[1], nc[2], t.ta, t.tm, t.tc,
+                     sub);
+}
+template <int TILES>
+void thomas_tiles(int axis, double* x, const int64_t nc[3], const AxisTab& t, const double* sub,
+                  hipStream_t s) {
+  if (axis == 2) thomas_tiles_axis<TILES, 2>(x, nc, t, sub, s);
+  else if (axis == 1) thomas_tiles_axis<TILES, 1>(x, nc, t, sub, s);
+  else thomas_tiles_axis<TILES, 0>(x, nc, t, sub, s);
+}
+}  // namespace
+
 void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
                    const double* sub, hipStream_t s, int cand) {
+  const int64_t L = nc[axis];
+  if (cand == 0 && L <= kThomasTile2MaxL && nc[0] * nc[1] * nc[2] <= kThomasTilePoints) {
+    if (L <= kThomasTile4MaxL) thomas_tiles<4>(axis, x, nc, t, sub, s);
+    else thomas_tiles<2>(axis, x, nc, t, sub, s);
+    return;
+  }
   switch (cand) {
     case 1: thomas_c<1>(axis, x, nc, t, sub, s); break;
     case 2: thomas_c<2>(axis, x, nc, t, sub, s); break;

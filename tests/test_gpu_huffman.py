@@ -20,6 +20,7 @@ CASES = [  # (n, scale, C)
     (1, 3.0, 1024), (1000, 3.0, 1024), (1024, 3.0, 1024), (5000, 0.2, 1024),
     (100003, 40.0, 1024), (300000, 3000.0, 1024), (70000, 5.0, 64), (4097, 2.0, 128),
     (2_000_000, 9000.0, 1024),
+    (12_600_007, 3000.0, 1024),  # enough chunks for the persistent encoder
 ]
 
 
