@@ -630,7 +630,14 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
   //    rank of each symbol among equal lengths in ascending symbol order
   if (tid < 34) sm.lfirst[tid] = 0;
   __syncthreads();
-  for (unsigned i = tid; i < n; i += 1024) atomicAdd(&sm.lfirst[clen[s.symAsc[i]]], 1u);
+  // one LDS add per distinct length in each wavefront's 64 symbols
+  for (unsigned t = tid & ~63u; t < n; t += 1024) {
+    const unsigned i = t + (tid & 63);
+    const bool valid = i < n;
+    const unsigned l = valid ? clen[s.symAsc[i]] : 0u;
+    const uint64_t peers = match_digit(l, 6, valid);
+    if (valid && __popcll(peers & lanemask_lt()) == 0) atomicAdd(&sm.lfirst[l], __popcll(peers));
+  }
   __syncthreads();
   if (tid == 0) {
     unsigned c = 0, ml = 0;
@@ -742,49 +749,76 @@ __device__ __forceinline__ void layout_scan_body(const uint32_t* __restrict__ cw
   const unsigned long long oval = opos + 8ull * no;
   const unsigned long long words = oval + 8ull * no;
   uint64_t* offs = reinterpret_cast<uint64_t*>(out + off);
-  // each thread owns a contiguous run of chunks: sum it (sixteen loads in
-  // flight, clamped indices), one block scan of the sums, then the run's
-  // offsets
-  const int64_t per = (n_chunks + 1023) / 1024;
-  const int64_t c0 = min<int64_t>(n_chunks, (int64_t)tid * per);
-  const int64_t c1 = min<int64_t>(n_chunks, c0 + per);
-  unsigned long long mine = 0;
-  for (int64_t j = c0; j < c1; j += 16) {
-    unsigned v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = cw[min<int64_t>(j + u, c1 - 1)];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) mine += j + u < c1 ? v[u] : 0u;
-  }
-  // exclusive scan of the 64-bit run sums over the 1024 threads
-  unsigned long long incl = mine;
+  // batches of 16384 chunks: sub-tile s (4096 chunks) gives thread t the
+  // four consecutive chunks 4t .. 4t+3, so every load and store of a wave
+  // is contiguous; all sixteen loads of a thread are in flight together and
+  // one block scan (four values per thread) serves the whole batch
+  __shared__ unsigned wsum[16][4];
   const int wave = tid >> 6, lane = tid & 63;
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned lo = (unsigned)__shfl_up((int)(unsigned)incl, o, 64);
-    const unsigned hi = (unsigned)__shfl_up((int)(unsigned)(incl >> 32), o, 64);
-    if (lane >= o) incl += ((unsigned long long)hi << 32) | lo;
-  }
-  __shared__ unsigned long long wsum[16];
-  if (lane == 63) wsum[wave] = incl;
-  __syncthreads();
-  unsigned long long before = 0, total = 0;
-  for (int w = 0; w < 16; ++w) {
-    if (w < wave) before += wsum[w];
-    total += wsum[w];
-  }
-  unsigned long long run = before + incl - mine;
-  for (int64_t j = c0; j < c1; j += 16) {
-    unsigned v[16];
+  unsigned long long base = 0;
+  const bool vec = (reinterpret_cast<uintptr_t>(cw) & 15) == 0;
+  for (int64_t b0 = 0; b0 < n_chunks; b0 += 16384) {
+    unsigned v[4][4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = cw[min<int64_t>(j + u, c1 - 1)];
+    for (int sb = 0; sb < 4; ++sb) {
+      const int64_t e = b0 + 4096 * sb + 4 * tid;
+      if (vec && e + 3 < n_chunks) {
+        const uint4 q = *reinterpret_cast<const uint4*>(cw + e);
+        v[sb][0] = q.x;
+        v[sb][1] = q.y;
+        v[sb][2] = q.z;
+        v[sb][3] = q.w;
+      } else {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      if (j + u < c1) {
-        offs[j + u] = run;
-        run += v[u];
+        for (int u = 0; u < 4; ++u) {
+          const unsigned x = cw[min<int64_t>(e + u, n_chunks - 1)];
+          v[sb][u] = e + u < n_chunks ? x : 0u;
+        }
       }
     }
+    unsigned sum[4], incl[4];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      sum[sb] = v[sb][0] + v[sb][1] + v[sb][2] + v[sb][3];
+      incl[sb] = sum[sb];
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        const unsigned y = (unsigned)__shfl_up((int)incl[sb], o, 64);
+        if (lane >= o) incl[sb] += y;
+      }
+    }
+    if (lane == 63) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) wsum[wave][sb] = incl[sb];
+    }
+    __syncthreads();
+    unsigned before[4] = {0u, 0u, 0u, 0u}, tot[4] = {0u, 0u, 0u, 0u};
+    for (int w = 0; w < 16; ++w) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        const unsigned c = wsum[w][sb];
+        before[sb] += w < wave ? c : 0u;
+        tot[sb] += c;
+      }
+    }
+    unsigned long long run = base;
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      const int64_t e = b0 + 4096 * sb + 4 * tid;
+      unsigned long long r = run + before[sb] + (incl[sb] - sum[sb]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (e + u < n_chunks) offs[e + u] = r;
+        r += v[sb][u];
+      }
+      run += tot[sb];
+    }
+    base = run;
+    __syncthreads();
   }
+  const unsigned long long total = base;
   if (tid == 0) carry = total;
   __syncthreads();
   if (tid == 0) {
@@ -1219,10 +1253,15 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     t->valid = 0;
   }
   __syncthreads();
-  for (unsigned i = tid; i < n; i += 1024) {
-    const unsigned l = lens[i];
-    if (l < 1 || l > (unsigned)kMaxCodeLen || (i > 0 && syms[i] <= syms[i - 1])) sm.flag = 1;
-    else atomicAdd(&sm.lcount[l], 1u);
+  // one LDS add per distinct length in each wavefront's 64 codes
+  for (unsigned t = tid & ~63u; t < n; t += 1024) {
+    const unsigned i = t + (tid & 63);
+    const unsigned l = i < n ? lens[i] : 0u;
+    const bool ok = l >= 1 && l <= (unsigned)kMaxCodeLen && (i == 0 || syms[i] > syms[i - 1]);
+    if (i < n && !ok) sm.flag = 1;
+    const bool valid = i < n && ok;
+    const uint64_t peers = match_digit(valid ? l : 0u, 6, valid);
+    if (valid && __popcll(peers & lanemask_lt()) == 0) atomicAdd(&sm.lcount[l], __popcll(peers));
   }
   __syncthreads();
   __shared__ unsigned long long llim[34];
