@@ -689,6 +689,370 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
   dec_level_body<Tin, TZ, TY, TX, MODE>(G, g, fout, sym, raw, r, ob, status, t);
 }
 
+// ------------------------------- decomposition of a 3-axis level, streamed
+// A block owns a column of SY x SX coarse outputs (fine region with a
+// two-node halo in y and x) and walks a segment of coarse z planes.  Each
+// fine plane is loaded once (the next plane's loads in flight while the
+// current one is processed), restricted along x and then y; the y results of
+// the last five fine planes and the raw values of the last three stay in
+// LDS rings.  When the five planes around a coarse plane are in, its outputs
+// are restricted along z and its cells are interpolated and quantised.  The
+// sums are formed in the same order as in the tiled kernel (x, y, z; taps in
+// order), so the results are the same; the z halo is paid once per segment
+// instead of once per tile.
+constexpr int kStreamSY = 8, kStreamSX = 32;
+constexpr int kStreamE1 = 2 * kStreamSY + 3, kStreamE2 = 2 * kStreamSX + 3;
+constexpr int kStreamNLD = (kStreamE1 * kStreamE2 + 255) / 256;
+// levels with fewer fine points use the tiled kernel (measured faster there)
+constexpr int64_t kStreamMinPoints = int64_t(1) << 25;
+
+template <typename Tin>
+struct StreamSmem {
+  Tin raw[3][kStreamE1][kStreamE2];
+  double X[kStreamE1][kStreamSX];
+  double Y[5][kStreamSY][kStreamSX];
+  double wl1[kStreamE1], wr1[kStreamE1], wl2[kStreamE2], wr2[kStreamE2];
+  double W1[kStreamSY][5], W2[kStreamSX][5];
+  int P1[kStreamSY], P2[kStreamSX];
+  uint32_t soff[8];
+};
+
+template <typename Tin, bool QUANT>
+__global__ __launch_bounds__(256) void k_dec_stream(const Tin* __restrict__ G, const LevelGeom g,
+                                                     double* __restrict__ fout,
+                                                     uint16_t* __restrict__ sym,
+                                                     double* __restrict__ raw, const double r,
+                                                     const OutlierBuf ob,
+                                                     unsigned* __restrict__ status, const int seg,
+                                                     const uint32_t n_blocks) {
+  constexpr int SY = kStreamSY, SX = kStreamSX, E1 = kStreamE1, E2 = kStreamE2;
+  __shared__ StreamSmem<Tin> sm;
+  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+  if (b >= n_blocks) return;
+  const uint32_t nf0 = (uint32_t)g.nf[0], nf1 = (uint32_t)g.nf[1], nf2 = (uint32_t)g.nf[2];
+  const uint32_t nc0 = (uint32_t)g.nc[0], nc1 = (uint32_t)g.nc[1], nc2 = (uint32_t)g.nc[2];
+  const uint32_t tiles_x = (nc2 + SX - 1) / SX, tiles_y = (nc1 + SY - 1) / SY;
+  const uint32_t tx = b % tiles_x, rest = b / tiles_x;
+  const uint32_t ty = rest % tiles_y, sg = rest / tiles_y;
+  const uint32_t c0y = ty * SY, c0x = tx * SX;
+  const int tky = (int)min<uint32_t>(SY, nc1 - c0y), tkx = (int)min<uint32_t>(SX, nc2 - c0x);
+  const uint32_t py0 = cpos32(c0y, nf1), px0 = cpos32(c0x, nf2);
+  const uint32_t lo1 = py0 >= 2 ? py0 - 2 : 0, lo2 = px0 >= 2 ? px0 - 2 : 0;
+  const int ext1 = (int)(min<uint32_t>(cpos32(c0y + tky - 1, nf1) + 2, nf1 - 1) - lo1 + 1);
+  const int ext2 = (int)(min<uint32_t>(cpos32(c0x + tkx - 1, nf2) + 2, nf2 - 1) - lo2 + 1);
+  const uint32_t cz0 = sg * (uint32_t)seg, cz1 = min<uint32_t>(cz0 + seg, nc0);
+  const uint32_t pz0 = cpos32(cz0, nf0);
+  const uint32_t zs = pz0 >= 2 ? pz0 - 2 : 0;
+  const uint32_t ze = min<uint32_t>(cpos32(cz1 - 1, nf0) + 2, nf0 - 1);
+  const int tid = threadIdx.x;
+  // per-block tables
+  for (int i = tid; i < ext1; i += 256) {
+    sm.wl1[i] = g.ax[1].wl[lo1 + i];
+    sm.wr1[i] = g.ax[1].wr[lo1 + i];
+  }
+  for (int i = tid; i < ext2; i += 256) {
+    sm.wl2[i] = g.ax[2].wl[lo2 + i];
+    sm.wr2[i] = g.ax[2].wr[lo2 + i];
+  }
+  for (int i = tid; i < 5 * tky; i += 256) sm.W1[i / 5][i % 5] = g.ax[1].W[5 * c0y + i];
+  for (int i = tid; i < 5 * tkx; i += 256) sm.W2[i / 5][i % 5] = g.ax[2].W[5 * c0x + i];
+  for (int i = tid; i < tky; i += 256) sm.P1[i] = (int)(cpos32(c0y + i, nf1) - lo1);
+  for (int i = tid; i < tkx; i += 256) sm.P2[i] = (int)(cpos32(c0x + i, nf2) - lo2);
+  if (tid < 8) sm.soff[tid] = (uint32_t)(tid == 0 ? 0 : g.sub_off[tid]);
+  // the lane's values of a plane: offsets inside the plane and LDS slots
+  const int n_pl = ext1 * ext2;
+  const uint64_t m2 = div_magic((uint32_t)ext2);
+  uint32_t goff[kStreamNLD];
+  int ldst[kStreamNLD];
+#pragma unroll
+  for (int u = 0; u < kStreamNLD; ++u) {
+    const int e = min(u * 256 + tid, n_pl - 1);
+    const int y = (int)div_small((uint32_t)e, m2), x = e - y * ext2;
+    goff[u] = (lo1 + y) * nf2 + lo2 + x;
+    ldst[u] = u * 256 + tid < n_pl ? y * E2 + x : -1;
+  }
+  const size_t plane = (size_t)nf1 * nf2;
+  Tin pv[kStreamNLD];
+  auto load_plane = [&](uint32_t z) {
+    const Tin* src = G + (size_t)z * plane;
+#pragma unroll
+    for (int u = 0; u < kStreamNLD; ++u) pv[u] = src[goff[u]];
+  };
+  // x pass: thread column cx, rows y = rsub, rsub + 8, ...
+  const int xcol = tid & 31, xrow = tid >> 5;
+  int xf[5];
+  double xw[5];
+  {
+    __syncthreads();  // tables
+    const int p = xcol < tkx ? sm.P2[xcol] : 0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      xf[d] = min(max(p + d - 2, 0), ext2 - 1);
+      xw[d] = xcol < tkx ? sm.W2[xcol][d] : 0.0;
+    }
+  }
+  // y pass / z pass / cells: thread (cy, cx)
+  const int ocy = tid >> 5, ocx = tid & 31;
+  const bool own = ocy < tky && ocx < tkx;
+  int yf[5];
+  double yw[5];
+  {
+    const int p = own ? sm.P1[ocy] : 0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      yf[d] = min(max(p + d - 2, 0), ext1 - 1);
+      yw[d] = own ? sm.W1[ocy][d] : 0.0;
+    }
+  }
+  // cell geometry along y and x (fixed per thread)
+  const uint32_t J1 = c0y + ocy, J2 = c0x + ocx;
+  const bool h1 = own && 2 * J1 + 1 < nf1 - 1, h2 = own && 2 * J2 + 1 < nf2 - 1;
+  const int p1 = own ? (int)(cpos32(J1, nf1) - lo1) : 0, p2 = own ? (int)(cpos32(J2, nf2) - lo2) : 0;
+  const int q1 = h1 ? p1 + 1 : p1, q2 = h2 ? p2 + 1 : p2;
+  const int s1 = h1 ? p1 + 2 : p1, s2 = h2 ? p2 + 2 : p2;
+  const double wy0 = sm.wl1[q1], wy1 = sm.wr1[q1], wx0 = sm.wl2[q2], wx1 = sm.wr2[q2];
+  const uint32_t e1c = nc1, e1n = nf1 - nc1, e2c = nc2, e2n = nf2 - nc2;
+  const uint32_t lvl = (uint32_t)g.level_off;
+  const int m0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, m1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
+            m2b = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
+  uint32_t next_cz = cz0;
+  load_plane(zs);
+  for (uint32_t zf = zs; zf <= ze; ++zf) {
+    const int s3 = (int)(zf % 3u), s5 = (int)(zf % 5u);
+#pragma unroll
+    for (int u = 0; u < kStreamNLD; ++u)
+      if (ldst[u] >= 0) (&sm.raw[s3][0][0])[ldst[u]] = pv[u];
+    if (zf < ze) load_plane(zf + 1);
+    __syncthreads();
+    if (xcol < tkx) {
+      for (int y = xrow; y < ext1; y += 8) {
+        const Tin* row = sm.raw[s3][y];
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) acc += xw[d] * (double)row[xf[d]];
+        sm.X[y][xcol] = acc;
+      }
+    }
+    __syncthreads();
+    if (own) {
+      double acc = 0.0;
+#pragma unroll
+      for (int d = 0; d < 5; ++d) acc += yw[d] * sm.X[yf[d]][ocx];
+      sm.Y[s5][ocy][ocx] = acc;
+    }
+    __syncthreads();
+    // coarse planes whose last fine plane is this one
+    while (next_cz < cz1 && min<uint32_t>(cpos32(next_cz, nf0) + 2, nf0 - 1) == zf) {
+      const uint32_t J0 = next_cz;
+      const uint32_t P0 = cpos32(J0, nf0);
+      const bool h0 = 2 * J0 + 1 < nf0 - 1;
+      const double* W0 = g.ax[0].W + 5 * (size_t)J0;
+      if (own) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+          const int zz = min(max((int)P0 + d - 2, 0), (int)nf0 - 1);
+          acc += W0[d] * sm.Y[zz % 5][ocy][ocx];
+        }
+        fout[((size_t)J0 * nc1 + J1) * nc2 + J2] = acc;
+      }
+      if (own && (h0 || h1 || h2)) {
+        const int r0 = (int)(P0 % 3u), rq = (int)((h0 ? P0 + 1 : P0) % 3u),
+                  rs = (int)((h0 ? P0 + 2 : P0) % 3u);
+        const double wz0 = h0 ? g.ax[0].wl[P0 + 1] : 1.0, wz1 = h0 ? g.ax[0].wr[P0 + 1] : 0.0;
+        auto T = [&](int pz, int y, int x) -> double { return (double)sm.raw[pz][y][x]; };
+        const double c000 = T(r0, p1, p2), c001 = T(r0, p1, s2), c010 = T(r0, s1, p2),
+                     c011 = T(r0, s1, s2), c100 = T(rs, p1, p2), c101 = T(rs, p1, s2),
+                     c110 = T(rs, s1, p2), c111 = T(rs, s1, s2);
+        const double ix00 = wx0 * c000 + wx1 * c001, ix01 = wx0 * c010 + wx1 * c011;
+        const double ix10 = wx0 * c100 + wx1 * c101, ix11 = wx0 * c110 + wx1 * c111;
+        const uint32_t base_cc = (J0 * e1c + J1) * e2c + J2, base_cn = (J0 * e1c + J1) * e2n + J2;
+        const uint32_t base_nc = (J0 * e1n + J1) * e2c + J2, base_nn = (J0 * e1n + J1) * e2n + J2;
+        auto emit = [&](uint32_t pos, double v) {
+          if (QUANT) emit_q(pos, v, r, sym, ob, status);
+          else raw[pos] = v;
+        };
+        if (h2) emit(lvl + sm.soff[m2b] + base_cn, T(r0, p1, q2) - ix00);
+        if (h1) emit(lvl + sm.soff[m1] + base_nc, T(r0, q1, p2) - (wy0 * c000 + wy1 * c010));
+        if (h1 && h2)
+          emit(lvl + sm.soff[m1 | m2b] + base_nn, T(r0, q1, q2) - (wy0 * ix00 + wy1 * ix01));
+        if (h0) emit(lvl + sm.soff[m0] + base_cc, T(rq, p1, p2) - (wz0 * c000 + wz1 * c100));
+        if (h0 && h2)
+          emit(lvl + sm.soff[m0 | m2b] + base_cn, T(rq, p1, q2) - (wz0 * ix00 + wz1 * ix10));
+        if (h0 && h1)
+          emit(lvl + sm.soff[m0 | m1] + base_nc,
+               T(rq, q1, p2) - (wz0 * (wy0 * c000 + wy1 * c010) + wz1 * (wy0 * c100 + wy1 * c110)));
+        if (h0 && h1 && h2)
+          emit(lvl + sm.soff[m0 | m1 | m2b] + base_nn,
+               T(rq, q1, q2) - (wz0 * (wy0 * ix00 + wy1 * ix01) + wz1 * (wy0 * ix10 + wy1 * ix11)));
+      }
+      ++next_cz;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------ recomposition restriction of a 3-axis level, streamed
+// f = (P^T M_l) c_l with the same z streaming as k_dec_stream: each fine
+// plane of the block's region is assembled from the dequantised coefficients
+// (zero at the nodes coarse along every axis) and restricted along x and y;
+// the y results of the last five planes stay in an LDS ring for the z pass.
+// A lane's region slots are fixed, so a coefficient's stream position is a
+// per-slot base (for the plane's new or coarse z) plus j0 times the
+// subband's plane stride.
+struct RecStreamSmem {
+  double P[kStreamE1][kStreamE2];
+  double X[kStreamE1][kStreamSX];
+  double Y[5][kStreamSY][kStreamSX];
+  double W1[kStreamSY][5], W2[kStreamSX][5];
+  int P1[kStreamSY], P2[kStreamSX];
+};
+
+template <bool RAW>
+__global__ __launch_bounds__(256) void k_rec_stream(const LevelGeom g, const CoeffSrc src,
+                                                     const double q, double* __restrict__ fout,
+                                                     const int seg, const uint32_t n_blocks) {
+  constexpr int SY = kStreamSY, SX = kStreamSX, E2 = kStreamE2;
+  __shared__ RecStreamSmem sm;
+  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+  if (b >= n_blocks) return;
+  const uint32_t nf0 = (uint32_t)g.nf[0], nf1 = (uint32_t)g.nf[1], nf2 = (uint32_t)g.nf[2];
+  const uint32_t nc0 = (uint32_t)g.nc[0], nc1 = (uint32_t)g.nc[1], nc2 = (uint32_t)g.nc[2];
+  const uint32_t tiles_x = (nc2 + SX - 1) / SX, tiles_y = (nc1 + SY - 1) / SY;
+  const uint32_t tx = b % tiles_x, rest = b / tiles_x;
+  const uint32_t ty = rest % tiles_y, sg = rest / tiles_y;
+  const uint32_t c0y = ty * SY, c0x = tx * SX;
+  const int tky = (int)min<uint32_t>(SY, nc1 - c0y), tkx = (int)min<uint32_t>(SX, nc2 - c0x);
+  const uint32_t py0 = cpos32(c0y, nf1), px0 = cpos32(c0x, nf2);
+  const uint32_t lo1 = py0 >= 2 ? py0 - 2 : 0, lo2 = px0 >= 2 ? px0 - 2 : 0;
+  const int ext1 = (int)(min<uint32_t>(cpos32(c0y + tky - 1, nf1) + 2, nf1 - 1) - lo1 + 1);
+  const int ext2 = (int)(min<uint32_t>(cpos32(c0x + tkx - 1, nf2) + 2, nf2 - 1) - lo2 + 1);
+  const uint32_t cz0 = sg * (uint32_t)seg, cz1 = min<uint32_t>(cz0 + seg, nc0);
+  const uint32_t pz0 = cpos32(cz0, nf0);
+  const uint32_t zs = pz0 >= 2 ? pz0 - 2 : 0;
+  const uint32_t ze = min<uint32_t>(cpos32(cz1 - 1, nf0) + 2, nf0 - 1);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 5 * tky; i += 256) sm.W1[i / 5][i % 5] = g.ax[1].W[5 * c0y + i];
+  for (int i = tid; i < 5 * tkx; i += 256) sm.W2[i / 5][i % 5] = g.ax[2].W[5 * c0x + i];
+  for (int i = tid; i < tky; i += 256) sm.P1[i] = (int)(cpos32(c0y + i, nf1) - lo1);
+  for (int i = tid; i < tkx; i += 256) sm.P2[i] = (int)(cpos32(c0x + i, nf2) - lo2);
+  // the lane's region slots: stream position = pbase[n0] + j0 * pstride
+  // (n0: the plane's z is a new node); coarse along all axes -> no value
+  const int n_pl = ext1 * ext2;
+  const uint64_t m2 = div_magic((uint32_t)ext2);
+  const uint32_t e1c = nc1, e1n = nf1 - nc1, e2c = nc2, e2n = nf2 - nc2;
+  const int mb0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, mb1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
+            mb2 = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
+  uint32_t so[8];
+  subband_offsets(g, so);
+  const uint32_t lvl = (uint32_t)g.level_off;
+  uint32_t pbase[kStreamNLD][2], pstride[kStreamNLD];
+  int ldst[kStreamNLD];
+  bool yxnew[kStreamNLD];
+#pragma unroll
+  for (int u = 0; u < kStreamNLD; ++u) {
+    const int e = min(u * 256 + tid, n_pl - 1);
+    const int y = (int)div_small((uint32_t)e, m2), x = e - y * ext2;
+    const uint32_t i1 = lo1 + y, i2 = lo2 + x;
+    const bool n1 = is_new32(i1, nf1), n2 = is_new32(i2, nf2);
+    const uint32_t j1 = n1 ? (i1 >> 1) : cidx32(i1, nf1);
+    const uint32_t j2 = n2 ? (i2 >> 1) : cidx32(i2, nf2);
+    const uint32_t ex1 = n1 ? e1n : e1c, ex2 = n2 ? e2n : e2c;
+    const int myx = (n1 ? mb1 : 0) | (n2 ? mb2 : 0);
+    pstride[u] = ex1 * ex2;
+    pbase[u][0] = lvl + sel8(so, myx) + j1 * ex2 + j2;
+    pbase[u][1] = lvl + sel8(so, myx | mb0) + j1 * ex2 + j2;
+    yxnew[u] = n1 || n2;
+    ldst[u] = u * 256 + tid < n_pl ? y * E2 + x : -1;
+  }
+  const int xcol = tid & 31, xrow = tid >> 5;
+  int xf[5];
+  double xw[5];
+  __syncthreads();  // tables
+  {
+    const int p = xcol < tkx ? sm.P2[xcol] : 0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      xf[d] = min(max(p + d - 2, 0), ext2 - 1);
+      xw[d] = xcol < tkx ? sm.W2[xcol][d] : 0.0;
+    }
+  }
+  const int ocy = tid >> 5, ocx = tid & 31;
+  const bool own = ocy < tky && ocx < tkx;
+  int yf[5];
+  double yw[5];
+  {
+    const int p = own ? sm.P1[ocy] : 0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      yf[d] = min(max(p + d - 2, 0), ext1 - 1);
+      yw[d] = own ? sm.W1[ocy][d] : 0.0;
+    }
+  }
+  const uint32_t J1 = c0y + ocy, J2 = c0x + ocx;
+  // coefficient loads of a plane (symbols or FP64 values), all in flight
+  uint32_t sv[kStreamNLD], pos[kStreamNLD];
+  double rv[kStreamNLD];
+  bool has[kStreamNLD];
+  auto load_plane = [&](uint32_t z) {
+    const bool n0 = is_new32(z, nf0);
+    const uint32_t j0 = n0 ? (z >> 1) : cidx32(z, nf0);
+#pragma unroll
+    for (int u = 0; u < kStreamNLD; ++u) {
+      has[u] = ldst[u] >= 0 && (n0 || yxnew[u]);
+      pos[u] = has[u] ? pbase[u][n0 ? 1 : 0] + j0 * pstride[u] : 0u;
+      if (RAW) rv[u] = src.raw[pos[u]];
+      else sv[u] = src.sym[pos[u]];
+    }
+  };
+  uint32_t next_cz = cz0;
+  load_plane(zs);
+  for (uint32_t zf = zs; zf <= ze; ++zf) {
+    const int s5 = (int)(zf % 5u);
+#pragma unroll
+    for (int u = 0; u < kStreamNLD; ++u) {
+      if (ldst[u] < 0) continue;
+      double v = 0.0;
+      if (has[u]) v = RAW ? rv[u] : dequant(src, sv[u], pos[u], q);
+      (&sm.P[0][0])[ldst[u]] = v;
+    }
+    __syncthreads();
+    if (zf < ze) load_plane(zf + 1);
+    if (xcol < tkx) {
+      for (int y = xrow; y < ext1; y += 8) {
+        const double* row = sm.P[y];
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) acc += xw[d] * row[xf[d]];
+        sm.X[y][xcol] = acc;
+      }
+    }
+    __syncthreads();
+    if (own) {
+      double acc = 0.0;
+#pragma unroll
+      for (int d = 0; d < 5; ++d) acc += yw[d] * sm.X[yf[d]][ocx];
+      sm.Y[s5][ocy][ocx] = acc;
+    }
+    __syncthreads();
+    while (next_cz < cz1 && min<uint32_t>(cpos32(next_cz, nf0) + 2, nf0 - 1) == zf) {
+      const uint32_t J0 = next_cz;
+      const uint32_t P0 = cpos32(J0, nf0);
+      const double* W0 = g.ax[0].W + 5 * (size_t)J0;
+      if (own) {
+        double acc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+          const int zz = min(max((int)P0 + d - 2, 0), (int)nf0 - 1);
+          acc += W0[d] * sm.Y[zz % 5][ocy][ocx];
+        }
+        fout[((size_t)J0 * nc1 + J1) * nc2 + J2] = acc;
+      }
+      ++next_cz;
+    }
+  }
+}
+
 // --------------------------------------------- recomposition of one level
 // f = (P^T M_l) c_l: the tile holds the dequantised coefficients (zero at the
 // coarse nodes); then the same separable restriction.
@@ -1549,6 +1913,29 @@ TileGrid tile_grid(const LevelGeom& g, int tz, int ty, int tx) {
   return t;
 }
 
+// Blocks of the z-streamed level kernels: (y, x) columns times z segments,
+// at most one block per resident slot (four per CU) so that every block runs
+// in the same pass; a segment is at least 8 coarse planes long (its 3-plane
+// halo then costs at most 3/16 of the planes).
+struct StreamGrid {
+  int seg;
+  uint32_t n_blocks;
+  unsigned grid;
+};
+
+StreamGrid stream_grid(const LevelGeom& g) {
+  const int64_t tiles_x = (g.nc[2] + kStreamSX - 1) / kStreamSX;
+  const int64_t tiles_y = (g.nc[1] + kStreamSY - 1) / kStreamSY;
+  const int64_t cols = tiles_x * tiles_y;
+  const int64_t want = std::max<int64_t>(1, std::min<int64_t>(g.nc[0], 1024 / cols));
+  StreamGrid sg;
+  sg.seg = (int)std::min<int64_t>(g.nc[0], std::max<int64_t>(8, (g.nc[0] + want - 1) / want));
+  const int64_t segs = (g.nc[0] + sg.seg - 1) / sg.seg;
+  sg.n_blocks = (uint32_t)(cols * segs);
+  sg.grid = (sg.n_blocks + 7) & ~7u;
+  return sg;
+}
+
 int active_axes(const LevelGeom& g) {
   return (g.bit[0] >= 0) + (g.bit[1] >= 0) + (g.bit[2] >= 0);
 }
@@ -1568,6 +1955,12 @@ void dec_dispatch(const void* G, const LevelGeom& g, double* fout, uint16_t* sym
                   int cand = 0) {
   const Tin* Gp = static_cast<const Tin*>(G);
   const int D = active_axes(g);
+  if (D == 3 && MODE != 2 && cand == 0 && g.nf[0] * g.nf[1] * g.nf[2] >= kStreamMinPoints) {
+    const StreamGrid sg = stream_grid(g);
+    hipLaunchKernelGGL((k_dec_stream<Tin, MODE == 0>), dim3(sg.grid), dim3(256), 0, s, Gp, g, fout,
+                       sym, raw, r, ob, status, sg.seg, sg.n_blocks);
+    return;
+  }
   if (D == 3) {
     if (MODE == 2) cand = 0;
     switch (cand) {
@@ -1593,6 +1986,12 @@ template <bool RAW>
 void rec_restrict_dispatch(const LevelGeom& g, const CoeffSrc& src, double q, double* fout,
                            hipStream_t s) {
   const int D = active_axes(g);
+  if (D == 3 && g.nf[0] * g.nf[1] * g.nf[2] >= kStreamMinPoints) {
+    const StreamGrid sg = stream_grid(g);
+    hipLaunchKernelGGL((k_rec_stream<RAW>), dim3(sg.grid), dim3(256), 0, s, g, src, q, fout,
+                       sg.seg, sg.n_blocks);
+    return;
+  }
   if (D == 3) {
     const TileGrid t = tile_grid(g, 4, 8, 8);
     hipLaunchKernelGGL((k_rec_restrict<4, 8, 8, RAW>), dim3(t.grid), dim3(256), 0, s, g, src, q,

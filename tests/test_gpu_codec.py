@@ -153,6 +153,34 @@ def test_repeat_calls_are_deterministic():
     assert a == b
 
 
+def test_streamed_level_kernel_matches_tiled():
+    """Levels of >= 2^25 points use the z-streamed decomposition kernel; the
+    tiled kernel (forced candidate 1) must give the same stream and the same
+    FP64 coefficients, bit for bit."""
+    torch, mgc = gpu()
+    gen = torch.Generator(device="cuda").manual_seed(17)
+    x = torch.randn((65, 513, 1025), generator=gen, device="cuda", dtype=torch.float32)
+    x += torch.linspace(-3.0, 3.0, 1025, device="cuda")
+    streamed = mgc.compress(x, 1e-3)
+    coeff_s = mgc.decompose(x)
+    mgc.set_tuning("dec_f32", 1)
+    try:
+        tiled = mgc.compress(x, 1e-3)
+        coeff_t = mgc.decompose(x)
+    finally:
+        mgc.set_tuning("dec_f32", -1)
+    assert streamed.numel() == tiled.numel() and bool((streamed == tiled).all())
+    assert bool((coeff_s == coeff_t).all())
+    # the streamed recomposition restriction: exact inversion without
+    # quantisation, and the decompressed field within the bound
+    back = mgc.recompose(coeff_s, tuple(x.shape), dtype=torch.float64)
+    err = torch.max(torch.abs(back - x.double())).item()
+    assert err <= 1e-12 * torch.max(torch.abs(x)).item()
+    y = mgc.decompress(streamed)
+    tau = 1e-3 * (x.max() - x.min()).item()
+    assert torch.max(torch.abs(y.double() - x.double())).item() <= tau
+
+
 @pytest.mark.parametrize("rel", [1e-2, 1e-3, 1e-4])
 def test_full_size_513(rel):
     """The benchmark's configuration: 513^3 FP32 |k|^-3 field."""
