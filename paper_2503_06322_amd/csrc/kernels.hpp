@@ -28,7 +28,7 @@ inline TileShape dec_tile(int D, bool f32, int cand) {
 // segment length on the contiguous axis (entry 0 is the plain default).
 constexpr int kThomasCands = 3;
 constexpr int kThomasU[kThomasCands] = {16, 8, 4};
-constexpr int kThomasSeg[kThomasCands] = {16, 32, 64};
+constexpr int kThomasSeg[kThomasCands] = {16, 32, 8};
 
 // ---- transform.hip -------------------------------------------------------
 // Blocks of the range pre-pass: a function of N alone, so that the sum of

@@ -1367,75 +1367,70 @@ __device__ __forceinline__ void thomas_strided_body(double* __restrict__ x, int6
     base = t;
   }
   // each sweep keeps the next batch's loads in flight while it runs the
-  // recurrence over the current batch (indices clamped: loads are never
-  // behind a branch); the batches a sweep reads ahead are not yet written
+  // recurrence over the current batch.  Two register buffers alternate in
+  // fixed roles (the loop takes two batches per iteration) and every load is
+  // issued unconditionally from a clamped index, so no copy of freshly
+  // loaded registers makes the wavefront wait for them; the batches a sweep
+  // reads ahead are not yet written.
   double* p = x + base;
   const double* ps = sub ? sub + base : nullptr;
   const int64_t last = len - 1;
+  double va[U], vb[U], sa[U], sb[U];
+  auto fload = [&](int64_t i0, double (&v)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = p[min<int64_t>(i0 + u, last) * stride];
+  };
   double prev = 0.0;
-  double v[U], nv[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) v[u] = p[min<int64_t>(u, last) * stride];
-  for (int64_t i0 = 0; i0 < len; i0 += U) {
-    const bool more = i0 + U < len;
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) nv[u] = p[min<int64_t>(i0 + U + u, last) * stride];
-    }
+  auto fsweep = [&](int64_t i0, double (&v)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + u;
-      if (i < len) {
-        v[u] = thomas_fwd(v[u], ta[i], tm[i], prev);
-        prev = v[u];
-      }
+      const int64_t i = min<int64_t>(i0 + u, last);
+      v[u] = thomas_fwd(v[u], ta[i], tm[i], prev);
+      prev = v[u];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (i0 + u < len) p[(i0 + u) * stride] = v[u];
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = nv[u];
-    }
+  };
+  fload(0, va);
+  for (int64_t i0 = 0; i0 < len; i0 += 2 * U) {
+    fload(i0 + U, vb);
+    fsweep(i0, va);
+    if (i0 + U >= len) break;
+    fload(i0 + 2 * U, va);
+    fsweep(i0 + U, vb);
   }
-  double nxt = 0.0;
-  double sv[U], nsv[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t i = max<int64_t>(last - u, 0);
-    v[u] = p[i * stride];
-    sv[u] = ps ? ps[i * stride] : 0.0;
-  }
-  for (int64_t hi = last; hi >= 0; hi -= U) {
-    const bool more = hi - U >= 0;
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t i = max<int64_t>(hi - U - u, 0);
-        nv[u] = p[i * stride];
-        nsv[u] = ps ? ps[i * stride] : 0.0;
-      }
-    }
+  // backward: batch k covers i = hi, hi-1, ..., hi-U+1 (indices below 0 are
+  // clamped reads whose results are not stored)
+  auto bload = [&](int64_t hi, double (&v)[U], double (&sv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t i = hi - u;
-      if (i >= 0) {
-        v[u] = thomas_bwd(v[u], tc[i], nxt);
-        nxt = v[u];
-      }
+      const int64_t i = max<int64_t>(hi - u, 0);
+      v[u] = p[i * stride];
+      sv[u] = ps ? ps[i * stride] : 0.0;
+    }
+  };
+  double nxt = 0.0;
+  auto bsweep = [&](int64_t hi, double (&v)[U], const double (&sv)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = max<int64_t>(hi - u, 0);
+      v[u] = thomas_bwd(v[u], tc[i], nxt);
+      nxt = v[u];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = hi - u;
       if (i >= 0) p[i * stride] = ps ? sv[u] - v[u] : v[u];
     }
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        v[u] = nv[u];
-        sv[u] = nsv[u];
-      }
-    }
+  };
+  bload(last, va, sa);
+  for (int64_t hi = last; hi >= 0; hi -= 2 * U) {
+    bload(hi - U, vb, sb);
+    bsweep(hi, va, sa);
+    if (hi - U < 0) break;
+    bload(hi - 2 * U, va, sa);
+    bsweep(hi - U, vb, sb);
   }
 }
 
@@ -1481,29 +1476,34 @@ __device__ __forceinline__ void thomas_rows_body(double* __restrict__ x, int64_t
   // real row and are never stored): under a lane-dependent branch the
   // compiler may move the factor loads into it, and a lane read back by
   // readlane would then be one that never loaded.
-  auto seg_load = [&](int64_t s0, int ns, double (&v)[K], double& fa, double& fm, double& fc,
-                      const double* src2, double (&w)[K]) {
-    const int64_t cc = s0 + min(c, ns - 1);
+  // Segments move through two register sets in fixed roles (the loops take
+  // two segments per iteration): the next segment's loads are in flight
+  // while the current one is solved, and no copy of freshly loaded
+  // registers makes the wavefront wait for them.  Indices are clamped to the
+  // row, so a segment past either end reads valid, unused values.
+  struct SegRegs {
+    double v[K], w[K], fa, fm, fc;
+  };
+  auto seg_load = [&](int64_t s0, SegRegs& R, const double* src2) {
+    const int64_t cc = min<int64_t>(max<int64_t>(s0, 0) + c, n - 1);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int j = min(jr + k * RP, nr - 1);
-      v[k] = x[(r0 + j) * n + cc];
-      if (src2) w[k] = src2[(r0 + j) * n + cc];
+      R.v[k] = x[(r0 + j) * n + cc];
+      if (src2) R.w[k] = src2[(r0 + j) * n + cc];
     }
-    fa = ta[cc];
-    fm = tm[cc];
-    fc = tc[cc];
+    R.fa = ta[cc];
+    R.fm = tm[cc];
+    R.fc = tc[cc];
   };
   double prev = 0.0;
-  for (int64_t s0 = 0; s0 < n; s0 += SEG) {
+  auto fwd_seg = [&](int64_t s0, const SegRegs& R) {
     const int ns = (int)min<int64_t>(SEG, n - s0);
-    double v[K], w[K], fa, fm, fc;
-    seg_load(s0, ns, v, fa, fm, fc, nullptr, w);
 #pragma unroll
-    for (int k = 0; k < K; ++k) buf[jr + k * RP][c] = v[k];
+    for (int k = 0; k < K; ++k) buf[jr + k * RP][c] = R.v[k];
     __syncthreads();
     for (int i = 0; i < ns; ++i) {
-      const double a = readlane_d(fa, i), m = readlane_d(fm, i);
+      const double a = readlane_d(R.fa, i), m = readlane_d(R.fm, i);
       const double y = thomas_fwd(buf[lane][i], a, m, prev);
       buf[lane][i] = y;
       prev = y;
@@ -1515,17 +1515,15 @@ __device__ __forceinline__ void thomas_rows_body(double* __restrict__ x, int64_t
       if (j < nr && c < ns) x[(r0 + j) * n + s0 + c] = buf[j][c];
     }
     __syncthreads();
-  }
+  };
   double nxt = 0.0;
-  for (int64_t s0 = ((n - 1) / SEG) * SEG; s0 >= 0; s0 -= SEG) {
+  auto bwd_seg = [&](int64_t s0, const SegRegs& R) {
     const int ns = (int)min<int64_t>(SEG, n - s0);
-    double v[K], w[K], fa, fm, fc;
-    seg_load(s0, ns, v, fa, fm, fc, sub, w);
 #pragma unroll
-    for (int k = 0; k < K; ++k) buf[jr + k * RP][c] = v[k];
+    for (int k = 0; k < K; ++k) buf[jr + k * RP][c] = R.v[k];
     __syncthreads();
     for (int i = ns - 1; i >= 0; --i) {
-      const double cf = readlane_d(fc, i);
+      const double cf = readlane_d(R.fc, i);
       const double y = thomas_bwd(buf[lane][i], cf, nxt);
       buf[lane][i] = y;
       nxt = y;
@@ -1536,10 +1534,28 @@ __device__ __forceinline__ void thomas_rows_body(double* __restrict__ x, int64_t
       const int j = jr + k * RP;
       if (j < nr && c < ns) {
         const int64_t gi = (r0 + j) * n + s0 + c;
-        x[gi] = sub ? w[k] - buf[j][c] : buf[j][c];
+        x[gi] = sub ? R.w[k] - buf[j][c] : buf[j][c];
       }
     }
     __syncthreads();
+  };
+  SegRegs A, B;
+  seg_load(0, A, nullptr);
+  for (int64_t s0 = 0; s0 < n; s0 += 2 * SEG) {
+    seg_load(s0 + SEG, B, nullptr);
+    fwd_seg(s0, A);
+    if (s0 + SEG >= n) break;
+    seg_load(s0 + 2 * SEG, A, nullptr);
+    fwd_seg(s0 + SEG, B);
+  }
+  const int64_t sl = ((n - 1) / SEG) * SEG;
+  seg_load(sl, A, sub);
+  for (int64_t s0 = sl; s0 >= 0; s0 -= 2 * SEG) {
+    seg_load(s0 - SEG, B, sub);
+    bwd_seg(s0, A);
+    if (s0 - SEG < 0) break;
+    seg_load(s0 - 2 * SEG, A, sub);
+    bwd_seg(s0 - SEG, B);
   }
 }
 
