@@ -218,11 +218,16 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
       launch_dec_level(Gcur, cur_f32, g, Gnext, sym, raw, sym ? r[l] : 0.0, ob, status, s,
                        tuned(ctx, cur_f32 ? MGC_TUNE_DEC_F32 : MGC_TUNE_DEC_F64));
     }
-    for (int axis = 2; axis >= 0; --axis) {
-      if (p.bit[axis] < 0) continue;
-      StageScope sc(&ctx->prof, l == p.L ? kThomasFinest[axis] : "thomas", s);
-      launch_thomas(axis, Gnext, g.nc, g.ax[axis], nullptr, s,
-                    tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED));
+    if (thomas_grid_fits(g)) {
+      StageScope sc(&ctx->prof, l == p.L ? "thomas[finest]" : "thomas", s);
+      launch_thomas_grid(Gnext, g, nullptr, s);
+    } else {
+      for (int axis = 2; axis >= 0; --axis) {
+        if (p.bit[axis] < 0) continue;
+        StageScope sc(&ctx->prof, l == p.L ? kThomasFinest[axis] : "thomas", s);
+        launch_thomas(axis, Gnext, g.nc, g.ax[axis], nullptr, s,
+                      tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED));
+      }
     }
     Gcur = Gnext;
     cur_f32 = false;
@@ -267,11 +272,16 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
       StageScope sc(&ctx->prof, fin ? "rec_restrict[finest]" : "rec_restrict", s);
       launch_rec_restrict(g, src, q[l], F, s);
     }
-    for (int axis = 2; axis >= 0; --axis) {
-      if (p.bit[axis] < 0) continue;
-      StageScope sc(&ctx->prof, fin ? kThomasFinest[axis] : "thomas", s);
-      launch_thomas(axis, F, g.nc, g.ax[axis], axis == last ? Gprev : nullptr, s,
-                    tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED));
+    if (thomas_grid_fits(g)) {
+      StageScope sc(&ctx->prof, fin ? "thomas[finest]" : "thomas", s);
+      launch_thomas_grid(F, g, Gprev, s);
+    } else {
+      for (int axis = 2; axis >= 0; --axis) {
+        if (p.bit[axis] < 0) continue;
+        StageScope sc(&ctx->prof, fin ? kThomasFinest[axis] : "thomas", s);
+        launch_thomas(axis, F, g.nc, g.ax[axis], axis == last ? Gprev : nullptr, s,
+                      tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED));
+      }
     }
     {
       StageScope sc(&ctx->prof, fin ? "rec_interp[finest]" : "rec_interp", s);
@@ -634,10 +644,15 @@ mgc_status mgc_recompose_adjoint(mgc_ctx ctx, const double* d_grad_u, int ndim,
         StageScope sc(&ctx->prof, "adj_restrict", s);
         launch_adj_restrict(g, geom, Gc, w.Y, s);
       }
-      for (int axis = 2; axis >= 0; --axis) {
-        if (p.bit[axis] < 0) continue;
+      if (thomas_grid_fits(geom)) {
         StageScope sc(&ctx->prof, "thomas", s);
-        launch_thomas(axis, w.Y, geom.nc, geom.ax[axis], nullptr, s);
+        launch_thomas_grid(w.Y, geom, nullptr, s);
+      } else {
+        for (int axis = 2; axis >= 0; --axis) {
+          if (p.bit[axis] < 0) continue;
+          StageScope sc(&ctx->prof, "thomas", s);
+          launch_thomas(axis, w.Y, geom.nc, geom.ax[axis], nullptr, s);
+        }
       }
       {
         StageScope sc(&ctx->prof, "adj_prolong", s);

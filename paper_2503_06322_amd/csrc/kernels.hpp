@@ -58,6 +58,11 @@ void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* 
 constexpr int64_t kThomasTilePoints = int64_t(1) << 22;
 void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
                    const double* sub, hipStream_t s, int cand = 0);
+// All active axes of a coarse grid small enough for LDS in one launch (the
+// same results as the per-axis launches, axis 2 first; sub as there, applied
+// after the last sweep).  Only for grids with thomas_grid_fits(g).
+bool thomas_grid_fits(const LevelGeom& g);
+void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStream_t s);
 // Level-0 block: values of G0 (m0 entries) quantised (sym) or copied (raw).
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
                    double r, const OutlierBuf& ob, unsigned* status, hipStream_t s);

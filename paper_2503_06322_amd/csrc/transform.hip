@@ -1758,6 +1758,80 @@ __global__ __launch_bounds__(64 * TILES) void k_thomas_tile(double* __restrict__
   }
 }
 
+// A coarse grid that fits in LDS: the three sweeps (axis 2, then 1, then 0,
+// the order of the per-axis launches) in one workgroup, one thread per line,
+// with the same arithmetic; sub - x is formed on the way out, as the last
+// per-axis sweep would.  Saves two launches (and their latency) per level on
+// the small levels.
+constexpr int kThomasGridMax = 16384;  // points (128 KiB of FP64)
+constexpr int kThomasGridMaxLine = 128;
+
+struct Thomas3Args {
+  const double* ta[3];
+  const double* tm[3];
+  const double* tc[3];
+  int active[3];
+};
+
+__global__ __launch_bounds__(256) void k_thomas_grid(double* __restrict__ x, int64_t n0,
+                                                      int64_t n1, int64_t n2, const Thomas3Args a,
+                                                      const double* __restrict__ sub) {
+  extern __shared__ double gsm[];
+  const int n = (int)(n0 * n1 * n2);
+  for (int i = threadIdx.x; i < n; i += 256) gsm[i] = x[i];
+  __syncthreads();
+  const int64_t nn[3] = {n0, n1, n2};
+  for (int axis = 2; axis >= 0; --axis) {
+    if (!a.active[axis]) continue;
+    const int L = (int)nn[axis];
+    const int lines = n / L;
+    const int stride = axis == 2 ? 1 : (axis == 1 ? (int)n2 : (int)(n1 * n2));
+    const double* ta = a.ta[axis];
+    const double* tm = a.tm[axis];
+    const double* tc = a.tc[axis];
+    for (int t = threadIdx.x; t < lines; t += 256) {
+      int base;
+      if (axis == 2) base = t * (int)n2;
+      else if (axis == 1) base = (t / (int)n2) * (int)(n1 * n2) + t % (int)n2;
+      else base = t;
+      // Four LDS loads issued ahead of each group of four dependent steps.
+      double* line = gsm + base;
+      double prev = 0.0;
+      for (int i0 = 0; i0 < L; i0 += 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = line[min(i0 + u, L - 1) * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = min(i0 + u, L - 1);
+          v[u] = thomas_fwd(v[u], ta[i], tm[i], prev);
+          if (i0 + u < L) prev = v[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u < L) line[(i0 + u) * stride] = v[u];
+      }
+      double nxt = 0.0;
+      for (int i0 = L - 1; i0 >= 0; i0 -= 4) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = line[max(i0 - u, 0) * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = max(i0 - u, 0);
+          v[u] = thomas_bwd(v[u], tc[i], nxt);
+          if (i0 - u >= 0) nxt = v[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 - u >= 0) line[(i0 - u) * stride] = v[u];
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += 256) x[i] = sub ? sub[i] - gsm[i] : gsm[i];
+}
+
 template <typename Tin, bool QUANT>
 __device__ __forceinline__ void level0_body(const Tin* __restrict__ G0, int64_t m0,
                                             uint16_t* __restrict__ sym, double* __restrict__ raw,
@@ -2138,6 +2212,35 @@ void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
     case 2: thomas_c<2>(axis, x, nc, t, sub, s); break;
     default: thomas_c<0>(axis, x, nc, t, sub, s);
   }
+}
+
+bool thomas_grid_fits(const LevelGeom& g) {
+  if (g.nc[0] * g.nc[1] * g.nc[2] > kThomasGridMax) return false;
+  // One thread per line: long lines would serialise the whole launch.
+  for (int k = 0; k < 3; ++k)
+    if (g.bit[k] >= 0 && g.nc[k] > kThomasGridMaxLine) return false;
+  return true;
+}
+
+void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStream_t s) {
+  const int64_t n = g.nc[0] * g.nc[1] * g.nc[2];
+  if (n > kThomasGridMax) throw std::logic_error("launch_thomas_grid: grid exceeds LDS");
+  static bool attr = false;
+  if (!attr) {
+    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_thomas_grid),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(kThomasGridMax * sizeof(double))));
+    attr = true;
+  }
+  Thomas3Args a;
+  for (int k = 0; k < 3; ++k) {
+    a.ta[k] = g.ax[k].ta;
+    a.tm[k] = g.ax[k].tm;
+    a.tc[k] = g.ax[k].tc;
+    a.active[k] = g.bit[k] >= 0;
+  }
+  hipLaunchKernelGGL(k_thomas_grid, dim3(1), dim3(256), (size_t)n * sizeof(double), s, x,
+                     g.nc[0], g.nc[1], g.nc[2], a, sub);
 }
 
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
