@@ -274,12 +274,18 @@ __device__ unsigned block_excl_scan(unsigned v, unsigned* sm32, unsigned* total)
 }
 
 // ---------------------------------------------------------------- codebook
-constexpr int kMergeCap = 4096;
+constexpr int kWin = 12288;  // LDS window per queue in a merge round
 constexpr int kMaxRounds = 256;
 
-struct CbSmem {
+// Large LDS of the codebook build: the sort's tables, then the merge windows.
+union CbBig {
   SortSmem sort;
-  uint32_t runL[kMergeCap], runI[kMergeCap], runS[kMergeCap];
+  struct {
+    uint32_t Lwin[kWin], Iwin[kWin], newI[kWin + 1];
+  } mw;
+};
+
+struct CbSmem {
   unsigned round_lo[kMaxRounds];
   unsigned sm32[16];
   unsigned m, li, ii, nI, la, ib, n, flag, lastw, rounds;
@@ -308,6 +314,32 @@ __device__ __forceinline__ unsigned upper_count(const uint32_t* a, unsigned n, u
     else hi = mid;
   }
   return lo;
+}
+
+// count of a[0..n) that are <= w (LE) or < w, a ascending: binary lifting
+// over powers of two, so every thread takes the same number of steps
+template <bool LE>
+__device__ __forceinline__ unsigned lds_count(const uint32_t* a, unsigned n, uint32_t w) {
+  unsigned pos = 0;
+  for (unsigned step = n ? 1u << (31 - __clz(n)) : 0u; step; step >>= 1) {
+    const unsigned q = pos + step;
+    if (q <= n && (LE ? a[q - 1] <= w : a[q - 1] < w)) pos = q;
+  }
+  return pos;
+}
+
+// Weight bound of a merge round: with m nodes taken (a pending first child
+// of weight lastw when m is odd), the next pair's weight; l0 <= l1 and
+// i0 <= i1 are the fronts of the leaf and internal queues (~0 when empty).
+__device__ __forceinline__ unsigned long long merge_threshold(unsigned m, uint32_t lastw,
+                                                              unsigned long long l0,
+                                                              unsigned long long l1,
+                                                              unsigned long long i0,
+                                                              unsigned long long i1) {
+  if (m & 1) return (unsigned long long)lastw + (l0 < i0 ? l0 : i0);
+  const unsigned long long a = l0 < i0 ? l0 : i0;
+  const unsigned long long b = l0 < i0 ? (l1 < i0 ? l1 : i0) : (l0 < i1 ? l0 : i1);
+  return a + b;
 }
 
 // Stable rank of each item among items with the same small digit (< 34), in
@@ -364,6 +396,7 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
                                               uint8_t* __restrict__ cb_out,
                                               Layout* __restrict__ lay) {
   __shared__ CbSmem sm;
+  __shared__ CbBig big;
   const int tid = threadIdx.x;
   for (unsigned i = tid; i < kDict; i += 1024) {
     clen[i] = 0;
@@ -432,13 +465,19 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
     fmax = block_max(fmax, sm.sm32);
     const int bits = 32 - __clz(fmax);
     __syncthreads();
-    const bool inB = block_radix_sort(s.keyA, s.valA, s.keyB, s.valB, n, bits, sm.sort);
+    const bool inB = block_radix_sort(s.keyA, s.valA, s.keyB, s.valB, n, bits, big.sort);
     const uint32_t* Lw = inB ? s.keyB : s.keyA;   // leaf weights, ascending
     const uint32_t* Lx = inB ? s.valB : s.valA;   // leaf -> index into symAsc
     __syncthreads();
-    // 3. two-queue merge in rounds.  A round's two runs are staged in LDS
-    //    when they fit (binary searches and the new internal weights then
-    //    stay in LDS); larger rounds use global memory.
+    // 3. two-queue merge in rounds.  A round stages the fronts of both
+    //    queues in LDS (up to kWin nodes each, 4096 at a time until a node
+    //    above the threshold shows up), ranks every taken node in the merged
+    //    order by a binary search in the other queue's window (ties to the
+    //    leaf), and adds its weight into its parent's slot with LDS atomics
+    //    (integer sums, so the order of the adds does not matter).  The next
+    //    round's threshold is read from the same windows.  A round that
+    //    takes more than a window's worth of one queue runs from global
+    //    memory instead.
     if (tid == 0) {
       sm.m = 0;
       sm.li = 0;
@@ -446,38 +485,145 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       sm.nI = 0;
       sm.lastw = 0;
       sm.rounds = 0;
+      sm.t = (unsigned long long)Lw[0] + Lw[1];
     }
     __syncthreads();
     while (true) {
       const unsigned m = sm.m, li = sm.li, ii = sm.ii, nI = sm.nI;
-      if (m == 2 * n - 2) break;
-      if (tid == 0) {
-        // internal nodes created in this round: [nI, m_new / 2), recorded below
-        if (sm.rounds < kMaxRounds) sm.round_lo[sm.rounds] = nI;
-      }
-      if (tid == 0) {
-        const unsigned long long INF = ~0ull;
-        const unsigned long long l0 = li < n ? Lw[li] : INF;
-        const unsigned long long l1 = li + 1 < n ? Lw[li + 1] : INF;
-        const unsigned long long i0 = ii < nI ? s.Iw[ii] : INF;
-        const unsigned long long i1 = ii + 1 < nI ? s.Iw[ii + 1] : INF;
-        unsigned long long t;
-        if (m & 1) {
-          // the pending first child (weight lastw) pairs with the next node
-          t = (unsigned long long)sm.lastw + (l0 < i0 ? l0 : i0);
-        } else {
-          // two smallest of the queue fronts
-          unsigned long long a = l0 < i0 ? l0 : i0;
-          unsigned long long b;
-          if (l0 < i0) b = l1 < i0 ? l1 : i0;
-          else b = l0 < i1 ? l0 : i1;
-          t = a + b;
-        }
-        sm.t = t;
-      }
-      __syncthreads();
       const unsigned long long t = sm.t;
-      // leaves and internal nodes of weight <= t (prefixes of sorted queues)
+      if (m == 2 * n - 2) break;
+      // internal nodes created in this round: [nI, m_new / 2)
+      if (tid == 0 && sm.rounds < kMaxRounds) sm.round_lo[sm.rounds] = nI;
+      const unsigned availL = min((unsigned)kWin, n - li);
+      const unsigned availI = min((unsigned)kWin, nI - ii);
+      const uint32_t lastw0 = sm.lastw;
+      for (unsigned k = tid; k <= (unsigned)kWin; k += 1024)
+        big.mw.newI[k] = (k == 0 && (m & 1)) ? lastw0 : 0u;
+      unsigned nLd = 0, nId = 0;
+      bool moreL = availL > 0, moreI = availI > 0;
+      while (moreL || moreI) {
+        if (moreL) {
+          uint32_t v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = Lw[li + min(nLd + u * 1024 + tid, availL - 1)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (nLd + u * 1024 + tid < availL) big.mw.Lwin[nLd + u * 1024 + tid] = v[u];
+        }
+        if (moreI) {
+          uint32_t v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = s.Iw[ii + min(nId + u * 1024 + tid, availI - 1)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (nId + u * 1024 + tid < availI) big.mw.Iwin[nId + u * 1024 + tid] = v[u];
+        }
+        __syncthreads();
+        if (moreL) {
+          const unsigned e = min(nLd + 4096, availL);
+          moreL = e < availL && (unsigned long long)big.mw.Lwin[e - 1] <= t;
+          nLd = e;
+        }
+        if (moreI) {
+          const unsigned e = min(nId + 4096, availI);
+          moreI = e < availI && (unsigned long long)big.mw.Iwin[e - 1] <= t;
+          nId = e;
+        }
+      }
+      const uint32_t tw = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
+      const unsigned nl = lds_count<true>(big.mw.Lwin, nLd, tw);
+      const unsigned ni = lds_count<true>(big.mw.Iwin, nId, tw);
+      const bool ovf = (nl == availL && availL < n - li) || (ni == availI && availI < nI - ii);
+      if (!ovf) {
+        const unsigned m_new = m + nl + ni;
+        if (m_new == m) {  // every round takes at least the smallest node
+          if (tid == 0) lay->status |= ST_INTERNAL;
+          return;
+        }
+        const unsigned mh = m_new >> 1;  // internal nodes complete after the round
+        const unsigned last = nl + ni - 1;
+        // leaves: rank = own index + internal nodes lighter than it
+        for (unsigned k0 = tid; k0 < nl; k0 += 4096) {
+          uint32_t w[4];
+          unsigned pos[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            w[u] = big.mw.Lwin[min(k0 + u * 1024, nl - 1)];
+            pos[u] = 0;
+          }
+          for (unsigned step = ni ? 1u << (31 - __clz(ni)) : 0u; step; step >>= 1) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const unsigned q = pos[u] + step;
+              if (q <= ni && big.mw.Iwin[q - 1] < w[u]) pos[u] = q;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const unsigned k = k0 + u * 1024;
+            if (k < nl) {
+              const unsigned r = k + pos[u];
+              const unsigned par = (m + r) >> 1;
+              s.leafPar[li + k] = par;
+              if (par < mh) atomicAdd(&big.mw.newI[par - nI], w[u]);
+              if (r == last) sm.lastw = w[u];
+            }
+          }
+        }
+        // internal nodes: rank = own index + leaves at most as heavy
+        for (unsigned k0 = tid; k0 < ni; k0 += 4096) {
+          uint32_t w[4];
+          unsigned pos[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            w[u] = big.mw.Iwin[min(k0 + u * 1024, ni - 1)];
+            pos[u] = 0;
+          }
+          for (unsigned step = nl ? 1u << (31 - __clz(nl)) : 0u; step; step >>= 1) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const unsigned q = pos[u] + step;
+              if (q <= nl && big.mw.Lwin[q - 1] <= w[u]) pos[u] = q;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const unsigned k = k0 + u * 1024;
+            if (k < ni) {
+              const unsigned r = k + pos[u];
+              const unsigned par = (m + r) >> 1;
+              s.parA[ii + k] = par;
+              if (par < mh) atomicAdd(&big.mw.newI[par - nI], w[u]);
+              if (r == last) sm.lastw = w[u];
+            }
+          }
+        }
+        __syncthreads();
+        for (unsigned k = tid; k < mh - nI; k += 1024) s.Iw[nI + k] = big.mw.newI[k];
+        if (tid == 0) {
+          const unsigned long long INF = ~0ull;
+          const unsigned li2 = li + nl, ii2 = ii + ni;
+          auto lw = [&](unsigned x) -> unsigned long long {
+            if (x >= n) return INF;
+            return x - li < nLd ? big.mw.Lwin[x - li] : Lw[x];
+          };
+          auto iw = [&](unsigned y) -> unsigned long long {
+            if (y >= mh) return INF;
+            if (y >= nI) return big.mw.newI[y - nI];
+            return y - ii < nId ? big.mw.Iwin[y - ii] : s.Iw[y];
+          };
+          sm.t = merge_threshold(m_new, sm.lastw, lw(li2), lw(li2 + 1), iw(ii2), iw(ii2 + 1));
+          sm.m = m_new;
+          sm.li = li2;
+          sm.ii = ii2;
+          sm.nI = mh;
+          ++sm.rounds;
+        }
+        __syncthreads();
+        continue;
+      }
+      // global-memory round: leaves and internal nodes of weight <= t
+      // (prefixes of the sorted queues)
       unsigned la = li, ib = ii;
       bool more_l = true, more_i = true;
       while (more_l || more_i) {
@@ -491,60 +637,35 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
         more_l = more_l && cl == 1024;
         more_i = more_i && ci == 1024;
       }
-      const unsigned nl = la - li, ni = ib - ii;
-      const unsigned m_new = m + nl + ni;
-      if (m_new == m) {  // every round takes at least the smallest node
-        if (tid == 0) lay->status |= ST_INTERNAL;
-        return;
+      const unsigned nl2 = la - li, ni2 = ib - ii;
+      const unsigned m_new = m + nl2 + ni2;
+      for (unsigned x = li + tid; x < la; x += 1024) {
+        const uint32_t w = Lw[x];
+        const unsigned pos = m + (x - li) + lower_count(s.Iw + ii, ni2, w);
+        s.Sw[pos] = w;
+        s.leafPar[x] = pos >> 1;
       }
-      if (nl + ni <= (unsigned)kMergeCap) {
-        for (unsigned k = tid; k < nl; k += 1024) sm.runL[k] = Lw[li + k];
-        for (unsigned k = tid; k < ni; k += 1024) sm.runI[k] = s.Iw[ii + k];
-        __syncthreads();
-        // merge: ties go to the leaf
-        for (unsigned k = tid; k < nl; k += 1024) {
-          const uint32_t w = sm.runL[k];
-          const unsigned r = k + lower_count(sm.runI, ni, w);
-          sm.runS[r] = w;
-          s.leafPar[li + k] = (m + r) >> 1;
-        }
-        for (unsigned k = tid; k < ni; k += 1024) {
-          const uint32_t w = sm.runI[k];
-          const unsigned r = k + upper_count(sm.runL, nl, w);
-          sm.runS[r] = w;
-          s.parA[ii + k] = (m + r) >> 1;
-        }
-        __syncthreads();
-        for (unsigned j = nI + tid; j < m_new / 2; j += 1024) {
-          const int r = (int)(2 * j) - (int)m;   // -1: first child placed last round
-          s.Iw[j] = (r < 0 ? sm.lastw : sm.runS[r]) + sm.runS[r + 1];
-        }
-        __syncthreads();
-        if (tid == 0) sm.lastw = sm.runS[nl + ni - 1];
-      } else {
-        for (unsigned x = li + tid; x < la; x += 1024) {
-          const uint32_t w = Lw[x];
-          const unsigned pos = m + (x - li) + lower_count(s.Iw + ii, ni, w);
-          s.Sw[pos] = w;
-          s.leafPar[x] = pos >> 1;
-        }
-        for (unsigned y = ii + tid; y < ib; y += 1024) {
-          const uint32_t w = s.Iw[y];
-          const unsigned pos = m + (y - ii) + upper_count(Lw + li, nl, w);
-          s.Sw[pos] = w;
-          s.parA[y] = pos >> 1;
-        }
-        __syncthreads();
-        for (unsigned j = nI + tid; j < m_new / 2; j += 1024)
-          s.Iw[j] = (2 * j + 1 == m ? sm.lastw : s.Sw[2 * j]) + s.Sw[2 * j + 1];
-        __syncthreads();
-        if (tid == 0) sm.lastw = s.Sw[m_new - 1];
+      for (unsigned y = ii + tid; y < ib; y += 1024) {
+        const uint32_t w = s.Iw[y];
+        const unsigned pos = m + (y - ii) + upper_count(Lw + li, nl2, w);
+        s.Sw[pos] = w;
+        s.parA[y] = pos >> 1;
       }
+      __syncthreads();
+      for (unsigned j = nI + tid; j < m_new / 2; j += 1024)
+        s.Iw[j] = (2 * j + 1 == m ? lastw0 : s.Sw[2 * j]) + s.Sw[2 * j + 1];
+      __syncthreads();
       if (tid == 0) {
+        const unsigned long long INF = ~0ull;
+        const unsigned mh = m_new / 2;
+        const uint32_t lw_new = s.Sw[m_new - 1];
+        sm.lastw = lw_new;
+        sm.t = merge_threshold(m_new, lw_new, la < n ? Lw[la] : INF, la + 1 < n ? Lw[la + 1] : INF,
+                               ib < mh ? s.Iw[ib] : INF, ib + 1 < mh ? s.Iw[ib + 1] : INF);
         sm.m = m_new;
         sm.li = la;
         sm.ii = ib;
-        sm.nI = m_new / 2;
+        sm.nI = mh;
         ++sm.rounds;
       }
       __syncthreads();
