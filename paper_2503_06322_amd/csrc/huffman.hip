@@ -275,6 +275,7 @@ __device__ unsigned block_excl_scan(unsigned v, unsigned* sm32, unsigned* total)
 
 // ---------------------------------------------------------------- codebook
 constexpr int kWin = 12288;  // LDS window per queue in a merge round
+static_assert(kWin < 2 * 8192, "window counts search from 8192 down");
 constexpr int kMaxRounds = 256;
 
 // Large LDS of the codebook build: the sort's tables, then the merge windows.
@@ -288,7 +289,7 @@ union CbBig {
 struct CbSmem {
   unsigned round_lo[kMaxRounds];
   unsigned sm32[16];
-  unsigned m, li, ii, nI, la, ib, n, flag, lastw, rounds;
+  unsigned m, li, ii, nI, la, ib, n, flag, lastw, rounds, cntL, cntI;
   unsigned long long t;
   unsigned lcount[34];
   unsigned lfirst[34];
@@ -316,16 +317,28 @@ __device__ __forceinline__ unsigned upper_count(const uint32_t* a, unsigned n, u
   return lo;
 }
 
-// count of a[0..n) that are <= w (LE) or < w, a ascending: binary lifting
-// over powers of two, so every thread takes the same number of steps
+// For four keys at once: pos[u] = count of a[0..n) below w[u] (LE: at most
+// w[u]), a ascending, n >= 1.  Branch-free halving (the probe is always in
+// range and the trip count depends on n only), so the four probes of a step
+// are in flight together.
 template <bool LE>
-__device__ __forceinline__ unsigned lds_count(const uint32_t* a, unsigned n, uint32_t w) {
-  unsigned pos = 0;
-  for (unsigned step = n ? 1u << (31 - __clz(n)) : 0u; step; step >>= 1) {
-    const unsigned q = pos + step;
-    if (q <= n && (LE ? a[q - 1] <= w : a[q - 1] < w)) pos = q;
+__device__ __forceinline__ void lds_count4(const uint32_t* a, unsigned n, const uint32_t (&w)[4],
+                                           unsigned (&pos)[4]) {
+  unsigned b[4] = {0u, 0u, 0u, 0u};
+  for (unsigned len = n; len > 1;) {
+    const unsigned half = len >> 1;
+    uint32_t v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = a[b[u] + half];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) b[u] = (LE ? v[u] <= w[u] : v[u] < w[u]) ? b[u] + half : b[u];
+    len -= half;
   }
-  return pos;
+  uint32_t v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = a[b[u]];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) pos[u] = b[u] + ((LE ? v[u] <= w[u] : v[u] < w[u]) ? 1u : 0u);
 }
 
 // Weight bound of a merge round: with m nodes taken (a pending first child
@@ -485,6 +498,8 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       sm.nI = 0;
       sm.lastw = 0;
       sm.rounds = 0;
+      sm.cntL = 0;
+      sm.cntI = 0;
       sm.t = (unsigned long long)Lw[0] + Lw[1];
     }
     __syncthreads();
@@ -499,6 +514,8 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       const uint32_t lastw0 = sm.lastw;
       for (unsigned k = tid; k <= (unsigned)kWin; k += 1024)
         big.mw.newI[k] = (k == 0 && (m & 1)) ? lastw0 : 0u;
+      // window loads; the entries <= t are counted on the way (ballots, one
+      // LDS add per wavefront), which the windows' order turns into nl, ni
       unsigned nLd = 0, nId = 0;
       bool moreL = availL > 0, moreI = availI > 0;
       while (moreL || moreI) {
@@ -506,17 +523,27 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
           uint32_t v[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) v[u] = Lw[li + min(nLd + u * 1024 + tid, availL - 1)];
+          unsigned c = 0;
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (nLd + u * 1024 + tid < availL) big.mw.Lwin[nLd + u * 1024 + tid] = v[u];
+          for (int u = 0; u < 4; ++u) {
+            const bool in = nLd + u * 1024 + tid < availL;
+            if (in) big.mw.Lwin[nLd + u * 1024 + tid] = v[u];
+            c += __popcll(__ballot(in && (unsigned long long)v[u] <= t));
+          }
+          if ((tid & 63) == 0 && c) atomicAdd(&sm.cntL, c);
         }
         if (moreI) {
           uint32_t v[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) v[u] = s.Iw[ii + min(nId + u * 1024 + tid, availI - 1)];
+          unsigned c = 0;
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (nId + u * 1024 + tid < availI) big.mw.Iwin[nId + u * 1024 + tid] = v[u];
+          for (int u = 0; u < 4; ++u) {
+            const bool in = nId + u * 1024 + tid < availI;
+            if (in) big.mw.Iwin[nId + u * 1024 + tid] = v[u];
+            c += __popcll(__ballot(in && (unsigned long long)v[u] <= t));
+          }
+          if ((tid & 63) == 0 && c) atomicAdd(&sm.cntI, c);
         }
         __syncthreads();
         if (moreL) {
@@ -530,9 +557,7 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
           nId = e;
         }
       }
-      const uint32_t tw = t > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)t;
-      const unsigned nl = lds_count<true>(big.mw.Lwin, nLd, tw);
-      const unsigned ni = lds_count<true>(big.mw.Iwin, nId, tw);
+      const unsigned nl = sm.cntL, ni = sm.cntI;
       const bool ovf = (nl == availL && availL < n - li) || (ni == availI && availI < nI - ii);
       if (!ovf) {
         const unsigned m_new = m + nl + ni;
@@ -545,19 +570,10 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
         // leaves: rank = own index + internal nodes lighter than it
         for (unsigned k0 = tid; k0 < nl; k0 += 4096) {
           uint32_t w[4];
-          unsigned pos[4];
+          unsigned pos[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            w[u] = big.mw.Lwin[min(k0 + u * 1024, nl - 1)];
-            pos[u] = 0;
-          }
-          for (unsigned step = ni ? 1u << (31 - __clz(ni)) : 0u; step; step >>= 1) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const unsigned q = pos[u] + step;
-              if (q <= ni && big.mw.Iwin[q - 1] < w[u]) pos[u] = q;
-            }
-          }
+          for (int u = 0; u < 4; ++u) w[u] = big.mw.Lwin[min(k0 + u * 1024, nl - 1)];
+          if (ni) lds_count4<false>(big.mw.Iwin, ni, w, pos);
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const unsigned k = k0 + u * 1024;
@@ -573,19 +589,10 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
         // internal nodes: rank = own index + leaves at most as heavy
         for (unsigned k0 = tid; k0 < ni; k0 += 4096) {
           uint32_t w[4];
-          unsigned pos[4];
+          unsigned pos[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            w[u] = big.mw.Iwin[min(k0 + u * 1024, ni - 1)];
-            pos[u] = 0;
-          }
-          for (unsigned step = nl ? 1u << (31 - __clz(nl)) : 0u; step; step >>= 1) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const unsigned q = pos[u] + step;
-              if (q <= nl && big.mw.Lwin[q - 1] <= w[u]) pos[u] = q;
-            }
-          }
+          for (int u = 0; u < 4; ++u) w[u] = big.mw.Iwin[min(k0 + u * 1024, ni - 1)];
+          if (nl) lds_count4<true>(big.mw.Lwin, nl, w, pos);
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const unsigned k = k0 + u * 1024;
@@ -613,6 +620,8 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
             return y - ii < nId ? big.mw.Iwin[y - ii] : s.Iw[y];
           };
           sm.t = merge_threshold(m_new, sm.lastw, lw(li2), lw(li2 + 1), iw(ii2), iw(ii2 + 1));
+          sm.cntL = 0;
+          sm.cntI = 0;
           sm.m = m_new;
           sm.li = li2;
           sm.ii = ii2;
@@ -662,6 +671,8 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
         sm.lastw = lw_new;
         sm.t = merge_threshold(m_new, lw_new, la < n ? Lw[la] : INF, la + 1 < n ? Lw[la + 1] : INF,
                                ib < mh ? s.Iw[ib] : INF, ib + 1 < mh ? s.Iw[ib + 1] : INF);
+        sm.cntL = 0;
+        sm.cntI = 0;
         sm.m = m_new;
         sm.li = la;
         sm.ii = ib;
