@@ -95,6 +95,8 @@ struct CodebookScratch {
   uint32_t *keyA, *valA, *keyB, *valB, *symAsc, *freqAsc, *Iw, *Sw, *leafPar, *parA, *parB,
       *dstA, *dstB;
   uint32_t* pk;  // per coded symbol: code << 6 | length (valid when max_len <= 26)
+  uint32_t* hcnt;   // multi-block leaf sort: [pass][digit][tile] item counts
+  uint32_t* fmaxT;  // multi-block leaf sort: largest frequency per tile
 };
 
 // Stream layout computed on the device once counts are known.

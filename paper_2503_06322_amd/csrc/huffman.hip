@@ -51,7 +51,7 @@ struct DecodeTables {
 
 size_t decode_tables_bytes() { return sizeof(DecodeTables); }
 
-size_t codebook_scratch_bytes() { return (size_t)kDict * 4 * 15; }
+size_t codebook_scratch_bytes() { return (size_t)kDict * 4 * 16; }
 
 CodebookScratch carve_codebook_scratch(void* base) {
   uint32_t* p = static_cast<uint32_t*>(base);
@@ -70,6 +70,8 @@ CodebookScratch carve_codebook_scratch(void* base) {
   s.dstA = p; p += kDict;
   s.dstB = p; p += kDict;
   s.pk = p; p += kDict;
+  s.hcnt = p; p += kDict / 2;
+  s.fmaxT = p; p += kDict / 2;
   return s;
 }
 
@@ -277,6 +279,11 @@ __device__ unsigned block_excl_scan(unsigned v, unsigned* sm32, unsigned* total)
 constexpr int kWin = 12288;  // LDS window per queue in a merge round
 static_assert(kWin < 2 * 8192, "window counts search from 8192 down");
 constexpr int kMaxRounds = 256;
+constexpr int kSortTile = 2048;                  // items per block of the multi-block sort
+constexpr int kSortTiles = kDict / kSortTile;    // tiles (and blocks) per pass
+constexpr int kSortPasses = 4;                   // 8-bit digits of a 32-bit frequency
+static_assert(kSortTiles % 4 == 0 && kSortPasses * 256 * kSortTiles <= kDict / 2,
+              "sort count table fits its scratch");
 
 // Large LDS of the codebook build: the sort's tables, then the merge windows.
 union CbBig {
@@ -402,21 +409,11 @@ __device__ void stable_digit_ranks(unsigned n, DigitFn digit_of, Fn fn, CbSmem& 
   __syncthreads();
 }
 
-__device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
-                                              const CodebookScratch& s,
-                                              uint32_t* __restrict__ code,
-                                              uint8_t* __restrict__ clen,
-                                              uint8_t* __restrict__ cb_out,
-                                              Layout* __restrict__ lay) {
-  __shared__ CbSmem sm;
-  __shared__ CbBig big;
+// 1. non-zero keys in ascending symbol order (each thread owns 64 symbols,
+//    read as sixteen 16-byte vectors kept in registers); returns their count
+__device__ unsigned compact_keys(const unsigned* __restrict__ hist, const CodebookScratch& s,
+                                 CbSmem& sm) {
   const int tid = threadIdx.x;
-  for (unsigned i = tid; i < kDict; i += 1024) {
-    clen[i] = 0;
-    code[i] = 0;
-  }
-  // 1. non-zero keys in ascending symbol order (each thread owns 64 symbols,
-  //    read as sixteen 16-byte vectors kept in registers)
   uint4 hv[16];
   const uint4* h4 = reinterpret_cast<const uint4*>(hist) + tid * 16;
 #pragma unroll
@@ -439,8 +436,43 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       }
     }
   }
-  const unsigned n = total;
+  return total;
+}
+
+// PRESORTED: the leaf sort of the first round was done by the multi-block
+// sort (k_cbs_count / k_cbs_pass), which also wrote the non-zero keys in
+// symbol order; otherwise the block compacts and sorts them itself.
+template <bool PRESORTED>
+__device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
+                                              const CodebookScratch& s,
+                                              uint32_t* __restrict__ code,
+                                              uint8_t* __restrict__ clen,
+                                              uint8_t* __restrict__ cb_out,
+                                              Layout* __restrict__ lay) {
+  __shared__ CbSmem sm;
+  __shared__ CbBig big;
+  const int tid = threadIdx.x;
+  for (unsigned i = tid; i < kDict; i += 1024) {
+    clen[i] = 0;
+    code[i] = 0;
+  }
+  unsigned n, pre_passes = 0;
+  if (PRESORTED) {
+    // item count: every non-zero bin is counted once in the first pass's
+    // (digit, tile) table
+    unsigned c = 0;
+    for (unsigned i = tid; i < 256u * kSortTiles; i += 1024) c += s.hcnt[i];
+    unsigned fm = 0;
+    for (int t = 0; t < kSortTiles; ++t) fm = max(fm, s.fmaxT[t]);
+    pre_passes = (32 - __clz(fm) + 7) / 8;
+    unsigned total;
+    block_excl_scan(c, sm.sm32, &total);
+    n = total;
+  } else {
+    n = compact_keys(hist, s, sm);
+  }
   __syncthreads();
+
   if (n == 0) {
     if (tid == 0) {
       lay->n_codes = 0;
@@ -469,16 +501,21 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
     }
     // 2. sort leaves by (frequency, symbol): stable radix sort of indices
     //    into the ascending-symbol list, keyed by frequency
-    unsigned fmax = 0;
-    for (unsigned i = tid; i < n; i += 1024) {
-      s.keyA[i] = s.freqAsc[i];
-      s.valA[i] = i;
-      fmax = max(fmax, s.freqAsc[i]);
+    bool inB;
+    if (PRESORTED && flatten == 0) {
+      inB = pre_passes & 1;  // passes alternate B, A, B, A
+    } else {
+      unsigned fmax = 0;
+      for (unsigned i = tid; i < n; i += 1024) {
+        s.keyA[i] = s.freqAsc[i];
+        s.valA[i] = i;
+        fmax = max(fmax, s.freqAsc[i]);
+      }
+      fmax = block_max(fmax, sm.sm32);
+      const int bits = 32 - __clz(fmax);
+      __syncthreads();
+      inB = block_radix_sort(s.keyA, s.valA, s.keyB, s.valB, n, bits, big.sort);
     }
-    fmax = block_max(fmax, sm.sm32);
-    const int bits = 32 - __clz(fmax);
-    __syncthreads();
-    const bool inB = block_radix_sort(s.keyA, s.valA, s.keyB, s.valB, n, bits, big.sort);
     const uint32_t* Lw = inB ? s.keyB : s.keyA;   // leaf weights, ascending
     const uint32_t* Lx = inB ? s.valB : s.valA;   // leaf -> index into symAsc
     __syncthreads();
@@ -805,7 +842,163 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
                                                     uint8_t* __restrict__ clen,
                                                     uint8_t* __restrict__ cb_out,
                                                     Layout* __restrict__ lay) {
-  codebook_body(hist, s, code, clen, cb_out, lay);
+  codebook_body<true>(hist, s, code, clen, cb_out, lay);
+}
+
+// ------------------------------------------------- multi-block leaf sort
+// Plain calls sort the leaves by (frequency, symbol) on many CUs before the
+// one-block code construction: a stable LSD radix sort, 8 bits a pass, over
+// tiles of kSortTile items, one 256-thread block per tile.  Pass 0 reads the
+// non-zero histogram bins in place (tile t = symbols [kSortTile t,
+// kSortTile (t + 1))) and also writes them compacted in symbol order; its
+// values are those positions.  A block's output positions are the digit's
+// start (counts of all smaller digits) plus the counts of its digit in
+// earlier tiles, read from the (digit, tile) table; inside the tile each
+// wavefront owns a contiguous run and ranks equal digits by ballots, so the
+// sort is stable.  While it scatters, a pass counts the next pass's digits
+// of its items by destination tile (global atomics), so every pass reads a
+// complete table.  Passes beyond the largest frequency's width return at
+// once; pass p writes (keyB, valB) for even p and (keyA, valA) for odd p.
+__global__ __launch_bounds__(256) void k_cbs_count(const unsigned* __restrict__ hist,
+                                                   CodebookScratch s) {
+  __shared__ unsigned cnt[256];
+  __shared__ unsigned wmax[4];
+  const int t = blockIdx.x, tid = threadIdx.x;
+  cnt[tid] = 0;
+  __syncthreads();
+  const uint4* h4 = reinterpret_cast<const uint4*>(hist + (size_t)t * kSortTile) + tid * 2;
+  const uint4 a = h4[0], b = h4[1];
+  const unsigned f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  unsigned fm = 0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (f[u]) atomicAdd(&cnt[f[u] & 255u], 1u);
+    fm = max(fm, f[u]);
+  }
+  for (int o = 32; o > 0; o >>= 1) fm = max(fm, (unsigned)__shfl_xor((int)fm, o, 64));
+  if ((tid & 63) == 0) wmax[tid >> 6] = fm;
+  __syncthreads();
+  s.hcnt[(size_t)tid * kSortTiles + t] = cnt[tid];
+  for (int p = 1; p < kSortPasses; ++p) s.hcnt[((size_t)p * 256 + tid) * kSortTiles + t] = 0;
+  if (tid == 0) s.fmaxT[t] = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_cbs_pass(const unsigned* __restrict__ hist,
+                                                  CodebookScratch s) {
+  __shared__ unsigned wcnt[4][256];
+  __shared__ unsigned sm32[16];
+  __shared__ unsigned nzw[4];
+  const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  unsigned fm = 0;
+  for (int k = 0; k < kSortTiles; ++k) fm = max(fm, s.fmaxT[k]);
+  const int passes = (32 - __clz(fm) + 7) / 8;
+  if (P >= passes) return;  // uniform over the grid
+  // this digit's counts over the tiles: total, and in the tiles before t
+  const uint4* hc = reinterpret_cast<const uint4*>(s.hcnt + ((size_t)P * 256 + tid) * kSortTiles);
+  unsigned tot = 0, pre = 0;
+#pragma unroll
+  for (int q = 0; q < kSortTiles / 4; ++q) {
+    const uint4 v = hc[q];
+    const unsigned c4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      tot += c4[r];
+      pre += 4 * q + r < t ? c4[r] : 0u;
+    }
+  }
+  // digit starts (exclusive scan of the totals over the 256 digits), item
+  // count and, for pass 0, the items of the tiles before t
+  unsigned x = tot, zp = pre;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = (unsigned)__shfl_up((int)x, o, 64);
+    if (lane >= o) x += y;
+  }
+  for (int o = 32; o > 0; o >>= 1) zp += (unsigned)__shfl_xor((int)zp, o, 64);
+  if (lane == 63) sm32[wave] = x;
+  if (lane == 0) sm32[4 + wave] = zp;
+  for (int d = lane; d < 256; d += 64) wcnt[wave][d] = 0;
+  __syncthreads();
+  unsigned before = 0, n = 0, zbase = 0;
+  for (int w = 0; w < 4; ++w) {
+    before += w < wave ? sm32[w] : 0u;
+    n += sm32[w];
+    zbase += sm32[4 + w];
+  }
+  const unsigned start = before + x - tot + pre;  // digit tid's first slot for tile t
+  if (P > 0 && (unsigned)t * kSortTile >= n) return;  // uniform over the block
+  const uint32_t* ksrc = (P & 1) ? s.keyB : s.keyA;
+  const uint32_t* vsrc = (P & 1) ? s.valB : s.valA;
+  uint32_t* kdst = (P & 1) ? s.keyA : s.keyB;
+  uint32_t* vdst = (P & 1) ? s.valA : s.valB;
+  constexpr int K = kSortTile / 256;  // 64-item groups per wavefront
+  const unsigned i0 = (unsigned)t * kSortTile + wave * (64 * K);
+  uint32_t key[K], val[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const unsigned i = i0 + 64 * k + lane;
+    if (P == 0) {
+      key[k] = hist[i];
+      val[k] = 0;
+    } else {
+      key[k] = ksrc[min(i, n - 1)];
+      val[k] = vsrc[min(i, n - 1)];
+    }
+  }
+  const int shift = 8 * P;
+  unsigned nz = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool valid = P == 0 ? key[k] != 0 : i0 + 64 * k + lane < n;
+    const uint64_t peers = match_digit((key[k] >> shift) & 255u, 8, valid);
+    if (valid && __popcll(peers & lanemask_lt()) == 0)
+      wcnt[wave][(key[k] >> shift) & 255u] += __popcll(peers);
+    nz += __popcll(__ballot(valid));
+    wave_lds_fence();
+  }
+  if (lane == 0) nzw[wave] = nz;
+  __syncthreads();
+  {
+    unsigned run = start;
+    for (int w = 0; w < 4; ++w) {
+      const unsigned c = wcnt[w][tid];
+      wcnt[w][tid] = run;
+      run += c;
+    }
+  }
+  unsigned zrun = zbase;
+  for (int w = 0; w < wave; ++w) zrun += nzw[w];
+  __syncthreads();
+  const bool count_next = P + 1 < kSortPasses && P + 1 < passes;
+  uint32_t* hnext = s.hcnt + (size_t)(P + 1) * 256 * kSortTiles;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool valid = P == 0 ? key[k] != 0 : i0 + 64 * k + lane < n;
+    const unsigned d = (key[k] >> shift) & 255u;
+    const uint64_t peers = match_digit(d, 8, valid);
+    const unsigned r = __popcll(peers & lanemask_lt());
+    const unsigned pos = valid ? wcnt[wave][d] + r : 0u;
+    if (P == 0) {
+      const uint64_t vm = __ballot(valid);
+      const unsigned zpos = zrun + __popcll(vm & lanemask_lt());
+      zrun += __popcll(vm);
+      if (valid) {
+        s.symAsc[zpos] = i0 + 64 * k + lane;
+        s.freqAsc[zpos] = key[k];
+      }
+      val[k] = zpos;
+    }
+    if (valid) {
+      kdst[pos] = key[k];
+      vdst[pos] = val[k];
+      if (count_next)
+        atomicAdd(&hnext[(size_t)((key[k] >> (shift + 8)) & 255u) * kSortTiles + pos / kSortTile],
+                  1u);
+    }
+    wave_lds_fence();
+    if (valid && r == 0) wcnt[wave][d] = pos + __popcll(peers);
+    wave_lds_fence();
+  }
 }
 
 // ---------------------------------------------------------------- encoding
@@ -1659,7 +1852,7 @@ __global__ __launch_bounds__(1024) void kb_histogram(const Job* __restrict__ job
 __global__ __launch_bounds__(1024) void kb_codebook(const Job* __restrict__ jobs) {
   const Job& J = jobs[blockIdx.x];
   if (job_skipped_h(J)) return;
-  codebook_body(J.hist, J.cbs, J.code, J.clen, J.out + job_cb_off(J), J.lay);
+  codebook_body<false>(J.hist, J.cbs, J.code, J.clen, J.out + job_cb_off(J), J.lay);
 }
 
 __global__ __launch_bounds__(256) void kb_chunk_words(const Job* __restrict__ jobs,
@@ -1790,6 +1983,11 @@ void launch_b_header(const Job* jobs, int n, hipStream_t s) {
 void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
                      uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
                      hipStream_t s) {
+  hipLaunchKernelGGL(k_cbs_count, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
+  hipLaunchKernelGGL(k_cbs_pass<0>, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
+  hipLaunchKernelGGL(k_cbs_pass<1>, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
+  hipLaunchKernelGGL(k_cbs_pass<2>, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
+  hipLaunchKernelGGL(k_cbs_pass<3>, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
   hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, s, hist, sc, code, clen,
                      cb_out_base + cb_off, lay);
 }
