@@ -889,6 +889,7 @@ __global__ __launch_bounds__(256) void k_cbs_pass(const unsigned* __restrict__ h
   __shared__ unsigned wcnt[4][256];
   __shared__ unsigned sm32[16];
   __shared__ unsigned nzw[4];
+  __shared__ unsigned ncnt[256 * kSortTiles];  // next pass: [digit][destination tile]
   const int t = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   unsigned fm = 0;
   for (int k = 0; k < kSortTiles; ++k) fm = max(fm, s.fmaxT[k]);
@@ -918,6 +919,7 @@ __global__ __launch_bounds__(256) void k_cbs_pass(const unsigned* __restrict__ h
   if (lane == 63) sm32[wave] = x;
   if (lane == 0) sm32[4 + wave] = zp;
   for (int d = lane; d < 256; d += 64) wcnt[wave][d] = 0;
+  for (int i = tid; i < 256 * kSortTiles; i += 256) ncnt[i] = 0;
   __syncthreads();
   unsigned before = 0, n = 0, zbase = 0;
   for (int w = 0; w < 4; ++w) {
@@ -992,12 +994,16 @@ __global__ __launch_bounds__(256) void k_cbs_pass(const unsigned* __restrict__ h
       kdst[pos] = key[k];
       vdst[pos] = val[k];
       if (count_next)
-        atomicAdd(&hnext[(size_t)((key[k] >> (shift + 8)) & 255u) * kSortTiles + pos / kSortTile],
-                  1u);
+        atomicAdd(&ncnt[((key[k] >> (shift + 8)) & 255u) * kSortTiles + pos / kSortTile], 1u);
     }
     wave_lds_fence();
     if (valid && r == 0) wcnt[wave][d] = pos + __popcll(peers);
     wave_lds_fence();
+  }
+  if (count_next) {
+    __syncthreads();
+    for (int i = tid; i < 256 * kSortTiles; i += 256)
+      if (ncnt[i]) atomicAdd(&hnext[i], ncnt[i]);
   }
 }
 
