@@ -293,6 +293,8 @@ union CbBig {
   } mw;
 };
 
+static_assert(sizeof(CbBig) >= 2 * kDict, "depth and length bytes fit the merge windows");
+
 struct CbSmem {
   unsigned round_lo[kMaxRounds];
   unsigned sm32[16];
@@ -718,29 +720,53 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       }
       __syncthreads();
     }
-    // 4. depths of internal nodes.  A node created in round r is taken in a
-    //    later round, so its parent is created later still: walking the
-    //    rounds backwards, each round's nodes are resolved in parallel.
-    uint32_t* da;
+    // 4. depths of internal nodes, in LDS as bytes saturated at 255 (a depth
+    //    that large only shows that the code must be flattened).  A node
+    //    created in round r is taken in a later round, so its parent is
+    //    created later still: walking the rounds backwards, each round's
+    //    nodes are resolved in parallel, the next round's parent indices
+    //    loaded while the current round is resolved.
+    uint8_t* dep = reinterpret_cast<uint8_t*>(&big);  // [n - 1] internal nodes
+    uint8_t* lenAsc = dep + kDict;                     // [n] lengths in symbol order
     const unsigned rounds = sm.rounds;
     if (rounds <= (unsigned)kMaxRounds) {
-      da = s.dstA;
+      constexpr int PF = 8;
+      auto round_hi = [&](int r) { return r + 1 < (int)rounds ? sm.round_lo[r + 1] : root + 1; };
+      uint32_t cur[PF], nxt[PF];
+#pragma unroll
+      for (int u = 0; u < PF; ++u) {
+        const unsigned y = sm.round_lo[rounds - 1] + tid + 1024u * u;
+        cur[u] = y < root + 1 ? s.parA[min(y, root)] : 0u;
+      }
       for (int r = (int)rounds - 1; r >= 0; --r) {
-        const unsigned lo = sm.round_lo[r];
-        const unsigned hi = r + 1 < (int)rounds ? sm.round_lo[r + 1] : root + 1;
-        for (unsigned y = lo + tid; y < hi; y += 1024)
-          da[y] = y == root ? 0u : da[s.parA[y]] + 1u;
+        const unsigned lo = sm.round_lo[r], hi = round_hi(r);
+        if (r > 0) {
+          const unsigned lo1 = sm.round_lo[r - 1], hi1 = lo;
+#pragma unroll
+          for (int u = 0; u < PF; ++u) {
+            const unsigned y = lo1 + tid + 1024u * u;
+            nxt[u] = s.parA[min(y, hi1 > 0 ? hi1 - 1 : 0u)];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+          const unsigned y = lo + tid + 1024u * u;
+          if (y < hi) dep[y] = y == root ? 0 : (uint8_t)min(dep[cur[u]] + 1u, 255u);
+        }
+        for (unsigned y = lo + tid + 1024u * PF; y < hi; y += 1024)
+          dep[y] = y == root ? 0 : (uint8_t)min(dep[s.parA[y]] + 1u, 255u);
         __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PF; ++u) cur[u] = nxt[u];
       }
     } else {
-      // pointer jumping towards the root
+      // pointer jumping towards the root (global memory), then saturated
       for (unsigned y = tid; y <= root; y += 1024) {
         if (y == root) s.parA[y] = root;
         s.dstA[y] = y == root ? 0u : 1u;
       }
       __syncthreads();
-      uint32_t *pa = s.parA, *pb = s.parB, *db = s.dstB;
-      da = s.dstA;
+      uint32_t *pa = s.parA, *pb = s.parB, *da = s.dstA, *db = s.dstB;
       for (int jump = 0;; ++jump) {
         if (jump > 40) {  // depth <= n - 1 < 2^17: 18 jumps suffice
           if (tid == 0) lay->status |= ST_INTERNAL;
@@ -759,51 +785,44 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
         tmp = da; da = db; db = tmp;
         if (!any) break;
       }
+      for (unsigned y = tid; y <= root; y += 1024) dep[y] = (uint8_t)min(da[y], 255u);
+      __syncthreads();
     }
-    // 5. leaf lengths (four items per thread in flight)
-    uint32_t* lenx = s.parB;  // free after step 4
+    // 5. leaf lengths, stored by the leaf's position in symbol order (four
+    //    leaves per thread in flight)
     unsigned lmax = 0;
     for (unsigned x0 = tid; x0 < n; x0 += 4096) {
-      uint32_t par[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) par[u] = x0 + 1024 * u < n ? s.leafPar[x0 + 1024 * u] : root;
+      uint32_t par[4], lx[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const unsigned x = x0 + 1024 * u;
-        if (x < n) {
-          const unsigned l = da[par[u]] + 1u;
-          lenx[x] = l;
+        const unsigned x = min(x0 + 1024 * u, n - 1);
+        par[u] = s.leafPar[x];
+        lx[u] = Lx[x];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (x0 + 1024 * u < n) {
+          const unsigned l = min(dep[par[u]] + 1u, 255u);
+          lenAsc[lx[u]] = (uint8_t)l;
           lmax = max(lmax, l);
         }
       }
     }
     lmax = block_max(lmax, sm.sm32);
-    if (lmax <= (unsigned)kMaxCodeLen) {
-      for (unsigned x0 = tid; x0 < n; x0 += 4096) {
-        uint32_t li4[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) li4[u] = x0 + 1024 * u < n ? Lx[x0 + 1024 * u] : 0u;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const unsigned x = x0 + 1024 * u;
-          if (x < n) clen[s.symAsc[li4[u]]] = (uint8_t)lenx[x];
-        }
-      }
-      __syncthreads();
-      break;
-    }
+    if (lmax <= (unsigned)kMaxCodeLen) break;
     for (unsigned i = tid; i < n; i += 1024) s.freqAsc[i] = (s.freqAsc[i] + 1u) >> 1;
     __syncthreads();
   }
   // 6. canonical codes: count per length, first code per length, then the
   //    rank of each symbol among equal lengths in ascending symbol order
+  const uint8_t* lenAsc = reinterpret_cast<const uint8_t*>(&big) + kDict;
   if (tid < 34) sm.lfirst[tid] = 0;
   __syncthreads();
   // one LDS add per distinct length in each wavefront's 64 symbols
   for (unsigned t = tid & ~63u; t < n; t += 1024) {
     const unsigned i = t + (tid & 63);
     const bool valid = i < n;
-    const unsigned l = valid ? clen[s.symAsc[i]] : 0u;
+    const unsigned l = valid ? lenAsc[i] : 0u;
     const uint64_t peers = match_digit(l, 6, valid);
     if (valid && __popcll(peers & lanemask_lt()) == 0) atomicAdd(&sm.lfirst[l], __popcll(peers));
   }
@@ -819,21 +838,22 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
     lay->max_len = ml;
   }
   __syncthreads();
-  stable_digit_ranks(
-      n, [&](unsigned i) { return (unsigned)clen[s.symAsc[i]]; },
-      [&](unsigned i, unsigned d, unsigned rank) { code[s.symAsc[i]] = sm.lfirst[d] + rank; },
-      sm);
-  __syncthreads();
-  // 7. codebook section: symbols ascending, then their lengths; the packed
-  //    (code, length) word of each coded symbol for the encoder
+  // 7. per symbol: code, length, the packed (code, length) word of the
+  //    encoder, and the codebook section (symbols ascending, then their
+  //    lengths)
   uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
-  for (unsigned i = tid; i < n; i += 1024) {
-    const unsigned sy = s.symAsc[i];
-    const unsigned l = clen[sy];
-    cs[i] = (uint16_t)sy;
-    cb_out[2 * n + i] = (uint8_t)l;
-    s.pk[sy] = (code[sy] << 6) | l;
-  }
+  stable_digit_ranks(
+      n, [&](unsigned i) { return (unsigned)lenAsc[i]; },
+      [&](unsigned i, unsigned d, unsigned rank) {
+        const unsigned sy = s.symAsc[i];
+        const unsigned c = sm.lfirst[d] + rank;
+        code[sy] = c;
+        clen[sy] = (uint8_t)d;
+        s.pk[sy] = (c << 6) | d;
+        cs[i] = (uint16_t)sy;
+        cb_out[2 * n + i] = (uint8_t)d;
+      },
+      sm);
   if (tid == 0) lay->n_codes = n;
 }
 

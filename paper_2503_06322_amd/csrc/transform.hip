@@ -705,6 +705,9 @@ constexpr int kStreamE1 = 2 * kStreamSY + 3, kStreamE2 = 2 * kStreamSX + 3;
 constexpr int kStreamNLD = (kStreamE1 * kStreamE2 + 255) / 256;
 // levels with fewer fine points use the tiled kernel (measured faster there)
 constexpr int64_t kStreamMinPoints = int64_t(1) << 25;
+// Recomposition's restriction (one value per coarse node from the dequantised
+// new nodes) gains from streaming already at half that size.
+constexpr int64_t kRecStreamMinPoints = int64_t(1) << 24;
 
 template <typename Tin>
 struct StreamSmem {
@@ -2076,7 +2079,7 @@ template <bool RAW>
 void rec_restrict_dispatch(const LevelGeom& g, const CoeffSrc& src, double q, double* fout,
                            hipStream_t s) {
   const int D = active_axes(g);
-  if (D == 3 && g.nf[0] * g.nf[1] * g.nf[2] >= kStreamMinPoints) {
+  if (D == 3 && g.nf[0] * g.nf[1] * g.nf[2] >= kRecStreamMinPoints) {
     const StreamGrid sg = stream_grid(g);
     hipLaunchKernelGGL((k_rec_stream<RAW>), dim3(sg.grid), dim3(256), 0, s, g, src, q, fout,
                        sg.seg, sg.n_blocks);
