@@ -1594,7 +1594,8 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
                                                          DecodeTables* __restrict__ t,
                                                          unsigned* status) {
   __shared__ CbSmem sm;
-  const int tid = threadIdx.x;
+  __shared__ uint8_t lenL[kDict];  // code lengths of the section, in its order
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint16_t* syms = reinterpret_cast<const uint16_t*>(cb);
   const uint8_t* lens = cb + 2 * n_codes;
   const unsigned n = (unsigned)n_codes;
@@ -1603,16 +1604,86 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     sm.flag = 0;
     t->valid = 0;
   }
+  // lengths into LDS and symbols checked for strict increase, both read as
+  // aligned 16-byte words covering the section (all of a thread's loads in
+  // flight at once)
+  bool bad = false;
+  {
+    // (the aligned base is formed by pointer arithmetic so that the loads
+    // stay global-memory loads)
+    const unsigned lskip = (unsigned)(reinterpret_cast<uintptr_t>(lens) & 15);
+    const uint4* lw = reinterpret_cast<const uint4*>(lens - lskip);
+    const unsigned nlw = (lskip + n + 15) / 16;
+    for (unsigned w0 = tid; w0 < nlw; w0 += 4096) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = lw[min(w0 + 1024 * u, nlw - 1)];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned w = w0 + 1024 * u;
+        if (w >= nlw) continue;
+        const uint32_t q[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+          const int64_t i = (int64_t)w * 16 + b - lskip;  // section index of this byte
+          if (i >= 0 && i < (int64_t)n) {
+            const unsigned l = (q[b >> 2] >> (8 * (b & 3))) & 255u;
+            bad |= l < 1 || l > (unsigned)kMaxCodeLen;
+            lenL[i] = (uint8_t)l;
+          }
+        }
+      }
+    }
+    const unsigned sskip = (unsigned)(reinterpret_cast<uintptr_t>(syms) & 15) / 2;  // even address
+    const uint4* sw = reinterpret_cast<const uint4*>(syms - sskip);
+    const unsigned nsw = (sskip + n + 7) / 8;
+    for (unsigned w0 = tid; w0 < nsw; w0 += 4096) {
+      uint4 v[4];
+      unsigned prev[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned w = min(w0 + 1024 * u, nsw - 1);
+        v[u] = sw[w];
+        // the element before this word's first one (if it is in the section)
+        const int64_t i = (int64_t)w * 8 - sskip - 1;
+        prev[u] = i >= 0 ? syms[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned w = w0 + 1024 * u;
+        if (w >= nsw) continue;
+        const uint32_t q[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+        int64_t i = (int64_t)w * 8 - sskip;
+        unsigned pv = prev[u];
+#pragma unroll
+        for (int e = 0; e < 8; ++e, ++i) {
+          const unsigned y = (q[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+          if (i >= 1 && i < (int64_t)n) bad |= y <= pv;
+          pv = y;
+        }
+      }
+    }
+  }
+  if (bad) sm.flag = 1;
+  // per-wave counts of each length: wavefront w takes a contiguous run of
+  // the section in tiles of 64 (the same runs rank the codes below)
+  const unsigned run = ((n + 16 * 64 - 1) / (16 * 64)) * 64;
+  const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
+  for (int d = lane; d < 34; d += 64) sm.wl[wave][d] = 0;
+  __syncthreads();  // lengths in LDS
+  for (unsigned t0 = i0; t0 < i1; t0 += 64) {
+    const unsigned i = t0 + lane;
+    const bool valid = i < i1;
+    const unsigned d = valid ? lenL[i] : 0u;
+    const uint64_t peers = match_digit(d, 6, valid);
+    if (valid && __popcll(peers & lanemask_lt()) == 0) sm.wl[wave][d] += __popcll(peers);
+    wave_lds_fence();
+  }
   __syncthreads();
-  // one LDS add per distinct length in each wavefront's 64 codes
-  for (unsigned t = tid & ~63u; t < n; t += 1024) {
-    const unsigned i = t + (tid & 63);
-    const unsigned l = i < n ? lens[i] : 0u;
-    const bool ok = l >= 1 && l <= (unsigned)kMaxCodeLen && (i == 0 || syms[i] > syms[i - 1]);
-    if (i < n && !ok) sm.flag = 1;
-    const bool valid = i < n && ok;
-    const uint64_t peers = match_digit(valid ? l : 0u, 6, valid);
-    if (valid && __popcll(peers & lanemask_lt()) == 0) atomicAdd(&sm.lcount[l], __popcll(peers));
+  if (tid < 34) {
+    unsigned c = 0;
+    for (int w = 0; w < 16; ++w) c += sm.wl[w][tid];
+    sm.lcount[tid] = c;
   }
   __syncthreads();
   __shared__ unsigned long long llim[34];
@@ -1648,11 +1719,46 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     lfirst[tid] = sm.lfirst[tid];
     lbase[tid] = sm.lbase[tid];
   }
+  // symbols in (length, symbol) order: the stable rank of each code among
+  // the codes of its length, from the per-wave counts (scanned over the
+  // wavefronts) and a ranking pass over the same runs, whose symbol loads
+  // run eight tiles ahead of the tile being ranked.
+  if (tid < 34) {
+    unsigned acc = lbase[tid];
+    for (int w = 0; w < 16; ++w) {
+      const unsigned c = sm.wl[w][tid];
+      sm.wl[w][tid] = acc;
+      acc += c;
+    }
+  }
   __syncthreads();
-  // symbols in (length, symbol) order
-  stable_digit_ranks(
-      n, [&](unsigned i) { return (unsigned)lens[i]; },
-      [&](unsigned i, unsigned d, unsigned rank) { t->sorted[lbase[d] + rank] = syms[i]; }, sm);
+  constexpr int PF = 8;
+  uint16_t cur[PF], nxt[PF];
+#pragma unroll
+  for (int u = 0; u < PF; ++u) cur[u] = i0 < i1 ? syms[min(i0 + 64 * u + lane, i1 - 1)] : 0;
+  for (unsigned g = i0; g < i1; g += 64 * PF) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const unsigned i = g + 64 * PF + 64 * u + lane;
+      nxt[u] = g + 64 * PF < i1 ? syms[min(i, i1 - 1)] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const unsigned i = g + 64 * u + lane;
+      const bool valid = i < i1;
+      const unsigned d = valid ? lenL[i] : 0u;
+      const uint64_t peers = match_digit(d, 6, valid);
+      const unsigned r = __popcll(peers & lanemask_lt());
+      const unsigned base = valid ? sm.wl[wave][d] : 0u;
+      if (valid) t->sorted[base + r] = cur[u];
+      wave_lds_fence();
+      if (valid && r == 0) sm.wl[wave][d] = base + __popcll(peers);
+      wave_lds_fence();
+    }
+#pragma unroll
+    for (int u = 0; u < PF; ++u) cur[u] = nxt[u];
+  }
+  __syncthreads();
   // prefix table: the code length at a left-aligned 32-bit window W is one
   // more than the number of lengths whose limit is <= W (limits do not
   // decrease with the length); a prefix's windows span [lo, hi]
