@@ -100,8 +100,7 @@ __device__ __forceinline__ void range_partial_body(const T* __restrict__ u, int6
   const int64_t stride = (int64_t)nblk * 256;
   const int64_t nvec = VEC ? N / V : 0;
   const Vec* uv = reinterpret_cast<const Vec*>(u);
-  for (int64_t i = (int64_t)blk * 256 + threadIdx.x; i < nvec; i += stride) {
-    const Vec w = uv[i];
+  auto acc = [&](const Vec& w) {
     if constexpr (sizeof(T) == 4) {
       range_acc<T>(w.x, mn, mx, ss, bad);
       range_acc<T>(w.y, mn, mx, ss, bad);
@@ -111,7 +110,17 @@ __device__ __forceinline__ void range_partial_body(const T* __restrict__ u, int6
       range_acc<T>(w.x, mn, mx, ss, bad);
       range_acc<T>(w.y, mn, mx, ss, bad);
     }
+  };
+  // four vectors per thread in flight, then the remainder one at a time
+  int64_t i = (int64_t)blk * 256 + threadIdx.x;
+  for (; i + 3 * stride < nvec; i += 4 * stride) {
+    Vec w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = uv[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc(w[k]);
   }
+  for (; i < nvec; i += stride) acc(uv[i]);
   for (int64_t i = nvec * V + (int64_t)blk * 256 + threadIdx.x; i < N; i += stride)
     range_acc<T>((double)u[i], mn, mx, ss, bad);
   for (int o = 32; o > 0; o >>= 1) {
