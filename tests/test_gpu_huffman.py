@@ -83,3 +83,41 @@ def test_gpu_decodes_oracle_stream_and_rejects_corruption():
     with pytest.raises(mgc.MgcError) as e:
         mgc.huffman_decode(dev[: len(ref) - 64], len(sym))
     assert e.value.name == "EFORMAT"
+
+
+def test_four_digit_frequencies_and_tile_edges():
+    """Leaf sort over all four 8-bit digits (a count above 2^24) and symbols
+    on the edges of the 2048-bin sort tiles; codebook and stream must equal
+    the oracle's."""
+    torch, mgc = gpu()
+    rng = np.random.default_rng(11)
+    edges = np.array([0, 1, 2047, 2048, 2049, 4095, 4096, 30719, 30720, 63487, 63488, 65534, 65535])
+    parts = [np.full((1 << 24) + 5, 32768, dtype=np.int64)]
+    for j, e in enumerate(edges):
+        parts.append(np.full(1 + 37 * j, e, dtype=np.int64))
+    parts.append(rng.integers(32000, 33500, size=40000))
+    sym = np.concatenate(parts)
+    rng.shuffle(sym)
+    print("case: four-digit frequencies, n =", len(sym), flush=True)
+    t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
+    enc = mgc.huffman_encode(t, 1024)
+    assert to_bytes(enc) == oracle_huffman_stream(sym, 1024)
+    back = mgc.huffman_decode(enc, len(sym))
+    assert bool((back == t).all())
+
+
+def test_decode_rejects_codebook_out_of_order():
+    """The codebook section lists symbols strictly ascending; a swapped pair
+    must be refused with EFORMAT."""
+    torch, mgc = gpu()
+    sym = _laplace_symbols(30000, 20.0, 8)
+    ref = oracle_huffman_stream(sym, 1024)
+    n_codes = struct.unpack_from("<Q", ref, 16)[0]
+    assert n_codes > 10
+    bad = bytearray(ref)
+    a, b = 48 + 2 * 5, 48 + 2 * 6  # symbols 5 and 6 of the section
+    bad[a:a + 2], bad[b:b + 2] = ref[b:b + 2], ref[a:a + 2]
+    with pytest.raises(mgc.MgcError) as e:
+        mgc.huffman_decode(torch.from_numpy(np.frombuffer(bytes(bad), dtype=np.uint8).copy()).cuda(),
+                           len(sym))
+    assert e.value.name == "EFORMAT"
