@@ -376,10 +376,12 @@ mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t*
       *h_out_size = write_trivial_stream(ctx, h, d_out, s);
       return;
     }
-    MGC_HIP(hipMemsetAsync(w.status, 0, 4 * sizeof(unsigned), s));
-    MGC_HIP(hipMemsetAsync(w.n_out, 0, sizeof(unsigned long long), s));
-    MGC_HIP(hipMemsetAsync(w.lay, 0, sizeof(Layout), s));
-    MGC_HIP(hipMemsetAsync(w.hist, 0, kDict * sizeof(unsigned), s));
+    {
+      void* const zp[4] = {w.status, w.n_out, w.lay, w.hist};
+      const size_t zb[4] = {4 * sizeof(unsigned), sizeof(unsigned long long), sizeof(Layout),
+                            kDict * sizeof(unsigned)};
+      launch_zero_words(zp, zb, 4, s);
+    }
     {
       StageScope sc(&ctx->prof, "range", s);
       const BudgetIn bi{(int)dtype, (int)norm, (int)mode, p.L, error_bound, p.N,
@@ -516,8 +518,8 @@ mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* 
     Carver c(d_ws);
     DecompressWs w = carve_decompress(c, p);
     const uint8_t* in = static_cast<const uint8_t*>(d_in);
-    MGC_HIP(hipMemsetAsync(w.status, 0, 4 * sizeof(unsigned), s));
     {
+      // (the table build clears the status words first)
       StageScope st(&ctx->prof, "decode_tables", s);
       launch_decode_tables(in + cb, h.n_codes, static_cast<DecodeTables*>(w.tables), w.status, s);
     }

@@ -1600,6 +1600,7 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
   const uint8_t* lens = cb + 2 * n_codes;
   const unsigned n = (unsigned)n_codes;
   if (tid < 34) sm.lcount[tid] = 0;
+  if (tid < 4) status[tid] = 0u;  // the call's status words start here (first kernel)
   if (tid == 0) {
     sm.flag = 0;
     t->valid = 0;

@@ -83,6 +83,8 @@ void launch_prolong(const double* v, const LevelGeom& g, double* out, hipStream_
 void launch_adj_mass(const double* Pv, const double* gl, const LevelGeom& g, double* cbar,
                      hipStream_t s);
 void launch_fill(void* out, bool out_f32, int64_t N, double v, hipStream_t s);
+// Zeroes n (1..4) ranges of whole 4-byte words in one launch.
+void launch_zero_words(void* const* ptrs, const size_t* bytes, int n, hipStream_t s);
 // Copies n (<= a few KiB) bytes with one block, e.g. into mapped host memory.
 void launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s);
 
@@ -142,6 +144,9 @@ void launch_header(uint8_t* out, const Header& h, const double* q, int nq, const
 void launch_huff_header(uint8_t* out, uint32_t C, uint64_t N, uint64_t n_chunks,
                         const Layout* lay, unsigned long long* info, hipStream_t s);
 
+// Decode tables from a codebook section; first sets status[0..3] to zero (it
+// is the first kernel of a decompression), then ORs ST_FORMAT into status[0]
+// when the section is invalid.
 void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
                           unsigned* status, hipStream_t s);
 void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,

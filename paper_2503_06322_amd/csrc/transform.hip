@@ -1880,6 +1880,18 @@ __global__ __launch_bounds__(256) void k_copy_bytes(uint8_t* __restrict__ dst,
   for (int i = threadIdx.x; i < n; i += 256) dst[i] = src[i];
 }
 
+// Up to four word ranges set to zero in one launch (the per-call counters
+// and tables a compression starts from).
+struct ZeroRanges {
+  uint32_t* p[4];
+  uint32_t n[4];
+};
+__global__ __launch_bounds__(256) void k_zero_ranges(const ZeroRanges z) {
+  const uint32_t stride = gridDim.x * 256;
+  for (int r = 0; r < 4; ++r)
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < z.n[r]; i += stride) z.p[r][i] = 0u;
+}
+
 template <typename Tout>
 __global__ __launch_bounds__(256) void k_fill(Tout* __restrict__ out, int64_t N, double v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -2407,6 +2419,22 @@ void launch_b_level0(const Job* jobs, const JobBlock* map, uint32_t nb, bool f32
 void launch_copy_bytes(void* dst, const void* src, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_bytes, dim3(1), dim3(256), 0, s, static_cast<uint8_t*>(dst),
                      static_cast<const uint8_t*>(src), (int)n);
+}
+
+void launch_zero_words(void* const* ptrs, const size_t* bytes, int n, hipStream_t s) {
+  if (n < 1 || n > 4) throw std::logic_error("launch_zero_words: one to four ranges");
+  ZeroRanges z{};
+  uint32_t most = 0;
+  for (int r = 0; r < n; ++r) {
+    if (bytes[r] % 4 != 0 || bytes[r] / 4 > 0xFFFFFFFFull ||
+        (reinterpret_cast<uintptr_t>(ptrs[r]) & 3) != 0)
+      throw std::logic_error("launch_zero_words: ranges of whole aligned words");
+    z.p[r] = static_cast<uint32_t*>(ptrs[r]);
+    z.n[r] = (uint32_t)(bytes[r] / 4);
+    most = std::max(most, z.n[r]);
+  }
+  const unsigned blocks = std::max(1u, std::min(64u, (most + 1023) / 1024));
+  hipLaunchKernelGGL(k_zero_ranges, dim3(blocks), dim3(256), 0, s, z);
 }
 
 void launch_fill(void* out, bool out_f32, int64_t N, double v, hipStream_t s) {
