@@ -204,6 +204,44 @@ uint64_t write_trivial_stream(mgc_ctx ctx, Header h, void* d_out, hipStream_t s)
   return h.total;
 }
 
+// The solves on one level's coarse grid x: axis 2, then 1, then 0 (the
+// active ones), sub - x formed after the last.  One launch when the grid fits
+// in LDS, two (x-y planes, then axis 0) when its planes do, else one per
+// axis with the tuned candidates (the caller's forced ones when tuned is
+// set).
+void solve_coarse(mgc_ctx ctx, const LevelGeom& g, double* x, const double* sub, bool fin,
+                  bool use_tuning, hipStream_t s) {
+  if (thomas_grid_fits(g)) {
+    StageScope sc(&ctx->prof, fin ? "thomas[finest]" : "thomas", s);
+    launch_thomas_grid(x, g, sub, s);
+    return;
+  }
+  auto cand = [&](int axis) {
+    return use_tuning ? tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED)
+                      : 0;
+  };
+  const bool ax0 = g.bit[0] >= 0;
+  if (thomas_planes_fit(g)) {
+    {
+      StageScope sc(&ctx->prof, fin ? "thomas[finest]" : "thomas", s);
+      launch_thomas_planes(x, g, ax0 ? nullptr : sub, s);
+    }
+    if (ax0) {
+      StageScope sc(&ctx->prof, fin ? kThomasFinest[0] : "thomas", s);
+      launch_thomas(0, x, g.nc, g.ax[0], sub, s, cand(0));
+    }
+    return;
+  }
+  int last = -1;  // the axis swept last
+  for (int axis = 0; axis <= 2 && last < 0; ++axis)
+    if (g.bit[axis] >= 0) last = axis;
+  for (int axis = 2; axis >= 0; --axis) {
+    if (g.bit[axis] < 0) continue;
+    StageScope sc(&ctx->prof, fin ? kThomasFinest[axis] : "thomas", s);
+    launch_thomas(axis, x, g.nc, g.ax[axis], axis == last ? sub : nullptr, s, cand(axis));
+  }
+}
+
 void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_f32,
                           double* gA, double* gB, uint16_t* sym, double* raw,
                           const std::vector<double>& r, const OutlierBuf& ob, unsigned* status,
@@ -218,17 +256,7 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
       launch_dec_level(Gcur, cur_f32, g, Gnext, sym, raw, sym ? r[l] : 0.0, ob, status, s,
                        tuned(ctx, cur_f32 ? MGC_TUNE_DEC_F32 : MGC_TUNE_DEC_F64));
     }
-    if (thomas_grid_fits(g)) {
-      StageScope sc(&ctx->prof, l == p.L ? "thomas[finest]" : "thomas", s);
-      launch_thomas_grid(Gnext, g, nullptr, s);
-    } else {
-      for (int axis = 2; axis >= 0; --axis) {
-        if (p.bit[axis] < 0) continue;
-        StageScope sc(&ctx->prof, l == p.L ? kThomasFinest[axis] : "thomas", s);
-        launch_thomas(axis, Gnext, g.nc, g.ax[axis], nullptr, s,
-                      tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED));
-      }
-    }
+    solve_coarse(ctx, g, Gnext, nullptr, l == p.L, true, s);
     Gcur = Gnext;
     cur_f32 = false;
   }
@@ -259,12 +287,6 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
   }
   double* Gprev = slot[0];
   double* F = gB;
-  int last = -1;
-  for (int axis = 0; axis <= 2; ++axis)
-    if (p.bit[axis] >= 0) {
-      last = axis;
-      break;
-    }
   for (int l = 1; l <= p.L; ++l) {
     const LevelGeom g = p.geom(l);
     const bool fin = l == p.L;
@@ -272,17 +294,7 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
       StageScope sc(&ctx->prof, fin ? "rec_restrict[finest]" : "rec_restrict", s);
       launch_rec_restrict(g, src, q[l], F, s);
     }
-    if (thomas_grid_fits(g)) {
-      StageScope sc(&ctx->prof, fin ? "thomas[finest]" : "thomas", s);
-      launch_thomas_grid(F, g, Gprev, s);
-    } else {
-      for (int axis = 2; axis >= 0; --axis) {
-        if (p.bit[axis] < 0) continue;
-        StageScope sc(&ctx->prof, fin ? kThomasFinest[axis] : "thomas", s);
-        launch_thomas(axis, F, g.nc, g.ax[axis], axis == last ? Gprev : nullptr, s,
-                      tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED));
-      }
-    }
+    solve_coarse(ctx, g, F, Gprev, fin, true, s);
     {
       StageScope sc(&ctx->prof, fin ? "rec_interp[finest]" : "rec_interp", s);
       double* dst = levels ? slot[l] : Gprev;
@@ -646,16 +658,7 @@ mgc_status mgc_recompose_adjoint(mgc_ctx ctx, const double* d_grad_u, int ndim,
         StageScope sc(&ctx->prof, "adj_restrict", s);
         launch_adj_restrict(g, geom, Gc, w.Y, s);
       }
-      if (thomas_grid_fits(geom)) {
-        StageScope sc(&ctx->prof, "thomas", s);
-        launch_thomas_grid(w.Y, geom, nullptr, s);
-      } else {
-        for (int axis = 2; axis >= 0; --axis) {
-          if (p.bit[axis] < 0) continue;
-          StageScope sc(&ctx->prof, "thomas", s);
-          launch_thomas(axis, w.Y, geom.nc, geom.ax[axis], nullptr, s);
-        }
-      }
+      solve_coarse(ctx, geom, w.Y, nullptr, false, false, s);
       {
         StageScope sc(&ctx->prof, "adj_prolong", s);
         launch_prolong(w.Y, geom, w.T, s);

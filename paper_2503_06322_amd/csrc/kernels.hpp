@@ -62,6 +62,12 @@ void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
 // same results as the per-axis launches, axis 2 first; sub as there, applied
 // after the last sweep).  Only for grids with thomas_grid_fits(g).
 bool thomas_grid_fits(const LevelGeom& g);
+// Axes 2 and 1 (those active) of a coarse grid whose x-y planes fit in LDS,
+// one workgroup per plane, the same results as the per-axis launches; axis 0
+// is left to launch_thomas.  sub as there (pass it only when axis 0 is
+// inactive).  Only for grids with thomas_planes_fit(g).
+bool thomas_planes_fit(const LevelGeom& g);
+void launch_thomas_planes(double* x, const LevelGeom& g, const double* sub, hipStream_t s);
 void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStream_t s);
 // Level-0 block: values of G0 (m0 entries) quantised (sym) or copied (raw).
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,

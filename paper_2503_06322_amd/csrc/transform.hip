@@ -1785,12 +1785,83 @@ struct Thomas3Args {
   int active[3];
 };
 
-__global__ __launch_bounds__(256) void k_thomas_grid(double* __restrict__ x, int64_t n0,
-                                                      int64_t n1, int64_t n2, const Thomas3Args a,
-                                                      const double* __restrict__ sub) {
+// Forward and backward sweep of one line held in LDS (L values, stride
+// apart), four LDS loads issued ahead of each group of four dependent steps.
+__device__ __forceinline__ void lds_line_sweep(double* line, int L, int stride,
+                                               const double* __restrict__ ta,
+                                               const double* __restrict__ tm,
+                                               const double* __restrict__ tc) {
+  double prev = 0.0;
+  for (int i0 = 0; i0 < L; i0 += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = line[min(i0 + u, L - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = min(i0 + u, L - 1);
+      v[u] = thomas_fwd(v[u], ta[i], tm[i], prev);
+      if (i0 + u < L) prev = v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + u < L) line[(i0 + u) * stride] = v[u];
+  }
+  double nxt = 0.0;
+  for (int i0 = L - 1; i0 >= 0; i0 -= 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = line[max(i0 - u, 0) * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = max(i0 - u, 0);
+      v[u] = thomas_bwd(v[u], tc[i], nxt);
+      if (i0 - u >= 0) nxt = v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 - u >= 0) line[(i0 - u) * stride] = v[u];
+  }
+}
+
+// n contiguous values from global memory into LDS (eight loads per thread in
+// flight), and back with sub - value formed on the way out when sub is set.
+template <int NT>
+__device__ __forceinline__ void block_load_lds(const double* __restrict__ src, double* dst, int n) {
+  constexpr int NB = 8;
+  for (int i0 = threadIdx.x; i0 < n; i0 += NB * NT) {
+    double v[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) v[u] = src[min(i0 + u * NT, n - 1)];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      if (i0 + u * NT < n) dst[i0 + u * NT] = v[u];
+  }
+}
+template <int NT>
+__device__ __forceinline__ void block_store_lds(double* __restrict__ dst, const double* src, int n,
+                                                const double* __restrict__ sub) {
+  constexpr int NB = 8;
+  for (int i0 = threadIdx.x; i0 < n; i0 += NB * NT) {
+    double sv[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) sv[u] = sub ? sub[min(i0 + u * NT, n - 1)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int i = i0 + u * NT;
+      if (i < n) dst[i] = sub ? sv[u] - src[i] : src[i];
+    }
+  }
+}
+
+constexpr int kThomasGridThreads = 1024;
+
+__global__ __launch_bounds__(kThomasGridThreads) void k_thomas_grid(
+    double* __restrict__ x, int64_t n0, int64_t n1, int64_t n2, const Thomas3Args a,
+    const double* __restrict__ sub) {
+  constexpr int NT = kThomasGridThreads;
   extern __shared__ double gsm[];
   const int n = (int)(n0 * n1 * n2);
-  for (int i = threadIdx.x; i < n; i += 256) gsm[i] = x[i];
+  block_load_lds<NT>(x, gsm, n);
   __syncthreads();
   const int64_t nn[3] = {n0, n1, n2};
   for (int axis = 2; axis >= 0; --axis) {
@@ -1798,50 +1869,47 @@ __global__ __launch_bounds__(256) void k_thomas_grid(double* __restrict__ x, int
     const int L = (int)nn[axis];
     const int lines = n / L;
     const int stride = axis == 2 ? 1 : (axis == 1 ? (int)n2 : (int)(n1 * n2));
-    const double* ta = a.ta[axis];
-    const double* tm = a.tm[axis];
-    const double* tc = a.tc[axis];
-    for (int t = threadIdx.x; t < lines; t += 256) {
+    for (int t = threadIdx.x; t < lines; t += NT) {
       int base;
       if (axis == 2) base = t * (int)n2;
       else if (axis == 1) base = (t / (int)n2) * (int)(n1 * n2) + t % (int)n2;
       else base = t;
-      // Four LDS loads issued ahead of each group of four dependent steps.
-      double* line = gsm + base;
-      double prev = 0.0;
-      for (int i0 = 0; i0 < L; i0 += 4) {
-        double v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = line[min(i0 + u, L - 1) * stride];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = min(i0 + u, L - 1);
-          v[u] = thomas_fwd(v[u], ta[i], tm[i], prev);
-          if (i0 + u < L) prev = v[u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (i0 + u < L) line[(i0 + u) * stride] = v[u];
-      }
-      double nxt = 0.0;
-      for (int i0 = L - 1; i0 >= 0; i0 -= 4) {
-        double v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = line[max(i0 - u, 0) * stride];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = max(i0 - u, 0);
-          v[u] = thomas_bwd(v[u], tc[i], nxt);
-          if (i0 - u >= 0) nxt = v[u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (i0 - u >= 0) line[(i0 - u) * stride] = v[u];
-      }
+      lds_line_sweep(gsm + base, L, stride, a.ta[axis], a.tm[axis], a.tc[axis]);
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < n; i += 256) x[i] = sub ? sub[i] - gsm[i] : gsm[i];
+  block_store_lds<NT>(x, gsm, n, sub);
+}
+
+// Axes 2 and 1 of a coarse grid whose x-y planes fit in LDS: one workgroup
+// per plane sweeps its rows, then its columns, in LDS (the order of the
+// per-axis launches, with the same arithmetic); axis 0 follows with the
+// per-axis kernel.  sub - x is formed on the way out when axis 0 is
+// inactive.
+constexpr int kThomasPlaneThreads = 1024;  // all of them load and store the plane
+constexpr int kThomasPlaneMaxLine = 256;    // lines per axis (one thread each)
+constexpr int kThomasPlaneMax = 18432;      // points per plane (144 KiB of FP64)
+
+__global__ __launch_bounds__(kThomasPlaneThreads) void k_thomas_planes(
+    double* __restrict__ x, int n1, int n2, const Thomas3Args a, const double* __restrict__ sub) {
+  constexpr int NT = kThomasPlaneThreads;
+  extern __shared__ double psm[];
+  const int m = n1 * n2;
+  double* xp = x + (size_t)blockIdx.x * m;
+  const double* sp = sub ? sub + (size_t)blockIdx.x * m : nullptr;
+  block_load_lds<NT>(xp, psm, m);
+  __syncthreads();
+  if (a.active[2]) {
+    for (int t = threadIdx.x; t < n1; t += NT)
+      lds_line_sweep(psm + t * n2, n2, 1, a.ta[2], a.tm[2], a.tc[2]);
+    __syncthreads();
+  }
+  if (a.active[1]) {
+    for (int t = threadIdx.x; t < n2; t += NT)
+      lds_line_sweep(psm + t, n1, n2, a.ta[1], a.tm[1], a.tc[1]);
+    __syncthreads();
+  }
+  block_store_lds<NT>(xp, psm, m, sp);
 }
 
 template <typename Tin, bool QUANT>
@@ -2246,6 +2314,34 @@ bool thomas_grid_fits(const LevelGeom& g) {
   return true;
 }
 
+bool thomas_planes_fit(const LevelGeom& g) {
+  if (g.bit[1] < 0 && g.bit[2] < 0) return false;  // nothing for the plane kernel
+  // one thread per line, at most one line per thread and axis
+  return g.nc[1] * g.nc[2] <= kThomasPlaneMax && g.nc[1] <= kThomasPlaneMaxLine &&
+         g.nc[2] <= kThomasPlaneMaxLine;
+}
+
+void launch_thomas_planes(double* x, const LevelGeom& g, const double* sub, hipStream_t s) {
+  if (!thomas_planes_fit(g)) throw std::logic_error("launch_thomas_planes: plane exceeds LDS");
+  static bool attr = false;
+  if (!attr) {
+    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_thomas_planes),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(kThomasPlaneMax * sizeof(double))));
+    attr = true;
+  }
+  Thomas3Args a;
+  for (int k = 0; k < 3; ++k) {
+    a.ta[k] = g.ax[k].ta;
+    a.tm[k] = g.ax[k].tm;
+    a.tc[k] = g.ax[k].tc;
+    a.active[k] = g.bit[k] >= 0;
+  }
+  const int m = (int)(g.nc[1] * g.nc[2]);
+  hipLaunchKernelGGL(k_thomas_planes, dim3((unsigned)g.nc[0]), dim3(kThomasPlaneThreads),
+                     (size_t)m * sizeof(double), s, x, (int)g.nc[1], (int)g.nc[2], a, sub);
+}
+
 void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStream_t s) {
   const int64_t n = g.nc[0] * g.nc[1] * g.nc[2];
   if (n > kThomasGridMax) throw std::logic_error("launch_thomas_grid: grid exceeds LDS");
@@ -2263,8 +2359,8 @@ void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStr
     a.tc[k] = g.ax[k].tc;
     a.active[k] = g.bit[k] >= 0;
   }
-  hipLaunchKernelGGL(k_thomas_grid, dim3(1), dim3(256), (size_t)n * sizeof(double), s, x,
-                     g.nc[0], g.nc[1], g.nc[2], a, sub);
+  hipLaunchKernelGGL(k_thomas_grid, dim3(1), dim3(kThomasGridThreads), (size_t)n * sizeof(double),
+                     s, x, g.nc[0], g.nc[1], g.nc[2], a, sub);
 }
 
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
