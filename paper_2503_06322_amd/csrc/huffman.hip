@@ -1795,9 +1795,10 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
 // Coded words reach the 64-bit bit buffer through a ring of RW words per
 // lane in LDS.  At fixed symbol counts (every four symbols, the same points
 // for every lane) a lane whose ring has room for four more words writes the
-// group it loaded earlier and requests the group after next, so two groups
-// of loads are in flight behind the ring and a wavefront waits only for
-// loads issued two refills before.  Four symbols take at most four words
+// group it loaded at its previous refill and loads the next one into the
+// same registers (no register copies, which would wait on the loads just
+// issued), so a wavefront waits only for loads issued a refill period
+// before.  Four symbols take at most four words
 // and each refill point leaves at least four in the ring, so the word a
 // symbol needs is always there.  Decoded symbols are staged in LDS, eight
 // per lane, and stored at the next batch's start, four rows of 16 bytes per
@@ -1864,8 +1865,8 @@ __global__ __launch_bounds__(1024) void k_decode(
   auto ld = [&](uint32_t i) -> uint32_t { return words[min<uint64_t>(w0 + i, last)]; };
   auto msk = [&](uint32_t i, uint32_t v) -> uint32_t { return i < nwc ? v : 0u; };
   uint32_t* rg = ring + (size_t)threadIdx.x * RS;
-  // prologue: the first RW words into the ring, the next two groups in flight
-  uint32_t g0, g1, g2, g3, h0, h1, h2, h3;
+  // prologue: the first RW words into the ring, the next group in flight
+  uint32_t g0, g1, g2, g3;
   {
     uint32_t pre[RW];
 #pragma unroll
@@ -1874,10 +1875,6 @@ __global__ __launch_bounds__(1024) void k_decode(
     g1 = ld(RW + 1);
     g2 = ld(RW + 2);
     g3 = ld(RW + 3);
-    h0 = ld(RW + 4);
-    h1 = ld(RW + 5);
-    h2 = ld(RW + 6);
-    h3 = ld(RW + 7);
 #pragma unroll
     for (int i = 0; i < RW; ++i) rg[i] = msk(i, pre[i]);
   }
@@ -1893,14 +1890,10 @@ __global__ __launch_bounds__(1024) void k_decode(
       rg[(wt + 2) % RW] = msk(wt + 2, g2);
       rg[(wt + 3) % RW] = msk(wt + 3, g3);
       wt += 4;
-      g0 = h0;
-      g1 = h1;
-      g2 = h2;
-      g3 = h3;
-      h0 = ld(wt + 4);
-      h1 = ld(wt + 5);
-      h2 = ld(wt + 6);
-      h3 = ld(wt + 7);
+      g0 = ld(wt);
+      g1 = ld(wt + 1);
+      g2 = ld(wt + 2);
+      g3 = ld(wt + 3);
     }
     nextw = rg[rd % RW];
   };
