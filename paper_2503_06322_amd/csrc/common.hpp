@@ -14,6 +14,7 @@ namespace mgc {
 constexpr uint32_t kDict = 65536;   // dictionary size S (16-bit symbols)
 constexpr uint32_t kHalf = 32768;   // symbol = k + S/2 for |k| < S/2; 0 = escape
 constexpr int kMaxCodeLen = 32;
+constexpr int kPkFirstWords = 64;   // first-code table behind the packed code words
 constexpr int kHeaderBytes = 128;
 constexpr int kHuffHeaderBytes = 48;
 constexpr uint32_t kMagic = 0x3143474Du;      // "MGC1"
@@ -94,7 +95,9 @@ struct CoeffSrc {
 struct CodebookScratch {
   uint32_t *keyA, *valA, *keyB, *valB, *symAsc, *freqAsc, *Iw, *Sw, *leafPar, *parA, *parB,
       *dstA, *dstB;
-  uint32_t* pk;  // per coded symbol: code << 6 | length (valid when max_len <= 26)
+  uint32_t* pk;  // per coded symbol: rank << 6 | length, the rank among the codes of
+                 // that length (code = first code of the length + rank); then, at
+                 // pk[kDict + l], the first code of each length l (kPkFirstWords)
   uint32_t* hcnt;   // multi-block leaf sort: [pass][digit][tile] item counts
   uint32_t* fmaxT;  // multi-block leaf sort: largest frequency per tile
 };

@@ -51,7 +51,7 @@ struct DecodeTables {
 
 size_t decode_tables_bytes() { return sizeof(DecodeTables); }
 
-size_t codebook_scratch_bytes() { return (size_t)kDict * 4 * 16; }
+size_t codebook_scratch_bytes() { return (size_t)kDict * 4 * 16 + kPkFirstWords * 4; }
 
 CodebookScratch carve_codebook_scratch(void* base) {
   uint32_t* p = static_cast<uint32_t*>(base);
@@ -69,7 +69,7 @@ CodebookScratch carve_codebook_scratch(void* base) {
   s.parB = p; p += kDict;
   s.dstA = p; p += kDict;
   s.dstB = p; p += kDict;
-  s.pk = p; p += kDict;
+  s.pk = p; p += kDict + kPkFirstWords;
   s.hcnt = p; p += kDict / 2;
   s.fmaxT = p; p += kDict / 2;
   return s;
@@ -487,7 +487,8 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       const unsigned sy = s.symAsc[0];
       clen[sy] = 1;
       code[sy] = 0;
-      s.pk[sy] = 1u;  // code 0, one bit
+      s.pk[sy] = 1u;  // rank 0, one bit
+      s.pk[kDict + 1] = 0u;  // first code of length 1
       reinterpret_cast<uint16_t*>(cb_out)[0] = (uint16_t)sy;
       cb_out[2] = 1;
       lay->n_codes = 1;
@@ -833,12 +834,13 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       const unsigned cntl = sm.lfirst[l];
       if (cntl) ml = l;
       sm.lfirst[l] = c;
+      s.pk[kDict + l] = c;  // first code of each length, for the encoder
       c = (c + cntl) << 1;
     }
     lay->max_len = ml;
   }
   __syncthreads();
-  // 7. per symbol: code, length, the packed (code, length) word of the
+  // 7. per symbol: code, length, the packed (rank, length) word of the
   //    encoder, and the codebook section (symbols ascending, then their
   //    lengths)
   uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
@@ -849,7 +851,7 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
         const unsigned c = sm.lfirst[d] + rank;
         code[sy] = c;
         clen[sy] = (uint8_t)d;
-        s.pk[sy] = (c << 6) | d;
+        s.pk[sy] = (rank << 6) | d;
         cs[i] = (uint16_t)sy;
         cb_out[2 * n + i] = (uint8_t)d;
       },
@@ -1253,7 +1255,9 @@ __device__ __forceinline__ void encode_body(const uint16_t* __restrict__ sym, in
   const int64_t n_chunks = (N + C - 1) / C;
   const int64_t chunk = (int64_t)blk * 4 + wave;
   uint32_t* w = wbuf + wave * C;
+  __shared__ uint32_t fst[kMaxCodeLen + 1];  // first code of each length
   for (int i = lane; i < C; i += 64) w[i] = 0;
+  if (threadIdx.x <= kMaxCodeLen) fst[threadIdx.x] = pk[kDict + threadIdx.x];
   __syncthreads();
   const uint64_t* offs = reinterpret_cast<const uint64_t*>(out + lay->off);
   uint32_t* words = reinterpret_cast<uint32_t*>(out + lay->words);
@@ -1261,9 +1265,9 @@ __device__ __forceinline__ void encode_body(const uint16_t* __restrict__ sym, in
   const int per = C / 64;
   const int64_t a = live ? chunk * C + (int64_t)lane * per : 0;
   const int64_t end = live ? min<int64_t>(chunk * C + C, N) : 0;
-  if (per == 16 && lay->max_len <= 26) {
+  if (per == 16) {
     // sixteen symbols per lane in two 16-byte loads (element loads at the
-    // array's end), one packed (code, length) word each
+    // array's end), one packed (rank, length) word each
     uint32_t cl[16];
     if (a + 16 <= end && (reinterpret_cast<uintptr_t>(sym) & 15) == 0) {
       const uint4* p = reinterpret_cast<const uint4*>(sym + a);
@@ -1291,7 +1295,7 @@ __device__ __forceinline__ void encode_body(const uint16_t* __restrict__ sym, in
     for (int k = 0; k < 16; ++k) {
       const unsigned l = cl[k] & 63u;
       if (l == 0) continue;
-      put_code(w, bitpos, cl[k] >> 6, l);
+      put_code(w, bitpos, fst[l] + (cl[k] >> 6), l);
       bitpos += l;
     }
     __syncthreads();
@@ -1356,10 +1360,10 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym
 
 // Encoder for large arrays (chunks of 1024 symbols): persistent blocks of
 // kEncWaves wavefronts, one chunk per wavefront at a time.  The packed
-// (code << 6 | length) words of the kEncWin symbols around the dictionary
+// (rank << 6 | length) words of the kEncWin symbols around the dictionary
 // centre (|k| < kEncWin/2, nearly all of them) are copied into LDS once per
-// block, so a symbol's code is an LDS read; the rest come from the global
-// table.  Symbols are loaded two chunks ahead and the global look-ups of
+// block, so a symbol's code (the first code of its length plus its rank) is
+// two LDS reads; the rest come from the global table.  Symbols are loaded two chunks ahead and the global look-ups of
 // the next chunk are issued before the current chunk is coded, so neither
 // waits on memory in the steady state (a look-up of an in-window symbol
 // reads one shared, cached word instead).  Each wavefront ORs its chunk's
@@ -1379,10 +1383,10 @@ struct EncSyms {
 };
 
 __global__ __launch_bounds__(64 * kEncWaves) void k_encode_win(
-    const uint16_t* __restrict__ sym, int64_t N, const uint32_t* __restrict__ code,
-    const uint8_t* __restrict__ clen, const uint32_t* __restrict__ pk, uint8_t* __restrict__ out,
-    const Layout* __restrict__ lay) {
+    const uint16_t* __restrict__ sym, int64_t N, const uint32_t* __restrict__ pk,
+    uint8_t* __restrict__ out, const Layout* __restrict__ lay) {
   extern __shared__ __align__(16) uint32_t esm[];
+  __shared__ uint32_t fst[kMaxCodeLen + 1];  // first code of each length
   if (lay->status) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   uint32_t* tab = esm;
@@ -1391,8 +1395,8 @@ __global__ __launch_bounds__(64 * kEncWaves) void k_encode_win(
   const uint64_t* offs = reinterpret_cast<const uint64_t*>(out + lay->off);
   uint32_t* words = reinterpret_cast<uint32_t*>(out + lay->words);
   const int64_t stride = (int64_t)gridDim.x * kEncWaves;
-  const bool fast = lay->max_len <= 26;
-  if (fast) {
+  if (threadIdx.x <= kMaxCodeLen) fst[threadIdx.x] = pk[kDict + threadIdx.x];
+  {
     const uint4* src = reinterpret_cast<const uint4*>(pk + kEncLo);
     uint4* dst = reinterpret_cast<uint4*>(tab);
     constexpr int NV = kEncWin / 4 / (64 * kEncWaves) + 1;
@@ -1460,35 +1464,6 @@ __global__ __launch_bounds__(64 * kEncWaves) void k_encode_win(
     return x - my_bits;
   };
   int64_t c = (int64_t)blockIdx.x * kEncWaves + wave;
-  if (!fast) {
-    // codes longer than 26 bits: code and length tables in global memory
-    for (; c < n_chunks; c += stride) {
-      EncSyms e;
-      load_syms(c, e);
-      const uint64_t w0 = offs[c], nw = offs[c + 1] - w0;
-      uint32_t cd[16];
-      unsigned ln[16], my_bits = 0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const uint32_t s = sym_at(e, k);
-        cd[k] = k < e.n ? code[s] : 0u;
-        ln[k] = k < e.n ? clen[s] : 0u;
-      }
-      zero_words();
-#pragma unroll
-      for (int k = 0; k < 16; ++k) my_bits += ln[k];
-      unsigned bitpos = scan_bits(my_bits);
-      wave_lds_fence();
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        if (ln[k] == 0) continue;
-        put_code(w, bitpos, cd[k], ln[k]);
-        bitpos += ln[k];
-      }
-      emit(c, w0, nw);
-    }
-    return;
-  }
   if (c >= n_chunks) return;
   EncSyms s0, s1, s2;
   uint32_t g0[16], g1[16];
@@ -1523,7 +1498,7 @@ __global__ __launch_bounds__(64 * kEncWaves) void k_encode_win(
     for (int k = 0; k < 16; ++k) {
       const unsigned l = cl[k] & 63u;
       if (l == 0) continue;
-      put_code(w, bitpos, cl[k] >> 6, l);
+      put_code(w, bitpos, fst[l] + (cl[k] >> 6), l);
       bitpos += l;
     }
     emit(c, o0a, o0b - o0a);
@@ -2164,7 +2139,7 @@ void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
     }
     const int64_t blocks = std::min<int64_t>(kCUs, (n_chunks + kEncWaves - 1) / kEncWaves);
     hipLaunchKernelGGL(k_encode_win, dim3((unsigned)blocks), dim3(64 * kEncWaves),
-                       enc_win_lds_bytes(), s, sym, N, code, clen, pk, out, lay);
+                       enc_win_lds_bytes(), s, sym, N, pk, out, lay);
     return;
   }
   hipLaunchKernelGGL(k_encode, dim3((unsigned)((n_chunks + 3) / 4)), dim3(256),

@@ -138,8 +138,8 @@ void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint
 void launch_outlier_sort(const OutlierBuf& ob, uint32_t* keyA, uint32_t* valA, uint32_t* keyB,
                          uint32_t* valB, int key_bits, uint8_t* out, Layout* lay,
                          hipStream_t s);
-// pk: packed (code << 6 | length) words from the codebook, used when the
-// longest code has at most 26 bits.
+// pk: the codebook's packed (rank << 6 | length) words and first-code table
+// (see CodebookScratch::pk).
 void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
                    const uint8_t* clen, const uint32_t* pk, uint8_t* out, const Layout* lay,
                    hipStream_t s);
