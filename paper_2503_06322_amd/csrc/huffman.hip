@@ -1368,9 +1368,9 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym
 // waits on memory in the steady state (a look-up of an in-window symbol
 // reads one shared, cached word instead).  Each wavefront ORs its chunk's
 // codes into its own LDS words and copies them out; no block barriers.
-constexpr int kEncWin = 32768;
+constexpr int kEncWin = 16384;
 constexpr uint32_t kEncLo = kHalf - kEncWin / 2;
-constexpr int kEncWaves = 6;
+constexpr int kEncWaves = 16;
 constexpr int kEncC = 1024;
 
 __host__ __device__ constexpr size_t enc_win_lds_bytes() {
@@ -2128,7 +2128,7 @@ void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
   // block per CU); the window copy needs 16-byte aligned symbol and table
   // arrays
   constexpr int64_t kCUs = 256;
-  if (C == kEncC && n_chunks >= 8 * kCUs * kEncWaves &&
+  if (C == kEncC && n_chunks >= 2 * kCUs * kEncWaves &&
       (reinterpret_cast<uintptr_t>(sym) & 15) == 0 && (reinterpret_cast<uintptr_t>(pk) & 15) == 0) {
     static bool attr = false;
     if (!attr) {
