@@ -125,7 +125,22 @@ __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ sym,
   const bool vec = (reinterpret_cast<uintptr_t>(sym) & 15) == 0;
   const int64_t nvec = vec ? n / 8 : 0;
   const uint4* sv = reinterpret_cast<const uint4*>(sym);
-  for (int64_t i = (int64_t)blk * 1024 + threadIdx.x; i < nvec; i += stride) {
+  int64_t i = (int64_t)blk * 1024 + threadIdx.x;
+  for (; i + 3 * stride < nvec; i += 4 * stride) {
+    uint4 w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = sv[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const unsigned a[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        hist_add(a[k] & 0xFFFFu, h, hist);
+        hist_add(a[k] >> 16, h, hist);
+      }
+    }
+  }
+  for (; i < nvec; i += stride) {
     const uint4 w = sv[i];
     const unsigned a[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -1368,7 +1383,7 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym
 // waits on memory in the steady state (a look-up of an in-window symbol
 // reads one shared, cached word instead).  Each wavefront ORs its chunk's
 // codes into its own LDS words and copies them out; no block barriers.
-constexpr int kEncWin = 16384;
+constexpr int kEncWin = 20480;
 constexpr uint32_t kEncLo = kHalf - kEncWin / 2;
 constexpr int kEncWaves = 16;
 constexpr int kEncC = 1024;
