@@ -96,7 +96,7 @@ CompressWs carve_compress(Carver& c, const Plan& p, uint64_t cap) {
   w.code = c.take<uint32_t>(kDict);
   w.clen = c.take<uint8_t>(kDict);
   w.cbs = c.take<uint8_t>(codebook_scratch_bytes());
-  w.cw = c.take<uint32_t>(std::max<int64_t>(n_chunks, 1));
+  w.cw = c.take<uint32_t>(chunk_words_len(n_chunks));
   w.opos = c.take<uint32_t>(cap);
   w.oval = c.take<int64_t>(cap);
   w.okA = c.take<uint32_t>(cap);
@@ -714,7 +714,7 @@ mgc_status mgc_huffman_query(uint64_t n, uint32_t C, size_t* ws_bytes, size_t* m
     c.take<uint32_t>(kDict);
     c.take<uint8_t>(kDict);
     c.take<uint8_t>(codebook_scratch_bytes());
-    c.take<uint32_t>(std::max<uint64_t>(n_chunks, 1));
+    c.take<uint32_t>(chunk_words_len((int64_t)n_chunks));
     c.take<Layout>(1);
     c.take<unsigned long long>(4);
     c.take<uint8_t>(decode_tables_bytes());
@@ -743,7 +743,7 @@ mgc_status mgc_huffman_encode(mgc_ctx ctx, const uint16_t* d_sym, uint64_t n, ui
     uint8_t* clen = c.take<uint8_t>(kDict);
     void* cbs = c.take<uint8_t>(codebook_scratch_bytes());
     const CodebookScratch cbsc = carve_codebook_scratch(cbs);
-    uint32_t* cw = c.take<uint32_t>(std::max<uint64_t>(n_chunks, 1));
+    uint32_t* cw = c.take<uint32_t>(chunk_words_len((int64_t)n_chunks));
     Layout* lay = c.take<Layout>(1);
     unsigned long long* info = c.take<unsigned long long>(4);
     uint8_t* out = static_cast<uint8_t*>(d_out);

@@ -1211,6 +1211,142 @@ __global__ __launch_bounds__(1024) void k_layout_scan(const uint32_t* __restrict
   layout_scan_body(cw, n_chunks, out, cb_off, lay, n_out, out_cap_n, huff_only);
 }
 
+// The same layout and offsets from many blocks (large arrays): block b owns
+// the chunks [b R, (b + 1) R).  k_scan_sums writes each range's word total;
+// k_scan_offsets adds the totals of the ranges before its own to an
+// exclusive scan of its range (256 threads, four consecutive chunks each,
+// sixteen loads in flight), and block 0 writes the layout.
+constexpr int kScanThreads = 256;
+constexpr int kScanBlocksMax = kScanSumWords / 2;
+
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
+                                                            unsigned long long* sm) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  unsigned long long t = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) t += sm[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const uint32_t* __restrict__ cw,
+                                                            int64_t n_chunks, int64_t R,
+                                                            unsigned long long* __restrict__ sums) {
+  __shared__ unsigned long long sm[kScanThreads / 64];
+  const int64_t lo = (int64_t)blockIdx.x * R, hi = min<int64_t>(lo + R, n_chunks);
+  unsigned long long acc = 0;
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += 8 * kScanThreads) {
+    uint32_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = cw[min<int64_t>(i0 + u * kScanThreads, hi - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += i0 + u * kScanThreads < hi ? v[u] : 0u;
+  }
+  acc = block_sum_u64(acc, sm);
+  if (threadIdx.x == 0) sums[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_offsets(
+    const uint32_t* __restrict__ cw, int64_t n_chunks, int64_t R,
+    const unsigned long long* __restrict__ sums, uint8_t* __restrict__ out, uint64_t cb_off,
+    Layout* __restrict__ lay, const unsigned long long* n_out, uint64_t out_cap_n,
+    int huff_only) {
+  __shared__ unsigned long long sm[kScanThreads / 64];
+  __shared__ unsigned wsum[kScanThreads / 64][4];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const unsigned long long n_codes = lay->n_codes;
+  const unsigned long long no = huff_only ? 0ull : *n_out;
+  if (no > out_cap_n) {
+    if (blockIdx.x == 0 && tid == 0) {
+      lay->n_outliers = no;
+      lay->status |= ST_OVERFLOW;
+    }
+    return;
+  }
+  const unsigned long long off = pad8(cb_off + 3 * n_codes);
+  const unsigned long long opos = off + 8ull * (n_chunks + 1);
+  const unsigned long long oval = opos + 8ull * no;
+  const unsigned long long words = oval + 8ull * no;
+  uint64_t* offs = reinterpret_cast<uint64_t*>(out + off);
+  // the word totals of the ranges before this block's, and of all ranges
+  unsigned long long pre = 0, all = 0;
+  for (int b = tid; b < (int)gridDim.x; b += kScanThreads) {
+    const unsigned long long v = sums[b];
+    all += v;
+    pre += b < (int)blockIdx.x ? v : 0ull;
+  }
+  pre = block_sum_u64(pre, sm);
+  all = block_sum_u64(all, sm);
+  const int64_t lo = (int64_t)blockIdx.x * R, hi = min<int64_t>(lo + R, n_chunks);
+  unsigned long long base = pre;
+  constexpr int TB = 4 * kScanThreads;  // chunks per sub-tile
+  for (int64_t b0 = lo; b0 < hi; b0 += 4 * TB) {
+    unsigned v[4][4];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      const int64_t e = b0 + TB * sb + 4 * tid;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned x = cw[min<int64_t>(e + u, hi - 1)];
+        v[sb][u] = e + u < hi ? x : 0u;
+      }
+    }
+    unsigned sum[4], incl[4];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      sum[sb] = v[sb][0] + v[sb][1] + v[sb][2] + v[sb][3];
+      incl[sb] = sum[sb];
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        const unsigned y = (unsigned)__shfl_up((int)incl[sb], o, 64);
+        if (lane >= o) incl[sb] += y;
+      }
+    }
+    if (lane == 63) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) wsum[wave][sb] = incl[sb];
+    }
+    __syncthreads();
+    unsigned before[4] = {0u, 0u, 0u, 0u}, tot[4] = {0u, 0u, 0u, 0u};
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb) {
+        const unsigned c = wsum[w][sb];
+        before[sb] += w < wave ? c : 0u;
+        tot[sb] += c;
+      }
+    }
+    unsigned long long run = base;
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      const int64_t e = b0 + TB * sb + 4 * tid;
+      unsigned long long r = run + before[sb] + (incl[sb] - sum[sb]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (e + u < hi) offs[e + u] = r;
+        r += v[sb][u];
+      }
+      run += tot[sb];
+    }
+    base = run;
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    offs[n_chunks] = all;
+    lay->n_outliers = no;
+    lay->n_words = all;
+    lay->cb = cb_off;
+    lay->off = off;
+    lay->opos = opos;
+    lay->oval = oval;
+    lay->words = words;
+    lay->end = pad8(words + 4ull * all);
+  }
+}
+
 __device__ __forceinline__ void outlier_sort_body(const OutlierBuf& ob, uint32_t* keyA,
                                                   uint32_t* valA, uint32_t* keyB,
                                                   uint32_t* valB, int key_bits,
@@ -2124,8 +2260,21 @@ void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* cl
 void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint64_t cb_off,
                         Layout* lay, const unsigned long long* n_out, uint64_t out_cap_n,
                         bool huff_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(1024), 0, s, cw, n_chunks, out, cb_off, lay,
-                     n_out, out_cap_n, huff_only ? 1 : 0);
+  // ranges of at least 4096 chunks; the range totals follow the counts
+  const int64_t nb = std::min<int64_t>(kScanBlocksMax, (n_chunks + 4095) / 4096);
+  if (nb <= 1) {
+    hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(1024), 0, s, cw, n_chunks, out, cb_off, lay,
+                       n_out, out_cap_n, huff_only ? 1 : 0);
+    return;
+  }
+  const int64_t R = ((n_chunks + nb - 1) / nb + 3) & ~int64_t(3);
+  const int64_t blocks = (n_chunks + R - 1) / R;
+  unsigned long long* sums =
+      reinterpret_cast<unsigned long long*>(const_cast<uint32_t*>(cw) + scan_sums_at(n_chunks));
+  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, cw, n_chunks,
+                     R, sums);
+  hipLaunchKernelGGL(k_scan_offsets, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, cw,
+                     n_chunks, R, sums, out, cb_off, lay, n_out, out_cap_n, huff_only ? 1 : 0);
 }
 
 void launch_outlier_sort(const OutlierBuf& ob, uint32_t* keyA, uint32_t* valA, uint32_t* keyB,

@@ -131,7 +131,14 @@ void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* 
 void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
                         uint32_t* cw, Layout* lay, hipStream_t s);
 // Section layout + exclusive scan of the chunk word counts into the stream's
-// offsets section.  huff_only selects the Huffman-only stream layout.
+// offsets section.  huff_only selects the Huffman-only stream layout.  cw
+// holds the n_chunks counts and has room for kScanSumWords more words at
+// cw + scan_sums_at(n_chunks) (the per-block totals of large scans).
+constexpr int kScanSumWords = 512;
+inline int64_t scan_sums_at(int64_t n_chunks) { return (n_chunks + 1) & ~int64_t(1); }
+inline int64_t chunk_words_len(int64_t n_chunks) {
+  return scan_sums_at(n_chunks) + kScanSumWords;
+}
 void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint64_t cb_off,
                         Layout* lay, const unsigned long long* n_out, uint64_t out_cap_n,
                         bool huff_only, hipStream_t s);
