@@ -1798,13 +1798,14 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
   const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
   for (int d = lane; d < 34; d += 64) sm.wl[wave][d] = 0;
   __syncthreads();  // lengths in LDS
+  // one LDS add per distinct length and tile (a wavefront's LDS atomics
+  // take effect in issue order, so the tiles need no fence between them)
   for (unsigned t0 = i0; t0 < i1; t0 += 64) {
     const unsigned i = t0 + lane;
     const bool valid = i < i1;
     const unsigned d = valid ? lenL[i] : 0u;
     const uint64_t peers = match_digit(d, 6, valid);
-    if (valid && __popcll(peers & lanemask_lt()) == 0) sm.wl[wave][d] += __popcll(peers);
-    wave_lds_fence();
+    if (valid && __popcll(peers & lanemask_lt()) == 0) atomicAdd(&sm.wl[wave][d], __popcll(peers));
   }
   __syncthreads();
   if (tid < 34) {
@@ -1871,16 +1872,18 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     }
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
+      // the lowest lane of each length takes the slots with one LDS
+      // add-and-return and hands the first slot to its peers
       const unsigned i = g + 64 * u + lane;
       const bool valid = i < i1;
       const unsigned d = valid ? lenL[i] : 0u;
       const uint64_t peers = match_digit(d, 6, valid);
       const unsigned r = __popcll(peers & lanemask_lt());
-      const unsigned base = valid ? sm.wl[wave][d] : 0u;
+      unsigned first = 0;
+      if (valid && r == 0) first = atomicAdd(&sm.wl[wave][d], __popcll(peers));
+      const int leader = valid ? __ffsll((long long)peers) - 1 : lane;
+      const unsigned base = (unsigned)__shfl((int)first, leader, 64);
       if (valid) t->sorted[base + r] = cur[u];
-      wave_lds_fence();
-      if (valid && r == 0) sm.wl[wave][d] = base + __popcll(peers);
-      wave_lds_fence();
     }
 #pragma unroll
     for (int u = 0; u < PF; ++u) cur[u] = nxt[u];
