@@ -104,8 +104,9 @@ mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t*
  *   shape (3 entries, unused = 0), dtype, the stream length and the
  *   decompression workspace size.  Errors: MGC_EFORMAT.
  * mgc_decompress (BLOCKING: it reads the header from the device): writes the
- *   reconstructed array (dtype and shape of the header) to d_out.
- *   Errors: MGC_EFORMAT, MGC_ENOSPC (out_cap/ws_bytes), MGC_EDEVICE.
+ *   reconstructed array (dtype and shape of the header) to d_out.  d_in
+ *   starts on a 4-byte boundary (MGC_EINVAL otherwise).
+ *   Errors: MGC_EINVAL, MGC_EFORMAT, MGC_ENOSPC (out_cap/ws_bytes), MGC_EDEVICE.
  * ---------------------------------------------------------------------- */
 mgc_status mgc_header_info(const void* h_prefix, size_t n, int* ndim, uint64_t* shape3,
                            mgc_dtype* dtype, uint64_t* stream_bytes, size_t* ws_bytes);
@@ -167,7 +168,7 @@ mgc_status mgc_recompose_levels(mgc_ctx ctx, const double* d_coeffs, int ndim,
  * words, each chunk starting on a word boundary.
  * mgc_huffman_encode is BLOCKING (returns the length in *h_out_size).
  * mgc_huffman_decode writes n symbols to d_sym (asynchronous after a
- * blocking read of the 48-byte header).
+ * blocking read of the 48-byte header); d_in starts on a 4-byte boundary.
  * Errors: MGC_EINVAL, MGC_ENOSPC, MGC_EFORMAT, MGC_EDEVICE.
  * ---------------------------------------------------------------------- */
 mgc_status mgc_huffman_query(uint64_t n, uint32_t C, size_t* ws_bytes, size_t* max_out_bytes);

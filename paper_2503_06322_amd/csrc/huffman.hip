@@ -1921,34 +1921,44 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
 // codes of several lengths (at most one per length boundary) count the
 // canonical limits between their shortest and longest length.
 //
-// Coded words reach the 64-bit bit buffer through a ring of RW words per
-// lane in LDS.  At fixed symbol counts (every four symbols, the same points
-// for every lane) a lane whose ring has room for four more words writes the
-// group it loaded at its previous refill and loads the next one into the
-// same registers (no register copies, which would wait on the loads just
-// issued), so a wavefront waits only for loads issued a refill period
-// before.  Four symbols take at most four words
-// and each refill point leaves at least four in the ring, so the word a
-// symbol needs is always there.  Decoded symbols are staged in LDS, eight
-// per lane, and stored at the next batch's start, four rows of 16 bytes per
-// wave instruction.
-constexpr int kDecSB = 8;
+// Every access to HBM covers whole pieces of a lane's own chunk, since 64
+// lanes read and write 64 chunks far apart and L2 keeps few of their lines
+// between two accesses of one lane:
+//  * coded words arrive in aligned pieces of G words (4G bytes) into a ring
+//    of RW words per lane in LDS; ring index i holds the word 4i bytes past
+//    the lane's first piece, so the chunk's first word sits at index s0 < G
+//    and indices past the chunk's last word read as zero;
+//  * at fixed symbol counts (every P symbols, the same points for every
+//    lane) a lane whose ring has room for G more words writes the piece it
+//    loaded at its previous refill and loads the next one into the same
+//    registers (no register copies, which would wait on the loads just
+//    issued), so a wavefront waits only for loads issued P symbols before;
+//    a refill point leaves at least min(G, RW - G + 1) >= P words in the
+//    ring and P symbols take at most P words, so the word a symbol needs is
+//    always there;
+//  * decoded symbols stay in registers, kDecOB per lane, and leave as whole
+//    128-byte rows (16-byte stores) at the next batch's first refill point.
+constexpr int kDecOB = 64;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __host__ __device__ constexpr size_t dec_sorted_bytes(uint64_t n_codes) {
   return ((size_t)n_codes * sizeof(uint16_t) + 15) & ~size_t(15);
 }
-// dynamic LDS per wavefront beyond the sorted table: ring and staging rows
+// dynamic LDS per wavefront beyond the sorted table: the rings
 __host__ __device__ constexpr size_t dec_wave_bytes(int rw) {
-  return (size_t)64 * ((size_t)(rw + 1) * 4 + (kDecSB + 2) * 2);
+  return (size_t)64 * (size_t)(rw + 1) * 4;
 }
 
-template <int RW>
+template <int RW, int G, int P>
 __global__ __launch_bounds__(1024) void k_decode(
     const uint8_t* __restrict__ in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
     uint64_t n_words, int C, int64_t N, uint32_t n_codes, const DecodeTables* __restrict__ t,
     uint16_t* __restrict__ sym, unsigned* status) {
-  static_assert(RW % 4 == 0 && RW >= 8, "ring of whole groups with room for two");
+  static_assert((RW & (RW - 1)) == 0 && (G & (G - 1)) == 0 && G >= 4 && 2 * G <= RW,
+                "ring of two or more whole pieces");
+  static_assert(G >= P && RW - G + 1 >= P && kDecOB % P == 0, "refill points keep P words");
   constexpr int RS = RW + 1;  // ring row pitch in words (odd: rows start on different banks)
+  constexpr int NQ = G / 4;   // 16-byte loads per piece
   extern __shared__ __align__(16) unsigned char dsm[];
   __shared__ uint32_t lut[1 << kLutBits];
   __shared__ uint32_t lim[kMaxCodeLen + 1], offd[kMaxCodeLen + 1];
@@ -1956,7 +1966,6 @@ __global__ __launch_bounds__(1024) void k_decode(
   const int nthr = blockDim.x;
   uint16_t* sorted = reinterpret_cast<uint16_t*>(dsm);
   uint32_t* ring = reinterpret_cast<uint32_t*>(dsm + dec_sorted_bytes(n_codes));
-  uint16_t* stage = reinterpret_cast<uint16_t*>(ring + (size_t)nthr * RS);
   if (threadIdx.x == 0) valid = t->valid;
   __syncthreads();
   if (!valid) return;  // table build rejected the codebook (status already set)
@@ -1972,10 +1981,8 @@ __global__ __launch_bounds__(1024) void k_decode(
   for (uint32_t i = threadIdx.x; i < n_codes; i += nthr) sorted[i] = t->sorted[i];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const uint64_t wave_chunk0 = (uint64_t)blockIdx.x * nthr + wave * 64;
-  const uint64_t chunk = wave_chunk0 + lane;
+  const uint64_t chunk = (uint64_t)blockIdx.x * nthr + wave * 64 + lane;
   const uint64_t* offs = reinterpret_cast<const uint64_t*>(in + off_sec);
-  const uint32_t* words = reinterpret_cast<const uint32_t*>(in + words_sec);
   bool live = chunk < n_chunks;
   uint64_t w0 = 0, w1 = 0;
   if (live) {
@@ -1988,41 +1995,79 @@ __global__ __launch_bounds__(1024) void k_decode(
   }
   const int64_t start = (int64_t)chunk * C;
   const int cnt = live ? (int)min<int64_t>(C, N - start) : 0;
-  const uint64_t nwc = live ? w1 - w0 : 0;  // words of the chunk; later ones read as zero
-  const uint64_t last = n_words > 0 ? n_words - 1 : 0;
-  // loads from a clamped index, so that no load sits behind a branch
-  auto ld = [&](uint32_t i) -> uint32_t { return words[min<uint64_t>(w0 + i, last)]; };
-  auto msk = [&](uint32_t i, uint32_t v) -> uint32_t { return i < nwc ? v : 0u; };
+  const uint64_t nwc = live ? w1 - w0 : 0;  // words of the chunk
+  // byte offsets from `in` (4-byte aligned): the section [W, E), the first
+  // and last 16-byte-aligned pieces that may be read whole, and the lane's
+  // first 4G-byte-aligned piece rb
+  const int64_t W = (int64_t)words_sec, E = W + 4 * (int64_t)n_words;
+  const int64_t a16 = (int64_t)(reinterpret_cast<uintptr_t>(in) & 15);
+  const int64_t aG = (int64_t)(reinterpret_cast<uintptr_t>(in) & (4 * G - 1));
+  const int64_t lo = ((W + a16) & ~int64_t(15)) - a16;
+  const int64_t hi = ((E + a16) & ~int64_t(15)) - a16 - 16;
+  const int64_t b0 = W + 4 * (int64_t)w0;
+  const int64_t rb = ((b0 + aG) & ~int64_t(4 * G - 1)) - aG;
+  const uint32_t s0 = (uint32_t)((b0 - rb) >> 2);
+  const uint32_t wend = s0 + (uint32_t)nwc;  // ring indices >= wend read as zero
+  // the piece holding ring words i..i+3: pieces before the section read its
+  // first piece (their words precede the chunk and are never used); a piece
+  // that runs past the section's end is read word by word, clamped
+  auto ldp = [&](uint32_t i) -> u32x4 {
+    const int64_t b = max(lo, rb + 4 * (int64_t)i);
+    if (b <= hi) return *reinterpret_cast<const u32x4*>(in + b);
+    const int64_t e4 = E - 4;
+    u32x4 r;
+    r.x = *reinterpret_cast<const uint32_t*>(in + min(b, e4));
+    r.y = *reinterpret_cast<const uint32_t*>(in + min(b + 4, e4));
+    r.z = *reinterpret_cast<const uint32_t*>(in + min(b + 8, e4));
+    r.w = *reinterpret_cast<const uint32_t*>(in + min(b + 12, e4));
+    return r;
+  };
   uint32_t* rg = ring + (size_t)threadIdx.x * RS;
-  // prologue: the first RW words into the ring, the next group in flight
-  uint32_t g0, g1, g2, g3;
+  auto put4 = [&](uint32_t i, const u32x4& v) {
+    rg[i % RW] = i < wend ? v.x : 0u;
+    rg[(i + 1) % RW] = i + 1 < wend ? v.y : 0u;
+    rg[(i + 2) % RW] = i + 2 < wend ? v.z : 0u;
+    rg[(i + 3) % RW] = i + 3 < wend ? v.w : 0u;
+  };
+  // prologue: the first RW words into the ring, the next piece in flight
+  u32x4 g[NQ];
   {
-    uint32_t pre[RW];
+    u32x4 pre[RW / 4];
 #pragma unroll
-    for (int i = 0; i < RW; ++i) pre[i] = ld(i);
-    g0 = ld(RW);
-    g1 = ld(RW + 1);
-    g2 = ld(RW + 2);
-    g3 = ld(RW + 3);
+    for (int q = 0; q < RW / 4; ++q) pre[q] = ldp(4 * q);
 #pragma unroll
-    for (int i = 0; i < RW; ++i) rg[i] = msk(i, pre[i]);
+    for (int q = 0; q < NQ; ++q) g[q] = ldp(RW + 4 * q);
+#pragma unroll
+    for (int q = 0; q < RW / 4; ++q) put4(4 * q, pre[q]);
   }
-  uint64_t buf = ((uint64_t)rg[0] << 32) | rg[1];
-  int nb = 64;                // valid bits in buf (left-aligned)
-  uint32_t rd = 2, wt = RW;   // next word into buf; words written to the ring
+  uint64_t buf = ((uint64_t)rg[s0] << 32) | rg[s0 + 1];
+  int nb = 64;                     // valid bits in buf (left-aligned)
+  uint32_t rd = s0 + 2, wt = RW;   // next word into buf; ring words written
   uint32_t nextw = rg[rd % RW];
   bool bad = false;
+  uint32_t ob[kDecOB / 2];  // the batch's symbols, two per register
+  const bool vec = (C & 7) == 0 && (reinterpret_cast<uintptr_t>(sym) & 15) == 0;
+  auto store_batch = [&](int kb) {
+    const int64_t pos = start + kb;
+    const int64_t n_here = live ? min<int64_t>(min<int64_t>(kDecOB, C - kb), N - pos) : 0;
+    if (vec && n_here == kDecOB) {
+      uint4* dst = reinterpret_cast<uint4*>(sym + pos);
+#pragma unroll
+      for (int q = 0; q < kDecOB / 8; ++q)
+        dst[q] = make_uint4(ob[4 * q], ob[4 * q + 1], ob[4 * q + 2], ob[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kDecOB; ++j)
+        if (j < n_here) sym[pos + j] = (uint16_t)(ob[j >> 1] >> (16 * (j & 1)));
+    }
+  };
   auto top_up = [&]() {
-    if (wt - rd <= (uint32_t)(RW - 4)) {
-      rg[wt % RW] = msk(wt, g0);
-      rg[(wt + 1) % RW] = msk(wt + 1, g1);
-      rg[(wt + 2) % RW] = msk(wt + 2, g2);
-      rg[(wt + 3) % RW] = msk(wt + 3, g3);
-      wt += 4;
-      g0 = ld(wt);
-      g1 = ld(wt + 1);
-      g2 = ld(wt + 2);
-      g3 = ld(wt + 3);
+    if (wt - rd <= (uint32_t)(RW - G)) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) put4(wt + 4 * q, g[q]);
+      wt += G;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) g[q] = ldp(wt + 4 * q);
     }
     nextw = rg[rd % RW];
   };
@@ -2038,50 +2083,39 @@ __global__ __launch_bounds__(1024) void k_decode(
     while (d < dhi && peek >= lim[d]) ++d;
     return offd[d];
   };
-  uint16_t* stw = stage + (size_t)wave * 64 * (kDecSB + 2);
-  uint16_t* mine = stw + lane * (kDecSB + 2);
-  // stores of a staged batch: lane l writes row r + l/8, column l%8
-  auto store_batch = [&](int kb) {
-    uint16_t v[kDecSB];
-#pragma unroll
-    for (int i = 0; i < kDecSB; ++i)
-      v[i] = stw[(i * (64 / kDecSB) + lane / kDecSB) * (kDecSB + 2) + lane % kDecSB];
-    wave_lds_fence();
-#pragma unroll
-    for (int i = 0; i < kDecSB; ++i) {
-      const int row = i * (64 / kDecSB) + lane / kDecSB, col = lane % kDecSB;
-      const uint64_t c = wave_chunk0 + row;
-      const int64_t pos = (int64_t)c * C + kb + col;
-      if (c < n_chunks && kb + col < C && pos < N) sym[pos] = v[i];
-    }
-  };
-  for (int k0 = 0; k0 < C; k0 += kDecSB) {
+  for (int k0 = 0; k0 < C; k0 += kDecOB) {
+    // the previous batch's stores follow the refill loads, so that the next
+    // refill point, which waits for those loads, finds no later store
     top_up();
-    if (k0 > 0) store_batch(k0 - kDecSB);
+    if (k0 > 0) store_batch(k0 - kDecOB);
 #pragma unroll
-    for (int k = 0; k < kDecSB; ++k) {
-      if (k == kDecSB / 2) top_up();
-      const uint32_t peek = (uint32_t)(buf >> 32);
-      uint32_t e = lut[peek >> (32 - kLutBits)];
-      if (e & kLutMixed) e = mixed(e, peek);
-      unsigned d = (e >> 16) & 63u;
-      const uint32_t v = (uint32_t)(((uint64_t)peek << d) >> 32);  // top d bits
-      mine[k] = sorted[(v + e) & 0xFFFFu];
-      d = k0 + k < cnt ? d : 0u;  // past the chunk's last symbol nothing is consumed
-      buf <<= d;
-      nb -= (int)d;
-      const bool need = nb < 32;
-      buf |= (uint64_t)(need ? nextw : 0u) << ((32 - nb) & 63);
-      nb += need ? 32 : 0;
-      rd += need ? 1u : 0u;
-      nextw = rg[rd % RW];
+    for (int k1 = 0; k1 < kDecOB; k1 += P) {
+      if (k1 > 0) top_up();
+#pragma unroll
+      for (int k2 = 0; k2 < P; ++k2) {
+        const int k = k1 + k2;
+        const uint32_t peek = (uint32_t)(buf >> 32);
+        uint32_t e = lut[peek >> (32 - kLutBits)];
+        if (e & kLutMixed) e = mixed(e, peek);
+        unsigned d = (e >> 16) & 63u;
+        const uint32_t v = (uint32_t)(((uint64_t)peek << d) >> 32);  // top d bits
+        const uint32_t sv = sorted[(v + e) & 0xFFFFu];
+        ob[k >> 1] = (k & 1) ? (ob[k >> 1] | (sv << 16)) : sv;
+        d = k0 + k < cnt ? d : 0u;  // past the chunk's last symbol nothing is consumed
+        buf <<= d;
+        nb -= (int)d;
+        const bool need = nb < 32;
+        buf |= (uint64_t)(need ? nextw : 0u) << ((32 - nb) & 63);
+        nb += need ? 32 : 0;
+        rd += need ? 1u : 0u;
+        nextw = rg[rd % RW];
+      }
     }
-    wave_lds_fence();
   }
-  store_batch(((C - 1) / kDecSB) * kDecSB);
+  store_batch(((C - 1) / kDecOB) * kDecOB);
   // bits taken from the chunk: the words moved into the buffer less those
   // still in it
-  const int64_t used = (int64_t)rd * 32 - nb;
+  const int64_t used = ((int64_t)rd - s0) * 32 - nb;
   if (live && (bad || used > (int64_t)nwc * 32)) atomicOr(status, ST_FORMAT);
 }
 
@@ -2331,15 +2365,16 @@ void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
 }
 
 namespace {
-template <int RW>
+// decoder shapes (ring words, piece words, refill period), widest first
+template <int RW, int G, int P>
 size_t decode_room() {
   // the dynamic LDS the kernel can take on top of its static LDS (160 KiB per CU)
   static size_t room = 0;
   if (room == 0) {
     hipFuncAttributes fa;
-    MGC_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_decode<RW>)));
+    MGC_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(k_decode<RW, G, P>)));
     const size_t r = 163840 - fa.sharedSizeBytes;
-    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_decode<RW>),
+    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_decode<RW, G, P>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)r));
     room = r;
   }
@@ -2350,29 +2385,37 @@ size_t decode_room() {
 void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
                    uint64_t n_words, int C, int64_t N, uint64_t n_codes, const DecodeTables* t,
                    uint16_t* sym, unsigned* status, hipStream_t s) {
+  // the kernel reads whole 16-byte pieces of the word section
+  if ((reinterpret_cast<uintptr_t>(in) & 3) != 0 || (words_sec & 3) != 0)
+    fail(MGC_EINVAL, "compressed stream must start on a 4-byte boundary");
   // wavefronts per block: enough that one block per CU covers every chunk
   // (one pass over the 256 CUs), at most 16; then the widest ring that fits
-  // in LDS beside the symbol table, else fewer wavefronts
+  // in LDS beside the symbol table (64-, 32- or 16-byte pieces), else fewer
+  // wavefronts with the narrowest ring
   constexpr uint64_t kCUs = 256;
   int waves = (int)std::min<uint64_t>(16, std::max<uint64_t>(1, (n_chunks + 64 * kCUs - 1) / (64 * kCUs)));
   const size_t tab = dec_sorted_bytes(n_codes);
-  int rw = 16;
-  while (true) {
-    const size_t room = rw == 16 ? decode_room<16>() : decode_room<8>();
-    if (tab + (size_t)waves * dec_wave_bytes(rw) <= room) break;
-    if (rw == 16) rw = 8;
+  constexpr int kRW[3] = {32, 16, 8};
+  const size_t room[3] = {decode_room<32, 16, 16>(), decode_room<16, 8, 8>(),
+                          decode_room<8, 4, 4>()};
+  int shape = 0;
+  while (tab + (size_t)waves * dec_wave_bytes(kRW[shape]) > room[shape]) {
+    if (shape < 2) ++shape;
     else if (waves > 1) --waves;
     else fail(MGC_EDEVICE, "decode table does not fit in LDS");
   }
   const int nthr = 64 * waves;
   const dim3 grid((unsigned)((n_chunks + nthr - 1) / nthr));
-  const size_t dyn = tab + (size_t)waves * dec_wave_bytes(rw);
-  if (rw == 16)
-    hipLaunchKernelGGL(k_decode<16>, grid, dim3(nthr), dyn, s, in, off_sec, words_sec, n_chunks,
-                       n_words, C, N, (uint32_t)n_codes, t, sym, status);
+  const size_t dyn = tab + (size_t)waves * dec_wave_bytes(kRW[shape]);
+  if (shape == 0)
+    hipLaunchKernelGGL((k_decode<32, 16, 16>), grid, dim3(nthr), dyn, s, in, off_sec, words_sec,
+                       n_chunks, n_words, C, N, (uint32_t)n_codes, t, sym, status);
+  else if (shape == 1)
+    hipLaunchKernelGGL((k_decode<16, 8, 8>), grid, dim3(nthr), dyn, s, in, off_sec, words_sec,
+                       n_chunks, n_words, C, N, (uint32_t)n_codes, t, sym, status);
   else
-    hipLaunchKernelGGL(k_decode<8>, grid, dim3(nthr), dyn, s, in, off_sec, words_sec, n_chunks,
-                       n_words, C, N, (uint32_t)n_codes, t, sym, status);
+    hipLaunchKernelGGL((k_decode<8, 4, 4>), grid, dim3(nthr), dyn, s, in, off_sec, words_sec,
+                       n_chunks, n_words, C, N, (uint32_t)n_codes, t, sym, status);
 }
 
 }  // namespace mgc

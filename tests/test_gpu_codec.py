@@ -133,6 +133,21 @@ def test_rejects_corrupt_streams():
         mgc.decompress(bad)
 
 
+def test_decompress_stream_at_word_offsets():
+    """A compressed stream copied 4, 12 or 36 bytes past an aligned address
+    reconstructs the same array, bit for bit."""
+    torch, mgc = gpu()
+    u = _field((65, 33, 47), np.float32, 5)
+    blob = mgc.compress(torch.from_numpy(u).cuda(), 1e-3)
+    ref = mgc.decompress(blob)
+    n = blob.numel()
+    for off in (4, 12, 36):
+        print("case: offset", off, flush=True)
+        buf = torch.zeros(n + 64, dtype=torch.uint8, device="cuda")
+        buf[off:off + n] = blob
+        assert bool(torch.equal(mgc.decompress(buf[off:off + n]), ref)), off
+
+
 def test_outlier_capacity_retry():
     torch, mgc = gpu()
     u = _field((65, 65, 65), np.float32, 3)

@@ -121,3 +121,29 @@ def test_decode_rejects_codebook_out_of_order():
         mgc.huffman_decode(torch.from_numpy(np.frombuffer(bytes(bad), dtype=np.uint8).copy()).cuda(),
                            len(sym))
     assert e.value.name == "EFORMAT"
+
+
+@pytest.mark.parametrize("C", [1024, 100])
+def test_decode_stream_at_any_word_offset(C):
+    """The decoder reads the coded words in aligned 16- and 64-byte pieces:
+    a stream starting 4..60 bytes past an aligned address decodes the same
+    (C = 100 also takes the element-wise symbol stores); a stream that does
+    not start on a 4-byte boundary is refused."""
+    torch, mgc = gpu()
+    sym = _laplace_symbols(100_003, 700.0, 12)
+    t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
+    # (the encoder takes chunk sizes in multiples of 64; the oracle any)
+    ref = oracle_huffman_stream(sym, C)
+    enc = torch.from_numpy(np.frombuffer(ref, dtype=np.uint8).copy()).cuda()
+    n = enc.numel()
+    for off in (0, 4, 8, 12, 20, 36, 60):
+        print("case: C", C, "offset", off, flush=True)
+        buf = torch.zeros(n + 128, dtype=torch.uint8, device="cuda")
+        buf[off:off + n] = enc
+        back = mgc.huffman_decode(buf[off:off + n], len(sym))
+        assert bool((back == t).all()), off
+    buf = torch.zeros(n + 128, dtype=torch.uint8, device="cuda")
+    buf[2:2 + n] = enc
+    with pytest.raises(mgc.MgcError) as e:
+        mgc.huffman_decode(buf[2:2 + n], len(sym))
+    assert e.value.name == "EINVAL"
