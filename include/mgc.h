@@ -234,6 +234,22 @@ mgc_status mgc_set_tuning(mgc_ctx ctx, int kind, int candidate);
 mgc_status mgc_tuning_info(mgc_ctx ctx, int kind, int* n_candidates, int* last_choice);
 
 /* ------------------------------------------------------------------------
+ * Decoder launch shape (Algorithm 2, decoding: one thread per chunk).  The
+ * decoder keeps each thread's coded words in an LDS ring refilled with whole
+ * aligned pieces: ring 1 = 64-byte pieces refilled every 16 symbols, 2 =
+ * 32-byte pieces every 8, 3 = 16-byte pieces every 4; by default the widest
+ * ring that fits beside the codebook's symbol table is used, with enough
+ * wavefronts per block that one pass of blocks covers the GPU.
+ * mgc_set_decoder forces a ring (0 = automatic) and a wavefront count per
+ * block (1..16, 0 = automatic) for later decodes on the context (decompress
+ * and huffman_decode); a forced pair that does not fit in LDS makes those
+ * calls fail with MGC_EINVAL.  Every shape decodes the same symbols.
+ * mgc_decoder_info returns the pair the context's latest decode used.
+ * ---------------------------------------------------------------------- */
+mgc_status mgc_set_decoder(mgc_ctx ctx, int ring, int waves);
+mgc_status mgc_decoder_info(mgc_ctx ctx, int* ring, int* waves);
+
+/* ------------------------------------------------------------------------
  * Stage timing.  When enabled, every entry point records HIP events around
  * each kernel launch on its stream; mgc_profile_read returns, per stage
  * name, the number of launches and their total GPU milliseconds accumulated

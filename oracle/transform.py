@@ -207,10 +207,15 @@ def finest_coefficients_at(u: np.ndarray, h: Hierarchy, flat_idx):
     multilinear interpolant from its nearest coarse neighbours on each axis
     where it is new (the lerp step), and its stream position.  Indices of
     coarse nodes are skipped.  Returns (stream positions, coefficients).
+    With no decomposition level (L = 0) the stream is the nodal block itself,
+    so every index is returned with its own value at its row-major position.
     """
     sizes = h.sizes[h.L]
     ua = np.asarray(u).reshape(sizes)
     l = h.L
+    if l == 0:
+        fi = np.asarray(flat_idx, dtype=np.int64)
+        return fi.copy(), np.asarray(ua, dtype=np.float64).ravel()[fi]
     sl = level_slices(h)
     sub_sets = {}
     sub_off = {}

@@ -25,7 +25,7 @@ __all__ = ["MgcError", "library_path", "compress", "decompress", "decompose", "r
            "recompose_adjoint", "recompose_levels", "Recompose", "huffman_encode",
            "huffman_decode", "header_info", "profile_enable", "profile_reset", "profile_read",
            "compress_query", "transform_query", "batch_query", "Batch", "compress_batched",
-           "set_tuning", "tuning_info"]
+           "set_tuning", "tuning_info", "set_decoder", "decoder_info"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmgc.so")
@@ -99,6 +99,8 @@ def _load():
             "mgc_set_tuning": [vp, ctypes.c_int, ctypes.c_int],
             "mgc_tuning_info": [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int)],
+            "mgc_set_decoder": [vp, ctypes.c_int, ctypes.c_int],
+            "mgc_decoder_info": [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
             "mgc_profile_enable": [vp, ctypes.c_int],
             "mgc_profile_reset": [vp],
             "mgc_profile_read": [vp, ctypes.c_char_p, ctypes.c_size_t, c_u64p,
@@ -337,6 +339,24 @@ def tuning_info(kind: str, device=None):
     _check(_load().mgc_tuning_info(_ctx(dev), TUNE_KINDS[kind], ctypes.byref(n),
                                    ctypes.byref(last)))
     return n.value, last.value
+
+
+def set_decoder(ring: int = 0, waves: int = 0, device=None):
+    """Force the decoder's ring (1: 64-byte pieces, 2: 32-byte, 3: 16-byte;
+    0 = automatic) and wavefronts per block (1..16, 0 = automatic)."""
+    torch = _torch()
+    dev = device if device is not None else torch.cuda.current_device()
+    _check(_load().mgc_set_decoder(_ctx(dev), int(ring), int(waves)))
+
+
+def decoder_info(device=None):
+    """(ring, wavefronts per block) used by the latest decode."""
+    torch = _torch()
+    dev = device if device is not None else torch.cuda.current_device()
+    ring = ctypes.c_int()
+    waves = ctypes.c_int()
+    _check(_load().mgc_decoder_info(_ctx(dev), ctypes.byref(ring), ctypes.byref(waves)))
+    return ring.value, waves.value
 
 
 def header_info(stream):

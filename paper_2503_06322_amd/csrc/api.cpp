@@ -537,8 +537,9 @@ mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* 
     }
     {
       StageScope st(&ctx->prof, "decode", s);
-      launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, p.N, h.n_codes,
-                    static_cast<const DecodeTables*>(w.tables), w.sym, w.status, s);
+      ctx->dec_last = launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, p.N,
+                                    h.n_codes, static_cast<const DecodeTables*>(w.tables),
+                                    w.sym, w.status, s, ctx->dec_force);
     }
     CoeffSrc src{w.sym, nullptr, reinterpret_cast<const uint64_t*>(in + opos),
                  reinterpret_cast<const int64_t*>(in + oval), (int64_t)h.n_outliers};
@@ -813,14 +814,33 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes, ui
     }
     {
       StageScope st(&ctx->prof, "decode", s);
-      launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, (int64_t)n, h.n_codes,
-                    static_cast<const DecodeTables*>(tables), d_sym, status, s);
+      ctx->dec_last = launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C,
+                                    (int64_t)n, h.n_codes,
+                                    static_cast<const DecodeTables*>(tables), d_sym, status, s,
+                                    ctx->dec_force);
     }
     MGC_HIP(hipGetLastError());
     unsigned st = 0;
     sync_read(ctx, ctx->pinned, status, sizeof(unsigned), s);
     std::memcpy(&st, ctx->pinned, sizeof(unsigned));
     if (st & ST_FORMAT) fail(MGC_EFORMAT, "corrupt coded data");
+  });
+}
+
+mgc_status mgc_set_decoder(mgc_ctx ctx, int ring, int waves) {
+  return guard([&] {
+    if (!ctx) fail(MGC_EINVAL, "null context");
+    if (ring < 0 || ring > 3) fail(MGC_EINVAL, "decoder ring must be 0..3");
+    if (waves < 0 || waves > 16) fail(MGC_EINVAL, "decoder wavefronts must be 0..16");
+    ctx->dec_force = DecodeShape{ring, waves};
+  });
+}
+
+mgc_status mgc_decoder_info(mgc_ctx ctx, int* ring, int* waves) {
+  return guard([&] {
+    if (!ctx) fail(MGC_EINVAL, "null context");
+    if (ring) *ring = ctx->dec_last.ring;
+    if (waves) *waves = ctx->dec_last.waves;
   });
 }
 

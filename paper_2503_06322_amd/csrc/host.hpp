@@ -137,6 +137,9 @@ struct mgc_ctx_s {
   hipStream_t capture_stream = nullptr;
   int forced_tuning[4] = {-1, -1, -1, -1};
   int last_tuning[4] = {-1, -1, -1, -1};
+  // decoder launch shape forced by the caller (0 = automatic) and the one
+  // the latest decode used
+  mgc::DecodeShape dec_force, dec_last;
 };
 
 namespace mgc {

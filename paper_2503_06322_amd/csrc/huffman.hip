@@ -1755,8 +1755,11 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
           const int64_t i = (int64_t)w * 16 + b - lskip;  // section index of this byte
           if (i >= 0 && i < (int64_t)n) {
             const unsigned l = (q[b >> 2] >> (8 * (b & 3))) & 255u;
-            bad |= l < 1 || l > (unsigned)kMaxCodeLen;
-            lenL[i] = (uint8_t)l;
+            const bool out_of_range = l < 1 || l > (unsigned)kMaxCodeLen;
+            bad |= out_of_range;
+            // a rejected length is stored as 0 so that the per-length counts
+            // below (which run before the rejection is acted on) index in range
+            lenL[i] = out_of_range ? (uint8_t)0 : (uint8_t)l;
           }
         }
       }
@@ -2382,24 +2385,29 @@ size_t decode_room() {
 }
 }  // namespace
 
-void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
-                   uint64_t n_words, int C, int64_t N, uint64_t n_codes, const DecodeTables* t,
-                   uint16_t* sym, unsigned* status, hipStream_t s) {
+DecodeShape launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec,
+                          uint64_t n_chunks, uint64_t n_words, int C, int64_t N,
+                          uint64_t n_codes, const DecodeTables* t, uint16_t* sym,
+                          unsigned* status, hipStream_t s, DecodeShape force) {
   // the kernel reads whole 16-byte pieces of the word section
   if ((reinterpret_cast<uintptr_t>(in) & 3) != 0 || (words_sec & 3) != 0)
     fail(MGC_EINVAL, "compressed stream must start on a 4-byte boundary");
   // wavefronts per block: enough that one block per CU covers every chunk
   // (one pass over the 256 CUs), at most 16; then the widest ring that fits
   // in LDS beside the symbol table (64-, 32- or 16-byte pieces), else fewer
-  // wavefronts with the narrowest ring
+  // wavefronts with the narrowest ring.  A forced ring or wavefront count
+  // replaces the automatic choice and must fit.
   constexpr uint64_t kCUs = 256;
   int waves = (int)std::min<uint64_t>(16, std::max<uint64_t>(1, (n_chunks + 64 * kCUs - 1) / (64 * kCUs)));
+  if (force.waves > 0) waves = force.waves;
   const size_t tab = dec_sorted_bytes(n_codes);
   constexpr int kRW[3] = {32, 16, 8};
   const size_t room[3] = {decode_room<32, 16, 16>(), decode_room<16, 8, 8>(),
                           decode_room<8, 4, 4>()};
-  int shape = 0;
+  int shape = force.ring > 0 ? force.ring - 1 : 0;
   while (tab + (size_t)waves * dec_wave_bytes(kRW[shape]) > room[shape]) {
+    if (force.ring > 0 || force.waves > 0)
+      fail(MGC_EINVAL, "the forced decoder ring and wavefront count do not fit in LDS");
     if (shape < 2) ++shape;
     else if (waves > 1) --waves;
     else fail(MGC_EDEVICE, "decode table does not fit in LDS");
@@ -2416,6 +2424,7 @@ void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint
   else
     hipLaunchKernelGGL((k_decode<8, 4, 4>), grid, dim3(nthr), dyn, s, in, off_sec, words_sec,
                        n_chunks, n_words, C, N, (uint32_t)n_codes, t, sym, status);
+  return DecodeShape{shape + 1, waves};
 }
 
 }  // namespace mgc

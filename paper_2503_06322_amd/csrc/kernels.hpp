@@ -162,8 +162,16 @@ void launch_huff_header(uint8_t* out, uint32_t C, uint64_t N, uint64_t n_chunks,
 // when the section is invalid.
 void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
                           unsigned* status, hipStream_t s);
-void launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec, uint64_t n_chunks,
-                   uint64_t n_words, int C, int64_t N, uint64_t n_codes, const DecodeTables* t,
-                   uint16_t* sym, unsigned* status, hipStream_t s);
+// Decoder launch shape: ring (1: 64-byte pieces, ring of 32 words, refill
+// every 16 symbols; 2: 32-byte pieces, 16 words, every 8; 3: 16-byte pieces,
+// 8 words, every 4) and wavefronts per block; 0 = automatic.  Returns the
+// shape used.
+struct DecodeShape {
+  int ring = 0, waves = 0;
+};
+DecodeShape launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_sec,
+                          uint64_t n_chunks, uint64_t n_words, int C, int64_t N,
+                          uint64_t n_codes, const DecodeTables* t, uint16_t* sym,
+                          unsigned* status, hipStream_t s, DecodeShape force = DecodeShape{});
 
 }  // namespace mgc

@@ -10,6 +10,10 @@
 * the 256-array batch (axes from {33, 65, 129, 257}, relative L-inf bounds
   from {1e-2, 1e-3, 1e-4}, bump and |k|^-3 fields) matches plain calls array
   by array and every reconstruction holds its bound;
+* every batched stream of the small mixed batch equals the FP64 oracle's
+  stream of the same array and request, byte for byte (oracle.compress), for
+  relative and absolute L-inf and relative L2 bounds; a slice of the
+  256-array batch is compared with the oracle in test_gpu_oracle_fullsize.py;
 * small arrays of the batch decode with the FP64 oracle's decoder too.
 """
 from concurrent.futures import ThreadPoolExecutor
@@ -19,7 +23,7 @@ import pytest
 
 import oracle
 import synthetic
-from tests.gpu_common import gpu, to_bytes
+from tests.gpu_common import assert_stream_matches_oracle, gpu, to_bytes
 
 pytestmark = pytest.mark.gpu
 
@@ -62,6 +66,21 @@ def test_batched_equals_plain(norm, mode, flags):
     bounds = [b for (_, _, _, b) in SMALL]
     out = mgc.compress_batched(xs, bounds, norm, mode, flags=flags)
     _assert_same_as_plain(mgc, xs, bounds, out, norm, mode)
+
+
+@pytest.mark.parametrize("norm,mode", [("linf", "rel"), ("l2", "rel"), ("linf", "abs")])
+def test_batched_streams_equal_oracle(norm, mode):
+    torch, mgc = gpu()
+    xs = _inputs(torch, seed=51)
+    bounds = [b for (_, _, _, b) in SMALL]
+    if mode == "abs":
+        bounds = [b * 2.0 for b in bounds]
+    out = mgc.compress_batched(xs, bounds, norm, mode)
+    for j, (x, bd) in enumerate(zip(xs, bounds)):
+        u = x.cpu().numpy()
+        ref = oracle.compress(u, bd, norm, mode)
+        print("case: array", j, u.shape, u.dtype, norm, mode, flush=True)
+        assert_stream_matches_oracle(to_bytes(out[j]), ref, norm)
 
 
 def test_every_tuning_candidate_gives_the_same_streams():

@@ -80,6 +80,17 @@ def test_gpu_decodes_oracle_stream_and_rejects_corruption():
         mgc.huffman_decode(torch.from_numpy(np.frombuffer(bytes(bad), dtype=np.uint8).copy()).cuda(),
                            len(sym))
     assert e.value.name == "EFORMAT"
+    # lengths beyond the 32-bit limit (one far beyond the per-length count
+    # tables) are rejected too, and a good stream decodes again afterwards
+    for bad_len in (33, 200, 255):
+        bad = bytearray(ref)
+        bad[48 + 2 * n_codes + 3] = bad_len
+        with pytest.raises(mgc.MgcError) as e:
+            mgc.huffman_decode(torch.from_numpy(np.frombuffer(bytes(bad), dtype=np.uint8).copy()).cuda(),
+                               len(sym))
+        assert e.value.name == "EFORMAT"
+    back = mgc.huffman_decode(dev, len(sym)).cpu().numpy().view(np.uint16)
+    assert np.array_equal(back.astype(np.int64), sym)
     with pytest.raises(mgc.MgcError) as e:
         mgc.huffman_decode(dev[: len(ref) - 64], len(sym))
     assert e.value.name == "EFORMAT"
@@ -147,3 +158,91 @@ def test_decode_stream_at_any_word_offset(C):
     with pytest.raises(mgc.MgcError) as e:
         mgc.huffman_decode(buf[2:2 + n], len(sym))
     assert e.value.name == "EINVAL"
+
+
+@pytest.fixture
+def forced_decoder():
+    """Forces decoder shapes inside a test and restores automatic choice."""
+    torch, mgc = gpu()
+    yield mgc.set_decoder
+    mgc.set_decoder(0, 0)
+
+
+@pytest.mark.parametrize("n,scale,C", [(300000, 3000.0, 1024), (70000, 5.0, 64),
+                                       (2_000_000, 9000.0, 1024), (12_600_007, 3000.0, 1024)])
+def test_every_decoder_ring_with_several_wavefronts(n, scale, C, forced_decoder):
+    """The three ring shapes (64-, 32- and 16-byte pieces, refill points every
+    16, 8 and 4 symbols) with 2, 4 and 16 wavefronts per block decode the
+    oracle's stream to exactly the encoded symbols (Algorithm 2, decoding).
+    The automatic choice of the full-size benchmark field is the 16-byte ring
+    with several wavefronts; these cases cover every shape on identical
+    streams."""
+    torch, mgc = gpu()
+    sym = _laplace_symbols(n, scale, n + 1)
+    ref = oracle_huffman_stream(sym, C)
+    enc = torch.from_numpy(np.frombuffer(ref, dtype=np.uint8).copy()).cuda()
+    t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
+    for ring in (1, 2, 3):
+        for waves in (2, 4, 16):
+            print("case: n", n, "ring", ring, "waves", waves, flush=True)
+            forced_decoder(ring, waves)
+            back = mgc.huffman_decode(enc, n)
+            assert mgc.decoder_info() == (ring, waves)
+            assert bool((back == t).all()), (ring, waves)
+
+
+@pytest.mark.parametrize("ring", [1, 2, 3])
+def test_decode_at_any_word_offset_every_ring(ring, forced_decoder):
+    """Stream starts 4..60 bytes past an aligned address, for each ring shape
+    with two wavefronts per block."""
+    torch, mgc = gpu()
+    sym = _laplace_symbols(100_003, 700.0, 12)
+    t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
+    ref = oracle_huffman_stream(sym, 1024)
+    enc = torch.from_numpy(np.frombuffer(ref, dtype=np.uint8).copy()).cuda()
+    n = enc.numel()
+    forced_decoder(ring, 2)
+    for off in (0, 4, 8, 12, 20, 36, 60):
+        buf = torch.zeros(n + 128, dtype=torch.uint8, device="cuda")
+        buf[off:off + n] = enc
+        back = mgc.huffman_decode(buf[off:off + n], len(sym))
+        assert mgc.decoder_info() == (ring, 2)
+        assert bool((back == t).all()), off
+
+
+def test_decoder_choice_on_large_codebook_and_forced_shapes_that_do_not_fit(forced_decoder):
+    """A codebook of 55,000 codes (the size class of the 513^3 benchmark
+    field's) leaves room only for a narrower ring when a block holds nine
+    wavefronts: the automatic choice falls back to one, a forced 64-byte ring
+    with nine wavefronts is refused (EINVAL) instead of overrunning LDS, and
+    every shape that fits decodes the same symbols."""
+    torch, mgc = gpu()
+    rng = np.random.default_rng(4)
+    base = np.arange(1, 55001, dtype=np.int64)
+    lap = np.clip(np.round(rng.laplace(0, 2000, 3_000_000)) + 27500, 1, 55000).astype(np.int64)
+    sym = np.concatenate([base, lap])
+    rng.shuffle(sym)
+    n = len(sym)
+    ref = oracle_huffman_stream(sym, 1024)
+    assert struct.unpack_from("<Q", ref, 16)[0] == 55000
+    enc = torch.from_numpy(np.frombuffer(ref, dtype=np.uint8).copy()).cuda()
+    t = torch.from_numpy(sym.astype(np.uint16).view(np.int16)).cuda()
+    forced_decoder(0, 9)
+    back = mgc.huffman_decode(enc, n)
+    ring_auto, waves_auto = mgc.decoder_info()
+    assert waves_auto == 9 and ring_auto > 1
+    assert bool((back == t).all())
+    forced_decoder(1, 9)
+    with pytest.raises(mgc.MgcError) as e:
+        mgc.huffman_decode(enc, n)
+    assert e.value.name == "EINVAL"
+    for ring in (1, 2, 3):
+        for waves in (1, 2, 4, 9):
+            forced_decoder(ring, waves)
+            try:
+                back = mgc.huffman_decode(enc, n)
+            except mgc.MgcError as err:
+                assert err.name == "EINVAL"
+                continue
+            assert mgc.decoder_info() == (ring, waves)
+            assert bool((back == t).all()), (ring, waves)

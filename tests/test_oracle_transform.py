@@ -7,7 +7,10 @@
 * closed forms: multilinear data has zero coefficients; the nodal x^2 projects
   to x^2 - h^2/2; the sawtooth projects to 1/2 per axis;
 * the adjoint is the transpose: dot-product test and dense R^T on small grids;
-* hierarchy sizes worked out by hand from the coarsening rule.
+* hierarchy sizes worked out by hand from the coarsening rule;
+* the one-by-one finest-level coefficient helper (used where the full
+  decomposition would be too large) equals the finest level of decompose,
+  positions included.
 """
 
 import numpy as np
@@ -184,3 +187,21 @@ def test_recompose_is_identity_plus_projection_complements():
     xc = np.array([0.0, 4.0, 8.0])      # the level-1 nodes of a 9-node axis
     M1 = _gram_by_quadrature(xc, x, x)
     assert np.max(np.abs(M1 @ g @ M1.T)) < 1e-13
+
+
+# ------------------------------------------------- finest_coefficients_at
+@pytest.mark.parametrize("shape", [(9, 5, 4), (6, 7, 5), (13, 10, 6), (17,), (12, 9), (1, 7, 1),
+                                   (2, 6, 3)])
+def test_finest_coefficients_at_equals_decompose(shape):
+    """Every index of the grid: coarse nodes are skipped, new nodes give the
+    coefficient and stream position that decompose writes."""
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal(shape)
+    h = Hierarchy(shape)
+    full = oracle.decompose(u, h)
+    a, b = level_slices(h)[h.L]
+    idx = np.arange(u.size)
+    pos, c = oracle.transform.finest_coefficients_at(u, h, idx)
+    assert len(pos) == b - a                      # one per new node
+    assert np.array_equal(np.sort(pos), np.arange(a, b))
+    assert np.max(np.abs(c - full[pos])) <= 1e-14 * max(1.0, float(np.max(np.abs(u))))
