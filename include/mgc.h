@@ -69,16 +69,31 @@ int mgc_version(void);
  * mgc_compress_query: workspace and worst-case output bytes for an array of
  *   `shape` (ndim entries) and dtype, with room for `outlier_cap` escaped
  *   values (0 = default, max(65536, N/16)).
- * mgc_compress (BLOCKING): compresses d_in into d_out and stores the stream
- *   length in *h_out_size.  error_bound > 0 is relative (to max - min for
- *   L-inf, to ||u||_2 for L2) when mode == MGC_REL, absolute otherwise; the
- *   reconstruction error in that norm is at most the bound.  out_cap and
- *   ws_bytes must be at least the queried sizes for the same outlier_cap
- *   (MGC_ENOSPC otherwise).  If more values escape the dictionary than
- *   outlier_cap, MGC_ENOSPC is returned and *h_out_size holds the number of
- *   escaped values needed; calling again with that capacity succeeds.
- *   Errors: MGC_EINVAL (shape, dtype, bound, NaN/Inf in the data),
- *   MGC_ERANGE, MGC_ENOSPC, MGC_EDEVICE.
+ * mgc_compress (asynchronous on `stream`): compresses d_in into d_out.
+ *   error_bound > 0 is relative (to max - min for L-inf, to ||u||_2 for L2)
+ *   when mode == MGC_REL, absolute otherwise; the reconstruction error in
+ *   that norm is at most the bound.  out_cap and ws_bytes must be at least
+ *   the queried sizes for the same outlier_cap (MGC_ENOSPC otherwise).  The
+ *   whole compression, including turning the relative bound into per-level
+ *   bins, runs on the device with no host round trip, so the call can be
+ *   captured into a HIP graph.  Its outcome lands in two device words,
+ *   d_result[0] = an mgc_status and d_result[1] = the stream length in
+ *   bytes, when the stream has been written:
+ *     MGC_OK       the stream is complete (constant and empty arrays get a
+ *                  136-byte stream);
+ *     MGC_EINVAL   the data holds NaN or Inf (d_result[1] = 0);
+ *     MGC_ERANGE   the bound is below the resolution of the data or the
+ *                  output type, or a quantised value reached 2^62;
+ *     MGC_ENOSPC   more values escaped the dictionary than outlier_cap;
+ *                  d_result[1] = the escaped values needed (call again with
+ *                  that capacity);
+ *     MGC_EDEVICE  a device-side consistency check failed.
+ *   Argument errors are returned directly: MGC_EINVAL (shape, dtype, bound,
+ *   null pointers), MGC_EUNSUPPORTED, MGC_ENOSPC (buffers), MGC_EDEVICE.
+ * mgc_compress_blocking: the same compression, BLOCKING: it waits for the
+ *   stream and returns the device outcome as its status (with the messages
+ *   above) and the stream length, or the escaped values needed after
+ *   MGC_ENOSPC, in *h_out_size.
  *
  * Stream layout (little-endian): a 128-byte header, the per-level bins
  * q_0..q_L (f64), then, unless the array is constant or empty, the codebook
@@ -93,8 +108,13 @@ mgc_status mgc_compress_query(int ndim, const uint64_t* shape, mgc_dtype dtype,
 mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
                         mgc_dtype dtype, double error_bound, mgc_norm norm,
                         mgc_mode mode, uint64_t outlier_cap, void* d_out,
-                        size_t out_cap, void* d_ws, size_t ws_bytes, void* stream,
-                        uint64_t* h_out_size);
+                        size_t out_cap, void* d_ws, size_t ws_bytes, uint64_t* d_result,
+                        void* stream);
+mgc_status mgc_compress_blocking(mgc_ctx ctx, const void* d_in, int ndim,
+                                 const uint64_t* shape, mgc_dtype dtype, double error_bound,
+                                 mgc_norm norm, mgc_mode mode, uint64_t outlier_cap,
+                                 void* d_out, size_t out_cap, void* d_ws, size_t ws_bytes,
+                                 void* stream, uint64_t* h_out_size);
 
 /* ------------------------------------------------------------------------
  * Decompression (inverse of the above).

@@ -21,7 +21,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["MgcError", "library_path", "compress", "decompress", "decompose", "recompose",
+__all__ = ["MgcError", "library_path", "compress", "compress_async", "decompress", "decompose", "recompose",
            "recompose_adjoint", "recompose_levels", "Recompose", "huffman_encode",
            "huffman_decode", "header_info", "profile_enable", "profile_reset", "profile_read",
            "compress_query", "transform_query", "batch_query", "Batch", "compress_batched",
@@ -70,7 +70,11 @@ def _load():
             "mgc_compress_query": [ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_uint64, c_szp, c_szp],
             "mgc_compress": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_double,
                              ctypes.c_int, ctypes.c_int, ctypes.c_uint64, vp, ctypes.c_size_t,
-                             vp, ctypes.c_size_t, vp, c_u64p],
+                             vp, ctypes.c_size_t, vp, vp],
+            "mgc_compress_blocking": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_uint64, vp, ctypes.c_size_t, vp, ctypes.c_size_t,
+                                      vp, c_u64p],
             "mgc_header_info": [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), c_u64p,
                                 ctypes.POINTER(ctypes.c_int), c_u64p, c_szp],
             "mgc_decompress": [vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp],
@@ -188,6 +192,44 @@ def compress_query(shape, dtype, outlier_cap: int = 0):
 _query_cache = {}
 
 
+_DEVICE_MESSAGES = {1: "input holds NaN or Inf",
+                    3: "more escaped values than the outlier capacity",
+                    5: "device-side consistency check failed",
+                    6: "error bound below the resolution of the data or the output type"}
+
+
+def compress_async(x, error_bound: float, norm: str = "linf", mode: str = "rel",
+                   outlier_cap: int = 0, workspace=None, out=None, result=None):
+    """Enqueue a compression on the current stream without waiting for it.
+
+    ``workspace`` and ``out`` are uint8 GPU tensors of at least the queried
+    sizes (compress_query) and ``result`` an int64 GPU tensor of 2 entries;
+    when the stream work is done, result[0] holds the status (0 = OK, else an
+    MgcError code) and result[1] the stream length in bytes (or, for status
+    3, the escaped values needed).  No host synchronisation takes place, so
+    the call can be captured into a CUDA/HIP graph (after one call outside
+    the capture has built the shape's plan).
+    """
+    _require_gpu(x, "input")
+    if not x.is_contiguous():
+        raise ValueError("input must be contiguous")
+    dev = x.device.index if x.device.index is not None else _torch().cuda.current_device()
+    shape = tuple(x.shape)
+    ws_n, out_n = compress_query(shape, x.dtype, outlier_cap)
+    torch = _torch()
+    if workspace is None or out is None or result is None:
+        raise ValueError("workspace, out and result tensors are required")
+    if workspace.numel() < ws_n or out.numel() < out_n or result.numel() < 2 \
+            or result.dtype != torch.int64:
+        raise ValueError("buffers smaller than the queried sizes")
+    _check(_load().mgc_compress(_ctx(dev), ctypes.c_void_p(x.data_ptr()), len(shape),
+                                _shape_arg(shape), _dtype_code(x.dtype), float(error_bound),
+                                _NORM[norm], _MODE[mode], outlier_cap,
+                                ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                ctypes.c_void_p(result.data_ptr()), _stream_ptr(dev)))
+
+
 def compress(x, error_bound: float, norm: str = "linf", mode: str = "rel",
              outlier_cap: int = 0, workspace=None, out=None):
     """Compress a 1-3D float32/float64 GPU tensor; returns a uint8 GPU tensor.
@@ -195,30 +237,27 @@ def compress(x, error_bound: float, norm: str = "linf", mode: str = "rel",
     The reconstruction error is at most ``error_bound`` in the chosen norm
     (relative to max-min for L-inf or to ||x||_2 for L2 when mode="rel").
     ``workspace``/``out`` may be preallocated uint8 tensors of the queried
-    sizes; the returned tensor is a view into ``out``.
+    sizes; the returned tensor is a view into ``out``.  Waits for the
+    stream length (one read of two device words).
     """
     _require_gpu(x, "input")
     x = x.contiguous()
-    dev = x.device.index if x.device.index is not None else _torch().cuda.current_device()
-    lib = _load()
-    ctx = _ctx(dev)
+    torch = _torch()
     shape = tuple(x.shape)
+    result = torch.empty(2, dtype=torch.int64, device=x.device)
     for _ in range(2):
         ws_n, out_n = compress_query(shape, x.dtype, outlier_cap)
         ws = workspace if workspace is not None and workspace.numel() >= ws_n else _empty(ws_n, x.device)
         ob = out if out is not None and out.numel() >= out_n else _empty(out_n, x.device)
-        size = ctypes.c_uint64()
-        st = lib.mgc_compress(ctx, ctypes.c_void_p(x.data_ptr()), len(shape), _shape_arg(shape),
-                              _dtype_code(x.dtype), float(error_bound), _NORM[norm], _MODE[mode],
-                              outlier_cap, ctypes.c_void_p(ob.data_ptr()), ob.numel(),
-                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(dev),
-                              ctypes.byref(size))
-        if st == 3 and size.value > outlier_cap and size.value > 0:
-            outlier_cap = int(size.value)   # more escaped values than room: retry once
+        compress_async(x, error_bound, norm, mode, outlier_cap, ws, ob, result)
+        st, size = (int(v) for v in result.cpu().tolist())
+        if st == 3 and size > outlier_cap:
+            outlier_cap = size   # more escaped values than room: retry once
             continue
-        _check(st)
-        return ob[: size.value]
-    _check(st)
+        if st != 0:
+            raise MgcError(st, _DEVICE_MESSAGES.get(st, "device status %d" % st))
+        return ob[:size]
+    raise MgcError(st, _DEVICE_MESSAGES.get(st, "device status %d" % st))
 
 
 BATCH_EAGER = 1

@@ -1,12 +1,14 @@
 // C-ABI entry points and host orchestration of the kernels.
 //
 // compress runs Algorithm 1 of the paper end to end on one stream: a range
-// pre-pass (min, max, sum of squares) for the relative bound, then for each
-// level from the finest the fused lerp/quantise/mass_trans kernel and the
-// tridiagonal sweeps, the coarsest block, and the Huffman stage of Algorithm
-// 2.  The host reads back 32 bytes after the pre-pass (to turn the relative
-// bound into bins and reject NaN/Inf or constant data) and 24 bytes at the
-// end (status, escaped-value count and stream length).
+// pre-pass (min, max, sum of squares) whose last block turns the relative
+// bound into the per-level bins on the device, then for each level from the
+// finest the fused lerp/quantise/mass_trans kernel and the tridiagonal
+// sweeps, the coarsest block, and the Huffman stage of Algorithm 2, ending
+// with a header kernel that writes the stream length and status to device
+// memory.  Nothing is read back to the host, so the call is asynchronous and
+// can be captured into a graph; inputs the range pass flags (constant,
+// NaN/Inf, no budget) close the gate of every later kernel.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -193,17 +195,6 @@ void sync_read(mgc_ctx ctx, void* host, const void* dev, size_t n, hipStream_t s
   MGC_HIP(hipStreamSynchronize(s));
 }
 
-// header of a constant or empty array (no sections)
-uint64_t write_trivial_stream(mgc_ctx ctx, Header h, void* d_out, hipStream_t s) {
-  h.L = 0;
-  h.total = kHeaderBytes + 8;
-  std::memcpy(ctx->pinned, &h, kHeaderBytes);
-  std::memset(ctx->pinned + kHeaderBytes, 0, 8);
-  MGC_HIP(hipMemcpyAsync(d_out, ctx->pinned, kHeaderBytes + 8, hipMemcpyHostToDevice, s));
-  MGC_HIP(hipStreamSynchronize(s));
-  return h.total;
-}
-
 // The solves on one level's coarse grid x: axis 2, then 1, then 0 (the
 // active ones), sub - x formed after the last.  One launch when the grid fits
 // in LDS, two (x-y planes, then axis 0) when its planes do, else one per
@@ -242,10 +233,12 @@ void solve_coarse(mgc_ctx ctx, const LevelGeom& g, double* x, const double* sub,
   }
 }
 
+// rdev: device reciprocal bins r_0..r_L (quantising runs, sym != nullptr);
+// gate: the compression's status word (null: ungated).
 void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_f32,
                           double* gA, double* gB, uint16_t* sym, double* raw,
-                          const std::vector<double>& r, const OutlierBuf& ob, unsigned* status,
-                          hipStream_t s) {
+                          const double* rdev, const OutlierBuf& ob, unsigned* status,
+                          const unsigned* gate, hipStream_t s) {
   const void* Gcur = d_in;
   bool cur_f32 = in_f32;
   for (int l = p.L; l >= 1; --l) {
@@ -253,15 +246,16 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
     const LevelGeom g = p.geom(l);
     {
       StageScope sc(&ctx->prof, l == p.L ? "dec_level[finest]" : "dec_level", s);
-      launch_dec_level(Gcur, cur_f32, g, Gnext, sym, raw, sym ? r[l] : 0.0, ob, status, s,
-                       tuned(ctx, cur_f32 ? MGC_TUNE_DEC_F32 : MGC_TUNE_DEC_F64));
+      launch_dec_level(Gcur, cur_f32, g, Gnext, sym, raw, sym ? rdev + l : nullptr, ob, status,
+                       gate, s, tuned(ctx, cur_f32 ? MGC_TUNE_DEC_F32 : MGC_TUNE_DEC_F64));
     }
     solve_coarse(ctx, g, Gnext, nullptr, l == p.L, true, s);
     Gcur = Gnext;
     cur_f32 = false;
   }
   StageScope sc(&ctx->prof, "level0", s);
-  launch_level0(Gcur, cur_f32, p.points(0), sym, raw, sym ? r[0] : 0.0, ob, status, s);
+  launch_level0(Gcur, cur_f32, p.points(0), sym, raw, sym ? rdev : nullptr, ob, status, gate,
+                s);
 }
 
 // levels (optional) receives G_0 .. G_{L-1}, level after level.
@@ -360,112 +354,144 @@ mgc_status mgc_compress_query(int ndim, const uint64_t* shape, mgc_dtype dtype,
   });
 }
 
+namespace {
+// Enqueues a whole compression on s (no host synchronisation).  res: two
+// device words receiving the mgc_status and the stream length (or, with
+// MGC_ENOSPC, the escaped values needed).  ws must hold carve_compress's
+// layout for the outlier capacity cap.
+void compress_enqueue(mgc_ctx ctx, const Plan& p, const void* d_in, int ndim,
+                      const uint64_t* shape, mgc_dtype dtype, double error_bound,
+                      mgc_norm norm, mgc_mode mode, uint64_t cap, void* d_out, void* d_ws,
+                      unsigned long long* res, hipStream_t s) {
+  Carver c(d_ws);
+  CompressWs w = carve_compress(c, p, cap);
+  uint8_t* out = static_cast<uint8_t*>(d_out);
+  const Header h = make_header(p, ndim, shape, dtype, error_bound, norm, mode);
+  if (p.N == 0) {
+    launch_header(out, h, nullptr, nullptr, nullptr, true, res, s);
+    return;
+  }
+  {
+    void* const zp[4] = {w.status, w.n_out, w.lay, w.hist};
+    const size_t zb[4] = {4 * sizeof(unsigned), sizeof(unsigned long long), sizeof(Layout),
+                          kDict * sizeof(unsigned)};
+    launch_zero_words(zp, zb, 4, s);
+  }
+  {
+    StageScope sc(&ctx->prof, "range", s);
+    const BudgetIn bi{(int)dtype, (int)norm, (int)mode, p.L, error_bound, p.N,
+                      p.d_K[norm == MGC_LINF ? 0 : 1]};
+    launch_range(d_in, dtype, p.N, w.part, bi, w.bud, w.status, s);
+  }
+  const unsigned* gate = w.status;
+  OutlierBuf ob{w.opos, w.oval, w.n_out, cap};
+  run_levels_decompose(ctx, p, d_in, dtype == MGC_F32, w.gA, w.gB, w.sym, nullptr,
+                       w.bud + bud_r(p.L, 0), ob, w.status, gate, s);
+  const uint64_t cb_off = kHeaderBytes + 8 * (p.L + 1);
+  const CodebookScratch sc = carve_codebook_scratch(w.cbs);
+  {
+    StageScope st(&ctx->prof, "histogram", s);
+    launch_histogram(w.sym, p.N, w.hist, s, gate);
+  }
+  {
+    StageScope st(&ctx->prof, "codebook", s);
+    launch_codebook(w.hist, sc, w.code, w.clen, out, cb_off, w.lay, s, gate);
+  }
+  {
+    StageScope st(&ctx->prof, "chunk_words", s);
+    launch_chunk_words(w.sym, p.N, kChunk, w.clen, w.cw, w.lay, s, gate);
+  }
+  {
+    StageScope st(&ctx->prof, "layout_scan", s);
+    launch_layout_scan(w.cw, (int64_t)h.n_chunks, out, cb_off, w.lay, w.n_out, cap, false, s,
+                       gate);
+  }
+  {
+    StageScope st(&ctx->prof, "outlier_sort", s);
+    launch_outlier_sort(ob, w.okA, w.ovA, w.okB, w.ovB, key_bits(p.N), out, w.lay, s, gate);
+  }
+  {
+    StageScope st(&ctx->prof, "encode", s);
+    launch_encode(w.sym, p.N, kChunk, w.code, w.clen, sc.pk, out, w.lay, s, gate);
+  }
+  {
+    StageScope st(&ctx->prof, "header", s);
+    launch_header(out, h, w.bud, w.lay, w.status, false, res, s);
+  }
+  MGC_HIP(hipGetLastError());
+}
+
+// Argument checks shared by the compression entry points; returns the plan.
+const Plan& compress_checks(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                            mgc_dtype dtype, double error_bound, mgc_norm norm, mgc_mode mode,
+                            uint64_t* cap, const void* d_out, size_t out_cap, const void* d_ws,
+                            size_t ws_bytes) {
+  check_ctx(ctx);
+  if (dtype != MGC_F32 && dtype != MGC_F64) fail(MGC_EINVAL, "dtype must be f32 or f64");
+  if (norm != MGC_LINF && norm != MGC_L2) fail(MGC_EINVAL, "norm must be L-inf or L2");
+  if (mode != MGC_REL && mode != MGC_ABS) fail(MGC_EINVAL, "mode must be rel or abs");
+  if (!(error_bound > 0.0) || !std::isfinite(error_bound))
+    fail(MGC_EINVAL, "error bound must be positive and finite");
+  const Plan& p = get_plan(ctx, ndim, shape);
+  *cap = *cap ? *cap : default_outlier_cap(p.N);
+  Carver meas(nullptr);
+  carve_compress(meas, p, *cap);
+  if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
+  if (out_cap < max_stream_bytes(p, *cap)) fail(MGC_ENOSPC, "output capacity too small");
+  if (!d_out) fail(MGC_EINVAL, "null output pointer");
+  if (p.N > 0 && (!d_in || !d_ws)) fail(MGC_EINVAL, "null device pointer");
+  return p;
+}
+}  // namespace
+
 mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
                         mgc_dtype dtype, double error_bound, mgc_norm norm, mgc_mode mode,
                         uint64_t outlier_cap, void* d_out, size_t out_cap, void* d_ws,
-                        size_t ws_bytes, void* stream, uint64_t* h_out_size) {
+                        size_t ws_bytes, uint64_t* d_result, void* stream) {
   return guard([&] {
-    check_ctx(ctx);
-    if (dtype != MGC_F32 && dtype != MGC_F64) fail(MGC_EINVAL, "dtype must be f32 or f64");
-    if (norm != MGC_LINF && norm != MGC_L2) fail(MGC_EINVAL, "norm must be L-inf or L2");
-    if (mode != MGC_REL && mode != MGC_ABS) fail(MGC_EINVAL, "mode must be rel or abs");
-    if (!(error_bound > 0.0) || !std::isfinite(error_bound))
-      fail(MGC_EINVAL, "error bound must be positive and finite");
-    if (!h_out_size) fail(MGC_EINVAL, "null size output");
-    const Plan& p = get_plan(ctx, ndim, shape);
-    const uint64_t cap = outlier_cap ? outlier_cap : default_outlier_cap(p.N);
-    Carver meas(nullptr);
-    carve_compress(meas, p, cap);
-    if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
-    if (out_cap < max_stream_bytes(p, cap)) fail(MGC_ENOSPC, "output capacity too small");
-    if (p.N > 0 && (!d_in || !d_out || !d_ws)) fail(MGC_EINVAL, "null device pointer");
-    hipStream_t s = as_stream(stream);
-    Carver c(d_ws);
-    CompressWs w = carve_compress(c, p, cap);
+    uint64_t cap = outlier_cap;
+    const Plan& p = compress_checks(ctx, d_in, ndim, shape, dtype, error_bound, norm, mode, &cap,
+                                    d_out, out_cap, d_ws, ws_bytes);
+    if (!d_result) fail(MGC_EINVAL, "null result pointer");
+    compress_enqueue(ctx, p, d_in, ndim, shape, dtype, error_bound, norm, mode, cap, d_out, d_ws,
+                     reinterpret_cast<unsigned long long*>(d_result), as_stream(stream));
+  });
+}
 
-    Header h = make_header(p, ndim, shape, dtype, error_bound, norm, mode);
-    if (p.N == 0) {
-      *h_out_size = write_trivial_stream(ctx, h, d_out, s);
-      return;
+mgc_status mgc_compress_blocking(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                                 mgc_dtype dtype, double error_bound, mgc_norm norm,
+                                 mgc_mode mode, uint64_t outlier_cap, void* d_out,
+                                 size_t out_cap, void* d_ws, size_t ws_bytes, void* stream,
+                                 uint64_t* h_out_size) {
+  return guard([&] {
+    if (!h_out_size) fail(MGC_EINVAL, "null size output");
+    uint64_t cap = outlier_cap;
+    const Plan& p = compress_checks(ctx, d_in, ndim, shape, dtype, error_bound, norm, mode, &cap,
+                                    d_out, out_cap, d_ws, ws_bytes);
+    hipStream_t s = as_stream(stream);
+    unsigned long long* res = nullptr;
+    if (p.N > 0) {
+      Carver c(d_ws);
+      res = carve_compress(c, p, cap).info;
+    } else {
+      res = reinterpret_cast<unsigned long long*>(ctx->pinned_dev + 2048);
     }
-    {
-      void* const zp[4] = {w.status, w.n_out, w.lay, w.hist};
-      const size_t zb[4] = {4 * sizeof(unsigned), sizeof(unsigned long long), sizeof(Layout),
-                            kDict * sizeof(unsigned)};
-      launch_zero_words(zp, zb, 4, s);
+    compress_enqueue(ctx, p, d_in, ndim, shape, dtype, error_bound, norm, mode, cap, d_out, d_ws,
+                     res, s);
+    unsigned long long r[2];
+    sync_read(ctx, ctx->pinned, res, sizeof(r), s);
+    std::memcpy(r, ctx->pinned, sizeof(r));
+    *h_out_size = r[1];
+    switch ((int)r[0]) {
+      case MGC_OK: return;
+      case MGC_ENOSPC:
+        fail(MGC_ENOSPC, "more escaped values than the outlier capacity; retry with capacity " +
+                             std::to_string(r[1]));
+      case MGC_EINVAL: fail(MGC_EINVAL, "input holds NaN or Inf");
+      case MGC_ERANGE:
+        fail(MGC_ERANGE, "error bound below the resolution of the data or the output type");
+      default: fail(MGC_EDEVICE, "device status " + std::to_string(r[0]));
     }
-    {
-      StageScope sc(&ctx->prof, "range", s);
-      const BudgetIn bi{(int)dtype, (int)norm, (int)mode, p.L, error_bound, p.N,
-                        p.d_K[norm == MGC_LINF ? 0 : 1]};
-      launch_range(d_in, dtype, p.N, w.part, bi, w.bud, w.status, s);
-    }
-    const int nbud = 6 + 2 * (p.L + 1);
-    std::vector<double> bud(nbud);
-    sync_read(ctx, ctx->pinned, w.bud, nbud * sizeof(double), s);
-    std::memcpy(bud.data(), ctx->pinned, nbud * sizeof(double));
-    if (bud[3] != 0.0) fail(MGC_EINVAL, "input holds NaN or Inf");
-    if (bud[0] == bud[1]) {
-      h.flags = FLAG_CONSTANT;
-      h.const_value = bud[0];
-      h.n_chunks = 0;
-      *h_out_size = write_trivial_stream(ctx, h, d_out, s);
-      return;
-    }
-    if (!(bud[5] > 0.0)) fail(MGC_ERANGE, "error bound below the resolution of the output type");
-    h.tau = bud[4];
-    h.tau_eff = bud[5];
-    std::vector<double> q(p.L + 1), r(p.L + 1);
-    for (int l = 0; l <= p.L; ++l) {
-      q[l] = bud[bud_q(l)];
-      r[l] = bud[bud_r(p.L, l)];
-    }
-    OutlierBuf ob{w.opos, w.oval, w.n_out, cap};
-    run_levels_decompose(ctx, p, d_in, dtype == MGC_F32, w.gA, w.gB, w.sym, nullptr, r, ob,
-                         w.status, s);
-    uint8_t* out = static_cast<uint8_t*>(d_out);
-    const uint64_t cb_off = kHeaderBytes + 8 * (p.L + 1);
-    const CodebookScratch sc = carve_codebook_scratch(w.cbs);
-    {
-      StageScope st(&ctx->prof, "histogram", s);
-      launch_histogram(w.sym, p.N, w.hist, s);
-    }
-    {
-      StageScope st(&ctx->prof, "codebook", s);
-      launch_codebook(w.hist, sc, w.code, w.clen, out, cb_off, w.lay, s);
-    }
-    {
-      StageScope st(&ctx->prof, "chunk_words", s);
-      launch_chunk_words(w.sym, p.N, kChunk, w.clen, w.cw, w.lay, s);
-    }
-    {
-      StageScope st(&ctx->prof, "layout_scan", s);
-      launch_layout_scan(w.cw, (int64_t)h.n_chunks, out, cb_off, w.lay, w.n_out, cap, false, s);
-    }
-    {
-      StageScope st(&ctx->prof, "outlier_sort", s);
-      launch_outlier_sort(ob, w.okA, w.ovA, w.okB, w.ovB, key_bits(p.N), out, w.lay, s);
-    }
-    {
-      StageScope st(&ctx->prof, "encode", s);
-      launch_encode(w.sym, p.N, kChunk, w.code, w.clen, sc.pk, out, w.lay, s);
-    }
-    {
-      StageScope st(&ctx->prof, "header", s);
-      launch_header(out, h, q.data(), p.L + 1, w.lay, w.status, w.info, s);
-    }
-    MGC_HIP(hipGetLastError());
-    unsigned long long info[3];
-    sync_read(ctx, ctx->pinned, w.info, sizeof(info), s);
-    std::memcpy(info, ctx->pinned, sizeof(info));
-    if (info[0] & ST_OVERFLOW) {
-      *h_out_size = info[1];
-      fail(MGC_ENOSPC, "more escaped values than the outlier capacity; retry with capacity " +
-                           std::to_string(info[1]));
-    }
-    if (info[0] & ST_RANGE) fail(MGC_ERANGE, "quantised value out of range (bound too small)");
-    if (info[0]) fail(MGC_EDEVICE, "device status " + std::to_string(info[0]));
-    *h_out_size = info[2];
   });
 }
 
@@ -580,8 +606,8 @@ mgc_status mgc_decompose(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t
     if (ws_bytes < c.off) fail(MGC_ENOSPC, "workspace too small");
     hipStream_t s = as_stream(stream);
     OutlierBuf ob{nullptr, nullptr, nullptr, 0};
-    run_levels_decompose(ctx, p, d_in, dtype == MGC_F32, gA, gB, nullptr, d_coeffs,
-                         std::vector<double>(p.L + 1, 0.0), ob, status, s);
+    run_levels_decompose(ctx, p, d_in, dtype == MGC_F32, gA, gB, nullptr, d_coeffs, nullptr, ob,
+                         status, nullptr, s);
     MGC_HIP(hipGetLastError());
   });
 }
@@ -671,7 +697,8 @@ mgc_status mgc_recompose_adjoint(mgc_ctx ctx, const double* d_grad_u, int ndim,
       g = Gc;
     }
     OutlierBuf ob{nullptr, nullptr, nullptr, 0};
-    launch_level0(g, false, p.points(0), nullptr, d_grad_coeffs, 0.0, ob, nullptr, s);
+    launch_level0(g, false, p.points(0), nullptr, d_grad_coeffs, nullptr, ob, nullptr, nullptr,
+                  s);
     MGC_HIP(hipGetLastError());
   });
 }

@@ -35,6 +35,13 @@ enum : uint32_t {
   ST_SKIP = ST_NONFINITE | ST_CONST | ST_BUDGET | ST_EMPTY,
 };
 
+// A compression's later kernels take its status word as a gate: once the
+// range pass has flagged the input (constant, empty, non-finite, or a budget
+// below the output precision) they return at once.  A null gate is open.
+__device__ __forceinline__ bool gate_closed(const unsigned* gate) {
+  return gate != nullptr && (*gate & ST_SKIP) != 0u;
+}
+
 // Error-budget block of a compression (device, doubles): [0..3] min, max, sum
 // of squares, non-finite flag; [4] tau; [5] tau'; [6 .. 6+L] bins q_l;
 // [7+L .. 7+2L] their reciprocals.

@@ -158,7 +158,9 @@ __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ sym,
 }
 
 __global__ __launch_bounds__(1024) void k_histogram(const uint16_t* __restrict__ sym, int64_t n,
-                                                     unsigned* __restrict__ hist) {
+                                                     unsigned* __restrict__ hist,
+                                                     const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   histogram_body(sym, n, hist, blockIdx.x, gridDim.x);
 }
 
@@ -878,7 +880,9 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
                                                     CodebookScratch s, uint32_t* __restrict__ code,
                                                     uint8_t* __restrict__ clen,
                                                     uint8_t* __restrict__ cb_out,
-                                                    Layout* __restrict__ lay) {
+                                                    Layout* __restrict__ lay,
+                                                    const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   codebook_body<true>(hist, s, code, clen, cb_out, lay);
 }
 
@@ -897,7 +901,9 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
 // complete table.  Passes beyond the largest frequency's width return at
 // once; pass p writes (keyB, valB) for even p and (keyA, valA) for odd p.
 __global__ __launch_bounds__(256) void k_cbs_count(const unsigned* __restrict__ hist,
-                                                   CodebookScratch s) {
+                                                   CodebookScratch s,
+                                                   const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   __shared__ unsigned cnt[256];
   __shared__ unsigned wmax[4];
   const int t = blockIdx.x, tid = threadIdx.x;
@@ -922,7 +928,9 @@ __global__ __launch_bounds__(256) void k_cbs_count(const unsigned* __restrict__ 
 
 template <int P>
 __global__ __launch_bounds__(256) void k_cbs_pass(const unsigned* __restrict__ hist,
-                                                  CodebookScratch s) {
+                                                  CodebookScratch s,
+                                                  const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   __shared__ unsigned wcnt[4][256];
   __shared__ unsigned sm32[16];
   __shared__ unsigned nzw[4];
@@ -1092,7 +1100,9 @@ __device__ __forceinline__ void chunk_words_body(const uint16_t* __restrict__ sy
 __global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict__ sym, int64_t N,
                                                       int C, const uint8_t* __restrict__ clen,
                                                       uint32_t* __restrict__ cw,
-                                                      const Layout* __restrict__ lay) {
+                                                      const Layout* __restrict__ lay,
+                                                      const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   chunk_words_body(sym, N, C, clen, cw, lay, blockIdx.x, gridDim.x);
 }
 
@@ -1207,7 +1217,9 @@ __global__ __launch_bounds__(1024) void k_layout_scan(const uint32_t* __restrict
                                                        int64_t n_chunks, uint8_t* __restrict__ out,
                                                        uint64_t cb_off, Layout* __restrict__ lay,
                                                        const unsigned long long* n_out,
-                                                       uint64_t out_cap_n, int huff_only) {
+                                                       uint64_t out_cap_n, int huff_only,
+                                                       const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   layout_scan_body(cw, n_chunks, out, cb_off, lay, n_out, out_cap_n, huff_only);
 }
 
@@ -1232,7 +1244,9 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_sums(const uint32_t* __restrict__ cw,
                                                             int64_t n_chunks, int64_t R,
-                                                            unsigned long long* __restrict__ sums) {
+                                                            unsigned long long* __restrict__ sums,
+                                                            const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   __shared__ unsigned long long sm[kScanThreads / 64];
   const int64_t lo = (int64_t)blockIdx.x * R, hi = min<int64_t>(lo + R, n_chunks);
   unsigned long long acc = 0;
@@ -1251,7 +1265,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_offsets(
     const uint32_t* __restrict__ cw, int64_t n_chunks, int64_t R,
     const unsigned long long* __restrict__ sums, uint8_t* __restrict__ out, uint64_t cb_off,
     Layout* __restrict__ lay, const unsigned long long* n_out, uint64_t out_cap_n,
-    int huff_only) {
+    int huff_only, const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   __shared__ unsigned long long sm[kScanThreads / 64];
   __shared__ unsigned wsum[kScanThreads / 64][4];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1376,7 +1391,9 @@ __global__ __launch_bounds__(1024) void k_outlier_sort(const OutlierBuf ob, uint
                                                         uint32_t* valA, uint32_t* keyB,
                                                         uint32_t* valB, int key_bits,
                                                         uint8_t* __restrict__ out,
-                                                        const Layout* __restrict__ lay) {
+                                                        const Layout* __restrict__ lay,
+                                                        const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   outlier_sort_body(ob, keyA, valA, keyB, valB, key_bits, out, lay);
 }
 
@@ -1504,7 +1521,9 @@ __global__ __launch_bounds__(256) void k_encode(const uint16_t* __restrict__ sym
                                                  const uint8_t* __restrict__ clen,
                                                  const uint32_t* __restrict__ pk,
                                                  uint8_t* __restrict__ out,
-                                                 const Layout* __restrict__ lay) {
+                                                 const Layout* __restrict__ lay,
+                                                 const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   extern __shared__ uint32_t wbuf[];  // 4 * C words
   encode_body(sym, N, C, code, clen, pk, out, lay, blockIdx.x, wbuf);
 }
@@ -1535,7 +1554,8 @@ struct EncSyms {
 
 __global__ __launch_bounds__(64 * kEncWaves) void k_encode_win(
     const uint16_t* __restrict__ sym, int64_t N, const uint32_t* __restrict__ pk,
-    uint8_t* __restrict__ out, const Layout* __restrict__ lay) {
+    uint8_t* __restrict__ out, const Layout* __restrict__ lay, const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
   extern __shared__ __align__(16) uint32_t esm[];
   __shared__ uint32_t fst[kMaxCodeLen + 1];  // first code of each length
   if (lay->status) return;
@@ -1668,19 +1688,49 @@ __global__ __launch_bounds__(64 * kEncWaves) void k_encode_win(
   }
 }
 
-struct QArgs {
-  double q[kMaxLevels + 1];
-};
-
-__global__ void k_header(uint8_t* __restrict__ out, Header h, const QArgs qa, int nq,
-                         const Layout* __restrict__ lay, const unsigned* status,
-                         unsigned long long* info) {
-  if (threadIdx.x != 0) return;
-  const unsigned st = lay->status | (status ? *status : 0u);
-  info[0] = st;
-  info[1] = lay->n_outliers;
-  info[2] = lay->end;
-  if (st) return;
+// Header, bins and result words of one compression (thread 0 of a block),
+// from the status bits st of the range pass and the quantiser and the
+// stream layout.  Constant and empty arrays get the 136-byte trivial stream
+// (header and one zero bin); a failed compression writes no stream and
+// reports MGC_EINVAL (non-finite input), MGC_ERANGE (no budget left, or a
+// quantised value out of range), MGC_ENOSPC with the escaped-value count it
+// needs, or MGC_EDEVICE.  Results: *size_out = stream bytes (or that count),
+// *status_out = the mgc_status.
+template <typename St>
+__device__ void header_body(Header h, uint8_t* __restrict__ out, const double* __restrict__ bud,
+                            int L, unsigned st, const Layout* __restrict__ lay,
+                            uint64_t* size_out, St* status_out) {
+  if (st & (ST_EMPTY | ST_CONST)) {
+    h.flags = (st & ST_EMPTY) ? FLAG_EMPTY : FLAG_CONSTANT;
+    if (!(st & ST_EMPTY)) h.const_value = bud[0];
+    h.L = 0;
+    h.n_chunks = 0;
+    h.total = kHeaderBytes + 8;
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(&h);
+    for (int i = 0; i < kHeaderBytes; ++i) out[i] = src[i];
+    for (int i = 0; i < 8; ++i) out[kHeaderBytes + i] = 0;
+    *size_out = h.total;
+    *status_out = MGC_OK;
+    return;
+  }
+  if (st & ST_NONFINITE) {
+    *size_out = 0;
+    *status_out = MGC_EINVAL;
+    return;
+  }
+  if (st & ST_BUDGET) {
+    *size_out = 0;
+    *status_out = MGC_ERANGE;
+    return;
+  }
+  const unsigned all = st | lay->status;
+  if (all) {
+    *size_out = (all & ST_OVERFLOW) ? lay->n_outliers : 0;
+    *status_out = (all & ST_OVERFLOW) ? MGC_ENOSPC : (all & ST_RANGE) ? MGC_ERANGE : MGC_EDEVICE;
+    return;
+  }
+  h.tau = bud[4];
+  h.tau_eff = bud[5];
   h.n_codes = lay->n_codes;
   h.n_outliers = lay->n_outliers;
   h.n_words = lay->n_words;
@@ -1688,10 +1738,24 @@ __global__ void k_header(uint8_t* __restrict__ out, Header h, const QArgs qa, in
   const uint8_t* src = reinterpret_cast<const uint8_t*>(&h);
   for (int i = 0; i < kHeaderBytes; ++i) out[i] = src[i];
   double* q = reinterpret_cast<double*>(out + kHeaderBytes);
-  for (int i = 0; i < nq; ++i) q[i] = qa.q[i];
+  for (int l = 0; l <= L; ++l) q[l] = bud[bud_q(l)];
   // zero the padding bytes after the codebook and after the words
   for (uint64_t i = lay->cb + 3 * lay->n_codes; i < lay->off; ++i) out[i] = 0;
   for (uint64_t i = lay->words + 4 * lay->n_words; i < lay->end; ++i) out[i] = 0;
+  *size_out = lay->end;
+  *status_out = MGC_OK;
+}
+
+// Plain compression: res[0] = mgc_status, res[1] = stream bytes (or the
+// escaped-value count needed).  `empty` marks an array without values (no
+// range pass ran).
+__global__ void k_header(uint8_t* __restrict__ out, Header h, const double* __restrict__ bud,
+                         const Layout* __restrict__ lay, const unsigned* __restrict__ status,
+                         int empty, unsigned long long* __restrict__ res) {
+  if (threadIdx.x != 0) return;
+  const unsigned st = empty ? (unsigned)ST_EMPTY : *status;
+  header_body(h, out, bud, (int)h.L, st, lay, reinterpret_cast<uint64_t*>(res + 1),
+              reinterpret_cast<uint64_t*>(res));
 }
 
 __global__ void k_huff_header(uint8_t* __restrict__ out, uint32_t C, uint64_t N, uint64_t n_chunks,
@@ -2182,58 +2246,11 @@ __global__ __launch_bounds__(256) void kb_encode(const Job* __restrict__ jobs,
               wbuf);
 }
 
-// Header, bins and result-table entries of one array (thread 0).  Constant
-// and empty arrays get the 136-byte trivial stream of the plain path.
+// Header, bins and result-table entries of one array (thread 0).
 __global__ void kb_header(const Job* __restrict__ jobs) {
   if (threadIdx.x != 0) return;
   const Job& J = jobs[blockIdx.x];
-  const unsigned st = *J.status;
-  Header h = J.hdr;
-  uint8_t* out = J.out;
-  if (st & (ST_EMPTY | ST_CONST)) {
-    h.flags = (st & ST_EMPTY) ? FLAG_EMPTY : FLAG_CONSTANT;
-    if (!(st & ST_EMPTY)) h.const_value = J.bud[0];
-    h.L = 0;
-    h.n_chunks = 0;
-    h.total = kHeaderBytes + 8;
-    const uint8_t* src = reinterpret_cast<const uint8_t*>(&h);
-    for (int i = 0; i < kHeaderBytes; ++i) out[i] = src[i];
-    for (int i = 0; i < 8; ++i) out[kHeaderBytes + i] = 0;
-    *J.size_out = h.total;
-    *J.status_out = MGC_OK;
-    return;
-  }
-  if (st & ST_NONFINITE) {
-    *J.size_out = 0;
-    *J.status_out = MGC_EINVAL;
-    return;
-  }
-  if (st & ST_BUDGET) {
-    *J.size_out = 0;
-    *J.status_out = MGC_ERANGE;
-    return;
-  }
-  const Layout* lay = J.lay;
-  const unsigned all = st | lay->status;
-  if (all) {
-    *J.size_out = (all & ST_OVERFLOW) ? lay->n_outliers : 0;
-    *J.status_out = (all & ST_OVERFLOW) ? MGC_ENOSPC : (all & ST_RANGE) ? MGC_ERANGE : MGC_EDEVICE;
-    return;
-  }
-  h.tau = J.bud[4];
-  h.tau_eff = J.bud[5];
-  h.n_codes = lay->n_codes;
-  h.n_outliers = lay->n_outliers;
-  h.n_words = lay->n_words;
-  h.total = lay->end;
-  const uint8_t* src = reinterpret_cast<const uint8_t*>(&h);
-  for (int i = 0; i < kHeaderBytes; ++i) out[i] = src[i];
-  double* q = reinterpret_cast<double*>(out + kHeaderBytes);
-  for (int l = 0; l <= J.L; ++l) q[l] = J.bud[bud_q(l)];
-  for (uint64_t i = lay->cb + 3 * lay->n_codes; i < lay->off; ++i) out[i] = 0;
-  for (uint64_t i = lay->words + 4 * lay->n_words; i < lay->end; ++i) out[i] = 0;
-  *J.size_out = lay->end;
-  *J.status_out = MGC_OK;
+  header_body(J.hdr, J.out, J.bud, J.L, *J.status, J.lay, J.size_out, J.status_out);
 }
 
 }  // namespace
@@ -2245,8 +2262,9 @@ uint32_t hist_blocks(int64_t n) {
   return (uint32_t)blocks;
 }
 
-void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s) {
-  hipLaunchKernelGGL(k_histogram, dim3(hist_blocks(n)), dim3(1024), 0, s, sym, n, hist);
+void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s,
+                      const unsigned* gate) {
+  hipLaunchKernelGGL(k_histogram, dim3(hist_blocks(n)), dim3(1024), 0, s, sym, n, hist, gate);
 }
 
 void launch_b_histogram(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s) {
@@ -2274,14 +2292,14 @@ void launch_b_header(const Job* jobs, int n, hipStream_t s) {
 
 void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
                      uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_cbs_count, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
-  hipLaunchKernelGGL(k_cbs_pass<0>, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
-  hipLaunchKernelGGL(k_cbs_pass<1>, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
-  hipLaunchKernelGGL(k_cbs_pass<2>, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
-  hipLaunchKernelGGL(k_cbs_pass<3>, dim3(kSortTiles), dim3(256), 0, s, hist, sc);
+                     hipStream_t s, const unsigned* gate) {
+  hipLaunchKernelGGL(k_cbs_count, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
+  hipLaunchKernelGGL(k_cbs_pass<0>, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
+  hipLaunchKernelGGL(k_cbs_pass<1>, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
+  hipLaunchKernelGGL(k_cbs_pass<2>, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
+  hipLaunchKernelGGL(k_cbs_pass<3>, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
   hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, s, hist, sc, code, clen,
-                     cb_out_base + cb_off, lay);
+                     cb_out_base + cb_off, lay, gate);
 }
 
 // Each block first copies the 64 KiB length table, so it takes at least 16
@@ -2292,19 +2310,19 @@ uint32_t chunk_words_blocks(int64_t N, int C) {
 }
 
 void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
-                        uint32_t* cw, Layout* lay, hipStream_t s) {
+                        uint32_t* cw, Layout* lay, hipStream_t s, const unsigned* gate) {
   hipLaunchKernelGGL(k_chunk_words, dim3(chunk_words_blocks(N, C)), dim3(256), 0, s, sym, N, C,
-                     clen, cw, lay);
+                     clen, cw, lay, gate);
 }
 
 void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint64_t cb_off,
                         Layout* lay, const unsigned long long* n_out, uint64_t out_cap_n,
-                        bool huff_only, hipStream_t s) {
+                        bool huff_only, hipStream_t s, const unsigned* gate) {
   // ranges of at least 4096 chunks; the range totals follow the counts
   const int64_t nb = std::min<int64_t>(kScanBlocksMax, (n_chunks + 4095) / 4096);
   if (nb <= 1) {
     hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(1024), 0, s, cw, n_chunks, out, cb_off, lay,
-                       n_out, out_cap_n, huff_only ? 1 : 0);
+                       n_out, out_cap_n, huff_only ? 1 : 0, gate);
     return;
   }
   const int64_t R = ((n_chunks + nb - 1) / nb + 3) & ~int64_t(3);
@@ -2312,21 +2330,22 @@ void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint
   unsigned long long* sums =
       reinterpret_cast<unsigned long long*>(const_cast<uint32_t*>(cw) + scan_sums_at(n_chunks));
   hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, cw, n_chunks,
-                     R, sums);
+                     R, sums, gate);
   hipLaunchKernelGGL(k_scan_offsets, dim3((unsigned)blocks), dim3(kScanThreads), 0, s, cw,
-                     n_chunks, R, sums, out, cb_off, lay, n_out, out_cap_n, huff_only ? 1 : 0);
+                     n_chunks, R, sums, out, cb_off, lay, n_out, out_cap_n, huff_only ? 1 : 0,
+                     gate);
 }
 
 void launch_outlier_sort(const OutlierBuf& ob, uint32_t* keyA, uint32_t* valA, uint32_t* keyB,
                          uint32_t* valB, int key_bits, uint8_t* out, Layout* lay,
-                         hipStream_t s) {
+                         hipStream_t s, const unsigned* gate) {
   hipLaunchKernelGGL(k_outlier_sort, dim3(1), dim3(1024), 0, s, ob, keyA, valA, keyB, valB,
-                     key_bits, out, lay);
+                     key_bits, out, lay, gate);
 }
 
 void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
                    const uint8_t* clen, const uint32_t* pk, uint8_t* out, const Layout* lay,
-                   hipStream_t s) {
+                   hipStream_t s, const unsigned* gate) {
   const int64_t n_chunks = (N + C - 1) / C;
   // large arrays: the persistent encoder with the code window in LDS (one
   // block per CU); the window copy needs 16-byte aligned symbol and table
@@ -2343,18 +2362,18 @@ void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
     }
     const int64_t blocks = std::min<int64_t>(kCUs, (n_chunks + kEncWaves - 1) / kEncWaves);
     hipLaunchKernelGGL(k_encode_win, dim3((unsigned)blocks), dim3(64 * kEncWaves),
-                       enc_win_lds_bytes(), s, sym, N, pk, out, lay);
+                       enc_win_lds_bytes(), s, sym, N, pk, out, lay, gate);
     return;
   }
   hipLaunchKernelGGL(k_encode, dim3((unsigned)((n_chunks + 3) / 4)), dim3(256),
-                     (size_t)4 * C * sizeof(uint32_t), s, sym, N, C, code, clen, pk, out, lay);
+                     (size_t)4 * C * sizeof(uint32_t), s, sym, N, C, code, clen, pk, out, lay,
+                     gate);
 }
 
-void launch_header(uint8_t* out, const Header& h, const double* q, int nq, const Layout* lay,
-                   const unsigned* status, unsigned long long* info, hipStream_t s) {
-  QArgs qa{};
-  for (int i = 0; i < nq && i <= kMaxLevels; ++i) qa.q[i] = q[i];
-  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, out, h, qa, nq, lay, status, info);
+void launch_header(uint8_t* out, const Header& h, const double* bud, const Layout* lay,
+                   const unsigned* status, bool empty, unsigned long long* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, s, out, h, bud, lay, status, empty ? 1 : 0,
+                     res);
 }
 
 void launch_huff_header(uint8_t* out, uint32_t C, uint64_t N, uint64_t n_chunks,

@@ -44,12 +44,14 @@ __host__ __device__ inline unsigned range_blocks(int64_t N) {
 void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, const BudgetIn& b,
                   double* bud, unsigned* status, hipStream_t s);
 // One decomposition level: coefficients of the level's new nodes (quantised
-// to symbols when sym != nullptr, else FP64 into raw) and the restriction
-// f = (P^T M_l) G_l onto the coarse grid (fout, FP64).
+// to symbols with the reciprocal bin *rp when sym != nullptr, else FP64 into
+// raw) and the restriction f = (P^T M_l) G_l onto the coarse grid (fout,
+// FP64).  rp is a device pointer (the compression's error-budget block); the
+// kernels return at once when the gate is closed (see gate_closed).
 // cand: tile candidate for three-axis levels (kDecTiles3F32/F64), others fixed.
 void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* fout,
-                      uint16_t* sym, double* raw, double r, const OutlierBuf& ob,
-                      unsigned* status, hipStream_t s, int cand = 0);
+                      uint16_t* sym, double* raw, const double* rp, const OutlierBuf& ob,
+                      unsigned* status, const unsigned* gate, hipStream_t s, int cand = 0);
 // Solve the coarse mass matrix along internal axis `axis` for every line of
 // x (coarse grid nc).  When sub != nullptr, x <- sub - solution.
 // cand: kThomasSeg (axis 2) or kThomasU (axes 0, 1) candidate; with cand 0,
@@ -69,9 +71,11 @@ bool thomas_grid_fits(const LevelGeom& g);
 bool thomas_planes_fit(const LevelGeom& g);
 void launch_thomas_planes(double* x, const LevelGeom& g, const double* sub, hipStream_t s);
 void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStream_t s);
-// Level-0 block: values of G0 (m0 entries) quantised (sym) or copied (raw).
+// Level-0 block: values of G0 (m0 entries) quantised with *rp (sym) or
+// copied (raw); gated like launch_dec_level.
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
-                   double r, const OutlierBuf& ob, unsigned* status, hipStream_t s);
+                   const double* rp, const OutlierBuf& ob, unsigned* status,
+                   const unsigned* gate, hipStream_t s);
 // Recomposition: f = (P^T M_l) c_l on the coarse grid from the coefficients.
 void launch_rec_restrict(const LevelGeom& g, const CoeffSrc& src, double q, double* fout,
                          hipStream_t s);
@@ -124,12 +128,15 @@ CodebookScratch carve_codebook_scratch(void* base);
 struct DecodeTables;
 size_t decode_tables_bytes();
 
-void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s);
+// The Huffman stage's kernels take an optional gate (a compression's status
+// word; see gate_closed): a null gate runs them unconditionally.
+void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s,
+                      const unsigned* gate = nullptr);
 void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
                      uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
-                     hipStream_t s);
+                     hipStream_t s, const unsigned* gate = nullptr);
 void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
-                        uint32_t* cw, Layout* lay, hipStream_t s);
+                        uint32_t* cw, Layout* lay, hipStream_t s, const unsigned* gate = nullptr);
 // Section layout + exclusive scan of the chunk word counts into the stream's
 // offsets section.  huff_only selects the Huffman-only stream layout.  cw
 // holds the n_chunks counts and has room for kScanSumWords more words at
@@ -141,19 +148,21 @@ inline int64_t chunk_words_len(int64_t n_chunks) {
 }
 void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint64_t cb_off,
                         Layout* lay, const unsigned long long* n_out, uint64_t out_cap_n,
-                        bool huff_only, hipStream_t s);
+                        bool huff_only, hipStream_t s, const unsigned* gate = nullptr);
 void launch_outlier_sort(const OutlierBuf& ob, uint32_t* keyA, uint32_t* valA, uint32_t* keyB,
                          uint32_t* valB, int key_bits, uint8_t* out, Layout* lay,
-                         hipStream_t s);
+                         hipStream_t s, const unsigned* gate = nullptr);
 // pk: the codebook's packed (rank << 6 | length) words and first-code table
 // (see CodebookScratch::pk).
 void launch_encode(const uint16_t* sym, int64_t N, int C, const uint32_t* code,
                    const uint8_t* clen, const uint32_t* pk, uint8_t* out, const Layout* lay,
-                   hipStream_t s);
-// Writes the header and bins (q holds nq <= kMaxLevels + 1 host values) once
-// the layout is known; info <- {status bits, outliers, stream bytes}.
-void launch_header(uint8_t* out, const Header& h, const double* q, int nq, const Layout* lay,
-                   const unsigned* status, unsigned long long* info, hipStream_t s);
+                   hipStream_t s, const unsigned* gate = nullptr);
+// Writes the header and bins (from the device error-budget block bud) once
+// the layout is known, or the trivial stream of a constant or empty array
+// (empty: no range pass ran), and the result words res[0] = mgc_status,
+// res[1] = stream bytes (MGC_ENOSPC: escaped values needed).
+void launch_header(uint8_t* out, const Header& h, const double* bud, const Layout* lay,
+                   const unsigned* status, bool empty, unsigned long long* res, hipStream_t s);
 void launch_huff_header(uint8_t* out, uint32_t C, uint64_t N, uint64_t n_chunks,
                         const Layout* lay, unsigned long long* info, hipStream_t s);
 

@@ -689,12 +689,15 @@ template <typename Tin, int TZ, int TY, int TX, int MODE>
 __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, const LevelGeom g,
                                                     double* __restrict__ fout,
                                                     uint16_t* __restrict__ sym,
-                                                    double* __restrict__ raw, const double r,
+                                                    double* __restrict__ raw,
+                                                    const double* __restrict__ rp,
                                                     const OutlierBuf ob,
                                                     unsigned* __restrict__ status,
+                                                    const unsigned* __restrict__ gate,
                                                     const uint32_t n_tiles) {
   const uint32_t t = xcd_tile(blockIdx.x, gridDim.x);
-  if (t >= n_tiles) return;
+  if (t >= n_tiles || gate_closed(gate)) return;
+  const double r = rp ? *rp : 0.0;
   dec_level_body<Tin, TZ, TY, TX, MODE>(G, g, fout, sym, raw, r, ob, status, t);
 }
 
@@ -733,14 +736,17 @@ template <typename Tin, bool QUANT>
 __global__ __launch_bounds__(256) void k_dec_stream(const Tin* __restrict__ G, const LevelGeom g,
                                                      double* __restrict__ fout,
                                                      uint16_t* __restrict__ sym,
-                                                     double* __restrict__ raw, const double r,
+                                                     double* __restrict__ raw,
+                                                     const double* __restrict__ rp,
                                                      const OutlierBuf ob,
-                                                     unsigned* __restrict__ status, const int seg,
-                                                     const uint32_t n_blocks) {
+                                                     unsigned* __restrict__ status,
+                                                     const unsigned* __restrict__ gate,
+                                                     const int seg, const uint32_t n_blocks) {
   constexpr int SY = kStreamSY, SX = kStreamSX, E1 = kStreamE1, E2 = kStreamE2;
   __shared__ StreamSmem<Tin> sm;
   const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
-  if (b >= n_blocks) return;
+  if (b >= n_blocks || gate_closed(gate)) return;
+  const double r = rp ? *rp : 0.0;
   const uint32_t nf0 = (uint32_t)g.nf[0], nf1 = (uint32_t)g.nf[1], nf2 = (uint32_t)g.nf[2];
   const uint32_t nc0 = (uint32_t)g.nc[0], nc1 = (uint32_t)g.nc[1], nc2 = (uint32_t)g.nc[2];
   const uint32_t tiles_x = (nc2 + SX - 1) / SX, tiles_y = (nc1 + SY - 1) / SY;
@@ -1928,9 +1934,12 @@ __device__ __forceinline__ void level0_body(const Tin* __restrict__ G0, int64_t 
 template <typename Tin, bool QUANT>
 __global__ __launch_bounds__(256) void k_level0(const Tin* __restrict__ G0, int64_t m0,
                                                  uint16_t* __restrict__ sym,
-                                                 double* __restrict__ raw, double r,
-                                                 const OutlierBuf ob, unsigned* status) {
-  level0_body<Tin, QUANT>(G0, m0, sym, raw, r, ob, status, blockIdx.x, gridDim.x);
+                                                 double* __restrict__ raw,
+                                                 const double* __restrict__ rp,
+                                                 const OutlierBuf ob, unsigned* status,
+                                                 const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
+  level0_body<Tin, QUANT>(G0, m0, sym, raw, rp ? *rp : 0.0, ob, status, blockIdx.x, gridDim.x);
 }
 
 template <typename Tout, bool RAW>
@@ -2123,44 +2132,45 @@ int active_axes(const LevelGeom& g) {
 }
 
 template <typename Tin, int MODE, int C>
-void dec_3(const Tin* Gp, const LevelGeom& g, double* fout, uint16_t* sym, double* raw, double r,
-           const OutlierBuf& ob, unsigned* status, hipStream_t s) {
+void dec_3(const Tin* Gp, const LevelGeom& g, double* fout, uint16_t* sym, double* raw,
+           const double* rp, const OutlierBuf& ob, unsigned* status, const unsigned* gate,
+           hipStream_t s) {
   constexpr TileShape ts = sizeof(Tin) == 4 ? kDecTiles3F32[C] : kDecTiles3F64[C];
   const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
   hipLaunchKernelGGL((k_dec_level<Tin, ts.z, ts.y, ts.x, MODE>), dim3(t.grid), dim3(256), 0, s,
-                     Gp, g, fout, sym, raw, r, ob, status, t.n_tiles);
+                     Gp, g, fout, sym, raw, rp, ob, status, gate, t.n_tiles);
 }
 
 template <typename Tin, int MODE>
 void dec_dispatch(const void* G, const LevelGeom& g, double* fout, uint16_t* sym, double* raw,
-                  double r, const OutlierBuf& ob, unsigned* status, hipStream_t s,
-                  int cand = 0) {
+                  const double* rp, const OutlierBuf& ob, unsigned* status,
+                  const unsigned* gate, hipStream_t s, int cand = 0) {
   const Tin* Gp = static_cast<const Tin*>(G);
   const int D = active_axes(g);
   if (D == 3 && MODE != 2 && cand == 0 && g.nf[0] * g.nf[1] * g.nf[2] >= kStreamMinPoints) {
     const StreamGrid sg = stream_grid(g);
     hipLaunchKernelGGL((k_dec_stream<Tin, MODE == 0>), dim3(sg.grid), dim3(256), 0, s, Gp, g, fout,
-                       sym, raw, r, ob, status, sg.seg, sg.n_blocks);
+                       sym, raw, rp, ob, status, gate, sg.seg, sg.n_blocks);
     return;
   }
   if (D == 3) {
     if (MODE == 2) cand = 0;
     switch (cand) {
-      case 1: dec_3<Tin, MODE, 1>(Gp, g, fout, sym, raw, r, ob, status, s); break;
-      case 2: dec_3<Tin, MODE, 2>(Gp, g, fout, sym, raw, r, ob, status, s); break;
-      case 3: dec_3<Tin, MODE, 3>(Gp, g, fout, sym, raw, r, ob, status, s); break;
-      default: dec_3<Tin, MODE, 0>(Gp, g, fout, sym, raw, r, ob, status, s);
+      case 1: dec_3<Tin, MODE, 1>(Gp, g, fout, sym, raw, rp, ob, status, gate, s); break;
+      case 2: dec_3<Tin, MODE, 2>(Gp, g, fout, sym, raw, rp, ob, status, gate, s); break;
+      case 3: dec_3<Tin, MODE, 3>(Gp, g, fout, sym, raw, rp, ob, status, gate, s); break;
+      default: dec_3<Tin, MODE, 0>(Gp, g, fout, sym, raw, rp, ob, status, gate, s);
     }
   } else if (D == 2) {
     constexpr TileShape ts = sizeof(Tin) == 4 ? kDecTile2F32 : kDecTile2F64;
     const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
     hipLaunchKernelGGL((k_dec_level<Tin, ts.z, ts.y, ts.x, MODE>), dim3(t.grid), dim3(256), 0, s,
-                       Gp, g, fout, sym, raw, r, ob, status, t.n_tiles);
+                       Gp, g, fout, sym, raw, rp, ob, status, gate, t.n_tiles);
   } else {
     constexpr TileShape ts = kDecTile1;
     const TileGrid t = tile_grid(g, ts.z, ts.y, ts.x);
     hipLaunchKernelGGL((k_dec_level<Tin, ts.z, ts.y, ts.x, MODE>), dim3(t.grid), dim3(256), 0, s,
-                       Gp, g, fout, sym, raw, r, ob, status, t.n_tiles);
+                       Gp, g, fout, sym, raw, rp, ob, status, gate, t.n_tiles);
   }
 }
 
@@ -2229,14 +2239,14 @@ void launch_range(const void* u, mgc_dtype dt, int64_t N, double* part, const Bu
 }
 
 void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* fout,
-                      uint16_t* sym, double* raw, double r, const OutlierBuf& ob,
-                      unsigned* status, hipStream_t s, int cand) {
+                      uint16_t* sym, double* raw, const double* rp, const OutlierBuf& ob,
+                      unsigned* status, const unsigned* gate, hipStream_t s, int cand) {
   if (sym) {
-    if (g_is_f32) dec_dispatch<float, 0>(G, g, fout, sym, raw, r, ob, status, s, cand);
-    else dec_dispatch<double, 0>(G, g, fout, sym, raw, r, ob, status, s, cand);
+    if (g_is_f32) dec_dispatch<float, 0>(G, g, fout, sym, raw, rp, ob, status, gate, s, cand);
+    else dec_dispatch<double, 0>(G, g, fout, sym, raw, rp, ob, status, gate, s, cand);
   } else {
-    if (g_is_f32) dec_dispatch<float, 1>(G, g, fout, sym, raw, r, ob, status, s, cand);
-    else dec_dispatch<double, 1>(G, g, fout, sym, raw, r, ob, status, s, cand);
+    if (g_is_f32) dec_dispatch<float, 1>(G, g, fout, sym, raw, rp, ob, status, gate, s, cand);
+    else dec_dispatch<double, 1>(G, g, fout, sym, raw, rp, ob, status, gate, s, cand);
   }
 }
 
@@ -2364,18 +2374,19 @@ void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStr
 }
 
 void launch_level0(const void* G0, bool g_is_f32, int64_t m0, uint16_t* sym, double* raw,
-                   double r, const OutlierBuf& ob, unsigned* status, hipStream_t s) {
+                   const double* rp, const OutlierBuf& ob, unsigned* status,
+                   const unsigned* gate, hipStream_t s) {
   const unsigned b = grid_for(m0);
   if (g_is_f32) {
     if (sym) hipLaunchKernelGGL((k_level0<float, true>), dim3(b), dim3(256), 0, s,
-                                static_cast<const float*>(G0), m0, sym, raw, r, ob, status);
+                                static_cast<const float*>(G0), m0, sym, raw, rp, ob, status, gate);
     else hipLaunchKernelGGL((k_level0<float, false>), dim3(b), dim3(256), 0, s,
-                            static_cast<const float*>(G0), m0, sym, raw, r, ob, status);
+                            static_cast<const float*>(G0), m0, sym, raw, rp, ob, status, gate);
   } else {
     if (sym) hipLaunchKernelGGL((k_level0<double, true>), dim3(b), dim3(256), 0, s,
-                                static_cast<const double*>(G0), m0, sym, raw, r, ob, status);
+                                static_cast<const double*>(G0), m0, sym, raw, rp, ob, status, gate);
     else hipLaunchKernelGGL((k_level0<double, false>), dim3(b), dim3(256), 0, s,
-                            static_cast<const double*>(G0), m0, sym, raw, r, ob, status);
+                            static_cast<const double*>(G0), m0, sym, raw, rp, ob, status, gate);
   }
 }
 
@@ -2398,8 +2409,8 @@ void launch_rec_interp(const double* Gc, const LevelGeom& g, const CoeffSrc& src
 
 void launch_adj_restrict(const double* gl, const LevelGeom& g, double* Gc, double* Gc_copy,
                          hipStream_t s) {
-  dec_dispatch<double, 2>(gl, g, Gc, nullptr, Gc_copy, 0.0, OutlierBuf{nullptr, nullptr, nullptr, 0},
-                          nullptr, s);
+  dec_dispatch<double, 2>(gl, g, Gc, nullptr, Gc_copy, nullptr,
+                          OutlierBuf{nullptr, nullptr, nullptr, 0}, nullptr, nullptr, s);
 }
 
 void launch_prolong(const double* v, const LevelGeom& g, double* out, hipStream_t s) {
