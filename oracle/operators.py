@@ -88,3 +88,27 @@ def solve_along(x: np.ndarray, F: np.ndarray, axis: int) -> np.ndarray:
     else:
         Z = scipy.linalg.solve_banded((1, 1), mass_banded(x), Fm.reshape(sh[0], -1))
     return np.moveaxis(np.asarray(Z).reshape(sh), 0, axis)
+
+
+KAPPA_GRID = 2.0 ** 20
+
+
+def transfer_norm(x: np.ndarray) -> float:
+    """kappa = ||M_c^{-1} P^T M||_inf for the axis whose level nodes are ``x``.
+
+    M_c^{-1} P^T M maps a function's nodal values on this level to the nodal
+    values of its L2 projection onto the next coarser level (the correction
+    step of the decomposition).  Its infinity norm (largest absolute row sum
+    of the dense nc x n matrix, formed by a banded solve per column) bounds
+    how much one projection can amplify a maximum.  It is rounded up to a
+    multiple of 2^-20 so that every implementation computing it in FP64
+    arrives at the same value.
+    """
+    xc = x[coarse_positions(len(x))]
+    B = (prolongation(x).T @ mass(x)).toarray()
+    if len(xc) == 1:
+        X = B / mass(xc).toarray()[0, 0]
+    else:
+        X = scipy.linalg.solve_banded((1, 1), mass_banded(xc), B)
+    kappa = float(np.max(np.sum(np.abs(X), axis=1)))
+    return float(np.ceil(kappa * KAPPA_GRID) / KAPPA_GRID)

@@ -9,11 +9,17 @@ linearity of recomposition: with quantisation errors delta_l (|delta| <= q_l/2
 per entry), the reconstruction error is R(delta) = delta_0 +
 sum_{l>=1} (I - Q_{l-1}) delta_l, with Q_{l-1} the L2 projection onto level l-1.
 
-* L-infinity: ||(I - Q_{l-1}) d||_inf <= (1 + 3^D) ||d||_inf because, per axis,
-  ||M_{l-1}^{-1} P^T M_l||_inf <= 3 for any spacing (the diagonal part of
-  M_{l-1} dominates its off-diagonal part 2:1, and each row of P^T M_l sums
-  to 3/2 of that diagonal) and interpolation never increases a maximum.  One
-  bin for all levels:  q = 2 tau' / (1 + L (1 + 3^D)).
+* L-infinity: Q_{l-1} acts on level-l nodal values as P (M_{l-1}^{-1} P^T M_l)
+  per axis, and interpolation never increases a maximum, so
+  ||(I - Q_{l-1}) d||_inf <= A_l ||d||_inf with A_l = 1 + prod_d kappa_{l,d},
+  kappa_{l,d} = ||M_{l-1,d}^{-1} P_d^T M_{l,d}||_inf computed exactly per axis
+  and level (operators.transfer_norm; about 1.866 on uniform axes, at most 3
+  for any spacing); A_0 = 1.  Any bins with sum_l A_l q_l / 2 <= tau' hold
+  the bound.  The paper asks for level-wise bins that improve the ratio: with
+  m_l coefficients on level l costing about log2(1/q_l) bits each, the split
+  that minimises the total under that constraint is q_l proportional to
+  m_l / A_l, i.e. q_l = 2 tau' m_l / (N A_l) (the finest level, with most of
+  the coefficients, gets the widest bins).
 * L2 (discrete, over all nodes): the terms of R(delta) are L2-orthogonal
   across levels, projections do not increase the L2 norm, the input-grid mass
   matrix has lambda_min >= 6^-D and level l's has lambda_max <= prod_d h_max.
@@ -33,6 +39,7 @@ from __future__ import annotations
 import numpy as np
 
 from .hierarchy import Hierarchy
+from .operators import transfer_norm
 from .transform import level_slices
 
 EPS_OUT = {np.dtype(np.float32): 2.0 ** -24, np.dtype(np.float64): 2.0 ** -53}
@@ -60,13 +67,25 @@ def error_budget(u: np.ndarray, bound: float, norm: str, mode: str):
     return float(tau), float(tau_eff)
 
 
+def linf_amplification(h: Hierarchy):
+    """A_l for l = 0..L: A_0 = 1, A_l = 1 + prod_d kappa_{l,d} (axis order)."""
+    A = [1.0]
+    for l in range(1, h.L + 1):
+        prod = 1.0
+        for d in range(h.D):
+            prod = prod * transfer_norm(h.coords[l][d])
+        A.append(1.0 + prod)
+    return A
+
+
 def level_bins(h: Hierarchy, tau_eff: float, norm: str):
     """q_l for l = 0..L (FP64, fixed operation order)."""
     D, L = h.D, h.L
     q = []
+    A = linf_amplification(h) if norm == "linf" else None
     for l in range(L + 1):
         if norm == "linf":
-            K = 2.0 / float(1 + L * (1 + 3 ** D))
+            K = (2.0 * float(h.level_count(l))) / (float(h.N) * A[l])
         else:
             den = float(6 ** D) * float(L + 1)
             for hm in h.max_spacing(l):

@@ -7,6 +7,12 @@
   at a vertex of the box);
 * the quantiser's rounding bound |c - k q| <= q/2 (1 + 2^-50) and the symbol /
   escape mapping at the dictionary edges;
+* the per-axis transfer norm kappa = ||M_c^{-1} P^T M||_inf behind the L-inf
+  bins: hand-derived on three nodes (3/2), the infinite uniform grid's closed
+  form 1 + sqrt(3)/2 (derived below), the same operator assembled
+  independently from quadrature of hat-function products and sampled coarse
+  hats, and the diagonal-dominance bound kappa <= 3 on random spacings;
+* the level-wise L-inf bins in closed form on 3 and 3x3 nodes;
 * the end-to-end bound on reconstructed data for both norms and both types.
 """
 import numpy as np
@@ -15,6 +21,7 @@ import pytest
 import oracle
 import synthetic
 from oracle import Hierarchy
+from oracle.operators import transfer_norm
 from oracle.quantize import level_bins, to_symbols, from_symbols
 from oracle.transform import level_slices
 
@@ -39,8 +46,9 @@ def test_linf_worst_case_within_budget(shape):
     R = _dense_R(h)
     worst = np.max(np.abs(R) @ _half_bins(h, q))
     assert worst <= tau_eff
-    # the bound is rigorous but not tight: record how loose (sanity, > 1%)
-    assert worst > 0.01 * tau_eff
+    # exact transfer norms make the bound tight to within a small factor
+    # (the slack left is that of bounding each level's term separately)
+    assert worst > 0.3 * tau_eff
 
 
 @pytest.mark.parametrize("shape", [(5, 4), (3, 3, 2), (17,), (3, 6)])
@@ -66,7 +74,7 @@ def test_quantizer_rounding_bound():
     q = level_bins(h, 1e-3, "linf")
     k = oracle.quantize(c, h, q)
     back = oracle.dequantize(k, h, q)
-    assert np.all(np.abs(c - back) <= q[0] / 2 * (1 + 2.0 ** -50))
+    assert np.all(np.abs(c - back) <= _half_bins(h, q) * (1 + 2.0 ** -50))
 
 
 def test_symbol_mapping_edges():
@@ -79,10 +87,75 @@ def test_symbol_mapping_edges():
 
 
 def test_linf_bins_closed_form():
-    # 3D, L = 6: q = 2 tau' / (1 + 6 * 28) = 2 tau' / 169 on every level
-    h = Hierarchy((65, 65, 65))
-    q = level_bins(h, 1.0, "linf")
-    assert np.all(q == 2.0 / 169.0)
+    # q_l = 2 tau' m_l / (N A_l), A_0 = 1, A_l = 1 + prod_d kappa, kappa = 3/2
+    # on three nodes.  3 nodes: m = (2, 1), A_1 = 5/2 -> q = (4/3, 4/15).
+    q = level_bins(Hierarchy((3,)), 1.0, "linf")
+    assert q[0] == 4.0 / 3.0 and abs(q[1] - 4.0 / 15.0) <= 1e-16
+    # 3x3: m = (4, 5), A_1 = 1 + 9/4 = 13/4 -> q = (8/9, 40/117)
+    q = level_bins(Hierarchy((3, 3)), 1.0, "linf")
+    assert abs(q[0] - 8.0 / 9.0) <= 1e-16 and abs(q[1] - 40.0 / 117.0) <= 1e-16
+
+
+# ---------------------------------------------------------- transfer norm
+def test_transfer_norm_three_nodes_by_hand():
+    # nodes 0, 1, 2 -> coarse 0, 2.  P^T M = [[5/12, 1/2, 1/12], [1/12, 1/2, 5/12]],
+    # M_c = [[2/3, 1/3], [1/3, 2/3]], M_c^{-1} = [[2, -1], [-1, 2]], so
+    # M_c^{-1} P^T M = [[3/4, 1/2, -1/4], [-1/4, 1/2, 3/4]]: row sums 3/2.
+    assert transfer_norm(np.arange(3.0)) == 1.5
+
+
+def test_transfer_norm_uniform_limit():
+    # Infinite uniform grid: M_c = (1/3) tridiag(1, 4, 1) whose inverse has
+    # entries 3 c (-r)^|k|, r = 2 - sqrt(3), c = 1/(2 sqrt 3).  The row of
+    # M_c^{-1} P^T M at a coarse node has entries 3/2 t_k + [k=0]/4 at the
+    # even fine nodes and 3/2 (t_k + t_{k-1}) at the odd ones (t_k = c(-r)^|k|),
+    # whose absolute values sum to 1/4 + 9c/2 + 3 c r/(1 - r) = 1 + sqrt(3)/2.  Far from the ends a long axis attains it.
+    limit = 1.0 + np.sqrt(3.0) / 2.0
+    expect = np.ceil(limit * 2.0 ** 20) / 2.0 ** 20
+    for n in (33, 65, 513, 300):
+        assert transfer_norm(np.arange(float(n))) == expect
+
+
+def _hat(xs, k, t):
+    e = np.zeros(len(xs))
+    e[k] = 1.0
+    return np.interp(t, xs, e)
+
+
+def _gram(xa, xb, xq):
+    """Gram matrix of the hats on nodes xa against those on xb, by 2-point
+    Gauss quadrature on every cell of the union grid xq (exact: products of
+    two linear pieces)."""
+    g = np.array([-1.0, 1.0]) / np.sqrt(3.0)
+    G = np.zeros((len(xa), len(xb)))
+    for lo, hi in zip(xq[:-1], xq[1:]):
+        t = (lo + hi) / 2 + (hi - lo) / 2 * g
+        fa = np.stack([_hat(xa, k, t) for k in range(len(xa))])
+        fb = np.stack([_hat(xb, k, t) for k in range(len(xb))])
+        G += (hi - lo) / 2 * fa @ fb.T
+    return G
+
+
+@pytest.mark.parametrize("x", [np.arange(9.0), np.arange(6.0), np.array([0.0, 1.0, 2.0, 4.0, 5.0, 8.0, 9.0]),
+                               np.cumsum(np.r_[0.0, np.random.default_rng(3).uniform(0.2, 3.0, 10)])])
+def test_transfer_norm_matches_quadrature_projection(x):
+    # the L2 projection onto the coarse hats, built without P or M: the
+    # coarse Gram matrix and the coarse-vs-fine Gram matrix by quadrature
+    xc = x[oracle.hierarchy.coarse_positions(len(x))]
+    Gc = _gram(xc, xc, x)
+    Gcf = _gram(xc, x, x)
+    X = np.linalg.solve(Gc, Gcf)
+    kappa = float(np.max(np.sum(np.abs(X), axis=1)))
+    assert abs(transfer_norm(x) - kappa) <= 2.0 ** -20
+    assert transfer_norm(x) >= kappa
+
+
+def test_transfer_norm_at_most_three():
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        n = int(rng.integers(3, 40))
+        x = np.cumsum(np.r_[0.0, rng.uniform(0.01, 5.0, n - 1)])
+        assert 1.0 <= transfer_norm(x) <= 3.0
 
 
 @pytest.mark.parametrize("norm", ["linf", "l2"])
