@@ -282,16 +282,65 @@ LevelGeom Plan::geom(int l) const {
   return g;
 }
 
+// kappa = ||M_c^{-1} P^T M_l||_inf of one axis of level l: the largest
+// absolute row sum of the dense nc x nf matrix, formed one fine column at a
+// time (column f of P^T M_l has at most three non-zeros, the restriction taps
+// W of the coarse nodes within two fine positions; each column is solved
+// with the Thomas factors of M_c), rounded up to a multiple of 2^-20.
+double Plan::transfer_norm(int l, int k) const {
+  const PlanLevel& v = lv[l];
+  const int64_t nf = v.nf[k], nc = v.nc[k];
+  const double* W = &tab[v.t_W[k]];
+  const double* ta = &tab[v.t_ta[k]];
+  const double* tm = &tab[v.t_tm[k]];
+  const double* tc = &tab[v.t_tc[k]];
+  std::vector<double> rows(nc, 0.0), y(nc), b(nc, 0.0);
+  for (int64_t f = 0; f < nf; ++f) {
+    // coarse nodes j with |p(j) - f| <= 2 (p(j) = min(2j, nf - 1))
+    const int64_t j0 = std::max<int64_t>(0, (f - 2 + 1) / 2), j1 = std::min<int64_t>(nc - 1, (f + 2) / 2 + 1);
+    int64_t lo = nc, hi = -1;
+    for (int64_t j = j0; j <= j1; ++j) {
+      const int64_t d = f - cpos(j, nf);
+      if (d < -2 || d > 2) continue;
+      b[j] = W[5 * j + d + 2];
+      lo = std::min(lo, j);
+      hi = std::max(hi, j);
+    }
+    if (hi < 0) continue;
+    // forward sweep from the first non-zero (y is zero before it)
+    for (int64_t j = lo; j < nc; ++j) y[j] = tm[j] * b[j] - (j > lo ? ta[j] * y[j - 1] : 0.0);
+    double x = 0.0;
+    for (int64_t j = nc - 1; j >= 0; --j) {
+      x = (j >= lo ? y[j] : 0.0) - (j < nc - 1 ? tc[j] * x : 0.0);
+      rows[j] += std::fabs(x);
+    }
+    for (int64_t j = lo; j <= hi; ++j) b[j] = 0.0;
+  }
+  double kappa = 0.0;
+  for (int64_t j = 0; j < nc; ++j) kappa = std::max(kappa, rows[j]);
+  return std::ceil(kappa * 1048576.0) / 1048576.0;
+}
+
+// q_l = tau' K_l.
+// L-inf: reconstruction error <= sum_l A_l q_l / 2 with A_0 = 1 and
+// A_l = 1 + prod over active axes of kappa (the transfer norm above); bins
+// proportional to m_l / A_l (m_l coefficients on level l) minimise the coded
+// size under that constraint: K_l = 2 m_l / (N A_l).
+// L2: every level gets an equal share of tau'^2 (see mgc.h).
 std::vector<double> Plan::bin_factors(mgc_norm norm) const {
   std::vector<double> K(L + 1);
-  int64_t pow3 = 1, pow6 = 1;
-  for (int d = 0; d < D; ++d) {
-    pow3 *= 3;
-    pow6 *= 6;
-  }
+  int64_t pow6 = 1;
+  for (int d = 0; d < D; ++d) pow6 *= 6;
   for (int l = 0; l <= L; ++l) {
     if (norm == MGC_LINF) {
-      K[l] = 2.0 / (double)(1 + (int64_t)L * (1 + pow3));
+      double A = 1.0;
+      if (l >= 1) {
+        double prod = 1.0;
+        for (int k = 0; k < 3; ++k)
+          if (bit[k] >= 0) prod = prod * transfer_norm(l, k);
+        A = 1.0 + prod;
+      }
+      K[l] = (2.0 * (double)lv[l].count) / ((double)N * A);
     } else {
       double den = (double)pow6 * (double)(L + 1);
       for (int k = 0; k < 3; ++k)

@@ -37,6 +37,9 @@ struct Plan {
   LevelGeom geom(int l) const;
   // q_l = tau_eff * K_l with K_l from the L-inf or L2 budget split.
   std::vector<double> bin_factors(mgc_norm norm) const;
+  // ||M_{l-1}^{-1} P^T M_l||_inf of internal axis k (active) of level l >= 1,
+  // rounded up to a multiple of 2^-20.
+  double transfer_norm(int l, int k) const;
 };
 
 // Builds the plan (host tables only).  Throws Fail on invalid shapes.
