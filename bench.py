@@ -9,10 +9,14 @@ before timing starts.  ``value`` is the round-trip throughput
 
 Prints one JSON line with the metric, a roofline entry for the dominant
 kernel (per-launch algorithmic bytes over its HIP-event-timed duration) and a
-CPU baseline (the FP64 oracle on a bounded sub-cube, one core).  Two more
-objects ride on the same line: "batched" (256 uneven arrays in one graph
-launch against 256 plain calls) and "differentiation" (gradient of a
-sub-box quantity of interest through the adjoint recomposition).
+CPU baseline (the FP64 oracle on a bounded slab of the same field, one
+thread, plus the oracle on a slice of the 256-array batch over every host
+core).  More objects ride on the same line: "batched" (256 uneven arrays in
+one graph launch against 256 plain calls), "differentiation" (gradient of a
+sub-box quantity of interest through the adjoint recomposition) and
+"workloads" (compress / decompress GB/s, compression ratio and error of the
+65^3 bump field, the 513^3 field at 1e-2 and 1e-4, the 8193^2 FP64 plane
+waves and the 300x400x500 field under both norms).
 """
 from __future__ import annotations
 
@@ -93,11 +97,21 @@ def stage_bytes(N: int, Nc: int, in_size: int, stream_bytes: int):
     }
 
 
-def cpu_baseline(u: np.ndarray, rel: float, edge: int):
-    """Time the FP64 oracle (compress + decompress) on a sub-cube, one thread."""
+def host_cores() -> int:
+    """Cores this process may run on (the GPU machine's share, not the machine's)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(u: np.ndarray, rel: float, planes: int):
+    """Time the FP64 oracle (compress + decompress, one thread) on a slab of
+    the benchmark field: its first ``planes`` x-y planes at full 513 x 513
+    extent, so the grid hierarchy's line lengths match the headline run."""
     import oracle
     from threadpoolctl import threadpool_limits
-    sub = np.ascontiguousarray(u[:edge, :edge, :edge])
+    sub = np.ascontiguousarray(u[:planes])
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         b = oracle.compress(sub, rel)
@@ -105,9 +119,113 @@ def cpu_baseline(u: np.ndarray, rel: float, edge: int):
         oracle.decompress(b)
         t2 = time.perf_counter()
     return {"value": round(2 * sub.nbytes / (t2 - t0) / 1e9, 5), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d^3 FP32 sub-cube of the same field, compress %.1fs + decompress %.1fs"
-                      % (edge, t1 - t0, t2 - t1)}
+            "host_cores_available": host_cores(), "kind": "oracle",
+            "sample": "%s FP32 slab (first %d planes) of the same field and bound, compress "
+                      "%.1fs + decompress %.1fs, one thread" % ("x".join(map(str, sub.shape)),
+                                                               planes, t1 - t0, t2 - t1)}
+
+
+def _oracle_batch_item(spec):
+    import oracle
+    import synthetic
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        u = synthetic.field_from_spec(spec)
+        t0 = time.perf_counter()
+        oracle.compress(u, spec["bound"])
+        return u.nbytes, time.perf_counter() - t0
+
+
+def cpu_batch_baseline(synthetic, stride: int = 8):
+    """The oracle compressing a slice of the 256-array batch (every
+    ``stride``-th array) on a process pool of every available host core
+    (arrays are independent).  GB/s = slice input bytes / pool wall time."""
+    import multiprocessing as mp
+    specs = synthetic.batch_specs(256, seed=5)[::stride]
+    workers = min(16, host_cores(), len(specs))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_batch_item, specs[:workers])   # start-up, imports
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_batch_item, specs, chunksize=1)
+        wall = time.perf_counter() - t0
+    nbytes = sum(r[0] for r in res)
+    return {"value": round(nbytes / wall / 1e9, 5), "unit": "GB/s", "cores": workers,
+            "kind": "oracle", "sample": "%d of the 256 arrays (every %dth, %.0f MB), compress "
+                                        "only, %d processes, %.1fs wall" %
+                                        (len(specs), stride, nbytes / 1e6, workers, wall)}
+
+
+def config_legs(torch, mgc, synthetic, u513, reps: int):
+    """Compress / decompress figures of every single-array workload.
+
+    Each: input resident on the GPU, buffers preallocated, two untimed
+    calls, then ``reps`` timed compress and decompress calls (HIP events on
+    the current stream, median).  err_over_tau: max |error| / tau for L-inf,
+    ||error||_2 / tau for L2 (tau = rel * (max - min) or rel * ||u||_2).
+    """
+    cases = [
+        ("bumps65_f32_linf_rel1e-3", lambda: synthetic.bumps((65, 65, 65), 1), "linf", 1e-3),
+        ("grf513_f32_linf_rel1e-2", lambda: u513, "linf", 1e-2),
+        ("grf513_f32_linf_rel1e-4", lambda: u513, "linf", 1e-4),
+        ("sin8193x8193_f64_linf_rel1e-4", lambda: synthetic.sinusoids((8193, 8193), 3),
+         "linf", 1e-4),
+        ("sin8193x8193_f64_l2_rel1e-3", None, "l2", 1e-3),
+        ("grf300x400x500_f32_linf_rel1e-4", lambda: synthetic.grf((300, 400, 500), 4),
+         "linf", 1e-4),
+        ("grf300x400x500_f32_l2_rel1e-3", None, "l2", 1e-3),
+    ]
+    out = []
+    u = None
+    stream = torch.cuda.current_stream()
+    for name, make, norm, rel in cases:
+        if make is not None:
+            u = make()
+        x = torch.from_numpy(u).cuda()
+        ws_n, out_n = mgc.compress_query(tuple(x.shape), x.dtype)
+        ws = torch.empty(ws_n, dtype=torch.uint8, device="cuda")
+        ob = torch.empty(out_n, dtype=torch.uint8, device="cuda")
+        blob = mgc.compress(x, rel, norm, workspace=ws, out=ob)
+        info = mgc.header_info(blob)
+        wsd = torch.empty(info["workspace_bytes"], dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        mgc.decompress(blob, workspace=wsd, out=y, info=info)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        torch.cuda.synchronize()
+        for e in ev:
+            e[0].record(stream)
+            blob = mgc.compress(x, rel, norm, workspace=ws, out=ob)
+            e[1].record(stream)
+            mgc.decompress(blob, workspace=wsd, out=y, info=info)
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        c_ms = float(np.median([a.elapsed_time(b) for a, b, _ in ev]))
+        d_ms = float(np.median([b.elapsed_time(c) for _, b, c in ev]))
+        err = (y.double() - x.double())
+        xd = x.double()
+        if norm == "linf":
+            tau = rel * (xd.max() - xd.min()).item()
+            e = err.abs().max().item()
+        else:
+            tau = rel * torch.linalg.vector_norm(xd).item()
+            e = torch.linalg.vector_norm(err).item()
+        nb = x.numel() * x.element_size()
+        row = {"workload": name, "shape": list(x.shape), "norm": norm, "rel": rel,
+               "compress_ms": round(c_ms, 4), "decompress_ms": round(d_ms, 4),
+               "compress_GBps": round(nb / (c_ms * 1e-3) / 1e9, 2),
+               "decompress_GBps": round(nb / (d_ms * 1e-3) / 1e9, 2),
+               "compress_frac_of_hbm_peak": round(nb / (c_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 5),
+               "decompress_frac_of_hbm_peak": round(nb / (d_ms * 1e-3) / 1e9 / PEAK_HBM_GBPS, 5),
+               "compression_ratio": round(nb / blob.numel(), 3),
+               "err_over_tau": round(e / tau, 4)}
+        log("workload %-32s compress %7.3f ms (%6.1f GB/s)  decompress %7.3f ms (%6.1f GB/s)  "
+            "CR %6.2f  err/tau %.3f" % (name, c_ms, row["compress_GBps"], d_ms,
+                                        row["decompress_GBps"], row["compression_ratio"],
+                                        row["err_over_tau"]))
+        out.append(row)
+        del x, ws, ob, wsd, y, err, xd, blob
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(torch, mgc, synthetic, reps: int):
@@ -237,10 +355,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--n", type=int, default=513)
-    ap.add_argument("--cpu-edge", type=int, default=257)
+    ap.add_argument("--cpu-planes", type=int, default=129)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--config-reps", type=int, default=5)
     ap.add_argument("--copy-reference", action="store_true",
                     help="also copy the input once on the device (a kernel of known "
                          "traffic, the scale for hardware byte counters)")
@@ -350,10 +470,19 @@ def main():
     if not args.no_diff:
         diff = differentiation_leg(torch, mgc, synthetic)
 
+    configs = None
+    if not args.no_configs:
+        configs = config_legs(torch, mgc, synthetic, u, args.config_reps)
+
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on a %d^3 sub-cube" % args.cpu_edge)
-        cpu = cpu_baseline(u, args.rel, args.cpu_edge)
+        log("cpu baseline: oracle on the first %d planes of the field" % args.cpu_planes)
+        cpu = cpu_baseline(u, args.rel, args.cpu_planes)
+        log("cpu baseline: %s" % json.dumps(cpu))
+        if not args.no_batched:
+            log("cpu baseline: oracle on a slice of the batch, all host cores")
+            cpu["batched"] = cpu_batch_baseline(synthetic)
+            log("cpu baseline (batch): %s" % json.dumps(cpu["batched"]))
 
     value = 2 * in_bytes / (ms_step * 1e-3) / 1e9
     res = {
@@ -371,6 +500,7 @@ def main():
         "compression_ratio": round(in_bytes / stream_bytes, 3),
         "max_err_over_tau": round(err / tau, 4),
         "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "differentiation": diff,
+        "workloads": configs,
         "stages": stages, "stages_ms_per_step_with_events": round(prof_ms_step, 4),
     }
     print(json.dumps(res), flush=True)

@@ -1593,6 +1593,234 @@ __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Partitioned sweeps for coarse grids above the LDS-tile limit.  A line is
+// cut into segments whose values stay in registers from their load to their
+// store, so every value is read once and written once per axis.  The forward
+// recurrence is affine in its start value: inside a segment starting at s it
+// runs from zero (y^_i), and the true value is y_i = y^_i + alpha_i y_{s-1}
+// with alpha_i = prod_{j=s..i} (-a_j).  The segments' end values chain the
+// start values from segment to segment (one multiply-add each); the backward
+// sweep splits the same way with beta_i = prod_{j=i..e-1} (-c_j) and the next
+// segment's first value.  Results agree with the serial sweep up to rounding.
+//
+// Strided axes: lanes take 64 adjacent lines (coalesced rows of 512 bytes)
+// and the W wavefronts of a block take W consecutive segments of them; the
+// chain of carries runs through LDS.
+constexpr int kPartWaves = 8;  // segments (wavefronts) per block at most
+template <int AXIS, int SEG>
+__global__ __launch_bounds__(64 * kPartWaves) void k_thomas_part(
+    double* __restrict__ x, int64_t n0, int64_t n1, int64_t n2, int sl,
+    const double* __restrict__ ta, const double* __restrict__ tm,
+    const double* __restrict__ tc, const double* __restrict__ sub) {
+  __shared__ double cy[kPartWaves][64], cx[kPartWaves][64];
+  __shared__ double ca[kPartWaves], cb[kPartWaves];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int W = (int)(blockDim.x >> 6);
+  int64_t lines, len, stride;
+  if (AXIS == 1) {
+    lines = n0 * n2;
+    len = n1;
+    stride = n2;
+  } else {
+    lines = n1 * n2;
+    len = n0;
+    stride = n1 * n2;
+  }
+  const int64_t t0 = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = t0 < lines;
+  const int64_t t = live ? t0 : lines - 1;
+  const int64_t base = AXIS == 1 ? (t / n2) * n1 * n2 + t % n2 : t;
+  const int64_t s = (int64_t)w * sl;
+  const int ns = (int)max<int64_t>(min<int64_t>(sl, len - s), 0);
+  double* p = x + base;
+  double v[SEG];
+  {
+    const int64_t hi = max<int64_t>(min<int64_t>(s + ns, len) - 1, 0);
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) v[k] = p[min<int64_t>(s + k, hi) * stride];
+  }
+  // forward sweep of the segment from a zero start
+  double prev = 0.0, A = 1.0;
+#pragma unroll
+  for (int k = 0; k < SEG; ++k)
+    if (k < ns) {
+      const double a = ta[s + k];
+      prev = thomas_fwd(v[k], a, tm[s + k], prev);
+      v[k] = prev;
+      A *= -a;
+    }
+  cy[w][lane] = prev;
+  if (lane == 0) ca[w] = A;
+  __syncthreads();
+  if (w > 0) {
+    double yin = 0.0;
+    for (int j = 0; j < w; ++j) yin = fma(ca[j], yin, cy[j][lane]);
+    double al = 1.0;
+#pragma unroll
+    for (int k = 0; k < SEG; ++k)
+      if (k < ns) {
+        al *= -ta[s + k];
+        v[k] = fma(al, yin, v[k]);
+      }
+  }
+  // backward sweep of the segment from a zero end
+  double nxt = 0.0, B = 1.0;
+#pragma unroll
+  for (int k = SEG - 1; k >= 0; --k)
+    if (k < ns) {
+      const double c = tc[s + k];
+      nxt = thomas_bwd(v[k], c, nxt);
+      v[k] = nxt;
+      B *= -c;
+    }
+  cx[w][lane] = nxt;
+  if (lane == 0) cb[w] = B;
+  __syncthreads();
+  if (w < W - 1) {
+    double xin = 0.0;
+    for (int j = W - 1; j > w; --j) xin = fma(cb[j], xin, cx[j][lane]);
+    double be = 1.0;
+#pragma unroll
+    for (int k = SEG - 1; k >= 0; --k)
+      if (k < ns) {
+        be *= -tc[s + k];
+        v[k] = fma(be, xin, v[k]);
+      }
+  }
+  if (!live) return;
+  if (sub) {
+    const double* q = sub + base;
+#pragma unroll
+    for (int k = 0; k < SEG; ++k)
+      if (k < ns) p[(s + k) * stride] = q[(s + k) * stride] - v[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < SEG; ++k)
+      if (k < ns) p[(s + k) * stride] = v[k];
+  }
+}
+
+// Contiguous axis: one wavefront per row at a time, lane l holding the row's
+// values l*sl .. l*sl+sl-1 (sl = ceil(n / 64)).  Rows move between HBM and
+// registers through LDS with coalesced loads and stores; the chains of
+// carries are wavefront scans of the segments' affine maps (composition of
+// y -> B + A y is associative).  Each lane keeps its factors in registers
+// for every row it solves.
+__device__ __forceinline__ double shfl_up_d(double v, int o) { return __shfl_up(v, o, 64); }
+__device__ __forceinline__ double shfl_down_d(double v, int o) { return __shfl_down(v, o, 64); }
+
+constexpr int kRowScanWaves = 4;
+template <int K>
+__global__ __launch_bounds__(64 * kRowScanWaves) void k_thomas_rowscan(
+    double* __restrict__ x, int64_t nrows, int64_t n, const double* __restrict__ ta,
+    const double* __restrict__ tm, const double* __restrict__ tc,
+    const double* __restrict__ sub) {
+  __shared__ double buf[kRowScanWaves][64 * K];
+  const int lane = threadIdx.x & 63;
+  const int wv = (int)(threadIdx.x >> 6);
+  double* b = buf[wv];
+  const int sl = (int)((n + 63) / 64);
+  const int s = lane * sl;
+  const int ns = (int)max<int64_t>(min<int64_t>(sl, n - s), 0);
+  double fa[K], fm[K], fc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int64_t i = min<int64_t>(s + k, n - 1);
+    fa[k] = ta[i];
+    fm[k] = tm[i];
+    fc[k] = tc[i];
+  }
+  const int64_t step = (int64_t)gridDim.x * kRowScanWaves;
+  for (int64_t r = (int64_t)blockIdx.x * kRowScanWaves + wv; r < nrows; r += step) {
+    double* row = x + r * n;
+    double g[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) g[k] = row[min<int64_t>(lane + 64 * k, n - 1)];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (lane + 64 * k < n) b[lane + 64 * k] = g[k];
+    wave_fence();
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = b[min<int64_t>(s + k, n - 1)];
+    // forward sweep of the lane's segment from a zero start, then the scan
+    // of the segments' maps y_end = B + A y_start
+    double B = 0.0, A = 1.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < ns) {
+        B = thomas_fwd(v[k], fa[k], fm[k], B);
+        v[k] = B;
+        A *= -fa[k];
+      }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double Ao = shfl_up_d(A, o), Bo = shfl_up_d(B, o);
+      if (lane >= o) {
+        B = fma(A, Bo, B);
+        A *= Ao;
+      }
+    }
+    double yin = shfl_up_d(B, 1);
+    if (lane == 0) yin = 0.0;
+    {
+      double al = 1.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (k < ns) {
+          al *= -fa[k];
+          v[k] = fma(al, yin, v[k]);
+        }
+    }
+    // backward sweep from a zero end, then the scan of the maps
+    // x_start = X + C x_end from the last lane down
+    double X = 0.0, C = 1.0;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k)
+      if (k < ns) {
+        X = thomas_bwd(v[k], fc[k], X);
+        v[k] = X;
+        C *= -fc[k];
+      }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double Co = shfl_down_d(C, o), Xo = shfl_down_d(X, o);
+      if (lane + o < 64) {
+        X = fma(C, Xo, X);
+        C *= Co;
+      }
+    }
+    double xin = shfl_down_d(X, 1);
+    if (lane == 63) xin = 0.0;
+    {
+      double be = 1.0;
+#pragma unroll
+      for (int k = K - 1; k >= 0; --k)
+        if (k < ns) {
+          be *= -fc[k];
+          v[k] = fma(be, xin, v[k]);
+        }
+    }
+    wave_fence();
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < ns) b[s + k] = v[k];
+    wave_fence();
+    if (sub) {
+      const double* q = sub + r * n;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (lane + 64 * k < n) row[lane + 64 * k] = q[lane + 64 * k] - b[lane + 64 * k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        if (lane + 64 * k < n) row[lane + 64 * k] = b[lane + 64 * k];
+    }
+    wave_fence();
+  }
+}
+
 // Whole lines in LDS, one tile per wavefront.  Each wavefront holds 16
 // lines of the axis in its own part of LDS: lines adjacent along the
 // contiguous axis for the strided axes (the 16 values at one position are
@@ -2301,6 +2529,52 @@ void thomas_tiles(int axis, double* x, const int64_t nc[3], const AxisTab& t, co
 }
 }  // namespace
 
+namespace {
+template <int K>
+void thomas_rowscan(double* x, const int64_t nc[3], const AxisTab& t, const double* sub,
+                    hipStream_t s) {
+  const int64_t rows = nc[0] * nc[1];
+  const int64_t blocks = std::min<int64_t>((rows + kRowScanWaves - 1) / kRowScanWaves, 4096);
+  hipLaunchKernelGGL(k_thomas_rowscan<K>, dim3((unsigned)blocks), dim3(64 * kRowScanWaves), 0, s,
+                     x, rows, nc[2], t.ta, t.tm, t.tc, sub);
+}
+template <int AXIS, int SEG>
+void thomas_part_axis(double* x, const int64_t nc[3], const AxisTab& t, const double* sub,
+                      hipStream_t s) {
+  const int64_t len = nc[AXIS];
+  const int64_t w = (len + SEG - 1) / SEG;
+  const int sl = (int)((len + w - 1) / w);
+  const int64_t lines = AXIS == 1 ? nc[0] * nc[2] : nc[1] * nc[2];
+  hipLaunchKernelGGL((k_thomas_part<AXIS, SEG>), dim3((unsigned)((lines + 63) / 64)),
+                     dim3((unsigned)(64 * w)), 0, s, x, nc[0], nc[1], nc[2], sl, t.ta, t.tm, t.tc,
+                     sub);
+}
+// Partitioned sweeps where the line fits (false otherwise).
+bool thomas_part(int axis, double* x, const int64_t nc[3], const AxisTab& t, const double* sub,
+                 hipStream_t s) {
+  const int64_t len = nc[axis];
+  if (axis == 2) {
+    if (len <= 128) thomas_rowscan<2>(x, nc, t, sub, s);
+    else if (len <= 256) thomas_rowscan<4>(x, nc, t, sub, s);
+    else if (len <= 320) thomas_rowscan<5>(x, nc, t, sub, s);
+    else if (len <= 512) thomas_rowscan<8>(x, nc, t, sub, s);
+    else if (len <= 1024) thomas_rowscan<16>(x, nc, t, sub, s);
+    else return false;
+    return true;
+  }
+  if (len > 64 * kPartWaves) return false;
+  const bool small = len <= 40 * kPartWaves;
+  if (axis == 1) {
+    if (small) thomas_part_axis<1, 40>(x, nc, t, sub, s);
+    else thomas_part_axis<1, 64>(x, nc, t, sub, s);
+  } else {
+    if (small) thomas_part_axis<0, 40>(x, nc, t, sub, s);
+    else thomas_part_axis<0, 64>(x, nc, t, sub, s);
+  }
+  return true;
+}
+}  // namespace
+
 void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
                    const double* sub, hipStream_t s, int cand) {
   const int64_t L = nc[axis];
@@ -2309,6 +2583,7 @@ void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
     else thomas_tiles<2>(axis, x, nc, t, sub, s);
     return;
   }
+  if (cand == 0 && thomas_part(axis, x, nc, t, sub, s)) return;
   switch (cand) {
     case 1: thomas_c<1>(axis, x, nc, t, sub, s); break;
     case 2: thomas_c<2>(axis, x, nc, t, sub, s); break;

@@ -64,3 +64,33 @@ def test_decompose_513_sampled_finest_coefficients():
     back = mgc.recompose(got, shape, torch.float64)
     assert torch.max(torch.abs(back - torch.from_numpy(u).cuda().double())).item() <= \
         1e-11 * float(np.max(np.abs(u)))
+
+
+@pytest.mark.parametrize("shape", [(65, 513, 1025), (300, 400, 500), (513, 513, 513)])
+def test_partitioned_sweeps_match_serial_sweeps(shape):
+    """Coarse grids above 2^22 points solve in partitioned sweeps (segments
+    in registers, carries chained between segments); the serial sweeps
+    (forced candidate 1) must give the same coefficients and recompositions
+    up to rounding.  The shapes reach the strided-axis kernel with one to
+    eight segments per line and the row kernel with 4 to 16 values per lane."""
+    torch, mgc = gpu()
+    u = synthetic.grf(shape, 11, dtype=np.float64)
+    x = torch.from_numpy(u).cuda()
+    del u
+    scale = torch.max(torch.abs(x)).item()
+    part = mgc.decompose(x)
+    rec_part = mgc.recompose(part, shape, torch.float64)
+    mgc.set_tuning("thomas_strided", 1)
+    mgc.set_tuning("thomas_rows", 1)
+    try:
+        serial = mgc.decompose(x)
+        rec_serial = mgc.recompose(part, shape, torch.float64)
+    finally:
+        mgc.set_tuning("thomas_strided", -1)
+        mgc.set_tuning("thomas_rows", -1)
+    d = torch.max(torch.abs(part - serial)).item()
+    r = torch.max(torch.abs(rec_part - rec_serial)).item()
+    print("%s: decompose %.3g, recompose %.3g of max|u|" % (shape, d / scale, r / scale))
+    assert d <= 1e-13 * scale
+    assert r <= 1e-13 * scale
+    assert torch.max(torch.abs(rec_part - x)).item() <= 1e-12 * scale
