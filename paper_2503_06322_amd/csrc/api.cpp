@@ -106,6 +106,10 @@ CompressWs carve_compress(Carver& c, const Plan& p, uint64_t cap) {
   w.okB = c.take<uint32_t>(cap);
   w.ovB = c.take<uint32_t>(cap);
   w.info = c.take<unsigned long long>(4);
+  w.zc = c.take<uint32_t>(std::max<int64_t>(n_chunks, 1));
+  w.zpre = c.take<uint32_t>(std::max<int64_t>(n_chunks, 1));
+  w.zsums = c.take<uint32_t>(kEscSumsMax);
+  w.zl = c.take<uint32_t>(64 * std::max<int64_t>(n_chunks, 1));
   return w;
 }
 
@@ -399,7 +403,7 @@ void compress_enqueue(mgc_ctx ctx, const Plan& p, const void* d_in, int ndim,
   }
   {
     StageScope st(&ctx->prof, "chunk_words", s);
-    launch_chunk_words(w.sym, p.N, kChunk, w.clen, w.cw, w.lay, s, gate);
+    launch_chunk_words(w.sym, p.N, kChunk, w.clen, w.cw, w.lay, s, gate, w.zc, w.zl);
   }
   {
     StageScope st(&ctx->prof, "layout_scan", s);
@@ -407,8 +411,9 @@ void compress_enqueue(mgc_ctx ctx, const Plan& p, const void* d_in, int ndim,
                        gate);
   }
   {
-    StageScope st(&ctx->prof, "outlier_sort", s);
-    launch_outlier_sort(ob, w.okA, w.ovA, w.okB, w.ovB, key_bits(p.N), out, w.lay, s, gate);
+    StageScope st(&ctx->prof, "outlier_order", s);
+    launch_escape_order(ob, w.zc, w.zl, w.zpre, w.zsums, (int64_t)h.n_chunks, out, w.lay,
+                        w.status, s, gate);
   }
   {
     StageScope st(&ctx->prof, "encode", s);

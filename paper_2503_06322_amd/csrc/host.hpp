@@ -100,6 +100,7 @@ struct CompressWs {
   int64_t* oval;
   uint32_t *okA, *ovA, *okB, *ovB;
   unsigned long long* info;
+  uint32_t *zc, *zpre, *zsums, *zl;  // escape counts, their prefix, lane masks
 };
 CompressWs carve_compress(Carver& c, const Plan& p, uint64_t cap);
 size_t max_stream_bytes(const Plan& p, uint64_t cap);

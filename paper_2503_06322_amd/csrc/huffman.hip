@@ -1056,11 +1056,17 @@ __global__ __launch_bounds__(256) void k_cbs_pass(const unsigned* __restrict__ h
 // Lane l of the chunk's wavefront owns symbols [l*per, (l+1)*per) of the
 // chunk; symbols and their code lengths are fetched in groups of 8 with all
 // loads in flight before use.
+// With zc != nullptr (C = 1024, 16 symbols a lane) the pass also records
+// where the escape symbol (0) occurs: zc[chunk] = escapes in the chunk and,
+// for chunks that have any, zl[64 chunk + lane] = the lane's 16-bit mask of
+// escapes | (escapes in the chunk's earlier lanes) << 16, from which the
+// escaped values are put in stream order without sorting.
 __device__ __forceinline__ void chunk_words_body(const uint16_t* __restrict__ sym, int64_t N,
                                                  int C, const uint8_t* __restrict__ clen,
                                                  uint32_t* __restrict__ cw,
                                                  const Layout* __restrict__ lay, uint32_t blk,
-                                                 uint32_t nblk) {
+                                                 uint32_t nblk, uint32_t* __restrict__ zc = nullptr,
+                                                 uint32_t* __restrict__ zl = nullptr) {
   // the code lengths of all 65536 symbols in LDS (one 16-byte load per
   // thread per 4 KiB), then chunk groups of four in a block-stride loop
   __shared__ __align__(16) uint8_t ln[kDict];
@@ -1082,18 +1088,37 @@ __device__ __forceinline__ void chunk_words_body(const uint16_t* __restrict__ sy
        chunk += (int64_t)nblk * 4) {
     const int64_t a = chunk * C + (int64_t)lane * per;
     const int64_t end = min<int64_t>(chunk * C + C, N);
-    unsigned bits = 0;
+    unsigned bits = 0, esc = 0;
     if (per == 16 && a + 16 <= end && (reinterpret_cast<uintptr_t>(sym) & 15) == 0) {
       const uint4* p = reinterpret_cast<const uint4*>(sym + a);
       const uint4 x0 = p[0], x1 = p[1];
       const unsigned w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
-      for (int k = 0; k < 8; ++k) bits += (unsigned)ln[w[k] & 0xFFFFu] + ln[w[k] >> 16];
+      for (int k = 0; k < 8; ++k) {
+        bits += (unsigned)ln[w[k] & 0xFFFFu] + ln[w[k] >> 16];
+        esc |= ((w[k] & 0xFFFFu) == 0u ? 1u : 0u) << (2 * k);
+        esc |= ((w[k] >> 16) == 0u ? 1u : 0u) << (2 * k + 1);
+      }
     } else {
-      for (int64_t i = a; i < min<int64_t>(a + per, end); ++i) bits += ln[sym[i]];
+      for (int64_t i = a; i < min<int64_t>(a + per, end); ++i) {
+        const uint16_t v = sym[i];
+        bits += ln[v];
+        if (v == 0 && i - a < 32) esc |= 1u << (i - a);
+      }
     }
     for (int o = 32; o > 0; o >>= 1) bits += (unsigned)__shfl_xor((int)bits, o, 64);
     if (lane == 0) cw[chunk] = (bits + 31u) >> 5;
+    if (zc) {
+      const unsigned cnt = (unsigned)__popc(esc);
+      unsigned incl = cnt;
+      for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = (unsigned)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      const unsigned total = (unsigned)__shfl((int)incl, 63, 64);
+      if (total) zl[chunk * 64 + lane] = esc | ((incl - cnt) << 16);
+      if (lane == 0) zc[chunk] = total;
+    }
   }
 }
 
@@ -1101,9 +1126,11 @@ __global__ __launch_bounds__(256) void k_chunk_words(const uint16_t* __restrict_
                                                       int C, const uint8_t* __restrict__ clen,
                                                       uint32_t* __restrict__ cw,
                                                       const Layout* __restrict__ lay,
-                                                      const unsigned* __restrict__ gate) {
+                                                      const unsigned* __restrict__ gate,
+                                                      uint32_t* __restrict__ zc,
+                                                      uint32_t* __restrict__ zl) {
   if (gate_closed(gate)) return;
-  chunk_words_body(sym, N, C, clen, cw, lay, blockIdx.x, gridDim.x);
+  chunk_words_body(sym, N, C, clen, cw, lay, blockIdx.x, gridDim.x, zc, zl);
 }
 
 __device__ __forceinline__ void layout_scan_body(const uint32_t* __restrict__ cw,
@@ -1395,6 +1422,92 @@ __global__ __launch_bounds__(1024) void k_outlier_sort(const OutlierBuf ob, uint
                                                         const unsigned* __restrict__ gate) {
   if (gate_closed(gate)) return;
   outlier_sort_body(ob, keyA, valA, keyB, valB, key_bits, out, lay);
+}
+
+// --------------------------------------------- escaped values in stream order
+// The level kernels append escaped values (stream position, value) in no
+// particular order.  Their order in the stream is that of the escape
+// symbols, so a value's rank is the number of escapes before its position:
+// the exclusive sum of the per-chunk counts (zpre) plus the escapes of the
+// chunk's earlier lanes and of the lane's symbols before it (zl).  The sums
+// over chunks run on many blocks: range totals, then range scans offset by
+// the totals before them.
+constexpr int kEscThreads = 256;
+__global__ __launch_bounds__(kEscThreads) void k_esc_sums(const uint32_t* __restrict__ zc,
+                                                          int64_t n_chunks, int64_t R,
+                                                          uint32_t* __restrict__ sums,
+                                                          const Layout* __restrict__ lay,
+                                                          const unsigned* __restrict__ gate) {
+  if (gate_closed(gate) || lay->status) return;
+  __shared__ unsigned long long sm[kScanThreads / 64];
+  const int64_t lo = (int64_t)blockIdx.x * R, hi = min<int64_t>(lo + R, n_chunks);
+  unsigned long long acc = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kEscThreads) acc += zc[i];
+  acc = block_sum_u64(acc, sm);
+  if (threadIdx.x == 0) sums[blockIdx.x] = (uint32_t)acc;
+}
+
+__global__ __launch_bounds__(kEscThreads) void k_esc_prefix(const uint32_t* __restrict__ zc,
+                                                            int64_t n_chunks, int64_t R,
+                                                            const uint32_t* __restrict__ sums,
+                                                            uint32_t* __restrict__ zpre,
+                                                            const Layout* __restrict__ lay,
+                                                            const unsigned* __restrict__ gate) {
+  if (gate_closed(gate) || lay->status) return;
+  __shared__ unsigned long long sm[kScanThreads / 64];
+  __shared__ uint32_t wtot[kEscThreads / 64];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  unsigned long long pre = 0;
+  for (int b = tid; b < (int)blockIdx.x; b += kEscThreads) pre += sums[b];
+  pre = block_sum_u64(pre, sm);
+  const int64_t lo = (int64_t)blockIdx.x * R, hi = min<int64_t>(lo + R, n_chunks);
+  uint32_t base = (uint32_t)pre;
+  for (int64_t t0 = lo; t0 < hi; t0 += kEscThreads) {
+    const int64_t i = t0 + tid;
+    const uint32_t v = i < hi ? zc[i] : 0u;
+    uint32_t incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < kEscThreads / 64; ++w) {
+      before += w < wave ? wtot[w] : 0u;
+      all += wtot[w];
+    }
+    if (i < hi) zpre[i] = base + before + incl - v;
+    base += all;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_esc_place(const OutlierBuf ob,
+                                                   const uint32_t* __restrict__ zpre,
+                                                   const uint32_t* __restrict__ zl,
+                                                   uint8_t* __restrict__ out,
+                                                   Layout* __restrict__ lay,
+                                                   unsigned* __restrict__ status,
+                                                   const unsigned* __restrict__ gate) {
+  if (gate_closed(gate) || lay->status) return;
+  const uint64_t n = lay->n_outliers;
+  uint64_t* op = reinterpret_cast<uint64_t*>(out + lay->opos);
+  int64_t* ov = reinterpret_cast<int64_t*>(out + lay->oval);
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * 256) {
+    const uint32_t pos = ob.pos[i];
+    const uint32_t chunk = pos >> 10, j = pos & 1023u;
+    const uint32_t e = zl[(size_t)chunk * 64 + (j >> 4)];
+    const uint32_t t = j & 15u;
+    const uint64_t rank = (uint64_t)zpre[chunk] + (e >> 16) + (uint32_t)__popc(e & ((1u << t) - 1u));
+    if (((e >> t) & 1u) == 0u || rank >= n) {
+      atomicOr(status, ST_INTERNAL);
+      continue;
+    }
+    op[rank] = pos;
+    ov[rank] = ob.val[i];
+  }
 }
 
 // One wavefront per chunk, four chunks per block; LDS holds each chunk's
@@ -2310,9 +2423,30 @@ uint32_t chunk_words_blocks(int64_t N, int C) {
 }
 
 void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
-                        uint32_t* cw, Layout* lay, hipStream_t s, const unsigned* gate) {
+                        uint32_t* cw, Layout* lay, hipStream_t s, const unsigned* gate,
+                        uint32_t* zc, uint32_t* zl) {
+  if (zc && C != 1024) throw std::logic_error("launch_chunk_words: escape counts need C = 1024");
   hipLaunchKernelGGL(k_chunk_words, dim3(chunk_words_blocks(N, C)), dim3(256), 0, s, sym, N, C,
-                     clen, cw, lay, gate);
+                     clen, cw, lay, gate, zc, zl);
+}
+
+int64_t esc_sum_blocks(int64_t n_chunks) {
+  return std::max<int64_t>(1, std::min<int64_t>(kEscSumsMax, (n_chunks + 1023) / 1024));
+}
+
+void launch_escape_order(const OutlierBuf& ob, const uint32_t* zc, const uint32_t* zl,
+                         uint32_t* zpre, uint32_t* sums, int64_t n_chunks, uint8_t* out,
+                         Layout* lay, unsigned* status, hipStream_t s, const unsigned* gate) {
+  const int64_t nb = esc_sum_blocks(n_chunks);
+  const int64_t R = (n_chunks + nb - 1) / nb;
+  const int64_t blocks = (n_chunks + R - 1) / R;
+  hipLaunchKernelGGL(k_esc_sums, dim3((unsigned)blocks), dim3(kEscThreads), 0, s, zc, n_chunks,
+                     R, sums, lay, gate);
+  hipLaunchKernelGGL(k_esc_prefix, dim3((unsigned)blocks), dim3(kEscThreads), 0, s, zc,
+                     n_chunks, R, sums, zpre, lay, gate);
+  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((ob.cap + 255) / 256, 2048));
+  hipLaunchKernelGGL(k_esc_place, dim3(grid), dim3(256), 0, s, ob, zpre, zl, out, lay, status,
+                     gate);
 }
 
 void launch_layout_scan(const uint32_t* cw, int64_t n_chunks, uint8_t* out, uint64_t cb_off,
@@ -2425,9 +2559,11 @@ DecodeShape launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_se
                           decode_room<8, 4, 4>()};
   int shape = force.ring > 0 ? force.ring - 1 : 0;
   while (tab + (size_t)waves * dec_wave_bytes(kRW[shape]) > room[shape]) {
-    if (force.ring > 0 || force.waves > 0)
+    if (force.ring > 0)
       fail(MGC_EINVAL, "the forced decoder ring and wavefront count do not fit in LDS");
     if (shape < 2) ++shape;
+    else if (force.waves > 0)
+      fail(MGC_EINVAL, "the forced decoder wavefront count does not fit in LDS");
     else if (waves > 1) --waves;
     else fail(MGC_EDEVICE, "decode table does not fit in LDS");
   }

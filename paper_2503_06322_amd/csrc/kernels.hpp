@@ -135,8 +135,20 @@ void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_
 void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
                      uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
                      hipStream_t s, const unsigned* gate = nullptr);
+// zc / zl (optional, C = 1024): per-chunk escape counts and per-lane escape
+// masks with in-chunk prefix counts, for launch_escape_order.
 void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
-                        uint32_t* cw, Layout* lay, hipStream_t s, const unsigned* gate = nullptr);
+                        uint32_t* cw, Layout* lay, hipStream_t s, const unsigned* gate = nullptr,
+                        uint32_t* zc = nullptr, uint32_t* zl = nullptr);
+// Escaped values in stream order without a sort: the rank of each appended
+// (position, value) record among the escapes, from the chunk counts zc
+// (prefix-summed into zpre) and the lane masks zl of launch_chunk_words;
+// writes the stream's outlier sections (after the layout scan).  sums holds
+// kEscSumsMax entries.  An inconsistent record sets ST_INTERNAL in *status.
+constexpr int64_t kEscSumsMax = 1024;
+void launch_escape_order(const OutlierBuf& ob, const uint32_t* zc, const uint32_t* zl,
+                         uint32_t* zpre, uint32_t* sums, int64_t n_chunks, uint8_t* out,
+                         Layout* lay, unsigned* status, hipStream_t s, const unsigned* gate);
 // Section layout + exclusive scan of the chunk word counts into the stream's
 // offsets section.  huff_only selects the Huffman-only stream layout.  cw
 // holds the n_chunks counts and has room for kScanSumWords more words at

@@ -323,14 +323,21 @@ double Plan::transfer_norm(int l, int k) const {
 
 // q_l = tau' K_l.
 // L-inf: reconstruction error <= sum_l A_l q_l / 2 with A_0 = 1 and
-// A_l = 1 + prod over active axes of kappa (the transfer norm above); bins
-// proportional to m_l / A_l (m_l coefficients on level l) minimise the coded
-// size under that constraint: K_l = 2 m_l / (N A_l).
+// A_l = 1 + prod over active axes of kappa (the transfer norm above).  The
+// budget is split as K_l = 2 sqrt(m_l) / (A_l S), S = sum_j sqrt(m_j) (m_l
+// coefficients on level l): the finest level gets the widest bins, and the
+// small coarse levels keep their quantised values inside the dictionary
+// (bins proportional to m_l / A_l, the split that minimises a log2(1/q)
+// bit count, send most coarse-level values to the escape list).
 // L2: every level gets an equal share of tau'^2 (see mgc.h).
 std::vector<double> Plan::bin_factors(mgc_norm norm) const {
   std::vector<double> K(L + 1);
   int64_t pow6 = 1;
   for (int d = 0; d < D; ++d) pow6 *= 6;
+  // L-inf: q_l = 2 tau' sqrt(m_l) / (A_l S), S = sum_j sqrt(m_j) (summed
+  // from level 0 up)
+  double S = 0.0;
+  for (int l = 0; l <= L; ++l) S = S + std::sqrt((double)lv[l].count);
   for (int l = 0; l <= L; ++l) {
     if (norm == MGC_LINF) {
       double A = 1.0;
@@ -340,7 +347,7 @@ std::vector<double> Plan::bin_factors(mgc_norm norm) const {
           if (bit[k] >= 0) prod = prod * transfer_norm(l, k);
         A = 1.0 + prod;
       }
-      K[l] = (2.0 * (double)lv[l].count) / ((double)N * A);
+      K[l] = (2.0 * std::sqrt((double)lv[l].count)) / (S * A);
     } else {
       double den = (double)pow6 * (double)(L + 1);
       for (int k = 0; k < 3; ++k)

@@ -715,6 +715,7 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
 constexpr int kStreamSY = 8, kStreamSX = 32;
 constexpr int kStreamE1 = 2 * kStreamSY + 3, kStreamE2 = 2 * kStreamSX + 3;
 constexpr int kStreamNLD = (kStreamE1 * kStreamE2 + 255) / 256;
+constexpr int kStreamPF = 2;  // fine planes whose loads are in flight
 // levels with fewer fine points use the tiled kernel (measured faster there)
 constexpr int64_t kStreamMinPoints = int64_t(1) << 25;
 // Recomposition's restriction (one value per coarse node from the dequantised
@@ -733,7 +734,7 @@ struct StreamSmem {
 };
 
 template <typename Tin, bool QUANT>
-__global__ __launch_bounds__(256) void k_dec_stream(const Tin* __restrict__ G, const LevelGeom g,
+__global__ __launch_bounds__(256, 4) void k_dec_stream(const Tin* __restrict__ G, const LevelGeom g,
                                                      double* __restrict__ fout,
                                                      uint16_t* __restrict__ sym,
                                                      double* __restrict__ raw,
@@ -790,11 +791,14 @@ __global__ __launch_bounds__(256) void k_dec_stream(const Tin* __restrict__ G, c
     ldst[u] = u * 256 + tid < n_pl ? y * E2 + x : -1;
   }
   const size_t plane = (size_t)nf1 * nf2;
-  Tin pv[kStreamNLD];
-  auto load_plane = [&](uint32_t z) {
+  // kStreamPF planes of loads in flight, one register set per plane in
+  // fixed roles (the plane loop is unrolled by kStreamPF); a set is reloaded
+  // with the plane kStreamPF ahead right after it has gone to LDS.
+  Tin pv[kStreamPF][kStreamNLD];
+  auto load_plane = [&](uint32_t z, Tin (&v)[kStreamNLD]) {
     const Tin* src = G + (size_t)z * plane;
 #pragma unroll
-    for (int u = 0; u < kStreamNLD; ++u) pv[u] = src[goff[u]];
+    for (int u = 0; u < kStreamNLD; ++u) v[u] = src[goff[u]];
   };
   // x pass: thread column cx, rows y = rsub, rsub + 8, ...
   const int xcol = tid & 31, xrow = tid >> 5;
@@ -834,13 +838,18 @@ __global__ __launch_bounds__(256) void k_dec_stream(const Tin* __restrict__ G, c
   const int m0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, m1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
             m2b = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
   uint32_t next_cz = cz0;
-  load_plane(zs);
-  for (uint32_t zf = zs; zf <= ze; ++zf) {
+#pragma unroll
+  for (int d = 0; d < kStreamPF; ++d) load_plane(min<uint32_t>(zs + d, ze), pv[d]);
+  for (uint32_t zb = zs; zb <= ze; zb += kStreamPF) {
+#pragma unroll
+  for (int d = 0; d < kStreamPF; ++d) {
+    const uint32_t zf = zb + d;
+    if (zf > ze) break;
     const int s3 = (int)(zf % 3u), s5 = (int)(zf % 5u);
 #pragma unroll
     for (int u = 0; u < kStreamNLD; ++u)
-      if (ldst[u] >= 0) (&sm.raw[s3][0][0])[ldst[u]] = pv[u];
-    if (zf < ze) load_plane(zf + 1);
+      if (ldst[u] >= 0) (&sm.raw[s3][0][0])[ldst[u]] = pv[d][u];
+    if (zf + kStreamPF <= ze) load_plane(zf + kStreamPF, pv[d]);
     __syncthreads();
     if (xcol < tkx) {
       for (int y = xrow; y < ext1; y += 8) {
@@ -908,6 +917,7 @@ __global__ __launch_bounds__(256) void k_dec_stream(const Tin* __restrict__ G, c
     }
     __syncthreads();
   }
+  }
 }
 
 // ------------------------ recomposition restriction of a 3-axis level, streamed
@@ -927,7 +937,7 @@ struct RecStreamSmem {
 };
 
 template <bool RAW>
-__global__ __launch_bounds__(256) void k_rec_stream(const LevelGeom g, const CoeffSrc src,
+__global__ __launch_bounds__(256, 4) void k_rec_stream(const LevelGeom g, const CoeffSrc src,
                                                      const double q, double* __restrict__ fout,
                                                      const int seg, const uint32_t n_blocks) {
   constexpr int SY = kStreamSY, SX = kStreamSX, E2 = kStreamE2;
@@ -1008,34 +1018,51 @@ __global__ __launch_bounds__(256) void k_rec_stream(const LevelGeom g, const Coe
     }
   }
   const uint32_t J1 = c0y + ocy, J2 = c0x + ocx;
-  // coefficient loads of a plane (symbols or FP64 values), all in flight
-  uint32_t sv[kStreamNLD], pos[kStreamNLD];
-  double rv[kStreamNLD];
-  bool has[kStreamNLD];
-  auto load_plane = [&](uint32_t z) {
+  // coefficient loads of a plane (symbols or FP64 values): kStreamPF planes
+  // in flight, one register set per plane in fixed roles (the plane loop is
+  // unrolled by kStreamPF)
+  // (a set holds only the loaded values: a slot's stream position and
+  // whether it holds a coefficient are recomputed from the plane index)
+  struct PlaneRegs {
+    uint32_t sv[kStreamNLD];
+    double rv[kStreamNLD];
+  };
+  PlaneRegs pr[kStreamPF];
+  auto slot_pos = [&](uint32_t z, int u, bool& has) -> uint32_t {
     const bool n0 = is_new32(z, nf0);
     const uint32_t j0 = n0 ? (z >> 1) : cidx32(z, nf0);
+    has = ldst[u] >= 0 && (n0 || yxnew[u]);
+    return has ? pbase[u][n0 ? 1 : 0] + j0 * pstride[u] : 0u;
+  };
+  auto load_plane = [&](uint32_t z, PlaneRegs& R) {
 #pragma unroll
     for (int u = 0; u < kStreamNLD; ++u) {
-      has[u] = ldst[u] >= 0 && (n0 || yxnew[u]);
-      pos[u] = has[u] ? pbase[u][n0 ? 1 : 0] + j0 * pstride[u] : 0u;
-      if (RAW) rv[u] = src.raw[pos[u]];
-      else sv[u] = src.sym[pos[u]];
+      bool has;
+      const uint32_t pos = slot_pos(z, u, has);
+      if (RAW) R.rv[u] = src.raw[pos];
+      else R.sv[u] = src.sym[pos];
     }
   };
   uint32_t next_cz = cz0;
-  load_plane(zs);
-  for (uint32_t zf = zs; zf <= ze; ++zf) {
+#pragma unroll
+  for (int d = 0; d < kStreamPF; ++d) load_plane(min<uint32_t>(zs + d, ze), pr[d]);
+  for (uint32_t zb = zs; zb <= ze; zb += kStreamPF) {
+#pragma unroll
+  for (int d = 0; d < kStreamPF; ++d) {
+    const uint32_t zf = zb + d;
+    if (zf > ze) break;
     const int s5 = (int)(zf % 5u);
 #pragma unroll
     for (int u = 0; u < kStreamNLD; ++u) {
       if (ldst[u] < 0) continue;
+      bool has;
+      const uint32_t pos = slot_pos(zf, u, has);
       double v = 0.0;
-      if (has[u]) v = RAW ? rv[u] : dequant(src, sv[u], pos[u], q);
+      if (has) v = RAW ? pr[d].rv[u] : dequant(src, pr[d].sv[u], pos, q);
       (&sm.P[0][0])[ldst[u]] = v;
     }
     __syncthreads();
-    if (zf < ze) load_plane(zf + 1);
+    if (zf + kStreamPF <= ze) load_plane(zf + kStreamPF, pr[d]);
     if (xcol < tkx) {
       for (int y = xrow; y < ext1; y += 8) {
         const double* row = sm.P[y];
@@ -1069,6 +1096,7 @@ __global__ __launch_bounds__(256) void k_rec_stream(const LevelGeom g, const Coe
       ++next_cz;
     }
   }
+  }
 }
 
 // --------------------------------------------- recomposition of one level
@@ -1095,6 +1123,19 @@ __device__ __forceinline__ void rec_restrict_body(const LevelGeom& g, const Coef
   Tile tl;
   if (!make_tile<TZ, TY, TX>(g, t, tiles_x, tiles_y, tl)) return;
   const int tid = threadIdx.x;
+  // On an axis of even length the last two coarse nodes are adjacent fine
+  // nodes, so a tile that starts at the last coarse node loads one fine node
+  // (its new node two coarse nodes back) that none of its cells covers.  The
+  // restriction reads that node with weight zero; it must hold a number, not
+  // whatever the LDS held before, so such tiles start from zeros.
+  bool gap = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    gap = gap || (tl.c0[k] >= 1 && cpos32(tl.c0[k], tl.nf[k]) - cpos32(tl.c0[k] - 1, tl.nf[k]) < 2);
+  if (gap) {
+    for (int i = tid; i < E0 * E1 * E2; i += 256) tile[i] = 0.0;
+    __syncthreads();
+  }
   uint32_t so[8];
   subband_offsets(g, so);
   const uint32_t e1c = tl.nc[1], e1n = tl.nf[1] - tl.nc[1];

@@ -94,3 +94,65 @@ def test_partitioned_sweeps_match_serial_sweeps(shape):
     assert d <= 1e-13 * scale
     assert r <= 1e-13 * scale
     assert torch.max(torch.abs(rec_part - x)).item() <= 1e-12 * scale
+
+
+def _leave_nan_in_lds(torch):
+    """Runs library kernels of torch's that stage NaN doubles in LDS on every
+    CU (a block scan and a row softmax over NaN inputs), so that the next
+    kernels start with NaN bit patterns in whatever LDS they do not write."""
+    torch.cumsum(torch.full((1 << 24,), float("nan"), dtype=torch.float64, device="cuda"), 0)
+    torch.softmax(torch.full((4096, 4096), float("nan"), dtype=torch.float64, device="cuda"), 1)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("shape", [(30, 41, 12), (40, 33, 17), (300, 400, 500), (64, 64),
+                                   (16, 21, 7), (66,), (9, 5, 4), (65, 65, 65)])
+def test_results_do_not_depend_on_stale_lds(shape):
+    """Every LDS value a kernel reads, also with a zero weight, must be one it
+    wrote: decomposition, recomposition (raw coefficients and quantised
+    symbols) and the adjoint give bit for bit the same results after kernels
+    that leave NaN in LDS as without them, and (small grids) the oracle's.
+    (Axes of even length end in two adjacent coarse nodes; a recomposition
+    tile starting at the last of them once read a fine node no cell had
+    written.)"""
+    torch, mgc = gpu()
+    u = synthetic.grf(shape, 13, dtype=np.float64)
+    h = Hierarchy(shape)
+    x = torch.from_numpy(u).cuda()
+    g = torch.from_numpy(np.random.default_rng(3).standard_normal(shape)).cuda()
+    scale = float(np.max(np.abs(u)))
+
+    def run(poisoned):
+        out = {}
+        if poisoned:
+            _leave_nan_in_lds(torch)
+        out["c"] = mgc.decompose(x)
+        if poisoned:
+            _leave_nan_in_lds(torch)
+        out["y"] = mgc.recompose(out["c"], shape, torch.float64)
+        if poisoned:
+            _leave_nan_in_lds(torch)
+        blob = mgc.compress(x, 1e-4)
+        out["blob"] = blob.clone()
+        if poisoned:
+            _leave_nan_in_lds(torch)
+        out["v"] = mgc.decompress(blob)
+        if poisoned:
+            _leave_nan_in_lds(torch)
+        out["ga"] = mgc.recompose_adjoint(g)
+        torch.cuda.synchronize()
+        return out
+
+    clean, dirty = run(False), run(True)
+    for k in clean:
+        assert not bool(torch.isnan(dirty[k].double() if k != "blob" else dirty[k].double()).any()), k
+        assert clean[k].shape == dirty[k].shape and bool(torch.equal(clean[k], dirty[k])), k
+    assert torch.max(torch.abs(clean["y"] - x)).item() <= 1e-12 * scale
+    tau = 1e-4 * (float(u.max()) - float(u.min()))
+    assert torch.max(torch.abs(clean["v"] - x)).item() <= tau
+    if h.N <= 300_000:
+        ref = oracle.decompose(u, h)
+        assert np.max(np.abs(clean["c"].cpu().numpy() - ref)) <= 1e-12 * scale
+        gref = oracle.recompose_adjoint(g.cpu().numpy(), h)
+        assert np.max(np.abs(clean["ga"].cpu().numpy() - gref)) <= \
+            1e-12 * max(1.0, float(np.max(np.abs(gref))))

@@ -12,7 +12,8 @@
   form 1 + sqrt(3)/2 (derived below), the same operator assembled
   independently from quadrature of hat-function products and sampled coarse
   hats, and the diagonal-dominance bound kappa <= 3 on random spacings;
-* the level-wise L-inf bins in closed form on 3 and 3x3 nodes;
+* the level-wise L-inf bins in closed form on 3 and 3x3 nodes, and the
+  budget they spend (sum_l A_l q_l / 2 = tau') on larger grids;
 * the end-to-end bound on reconstructed data for both norms and both types.
 """
 import numpy as np
@@ -87,13 +88,25 @@ def test_symbol_mapping_edges():
 
 
 def test_linf_bins_closed_form():
-    # q_l = 2 tau' m_l / (N A_l), A_0 = 1, A_l = 1 + prod_d kappa, kappa = 3/2
-    # on three nodes.  3 nodes: m = (2, 1), A_1 = 5/2 -> q = (4/3, 4/15).
+    # q_l = 2 tau' sqrt(m_l) / (A_l S), S = sum_j sqrt(m_j), A_0 = 1,
+    # A_l = 1 + prod_d kappa, kappa = 3/2 on three nodes.
+    # 3 nodes: m = (2, 1), A_1 = 5/2, S = 1 + sqrt 2 ->
+    # q = (4 - 2 sqrt 2, (4/5)(sqrt 2 - 1)); A_0 q_0 / 2 + A_1 q_1 / 2 = 1.
+    r2, r5 = np.sqrt(2.0), np.sqrt(5.0)
     q = level_bins(Hierarchy((3,)), 1.0, "linf")
-    assert q[0] == 4.0 / 3.0 and abs(q[1] - 4.0 / 15.0) <= 1e-16
-    # 3x3: m = (4, 5), A_1 = 1 + 9/4 = 13/4 -> q = (8/9, 40/117)
+    assert abs(q[0] - (4.0 - 2.0 * r2)) <= 1e-15 and abs(q[1] - 0.8 * (r2 - 1.0)) <= 1e-15
+    # 3x3: m = (4, 5), A_1 = 1 + 9/4 = 13/4, S = 2 + sqrt 5 ->
+    # q = (4 (sqrt 5 - 2), (8/13)(5 - 2 sqrt 5))
     q = level_bins(Hierarchy((3, 3)), 1.0, "linf")
-    assert abs(q[0] - 8.0 / 9.0) <= 1e-16 and abs(q[1] - 40.0 / 117.0) <= 1e-16
+    assert abs(q[0] - 4.0 * (r5 - 2.0)) <= 1e-15
+    assert abs(q[1] - 8.0 / 13.0 * (5.0 - 2.0 * r5)) <= 1e-15
+    # the whole budget is spent: sum_l A_l q_l / 2 = tau'
+    for shape in [(9, 9, 9), (17, 12), (33,), (6, 6, 6)]:
+        h = Hierarchy(shape)
+        from oracle.quantize import linf_amplification
+        A = linf_amplification(h)
+        q = level_bins(h, 1.0, "linf")
+        assert abs(sum(a * b / 2 for a, b in zip(A, q)) - 1.0) <= 1e-14
 
 
 # ---------------------------------------------------------- transfer norm
