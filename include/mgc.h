@@ -117,6 +117,33 @@ mgc_status mgc_compress_blocking(mgc_ctx ctx, const void* d_in, int ndim,
                                  void* stream, uint64_t* h_out_size);
 
 /* ------------------------------------------------------------------------
+ * Allocation-free compression, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  mgc_compress_noalloc is mgc_compress with no workspace
+ * argument: the plan tables of the shape and every work buffer live in a
+ * device array of MGC_NOALLOC_SCRATCH_BYTES that the library holds on each
+ * device until the process ends, and the call makes no hipMalloc, hipFree or
+ * other allocating call (stage timing is not recorded during it).  The
+ * caller passes the input, the output (out_cap >= the max_out_bytes of
+ * mgc_compress_query for the same outlier_cap) and the two result words;
+ * the outcome is reported there exactly as by mgc_compress, and the stream
+ * is byte-identical to mgc_compress's.  Arrays whose tables and buffers do
+ * not fit the scratch are rejected with MGC_ENOSPC before anything is
+ * enqueued (with the default outlier capacity: three-axis arrays up to
+ * about 9.5 million values, e.g. 211^3; two-axis ones up to about 7 million).  Every call on a device shares that device's
+ * scratch, which keeps the last call's contents: calls that overlap on one
+ * device (other streams, other host threads, other contexts) race and must
+ * be ordered by the caller.  The first call for a shape builds its plan on
+ * the host; a call whose shape differs from the previous call's on the
+ * device copies the tables (a few hundred KB) into the scratch on `stream`.
+ * ---------------------------------------------------------------------- */
+#define MGC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mgc_status mgc_compress_noalloc(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                                mgc_dtype dtype, double error_bound, mgc_norm norm,
+                                mgc_mode mode, uint64_t outlier_cap, void* d_out,
+                                size_t out_cap, uint64_t* d_result, void* stream);
+
+/* ------------------------------------------------------------------------
  * Decompression (inverse of the above).
  *
  * mgc_header_info: parses a host copy of the first bytes of a stream (at least

@@ -75,6 +75,9 @@ def _load():
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_uint64, vp, ctypes.c_size_t, vp, ctypes.c_size_t,
                                       vp, c_u64p],
+            "mgc_compress_noalloc": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_uint64, vp, ctypes.c_size_t, vp, vp],
             "mgc_header_info": [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), c_u64p,
                                 ctypes.POINTER(ctypes.c_int), c_u64p, c_szp],
             "mgc_decompress": [vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp],
@@ -228,6 +231,36 @@ def compress_async(x, error_bound: float, norm: str = "linf", mode: str = "rel",
                                 ctypes.c_void_p(out.data_ptr()), out.numel(),
                                 ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                 ctypes.c_void_p(result.data_ptr()), _stream_ptr(dev)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def compress_noalloc(x, error_bound: float, out, result, norm: str = "linf",
+                     mode: str = "rel", outlier_cap: int = 0):
+    """Enqueue a compression that allocates no device memory.
+
+    The library keeps the work buffers and plan tables in a device array of
+    NOALLOC_SCRATCH_BYTES per device; ``out`` (uint8, at least the queried
+    output capacity) and ``result`` (int64, 2 entries: status and stream
+    length, as in compress_async) are the caller's.  Larger arrays raise
+    MgcError (code 3).  Calls that overlap on one device share the scratch
+    and must be ordered by the caller.
+    """
+    _require_gpu(x, "input")
+    if not x.is_contiguous():
+        raise ValueError("input must be contiguous")
+    torch = _torch()
+    dev = x.device.index if x.device.index is not None else torch.cuda.current_device()
+    shape = tuple(x.shape)
+    if result.numel() < 2 or result.dtype != torch.int64 or not result.is_cuda:
+        raise ValueError("result must be an int64 GPU tensor of 2 entries")
+    _check(_load().mgc_compress_noalloc(_ctx(dev), ctypes.c_void_p(x.data_ptr()), len(shape),
+                                        _shape_arg(shape), _dtype_code(x.dtype),
+                                        float(error_bound), _NORM[norm], _MODE[mode],
+                                        outlier_cap, ctypes.c_void_p(out.data_ptr()),
+                                        out.numel(), ctypes.c_void_p(result.data_ptr()),
+                                        _stream_ptr(dev)))
 
 
 def compress(x, error_bound: float, norm: str = "linf", mode: str = "rel",

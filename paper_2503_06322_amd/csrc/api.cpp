@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "host.hpp"
@@ -302,6 +303,48 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
   }
 }
 
+
+// ------------------------------------------------ allocation-free compression
+// Device scratch of mgc_compress_noalloc: the plan tables and every work
+// buffer of one compression, so that call allocates no device memory.  Each
+// device holds its own copy until the process ends.  In host code the
+// array's name is not a device address: the address of a device's copy comes
+// from hipGetSymbolAddress, taken once per device at context creation, and
+// only that pointer reaches kernels and copies.
+static __device__ __align__(256) uint8_t scratch[MGC_NOALLOC_SCRATCH_BYTES];
+
+struct ScratchState {
+  uint8_t* ptr = nullptr;          // this device's copy of the scratch array
+  std::vector<uint64_t> resident;  // shape whose plan tables the copy holds
+};
+struct NoAllocPlan {
+  Plan plan;                       // device pointers into the device's scratch
+  std::vector<uint8_t> image;      // the tables as uploaded (kept alive)
+};
+std::mutex g_scratch_mu;
+std::map<int, ScratchState> g_scratch;  // by device ordinal
+std::map<std::pair<int, std::vector<uint64_t>>, NoAllocPlan> g_noalloc_plans;
+
+// Called with `device` current.
+void scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  ScratchState& st = g_scratch[device];
+  if (st.ptr) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr)
+    fail(MGC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  st.ptr = static_cast<uint8_t*>(p);
+}
+
+// Stage timing is off for the duration of a call (its events are created on
+// demand).
+struct ProfilerPause {
+  Profiler& p;
+  bool was;
+  explicit ProfilerPause(Profiler& prof) : p(prof), was(prof.enabled) { p.enabled = false; }
+  ~ProfilerPause() { p.enabled = was; }
+};
 }  // namespace
 
 extern "C" {
@@ -317,6 +360,7 @@ mgc_status mgc_create(int device, mgc_ctx* out) {
     MGC_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) fail(MGC_EINVAL, "device ordinal out of range");
     MGC_HIP(hipSetDevice(device));
+    scratch_setup(device);
     auto* c = new mgc_ctx_s;
     c->device = device;
     if (hipHostMalloc((void**)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
@@ -497,6 +541,58 @@ mgc_status mgc_compress_blocking(mgc_ctx ctx, const void* d_in, int ndim, const 
         fail(MGC_ERANGE, "error bound below the resolution of the data or the output type");
       default: fail(MGC_EDEVICE, "device status " + std::to_string(r[0]));
     }
+  });
+}
+
+mgc_status mgc_compress_noalloc(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                                mgc_dtype dtype, double error_bound, mgc_norm norm, mgc_mode mode,
+                                uint64_t outlier_cap, void* d_out, size_t out_cap,
+                                uint64_t* d_result, void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (dtype != MGC_F32 && dtype != MGC_F64) fail(MGC_EINVAL, "dtype must be f32 or f64");
+    if (norm != MGC_LINF && norm != MGC_L2) fail(MGC_EINVAL, "norm must be L-inf or L2");
+    if (mode != MGC_REL && mode != MGC_ABS) fail(MGC_EINVAL, "mode must be rel or abs");
+    if (!(error_bound > 0.0) || !std::isfinite(error_bound))
+      fail(MGC_EINVAL, "error bound must be positive and finite");
+    if (ndim < 1) fail(MGC_EINVAL, "ndim must be at least 1");
+    if (ndim > 3) fail(MGC_EUNSUPPORTED, "ndim above 3 is not supported");
+    if (!shape) fail(MGC_EINVAL, "null shape");
+    if (!d_out || !d_result) fail(MGC_EINVAL, "null output pointer");
+    MGC_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchState& st = g_scratch[ctx->device];
+    if (!st.ptr) fail(MGC_EDEVICE, "scratch of the device not set up");
+    std::vector<uint64_t> key(shape, shape + ndim);
+    key.insert(key.begin(), (uint64_t)ndim);
+    auto it = g_noalloc_plans.find({ctx->device, key});
+    if (it == g_noalloc_plans.end()) {
+      NoAllocPlan np;
+      np.plan = build_plan(ndim, shape);
+      np.image = plan_device_image(np.plan, st.ptr);
+      it = g_noalloc_plans.emplace(std::make_pair(ctx->device, key), std::move(np)).first;
+    }
+    const Plan& p = it->second.plan;
+    const uint64_t cap = outlier_cap ? outlier_cap : default_outlier_cap(p.N);
+    const size_t tab_bytes = (it->second.image.size() + 255) & ~size_t(255);
+    Carver meas(nullptr);
+    carve_compress(meas, p, cap);
+    const size_t need = tab_bytes + meas.off;
+    if (need > (size_t)MGC_NOALLOC_SCRATCH_BYTES)
+      fail(MGC_ENOSPC, "the allocation-free compression needs " + std::to_string(need) +
+                           " bytes of device scratch for this shape and outlier capacity; its "
+                           "scratch holds " + std::to_string((size_t)MGC_NOALLOC_SCRATCH_BYTES));
+    if (out_cap < max_stream_bytes(p, cap)) fail(MGC_ENOSPC, "output capacity too small");
+    if (p.N > 0 && !d_in) fail(MGC_EINVAL, "null device pointer");
+    hipStream_t s = as_stream(stream);
+    if (st.resident != key) {
+      MGC_HIP(hipMemcpyAsync(st.ptr, it->second.image.data(), it->second.image.size(),
+                             hipMemcpyHostToDevice, s));
+      st.resident = key;
+    }
+    ProfilerPause pause(ctx->prof);
+    compress_enqueue(ctx, p, d_in, ndim, shape, dtype, error_bound, norm, mode, cap, d_out,
+                     st.ptr + tab_bytes, reinterpret_cast<unsigned long long*>(d_result), s);
   });
 }
 

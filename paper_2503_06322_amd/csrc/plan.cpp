@@ -228,16 +228,13 @@ Plan build_plan(int ndim, const uint64_t* shape) {
 
 // Device block: the operator tables, the bin factors K_l of both norms, then
 // the per-level geometry records (whose table pointers point into the block).
-void upload_plan(Plan& p) {
-  if (p.d_tab) return;
+std::vector<uint8_t> plan_device_image(Plan& p, void* base) {
   const size_t n_tab = p.tab.size();
   const size_t k_off = n_tab, k_len = (size_t)p.L + 1;
   const size_t geo_bytes = sizeof(LevelGeom) * ((size_t)p.L + 1);
   const size_t geo_off = ((n_tab + 2 * k_len) * sizeof(double) + 255) & ~size_t(255);
   const size_t total = geo_off + geo_bytes;
-  void* mem = nullptr;
-  MGC_HIP(hipMalloc(&mem, total));
-  p.d_tab = static_cast<double*>(mem);
+  p.d_tab = static_cast<double*>(base);
   std::vector<uint8_t> host(total, 0);
   if (n_tab) std::memcpy(host.data(), p.tab.data(), n_tab * sizeof(double));
   for (int nrm = 0; nrm < 2; ++nrm) {
@@ -246,12 +243,26 @@ void upload_plan(Plan& p) {
                 k_len * sizeof(double));
     p.d_K[nrm] = p.d_tab + k_off + nrm * k_len;
   }
-  p.d_geo = reinterpret_cast<const LevelGeom*>(static_cast<uint8_t*>(mem) + geo_off);
+  p.d_geo = reinterpret_cast<const LevelGeom*>(static_cast<uint8_t*>(base) + geo_off);
   for (int l = 0; l <= p.L; ++l) {
     const LevelGeom g = p.geom(l);
     std::memcpy(host.data() + geo_off + l * sizeof(LevelGeom), &g, sizeof(LevelGeom));
   }
-  MGC_HIP(hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice));
+  return host;
+}
+
+size_t plan_device_bytes(const Plan& p) {
+  const size_t k_len = (size_t)p.L + 1;
+  const size_t geo_off = ((p.tab.size() + 2 * k_len) * sizeof(double) + 255) & ~size_t(255);
+  return geo_off + sizeof(LevelGeom) * k_len;
+}
+
+void upload_plan(Plan& p) {
+  if (p.d_tab) return;
+  void* mem = nullptr;
+  MGC_HIP(hipMalloc(&mem, plan_device_bytes(p)));
+  const std::vector<uint8_t> host = plan_device_image(p, mem);
+  MGC_HIP(hipMemcpy(mem, host.data(), host.size(), hipMemcpyHostToDevice));
 }
 
 void free_plan(Plan& p) {

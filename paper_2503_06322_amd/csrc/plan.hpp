@@ -3,6 +3,7 @@
 #pragma once
 
 #include <array>
+#include <cstdint>
 #include <vector>
 
 #include "common.hpp"
@@ -45,6 +46,11 @@ struct Plan {
 // Builds the plan (host tables only).  Throws Fail on invalid shapes.
 Plan build_plan(int ndim, const uint64_t* shape);
 void upload_plan(Plan& p);
+// The plan's device block as host bytes, with every device pointer of the
+// plan (tables, bin factors, geometry) set to point into a block at `base`;
+// plan_device_bytes is its size.  upload_plan = allocate, image, copy.
+std::vector<uint8_t> plan_device_image(Plan& p, void* base);
+size_t plan_device_bytes(const Plan& p);
 void free_plan(Plan& p);
 
 
