@@ -123,6 +123,7 @@ size_t max_stream_bytes(const Plan& p, uint64_t cap) {
 struct DecompressWs {
   uint16_t* sym;
   double *gA, *gB;
+  double* coarse;  // dequantised coefficients of levels 0 .. L-2
   void* tables;
   unsigned* status;
 };
@@ -135,6 +136,7 @@ DecompressWs carve_decompress(Carver& c, const Plan& p) {
   w.gB = c.take<double>(n_coarse);
   w.tables = c.take<uint8_t>(decode_tables_bytes());
   w.status = c.take<unsigned>(4);
+  w.coarse = p.L >= 2 ? c.take<double>(p.points(p.L - 2)) : nullptr;
   return w;
 }
 
@@ -264,12 +266,18 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
 }
 
 // levels (optional) receives G_0 .. G_{L-1}, level after level.
+// coarse (optional): FP64 coefficients read for levels 0 .. coarse_top
+// instead of src.
 void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
                           const std::vector<double>& q, double* gA, double* gB, void* d_out,
-                          bool out_f32, hipStream_t s, double* levels = nullptr) {
+                          bool out_f32, hipStream_t s, double* levels = nullptr,
+                          const CoeffSrc* coarse = nullptr, int coarse_top = -1) {
+  auto src_of = [&](int l) -> const CoeffSrc& {
+    return coarse && l <= coarse_top ? *coarse : src;
+  };
   if (p.L == 0) {
     StageScope sc(&ctx->prof, "rec_level0", s);
-    launch_rec_level0(src, p.points(0), q[0], d_out, out_f32, s);
+    launch_rec_level0(src_of(0), p.points(0), q[0], d_out, out_f32, s);
     return;
   }
   std::vector<double*> slot(p.L + 1, gA);
@@ -282,7 +290,7 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
   }
   {
     StageScope sc(&ctx->prof, "rec_level0", s);
-    launch_rec_level0(src, p.points(0), q[0], slot[0], false, s);
+    launch_rec_level0(src_of(0), p.points(0), q[0], slot[0], false, s);
   }
   double* Gprev = slot[0];
   double* F = gB;
@@ -291,13 +299,13 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
     const bool fin = l == p.L;
     {
       StageScope sc(&ctx->prof, fin ? "rec_restrict[finest]" : "rec_restrict", s);
-      launch_rec_restrict(g, src, q[l], F, s);
+      launch_rec_restrict(g, src_of(l), q[l], F, s);
     }
     solve_coarse(ctx, g, F, Gprev, fin, true, s);
     {
       StageScope sc(&ctx->prof, fin ? "rec_interp[finest]" : "rec_interp", s);
       double* dst = levels ? slot[l] : Gprev;
-      launch_rec_interp(F, g, src, q[l], fin ? d_out : (void*)dst, fin && out_f32, s);
+      launch_rec_interp(F, g, src_of(l), q[l], fin ? d_out : (void*)dst, fin && out_f32, s);
       if (!fin) Gprev = dst;
     }
   }
@@ -670,7 +678,25 @@ mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* 
     }
     CoeffSrc src{w.sym, nullptr, reinterpret_cast<const uint64_t*>(in + opos),
                  reinterpret_cast<const int64_t*>(in + oval), (int64_t)h.n_outliers};
-    run_levels_recompose(ctx, p, src, q, w.gA, w.gB, d_out, dt == MGC_F32, s);
+    if (p.L >= 2) {
+      // levels 0 .. L-2 dequantised ahead (escaped values resolved once)
+      LevelBins lb{};
+      lb.n = p.L - 1;
+      for (int l = 0; l < lb.n; ++l) {
+        lb.off[l] = p.lv[l].off;
+        lb.q[l] = q[l];
+      }
+      const int64_t m = p.points(p.L - 2);
+      {
+        StageScope st(&ctx->prof, "dequant_coarse", s);
+        launch_dequant_prefix(src, m, lb, w.coarse, s);
+      }
+      const CoeffSrc coarse{nullptr, w.coarse, nullptr, nullptr, 0};
+      run_levels_recompose(ctx, p, src, q, w.gA, w.gB, d_out, dt == MGC_F32, s, nullptr,
+                           &coarse, p.L - 2);
+    } else {
+      run_levels_recompose(ctx, p, src, q, w.gA, w.gB, d_out, dt == MGC_F32, s);
+    }
     MGC_HIP(hipGetLastError());
     unsigned st = 0;
     sync_read(ctx, ctx->pinned, w.status, sizeof(unsigned), s);

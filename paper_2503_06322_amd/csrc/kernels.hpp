@@ -82,6 +82,15 @@ void launch_rec_restrict(const LevelGeom& g, const CoeffSrc& src, double q, doub
 // Recomposition: G_l = P Gc + c_l (out in FP32 or FP64).
 void launch_rec_interp(const double* Gc, const LevelGeom& g, const CoeffSrc& src, double q,
                        void* out, bool out_f32, hipStream_t s);
+// Dequantised coefficients of stream positions [0, m) (levels 0 .. n-1 of lb,
+// level l starting at off[l], bin q[l]) into raw, escaped values included.
+struct LevelBins {
+  int64_t off[kMaxLevels + 1];
+  double q[kMaxLevels + 1];
+  int n;
+};
+void launch_dequant_prefix(const CoeffSrc& src, int64_t m, const LevelBins& lb, double* raw,
+                           hipStream_t s);
 void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, bool out_f32,
                        hipStream_t s);
 // Adjoint of recomposition, one level: Gc = P^T g (also copied to Gc_copy,

@@ -2219,6 +2219,45 @@ __global__ __launch_bounds__(256) void k_rec_level0(const CoeffSrc src, int64_t 
     out[i] = (Tout)coeff_at<RAW>(src, i, q);
 }
 
+// Coarse levels of a decompression dequantised ahead of the level loop: the
+// coarse levels hold most escaped values, and a binary search through the
+// outlier list per escaped coefficient (a chain of dependent loads) would
+// make their small launches latency-bound.  The first kernel writes k q_l
+// for every symbol of stream positions [0, m) (0 for the escape symbol), the
+// second the escaped values there; the level kernels then read FP64 values.
+// Same products as the symbol path, so the results are identical.
+__device__ __forceinline__ int level_of(const LevelBins& lb, int64_t pos) {
+  int lo = 0, hi = lb.n - 1;  // largest l with off[l] <= pos
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (lb.off[mid] <= pos) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_dequant_prefix(const uint16_t* __restrict__ sym,
+                                                         int64_t m, const LevelBins lb,
+                                                         double* __restrict__ raw) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const uint16_t v = sym[i];
+    raw[i] = v != 0 ? (double)((int64_t)v - 32768) * lb.q[level_of(lb, i)] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dequant_escapes(const uint64_t* __restrict__ opos,
+                                                          const int64_t* __restrict__ oval,
+                                                          int64_t n_out, int64_t m,
+                                                          const LevelBins lb,
+                                                          double* __restrict__ raw) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_out; i += stride) {
+    const uint64_t p = opos[i];
+    if (p < (uint64_t)m) raw[p] = (double)oval[i] * lb.q[level_of(lb, (int64_t)p)];
+  }
+}
+
 // Small device-to-host transfers: one block copies n bytes into mapped
 // pinned host memory (cheaper than a runtime copy for a few hundred bytes).
 __global__ __launch_bounds__(256) void k_copy_bytes(uint8_t* __restrict__ dst,
@@ -2739,6 +2778,18 @@ void launch_adj_mass(const double* Pv, const double* gl, const LevelGeom& g, dou
   const int64_t rows = g.nf[0] * g.nf[1];
   const dim3 grid((unsigned)((g.nf[2] + 255) / 256), (unsigned)(rows < 65535 ? rows : 65535));
   hipLaunchKernelGGL(k_adj_mass, grid, dim3(256), 0, s, Pv, gl, g, cbar);
+}
+
+void launch_dequant_prefix(const CoeffSrc& src, int64_t m, const LevelBins& lb, double* raw,
+                           hipStream_t s) {
+  if (m <= 0) return;
+  const unsigned b = (unsigned)std::min<int64_t>((m + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_dequant_prefix, dim3(b), dim3(256), 0, s, src.sym, m, lb, raw);
+  if (src.n_out > 0) {
+    const unsigned bo = (unsigned)std::min<int64_t>((src.n_out + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_dequant_escapes, dim3(bo), dim3(256), 0, s, src.opos, src.oval,
+                       src.n_out, m, lb, raw);
+  }
 }
 
 void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, bool out_f32,
