@@ -5,23 +5,34 @@
 //  * histogram: LDS-privatised counts for a central window of symbols (the
 //    quantised coefficients cluster around the dictionary centre), global
 //    atomics for the rest.
-//  * codebook: one workgroup of 1024 threads.  The non-zero keys are
-//    compacted in symbol order and sorted by frequency with a stable LSD
-//    radix sort (wave ballots rank equal digits), giving the (frequency,
-//    symbol) order.  Code lengths follow the two-queue construction (leaves in
-//    that order, internal nodes in creation order, ties to the leaf), computed
-//    in rounds: with m nodes already taken, no node created later can weigh
-//    less than t = (the next node to be paired) + (the smallest remaining),
-//    so every available node of weight <= t is taken in this round by a
-//    parallel merge of the two sorted queues.  The threshold at least doubles
-//    every two rounds, so the round count is logarithmic in the total weight.
+//  * codebook: the non-zero keys are sorted by (frequency, symbol) with a
+//    stable LSD radix sort over many blocks (k_cbs_count / k_cbs_pass; the
+//    batched form sorts in the one workgroup below).  Code lengths follow the
+//    two-queue construction (leaves in that order, internal nodes in creation
+//    order, ties to the leaf), computed by one workgroup of 1024 threads in
+//    rounds: with m nodes already taken, no node created later can weigh less
+//    than t = (the next node to be paired) + (the smallest remaining), so
+//    every available node of weight <= t is taken in this round by a parallel
+//    merge of the two sorted queues.  The threshold at least doubles every
+//    two rounds, so the round count is logarithmic in the total weight.
 //    Depths come from pointer jumping; lengths above 32 halve the
 //    frequencies and rebuild.  Codes are canonical (RFC 1951 construction).
-//  * encode: one wavefront per chunk of C symbols; a wave prefix scan of code
-//    lengths gives each lane its bit offset; codes are OR-ed MSB-first into
-//    the chunk's 32-bit words in LDS, then stored coalesced.
-//  * decode: one thread per chunk; an LDS lookup table resolves codes of up
-//    to 11 bits, longer codes use the canonical limit table.
+//  * chunk lengths and layout: one wavefront per chunk sums the code lengths
+//    (and, in a compression, counts the escape symbols per chunk and lane);
+//    an exclusive scan of the chunk word counts over many blocks gives the
+//    offsets; escaped values are placed in stream order by their rank.
+//  * encode: arrays of at least 8,192 chunks use persistent blocks of 16
+//    wavefronts that keep the packed (rank, length) words of a central symbol
+//    window in LDS (k_encode_win); smaller ones one wavefront per chunk
+//    (k_encode).  A wave prefix scan of code lengths gives each lane its bit
+//    offset; codes are OR-ed MSB-first into the chunk's 32-bit words in LDS,
+//    then stored coalesced.
+//  * decode: one thread per chunk; a 12-bit prefix table in LDS gives the
+//    code length shared by all codes under a prefix (or the lengths to test
+//    against the canonical limits when several share it), and the code's
+//    index in the (length, symbol)-ordered symbol table, also in LDS.  Coded
+//    words reach each lane's LDS ring as whole aligned pieces; decoded
+//    symbols leave as whole 128-byte rows.
 #include "kernels.hpp"
 
 #include <algorithm>

@@ -55,23 +55,23 @@ __device__ __forceinline__ void emit_q(int64_t pos, double c, double r, uint16_t
 
 // Coefficient at stream position pos: raw FP64, or dequantised k * q with
 // escaped values found by binary search in the sorted outlier positions.
+// Value of the escaped coefficient at stream position pos (binary search in
+// the sorted outlier positions; 0 when there is no record).
+__device__ __forceinline__ int64_t escaped_k(const CoeffSrc& s, uint64_t pos) {
+  int64_t lo = 0, hi = s.n_out;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (s.opos[mid] < pos) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < s.n_out && s.opos[lo] == pos) ? s.oval[lo] : 0;
+}
 template <bool RAW>
 __device__ __forceinline__ double coeff_at(const CoeffSrc& s, int64_t pos, double q) {
   if (RAW) return s.raw[pos];
   const uint16_t v = s.sym[pos];
-  int64_t k;
-  if (v != 0) {
-    k = (int64_t)v - 32768;
-  } else {
-    int64_t lo = 0, hi = s.n_out;
-    while (lo < hi) {
-      int64_t mid = (lo + hi) >> 1;
-      if (s.opos[mid] < (uint64_t)pos) lo = mid + 1;
-      else hi = mid;
-    }
-    k = (lo < s.n_out && s.opos[lo] == (uint64_t)pos) ? s.oval[lo] : 0;
-  }
-  return (double)k * q;
+  if (v != 0) return (double)((int)v - 32768) * q;
+  return (double)escaped_k(s, (uint64_t)pos) * q;
 }
 
 // ------------------------------------------------------------ range pass
@@ -263,6 +263,13 @@ __device__ __forceinline__ uint64_t div_magic(uint32_t d) { return (0xFFFFFFFFul
 // Workgroups are dispatched round-robin over the 8 XCDs; giving each XCD a
 // contiguous range of tiles keeps neighbouring tiles (which share halos) in
 // the same L2.  grid = n_tiles rounded up to a multiple of 8.
+// Orders a wavefront's LDS accesses (its lanes exchange values through LDS).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t grid) {
   return (b & 7u) * (grid >> 3) + (b >> 3);
 }
@@ -422,20 +429,10 @@ __device__ __forceinline__ void subband_offsets(const LevelGeom& g, uint32_t (&s
 
 // Dequantised coefficient from an already loaded symbol v at stream position
 // pos (escaped values: binary search in the sorted outlier positions).
+// k q_l for symbol v (k = v - 32768 converts exactly through 32 bits).
 __device__ __forceinline__ double dequant(const CoeffSrc& s, uint32_t v, uint32_t pos, double q) {
-  int64_t k;
-  if (v != 0) {
-    k = (int64_t)v - 32768;
-  } else {
-    int64_t lo = 0, hi = s.n_out;
-    while (lo < hi) {
-      int64_t mid = (lo + hi) >> 1;
-      if (s.opos[mid] < (uint64_t)pos) lo = mid + 1;
-      else hi = mid;
-    }
-    k = (lo < s.n_out && s.opos[lo] == (uint64_t)pos) ? s.oval[lo] : 0;
-  }
-  return (double)k * q;
+  if (v != 0) return (double)((int)v - 32768) * q;
+  return (double)escaped_k(s, pos) * q;
 }
 
 // The separable restriction (P^T M_l along x, then y, then z) of a fine tile
@@ -974,11 +971,9 @@ __global__ __launch_bounds__(256, 4) void k_rec_stream(const LevelGeom g, const 
   uint32_t so[8];
   subband_offsets(g, so);
   const uint32_t lvl = (uint32_t)g.level_off;
-  uint32_t pbase[kStreamNLD][2], pstride[kStreamNLD];
-  int ldst[kStreamNLD];
-  bool yxnew[kStreamNLD];
-#pragma unroll
-  for (int u = 0; u < kStreamNLD; ++u) {
+  // stream position of slot u on a plane that is new (n0) or coarse along z:
+  // base + j0 * stride (j0: the plane's index among the planes of its kind)
+  auto slot_base = [&](int u, bool n0, uint32_t& stride, bool& yx) -> uint32_t {
     const int e = min(u * 256 + tid, n_pl - 1);
     const int y = (int)div_small((uint32_t)e, m2), x = e - y * ext2;
     const uint32_t i1 = lo1 + y, i2 = lo2 + x;
@@ -987,11 +982,26 @@ __global__ __launch_bounds__(256, 4) void k_rec_stream(const LevelGeom g, const 
     const uint32_t j2 = n2 ? (i2 >> 1) : cidx32(i2, nf2);
     const uint32_t ex1 = n1 ? e1n : e1c, ex2 = n2 ? e2n : e2c;
     const int myx = (n1 ? mb1 : 0) | (n2 ? mb2 : 0);
-    pstride[u] = ex1 * ex2;
-    pbase[u][0] = lvl + sel8(so, myx) + j1 * ex2 + j2;
-    pbase[u][1] = lvl + sel8(so, myx | mb0) + j1 * ex2 + j2;
-    yxnew[u] = n1 || n2;
-    ldst[u] = u * 256 + tid < n_pl ? y * E2 + x : -1;
+    stride = ex1 * ex2;
+    yx = n1 || n2;
+    return lvl + sel8(so, n0 ? (myx | mb0) : myx) + j1 * ex2 + j2;
+  };
+  // running positions of the next coarse and the next new plane to load
+  // (planes are loaded once each, in order; the first coarse plane at or
+  // after zs has j0 = (zs + 1) / 2, the first new one j0 = zs / 2)
+  uint32_t pc[kStreamNLD], pn[kStreamNLD], pstride[kStreamNLD];
+  int ldst[kStreamNLD];  // LDS slot | 1 << 30 when new along y or x; -1: none
+#pragma unroll
+  for (int u = 0; u < kStreamNLD; ++u) {
+    uint32_t st;
+    bool yx;
+    const uint32_t bc = slot_base(u, false, st, yx), bn = slot_base(u, true, st, yx);
+    pstride[u] = st;
+    pc[u] = bc + ((zs + 1) >> 1) * st;
+    pn[u] = bn + (zs >> 1) * st;
+    const int e = min(u * 256 + tid, n_pl - 1);
+    const int y = (int)div_small((uint32_t)e, m2), x = e - y * ext2;
+    ldst[u] = u * 256 + tid < n_pl ? ((y * E2 + x) | (yx ? 1 << 30 : 0)) : -1;
   }
   const int xcol = tid & 31, xrow = tid >> 5;
   int xf[5];
@@ -1028,38 +1038,47 @@ __global__ __launch_bounds__(256, 4) void k_rec_stream(const LevelGeom g, const 
     double rv[kStreamNLD];
   };
   PlaneRegs pr[kStreamPF];
-  auto slot_pos = [&](uint32_t z, int u, bool& has) -> uint32_t {
-    const bool n0 = is_new32(z, nf0);
-    const uint32_t j0 = n0 ? (z >> 1) : cidx32(z, nf0);
-    has = ldst[u] >= 0 && (n0 || yxnew[u]);
-    return has ? pbase[u][n0 ? 1 : 0] + j0 * pstride[u] : 0u;
-  };
   auto load_plane = [&](uint32_t z, PlaneRegs& R) {
+    const bool n0 = is_new32(z, nf0);
 #pragma unroll
     for (int u = 0; u < kStreamNLD; ++u) {
-      bool has;
-      const uint32_t pos = slot_pos(z, u, has);
+      const bool has = ldst[u] >= 0 && (n0 || (ldst[u] >> 30) != 0);
+      const uint32_t pos = has ? (n0 ? pn[u] : pc[u]) : 0u;
+      if (n0) pn[u] += pstride[u];
+      else pc[u] += pstride[u];
       if (RAW) R.rv[u] = src.raw[pos];
       else R.sv[u] = src.sym[pos];
     }
   };
   uint32_t next_cz = cz0;
 #pragma unroll
-  for (int d = 0; d < kStreamPF; ++d) load_plane(min<uint32_t>(zs + d, ze), pr[d]);
+  for (int d = 0; d < kStreamPF; ++d)
+    if (zs + d <= ze) load_plane(zs + d, pr[d]);
   for (uint32_t zb = zs; zb <= ze; zb += kStreamPF) {
 #pragma unroll
   for (int d = 0; d < kStreamPF; ++d) {
     const uint32_t zf = zb + d;
     if (zf > ze) break;
     const int s5 = (int)(zf % 5u);
+    const bool n0 = is_new32(zf, nf0);
 #pragma unroll
     for (int u = 0; u < kStreamNLD; ++u) {
       if (ldst[u] < 0) continue;
-      bool has;
-      const uint32_t pos = slot_pos(zf, u, has);
       double v = 0.0;
-      if (has) v = RAW ? pr[d].rv[u] : dequant(src, pr[d].sv[u], pos, q);
-      (&sm.P[0][0])[ldst[u]] = v;
+      if (n0 || (ldst[u] >> 30) != 0) {
+        if (RAW) {
+          v = pr[d].rv[u];
+        } else if (pr[d].sv[u] != 0) {
+          v = (double)((int)pr[d].sv[u] - 32768) * q;
+        } else {
+          // escaped value (rare): its stream position from scratch
+          uint32_t st;
+          bool yx;
+          const uint32_t j0 = n0 ? (zf >> 1) : cidx32(zf, nf0);
+          v = (double)escaped_k(src, slot_base(u, n0, st, yx) + j0 * st) * q;
+        }
+      }
+      (&sm.P[0][0])[ldst[u] & 0xFFFF] = v;
     }
     __syncthreads();
     if (zf + kStreamPF <= ze) load_plane(zf + kStreamPF, pr[d]);
@@ -1098,6 +1117,7 @@ __global__ __launch_bounds__(256, 4) void k_rec_stream(const LevelGeom g, const 
   }
   }
 }
+
 
 // --------------------------------------------- recomposition of one level
 // f = (P^T M_l) c_l: the tile holds the dequantised coefficients (zero at the
@@ -1627,12 +1647,6 @@ __global__ __launch_bounds__(64) void k_thomas_rows(double* __restrict__ x, int6
   thomas_rows_body<SEG>(x, nrows, n, ta, tm, tc, sub, blockIdx.x);
 }
 
-// Orders a wavefront's LDS accesses (its lanes exchange values through LDS).
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Partitioned sweeps for coarse grids above the LDS-tile limit.  A line is
 // cut into segments whose values stay in registers from their load to their
