@@ -55,6 +55,12 @@ __device__ __forceinline__ void emit_q(int64_t pos, double c, double r, uint16_t
 
 // Coefficient at stream position pos: raw FP64, or dequantised k * q with
 // escaped values found by binary search in the sorted outlier positions.
+// w0 a + w1 b as one multiply and one fused multiply-add (every variant of
+// the interpolation uses this exact form, so their results agree bit for bit)
+__device__ __forceinline__ double lin2(double w0, double a, double w1, double b) {
+  return fma(w0, a, w1 * b);
+}
+
 // Value of the escaped coefficient at stream position pos (binary search in
 // the sorted outlier positions; 0 when there is no record).
 __device__ __forceinline__ int64_t escaped_k(const CoeffSrc& s, uint64_t pos) {
@@ -472,7 +478,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
         const V* row = tile + (z * E1 + y) * E2;
         double acc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 5; ++d) acc += w[d] * (double)row[f[d]];
+        for (int d = 0; d < 5; ++d) acc = fma(w[d], (double)row[f[d]], acc);
         A[(z * E1 + y) * TX + cx] = acc;
       }
     }
@@ -498,7 +504,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
         const double* col = A + z * E1 * TX + cx;
         double acc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 5; ++d) acc += w[d] * col[f[d] * TX];
+        for (int d = 0; d < 5; ++d) acc = fma(w[d], col[f[d] * TX], acc);
         B[(z * TY + cy) * TX + cx] = acc;
       }
     }
@@ -513,7 +519,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
         double acc = 0.0;
 #pragma unroll
         for (int d = 0; d < 5; ++d)
-          acc += tb.W1(cy, d) * A[(z * E1 + min(max(p + d - 2, 0), last)) * TX + cx];
+          acc = fma(tb.W1(cy, d), A[(z * E1 + min(max(p + d - 2, 0), last)) * TX + cx], acc);
         B[(z * TY + cy) * TX + cx] = acc;
       }
     }
@@ -532,7 +538,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
           double acc = 0.0;
 #pragma unroll
           for (int d = 0; d < 5; ++d)
-            acc += tb.W0(cz, d) * B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx];
+            acc = fma(tb.W0(cz, d), B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx], acc);
           const size_t o = ((size_t)(tl.c0[0] + cz) * tl.nc[1] + tl.c0[1] + cy) * tl.nc[2] +
                            tl.c0[2] + cx;
           fout[o] = acc;
@@ -550,7 +556,7 @@ __device__ void restrict_tile(const V* tile, double* A, double* B, const Tile& t
           double acc = 0.0;
 #pragma unroll
           for (int d = 0; d < 5; ++d)
-            acc += tb.W0(cz, d) * B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx];
+            acc = fma(tb.W0(cz, d), B[(min(max(p + d - 2, 0), last) * TY + cy) * TX + cx], acc);
           fout[ro + cx] = acc;
           if (fout2) fout2[ro + cx] = acc;
         }
@@ -605,23 +611,23 @@ __device__ __forceinline__ void lerp_cells(const Tin* tile, const Tile& tl, cons
     const double c000 = T(p0, p1, p2), c001 = T(p0, p1, s2), c010 = T(p0, s1, p2),
                  c011 = T(p0, s1, s2), c100 = T(s0, p1, p2), c101 = T(s0, p1, s2),
                  c110 = T(s0, s1, p2), c111 = T(s0, s1, s2);
-    const double ix00 = wx0 * c000 + wx1 * c001, ix01 = wx0 * c010 + wx1 * c011;
-    const double ix10 = wx0 * c100 + wx1 * c101, ix11 = wx0 * c110 + wx1 * c111;
+    const double ix00 = lin2(wx0, c000, wx1, c001), ix01 = lin2(wx0, c010, wx1, c011);
+    const double ix10 = lin2(wx0, c100, wx1, c101), ix11 = lin2(wx0, c110, wx1, c111);
     const uint32_t base_cc = (J0 * e1c + J1) * e2c + J2, base_cn = (J0 * e1c + J1) * e2n + J2;
     const uint32_t base_nc = (J0 * e1n + J1) * e2c + J2, base_nn = (J0 * e1n + J1) * e2n + J2;
     if (h2) emit(lvl + tb.soff[m2] + base_cn, T(p0, p1, q2) - ix00);
-    if (h1) emit(lvl + tb.soff[m1] + base_nc, T(p0, q1, p2) - (wy0 * c000 + wy1 * c010));
+    if (h1) emit(lvl + tb.soff[m1] + base_nc, T(p0, q1, p2) - (lin2(wy0, c000, wy1, c010)));
     if (h1 && h2)
-      emit(lvl + tb.soff[m1 | m2] + base_nn, T(p0, q1, q2) - (wy0 * ix00 + wy1 * ix01));
-    if (h0) emit(lvl + tb.soff[m0] + base_cc, T(q0, p1, p2) - (wz0 * c000 + wz1 * c100));
+      emit(lvl + tb.soff[m1 | m2] + base_nn, T(p0, q1, q2) - (lin2(wy0, ix00, wy1, ix01)));
+    if (h0) emit(lvl + tb.soff[m0] + base_cc, T(q0, p1, p2) - (lin2(wz0, c000, wz1, c100)));
     if (h0 && h2)
-      emit(lvl + tb.soff[m0 | m2] + base_cn, T(q0, p1, q2) - (wz0 * ix00 + wz1 * ix10));
+      emit(lvl + tb.soff[m0 | m2] + base_cn, T(q0, p1, q2) - (lin2(wz0, ix00, wz1, ix10)));
     if (h0 && h1)
       emit(lvl + tb.soff[m0 | m1] + base_nc,
-           T(q0, q1, p2) - (wz0 * (wy0 * c000 + wy1 * c010) + wz1 * (wy0 * c100 + wy1 * c110)));
+           T(q0, q1, p2) - (lin2(wz0, lin2(wy0, c000, wy1, c010), wz1, lin2(wy0, c100, wy1, c110))));
     if (h0 && h1 && h2)
       emit(lvl + tb.soff[m0 | m1 | m2] + base_nn,
-           T(q0, q1, q2) - (wz0 * (wy0 * ix00 + wy1 * ix01) + wz1 * (wy0 * ix10 + wy1 * ix11)));
+           T(q0, q1, q2) - (lin2(wz0, lin2(wy0, ix00, wy1, ix01), wz1, lin2(wy0, ix10, wy1, ix11))));
   }
 }
 
@@ -712,7 +718,8 @@ __global__ __launch_bounds__(256) void k_dec_level(const Tin* __restrict__ G, co
 constexpr int kStreamSY = 8, kStreamSX = 32;
 constexpr int kStreamE1 = 2 * kStreamSY + 3, kStreamE2 = 2 * kStreamSX + 3;
 constexpr int kStreamNLD = (kStreamE1 * kStreamE2 + 255) / 256;
-constexpr int kStreamPF = 2;  // fine planes whose loads are in flight
+constexpr int kStreamPF = 2;     // fine planes whose loads are in flight (recomposition)
+constexpr int kDecStreamPF = 1;  // (decomposition: registers go to the cells)
 // levels with fewer fine points use the tiled kernel (measured faster there)
 constexpr int64_t kStreamMinPoints = int64_t(1) << 25;
 // Recomposition's restriction (one value per coarse node from the dequantised
@@ -727,7 +734,6 @@ struct StreamSmem {
   double wl1[kStreamE1], wr1[kStreamE1], wl2[kStreamE2], wr2[kStreamE2];
   double W1[kStreamSY][5], W2[kStreamSX][5];
   int P1[kStreamSY], P2[kStreamSX];
-  uint32_t soff[8];
 };
 
 template <typename Tin, bool QUANT>
@@ -774,7 +780,6 @@ __global__ __launch_bounds__(256, 4) void k_dec_stream(const Tin* __restrict__ G
   for (int i = tid; i < 5 * tkx; i += 256) sm.W2[i / 5][i % 5] = g.ax[2].W[5 * c0x + i];
   for (int i = tid; i < tky; i += 256) sm.P1[i] = (int)(cpos32(c0y + i, nf1) - lo1);
   for (int i = tid; i < tkx; i += 256) sm.P2[i] = (int)(cpos32(c0x + i, nf2) - lo2);
-  if (tid < 8) sm.soff[tid] = (uint32_t)(tid == 0 ? 0 : g.sub_off[tid]);
   // the lane's values of a plane: offsets inside the plane and LDS slots
   const int n_pl = ext1 * ext2;
   const uint64_t m2 = div_magic((uint32_t)ext2);
@@ -788,10 +793,10 @@ __global__ __launch_bounds__(256, 4) void k_dec_stream(const Tin* __restrict__ G
     ldst[u] = u * 256 + tid < n_pl ? y * E2 + x : -1;
   }
   const size_t plane = (size_t)nf1 * nf2;
-  // kStreamPF planes of loads in flight, one register set per plane in
-  // fixed roles (the plane loop is unrolled by kStreamPF); a set is reloaded
-  // with the plane kStreamPF ahead right after it has gone to LDS.
-  Tin pv[kStreamPF][kStreamNLD];
+  // kDecStreamPF planes of loads in flight, one register set per plane in
+  // fixed roles (the plane loop is unrolled by kDecStreamPF); a set is reloaded
+  // with the plane kDecStreamPF ahead right after it has gone to LDS.
+  Tin pv[kDecStreamPF][kStreamNLD];
   auto load_plane = [&](uint32_t z, Tin (&v)[kStreamNLD]) {
     const Tin* src = G + (size_t)z * plane;
 #pragma unroll
@@ -834,26 +839,33 @@ __global__ __launch_bounds__(256, 4) void k_dec_stream(const Tin* __restrict__ G
   const uint32_t lvl = (uint32_t)g.level_off;
   const int m0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, m1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
             m2b = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
+  // first stream position of each subband of the level (uniform)
+  uint32_t so[8];
+  subband_offsets(g, so);
+  const uint32_t sb_x = lvl + sel8(so, m2b), sb_y = lvl + sel8(so, m1),
+                 sb_yx = lvl + sel8(so, m1 | m2b), sb_z = lvl + sel8(so, m0),
+                 sb_zx = lvl + sel8(so, m0 | m2b), sb_zy = lvl + sel8(so, m0 | m1),
+                 sb_zyx = lvl + sel8(so, m0 | m1 | m2b);
   uint32_t next_cz = cz0;
 #pragma unroll
-  for (int d = 0; d < kStreamPF; ++d) load_plane(min<uint32_t>(zs + d, ze), pv[d]);
-  for (uint32_t zb = zs; zb <= ze; zb += kStreamPF) {
+  for (int d = 0; d < kDecStreamPF; ++d) load_plane(min<uint32_t>(zs + d, ze), pv[d]);
+  for (uint32_t zb = zs; zb <= ze; zb += kDecStreamPF) {
 #pragma unroll
-  for (int d = 0; d < kStreamPF; ++d) {
+  for (int d = 0; d < kDecStreamPF; ++d) {
     const uint32_t zf = zb + d;
     if (zf > ze) break;
     const int s3 = (int)(zf % 3u), s5 = (int)(zf % 5u);
 #pragma unroll
     for (int u = 0; u < kStreamNLD; ++u)
       if (ldst[u] >= 0) (&sm.raw[s3][0][0])[ldst[u]] = pv[d][u];
-    if (zf + kStreamPF <= ze) load_plane(zf + kStreamPF, pv[d]);
+    if (zf + kDecStreamPF <= ze) load_plane(zf + kDecStreamPF, pv[d]);
     __syncthreads();
     if (xcol < tkx) {
       for (int y = xrow; y < ext1; y += 8) {
         const Tin* row = sm.raw[s3][y];
         double acc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 5; ++d) acc += xw[d] * (double)row[xf[d]];
+        for (int d = 0; d < 5; ++d) acc = fma(xw[d], (double)row[xf[d]], acc);
         sm.X[y][xcol] = acc;
       }
     }
@@ -861,7 +873,7 @@ __global__ __launch_bounds__(256, 4) void k_dec_stream(const Tin* __restrict__ G
     if (own) {
       double acc = 0.0;
 #pragma unroll
-      for (int d = 0; d < 5; ++d) acc += yw[d] * sm.X[yf[d]][ocx];
+      for (int d = 0; d < 5; ++d) acc = fma(yw[d], sm.X[yf[d]][ocx], acc);
       sm.Y[s5][ocy][ocx] = acc;
     }
     __syncthreads();
@@ -876,7 +888,7 @@ __global__ __launch_bounds__(256, 4) void k_dec_stream(const Tin* __restrict__ G
 #pragma unroll
         for (int d = 0; d < 5; ++d) {
           const int zz = min(max((int)P0 + d - 2, 0), (int)nf0 - 1);
-          acc += W0[d] * sm.Y[zz % 5][ocy][ocx];
+          acc = fma(W0[d], sm.Y[zz % 5][ocy][ocx], acc);
         }
         fout[((size_t)J0 * nc1 + J1) * nc2 + J2] = acc;
       }
@@ -888,27 +900,27 @@ __global__ __launch_bounds__(256, 4) void k_dec_stream(const Tin* __restrict__ G
         const double c000 = T(r0, p1, p2), c001 = T(r0, p1, s2), c010 = T(r0, s1, p2),
                      c011 = T(r0, s1, s2), c100 = T(rs, p1, p2), c101 = T(rs, p1, s2),
                      c110 = T(rs, s1, p2), c111 = T(rs, s1, s2);
-        const double ix00 = wx0 * c000 + wx1 * c001, ix01 = wx0 * c010 + wx1 * c011;
-        const double ix10 = wx0 * c100 + wx1 * c101, ix11 = wx0 * c110 + wx1 * c111;
+        const double ix00 = lin2(wx0, c000, wx1, c001), ix01 = lin2(wx0, c010, wx1, c011);
+        const double ix10 = lin2(wx0, c100, wx1, c101), ix11 = lin2(wx0, c110, wx1, c111);
         const uint32_t base_cc = (J0 * e1c + J1) * e2c + J2, base_cn = (J0 * e1c + J1) * e2n + J2;
         const uint32_t base_nc = (J0 * e1n + J1) * e2c + J2, base_nn = (J0 * e1n + J1) * e2n + J2;
         auto emit = [&](uint32_t pos, double v) {
           if (QUANT) emit_q(pos, v, r, sym, ob, status);
           else raw[pos] = v;
         };
-        if (h2) emit(lvl + sm.soff[m2b] + base_cn, T(r0, p1, q2) - ix00);
-        if (h1) emit(lvl + sm.soff[m1] + base_nc, T(r0, q1, p2) - (wy0 * c000 + wy1 * c010));
+        if (h2) emit(sb_x + base_cn, T(r0, p1, q2) - ix00);
+        if (h1) emit(sb_y + base_nc, T(r0, q1, p2) - (lin2(wy0, c000, wy1, c010)));
         if (h1 && h2)
-          emit(lvl + sm.soff[m1 | m2b] + base_nn, T(r0, q1, q2) - (wy0 * ix00 + wy1 * ix01));
-        if (h0) emit(lvl + sm.soff[m0] + base_cc, T(rq, p1, p2) - (wz0 * c000 + wz1 * c100));
+          emit(sb_yx + base_nn, T(r0, q1, q2) - (lin2(wy0, ix00, wy1, ix01)));
+        if (h0) emit(sb_z + base_cc, T(rq, p1, p2) - (lin2(wz0, c000, wz1, c100)));
         if (h0 && h2)
-          emit(lvl + sm.soff[m0 | m2b] + base_cn, T(rq, p1, q2) - (wz0 * ix00 + wz1 * ix10));
+          emit(sb_zx + base_cn, T(rq, p1, q2) - (lin2(wz0, ix00, wz1, ix10)));
         if (h0 && h1)
-          emit(lvl + sm.soff[m0 | m1] + base_nc,
-               T(rq, q1, p2) - (wz0 * (wy0 * c000 + wy1 * c010) + wz1 * (wy0 * c100 + wy1 * c110)));
+          emit(sb_zy + base_nc,
+               T(rq, q1, p2) - (lin2(wz0, lin2(wy0, c000, wy1, c010), wz1, lin2(wy0, c100, wy1, c110))));
         if (h0 && h1 && h2)
-          emit(lvl + sm.soff[m0 | m1 | m2b] + base_nn,
-               T(rq, q1, q2) - (wz0 * (wy0 * ix00 + wy1 * ix01) + wz1 * (wy0 * ix10 + wy1 * ix11)));
+          emit(sb_zyx + base_nn,
+               T(rq, q1, q2) - (lin2(wz0, lin2(wy0, ix00, wy1, ix01), wz1, lin2(wy0, ix10, wy1, ix11))));
       }
       ++next_cz;
     }
@@ -1087,7 +1099,7 @@ __global__ __launch_bounds__(256, 4) void k_rec_stream(const LevelGeom g, const 
         const double* row = sm.P[y];
         double acc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 5; ++d) acc += xw[d] * row[xf[d]];
+        for (int d = 0; d < 5; ++d) acc = fma(xw[d], row[xf[d]], acc);
         sm.X[y][xcol] = acc;
       }
     }
@@ -1095,7 +1107,7 @@ __global__ __launch_bounds__(256, 4) void k_rec_stream(const LevelGeom g, const 
     if (own) {
       double acc = 0.0;
 #pragma unroll
-      for (int d = 0; d < 5; ++d) acc += yw[d] * sm.X[yf[d]][ocx];
+      for (int d = 0; d < 5; ++d) acc = fma(yw[d], sm.X[yf[d]][ocx], acc);
       sm.Y[s5][ocy][ocx] = acc;
     }
     __syncthreads();
@@ -1108,7 +1120,7 @@ __global__ __launch_bounds__(256, 4) void k_rec_stream(const LevelGeom g, const 
 #pragma unroll
         for (int d = 0; d < 5; ++d) {
           const int zz = min(max((int)P0 + d - 2, 0), (int)nf0 - 1);
-          acc += W0[d] * sm.Y[zz % 5][ocy][ocx];
+          acc = fma(W0[d], sm.Y[zz % 5][ocy][ocx], acc);
         }
         fout[((size_t)J0 * nc1 + J1) * nc2 + J2] = acc;
       }
@@ -1325,8 +1337,8 @@ __device__ __forceinline__ void rec_interp_body(const double* __restrict__ Gc, c
     const double c000 = G(cz, cy, cx), c001 = G(cz, cy, c1), c010 = G(cz, b1, cx),
                  c011 = G(cz, b1, c1), c100 = G(a1, cy, cx), c101 = G(a1, cy, c1),
                  c110 = G(a1, b1, cx), c111 = G(a1, b1, c1);
-    const double ix00 = wx0 * c000 + wx1 * c001, ix01 = wx0 * c010 + wx1 * c011;
-    const double ix10 = wx0 * c100 + wx1 * c101, ix11 = wx0 * c110 + wx1 * c111;
+    const double ix00 = lin2(wx0, c000, wx1, c001), ix01 = lin2(wx0, c010, wx1, c011);
+    const double ix10 = lin2(wx0, c100, wx1, c101), ix11 = lin2(wx0, c110, wx1, c111);
     auto coef = [&](int k) -> double {
       if (SRC == 2) return 0.0;
       return SRC == 1 ? crv[u][k] : dequant(src, csv[u][k], cpos[u][k], q);
@@ -1337,16 +1349,16 @@ __device__ __forceinline__ void rec_interp_body(const double* __restrict__ Gc, c
     };
     put(P0, P1, P2, c000);
     if (h2) put(P0, P1, P2 + 1, ix00 + coef(1));
-    if (h1) put(P0, P1 + 1, P2, (wy0 * c000 + wy1 * c010) + coef(2));
-    if (h1 && h2) put(P0, P1 + 1, P2 + 1, (wy0 * ix00 + wy1 * ix01) + coef(3));
-    if (h0) put(P0 + 1, P1, P2, (wz0 * c000 + wz1 * c100) + coef(4));
-    if (h0 && h2) put(P0 + 1, P1, P2 + 1, (wz0 * ix00 + wz1 * ix10) + coef(5));
+    if (h1) put(P0, P1 + 1, P2, (lin2(wy0, c000, wy1, c010)) + coef(2));
+    if (h1 && h2) put(P0, P1 + 1, P2 + 1, (lin2(wy0, ix00, wy1, ix01)) + coef(3));
+    if (h0) put(P0 + 1, P1, P2, (lin2(wz0, c000, wz1, c100)) + coef(4));
+    if (h0 && h2) put(P0 + 1, P1, P2 + 1, (lin2(wz0, ix00, wz1, ix10)) + coef(5));
     if (h0 && h1)
       put(P0 + 1, P1 + 1, P2,
-          (wz0 * (wy0 * c000 + wy1 * c010) + wz1 * (wy0 * c100 + wy1 * c110)) + coef(6));
+          (lin2(wz0, lin2(wy0, c000, wy1, c010), wz1, lin2(wy0, c100, wy1, c110))) + coef(6));
     if (h0 && h1 && h2)
       put(P0 + 1, P1 + 1, P2 + 1,
-          (wz0 * (wy0 * ix00 + wy1 * ix01) + wz1 * (wy0 * ix10 + wy1 * ix11)) + coef(7));
+          (lin2(wz0, lin2(wy0, ix00, wy1, ix01), wz1, lin2(wy0, ix10, wy1, ix11))) + coef(7));
   }
 }
 
