@@ -258,9 +258,16 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes,
  *   MGC_TUNE_DEC_F32 / MGC_TUNE_DEC_F64 - tile shape (coarse outputs, z y x)
  *   of the three-axis decomposition kernel on FP32 / FP64 input: f32
  *   {4x8x16, 8x8x8, 4x4x16, 2x8x32}, f64 {4x8x8, 4x4x16, 2x8x16, 8x8x8};
- *   MGC_TUNE_THOMAS_STRIDED - values in flight per line {8, 4, 16};
- *   MGC_TUNE_THOMAS_ROWS - LDS segment of the contiguous sweep {32, 16, 64}.
- *   Every candidate gives bit-identical output.
+ *   every tile candidate gives bit-identical output.
+ *   MGC_TUNE_THOMAS_STRIDED / MGC_TUNE_THOMAS_ROWS - tridiagonal sweeps of
+ *   the strided axes / the contiguous axis: candidate 0 (the default, kept
+ *   by the autotuner) solves every coarse grid too large for one workgroup
+ *   with partitioned sweeps where its lines fit (512 values on strided axes,
+ *   1024 on the contiguous one) and with serial sweeps otherwise (16 values
+ *   in flight per line / 16-value LDS segments); candidates 1 and 2 force
+ *   serial sweeps everywhere (8 / 4 values in flight; 32 / 8-value
+ *   segments), whose results agree with candidate 0 up to rounding.  Batched
+ *   and plain calls under the same candidates give identical streams.
  * mgc_tuning_info: the candidate count of a kind and the choice used by the
  *   context's most recent batched call (-1 before any).
  * ---------------------------------------------------------------------- */

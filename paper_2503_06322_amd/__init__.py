@@ -25,7 +25,8 @@ __all__ = ["MgcError", "library_path", "compress", "compress_async", "decompress
            "recompose_adjoint", "recompose_levels", "Recompose", "huffman_encode",
            "huffman_decode", "header_info", "profile_enable", "profile_reset", "profile_read",
            "compress_query", "transform_query", "batch_query", "Batch", "compress_batched",
-           "set_tuning", "tuning_info", "set_decoder", "decoder_info"]
+           "set_tuning", "tuning_info", "set_decoder", "decoder_info", "compress_noalloc",
+           "NOALLOC_SCRATCH_BYTES"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmgc.so")

@@ -204,9 +204,9 @@ void sync_read(mgc_ctx ctx, void* host, const void* dev, size_t n, hipStream_t s
 
 // The solves on one level's coarse grid x: axis 2, then 1, then 0 (the
 // active ones), sub - x formed after the last.  One launch when the grid fits
-// in LDS, two (x-y planes, then axis 0) when its planes do, else one per
-// axis with the tuned candidates (the caller's forced ones when tuned is
-// set).
+// in LDS (serial sweeps), else one per axis: partitioned sweeps where the
+// lines fit, serial ones otherwise or when a tuning candidate forces them
+// (the caller's forced candidates when use_tuning is set).
 void solve_coarse(mgc_ctx ctx, const LevelGeom& g, double* x, const double* sub, bool fin,
                   bool use_tuning, hipStream_t s) {
   if (thomas_grid_fits(g)) {
@@ -218,18 +218,6 @@ void solve_coarse(mgc_ctx ctx, const LevelGeom& g, double* x, const double* sub,
     return use_tuning ? tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED)
                       : 0;
   };
-  const bool ax0 = g.bit[0] >= 0;
-  if (thomas_planes_fit(g)) {
-    {
-      StageScope sc(&ctx->prof, fin ? "thomas[finest]" : "thomas", s);
-      launch_thomas_planes(x, g, ax0 ? nullptr : sub, s);
-    }
-    if (ax0) {
-      StageScope sc(&ctx->prof, fin ? kThomasFinest[0] : "thomas", s);
-      launch_thomas(0, x, g.nc, g.ax[0], sub, s, cand(0));
-    }
-    return;
-  }
   int last = -1;  // the axis swept last
   for (int axis = 0; axis <= 2 && last < 0; ++axis)
     if (g.bit[axis] >= 0) last = axis;

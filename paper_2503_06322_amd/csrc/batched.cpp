@@ -36,13 +36,20 @@ enum {
 constexpr int kTuneKinds = 4;
 int tune_candidates(int kind) { return kind < 2 ? kDecCands : kThomasCands; }
 
-enum class BK { Zero, Range, Budget, Dec, Thomas, Level0, Hist, Codebook, ChunkW, Scan, OSort,
-                Encode, Header };
+// Candidates the autotuner compares: every tile shape of the decomposition
+// kernel (identical results); the Thomas kinds stay at candidate 0 (the
+// partitioned sweeps wherever lines fit), since candidates 1 and 2 force the
+// serial sweeps, whose results agree only up to rounding.
+int autotune_candidates(int kind) { return kind < 2 ? kDecCands : 1; }
+
+enum class BK { Zero, Range, Budget, Dec, Thomas, ThomasPart, Level0, Hist, Codebook, ChunkW,
+                Scan, OSort, Encode, Header };
 
 struct BLaunch {
   BK kind;
   const char* name;
   int step = 0, axis = 0, D = 0;
+  int part = 0, waves = 1;  // ThomasPart: class (thomas_part_class) and block wavefronts
   bool f32 = false;
   size_t map_off = 0;  // first entry of the launch in the map buffer
   uint32_t nb = 0;     // map entries (blocks)
@@ -185,20 +192,57 @@ void build_launches(BatchPlan& b, const int t[kTuneKinds], std::vector<JobBlock>
       }
     }
     for (int axis = 2; axis >= 0; --axis) {
-      BLaunch L;
-      L.kind = BK::Thomas;
-      L.name = s == 0 ? "b_thomas[finest]" : "b_thomas";
-      L.step = s;
-      L.axis = axis;
-      L.tune = axis == 2 ? TUNE_THOMAS_ROWS : TUNE_THOMAS_STRIDED;
-      mapped(L, [&](int j) -> uint32_t {
+      const int kind = axis == 2 ? TUNE_THOMAS_ROWS : TUNE_THOMAS_STRIDED;
+      // the plain path's choice per array: serial sweeps for grids of the
+      // one-launch grid kernel, for lines too long or when a candidate
+      // forces them; the partitioned class otherwise
+      auto cls = [&](int j) -> int {
         const Plan& p = *b.plans[j];
-        if (!at(j) || p.bit[axis] < 0) return 0;
-        const PlanLevel& v = p.lv[p.L - s];
-        if (axis == 2) return ceil_div(v.nc[0] * v.nc[1], 64);
-        if (axis == 1) return ceil_div(v.nc[0] * v.nc[2], 256);
-        return ceil_div(v.nc[1] * v.nc[2], 256);
-      });
+        if (t[kind] != 0) return kPartNone;
+        const LevelGeom g = p.geom(p.L - s);
+        if (thomas_grid_fits(g)) return kPartNone;
+        const int c = thomas_part_class(axis, g.nc[axis]);
+        return c == kPartScan && g.nc[2] > 256 ? kPartScanLong : c;
+      };
+      {
+        BLaunch L;
+        L.kind = BK::Thomas;
+        L.name = s == 0 ? "b_thomas[finest]" : "b_thomas";
+        L.step = s;
+        L.axis = axis;
+        L.tune = kind;
+        mapped(L, [&](int j) -> uint32_t {
+          const Plan& p = *b.plans[j];
+          if (!at(j) || p.bit[axis] < 0 || cls(j) != kPartNone) return 0;
+          const PlanLevel& v = p.lv[p.L - s];
+          if (axis == 2) return ceil_div(v.nc[0] * v.nc[1], 64);
+          if (axis == 1) return ceil_div(v.nc[0] * v.nc[2], 256);
+          return ceil_div(v.nc[1] * v.nc[2], 256);
+        });
+      }
+      for (int c : {kPart40, kPart64, kPartScan, kPartScanLong}) {
+        if ((axis == 2) != (c >= kPartScan)) continue;
+        BLaunch L;
+        L.kind = BK::ThomasPart;
+        L.name = s == 0 ? "b_thomas[finest]" : "b_thomas";
+        L.step = s;
+        L.axis = axis;
+        L.part = c;
+        const int seg = c == kPart40 ? 40 : 64;
+        for (int j = 0; j < n; ++j) {
+          const Plan& p = *b.plans[j];
+          if (axis < 2 && at(j) && p.bit[axis] >= 0 && cls(j) == c)
+            L.waves = std::max<int>(L.waves, (int)ceil_div(p.lv[p.L - s].nc[axis], seg));
+        }
+        mapped(L, [&](int j) -> uint32_t {
+          const Plan& p = *b.plans[j];
+          if (!at(j) || p.bit[axis] < 0 || cls(j) != c) return 0;
+          const PlanLevel& v = p.lv[p.L - s];
+          if (axis == 2) return std::min<uint32_t>(ceil_div(v.nc[0] * v.nc[1], 4), 1024);
+          if (axis == 1) return ceil_div(v.nc[0] * v.nc[2], 64);
+          return ceil_div(v.nc[1] * v.nc[2], 64);
+        });
+      }
     }
   }
   for (int f = 0; f < 2; ++f) {
@@ -247,6 +291,9 @@ void launch_one(const BatchPlan& b, const BLaunch& L, const int t[kTuneKinds], h
     case BK::Budget: launch_b_budget(J, b.n, s); break;
     case BK::Dec: launch_b_dec_level(J, m, L.nb, L.step, L.D, L.f32, cand, s); break;
     case BK::Thomas: launch_b_thomas(L.axis, J, m, L.nb, L.step, cand, s); break;
+    case BK::ThomasPart:
+      launch_b_thomas_part(L.axis, L.part, L.waves, J, m, L.nb, L.step, s);
+      break;
     case BK::Level0: launch_b_level0(J, m, L.nb, L.f32, s); break;
     case BK::Hist: launch_b_histogram(J, m, L.nb, s); break;
     case BK::Codebook: launch_b_codebook(J, b.n, s); break;
@@ -332,16 +379,17 @@ void upload_jobs(BatchPlan& b, const std::vector<Job>& jobs, hipStream_t s) {
 void autotune(mgc_ctx ctx, BatchPlan& b, hipStream_t s) {
   std::vector<double> best(kTuneKinds, std::numeric_limits<double>::infinity());
   int choice[kTuneKinds] = {0, 0, 0, 0};
-  const int rounds = std::max(kDecCands, kThomasCands);
+  int rounds = 0;
+  for (int k = 0; k < kTuneKinds; ++k) rounds = std::max(rounds, autotune_candidates(k));
   for (int c = 0; c < rounds; ++c) {
     int t[kTuneKinds];
-    for (int k = 0; k < kTuneKinds; ++k) t[k] = std::min(c, tune_candidates(k) - 1);
+    for (int k = 0; k < kTuneKinds; ++k) t[k] = std::min(c, autotune_candidates(k) - 1);
     set_tuning(b, t, s);
     std::vector<double> ms;
     run_eager(ctx, b, s, &ms);  // warm-up
     run_eager(ctx, b, s, &ms);
     for (int k = 0; k < kTuneKinds; ++k)
-      if (c < tune_candidates(k) && ms[k] < best[k]) {
+      if (c < autotune_candidates(k) && ms[k] < best[k]) {
         best[k] = ms[k];
         choice[k] = c;
       }

@@ -57,19 +57,23 @@ void launch_dec_level(const void* G, bool g_is_f32, const LevelGeom& g, double* 
 // cand: kThomasSeg (axis 2) or kThomasU (axes 0, 1) candidate; with cand 0,
 // grids of at most kThomasTilePoints points and lines of at most 540 values
 // use the LDS line tiles instead (all variants give identical results).
+// With cand 0 an axis whose lines fit (thomas_part_class) is solved by the
+// partitioned sweeps, whose results agree with the serial ones up to
+// rounding; the caller decides which grids go this way (a grid small enough
+// for launch_thomas_grid is solved serially in one launch instead).  The
+// batched form makes the same choice per array, so both agree bit for bit.
 constexpr int64_t kThomasTilePoints = int64_t(1) << 22;
 void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
                    const double* sub, hipStream_t s, int cand = 0);
+// Partitioned-sweep class of a line of len values along internal axis `axis`
+// (kPartNone: serial sweeps).  kPartScanLong marks rows of 257..1024 values
+// for the batched form's launches.
+enum { kPartNone = 0, kPart40 = 1, kPart64 = 2, kPartScan = 3, kPartScanLong = 4 };
+int thomas_part_class(int axis, int64_t len);
 // All active axes of a coarse grid small enough for LDS in one launch (the
 // same results as the per-axis launches, axis 2 first; sub as there, applied
 // after the last sweep).  Only for grids with thomas_grid_fits(g).
 bool thomas_grid_fits(const LevelGeom& g);
-// Axes 2 and 1 (those active) of a coarse grid whose x-y planes fit in LDS,
-// one workgroup per plane, the same results as the per-axis launches; axis 0
-// is left to launch_thomas.  sub as there (pass it only when axis 0 is
-// inactive).  Only for grids with thomas_planes_fit(g).
-bool thomas_planes_fit(const LevelGeom& g);
-void launch_thomas_planes(double* x, const LevelGeom& g, const double* sub, hipStream_t s);
 void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStream_t s);
 // Level-0 block: values of G0 (m0 entries) quantised with *rp (sym) or
 // copied (raw); gated like launch_dec_level.
@@ -116,6 +120,11 @@ void launch_b_dec_level(const Job* jobs, const JobBlock* map, uint32_t nb, int s
                         bool f32, int cand, hipStream_t s);
 void launch_b_thomas(int axis, const Job* jobs, const JobBlock* map, uint32_t nb, int step,
                      int cand, hipStream_t s);
+// Partitioned sweeps (class c of thomas_part_class; kPartScan / kPartScanLong
+// on axis 2) of every mapped array; waves = wavefronts per block, at least
+// the largest segment count of the mapped arrays (axes 0 and 1).
+void launch_b_thomas_part(int axis, int c, int waves, const Job* jobs, const JobBlock* map,
+                          uint32_t nb, int step, hipStream_t s);
 void launch_b_level0(const Job* jobs, const JobBlock* map, uint32_t nb, bool f32,
                      hipStream_t s);
 void launch_b_histogram(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s);

@@ -1673,12 +1673,17 @@ __global__ __launch_bounds__(64) void k_thomas_rows(double* __restrict__ x, int6
 // Strided axes: lanes take 64 adjacent lines (coalesced rows of 512 bytes)
 // and the W wavefronts of a block take W consecutive segments of them; the
 // chain of carries runs through LDS.
+// The segmentation depends only on the line length: W = ceil(len / SEG)
+// segments of sl = ceil(len / W) values, so a block of more wavefronts than W
+// (the batched form sizes blocks for its longest line) computes the same
+// values; its spare wavefronts carry identity maps through the chains.
 constexpr int kPartWaves = 8;  // segments (wavefronts) per block at most
 template <int AXIS, int SEG>
-__global__ __launch_bounds__(64 * kPartWaves) void k_thomas_part(
-    double* __restrict__ x, int64_t n0, int64_t n1, int64_t n2, int sl,
-    const double* __restrict__ ta, const double* __restrict__ tm,
-    const double* __restrict__ tc, const double* __restrict__ sub) {
+__device__ __forceinline__ void thomas_part_body(double* __restrict__ x, int64_t n0, int64_t n1,
+                                                 int64_t n2, const double* __restrict__ ta,
+                                                 const double* __restrict__ tm,
+                                                 const double* __restrict__ tc,
+                                                 const double* __restrict__ sub, int64_t blk) {
   __shared__ double cy[kPartWaves][64], cx[kPartWaves][64];
   __shared__ double ca[kPartWaves], cb[kPartWaves];
   const int lane = threadIdx.x & 63;
@@ -1694,12 +1699,17 @@ __global__ __launch_bounds__(64 * kPartWaves) void k_thomas_part(
     len = n0;
     stride = n1 * n2;
   }
-  const int64_t t0 = (int64_t)blockIdx.x * 64 + lane;
+  // segment geometry in scalar registers (wavefront-uniform), so the loops
+  // over a segment branch on scalars
+  const int len32 = (int)len;
+  const int nseg = (len32 + SEG - 1) / SEG;
+  const int sl = __builtin_amdgcn_readfirstlane((len32 + nseg - 1) / nseg);
+  const int64_t t0 = blk * 64 + lane;
   const bool live = t0 < lines;
   const int64_t t = live ? t0 : lines - 1;
   const int64_t base = AXIS == 1 ? (t / n2) * n1 * n2 + t % n2 : t;
   const int64_t s = (int64_t)w * sl;
-  const int ns = (int)max<int64_t>(min<int64_t>(sl, len - s), 0);
+  const int ns = __builtin_amdgcn_readfirstlane(max(min(sl, len32 - w * sl), 0));
   double* p = x + base;
   double v[SEG];
   {
@@ -1768,6 +1778,14 @@ __global__ __launch_bounds__(64 * kPartWaves) void k_thomas_part(
   }
 }
 
+template <int AXIS, int SEG>
+__global__ __launch_bounds__(64 * kPartWaves) void k_thomas_part(
+    double* __restrict__ x, int64_t n0, int64_t n1, int64_t n2, const double* __restrict__ ta,
+    const double* __restrict__ tm, const double* __restrict__ tc,
+    const double* __restrict__ sub) {
+  thomas_part_body<AXIS, SEG>(x, n0, n1, n2, ta, tm, tc, sub, blockIdx.x);
+}
+
 // Contiguous axis: one wavefront per row at a time, lane l holding the row's
 // values l*sl .. l*sl+sl-1 (sl = ceil(n / 64)).  Rows move between HBM and
 // registers through LDS with coalesced loads and stores; the chains of
@@ -1778,11 +1796,14 @@ __device__ __forceinline__ double shfl_up_d(double v, int o) { return __shfl_up(
 __device__ __forceinline__ double shfl_down_d(double v, int o) { return __shfl_down(v, o, 64); }
 
 constexpr int kRowScanWaves = 4;
+// (rows blk * 4 + wavefront, then every nblk * 4 rows)
 template <int K>
-__global__ __launch_bounds__(64 * kRowScanWaves) void k_thomas_rowscan(
-    double* __restrict__ x, int64_t nrows, int64_t n, const double* __restrict__ ta,
-    const double* __restrict__ tm, const double* __restrict__ tc,
-    const double* __restrict__ sub) {
+__device__ __forceinline__ void thomas_rowscan_body(double* __restrict__ x, int64_t nrows,
+                                                    int64_t n, const double* __restrict__ ta,
+                                                    const double* __restrict__ tm,
+                                                    const double* __restrict__ tc,
+                                                    const double* __restrict__ sub, int64_t blk,
+                                                    int64_t nblk) {
   __shared__ double buf[kRowScanWaves][64 * K];
   const int lane = threadIdx.x & 63;
   const int wv = (int)(threadIdx.x >> 6);
@@ -1798,8 +1819,8 @@ __global__ __launch_bounds__(64 * kRowScanWaves) void k_thomas_rowscan(
     fm[k] = tm[i];
     fc[k] = tc[i];
   }
-  const int64_t step = (int64_t)gridDim.x * kRowScanWaves;
-  for (int64_t r = (int64_t)blockIdx.x * kRowScanWaves + wv; r < nrows; r += step) {
+  const int64_t step = nblk * kRowScanWaves;
+  for (int64_t r = blk * kRowScanWaves + wv; r < nrows; r += step) {
     double* row = x + r * n;
     double g[K];
 #pragma unroll
@@ -1886,6 +1907,14 @@ __global__ __launch_bounds__(64 * kRowScanWaves) void k_thomas_rowscan(
     }
     wave_fence();
   }
+}
+
+template <int K>
+__global__ __launch_bounds__(64 * kRowScanWaves) void k_thomas_rowscan(
+    double* __restrict__ x, int64_t nrows, int64_t n, const double* __restrict__ ta,
+    const double* __restrict__ tm, const double* __restrict__ tc,
+    const double* __restrict__ sub) {
+  thomas_rowscan_body<K>(x, nrows, n, ta, tm, tc, sub, blockIdx.x, gridDim.x);
 }
 
 // Whole lines in LDS, one tile per wavefront.  Each wavefront holds 16
@@ -2182,37 +2211,6 @@ __global__ __launch_bounds__(kThomasGridThreads) void k_thomas_grid(
   block_store_lds<NT>(x, gsm, n, sub);
 }
 
-// Axes 2 and 1 of a coarse grid whose x-y planes fit in LDS: one workgroup
-// per plane sweeps its rows, then its columns, in LDS (the order of the
-// per-axis launches, with the same arithmetic); axis 0 follows with the
-// per-axis kernel.  sub - x is formed on the way out when axis 0 is
-// inactive.
-constexpr int kThomasPlaneThreads = 1024;  // all of them load and store the plane
-constexpr int kThomasPlaneMaxLine = 256;    // lines per axis (one thread each)
-constexpr int kThomasPlaneMax = 18432;      // points per plane (144 KiB of FP64)
-
-__global__ __launch_bounds__(kThomasPlaneThreads) void k_thomas_planes(
-    double* __restrict__ x, int n1, int n2, const Thomas3Args a, const double* __restrict__ sub) {
-  constexpr int NT = kThomasPlaneThreads;
-  extern __shared__ double psm[];
-  const int m = n1 * n2;
-  double* xp = x + (size_t)blockIdx.x * m;
-  const double* sp = sub ? sub + (size_t)blockIdx.x * m : nullptr;
-  block_load_lds<NT>(xp, psm, m);
-  __syncthreads();
-  if (a.active[2]) {
-    for (int t = threadIdx.x; t < n1; t += NT)
-      lds_line_sweep(psm + t * n2, n2, 1, a.ta[2], a.tm[2], a.tc[2]);
-    __syncthreads();
-  }
-  if (a.active[1]) {
-    for (int t = threadIdx.x; t < n2; t += NT)
-      lds_line_sweep(psm + t, n1, n2, a.ta[1], a.tm[1], a.tc[1]);
-    __syncthreads();
-  }
-  block_store_lds<NT>(xp, psm, m, sp);
-}
-
 template <typename Tin, bool QUANT>
 __device__ __forceinline__ void level0_body(const Tin* __restrict__ G0, int64_t m0,
                                             uint16_t* __restrict__ sym, double* __restrict__ raw,
@@ -2400,6 +2398,33 @@ __global__ __launch_bounds__(256) void kb_thomas_strided(const Job* __restrict__
   const AxisTab& t = g.ax[AXIS];
   thomas_strided_body<AXIS, U>((step & 1) ? J.gB : J.gA, g.nc[0], g.nc[1], g.nc[2], t.ta, t.tm,
                                t.tc, nullptr, (int64_t)jb.local * 256 + threadIdx.x);
+}
+
+template <int AXIS, int SEG>
+__global__ __launch_bounds__(64 * kPartWaves) void kb_thomas_part(const Job* __restrict__ jobs,
+                                                                   const JobBlock* __restrict__ map,
+                                                                   uint32_t nb, int step) {
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  if (job_skipped(J)) return;
+  const LevelGeom& g = J.geo[J.L - step];
+  const AxisTab& t = g.ax[AXIS];
+  thomas_part_body<AXIS, SEG>((step & 1) ? J.gB : J.gA, g.nc[0], g.nc[1], g.nc[2], t.ta, t.tm,
+                              t.tc, nullptr, jb.local);
+}
+
+template <int K>
+__global__ __launch_bounds__(64 * kRowScanWaves) void kb_thomas_rowscan(
+    const Job* __restrict__ jobs, const JobBlock* __restrict__ map, uint32_t nb, int step) {
+  if (blockIdx.x >= nb) return;
+  const JobBlock jb = map[blockIdx.x];
+  const Job& J = jobs[jb.job];
+  if (job_skipped(J)) return;
+  const LevelGeom& g = J.geo[J.L - step];
+  const AxisTab& t = g.ax[2];
+  thomas_rowscan_body<K>((step & 1) ? J.gB : J.gA, g.nc[0] * g.nc[1], g.nc[2], t.ta, t.tm, t.tc,
+                         nullptr, jb.local, jb.count);
 }
 
 template <typename Tin>
@@ -2647,49 +2672,56 @@ void thomas_rowscan(double* x, const int64_t nc[3], const AxisTab& t, const doub
 template <int AXIS, int SEG>
 void thomas_part_axis(double* x, const int64_t nc[3], const AxisTab& t, const double* sub,
                       hipStream_t s) {
-  const int64_t len = nc[AXIS];
-  const int64_t w = (len + SEG - 1) / SEG;
-  const int sl = (int)((len + w - 1) / w);
+  const int64_t w = (nc[AXIS] + SEG - 1) / SEG;
   const int64_t lines = AXIS == 1 ? nc[0] * nc[2] : nc[1] * nc[2];
   hipLaunchKernelGGL((k_thomas_part<AXIS, SEG>), dim3((unsigned)((lines + 63) / 64)),
-                     dim3((unsigned)(64 * w)), 0, s, x, nc[0], nc[1], nc[2], sl, t.ta, t.tm, t.tc,
+                     dim3((unsigned)(64 * w)), 0, s, x, nc[0], nc[1], nc[2], t.ta, t.tm, t.tc,
                      sub);
 }
-// Partitioned sweeps where the line fits (false otherwise).
-bool thomas_part(int axis, double* x, const int64_t nc[3], const AxisTab& t, const double* sub,
-                 hipStream_t s) {
-  const int64_t len = nc[axis];
+// Partitioned sweeps of class c (thomas_part_class).
+void thomas_part(int axis, int c, double* x, const int64_t nc[3], const AxisTab& t,
+                 const double* sub, hipStream_t s) {
   if (axis == 2) {
+    const int64_t len = nc[2];
     if (len <= 128) thomas_rowscan<2>(x, nc, t, sub, s);
     else if (len <= 256) thomas_rowscan<4>(x, nc, t, sub, s);
     else if (len <= 320) thomas_rowscan<5>(x, nc, t, sub, s);
     else if (len <= 512) thomas_rowscan<8>(x, nc, t, sub, s);
-    else if (len <= 1024) thomas_rowscan<16>(x, nc, t, sub, s);
-    else return false;
-    return true;
+    else thomas_rowscan<16>(x, nc, t, sub, s);
+    return;
   }
-  if (len > 64 * kPartWaves) return false;
-  const bool small = len <= 40 * kPartWaves;
   if (axis == 1) {
-    if (small) thomas_part_axis<1, 40>(x, nc, t, sub, s);
+    if (c == kPart40) thomas_part_axis<1, 40>(x, nc, t, sub, s);
     else thomas_part_axis<1, 64>(x, nc, t, sub, s);
   } else {
-    if (small) thomas_part_axis<0, 40>(x, nc, t, sub, s);
+    if (c == kPart40) thomas_part_axis<0, 40>(x, nc, t, sub, s);
     else thomas_part_axis<0, 64>(x, nc, t, sub, s);
   }
-  return true;
 }
 }  // namespace
+
+int thomas_part_class(int axis, int64_t len) {
+  if (axis == 2) return len <= 1024 ? kPartScan : kPartNone;
+  if (len <= 40 * kPartWaves) return kPart40;
+  if (len <= 64 * kPartWaves) return kPart64;
+  return kPartNone;
+}
 
 void launch_thomas(int axis, double* x, const int64_t nc[3], const AxisTab& t,
                    const double* sub, hipStream_t s, int cand) {
   const int64_t L = nc[axis];
+  if (cand == 0) {
+    const int c = thomas_part_class(axis, L);
+    if (c != kPartNone) {
+      thomas_part(axis, c, x, nc, t, sub, s);
+      return;
+    }
+  }
   if (cand == 0 && L <= kThomasTile2MaxL && nc[0] * nc[1] * nc[2] <= kThomasTilePoints) {
     if (L <= kThomasTile4MaxL) thomas_tiles<4>(axis, x, nc, t, sub, s);
     else thomas_tiles<2>(axis, x, nc, t, sub, s);
     return;
   }
-  if (cand == 0 && thomas_part(axis, x, nc, t, sub, s)) return;
   switch (cand) {
     case 1: thomas_c<1>(axis, x, nc, t, sub, s); break;
     case 2: thomas_c<2>(axis, x, nc, t, sub, s); break;
@@ -2703,34 +2735,6 @@ bool thomas_grid_fits(const LevelGeom& g) {
   for (int k = 0; k < 3; ++k)
     if (g.bit[k] >= 0 && g.nc[k] > kThomasGridMaxLine) return false;
   return true;
-}
-
-bool thomas_planes_fit(const LevelGeom& g) {
-  if (g.bit[1] < 0 && g.bit[2] < 0) return false;  // nothing for the plane kernel
-  // one thread per line, at most one line per thread and axis
-  return g.nc[1] * g.nc[2] <= kThomasPlaneMax && g.nc[1] <= kThomasPlaneMaxLine &&
-         g.nc[2] <= kThomasPlaneMaxLine;
-}
-
-void launch_thomas_planes(double* x, const LevelGeom& g, const double* sub, hipStream_t s) {
-  if (!thomas_planes_fit(g)) throw std::logic_error("launch_thomas_planes: plane exceeds LDS");
-  static bool attr = false;
-  if (!attr) {
-    MGC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_thomas_planes),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(kThomasPlaneMax * sizeof(double))));
-    attr = true;
-  }
-  Thomas3Args a;
-  for (int k = 0; k < 3; ++k) {
-    a.ta[k] = g.ax[k].ta;
-    a.tm[k] = g.ax[k].tm;
-    a.tc[k] = g.ax[k].tc;
-    a.active[k] = g.bit[k] >= 0;
-  }
-  const int m = (int)(g.nc[1] * g.nc[2]);
-  hipLaunchKernelGGL(k_thomas_planes, dim3((unsigned)g.nc[0]), dim3(kThomasPlaneThreads),
-                     (size_t)m * sizeof(double), s, x, (int)g.nc[1], (int)g.nc[2], a, sub);
 }
 
 void launch_thomas_grid(double* x, const LevelGeom& g, const double* sub, hipStream_t s) {
@@ -2907,6 +2911,28 @@ void launch_b_thomas(int axis, const Job* jobs, const JobBlock* map, uint32_t nb
     case 1: b_thomas<1>(axis, jobs, map, nb, step, s); break;
     case 2: b_thomas<2>(axis, jobs, map, nb, step, s); break;
     default: b_thomas<0>(axis, jobs, map, nb, step, s);
+  }
+}
+
+void launch_b_thomas_part(int axis, int c, int waves, const Job* jobs, const JobBlock* map,
+                          uint32_t nb, int step, hipStream_t s) {
+  if (waves < 1 || waves > kPartWaves) throw std::logic_error("launch_b_thomas_part: waves");
+  const dim3 blk((unsigned)(64 * waves));
+  if (axis == 2) {
+    if (c == kPartScanLong)
+      hipLaunchKernelGGL(kb_thomas_rowscan<16>, dim3(nb), dim3(64 * kRowScanWaves), 0, s, jobs,
+                         map, nb, step);
+    else
+      hipLaunchKernelGGL(kb_thomas_rowscan<4>, dim3(nb), dim3(64 * kRowScanWaves), 0, s, jobs,
+                         map, nb, step);
+  } else if (axis == 1) {
+    if (c == kPart40)
+      hipLaunchKernelGGL((kb_thomas_part<1, 40>), dim3(nb), blk, 0, s, jobs, map, nb, step);
+    else hipLaunchKernelGGL((kb_thomas_part<1, 64>), dim3(nb), blk, 0, s, jobs, map, nb, step);
+  } else {
+    if (c == kPart40)
+      hipLaunchKernelGGL((kb_thomas_part<0, 40>), dim3(nb), blk, 0, s, jobs, map, nb, step);
+    else hipLaunchKernelGGL((kb_thomas_part<0, 64>), dim3(nb), blk, 0, s, jobs, map, nb, step);
   }
 }
 
