@@ -1677,6 +1677,12 @@ __global__ __launch_bounds__(64) void k_thomas_rows(double* __restrict__ x, int6
 // segments of sl = ceil(len / W) values, so a block of more wavefronts than W
 // (the batched form sizes blocks for its longest line) computes the same
 // values; its spare wavefronts carry identity maps through the chains.
+// A segment of ns values sits at the end of the SEG register slots; the
+// off = SEG - ns slots before it are padding steps with a = -1, m = 0 in the
+// forward sweep (y stays y, here 0) and c = -1 with y = 0 in the backward
+// sweep (x stays x), both exact, so the sweeps run without per-value
+// branches.  Lane j holds the factors of slot j and the sweeps broadcast
+// them with readlane, so no scalar load sits on the recurrence.
 constexpr int kPartWaves = 8;  // segments (wavefronts) per block at most
 template <int AXIS, int SEG>
 __device__ __forceinline__ void thomas_part_body(double* __restrict__ x, int64_t n0, int64_t n1,
@@ -1684,6 +1690,7 @@ __device__ __forceinline__ void thomas_part_body(double* __restrict__ x, int64_t
                                                  const double* __restrict__ tm,
                                                  const double* __restrict__ tc,
                                                  const double* __restrict__ sub, int64_t blk) {
+  static_assert(SEG <= 64, "one factor slot per lane");
   __shared__ double cy[kPartWaves][64], cx[kPartWaves][64];
   __shared__ double ca[kPartWaves], cb[kPartWaves];
   const int lane = threadIdx.x & 63;
@@ -1699,34 +1706,60 @@ __device__ __forceinline__ void thomas_part_body(double* __restrict__ x, int64_t
     len = n0;
     stride = n1 * n2;
   }
-  // segment geometry in scalar registers (wavefront-uniform), so the loops
-  // over a segment branch on scalars
+  // segment geometry in scalar registers (wavefront-uniform)
   const int len32 = (int)len;
   const int nseg = (len32 + SEG - 1) / SEG;
   const int sl = __builtin_amdgcn_readfirstlane((len32 + nseg - 1) / nseg);
-  const int64_t t0 = blk * 64 + lane;
+  const int s = w * sl;
+  const int ns = __builtin_amdgcn_readfirstlane(max(min(sl, len32 - s), 0));
+  const int off = SEG - ns;
+  // the lane's line as a byte offset from the block's first line (below 2^32
+  // for every grid the library accepts: at most the grid's 8-byte values), so
+  // each row access is a uniform address plus a 32-bit lane offset
+  const int64_t tf = blk * 64;
+  const int64_t t0 = tf + lane;
   const bool live = t0 < lines;
   const int64_t t = live ? t0 : lines - 1;
-  const int64_t base = AXIS == 1 ? (t / n2) * n1 * n2 + t % n2 : t;
-  const int64_t s = (int64_t)w * sl;
-  const int ns = __builtin_amdgcn_readfirstlane(max(min(sl, len32 - w * sl), 0));
-  double* p = x + base;
+  int64_t bf, bt;
+  if (AXIS == 1) {
+    bf = (tf / n2) * n1 * n2 + tf % n2;
+    bt = (t / n2) * n1 * n2 + t % n2;
+  } else {
+    bf = tf;
+    bt = t;
+  }
+  const uint32_t lb = (uint32_t)(bt - bf) * 8u;  // bytes
+  double* const xb = x + bf;
+  // row i of the segment's lines: uniform row address plus the lane's bytes
+  const auto at = [&](double* base, int64_t i) -> double& {
+    return *reinterpret_cast<double*>(reinterpret_cast<char*>(base + i * stride) + lb);
+  };
+  double fa = -1.0, fm = 0.0, fc = -1.0;
+  if (lane >= off && lane < SEG) {
+    const int i = s + lane - off;
+    fa = ta[i];
+    fm = tm[i];
+    fc = tc[i];
+  }
   double v[SEG];
-  {
-    const int64_t hi = max<int64_t>(min<int64_t>(s + ns, len) - 1, 0);
+  if (ns > 0) {
 #pragma unroll
-    for (int k = 0; k < SEG; ++k) v[k] = p[min<int64_t>(s + k, hi) * stride];
+    for (int k = 0; k < SEG; ++k) {
+      v[k] = at(xb, max(s + k - off, s));  // padding slots reload the first value
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) v[k] = 0.0;
   }
   // forward sweep of the segment from a zero start
   double prev = 0.0, A = 1.0;
 #pragma unroll
-  for (int k = 0; k < SEG; ++k)
-    if (k < ns) {
-      const double a = ta[s + k];
-      prev = thomas_fwd(v[k], a, tm[s + k], prev);
-      v[k] = prev;
-      A *= -a;
-    }
+  for (int k = 0; k < SEG; ++k) {
+    const double a = readlane_d(fa, k);
+    prev = thomas_fwd(v[k], a, readlane_d(fm, k), prev);
+    v[k] = prev;
+    A *= -a;
+  }
   cy[w][lane] = prev;
   if (lane == 0) ca[w] = A;
   __syncthreads();
@@ -1735,22 +1768,20 @@ __device__ __forceinline__ void thomas_part_body(double* __restrict__ x, int64_t
     for (int j = 0; j < w; ++j) yin = fma(ca[j], yin, cy[j][lane]);
     double al = 1.0;
 #pragma unroll
-    for (int k = 0; k < SEG; ++k)
-      if (k < ns) {
-        al *= -ta[s + k];
-        v[k] = fma(al, yin, v[k]);
-      }
+    for (int k = 0; k < SEG; ++k) {
+      al *= -readlane_d(fa, k);
+      if (k >= off) v[k] = fma(al, yin, v[k]);  // padding slots stay 0
+    }
   }
   // backward sweep of the segment from a zero end
   double nxt = 0.0, B = 1.0;
 #pragma unroll
-  for (int k = SEG - 1; k >= 0; --k)
-    if (k < ns) {
-      const double c = tc[s + k];
-      nxt = thomas_bwd(v[k], c, nxt);
-      v[k] = nxt;
-      B *= -c;
-    }
+  for (int k = SEG - 1; k >= 0; --k) {
+    const double c = readlane_d(fc, k);
+    nxt = thomas_bwd(v[k], c, nxt);
+    v[k] = nxt;
+    B *= -c;
+  }
   cx[w][lane] = nxt;
   if (lane == 0) cb[w] = B;
   __syncthreads();
@@ -1759,22 +1790,21 @@ __device__ __forceinline__ void thomas_part_body(double* __restrict__ x, int64_t
     for (int j = W - 1; j > w; --j) xin = fma(cb[j], xin, cx[j][lane]);
     double be = 1.0;
 #pragma unroll
-    for (int k = SEG - 1; k >= 0; --k)
-      if (k < ns) {
-        be *= -tc[s + k];
-        v[k] = fma(be, xin, v[k]);
-      }
+    for (int k = SEG - 1; k >= 0; --k) {
+      be *= -readlane_d(fc, k);
+      v[k] = fma(be, xin, v[k]);
+    }
   }
   if (!live) return;
   if (sub) {
-    const double* q = sub + base;
+    double* const qb = const_cast<double*>(sub) + bf;
 #pragma unroll
     for (int k = 0; k < SEG; ++k)
-      if (k < ns) p[(s + k) * stride] = q[(s + k) * stride] - v[k];
+      if (k >= off) at(xb, s + k - off) = at(qb, s + k - off) - v[k];
   } else {
 #pragma unroll
     for (int k = 0; k < SEG; ++k)
-      if (k < ns) p[(s + k) * stride] = v[k];
+      if (k >= off) at(xb, s + k - off) = v[k];
   }
 }
 
