@@ -1812,8 +1812,12 @@ template <int AXIS, int SEG>
 __global__ __launch_bounds__(64 * kPartWaves) void k_thomas_part(
     double* __restrict__ x, int64_t n0, int64_t n1, int64_t n2, const double* __restrict__ ta,
     const double* __restrict__ tm, const double* __restrict__ tc,
-    const double* __restrict__ sub) {
-  thomas_part_body<AXIS, SEG>(x, n0, n1, n2, ta, tm, tc, sub, blockIdx.x);
+    const double* __restrict__ sub, uint32_t nblk) {
+  // Consecutive line windows share their edge cache lines (rows are not
+  // line-aligned), so each XCD takes a contiguous range of windows.
+  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+  if (b >= nblk) return;
+  thomas_part_body<AXIS, SEG>(x, n0, n1, n2, ta, tm, tc, sub, b);
 }
 
 // Contiguous axis: one wavefront per row at a time, lane l holding the row's
@@ -2704,9 +2708,9 @@ void thomas_part_axis(double* x, const int64_t nc[3], const AxisTab& t, const do
                       hipStream_t s) {
   const int64_t w = (nc[AXIS] + SEG - 1) / SEG;
   const int64_t lines = AXIS == 1 ? nc[0] * nc[2] : nc[1] * nc[2];
-  hipLaunchKernelGGL((k_thomas_part<AXIS, SEG>), dim3((unsigned)((lines + 63) / 64)),
-                     dim3((unsigned)(64 * w)), 0, s, x, nc[0], nc[1], nc[2], t.ta, t.tm, t.tc,
-                     sub);
+  const uint32_t nblk = (uint32_t)((lines + 63) / 64);
+  hipLaunchKernelGGL((k_thomas_part<AXIS, SEG>), dim3((nblk + 7u) & ~7u), dim3((unsigned)(64 * w)),
+                     0, s, x, nc[0], nc[1], nc[2], t.ta, t.tm, t.tc, sub, nblk);
 }
 // Partitioned sweeps of class c (thomas_part_class).
 void thomas_part(int axis, int c, double* x, const int64_t nc[3], const AxisTab& t,
