@@ -203,7 +203,10 @@ void sync_read(mgc_ctx ctx, void* host, const void* dev, size_t n, hipStream_t s
 }
 
 // The solves on one level's coarse grid x: axis 2, then 1, then 0 (the
-// active ones), sub - x formed after the last.  One launch when the grid fits
+// active ones); with sub (recomposition) axis 0, then 1, then 2, and sub - x
+// formed by the last, so the subtraction rides on the contiguous-axis sweep,
+// which loads its rows one ahead.  The axes' solves commute (the mass matrix
+// is a Kronecker product of per-axis factors).  One launch when the grid fits
 // in LDS (serial sweeps), else one per axis: partitioned sweeps where the
 // lines fit, serial ones otherwise or when a tuning candidate forces them
 // (the caller's forced candidates when use_tuning is set).
@@ -218,10 +221,13 @@ void solve_coarse(mgc_ctx ctx, const LevelGeom& g, double* x, const double* sub,
     return use_tuning ? tuned(ctx, axis == 2 ? MGC_TUNE_THOMAS_ROWS : MGC_TUNE_THOMAS_STRIDED)
                       : 0;
   };
+  int order[3] = {2, 1, 0};
+  if (sub) order[0] = 0, order[2] = 2;
   int last = -1;  // the axis swept last
-  for (int axis = 0; axis <= 2 && last < 0; ++axis)
-    if (g.bit[axis] >= 0) last = axis;
-  for (int axis = 2; axis >= 0; --axis) {
+  for (int i = 0; i < 3; ++i)
+    if (g.bit[order[i]] >= 0) last = order[i];
+  for (int i = 0; i < 3; ++i) {
+    const int axis = order[i];
     if (g.bit[axis] < 0) continue;
     StageScope sc(&ctx->prof, fin ? kThomasFinest[axis] : "thomas", s);
     launch_thomas(axis, x, g.nc, g.ax[axis], axis == last ? sub : nullptr, s, cand(axis));
@@ -467,7 +473,8 @@ void compress_enqueue(mgc_ctx ctx, const Plan& p, const void* d_in, int ndim,
 }
 
 // Argument checks shared by the compression entry points; returns the plan.
-const Plan& compress_checks(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+extern "C++" {
+static const Plan& compress_checks(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
                             mgc_dtype dtype, double error_bound, mgc_norm norm, mgc_mode mode,
                             uint64_t* cap, const void* d_out, size_t out_cap, const void* d_ws,
                             size_t ws_bytes) {
@@ -487,6 +494,7 @@ const Plan& compress_checks(mgc_ctx ctx, const void* d_in, int ndim, const uint6
   if (p.N > 0 && (!d_in || !d_ws)) fail(MGC_EINVAL, "null device pointer");
   return p;
 }
+}  // extern "C++"
 }  // namespace
 
 mgc_status mgc_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,

@@ -746,7 +746,7 @@ __global__ __launch_bounds__(256, 4) void k_dec_stream(const Tin* __restrict__ G
                                                      unsigned* __restrict__ status,
                                                      const unsigned* __restrict__ gate,
                                                      const int seg, const uint32_t n_blocks) {
-  constexpr int SY = kStreamSY, SX = kStreamSX, E1 = kStreamE1, E2 = kStreamE2;
+  constexpr int SY = kStreamSY, SX = kStreamSX, E2 = kStreamE2;
   __shared__ StreamSmem<Tin> sm;
   const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
   if (b >= n_blocks || gate_closed(gate)) return;
@@ -1854,14 +1854,29 @@ __device__ __forceinline__ void thomas_rowscan_body(double* __restrict__ x, int6
     fc[k] = tc[i];
   }
   const int64_t step = nblk * kRowScanWaves;
-  for (int64_t r = blk * kRowScanWaves + wv; r < nrows; r += step) {
-    double* row = x + r * n;
-    double g[K];
+  // Row r's values (g) and the values it is subtracted from (q) are loaded
+  // one row ahead: the next row's loads are in flight while this row is
+  // solved, and its q loads while the next row is.
+  int64_t r = blk * kRowScanWaves + wv;
+  double g[K], q[K];
+  if (r < nrows) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) g[k] = row[min<int64_t>(lane + 64 * k, n - 1)];
+    for (int k = 0; k < K; ++k) g[k] = x[r * n + min<int64_t>(lane + 64 * k, n - 1)];
+    if (sub) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) q[k] = sub[r * n + min<int64_t>(lane + 64 * k, n - 1)];
+    }
+  }
+  for (; r < nrows; r += step) {
+    double* row = x + r * n;
+    const int64_t rn = r + step;
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (lane + 64 * k < n) b[lane + 64 * k] = g[k];
+    if (rn < nrows) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) g[k] = x[rn * n + min<int64_t>(lane + 64 * k, n - 1)];
+    }
     wave_fence();
     double v[K];
 #pragma unroll
@@ -1930,10 +1945,13 @@ __device__ __forceinline__ void thomas_rowscan_body(double* __restrict__ x, int6
       if (k < ns) b[s + k] = v[k];
     wave_fence();
     if (sub) {
-      const double* q = sub + r * n;
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (lane + 64 * k < n) row[lane + 64 * k] = q[lane + 64 * k] - b[lane + 64 * k];
+        if (lane + 64 * k < n) row[lane + 64 * k] = q[k] - b[lane + 64 * k];
+      if (rn < nrows) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) q[k] = sub[rn * n + min<int64_t>(lane + 64 * k, n - 1)];
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k)
