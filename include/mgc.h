@@ -227,6 +227,47 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes,
                               void* stream);
 
 /* ------------------------------------------------------------------------
+ * Huffman-X: the Huffman pipeline of Algorithm 2 (Section IV-B) as a
+ * standalone lossless codec for byte and integer streams.
+ *
+ * Keys: u8 and u16 values are their own keys (dict 256 / 65536, base 0, no
+ * escapes).  An i32 or i64 value v with base <= v <= base + dict - 2 is key
+ * v - base (2 <= dict <= 65536); every other value is key dict - 1 and is
+ * stored raw after the coded section, in position order.  The keys are coded
+ * by the Huffman stage above (its stream, 8-byte aligned, is the coded
+ * section).  Stream, little-endian: u32 magic 0x5848474D, u8 type, 3 zero
+ * bytes, u32 dict, u32 C, i64 base, u64 n, u64 escaped values, u64 coded
+ * section bytes (0 when n = 0), u64 total bytes, u64 0 (64-byte header);
+ * the coded section; the escaped values (type width each); zero padding to a
+ * multiple of 8 bytes.
+ * mgc_hx_query: workspace bytes and the largest stream for n values.
+ * mgc_hx_compress (asynchronous on `stream`): d_in holds n values of `type`
+ *   (device, naturally aligned).  d_out receives the stream; d_result
+ *   (device, two u64) receives {mgc_status of the run (MGC_OK, or
+ *   MGC_EDEVICE when a device-side check failed), stream bytes}.
+ * mgc_hx_parse_header: fields of a stream header already copied to the host
+ *   (at least 64 bytes); any output pointer may be null.
+ * mgc_hx_decompress: writes the n values to d_out (n and type must match the
+ *   header); BLOCKING (reads the headers first and a status word at the end).
+ *   d_in starts on an 8-byte boundary.
+ * n < 2^32.  Errors: MGC_EINVAL (type, dict, base, C, pointers),
+ * MGC_EUNSUPPORTED (n >= 2^32), MGC_ENOSPC (out_cap, ws_bytes), MGC_EFORMAT
+ * (corrupt or truncated stream), MGC_EDEVICE.
+ * ---------------------------------------------------------------------- */
+typedef enum { MGC_HX_U8 = 0, MGC_HX_U16 = 1, MGC_HX_I32 = 2, MGC_HX_I64 = 3 } mgc_hx_type;
+mgc_status mgc_hx_query(uint64_t n, mgc_hx_type type, uint32_t C, size_t* ws_bytes,
+                        size_t* max_out_bytes);
+mgc_status mgc_hx_compress(mgc_ctx ctx, const void* d_in, uint64_t n, mgc_hx_type type,
+                           uint32_t dict, int64_t base, uint32_t C, void* d_out, size_t out_cap,
+                           void* d_ws, size_t ws_bytes, uint64_t* d_result, void* stream);
+mgc_status mgc_hx_parse_header(const void* h_header, size_t bytes, mgc_hx_type* type,
+                               uint64_t* n, uint32_t* dict, int64_t* base, uint32_t* C,
+                               uint64_t* total);
+mgc_status mgc_hx_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* d_out,
+                             uint64_t n, mgc_hx_type type, void* d_ws, size_t ws_bytes,
+                             void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: n arrays (uneven shapes, dtypes and bounds; one norm and
  * mode) compressed together.  Each stage of Algorithm 1 and Algorithm 2 runs
  * as one launch over the blocks of every array, with the per-array error

@@ -13,6 +13,7 @@ Entry points (same names as the C functions, without the ``mgc_`` prefix):
 ``decompose(x)`` / ``recompose(coeffs, shape, dtype)``   (FP64 coefficients)
 ``compress_batched(tensors, bounds)`` / ``Batch`` (one graph launch for many arrays)
 ``huffman_encode(symbols, C=1024)`` / ``huffman_decode(stream, n)``
+``hx_compress(x, dict, base, C)`` / ``hx_decompress(stream)`` (Huffman-X lossless codec)
 ``header_info(stream)``, ``profile_enable / profile_reset / profile_read``
 """
 from __future__ import annotations
@@ -26,7 +27,7 @@ __all__ = ["MgcError", "library_path", "compress", "compress_async", "decompress
            "huffman_decode", "header_info", "profile_enable", "profile_reset", "profile_read",
            "compress_query", "transform_query", "batch_query", "Batch", "compress_batched",
            "set_tuning", "tuning_info", "set_decoder", "decoder_info", "compress_noalloc",
-           "NOALLOC_SCRATCH_BYTES"]
+           "NOALLOC_SCRATCH_BYTES", "hx_query", "hx_compress", "hx_decompress", "hx_header"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmgc.so")
@@ -95,6 +96,16 @@ def _load():
                                    vp, ctypes.c_size_t, vp, c_u64p],
             "mgc_huffman_decode": [vp, vp, ctypes.c_size_t, vp, ctypes.c_uint64, vp,
                                    ctypes.c_size_t, vp],
+            "mgc_hx_query": [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, c_szp, c_szp],
+            "mgc_hx_compress": [vp, vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
+                                ctypes.c_int64, ctypes.c_uint32, vp, ctypes.c_size_t, vp,
+                                ctypes.c_size_t, vp, vp],
+            "mgc_hx_parse_header": [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), c_u64p,
+                                    ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_uint32), c_u64p],
+            "mgc_hx_decompress": [vp, vp, ctypes.c_size_t, vp, ctypes.c_uint64, ctypes.c_int, vp,
+                                  ctypes.c_size_t, vp],
             "mgc_batch_query": [ctypes.c_int, ctypes.POINTER(ctypes.c_int), c_u64p,
                                 ctypes.POINTER(ctypes.c_int), ctypes.c_uint64, c_szp, c_szp,
                                 c_u64p],
@@ -639,6 +650,87 @@ def huffman_decode(stream, n: int):
                                       ctypes.c_void_p(out.data_ptr()), n,
                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(dev)))
     return out[:n]
+
+
+def _hx_types():
+    torch = _torch()
+    return {torch.uint8: 0, torch.uint16: 1, torch.int32: 2, torch.int64: 3}
+
+
+def hx_query(n: int, dtype, C: int = 1024):
+    """(workspace bytes, largest stream bytes) of the Huffman-X codec."""
+    t = _hx_types().get(dtype)
+    if t is None:
+        raise TypeError("Huffman-X streams hold uint8, uint16, int32 or int64 values")
+    ws = ctypes.c_size_t()
+    mx = ctypes.c_size_t()
+    _check(_load().mgc_hx_query(n, t, C, ctypes.byref(ws), ctypes.byref(mx)))
+    return ws.value, mx.value
+
+
+def hx_compress(x, dict: int | None = None, base: int | None = None, C: int = 1024,
+                workspace=None, out=None, result=None):
+    """Lossless Huffman-X stream of a uint8/uint16/int32/int64 GPU tensor.
+
+    Defaults: the full range for uint8 and uint16; 65536 keys with base
+    -32767 for int32 and int64.  Returns the stream as a uint8 GPU tensor.
+    """
+    _require_gpu(x, "x")
+    torch = _torch()
+    t = _hx_types().get(x.dtype)
+    if t is None:
+        raise TypeError("Huffman-X streams hold uint8, uint16, int32 or int64 values")
+    x = x.contiguous().reshape(-1)
+    if dict is None:
+        dict = 256 if t == 0 else 65536
+    if base is None:
+        base = 0 if t < 2 else -(65536 // 2 - 1)
+    dev = x.device.index if x.device.index is not None else torch.cuda.current_device()
+    ws_n, out_n = hx_query(x.numel(), x.dtype, C)
+    ws = workspace if workspace is not None else _empty(ws_n, x.device)
+    o = out if out is not None else _empty(out_n, x.device)
+    res = result if result is not None else torch.zeros(2, dtype=torch.int64, device=x.device)
+    _check(_load().mgc_hx_compress(_ctx(dev), ctypes.c_void_p(x.data_ptr()), x.numel(), t, dict,
+                                   base, C, ctypes.c_void_p(o.data_ptr()), o.numel(),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                   ctypes.c_void_p(res.data_ptr()), _stream_ptr(dev)))
+    st, size = (int(v) for v in res.cpu())
+    if st:
+        raise MgcError(st, "Huffman-X compression failed on the device")
+    return o[:size]
+
+
+def hx_header(stream):
+    """(dtype, n, dict, base, C, total) of a Huffman-X stream."""
+    head = stream[:64].cpu().numpy().tobytes()
+    t = ctypes.c_int()
+    n = ctypes.c_uint64()
+    d = ctypes.c_uint32()
+    b = ctypes.c_int64()
+    C = ctypes.c_uint32()
+    tot = ctypes.c_uint64()
+    _check(_load().mgc_hx_parse_header(head, len(head), ctypes.byref(t), ctypes.byref(n),
+                                       ctypes.byref(d), ctypes.byref(b), ctypes.byref(C),
+                                       ctypes.byref(tot)))
+    dtype = {v: k for k, v in _hx_types().items()}[t.value]
+    return dtype, n.value, d.value, b.value, C.value, tot.value
+
+
+def hx_decompress(stream, workspace=None, out=None):
+    """Values of a Huffman-X stream (uint8 GPU tensor) as a GPU tensor."""
+    _require_gpu(stream, "stream")
+    torch = _torch()
+    stream = stream.contiguous()
+    dev = stream.device.index if stream.device.index is not None else torch.cuda.current_device()
+    dtype, n, _, _, C, _ = hx_header(stream)
+    ws_n, _ = hx_query(n, dtype, C)
+    ws = workspace if workspace is not None else _empty(ws_n, stream.device)
+    y = out if out is not None else torch.empty(max(n, 1), dtype=dtype, device=stream.device)
+    _check(_load().mgc_hx_decompress(_ctx(dev), ctypes.c_void_p(stream.data_ptr()),
+                                     stream.numel(), ctypes.c_void_p(y.data_ptr()), n,
+                                     _hx_types()[dtype], ctypes.c_void_p(ws.data_ptr()),
+                                     ws.numel(), _stream_ptr(dev)))
+    return y[:n]
 
 
 def profile_enable(flag: bool = True, device: int = 0):

@@ -347,6 +347,115 @@ struct ProfilerPause {
   explicit ProfilerPause(Profiler& prof) : p(prof), was(prof.enabled) { p.enabled = false; }
   ~ProfilerPause() { p.enabled = was; }
 };
+
+// Work buffers of the Huffman stage on its own (Algorithm 2 alone).
+struct HuffWs {
+  unsigned* hist;
+  uint32_t* code;
+  uint8_t* clen;
+  CodebookScratch cbsc;
+  uint32_t* cw;
+  Layout* lay;
+};
+HuffWs carve_huff(Carver& c, uint64_t n_chunks) {
+  HuffWs w;
+  w.hist = c.take<unsigned>(kDict);
+  w.code = c.take<uint32_t>(kDict);
+  w.clen = c.take<uint8_t>(kDict);
+  void* cbs = c.take<uint8_t>(codebook_scratch_bytes());
+  w.cbsc = c.base ? carve_codebook_scratch(cbs) : CodebookScratch{};
+  w.cw = c.take<uint32_t>(chunk_words_len((int64_t)n_chunks));
+  w.lay = c.take<Layout>(1);
+  return w;
+}
+uint64_t huff_max_bytes(uint64_t n, uint32_t C) {
+  const uint64_t n_chunks = (n + C - 1) / C;
+  return kHuffHeaderBytes + pad8(3 * kDict) + 8 * (n_chunks + 1) + 4 * (n + n_chunks) + 8;
+}
+// Histogram, codebook, chunk sizes, layout scan and encode of n > 0 keys into
+// the Huffman-only stream at out (its 48-byte header is written separately).
+void huff_encode_enqueue(mgc_ctx ctx, const uint16_t* sym, uint64_t n, uint32_t C,
+                         uint8_t* out, const HuffWs& w, hipStream_t s) {
+  const uint64_t n_chunks = (n + C - 1) / C;
+  {
+    StageScope st(&ctx->prof, "histogram", s);
+    launch_histogram(sym, (int64_t)n, w.hist, s);
+  }
+  {
+    StageScope st(&ctx->prof, "codebook", s);
+    launch_codebook(w.hist, w.cbsc, w.code, w.clen, out, kHuffHeaderBytes, w.lay, s);
+  }
+  {
+    StageScope st(&ctx->prof, "chunk_words", s);
+    launch_chunk_words(sym, (int64_t)n, (int)C, w.clen, w.cw, w.lay, s);
+  }
+  {
+    StageScope st(&ctx->prof, "layout_scan", s);
+    launch_layout_scan(w.cw, (int64_t)n_chunks, out, kHuffHeaderBytes, w.lay, nullptr, 0, true, s);
+  }
+  {
+    StageScope st(&ctx->prof, "encode", s);
+    launch_encode(sym, (int64_t)n, (int)C, w.code, w.clen, w.cbsc.pk, out, w.lay, s);
+  }
+}
+// Checks a Huffman-only stream header against the values it must describe;
+// returns the byte offsets of its chunk offsets and words sections.
+void check_huff_header(const HuffHeader& h, uint64_t n, uint64_t avail, uint64_t* off,
+                       uint64_t* words) {
+  if (h.magic != kHuffMagic || h.N != n || h.C < 1 || h.C > (1u << 20) ||
+      h.n_chunks != (h.N + h.C - 1) / h.C || h.n_codes > kDict || (n > 0 && h.n_codes < 1))
+    fail(MGC_EFORMAT, "bad huffman header");
+  *off = pad8(kHuffHeaderBytes + 3 * h.n_codes);
+  *words = *off + 8 * (h.n_chunks + 1);
+  const uint64_t end = pad8(*words + 4 * h.n_words);
+  if (end != h.total || h.total > avail) fail(MGC_EFORMAT, "truncated huffman stream");
+  if (n > 0 && h.n_words < 1) fail(MGC_EFORMAT, "huffman stream without coded words");
+}
+
+// Huffman-X value types: width, whether values can escape, and the key
+// window [lo, hi] of a dictionary and base (validated).
+uint32_t hx_width(int type) { return type == MGC_HX_U8 ? 1 : type == MGC_HX_U16 ? 2 : type == MGC_HX_I32 ? 4 : 8; }
+bool hx_escapes(int type) { return type == MGC_HX_I32 || type == MGC_HX_I64; }
+void hx_window(int type, uint32_t dict, int64_t base, int64_t* lo, int64_t* hi) {
+  if (type < MGC_HX_U8 || type > MGC_HX_I64) fail(MGC_EINVAL, "unknown Huffman-X value type");
+  if (!hx_escapes(type)) {
+    if (dict != (type == MGC_HX_U8 ? 256u : 65536u) || base != 0)
+      fail(MGC_EINVAL, "u8 and u16 streams take their full range as the dictionary, base 0");
+    *lo = 0;
+    *hi = (int64_t)dict - 1;
+    return;
+  }
+  if (dict < 2 || dict > 65536) fail(MGC_EINVAL, "dictionary size must be in [2, 65536]");
+  const int64_t tmax = type == MGC_HX_I32 ? INT32_MAX : INT64_MAX;
+  const int64_t tmin = type == MGC_HX_I32 ? INT32_MIN : INT64_MIN;
+  if (base < tmin || base > tmax) fail(MGC_EINVAL, "base outside the value type");
+  *lo = base;
+  *hi = base > tmax - (int64_t)(dict - 2) ? tmax : base + (int64_t)(dict - 2);
+}
+
+struct HxWs {
+  uint16_t* key;  // null for u16 (the values are the keys)
+  HuffWs huff;
+  unsigned long long* info;
+  uint32_t *zc, *zpre, *sums;
+  DecodeTables* tables;
+  unsigned* status;
+  Layout* lay0;  // a clear layout for the decoder's chunk prefix
+};
+HxWs carve_hx(Carver& c, uint64_t n, int type, uint32_t C) {
+  HxWs w;
+  const uint64_t n_chunks = (n + C - 1) / C, n1024 = (n + 1023) / 1024;
+  w.key = type == MGC_HX_U16 ? nullptr : c.take<uint16_t>(std::max<uint64_t>(n, 1));
+  w.huff = carve_huff(c, n_chunks);
+  w.info = c.take<unsigned long long>(4);
+  w.zc = c.take<uint32_t>(std::max<uint64_t>(n1024, 1));
+  w.zpre = c.take<uint32_t>(std::max<uint64_t>(n1024, 1));
+  w.sums = c.take<uint32_t>(kEscSumsMax);
+  w.tables = reinterpret_cast<DecodeTables*>(c.take<uint8_t>(decode_tables_bytes()));
+  w.status = c.take<unsigned>(4);
+  w.lay0 = c.take<Layout>(1);
+  return w;
+}
 }  // namespace
 
 extern "C" {
@@ -861,18 +970,12 @@ mgc_status mgc_huffman_query(uint64_t n, uint32_t C, size_t* ws_bytes, size_t* m
     if (C < 64 || C > 65536 || C % 64) fail(MGC_EINVAL, "chunk size must be a multiple of 64 in [64, 65536]");
     const uint64_t n_chunks = (n + C - 1) / C;
     Carver c(nullptr);
-    c.take<unsigned>(kDict);
-    c.take<uint32_t>(kDict);
-    c.take<uint8_t>(kDict);
-    c.take<uint8_t>(codebook_scratch_bytes());
-    c.take<uint32_t>(chunk_words_len((int64_t)n_chunks));
-    c.take<Layout>(1);
+    carve_huff(c, n_chunks);
     c.take<unsigned long long>(4);
     c.take<uint8_t>(decode_tables_bytes());
     c.take<unsigned>(4);
     if (ws_bytes) *ws_bytes = c.off;
-    if (max_out_bytes)
-      *max_out_bytes = kHuffHeaderBytes + pad8(3 * kDict) + 8 * (n_chunks + 1) + 4 * (n + n_chunks) + 8;
+    if (max_out_bytes) *max_out_bytes = huff_max_bytes(n, C);
   });
 }
 
@@ -889,38 +992,19 @@ mgc_status mgc_huffman_encode(mgc_ctx ctx, const uint16_t* d_sym, uint64_t n, ui
     hipStream_t s = as_stream(stream);
     const uint64_t n_chunks = (n + C - 1) / C;
     Carver c(d_ws);
-    unsigned* hist = c.take<unsigned>(kDict);
-    uint32_t* code = c.take<uint32_t>(kDict);
-    uint8_t* clen = c.take<uint8_t>(kDict);
-    void* cbs = c.take<uint8_t>(codebook_scratch_bytes());
-    const CodebookScratch cbsc = carve_codebook_scratch(cbs);
-    uint32_t* cw = c.take<uint32_t>(chunk_words_len((int64_t)n_chunks));
-    Layout* lay = c.take<Layout>(1);
+    const HuffWs w = carve_huff(c, n_chunks);
     unsigned long long* info = c.take<unsigned long long>(4);
     uint8_t* out = static_cast<uint8_t*>(d_out);
-    MGC_HIP(hipMemsetAsync(hist, 0, kDict * sizeof(unsigned), s));
-    MGC_HIP(hipMemsetAsync(lay, 0, sizeof(Layout), s));
+    MGC_HIP(hipMemsetAsync(w.hist, 0, kDict * sizeof(unsigned), s));
+    MGC_HIP(hipMemsetAsync(w.lay, 0, sizeof(Layout), s));
     if (n > 0) {
-      StageScope st(&ctx->prof, "histogram", s);
-      launch_histogram(d_sym, (int64_t)n, hist, s);
-    }
-    {
+      huff_encode_enqueue(ctx, d_sym, n, C, out, w, s);
+    } else {
       StageScope st(&ctx->prof, "codebook", s);
-      launch_codebook(hist, cbsc, code, clen, out, kHuffHeaderBytes, lay, s);
+      launch_codebook(w.hist, w.cbsc, w.code, w.clen, out, kHuffHeaderBytes, w.lay, s);
+      launch_layout_scan(w.cw, 0, out, kHuffHeaderBytes, w.lay, nullptr, 0, true, s);
     }
-    if (n > 0) {
-      StageScope st(&ctx->prof, "chunk_words", s);
-      launch_chunk_words(d_sym, (int64_t)n, (int)C, clen, cw, lay, s);
-    }
-    {
-      StageScope st(&ctx->prof, "layout_scan", s);
-      launch_layout_scan(cw, (int64_t)n_chunks, out, kHuffHeaderBytes, lay, nullptr, 0, true, s);
-    }
-    if (n > 0) {
-      StageScope st(&ctx->prof, "encode", s);
-      launch_encode(d_sym, (int64_t)n, (int)C, code, clen, cbsc.pk, out, lay, s);
-    }
-    launch_huff_header(out, C, n, n_chunks, lay, info, s);
+    launch_huff_header(out, C, n, n_chunks, w.lay, info, s);
     MGC_HIP(hipGetLastError());
     unsigned long long inf[3];
     sync_read(ctx, ctx->pinned, info, sizeof(inf), s);
@@ -939,19 +1023,13 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes, ui
     sync_read(ctx, ctx->pinned, d_in, kHuffHeaderBytes, s);
     HuffHeader h;
     std::memcpy(&h, ctx->pinned, kHuffHeaderBytes);
-    if (h.magic != kHuffMagic || h.N != n || h.C < 1 || h.C > (1u << 20) ||
-        h.n_chunks != (h.N + h.C - 1) / h.C || h.n_codes > kDict || (n > 0 && h.n_codes < 1))
-      fail(MGC_EFORMAT, "bad huffman header");
-    const uint64_t off = pad8(kHuffHeaderBytes + 3 * h.n_codes);
-    const uint64_t words = off + 8 * (h.n_chunks + 1);
-    const uint64_t end = pad8(words + 4 * h.n_words);
-    if (end != h.total || h.total > in_bytes) fail(MGC_EFORMAT, "truncated huffman stream");
+    uint64_t off = 0, words = 0;
+    check_huff_header(h, n, in_bytes, &off, &words);
     Carver meas(nullptr);
     meas.take<uint8_t>(decode_tables_bytes());
     meas.take<unsigned>(4);
     if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
     if (n == 0) return;
-    if (h.n_words < 1) fail(MGC_EFORMAT, "huffman stream without coded words");
     Carver c(d_ws);
     void* tables = c.take<uint8_t>(decode_tables_bytes());
     unsigned* status = c.take<unsigned>(4);
@@ -972,6 +1050,171 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes, ui
     MGC_HIP(hipGetLastError());
     unsigned st = 0;
     sync_read(ctx, ctx->pinned, status, sizeof(unsigned), s);
+    std::memcpy(&st, ctx->pinned, sizeof(unsigned));
+    if (st & ST_FORMAT) fail(MGC_EFORMAT, "corrupt coded data");
+  });
+}
+
+mgc_status mgc_hx_query(uint64_t n, mgc_hx_type type, uint32_t C, size_t* ws_bytes,
+                        size_t* max_out_bytes) {
+  return guard([&] {
+    if (C < 64 || C > 65536 || C % 64) fail(MGC_EINVAL, "chunk size must be a multiple of 64 in [64, 65536]");
+    if (type < MGC_HX_U8 || type > MGC_HX_I64) fail(MGC_EINVAL, "unknown Huffman-X value type");
+    Carver c(nullptr);
+    carve_hx(c, n, type, C);
+    if (ws_bytes) *ws_bytes = c.off;
+    if (max_out_bytes)
+      *max_out_bytes = kHxHeaderBytes + huff_max_bytes(n, C) +
+                       (hx_escapes(type) ? pad8(n * hx_width(type)) : 0);
+  });
+}
+
+mgc_status mgc_hx_compress(mgc_ctx ctx, const void* d_in, uint64_t n, mgc_hx_type type,
+                           uint32_t dict, int64_t base, uint32_t C, void* d_out, size_t out_cap,
+                           void* d_ws, size_t ws_bytes, uint64_t* d_result, void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    int64_t lo = 0, hi = 0;
+    hx_window(type, dict, base, &lo, &hi);
+    size_t need_ws = 0, need_out = 0;
+    if (mgc_hx_query(n, type, C, &need_ws, &need_out) != MGC_OK) throw Fail{MGC_EINVAL};
+    if (n >= (1ull << 32)) fail(MGC_EUNSUPPORTED, "2^32 or more values");
+    if (!d_out || !d_ws || !d_result || (n > 0 && !d_in)) fail(MGC_EINVAL, "null pointer");
+    if (reinterpret_cast<uintptr_t>(d_in) % hx_width(type) ||
+        reinterpret_cast<uintptr_t>(d_out) % 8)
+      fail(MGC_EINVAL, "input not aligned to its value type or output not 8-byte aligned");
+    if (ws_bytes < need_ws || out_cap < need_out) fail(MGC_ENOSPC, "workspace or output too small");
+    hipStream_t s = as_stream(stream);
+    Carver c(d_ws);
+    const HxWs w = carve_hx(c, n, type, C);
+    uint8_t* out = static_cast<uint8_t*>(d_out);
+    uint8_t* sec = out + kHxHeaderBytes;
+    const bool esc = hx_escapes(type);
+    const uint64_t n_chunks = (n + C - 1) / C;
+    if (n > 0) {
+      MGC_HIP(hipMemsetAsync(w.huff.hist, 0, kDict * sizeof(unsigned), s));
+      MGC_HIP(hipMemsetAsync(w.huff.lay, 0, sizeof(Layout), s));
+      const uint16_t* key = static_cast<const uint16_t*>(d_in);
+      if (type != MGC_HX_U16) {
+        StageScope st(&ctx->prof, "hx_keys", s);
+        launch_hx_keys(d_in, n, type, lo, hi, dict - 1, w.key, w.zc, s);
+        key = w.key;
+      }
+      huff_encode_enqueue(ctx, key, n, C, sec, w.huff, s);
+      launch_huff_header(sec, C, n, n_chunks, w.huff.lay, w.info, s);
+      if (esc) {
+        StageScope st(&ctx->prof, "hx_escapes", s);
+        launch_chunk_prefix(w.zc, w.zpre, w.sums, (int64_t)((n + 1023) / 1024), w.huff.lay, s);
+        launch_hx_place(d_in, n, type, lo, hi, w.zc, w.zpre, sec, w.huff.lay, s);
+      }
+    }
+    launch_hx_header(out, type, dict, C, base, n, (esc && n > 0) ? w.zc : nullptr,
+                     (esc && n > 0) ? w.zpre : nullptr, w.huff.lay,
+                     reinterpret_cast<unsigned long long*>(d_result), s);
+    MGC_HIP(hipGetLastError());
+  });
+}
+
+mgc_status mgc_hx_parse_header(const void* h_header, size_t bytes, mgc_hx_type* type,
+                               uint64_t* n, uint32_t* dict, int64_t* base, uint32_t* C,
+                               uint64_t* total) {
+  return guard([&] {
+    if (!h_header || bytes < (size_t)kHxHeaderBytes) fail(MGC_EFORMAT, "stream shorter than its header");
+    const uint8_t* b = static_cast<const uint8_t*>(h_header);
+    uint32_t magic, d, c;
+    int64_t bs;
+    uint64_t nn, tot;
+    std::memcpy(&magic, b, 4);
+    std::memcpy(&d, b + 8, 4);
+    std::memcpy(&c, b + 12, 4);
+    std::memcpy(&bs, b + 16, 8);
+    std::memcpy(&nn, b + 24, 8);
+    std::memcpy(&tot, b + 48, 8);
+    if (magic != kHxMagic || b[4] > MGC_HX_I64) fail(MGC_EFORMAT, "not a Huffman-X stream");
+    if (type) *type = static_cast<mgc_hx_type>(b[4]);
+    if (n) *n = nn;
+    if (dict) *dict = d;
+    if (base) *base = bs;
+    if (C) *C = c;
+    if (total) *total = tot;
+  });
+}
+
+mgc_status mgc_hx_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* d_out,
+                             uint64_t n, mgc_hx_type type, void* d_ws, size_t ws_bytes,
+                             void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (!d_in || (n > 0 && !d_out)) fail(MGC_EINVAL, "null pointer");
+    if (reinterpret_cast<uintptr_t>(d_in) % 8 ||
+        reinterpret_cast<uintptr_t>(d_out) % hx_width(type))
+      fail(MGC_EINVAL, "stream not 8-byte aligned or output not aligned to its value type");
+    if (in_bytes < (size_t)kHxHeaderBytes) fail(MGC_EFORMAT, "stream shorter than its header");
+    hipStream_t s = as_stream(stream);
+    const size_t head = in_bytes >= (size_t)(kHxHeaderBytes + kHuffHeaderBytes)
+                            ? kHxHeaderBytes + kHuffHeaderBytes : kHxHeaderBytes;
+    sync_read(ctx, ctx->pinned, d_in, head, s);
+    uint8_t hb[kHxHeaderBytes + kHuffHeaderBytes] = {};
+    std::memcpy(hb, ctx->pinned, head);
+    mgc_hx_type t;
+    uint64_t hn, total, n_esc, secb;
+    uint32_t dict, C;
+    int64_t base;
+    if (mgc_hx_parse_header(hb, head, &t, &hn, &dict, &base, &C, &total) != MGC_OK)
+      fail(MGC_EFORMAT, "not a Huffman-X stream");
+    std::memcpy(&n_esc, hb + 32, 8);
+    std::memcpy(&secb, hb + 40, 8);
+    if (t != type || hn != n) fail(MGC_EINVAL, "value type or count differs from the stream's");
+    int64_t lo = 0, hi = 0;
+    try {
+      hx_window(type, dict, base, &lo, &hi);
+    } catch (const Fail&) {
+      fail(MGC_EFORMAT, "bad dictionary or base in the stream");
+    }
+    if (C < 64 || C > 65536 || C % 64) fail(MGC_EFORMAT, "bad chunk size in the stream");
+    const bool esc = hx_escapes(type);
+    const uint32_t width = hx_width(type);
+    if (n_esc > n || (!esc && n_esc) || (n == 0 && secb) || secb % 8 ||
+        total != kHxHeaderBytes + secb + pad8(n_esc * width) || total > in_bytes)
+      fail(MGC_EFORMAT, "inconsistent Huffman-X stream lengths");
+    size_t need_ws = 0;
+    if (mgc_hx_query(n, type, C, &need_ws, nullptr) != MGC_OK) throw Fail{MGC_EINVAL};
+    if (!d_ws || ws_bytes < need_ws) fail(MGC_ENOSPC, "workspace too small");
+    if (n == 0) return;
+    if (n >= (1ull << 32)) fail(MGC_EUNSUPPORTED, "2^32 or more values");
+    if (head < (size_t)(kHxHeaderBytes + kHuffHeaderBytes)) fail(MGC_EFORMAT, "truncated stream");
+    HuffHeader h;
+    std::memcpy(&h, hb + kHxHeaderBytes, kHuffHeaderBytes);
+    uint64_t off = 0, words = 0;
+    check_huff_header(h, n, secb, &off, &words);
+    if (h.C != C) fail(MGC_EFORMAT, "chunk sizes of the header and the coded section differ");
+    Carver c(d_ws);
+    const HxWs w = carve_hx(c, n, type, C);
+    const uint8_t* sec = static_cast<const uint8_t*>(d_in) + kHxHeaderBytes;
+    uint16_t* key = type == MGC_HX_U16 ? static_cast<uint16_t*>(d_out) : w.key;
+    MGC_HIP(hipMemsetAsync(w.status, 0, 4 * sizeof(unsigned), s));
+    {
+      StageScope st(&ctx->prof, "decode_tables", s);
+      launch_decode_tables(sec + kHuffHeaderBytes, h.n_codes, w.tables, w.status, s);
+    }
+    {
+      StageScope st(&ctx->prof, "decode", s);
+      ctx->dec_last = launch_decode(sec, off, words, h.n_chunks, h.n_words, (int)C, (int64_t)n,
+                                    h.n_codes, w.tables, key, w.status, s, ctx->dec_force);
+    }
+    if (type != MGC_HX_U16) {
+      StageScope st(&ctx->prof, "hx_values", s);
+      if (esc) {
+        MGC_HIP(hipMemsetAsync(w.lay0, 0, sizeof(Layout), s));
+        launch_hx_count(key, n, dict - 1, w.zc, s);
+        launch_chunk_prefix(w.zc, w.zpre, w.sums, (int64_t)((n + 1023) / 1024), w.lay0, s);
+      }
+      launch_hx_values(key, n, type, lo, (uint32_t)(hi - lo), dict - 1, sec + secb, n_esc, w.zc,
+                       w.zpre, d_out, w.status, s);
+    }
+    MGC_HIP(hipGetLastError());
+    unsigned st = 0;
+    sync_read(ctx, ctx->pinned, w.status, sizeof(unsigned), s);
     std::memcpy(&st, ctx->pinned, sizeof(unsigned));
     if (st & ST_FORMAT) fail(MGC_EFORMAT, "corrupt coded data");
   });

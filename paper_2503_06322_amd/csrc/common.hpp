@@ -19,6 +19,8 @@ constexpr int kHeaderBytes = 128;
 constexpr int kHuffHeaderBytes = 48;
 constexpr uint32_t kMagic = 0x3143474Du;      // "MGC1"
 constexpr uint32_t kHuffMagic = 0x3148474Du;  // "MGH1"
+constexpr int kHxHeaderBytes = 64;
+constexpr uint32_t kHxMagic = 0x5848474Du;    // "MGHX"
 constexpr uint16_t kVersion = 1;
 constexpr int kMaxLevels = 62;
 

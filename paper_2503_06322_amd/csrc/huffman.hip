@@ -2445,6 +2445,17 @@ int64_t esc_sum_blocks(int64_t n_chunks) {
   return std::max<int64_t>(1, std::min<int64_t>(kEscSumsMax, (n_chunks + 1023) / 1024));
 }
 
+void launch_chunk_prefix(const uint32_t* zc, uint32_t* zpre, uint32_t* sums, int64_t n_chunks,
+                         const Layout* lay, hipStream_t s) {
+  const int64_t nb = esc_sum_blocks(n_chunks);
+  const int64_t R = (n_chunks + nb - 1) / nb;
+  const int64_t blocks = (n_chunks + R - 1) / R;
+  hipLaunchKernelGGL(k_esc_sums, dim3((unsigned)blocks), dim3(kEscThreads), 0, s, zc, n_chunks,
+                     R, sums, lay, nullptr);
+  hipLaunchKernelGGL(k_esc_prefix, dim3((unsigned)blocks), dim3(kEscThreads), 0, s, zc,
+                     n_chunks, R, sums, zpre, lay, nullptr);
+}
+
 void launch_escape_order(const OutlierBuf& ob, const uint32_t* zc, const uint32_t* zl,
                          uint32_t* zpre, uint32_t* sums, int64_t n_chunks, uint8_t* out,
                          Layout* lay, unsigned* status, hipStream_t s, const unsigned* gate) {

@@ -164,6 +164,10 @@ void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* cl
 // writes the stream's outlier sections (after the layout scan).  sums holds
 // kEscSumsMax entries.  An inconsistent record sets ST_INTERNAL in *status.
 constexpr int64_t kEscSumsMax = 1024;
+// Exclusive prefix sums zpre of the n_chunks counts zc (sums: kEscSumsMax
+// words); skipped when lay->status is set.
+void launch_chunk_prefix(const uint32_t* zc, uint32_t* zpre, uint32_t* sums, int64_t n_chunks,
+                         const Layout* lay, hipStream_t s);
 void launch_escape_order(const OutlierBuf& ob, const uint32_t* zc, const uint32_t* zl,
                          uint32_t* zpre, uint32_t* sums, int64_t n_chunks, uint8_t* out,
                          Layout* lay, unsigned* status, hipStream_t s, const unsigned* gate);
@@ -212,5 +216,29 @@ DecodeShape launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_se
                           uint64_t n_chunks, uint64_t n_words, int C, int64_t N,
                           uint64_t n_codes, const DecodeTables* t, uint16_t* sym,
                           unsigned* status, hipStream_t s, DecodeShape force = DecodeShape{});
+
+// Huffman-X (hx.hip).  Keys of n values of a stream type (mgc_hx_type):
+// u8/u16 values are their keys; i32/i64 values in [lo, hi] are key v - lo,
+// others key esc with zc[chunk] = escapes per 1024 values (zc unused for
+// u8/u16).
+void launch_hx_keys(const void* in, uint64_t n, int type, int64_t lo, int64_t hi, uint32_t esc,
+                    uint16_t* key, uint32_t* zc, hipStream_t s);
+// Escaped i32/i64 values, in position order, at sec + lay->end (after the
+// coded section) from the exclusive chunk prefix zpre.
+void launch_hx_place(const void* in, uint64_t n, int type, int64_t lo, int64_t hi,
+                     const uint32_t* zc, const uint32_t* zpre, uint8_t* sec, const Layout* lay,
+                     hipStream_t s);
+// 64-byte stream header and res = {mgc_status, stream bytes}; zc/zpre null
+// for types without escapes, lay unused when n = 0.
+void launch_hx_header(uint8_t* out, int type, uint32_t D, uint32_t C, int64_t base, uint64_t n,
+                      const uint32_t* zc, const uint32_t* zpre, const Layout* lay,
+                      unsigned long long* res, hipStream_t s);
+// Escape keys per 1024 decoded keys.
+void launch_hx_count(const uint16_t* key, uint64_t n, uint32_t esc, uint32_t* zc, hipStream_t s);
+// Values from decoded keys (u8, i32, i64); ST_FORMAT into *status for keys
+// no value maps to or escape counts that disagree with n_esc.
+void launch_hx_values(const uint16_t* key, uint64_t n, int type, int64_t lo, uint32_t kmax,
+                      uint32_t esc_key, const void* esc, uint64_t n_esc, const uint32_t* zc,
+                      const uint32_t* zpre, void* out, unsigned* status, hipStream_t s);
 
 }  // namespace mgc

@@ -100,3 +100,26 @@ def test_batch_query_lays_out_plain_slots():
     with pytest.raises(mgc.MgcError) as e:
         mgc.batch_query([], [])
     assert e.value.name == "EINVAL"
+
+
+def test_hx_host_calls():
+    """Huffman-X size query and header parsing run on the host."""
+    import numpy as np
+    from oracle import hx
+    lib = _lib()
+    ws, mx = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.mgc_hx_query(ctypes.c_uint64(100000), 2, ctypes.c_uint32(1024), ctypes.byref(ws),
+                            ctypes.byref(mx)) == 0
+    # header, the largest coded section, and every value escaped (4 bytes each)
+    assert mx.value >= 64 + 48 + 4 * 100000 + 4 * 100000
+    assert lib.mgc_hx_query(ctypes.c_uint64(10), 7, ctypes.c_uint32(1024), None, None) == 1
+    assert lib.mgc_hx_query(ctypes.c_uint64(10), 0, ctypes.c_uint32(100), None, None) == 1
+    buf = hx.compress(np.array([5, -70000, 3], dtype=np.int64), D=1024, b=-7)
+    t, n, d, C, tot = ctypes.c_int(), ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+    b = ctypes.c_int64()
+    assert lib.mgc_hx_parse_header(buf, ctypes.c_size_t(len(buf)), ctypes.byref(t), ctypes.byref(n),
+                                   ctypes.byref(d), ctypes.byref(b), ctypes.byref(C),
+                                   ctypes.byref(tot)) == 0
+    assert (t.value, n.value, d.value, b.value, C.value, tot.value) == (3, 3, 1024, -7, 1024, len(buf))
+    assert lib.mgc_hx_parse_header(b"\0" * 64, ctypes.c_size_t(64), None, None, None, None, None,
+                                   None) == 4
