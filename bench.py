@@ -16,7 +16,9 @@ one graph launch against 256 plain calls), "differentiation" (gradient of a
 sub-box quantity of interest through the adjoint recomposition) and
 "workloads" (compress / decompress GB/s, compression ratio and error of the
 65^3 bump field, the 513^3 field at 1e-2 and 1e-4, the 8193^2 FP64 plane
-waves and the 300x400x500 field under both norms).
+waves and the 300x400x500 field under both norms) and "huffman_x" (the
+Huffman pipeline as a standalone lossless codec on a byte stream and an
+integer stream, with its own oracle baseline).
 """
 from __future__ import annotations
 
@@ -154,6 +156,74 @@ def cpu_batch_baseline(synthetic, stride: int = 8):
             "kind": "oracle", "sample": "%d of the 256 arrays (every %dth, %.0f MB), compress "
                                         "only, %d processes, %.1fs wall" %
                                         (len(specs), stride, nbytes / 1e6, workers, wall)}
+
+
+def hx_leg(torch, mgc, synthetic, reps: int):
+    """Huffman-X (the Huffman pipeline as a standalone lossless codec): GB/s
+    of input bytes for compression and decompression of a byte stream and an
+    integer stream, inputs resident on the GPU, buffers preallocated, two
+    untimed calls, then ``reps`` timed calls of each (HIP events on the
+    current stream, median).  Decompression is the blocking entry point (it
+    reads the stream header and a status word on the host), so its time
+    includes those two reads.  Every timed round trip is checked exact."""
+    cases = [("u8_zipf1.2_256MiB", lambda: synthetic.zipf_bytes(1 << 28, 21)),
+             ("i32_laplace8_wild1e-3_256MiB", lambda: synthetic.laplace_ints(1 << 26, 22))]
+    stream = torch.cuda.current_stream()
+    out = []
+    for name, make in cases:
+        v = make()
+        x = torch.from_numpy(v).cuda()
+        ws_n, out_n = mgc.hx_query(x.numel(), x.dtype)
+        ws = torch.empty(ws_n, dtype=torch.uint8, device="cuda")
+        ob = torch.empty(out_n, dtype=torch.uint8, device="cuda")
+        res = torch.zeros(2, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(2):
+            blob = mgc.hx_compress(x, workspace=ws, out=ob, result=res)
+            mgc.hx_decompress(blob, workspace=ws, out=y)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        torch.cuda.synchronize()
+        for e in ev:
+            e[0].record(stream)
+            mgc.hx_compress(x, workspace=ws, out=ob, result=res, sync=False)
+            e[1].record(stream)
+            mgc.hx_decompress(blob, workspace=ws, out=y)
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        exact = bool((y == x).all())
+        size = int(res[1].item())
+        assert int(res[0].item()) == 0 and size == blob.numel()
+        c_ms = float(np.median([a.elapsed_time(b) for a, b, _ in ev]))
+        d_ms = float(np.median([b.elapsed_time(c) for _, b, c in ev]))
+        nb = x.numel() * x.element_size()
+        row = {"workload": name, "values": x.numel(), "dtype": str(v.dtype),
+               "compress_ms": round(c_ms, 4), "decompress_ms": round(d_ms, 4),
+               "compress_GBps": round(nb / (c_ms * 1e-3) / 1e9, 2),
+               "decompress_GBps": round(nb / (d_ms * 1e-3) / 1e9, 2),
+               "compression_ratio": round(nb / size, 3), "lossless": exact}
+        log("huffman-x %-30s compress %8.3f ms (%7.1f GB/s)  decompress %8.3f ms (%7.1f GB/s)  CR %6.3f  exact %s"
+            % (name, c_ms, row["compress_GBps"], d_ms, row["decompress_GBps"],
+               row["compression_ratio"], exact))
+        out.append(row)
+        del x, ws, ob, y, blob
+    return out
+
+
+def hx_cpu_baseline(synthetic):
+    """The Huffman-X oracle (one thread) on the first 2^24 values of the
+    integer stream workload: compress + decompress, GB/s of input bytes."""
+    from oracle import hx
+    v = synthetic.laplace_ints(1 << 26, 22)[: 1 << 24]
+    t0 = time.perf_counter()
+    buf = hx.compress(v)
+    t1 = time.perf_counter()
+    back = hx.decompress(buf)
+    t2 = time.perf_counter()
+    assert np.array_equal(back, v)
+    return {"value": round(2 * v.nbytes / (t2 - t0) / 1e9, 5), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "first 2^24 values (64 MiB) of the i32 integer stream, compress %.1fs + "
+                      "decompress %.1fs, one thread" % (t1 - t0, t2 - t1)}
 
 
 def config_legs(torch, mgc, synthetic, u513, reps: int):
@@ -360,6 +430,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--no-hx", action="store_true")
     ap.add_argument("--config-reps", type=int, default=5)
     ap.add_argument("--copy-reference", action="store_true",
                     help="also copy the input once on the device (a kernel of known "
@@ -474,8 +545,15 @@ def main():
     if not args.no_configs:
         configs = config_legs(torch, mgc, synthetic, u, args.config_reps)
 
+    hxr = None
+    if not args.no_hx:
+        hxr = {"workloads": hx_leg(torch, mgc, synthetic, args.config_reps)}
+
     cpu = None
     if not args.no_cpu_baseline:
+        if hxr is not None:
+            hxr["cpu_baseline"] = hx_cpu_baseline(synthetic)
+            log("cpu baseline (huffman-x): %s" % json.dumps(hxr["cpu_baseline"]))
         log("cpu baseline: oracle on the first %d planes of the field" % args.cpu_planes)
         cpu = cpu_baseline(u, args.rel, args.cpu_planes)
         log("cpu baseline: %s" % json.dumps(cpu))
@@ -500,7 +578,7 @@ def main():
         "compression_ratio": round(in_bytes / stream_bytes, 3),
         "max_err_over_tau": round(err / tau, 4),
         "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "differentiation": diff,
-        "workloads": configs,
+        "workloads": configs, "huffman_x": hxr,
         "stages": stages, "stages_ms_per_step_with_events": round(prof_ms_step, 4),
     }
     print(json.dumps(res), flush=True)

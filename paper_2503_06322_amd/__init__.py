@@ -669,11 +669,13 @@ def hx_query(n: int, dtype, C: int = 1024):
 
 
 def hx_compress(x, dict: int | None = None, base: int | None = None, C: int = 1024,
-                workspace=None, out=None, result=None):
+                workspace=None, out=None, result=None, sync: bool = True):
     """Lossless Huffman-X stream of a uint8/uint16/int32/int64 GPU tensor.
 
     Defaults: the full range for uint8 and uint16; 65536 keys with base
-    -32767 for int32 and int64.  Returns the stream as a uint8 GPU tensor.
+    -32767 for int32 and int64.  Returns the stream as a uint8 GPU tensor;
+    with ``sync=False`` returns (output buffer, result) at once, result being
+    the device words {status, stream bytes}.
     """
     _require_gpu(x, "x")
     torch = _torch()
@@ -694,6 +696,8 @@ def hx_compress(x, dict: int | None = None, base: int | None = None, C: int = 10
                                    base, C, ctypes.c_void_p(o.data_ptr()), o.numel(),
                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                    ctypes.c_void_p(res.data_ptr()), _stream_ptr(dev)))
+    if not sync:
+        return o, res
     st, size = (int(v) for v in res.cpu())
     if st:
         raise MgcError(st, "Huffman-X compression failed on the device")

@@ -375,11 +375,12 @@ uint64_t huff_max_bytes(uint64_t n, uint32_t C) {
 // Histogram, codebook, chunk sizes, layout scan and encode of n > 0 keys into
 // the Huffman-only stream at out (its 48-byte header is written separately).
 void huff_encode_enqueue(mgc_ctx ctx, const uint16_t* sym, uint64_t n, uint32_t C,
-                         uint8_t* out, const HuffWs& w, hipStream_t s) {
+                         uint8_t* out, const HuffWs& w, hipStream_t s,
+                         uint32_t win_lo = kHistWinLo, uint32_t hot = 0) {
   const uint64_t n_chunks = (n + C - 1) / C;
   {
     StageScope st(&ctx->prof, "histogram", s);
-    launch_histogram(sym, (int64_t)n, w.hist, s);
+    launch_histogram(sym, (int64_t)n, w.hist, s, nullptr, win_lo, hot);
   }
   {
     StageScope st(&ctx->prof, "codebook", s);
@@ -1100,7 +1101,14 @@ mgc_status mgc_hx_compress(mgc_ctx ctx, const void* d_in, uint64_t n, mgc_hx_typ
         launch_hx_keys(d_in, n, type, lo, hi, dict - 1, w.key, w.zc, s);
         key = w.key;
       }
-      huff_encode_enqueue(ctx, key, n, C, sec, w.huff, s);
+      // histogram window: u8 keys from 0; otherwise centred on the key of
+      // value 0 (the centre of the range for u16), escapes in the spare slot
+      const int64_t k0 = type == MGC_HX_U16 ? (int64_t)kHalf
+                         : lo > 0 ? 0 : lo < -(int64_t)kDict ? (int64_t)kDict : -lo;
+      const int64_t wl = std::min<int64_t>(std::max<int64_t>(k0 - (int64_t)kHistWindow / 2, 0),
+                                           (int64_t)(kDict - kHistWindow));
+      huff_encode_enqueue(ctx, key, n, C, sec, w.huff, s,
+                          type == MGC_HX_U8 ? 0u : (uint32_t)wl, esc ? dict - 1 : 0u);
       launch_huff_header(sec, C, n, n_chunks, w.huff.lay, w.info, s);
       if (esc) {
         StageScope st(&ctx->prof, "hx_escapes", s);

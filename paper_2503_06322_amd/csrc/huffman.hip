@@ -115,20 +115,23 @@ __device__ __forceinline__ uint64_t match_digit(unsigned digit, int nbits, bool 
 // One 1024-thread block per CU.  A window of 32768 bins around the
 // dictionary centre (|k| < 16384) is counted in LDS; symbols outside it and
 // the escape symbol go to global atomics.  Symbols are read 8 at a time.
-constexpr int kHistWin = 32768;
+constexpr int kHistWin = kHistWindow;
 
-// h[kHistWin] counts the escape symbol 0 (frequent when many values escape
-// the dictionary, and then too contended for one global counter).
-__device__ __forceinline__ void hist_add(unsigned s, unsigned* h, unsigned* hist) {
-  const unsigned d = s - (kHalf - kHistWin / 2);
+// Symbols lo .. lo + kHistWin - 1 are counted in LDS; h[kHistWin] counts the
+// symbol `hot` when it lies outside (the escape symbol: frequent when many
+// values escape the dictionary, and then too contended for one global
+// counter); other symbols go to global atomics.
+__device__ __forceinline__ void hist_add(unsigned s, unsigned* h, unsigned* hist, unsigned lo,
+                                         unsigned hot) {
+  const unsigned d = s - lo;
   if (d < (unsigned)kHistWin) atomicAdd(&h[d], 1u);
-  else if (s == 0) atomicAdd(&h[kHistWin], 1u);
+  else if (s == hot) atomicAdd(&h[kHistWin], 1u);
   else atomicAdd(&hist[s], 1u);
 }
 
 __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ sym, int64_t n,
                                                unsigned* __restrict__ hist, uint32_t blk,
-                                               uint32_t nblk) {
+                                               uint32_t nblk, unsigned lo, unsigned hot) {
   __shared__ unsigned h[kHistWin + 1];
   for (int i = threadIdx.x; i <= kHistWin; i += 1024) h[i] = 0;
   __syncthreads();
@@ -146,8 +149,8 @@ __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ sym,
       const unsigned a[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        hist_add(a[k] & 0xFFFFu, h, hist);
-        hist_add(a[k] >> 16, h, hist);
+        hist_add(a[k] & 0xFFFFu, h, hist, lo, hot);
+        hist_add(a[k] >> 16, h, hist, lo, hot);
       }
     }
   }
@@ -156,23 +159,24 @@ __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ sym,
     const unsigned a[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      hist_add(a[k] & 0xFFFFu, h, hist);
-      hist_add(a[k] >> 16, h, hist);
+      hist_add(a[k] & 0xFFFFu, h, hist, lo, hot);
+      hist_add(a[k] >> 16, h, hist, lo, hot);
     }
   }
   for (int64_t i = nvec * 8 + (int64_t)blk * 1024 + threadIdx.x; i < n; i += stride)
-    hist_add(sym[i], h, hist);
+    hist_add(sym[i], h, hist, lo, hot);
   __syncthreads();
   for (int i = threadIdx.x; i < kHistWin; i += 1024)
-    if (h[i]) atomicAdd(&hist[kHalf - kHistWin / 2 + i], h[i]);
-  if (threadIdx.x == 0 && h[kHistWin]) atomicAdd(&hist[0], h[kHistWin]);
+    if (h[i]) atomicAdd(&hist[lo + i], h[i]);
+  if (threadIdx.x == 0 && h[kHistWin]) atomicAdd(&hist[hot], h[kHistWin]);
 }
 
 __global__ __launch_bounds__(1024) void k_histogram(const uint16_t* __restrict__ sym, int64_t n,
                                                      unsigned* __restrict__ hist,
-                                                     const unsigned* __restrict__ gate) {
+                                                     const unsigned* __restrict__ gate,
+                                                     unsigned lo, unsigned hot) {
   if (gate_closed(gate)) return;
-  histogram_body(sym, n, hist, blockIdx.x, gridDim.x);
+  histogram_body(sym, n, hist, blockIdx.x, gridDim.x, lo, hot);
 }
 
 // ---------------------------------------------------- single-block helpers
@@ -2326,7 +2330,7 @@ __global__ __launch_bounds__(1024) void kb_histogram(const Job* __restrict__ job
   const JobBlock jb = map[blockIdx.x];
   const Job& J = jobs[jb.job];
   if (job_skipped_h(J)) return;
-  histogram_body(J.sym, J.N, J.hist, jb.local, jb.count);
+  histogram_body(J.sym, J.N, J.hist, jb.local, jb.count, kHistWinLo, 0u);
 }
 
 __global__ __launch_bounds__(1024) void kb_codebook(const Job* __restrict__ jobs) {
@@ -2387,8 +2391,10 @@ uint32_t hist_blocks(int64_t n) {
 }
 
 void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s,
-                      const unsigned* gate) {
-  hipLaunchKernelGGL(k_histogram, dim3(hist_blocks(n)), dim3(1024), 0, s, sym, n, hist, gate);
+                      const unsigned* gate, uint32_t win_lo, uint32_t hot) {
+  if (win_lo > (uint32_t)(kDict - kHistWin)) throw std::logic_error("histogram window out of range");
+  hipLaunchKernelGGL(k_histogram, dim3(hist_blocks(n)), dim3(1024), 0, s, sym, n, hist, gate,
+                     win_lo, hot);
 }
 
 void launch_b_histogram(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s) {

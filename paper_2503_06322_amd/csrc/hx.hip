@@ -62,6 +62,30 @@ __global__ __launch_bounds__(64 * kHxWaves) void k_hx_keys(const T* __restrict__
   }
 }
 
+// Byte keys, sixteen bytes a thread (one 16-byte load, two 16-byte stores);
+// the tail of n mod 16 bytes one by one.  Needs a 16-byte aligned input.
+__global__ __launch_bounds__(256) void k_hx_keys_u8(const uint8_t* __restrict__ in, uint64_t n,
+                                                    uint16_t* __restrict__ key) {
+  const uint64_t n16 = n / 16;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  const uint4* src = reinterpret_cast<const uint4*>(in);
+  uint4* dst = reinterpret_cast<uint4*>(key);
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) {
+    const uint4 w = src[i];
+    const uint32_t a[4] = {w.x, w.y, w.z, w.w};
+    uint32_t o[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      o[2 * k] = (a[k] & 0xFFu) | ((a[k] & 0xFF00u) << 8);
+      o[2 * k + 1] = ((a[k] >> 16) & 0xFFu) | ((a[k] >> 8) & 0xFF0000u);
+    }
+    dst[2 * i] = make_uint4(o[0], o[1], o[2], o[3]);
+    dst[2 * i + 1] = make_uint4(o[4], o[5], o[6], o[7]);
+  }
+  for (uint64_t i = n16 * 16 + (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    key[i] = in[i];
+}
+
 // Escaped values of each chunk at zpre[chunk] + rank in the escape section,
 // which starts right after the coded section (sec + lay->end).
 template <typename T>
@@ -213,8 +237,14 @@ void launch_hx_keys(const void* in, uint64_t n, int type, int64_t lo, int64_t hi
   const dim3 grid(hx_blocks(nc)), blk(64 * kHxWaves);
   switch (type) {
     case MGC_HX_U8:
-      hipLaunchKernelGGL((k_hx_keys<uint8_t, false>), grid, blk, 0, s,
-                         static_cast<const uint8_t*>(in), n, lo, hi, esc, key, zc, nc);
+      if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(key)) % 16 == 0) {
+        const uint64_t b = (n / 16 + 255) / 256;
+        hipLaunchKernelGGL(k_hx_keys_u8, dim3((unsigned)std::max<uint64_t>(1, std::min<uint64_t>(b, 8192))),
+                           dim3(256), 0, s, static_cast<const uint8_t*>(in), n, key);
+      } else {
+        hipLaunchKernelGGL((k_hx_keys<uint8_t, false>), grid, blk, 0, s,
+                           static_cast<const uint8_t*>(in), n, lo, hi, esc, key, zc, nc);
+      }
       break;
     case MGC_HX_U16:
       hipLaunchKernelGGL((k_hx_keys<uint16_t, false>), grid, blk, 0, s,

@@ -148,8 +148,14 @@ size_t decode_tables_bytes();
 
 // The Huffman stage's kernels take an optional gate (a compression's status
 // word; see gate_closed): a null gate runs them unconditionally.
+// The histogram counts symbols win_lo .. win_lo + kHistWindow - 1 and the
+// symbol `hot` in LDS (the rest with global atomics); the default window is
+// centred on the compressor's zero symbol and hot is its escape symbol.
+constexpr uint32_t kHistWindow = 32768;
+constexpr uint32_t kHistWinLo = kHalf - kHistWindow / 2;
 void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s,
-                      const unsigned* gate = nullptr);
+                      const unsigned* gate = nullptr, uint32_t win_lo = kHistWinLo,
+                      uint32_t hot = 0);
 void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
                      uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
                      hipStream_t s, const unsigned* gate = nullptr);

@@ -8,7 +8,11 @@ those files are not available, so these generators stand in for their shapes:
 
 * ``bumps``      a sum of Gaussian bumps plus white noise (smooth field);
 * ``grf``        an isotropic Gaussian random field with power ~ |k|^-3;
-* ``sinusoids``  a 2D sum of plane waves with amplitudes decaying as 1/k.
+* ``sinusoids``  a 2D sum of plane waves with amplitudes decaying as 1/k;
+* ``zipf_bytes`` / ``laplace_ints``  byte and integer streams for the
+  standalone Huffman codec: Zipf-like bytes, and Laplacian integers around
+  zero (the shape of quantised multilevel coefficients) with a fraction of
+  arbitrary values.
 
 Every generator uses ``numpy.random.default_rng(seed)`` (PCG64) and draws its
 random numbers in the order stated in its docstring, so the same seed gives
@@ -18,7 +22,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["bumps", "grf", "sinusoids", "batch_specs", "field_from_spec"]
+__all__ = ["bumps", "grf", "sinusoids", "batch_specs", "field_from_spec", "zipf_bytes",
+           "laplace_ints"]
 
 
 def _axis_coords(n: int) -> np.ndarray:
@@ -139,3 +144,27 @@ def field_from_spec(spec, dtype=np.float32) -> np.ndarray:
     if spec["kind"] == "bumps":
         return bumps(spec["shape"], spec["seed"], dtype=dtype)
     return grf(spec["shape"], spec["seed"], dtype=dtype)
+
+
+def zipf_bytes(n: int, seed: int, s: float = 1.2) -> np.ndarray:
+    """n bytes with P(b) proportional to (b + 1)^-s.  Draws n 16-bit uniform
+    integers and maps each through the inverse CDF sampled at 65536 points."""
+    p = 1.0 / np.arange(1, 257, dtype=np.float64) ** s
+    cdf = np.cumsum(p) / p.sum()
+    table = np.minimum(np.searchsorted(cdf, (np.arange(65536) + 0.5) / 65536), 255).astype(np.uint8)
+    rng = np.random.default_rng(seed)
+    return table[rng.integers(0, 65536, size=n, dtype=np.uint16)]
+
+
+def laplace_ints(n: int, seed: int, dtype=np.int32, scale: float = 8.0,
+                 wild: float = 1e-3) -> np.ndarray:
+    """n integers: Laplace(0, scale) rounded to the nearest integer, then a
+    fraction ``wild`` of positions (uniform draws below wild) replaced by
+    uniform values over the whole type.  Draw order: the n Laplace variates,
+    the n selection uniforms, then the replacement values."""
+    rng = np.random.default_rng(seed)
+    info = np.iinfo(dtype)
+    v = np.round(rng.laplace(0.0, scale, size=n)).astype(dtype)
+    m = rng.random(n) < wild
+    v[m] = rng.integers(info.min, info.max, size=int(m.sum()), dtype=dtype, endpoint=True)
+    return v
