@@ -89,7 +89,9 @@ def stage_bytes(N: int, Nc: int, in_size: int, stream_bytes: int):
         "dec_level[finest]": in_size * N + 2 * new + 8 * Nc,
         "thomas_ax0[finest]": 2 * 8 * Nc,
         "thomas_ax1[finest]": 2 * 8 * Nc,
-        "thomas_ax2[finest]": 2 * 8 * Nc,
+        # recomposition sweeps the contiguous axis last and also reads the
+        # values it subtracts from: the mean of 2 and 3 passes per launch
+        "thomas_ax2[finest]": 5 * 4 * Nc,
         "histogram": 2 * N,
         "chunk_words": 2 * N,
         "encode": 2 * N + stream_bytes,
