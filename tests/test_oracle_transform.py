@@ -205,3 +205,24 @@ def test_finest_coefficients_at_equals_decompose(shape):
     assert len(pos) == b - a                      # one per new node
     assert np.array_equal(np.sort(pos), np.arange(a, b))
     assert np.max(np.abs(c - full[pos])) <= 1e-14 * max(1.0, float(np.max(np.abs(u))))
+
+
+@pytest.mark.parametrize("shape", [(17, 9, 13), (33, 33, 33), (65, 40), (100,), (5, 1, 7), (2, 3)])
+def test_finest_coefficients_at_equals_the_decomposition(shape):
+    # the one-by-one sampler the full-size GPU checks use: at every input
+    # index it must return the finest level's coefficient (value minus the
+    # multilinear interpolant of the coarse corners) at its stream position,
+    # exactly as the level-by-level decomposition stores it
+    rng = np.random.default_rng(len(shape) * 7 + shape[0])
+    u = rng.standard_normal(shape)
+    u += np.cumsum(np.cumsum(u, axis=0), axis=-1) * 0.1
+    h = Hierarchy(shape)
+    stream = oracle.decompose(u, h)
+    pos, c = oracle.transform.finest_coefficients_at(u, h, np.arange(u.size))
+    lo, hi = level_slices(h)[h.L]
+    if h.L == 0:
+        assert np.array_equal(pos, np.arange(u.size))
+    else:
+        assert np.array_equal(np.sort(pos), np.arange(lo, hi))   # every new node once
+    scale = float(np.max(np.abs(u)))
+    assert np.max(np.abs(stream[pos] - c)) <= 1e-13 * scale
