@@ -161,6 +161,65 @@ mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* 
                           size_t out_cap, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Host-resident arrays (Section V: the host-device execution model, the
+ * three-queue pipeline with two buffer pairs, Algorithm "Adaptive
+ * Pipeline").  The array is cut along its slowest axis into chunks of whole
+ * planes; each chunk is compressed as an array of its own (the same bound:
+ * absolute tau for L-inf, tau * sqrt(chunk values / values) for L2, so the
+ * whole array keeps the requested bound) while the next chunk is copied in
+ * and the previous stream copied out on three HIP streams.  A relative bound
+ * first streams the array through the range pass (one more host-to-device
+ * copy of the data) to fix tau.  Chunk sizes start at init_chunk_bytes and
+ * follow C_next = min(max(Theta(C / Phi(C)), C), limit_chunk_bytes, rest),
+ * Phi(C) = phi_alpha C + phi_beta below phi_threshold and phi_gamma above
+ * (compression throughput, bytes/s), Theta(t) = t * h2d_bytes_per_s; with
+ * phi_gamma = 0 every chunk has init_chunk_bytes.  mgc_pipe_profile fits
+ * Phi and measures the copy bandwidth on a prefix of the data.
+ *
+ * Container (little-endian): u32 magic 0x5043474D, u32 chunk count, u8
+ * dtype, norm, mode, ndim, u32 0, u64 shape[3], f64 bound, f64 tau, u64
+ * total bytes (64-byte header); per chunk {u64 first plane, u64 planes, u64
+ * stream offset, u64 stream bytes}; the chunk streams (mgc_compress's
+ * format), each at a multiple of 8 bytes.  mgc_pipe_info parses a host copy
+ * of the header (ndim, shape, dtype, total bytes, chunk count).
+ *
+ * h_in / h_out are host memory (pinned memory lets the copies overlap the
+ * kernels; pageable memory works but the copies then wait).  The calls are
+ * BLOCKING and allocate their device buffers (two input, two output, one
+ * workspace) for the call.  stats (optional) receives seconds spent in
+ * host-to-device copies, kernels, device-to-host copies, the relative-bound
+ * pre-pass and overall, the overlap ratio (copy time overlapped by kernel
+ * time over all copy time) and the chunk count.
+ * Errors: MGC_EINVAL (arguments, NaN/Inf data), MGC_ENOSPC (out_cap),
+ * MGC_ERANGE, MGC_EFORMAT (container), MGC_EUNSUPPORTED, MGC_EDEVICE.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  uint64_t init_chunk_bytes;   /* C_init (0: 64 MiB) */
+  uint64_t limit_chunk_bytes;  /* C_limit (0: 1 GiB) */
+  double phi_alpha, phi_beta;  /* Phi(C) = alpha C + beta below the threshold (bytes/s) */
+  double phi_gamma;            /* Phi(C) = gamma from the threshold on; 0 = fixed chunks */
+  uint64_t phi_threshold;      /* bytes */
+  double h2d_bytes_per_s;      /* Theta(t) = t * h2d_bytes_per_s */
+} mgc_pipe_model;
+typedef struct {
+  double total_s, h2d_s, kernel_s, d2h_s, prepass_s, overlap;
+  uint64_t chunks;
+} mgc_pipe_stats;
+mgc_status mgc_pipe_max_bytes(int ndim, const uint64_t* shape, mgc_dtype dtype,
+                              const mgc_pipe_model* model, size_t* max_out_bytes);
+mgc_status mgc_pipe_compress(mgc_ctx ctx, const void* h_in, int ndim, const uint64_t* shape,
+                             mgc_dtype dtype, double error_bound, mgc_norm norm, mgc_mode mode,
+                             const mgc_pipe_model* model, void* h_out, size_t out_cap,
+                             uint64_t* h_out_size, mgc_pipe_stats* stats);
+mgc_status mgc_pipe_info(const void* h_in, size_t in_bytes, int* ndim, uint64_t* shape3,
+                         mgc_dtype* dtype, uint64_t* total, uint64_t* chunks);
+mgc_status mgc_pipe_decompress(mgc_ctx ctx, const void* h_in, size_t in_bytes, void* h_out,
+                               size_t out_cap, mgc_pipe_stats* stats);
+mgc_status mgc_pipe_profile(mgc_ctx ctx, const void* h_in, int ndim, const uint64_t* shape,
+                            mgc_dtype dtype, double error_bound, mgc_norm norm, mgc_mode mode,
+                            mgc_pipe_model* model);
+
+/* ------------------------------------------------------------------------
  * Transform only (Algorithm 1 without quantisation): the multilevel
  * coefficients as FP64 values in stream order - the coarsest level's nodal
  * values row-major, then for each finer level its 2^D - 1 subbands (subband

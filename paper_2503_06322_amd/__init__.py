@@ -14,6 +14,7 @@ Entry points (same names as the C functions, without the ``mgc_`` prefix):
 ``compress_batched(tensors, bounds)`` / ``Batch`` (one graph launch for many arrays)
 ``huffman_encode(symbols, C=1024)`` / ``huffman_decode(stream, n)``
 ``hx_compress(x, dict, base, C)`` / ``hx_decompress(stream)`` (Huffman-X lossless codec)
+``pipe_compress(host_x, bound)`` / ``pipe_decompress(container)`` / ``pipe_profile`` (host-resident arrays)
 ``header_info(stream)``, ``profile_enable / profile_reset / profile_read``
 """
 from __future__ import annotations
@@ -27,7 +28,8 @@ __all__ = ["MgcError", "library_path", "compress", "compress_async", "decompress
            "huffman_decode", "header_info", "profile_enable", "profile_reset", "profile_read",
            "compress_query", "transform_query", "batch_query", "Batch", "compress_batched",
            "set_tuning", "tuning_info", "set_decoder", "decoder_info", "compress_noalloc",
-           "NOALLOC_SCRATCH_BYTES", "hx_query", "hx_compress", "hx_decompress", "hx_header"]
+           "NOALLOC_SCRATCH_BYTES", "hx_query", "hx_compress", "hx_decompress", "hx_header",
+           "pipe_max_bytes", "pipe_compress", "pipe_decompress", "pipe_profile"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmgc.so")
@@ -40,6 +42,28 @@ _STATUS = {0: "OK", 1: "EINVAL", 2: "EUNSUPPORTED", 3: "ENOSPC", 4: "EFORMAT",
 _NORM = {"linf": 0, "l2": 1}
 _MODE = {"rel": 0, "abs": 1}
 HEADER_PREFIX = 128 + 8 * 63
+
+
+class PipeModel(ctypes.Structure):
+    """mgc_pipe_model: chunk sizes and the throughput models of the pipeline."""
+    _fields_ = [("init_chunk_bytes", ctypes.c_uint64), ("limit_chunk_bytes", ctypes.c_uint64),
+                ("phi_alpha", ctypes.c_double), ("phi_beta", ctypes.c_double),
+                ("phi_gamma", ctypes.c_double), ("phi_threshold", ctypes.c_uint64),
+                ("h2d_bytes_per_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PipeStats(ctypes.Structure):
+    """mgc_pipe_stats: seconds per kind of task, overlap ratio, chunk count."""
+    _fields_ = [("total_s", ctypes.c_double), ("h2d_s", ctypes.c_double),
+                ("kernel_s", ctypes.c_double), ("d2h_s", ctypes.c_double),
+                ("prepass_s", ctypes.c_double), ("overlap", ctypes.c_double),
+                ("chunks", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class MgcError(RuntimeError):
@@ -96,6 +120,17 @@ def _load():
                                    vp, ctypes.c_size_t, vp, c_u64p],
             "mgc_huffman_decode": [vp, vp, ctypes.c_size_t, vp, ctypes.c_uint64, vp,
                                    ctypes.c_size_t, vp],
+            "mgc_pipe_max_bytes": [ctypes.c_int, c_u64p, ctypes.c_int,
+                                   ctypes.POINTER(PipeModel), c_szp],
+            "mgc_pipe_compress": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_int, ctypes.POINTER(PipeModel), vp,
+                                  ctypes.c_size_t, c_u64p, ctypes.POINTER(PipeStats)],
+            "mgc_pipe_decompress": [vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t,
+                                    ctypes.POINTER(PipeStats)],
+            "mgc_pipe_info": [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), c_u64p,
+                              ctypes.POINTER(ctypes.c_int), c_u64p, c_u64p],
+            "mgc_pipe_profile": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_int, ctypes.POINTER(PipeModel)],
             "mgc_hx_query": [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, c_szp, c_szp],
             "mgc_hx_compress": [vp, vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
                                 ctypes.c_int64, ctypes.c_uint32, vp, ctypes.c_size_t, vp,
@@ -735,6 +770,86 @@ def hx_decompress(stream, workspace=None, out=None):
                                      _hx_types()[dtype], ctypes.c_void_p(ws.data_ptr()),
                                      ws.numel(), _stream_ptr(dev)))
     return y[:n]
+
+
+def _pipe_model(model):
+    m = PipeModel()
+    if model:
+        for k, v in dict(model).items():
+            setattr(m, k, v)
+    return m
+
+
+def _require_host(t, what):
+    if t.device.type != "cpu":
+        raise ValueError("%s must be a host (CPU) tensor" % what)
+
+
+def pipe_max_bytes(shape, dtype, model=None) -> int:
+    shp = _shape_arg(shape)
+    out = ctypes.c_size_t()
+    m = _pipe_model(model)
+    _check(_load().mgc_pipe_max_bytes(len(shape), shp, _dtype_code(dtype), ctypes.byref(m),
+                                      ctypes.byref(out)))
+    return out.value
+
+
+def pipe_compress(x, error_bound: float, norm: str = "linf", mode: str = "rel", model=None,
+                  out=None, device: int = 0):
+    """Compress a host (CPU, preferably pinned) FP32/FP64 tensor through the
+    chunked host-device pipeline.  Returns (container as a uint8 CPU tensor,
+    stats dict)."""
+    torch = _torch()
+    _require_host(x, "x")
+    x = x.contiguous()
+    shp = _shape_arg(tuple(x.shape))
+    m = _pipe_model(model)
+    if out is None:
+        out = torch.empty(pipe_max_bytes(tuple(x.shape), x.dtype, model), dtype=torch.uint8,
+                          pin_memory=True)
+    size = ctypes.c_uint64()
+    st = PipeStats()
+    _check(_load().mgc_pipe_compress(_ctx(device), ctypes.c_void_p(x.data_ptr()), x.dim(), shp,
+                                     _dtype_code(x.dtype), error_bound, _NORM[norm], _MODE[mode],
+                                     ctypes.byref(m), ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                     ctypes.byref(size), ctypes.byref(st)))
+    return out[: size.value], st.as_dict()
+
+
+def pipe_decompress(container, out=None, device: int = 0):
+    """Array of a pipeline container (uint8 CPU tensor) as a CPU tensor.
+    Returns (array, stats dict)."""
+    torch = _torch()
+    _require_host(container, "container")
+    container = container.contiguous()
+    nd = ctypes.c_int()
+    shp = (ctypes.c_uint64 * 3)()
+    dt = ctypes.c_int()
+    _check(_load().mgc_pipe_info(ctypes.c_void_p(container.data_ptr()), container.numel(),
+                                 ctypes.byref(nd), shp, ctypes.byref(dt), None, None))
+    shape = tuple(int(shp[d]) for d in range(nd.value))
+    dtype = torch.float32 if dt.value == 0 else torch.float64
+    if out is None:
+        out = torch.empty(shape, dtype=dtype, pin_memory=True)
+    st = PipeStats()
+    _check(_load().mgc_pipe_decompress(_ctx(device), ctypes.c_void_p(container.data_ptr()),
+                                       container.numel(), ctypes.c_void_p(out.data_ptr()),
+                                       out.numel() * out.element_size(), ctypes.byref(st)))
+    return out, st.as_dict()
+
+
+def pipe_profile(x, error_bound: float, norm: str = "linf", mode: str = "rel", model=None,
+                 device: int = 0):
+    """Fit the pipeline's throughput models on a host tensor; returns the
+    model dict for pipe_compress."""
+    _require_host(x, "x")
+    x = x.contiguous()
+    shp = _shape_arg(tuple(x.shape))
+    m = _pipe_model(model)
+    _check(_load().mgc_pipe_profile(_ctx(device), ctypes.c_void_p(x.data_ptr()), x.dim(), shp,
+                                    _dtype_code(x.dtype), error_bound, _NORM[norm], _MODE[mode],
+                                    ctypes.byref(m)))
+    return m.as_dict()
 
 
 def profile_enable(flag: bool = True, device: int = 0):

@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmgc.so")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "api.cpp", "batched.cpp", "transform.hip", "huffman.hip", "hx.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "batched.cpp", "pipeline.cpp", "transform.hip", "huffman.hip",
+           "hx.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
           "-ffp-contract=off", "-Wall", "-Wno-unused-function"]

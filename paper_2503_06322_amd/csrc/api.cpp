@@ -140,6 +140,12 @@ DecompressWs carve_decompress(Carver& c, const Plan& p) {
   return w;
 }
 
+size_t decompress_ws_bytes(const Plan& p) {
+  Carver c(nullptr);
+  carve_decompress(c, p);
+  return c.off;
+}
+
 size_t dtype_size(mgc_dtype d) { return d == MGC_F32 ? 4 : 8; }
 
 // Parses and validates a stream header held in host memory.
@@ -459,6 +465,82 @@ HxWs carve_hx(Carver& c, uint64_t n, int type, uint32_t C) {
 }
 }  // namespace
 
+namespace mgc {
+// Decompression launches on stream s for a stream whose first head_bytes
+// (header and bins) the host already holds; returns the device status word
+// the decoder sets (ST_FORMAT on corrupt data), or null when nothing was
+// decoded (empty or constant arrays).
+const unsigned* decompress_enqueue(mgc_ctx ctx, const uint8_t* head, size_t head_bytes,
+                                   const void* d_in, size_t in_bytes, void* d_out,
+                                   size_t out_cap, void* d_ws, size_t ws_bytes, hipStream_t s) {
+  Header h;
+  std::vector<double> q;
+  parse_header(head, head_bytes, &h, &q);
+  const Plan& p = get_plan(ctx, h.ndim, h.shape);
+  const mgc_dtype dt = (mgc_dtype)h.dtype;
+  if ((uint64_t)p.N != h.N) fail(MGC_EFORMAT, "header size inconsistent with its shape");
+  if (h.total > in_bytes) fail(MGC_EFORMAT, "truncated stream");
+  if (out_cap < (size_t)p.N * dtype_size(dt)) fail(MGC_ENOSPC, "output capacity too small");
+  if (h.flags & FLAG_EMPTY) return nullptr;
+  if (h.flags & FLAG_CONSTANT) {
+    launch_fill(d_out, dt == MGC_F32, p.N, h.const_value, s);
+    MGC_HIP(hipGetLastError());
+    return nullptr;
+  }
+  if (h.L != (uint32_t)p.L || h.S != kDict || h.C < 1 || h.C > (1u << 20) ||
+      h.n_chunks != (h.N + h.C - 1) / h.C || h.n_codes > kDict || h.n_codes < 1 ||
+      h.n_outliers > h.N || h.n_words < 1)
+    fail(MGC_EFORMAT, "inconsistent header counts");
+  const uint64_t cb = kHeaderBytes + 8 * (h.L + 1);
+  const uint64_t off = pad8(cb + 3 * h.n_codes);
+  const uint64_t opos = off + 8 * (h.n_chunks + 1);
+  const uint64_t oval = opos + 8 * h.n_outliers;
+  const uint64_t words = oval + 8 * h.n_outliers;
+  const uint64_t end = pad8(words + 4 * h.n_words);
+  if (end != h.total) fail(MGC_EFORMAT, "section sizes disagree with the stream length");
+  Carver meas(nullptr);
+  carve_decompress(meas, p);
+  if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
+  Carver c(d_ws);
+  DecompressWs w = carve_decompress(c, p);
+  const uint8_t* in = static_cast<const uint8_t*>(d_in);
+  {
+    // (the table build clears the status words first)
+    StageScope st(&ctx->prof, "decode_tables", s);
+    launch_decode_tables(in + cb, h.n_codes, static_cast<DecodeTables*>(w.tables), w.status, s);
+  }
+  {
+    StageScope st(&ctx->prof, "decode", s);
+    ctx->dec_last = launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, p.N,
+                                  h.n_codes, static_cast<const DecodeTables*>(w.tables),
+                                  w.sym, w.status, s, ctx->dec_force);
+  }
+  CoeffSrc src{w.sym, nullptr, reinterpret_cast<const uint64_t*>(in + opos),
+               reinterpret_cast<const int64_t*>(in + oval), (int64_t)h.n_outliers};
+  if (p.L >= 2) {
+    // levels 0 .. L-2 dequantised ahead (escaped values resolved once)
+    LevelBins lb{};
+    lb.n = p.L - 1;
+    for (int l = 0; l < lb.n; ++l) {
+      lb.off[l] = p.lv[l].off;
+      lb.q[l] = q[l];
+    }
+    const int64_t m = p.points(p.L - 2);
+    {
+      StageScope st(&ctx->prof, "dequant_coarse", s);
+      launch_dequant_prefix(src, m, lb, w.coarse, s);
+    }
+    const CoeffSrc coarse{nullptr, w.coarse, nullptr, nullptr, 0};
+    run_levels_recompose(ctx, p, src, q, w.gA, w.gB, d_out, dt == MGC_F32, s, nullptr,
+                         &coarse, p.L - 2);
+  } else {
+    run_levels_recompose(ctx, p, src, q, w.gA, w.gB, d_out, dt == MGC_F32, s);
+  }
+  MGC_HIP(hipGetLastError());
+  return w.status;
+}
+}  // namespace mgc
+
 extern "C" {
 
 int mgc_version(void) { return 1; }
@@ -740,72 +822,12 @@ mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* 
     const size_t pre = std::min<size_t>(in_bytes, kHeaderBytes + 8 * (kMaxLevels + 1));
     if (pre < (size_t)kHeaderBytes) fail(MGC_EFORMAT, "stream shorter than its header");
     sync_read(ctx, ctx->pinned, d_in, pre, s);
-    Header h;
-    std::vector<double> q;
-    parse_header(ctx->pinned, pre, &h, &q);
-    const Plan& p = get_plan(ctx, h.ndim, h.shape);
-    const mgc_dtype dt = (mgc_dtype)h.dtype;
-    if ((uint64_t)p.N != h.N) fail(MGC_EFORMAT, "header size inconsistent with its shape");
-    if (h.total > in_bytes) fail(MGC_EFORMAT, "truncated stream");
-    if (out_cap < (size_t)p.N * dtype_size(dt)) fail(MGC_ENOSPC, "output capacity too small");
-    if (h.flags & FLAG_EMPTY) return;
-    if (h.flags & FLAG_CONSTANT) {
-      launch_fill(d_out, dt == MGC_F32, p.N, h.const_value, s);
-      MGC_HIP(hipGetLastError());
-      return;
-    }
-    if (h.L != (uint32_t)p.L || h.S != kDict || h.C < 1 || h.C > (1u << 20) ||
-        h.n_chunks != (h.N + h.C - 1) / h.C || h.n_codes > kDict || h.n_codes < 1 ||
-        h.n_outliers > h.N || h.n_words < 1)
-      fail(MGC_EFORMAT, "inconsistent header counts");
-    const uint64_t cb = kHeaderBytes + 8 * (h.L + 1);
-    const uint64_t off = pad8(cb + 3 * h.n_codes);
-    const uint64_t opos = off + 8 * (h.n_chunks + 1);
-    const uint64_t oval = opos + 8 * h.n_outliers;
-    const uint64_t words = oval + 8 * h.n_outliers;
-    const uint64_t end = pad8(words + 4 * h.n_words);
-    if (end != h.total) fail(MGC_EFORMAT, "section sizes disagree with the stream length");
-    Carver meas(nullptr);
-    carve_decompress(meas, p);
-    if (ws_bytes < meas.off) fail(MGC_ENOSPC, "workspace too small");
-    Carver c(d_ws);
-    DecompressWs w = carve_decompress(c, p);
-    const uint8_t* in = static_cast<const uint8_t*>(d_in);
-    {
-      // (the table build clears the status words first)
-      StageScope st(&ctx->prof, "decode_tables", s);
-      launch_decode_tables(in + cb, h.n_codes, static_cast<DecodeTables*>(w.tables), w.status, s);
-    }
-    {
-      StageScope st(&ctx->prof, "decode", s);
-      ctx->dec_last = launch_decode(in, off, words, h.n_chunks, h.n_words, (int)h.C, p.N,
-                                    h.n_codes, static_cast<const DecodeTables*>(w.tables),
-                                    w.sym, w.status, s, ctx->dec_force);
-    }
-    CoeffSrc src{w.sym, nullptr, reinterpret_cast<const uint64_t*>(in + opos),
-                 reinterpret_cast<const int64_t*>(in + oval), (int64_t)h.n_outliers};
-    if (p.L >= 2) {
-      // levels 0 .. L-2 dequantised ahead (escaped values resolved once)
-      LevelBins lb{};
-      lb.n = p.L - 1;
-      for (int l = 0; l < lb.n; ++l) {
-        lb.off[l] = p.lv[l].off;
-        lb.q[l] = q[l];
-      }
-      const int64_t m = p.points(p.L - 2);
-      {
-        StageScope st(&ctx->prof, "dequant_coarse", s);
-        launch_dequant_prefix(src, m, lb, w.coarse, s);
-      }
-      const CoeffSrc coarse{nullptr, w.coarse, nullptr, nullptr, 0};
-      run_levels_recompose(ctx, p, src, q, w.gA, w.gB, d_out, dt == MGC_F32, s, nullptr,
-                           &coarse, p.L - 2);
-    } else {
-      run_levels_recompose(ctx, p, src, q, w.gA, w.gB, d_out, dt == MGC_F32, s);
-    }
-    MGC_HIP(hipGetLastError());
+    std::vector<uint8_t> head(ctx->pinned, ctx->pinned + pre);
+    const unsigned* status =
+        decompress_enqueue(ctx, head.data(), pre, d_in, in_bytes, d_out, out_cap, d_ws, ws_bytes, s);
+    if (!status) return;
     unsigned st = 0;
-    sync_read(ctx, ctx->pinned, w.status, sizeof(unsigned), s);
+    sync_read(ctx, ctx->pinned, status, sizeof(unsigned), s);
     std::memcpy(&st, ctx->pinned, sizeof(unsigned));
     if (st & ST_FORMAT) fail(MGC_EFORMAT, "corrupt coded data");
   });

@@ -146,4 +146,13 @@ struct mgc_ctx_s {
 namespace mgc {
 void check_ctx(mgc_ctx ctx);
 const Plan& get_plan(mgc_ctx ctx, int ndim, const uint64_t* shape);
+// Decompression launches on stream s for a stream whose header and bins
+// (the first head_bytes, at least 128 + 8 (L + 1)) the host already holds;
+// returns the device status word the decoder sets (ST_FORMAT on corrupt
+// data), or null when nothing was decoded (empty or constant arrays).
+const unsigned* decompress_enqueue(mgc_ctx ctx, const uint8_t* head, size_t head_bytes,
+                                   const void* d_in, size_t in_bytes, void* d_out,
+                                   size_t out_cap, void* d_ws, size_t ws_bytes, hipStream_t s);
+// Decompression workspace bytes of an array (its plan).
+size_t decompress_ws_bytes(const Plan& p);
 }  // namespace mgc
