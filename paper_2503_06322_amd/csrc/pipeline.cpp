@@ -213,13 +213,16 @@ void read_small(mgc_ctx ctx, void* host, const void* dev, size_t n, hipStream_t 
 }
 
 // min, max, sum of squares of the whole array: chunks streamed through the
-// range pass on two streams.
+// range pass on two streams.  With `resident` (a device copy of the whole
+// array) the chunks are copied there and stay for the compression.
 void range_prepass(mgc_ctx ctx, const uint8_t* h_in, int ndim, const uint64_t* shape,
-                   mgc_dtype dt, uint64_t chunk_bytes, Queues& Q, double r[3]) {
+                   mgc_dtype dt, uint64_t chunk_bytes, Queues& Q, double r[3],
+                   uint8_t* resident) {
   const uint64_t pb = plane_values(ndim, shape) * esize(dt);
   const uint64_t cp = planes_of(chunk_bytes, pb);
   DevMem in[2], part, bud, st;
-  for (auto& b : in) b.need(cp * pb);
+  if (!resident)
+    for (auto& b : in) b.need(cp * pb);
   part.need(2 * 8 * 4 * (size_t)kRangeBlocks);
   bud.need(2 * 8 * 128);
   st.need(2 * 16);
@@ -232,7 +235,7 @@ void range_prepass(mgc_ctx ctx, const uint8_t* h_in, int ndim, const uint64_t* s
   for (uint64_t k = 0; k < nck; ++k) {
     hipStream_t s = Q.q[k % 2];
     const uint64_t p0 = k * cp, np = std::min(cp, shape[0] - p0);
-    void* dst = in[k % 2].p;
+    void* dst = resident ? static_cast<void*>(resident + p0 * pb) : in[k % 2].p;
     MGC_HIP(hipMemcpyAsync(dst, h_in + p0 * pb, np * pb, hipMemcpyHostToDevice, s));
     BudgetIn b{};
     b.dtype = dt;
@@ -300,12 +303,23 @@ mgc_status mgc_pipe_compress(mgc_ctx ctx, const void* h_in, int ndim, const uint
     uint8_t* out = static_cast<uint8_t*>(h_out);
     Queues Q;
     mgc_pipe_stats st{};
+    // Arrays that fit in a quarter of the free device memory stay resident
+    // once copied: the chunks of a relative bound's range pass are then the
+    // compression's input, and no chunk waits for an input buffer.
+    DevMem Res;
+    {
+      size_t free_b = 0, total_b = 0;
+      MGC_HIP(hipMemGetInfo(&free_b, &total_b));
+      if (N * esize(dtype) <= free_b / 4) Res.need(N * esize(dtype));
+    }
+    const bool resident = Res.p != nullptr;
     // the absolute bound of the whole array
     double tau = error_bound;
     if (mode == MGC_REL) {
       const double a = now_s();
       double r[3];
-      range_prepass(ctx, src, ndim, shape, dtype, m.limit_chunk_bytes, Q, r);
+      range_prepass(ctx, src, ndim, shape, dtype, m.limit_chunk_bytes, Q, r,
+                    static_cast<uint8_t*>(Res.p));
       tau = norm == MGC_LINF ? error_bound * (r[1] - r[0]) : error_bound * std::sqrt(r[2]);
       if (r[1] == r[0]) tau = 1.0;  // constant array: every chunk stores its value
       st.prepass_s = now_s() - a;
@@ -333,9 +347,21 @@ mgc_status mgc_pipe_compress(mgc_ctx ctx, const void* h_in, int ndim, const uint
     chunk_shape(ndim, shape, maxp, cs);
     size_t ws_n = 0, so_n = 0;
     if (mgc_compress_query(ndim, cs, dtype, 0, &ws_n, &so_n) != MGC_OK) throw Fail{MGC_EINVAL};
-    DevMem I[2], O[2], W, R;
-    for (auto& b : I) b.need(maxp * pb);
-    for (auto& b : O) b.need(so_n);
+    DevMem I[2], O[2], W, R, OR;
+    if (!resident)
+      for (auto& b : I) b.need(maxp * pb);
+    if (resident) {  // every chunk's stream in its own slot when they fit
+      size_t free_b = 0, total_b = 0;
+      MGC_HIP(hipMemGetInfo(&free_b, &total_b));
+      if ((size_t)K * so_n <= free_b / 4) OR.need((size_t)K * so_n);
+    }
+    const bool out_resident = OR.p != nullptr;
+    auto input_of = [&](size_t i) -> void* {
+      return resident ? static_cast<void*>(static_cast<uint8_t*>(Res.p) + ent[i].first * pb)
+                      : I[i % 2].p;
+    };
+    if (!out_resident)
+      for (auto& b : O) b.need(so_n);
     W.need(ws_n);
     R.need(2 * 16);
     Timeline tl;
@@ -344,11 +370,13 @@ mgc_status mgc_pipe_compress(mgc_ctx ctx, const void* h_in, int ndim, const uint
     for (auto s : Q.q) MGC_HIP(hipStreamWaitEvent(s, tl.base, 0));
     std::vector<size_t> t_in(K), t_k(K), t_out(K);
     uint64_t off = pad8(table);
+    const bool copied = resident && mode == MGC_REL;  // the range pass brought it in
     auto copy_in = [&](size_t i) {
+      if (copied) return;
       hipStream_t s = Q.q[i % 3];
-      if (i >= 2) MGC_HIP(hipStreamWaitEvent(s, tl.done(t_k[i - 2]), 0));  // input buffer free
+      if (i >= 2 && !resident) MGC_HIP(hipStreamWaitEvent(s, tl.done(t_k[i - 2]), 0));
       t_in[i] = tl.begin(0, s);
-      MGC_HIP(hipMemcpyAsync(I[i % 2].p, src + ent[i].first * pb, ent[i].planes * pb,
+      MGC_HIP(hipMemcpyAsync(input_of(i), src + ent[i].first * pb, ent[i].planes * pb,
                              hipMemcpyHostToDevice, s));
       tl.end(t_in[i], s);
     };
@@ -356,15 +384,20 @@ mgc_status mgc_pipe_compress(mgc_ctx ctx, const void* h_in, int ndim, const uint
     for (size_t i = 0; i < K; ++i) {
       hipStream_t s = Q.q[i % 3];
       if (i + 1 < K) copy_in(i + 1);
-      if (i >= 2) MGC_HIP(hipStreamWaitEvent(s, tl.done(t_out[i - 2]), 0));  // output buffer free
+      if (i >= 2 && !out_resident)
+        MGC_HIP(hipStreamWaitEvent(s, tl.done(t_out[i - 2]), 0));  // output buffer free
+      DevMem& Ob = O[i % 2];
+      uint8_t* obuf = out_resident ? static_cast<uint8_t*>(OR.p) + i * so_n
+                                   : static_cast<uint8_t*>(Ob.p);
+      size_t ocap = out_resident ? so_n : Ob.n;
       chunk_shape(ndim, shape, ent[i].planes, cs);
       const double tc = norm == MGC_LINF
                             ? tau
                             : tau * std::sqrt((double)(ent[i].planes * pv) / (double)N);
       uint64_t* res = static_cast<uint64_t*>(R.p) + 2 * (i % 2);
       t_k[i] = tl.begin(1, s);
-      mgc_status rc = mgc_compress(ctx, I[i % 2].p, ndim, cs, dtype, tc, norm, MGC_ABS, 0,
-                                   O[i % 2].p, O[i % 2].n, W.p, W.n, res, s);
+      mgc_status rc = mgc_compress(ctx, input_of(i), ndim, cs, dtype, tc, norm, MGC_ABS, 0,
+                                   obuf, ocap, W.p, W.n, res, s);
       if (rc != MGC_OK) throw Fail{rc};
       uint64_t r2[2];
       read_small(ctx, r2, res, 16, s);
@@ -373,10 +406,15 @@ mgc_status mgc_pipe_compress(mgc_ctx ctx, const void* h_in, int ndim, const uint
         const uint64_t cap = r2[1];
         size_t w2 = 0, o2 = 0;
         if (mgc_compress_query(ndim, cs, dtype, cap, &w2, &o2) != MGC_OK) throw Fail{MGC_EINVAL};
-        O[i % 2].need(o2);
+        // (a buffer of its own for this chunk's stream: nothing may still
+        // read the one it replaces)
+        for (auto q : Q.q) MGC_HIP(hipStreamSynchronize(q));
+        Ob.need(o2);
+        obuf = static_cast<uint8_t*>(Ob.p);
+        ocap = Ob.n;
         W.need(w2);
-        rc = mgc_compress(ctx, I[i % 2].p, ndim, cs, dtype, tc, norm, MGC_ABS, cap, O[i % 2].p,
-                          O[i % 2].n, W.p, W.n, res, s);
+        rc = mgc_compress(ctx, input_of(i), ndim, cs, dtype, tc, norm, MGC_ABS, cap, obuf, ocap,
+                          W.p, W.n, res, s);
         if (rc != MGC_OK) throw Fail{rc};
         read_small(ctx, r2, res, 16, s);
       }
@@ -386,7 +424,7 @@ mgc_status mgc_pipe_compress(mgc_ctx ctx, const void* h_in, int ndim, const uint
       ent[i].bytes = r2[1];
       if (off + r2[1] > out_cap) fail(MGC_ENOSPC, "output too small");
       t_out[i] = tl.begin(2, s);
-      MGC_HIP(hipMemcpyAsync(out + off, O[i % 2].p, r2[1], hipMemcpyDeviceToHost, s));
+      MGC_HIP(hipMemcpyAsync(out + off, obuf, r2[1], hipMemcpyDeviceToHost, s));
       tl.end(t_out[i], s);
       off = pad8(off + r2[1]);
     }
@@ -475,9 +513,31 @@ mgc_status mgc_pipe_decompress(mgc_ctx ctx, const void* h_in, size_t in_bytes, v
       chunk_shape(ndim, h.shape, e.planes, cs);
       ws = std::max(ws, decompress_ws_bytes(get_plan(ctx, ndim, cs)));
     }
-    DevMem I[2], O[2], W, S;
-    for (auto& b : I) b.need(maxs);
-    for (auto& b : O) b.need(maxp * pb);
+    // With room (a quarter of the free device memory) the whole container
+    // and the whole array live on the device, so no chunk waits for a
+    // buffer; otherwise two input and two output buffers rotate.
+    DevMem I[2], O[2], W, RI, RO;
+    {
+      size_t free_b = 0, total_b = 0;
+      MGC_HIP(hipMemGetInfo(&free_b, &total_b));
+      if (h.total + h.shape[0] * pb <= free_b / 4) {
+        RI.need(h.total);
+        RO.need(h.shape[0] * pb);
+      }
+    }
+    const bool resident = RI.p != nullptr;
+    if (!resident) {
+      for (auto& b : I) b.need(maxs);
+      for (auto& b : O) b.need(maxp * pb);
+    }
+    auto in_of = [&](size_t i) -> uint8_t* {
+      return resident ? static_cast<uint8_t*>(RI.p) + ent[i].offset
+                      : static_cast<uint8_t*>(I[i % 2].p);
+    };
+    auto out_of = [&](size_t i) -> uint8_t* {
+      return resident ? static_cast<uint8_t*>(RO.p) + ent[i].first * pb
+                      : static_cast<uint8_t*>(O[i % 2].p);
+    };
     W.need(ws);
     uint8_t* out = static_cast<uint8_t*>(h_out);
     Queues Q;
@@ -488,9 +548,9 @@ mgc_status mgc_pipe_decompress(mgc_ctx ctx, const void* h_in, size_t in_bytes, v
     std::vector<size_t> t_in(K), t_k(K), t_out(K);
     auto copy_in = [&](size_t i) {
       hipStream_t s = Q.q[i % 3];
-      if (i >= 2) MGC_HIP(hipStreamWaitEvent(s, tl.done(t_k[i - 2]), 0));
+      if (i >= 2 && !resident) MGC_HIP(hipStreamWaitEvent(s, tl.done(t_k[i - 2]), 0));
       t_in[i] = tl.begin(0, s);
-      MGC_HIP(hipMemcpyAsync(I[i % 2].p, in + ent[i].offset, ent[i].bytes,
+      MGC_HIP(hipMemcpyAsync(in_of(i), in + ent[i].offset, ent[i].bytes,
                              hipMemcpyHostToDevice, s));
       tl.end(t_in[i], s);
     };
@@ -501,7 +561,7 @@ mgc_status mgc_pipe_decompress(mgc_ctx ctx, const void* h_in, size_t in_bytes, v
       hipStream_t s = Q.q[i % 3];
       if (i + 1 < K) copy_in(i + 1);
       if (i >= 1) MGC_HIP(hipStreamWaitEvent(s, tl.done(t_k[i - 1]), 0));  // one at a time
-      if (i >= 2) MGC_HIP(hipStreamWaitEvent(s, tl.done(t_out[i - 2]), 0));
+      if (i >= 2 && !resident) MGC_HIP(hipStreamWaitEvent(s, tl.done(t_out[i - 2]), 0));
       chunk_shape(ndim, h.shape, ent[i].planes, cs);
       Header ch;
       std::memcpy(&ch, in + ent[i].offset, kHeaderBytes);
@@ -511,12 +571,13 @@ mgc_status mgc_pipe_decompress(mgc_ctx ctx, const void* h_in, size_t in_bytes, v
       // the chunk's header is parsed from the host copy: no device read
       const size_t head = std::min<size_t>(ent[i].bytes, kHeaderBytes + 8 * (kMaxLevels + 1));
       t_k[i] = tl.begin(1, s);
-      const unsigned* sw = decompress_enqueue(ctx, in + ent[i].offset, head, I[i % 2].p,
-                                              ent[i].bytes, O[i % 2].p, O[i % 2].n, W.p, W.n, s);
+      const unsigned* sw = decompress_enqueue(ctx, in + ent[i].offset, head, in_of(i),
+                                              ent[i].bytes, out_of(i), ent[i].planes * pb, W.p,
+                                              W.n, s);
       if (sw) launch_copy_bytes(ctx->pinned_dev + kPinSlot + 4 * i, sw, 4, s);
       tl.end(t_k[i], s);
       t_out[i] = tl.begin(2, s);
-      MGC_HIP(hipMemcpyAsync(out + ent[i].first * pb, O[i % 2].p, ent[i].planes * pb,
+      MGC_HIP(hipMemcpyAsync(out + ent[i].first * pb, out_of(i), ent[i].planes * pb,
                              hipMemcpyDeviceToHost, s));
       tl.end(t_out[i], s);
     }
