@@ -25,6 +25,8 @@ hx          the Huffman pipeline as a standalone lossless codec for byte and
             integer streams (keys, escapes, stream layout)
 pipe        chunked compression of host-resident arrays: the adaptive chunk
             rule, per-chunk bounds and the container layout
+zfp         fixed-rate block transform coding (alignment, lifting, negabinary,
+            bit planes with group tests)
 """
 from .hierarchy import Hierarchy
 from .transform import decompose, recompose, recompose_adjoint, level_slices
@@ -32,11 +34,11 @@ from .quantize import error_budget, level_bins, quantize, dequantize, to_symbols
 from .huffman import (histogram, code_lengths, canonical_codes, encode_chunks,
                       decode_chunks)
 from .stream import compress, decompress, parse_header
-from . import hx, pipe
+from . import hx, pipe, zfp
 
 __all__ = [
     "Hierarchy", "decompose", "recompose", "recompose_adjoint", "level_slices",
     "error_budget", "level_bins", "quantize", "dequantize", "to_symbols",
     "from_symbols", "histogram", "code_lengths", "canonical_codes",
-    "encode_chunks", "decode_chunks", "compress", "decompress", "parse_header", "hx", "pipe",
+    "encode_chunks", "decode_chunks", "compress", "decompress", "parse_header", "hx", "pipe", "zfp",
 ]
