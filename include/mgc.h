@@ -161,6 +161,44 @@ mgc_status mgc_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* 
                           size_t out_cap, void* d_ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Fixed-rate block transform coding (ZFP-X: Algorithm "ZFP Fix-Rate
+ * Compression", Section IV-C).  The array (FP32 or FP64, 1 to 3 axes) is cut
+ * into blocks of 4^ndim values in row-major block order (a partial block
+ * repeats each axis' last value).  Each block keeps exactly
+ * maxbits = round(rate * 4^ndim) bits: its values are aligned to the block's
+ * largest exponent e as P-bit integers trunc(x 2^(q - e)) (P = 32 or 64,
+ * q = P - 2 - ndim), transformed per axis (the last axis first) by two levels
+ * of reversible integer Haar lifting, ordered by total frequency, mapped to
+ * negabinary and coded bit plane by bit plane with group tests until the
+ * budget is spent.  There is no error bound: the rate fixes the size.
+ * rate: bits per value, with maxbits >= 2 + exponent bits (9 for FP32, 12 for
+ * FP64) and rate <= 2 P.
+ * Stream (little-endian): u32 magic 0x465A474D, u8 dtype, u8 ndim, u16 0,
+ * u32 maxbits, u32 0, u64 shape[3], f64 rate, u64 blocks, u64 total bytes
+ * (64-byte header); then the blocks' bits, block b at bits
+ * [b maxbits, (b + 1) maxbits) of u64 words in which bit j is bit j mod 64 of
+ * word j / 64; zero padding to 8 bytes.
+ * mgc_zfp_query: the stream's exact size (and 0 workspace bytes).
+ * mgc_zfp_compress (asynchronous on `stream`): d_result (device, two u64)
+ *   receives {MGC_OK or MGC_EINVAL (NaN/Inf in the data), stream bytes}.
+ * mgc_zfp_parse_header: fields of a host copy of the header.
+ * mgc_zfp_decompress (BLOCKING: reads the 64-byte header from the device):
+ *   writes the array to d_out.
+ * Errors: MGC_EINVAL (shape, dtype, rate, pointers), MGC_ENOSPC (out_cap),
+ * MGC_EFORMAT, MGC_EDEVICE.
+ * ---------------------------------------------------------------------- */
+mgc_status mgc_zfp_query(int ndim, const uint64_t* shape, mgc_dtype dtype, double rate,
+                         size_t* stream_bytes);
+mgc_status mgc_zfp_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                            mgc_dtype dtype, double rate, void* d_out, size_t out_cap,
+                            uint64_t* d_result, void* stream);
+mgc_status mgc_zfp_parse_header(const void* h_header, size_t bytes, int* ndim,
+                                uint64_t* shape3, mgc_dtype* dtype, double* rate,
+                                uint64_t* stream_bytes);
+mgc_status mgc_zfp_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* d_out,
+                              size_t out_cap, void* stream);
+
+/* ------------------------------------------------------------------------
  * Host-resident arrays (Section V: the host-device execution model, the
  * three-queue pipeline with two buffer pairs, Algorithm "Adaptive
  * Pipeline").  The array is cut along its slowest axis into chunks of whole

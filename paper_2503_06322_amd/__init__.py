@@ -15,6 +15,7 @@ Entry points (same names as the C functions, without the ``mgc_`` prefix):
 ``huffman_encode(symbols, C=1024)`` / ``huffman_decode(stream, n)``
 ``hx_compress(x, dict, base, C)`` / ``hx_decompress(stream)`` (Huffman-X lossless codec)
 ``pipe_compress(host_x, bound)`` / ``pipe_decompress(container)`` / ``pipe_profile`` (host-resident arrays)
+``zfp_compress(x, rate)`` / ``zfp_decompress(stream)`` (fixed-rate block transform coding)
 ``header_info(stream)``, ``profile_enable / profile_reset / profile_read``
 """
 from __future__ import annotations
@@ -29,7 +30,8 @@ __all__ = ["MgcError", "library_path", "compress", "compress_async", "decompress
            "compress_query", "transform_query", "batch_query", "Batch", "compress_batched",
            "set_tuning", "tuning_info", "set_decoder", "decoder_info", "compress_noalloc",
            "NOALLOC_SCRATCH_BYTES", "hx_query", "hx_compress", "hx_decompress", "hx_header",
-           "pipe_max_bytes", "pipe_compress", "pipe_decompress", "pipe_profile"]
+           "pipe_max_bytes", "pipe_compress", "pipe_decompress", "pipe_profile", "zfp_query",
+           "zfp_compress", "zfp_decompress"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libmgc.so")
@@ -131,6 +133,13 @@ def _load():
                               ctypes.POINTER(ctypes.c_int), c_u64p, c_u64p],
             "mgc_pipe_profile": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_int, ctypes.c_int, ctypes.POINTER(PipeModel)],
+            "mgc_zfp_query": [ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_double, c_szp],
+            "mgc_zfp_compress": [vp, vp, ctypes.c_int, c_u64p, ctypes.c_int, ctypes.c_double, vp,
+                                 ctypes.c_size_t, vp, vp],
+            "mgc_zfp_parse_header": [vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_int), c_u64p,
+                                     ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_double), c_u64p],
+            "mgc_zfp_decompress": [vp, vp, ctypes.c_size_t, vp, ctypes.c_size_t, vp],
             "mgc_hx_query": [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, c_szp, c_szp],
             "mgc_hx_compress": [vp, vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32,
                                 ctypes.c_int64, ctypes.c_uint32, vp, ctypes.c_size_t, vp,
@@ -770,6 +779,59 @@ def hx_decompress(stream, workspace=None, out=None):
                                      _hx_types()[dtype], ctypes.c_void_p(ws.data_ptr()),
                                      ws.numel(), _stream_ptr(dev)))
     return y[:n]
+
+
+def zfp_query(shape, dtype, rate: float) -> int:
+    """Exact stream bytes of a fixed-rate block-coded array."""
+    shp = _shape_arg(shape)
+    out = ctypes.c_size_t()
+    _check(_load().mgc_zfp_query(len(shape), shp, _dtype_code(dtype), rate, ctypes.byref(out)))
+    return out.value
+
+
+def zfp_compress(x, rate: float, out=None, result=None, sync: bool = True):
+    """Fixed-rate block transform coding of an FP32/FP64 GPU tensor (1 to 3
+    axes) at ``rate`` bits per value; returns the stream (uint8 GPU tensor),
+    or (buffer, result words) with ``sync=False``."""
+    _require_gpu(x, "x")
+    torch = _torch()
+    x = x.contiguous()
+    dev = x.device.index if x.device.index is not None else torch.cuda.current_device()
+    shp = _shape_arg(tuple(x.shape))
+    n = zfp_query(tuple(x.shape), x.dtype, rate)
+    o = out if out is not None else _empty(n, x.device)
+    res = result if result is not None else torch.zeros(2, dtype=torch.int64, device=x.device)
+    _check(_load().mgc_zfp_compress(_ctx(dev), ctypes.c_void_p(x.data_ptr()), x.dim(), shp,
+                                    _dtype_code(x.dtype), rate, ctypes.c_void_p(o.data_ptr()),
+                                    o.numel(), ctypes.c_void_p(res.data_ptr()), _stream_ptr(dev)))
+    if not sync:
+        return o, res
+    st, size = (int(v) for v in res.cpu())
+    if st:
+        raise MgcError(st, "fixed-rate coding failed: the data holds NaN or Inf")
+    return o[:size]
+
+
+def zfp_decompress(stream, out=None):
+    """Array of a fixed-rate block-coded stream (uint8 GPU tensor)."""
+    _require_gpu(stream, "stream")
+    torch = _torch()
+    stream = stream.contiguous()
+    dev = stream.device.index if stream.device.index is not None else torch.cuda.current_device()
+    head = stream[:64].cpu().numpy().tobytes()
+    nd = ctypes.c_int()
+    shp = (ctypes.c_uint64 * 3)()
+    dt = ctypes.c_int()
+    rate = ctypes.c_double()
+    _check(_load().mgc_zfp_parse_header(head, len(head), ctypes.byref(nd), shp, ctypes.byref(dt),
+                                        ctypes.byref(rate), None))
+    shape = tuple(int(shp[d]) for d in range(nd.value))
+    dtype = torch.float32 if dt.value == 0 else torch.float64
+    y = out if out is not None else torch.empty(shape, dtype=dtype, device=stream.device)
+    _check(_load().mgc_zfp_decompress(_ctx(dev), ctypes.c_void_p(stream.data_ptr()),
+                                      stream.numel(), ctypes.c_void_p(y.data_ptr()),
+                                      y.numel() * y.element_size(), _stream_ptr(dev)))
+    return y
 
 
 def _pipe_model(model):

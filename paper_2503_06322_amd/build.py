@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmgc.so")
 ARCH = "gfx950"
 
 SOURCES = ["plan.cpp", "api.cpp", "batched.cpp", "pipeline.cpp", "transform.hip", "huffman.hip",
-           "hx.hip"]
+           "hx.hip", "zfp.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
           "-ffp-contract=off", "-Wall", "-Wno-unused-function"]

@@ -1078,6 +1078,116 @@ mgc_status mgc_huffman_decode(mgc_ctx ctx, const void* d_in, size_t in_bytes, ui
   });
 }
 
+mgc_status mgc_zfp_query(int ndim, const uint64_t* shape, mgc_dtype dtype, double rate,
+                         size_t* stream_bytes) {
+  return guard([&] {
+    if (ndim < 1 || ndim > 3 || !shape) fail(MGC_EINVAL, "ndim must be 1..3");
+    if (dtype != MGC_F32 && dtype != MGC_F64) fail(MGC_EINVAL, "bad dtype");
+    uint64_t nb = 1;
+    for (int d = 0; d < ndim; ++d) {
+      if (shape[d] == 0) fail(MGC_EINVAL, "empty arrays are not block-coded");
+      nb *= (shape[d] + 3) / 4;
+    }
+    const int P = dtype == MGC_F64 ? 64 : 32, eb = dtype == MGC_F64 ? 12 : 9;
+    const double mbd = std::nearbyint(rate * (double)(1u << (2 * ndim)));
+    if (!std::isfinite(rate) || mbd < 2 + eb || rate > 2.0 * P)
+      fail(MGC_EINVAL, "rate out of range");
+    const uint64_t mb = (uint64_t)mbd;
+    if (stream_bytes) *stream_bytes = kZfpHeaderBytes + 8 * ((nb * mb + 63) / 64);
+  });
+}
+
+mgc_status mgc_zfp_compress(mgc_ctx ctx, const void* d_in, int ndim, const uint64_t* shape,
+                            mgc_dtype dtype, double rate, void* d_out, size_t out_cap,
+                            uint64_t* d_result, void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    size_t need = 0;
+    if (mgc_zfp_query(ndim, shape, dtype, rate, &need) != MGC_OK) throw Fail{MGC_EINVAL};
+    if (!d_in || !d_out || !d_result) fail(MGC_EINVAL, "null pointer");
+    if (reinterpret_cast<uintptr_t>(d_out) % 8 ||
+        reinterpret_cast<uintptr_t>(d_in) % (dtype == MGC_F64 ? 8 : 4))
+      fail(MGC_EINVAL, "misaligned input or output");
+    if (out_cap < need) fail(MGC_ENOSPC, "output too small");
+    hipStream_t s = as_stream(stream);
+    ZfpHead h{};
+    h.magic = kZfpMagic;
+    h.dtype = (uint8_t)dtype;
+    h.ndim = (uint8_t)ndim;
+    h.maxbits = (uint32_t)std::nearbyint(rate * (double)(1u << (2 * ndim)));
+    uint64_t nb = 1;
+    for (int d = 0; d < ndim; ++d) {
+      h.shape[d] = shape[d];
+      nb *= (shape[d] + 3) / 4;
+    }
+    h.rate = rate;
+    h.blocks = nb;
+    h.total = need;
+    uint8_t* out = static_cast<uint8_t*>(d_out);
+    // blocks that share words OR their bits into a cleared payload
+    if (h.maxbits % 64) MGC_HIP(hipMemsetAsync(out + kZfpHeaderBytes, 0, need - kZfpHeaderBytes, s));
+    // d_result[0] serves as the non-finite flag until the header kernel
+    // turns it into the outcome
+    MGC_HIP(hipMemsetAsync(d_result, 0, 16, s));
+    launch_zfp_encode(d_in, dtype == MGC_F64, ndim, shape, nb, h.maxbits, out,
+                      reinterpret_cast<unsigned*>(d_result), h,
+                      reinterpret_cast<unsigned long long*>(d_result), s);
+    MGC_HIP(hipGetLastError());
+  });
+}
+
+mgc_status mgc_zfp_parse_header(const void* h_header, size_t bytes, int* ndim,
+                                uint64_t* shape3, mgc_dtype* dtype, double* rate,
+                                uint64_t* stream_bytes) {
+  return guard([&] {
+    if (!h_header || bytes < (size_t)kZfpHeaderBytes) fail(MGC_EFORMAT, "stream shorter than its header");
+    ZfpHead h;
+    std::memcpy(&h, h_header, kZfpHeaderBytes);
+    if (h.magic != kZfpMagic || h.dtype > 1 || h.ndim < 1 || h.ndim > 3)
+      fail(MGC_EFORMAT, "not a fixed-rate block-coded stream");
+    if (ndim) *ndim = h.ndim;
+    if (shape3)
+      for (int d = 0; d < 3; ++d) shape3[d] = d < h.ndim ? h.shape[d] : 0;
+    if (dtype) *dtype = (mgc_dtype)h.dtype;
+    if (rate) *rate = h.rate;
+    if (stream_bytes) *stream_bytes = h.total;
+  });
+}
+
+mgc_status mgc_zfp_decompress(mgc_ctx ctx, const void* d_in, size_t in_bytes, void* d_out,
+                              size_t out_cap, void* stream) {
+  return guard([&] {
+    check_ctx(ctx);
+    if (!d_in || !d_out) fail(MGC_EINVAL, "null pointer");
+    if (reinterpret_cast<uintptr_t>(d_in) % 8) fail(MGC_EINVAL, "stream not 8-byte aligned");
+    if (in_bytes < (size_t)kZfpHeaderBytes) fail(MGC_EFORMAT, "stream shorter than its header");
+    hipStream_t s = as_stream(stream);
+    sync_read(ctx, ctx->pinned, d_in, kZfpHeaderBytes, s);
+    ZfpHead h;
+    std::memcpy(&h, ctx->pinned, kZfpHeaderBytes);
+    int nd = 0;
+    uint64_t shp[3];
+    mgc_dtype dt;
+    double rate = 0;
+    uint64_t total = 0;
+    if (mgc_zfp_parse_header(&h, sizeof(h), &nd, shp, &dt, &rate, &total) != MGC_OK)
+      fail(MGC_EFORMAT, "not a fixed-rate block-coded stream");
+    size_t need = 0;
+    if (mgc_zfp_query(nd, shp, dt, rate, &need) != MGC_OK || need != total ||
+        h.maxbits != (uint32_t)std::nearbyint(rate * (double)(1u << (2 * nd))))
+      fail(MGC_EFORMAT, "inconsistent header");
+    if (total > in_bytes) fail(MGC_EFORMAT, "truncated stream");
+    uint64_t n = 1;
+    for (int d = 0; d < nd; ++d) n *= shp[d];
+    if (reinterpret_cast<uintptr_t>(d_out) % (dt == MGC_F64 ? 8 : 4))
+      fail(MGC_EINVAL, "misaligned output");
+    if (out_cap < n * (dt == MGC_F64 ? 8 : 4)) fail(MGC_ENOSPC, "output too small");
+    launch_zfp_decode(static_cast<const uint8_t*>(d_in), dt == MGC_F64, nd, shp, h.blocks,
+                      h.maxbits, d_out, s);
+    MGC_HIP(hipGetLastError());
+  });
+}
+
 mgc_status mgc_hx_query(uint64_t n, mgc_hx_type type, uint32_t C, size_t* ws_bytes,
                         size_t* max_out_bytes) {
   return guard([&] {

@@ -20,6 +20,8 @@ constexpr int kHuffHeaderBytes = 48;
 constexpr uint32_t kMagic = 0x3143474Du;      // "MGC1"
 constexpr uint32_t kHuffMagic = 0x3148474Du;  // "MGH1"
 constexpr int kHxHeaderBytes = 64;
+constexpr int kZfpHeaderBytes = 64;
+constexpr uint32_t kZfpMagic = 0x465A474Du;   // "MGZF"
 constexpr uint32_t kHxMagic = 0x5848474Du;    // "MGHX"
 constexpr uint16_t kVersion = 1;
 constexpr int kMaxLevels = 62;
@@ -141,6 +143,20 @@ struct HuffHeader {
 #pragma pack(pop)
 static_assert(sizeof(Header) == kHeaderBytes, "header layout");
 static_assert(sizeof(HuffHeader) == kHuffHeaderBytes, "huffman header layout");
+
+// 64-byte header of a fixed-rate block-coded stream.
+#pragma pack(push, 1)
+struct ZfpHead {
+  uint32_t magic;
+  uint8_t dtype, ndim;
+  uint16_t z0;
+  uint32_t maxbits, z1;
+  uint64_t shape[3];
+  double rate;
+  uint64_t blocks, total;
+};
+#pragma pack(pop)
+static_assert(sizeof(ZfpHead) == kZfpHeaderBytes, "fixed-rate header layout");
 
 enum : uint8_t { FLAG_CONSTANT = 1, FLAG_EMPTY = 2 };
 

@@ -223,6 +223,16 @@ DecodeShape launch_decode(const uint8_t* in, uint64_t off_sec, uint64_t words_se
                           uint64_t n_codes, const DecodeTables* t, uint16_t* sym,
                           unsigned* status, hipStream_t s, DecodeShape force = DecodeShape{});
 
+// Fixed-rate block coding (zfp.hip): blocks of 4^ndim values, maxbits bits
+// each, payload at out + kZfpHeaderBytes (cleared beforehand unless maxbits
+// is a multiple of 64); h is written as the header and res = {mgc_status,
+// stream bytes} (MGC_EINVAL when *status shows a non-finite value).
+void launch_zfp_encode(const void* in, bool f64, int ndim, const uint64_t* shape,
+                       uint64_t nblocks, uint32_t maxbits, uint8_t* out, unsigned* status,
+                       const ZfpHead& h, unsigned long long* res, hipStream_t s);
+void launch_zfp_decode(const uint8_t* in, bool f64, int ndim, const uint64_t* shape,
+                       uint64_t nblocks, uint32_t maxbits, void* out, hipStream_t s);
+
 // Huffman-X (hx.hip).  Keys of n values of a stream type (mgc_hx_type):
 // u8/u16 values are their keys; i32/i64 values in [lo, hi] are key v - lo,
 // others key esc with zc[chunk] = escapes per 1024 values (zc unused for
