@@ -21,7 +21,8 @@ Huffman pipeline as a standalone lossless codec on a byte stream and an
 integer stream, with its own oracle baseline) and "host_pipeline" (the field
 in host memory through the chunked three-queue pipeline: host-to-host GB/s
 and overlap ratios; these include the host link and are never the headline
-value).
+value) and "zfp_x" (fixed-rate block transform coding of the field at 4, 8
+and 16 bits per value).
 """
 from __future__ import annotations
 
@@ -266,6 +267,58 @@ def pipe_leg(torch, mgc, u, rel: float):
             "variants": rows}
 
 
+def zfp_leg(torch, mgc, u, reps: int):
+    """Fixed-rate block transform coding of the 513^3 field at 4, 8 and 16
+    bits per value: GB/s of input bytes (inputs resident, buffers
+    preallocated, HIP events, median of ``reps``), ratio, max error relative
+    to max|u|, and one oracle timing on a 65^3 corner (one thread)."""
+    from oracle import zfp as ozfp
+    x = torch.from_numpy(u).cuda()
+    nb = u.nbytes
+    stream = torch.cuda.current_stream()
+    rows = []
+    for rate in (4, 8, 16):
+        n = mgc.zfp_query(tuple(x.shape), x.dtype, rate)
+        ob = torch.empty(n, dtype=torch.uint8, device="cuda")
+        res = torch.zeros(2, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(2):
+            s = mgc.zfp_compress(x, rate, out=ob, result=res)
+            mgc.zfp_decompress(s, out=y)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps)]
+        torch.cuda.synchronize()
+        for e in ev:
+            e[0].record(stream)
+            mgc.zfp_compress(x, rate, out=ob, result=res, sync=False)
+            e[1].record(stream)
+            mgc.zfp_decompress(s, out=y)
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        c_ms = float(np.median([a.elapsed_time(b) for a, b, _ in ev]))
+        d_ms = float(np.median([b.elapsed_time(c) for _, b, c in ev]))
+        err = float((y.double() - x.double()).abs().max().item()) / float(x.abs().max().item())
+        row = {"rate_bits_per_value": rate, "compress_ms": round(c_ms, 4),
+               "decompress_ms": round(d_ms, 4),
+               "compress_GBps": round(nb / (c_ms * 1e-3) / 1e9, 2),
+               "decompress_GBps": round(nb / (d_ms * 1e-3) / 1e9, 2),
+               "compression_ratio": round(nb / n, 3), "max_err_over_max_abs": round(err, 6)}
+        log("zfp-x rate %2d  compress %7.3f ms (%7.1f GB/s)  decompress %7.3f ms (%7.1f GB/s)  CR %5.2f  err %.2e"
+            % (rate, c_ms, row["compress_GBps"], d_ms, row["decompress_GBps"],
+               row["compression_ratio"], err))
+        rows.append(row)
+        del ob, y
+    sub = np.ascontiguousarray(u[:65, :65, :65])
+    t0 = time.perf_counter()
+    buf = ozfp.compress(sub, 8)
+    t1 = time.perf_counter()
+    ozfp.decompress(buf)
+    t2 = time.perf_counter()
+    cpu = {"value": round(2 * sub.nbytes / (t2 - t0) / 1e9, 5), "unit": "GB/s", "cores": 1,
+           "kind": "oracle", "sample": "65^3 corner of the field at 8 bits per value, compress "
+           "%.1fs + decompress %.1fs, one thread" % (t1 - t0, t2 - t1)}
+    return {"workload": "grf513_f32_fixed_rate", "rates": rows, "cpu_baseline": cpu}
+
+
 def hx_cpu_baseline(synthetic):
     """The Huffman-X oracle (one thread) on the first 2^24 values of the
     integer stream workload: compress + decompress, GB/s of input bytes."""
@@ -489,6 +542,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--no-hx", action="store_true")
     ap.add_argument("--no-pipe", action="store_true")
+    ap.add_argument("--no-zfp", action="store_true")
     ap.add_argument("--config-reps", type=int, default=5)
     ap.add_argument("--copy-reference", action="store_true",
                     help="also copy the input once on the device (a kernel of known "
@@ -603,6 +657,10 @@ def main():
     if not args.no_configs:
         configs = config_legs(torch, mgc, synthetic, u, args.config_reps)
 
+    zfpr = None
+    if not args.no_zfp:
+        zfpr = zfp_leg(torch, mgc, u, args.config_reps)
+
     piper = None
     if not args.no_pipe:
         piper = pipe_leg(torch, mgc, u, args.rel)
@@ -640,7 +698,7 @@ def main():
         "compression_ratio": round(in_bytes / stream_bytes, 3),
         "max_err_over_tau": round(err / tau, 4),
         "roofline": roofline, "cpu_baseline": cpu, "batched": batched, "differentiation": diff,
-        "workloads": configs, "huffman_x": hxr, "host_pipeline": piper,
+        "workloads": configs, "huffman_x": hxr, "host_pipeline": piper, "zfp_x": zfpr,
         "stages": stages, "stages_ms_per_step_with_events": round(prof_ms_step, 4),
     }
     print(json.dumps(res), flush=True)
