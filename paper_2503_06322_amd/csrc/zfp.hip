@@ -185,25 +185,42 @@ struct BitWriter {
     acc |= bit << nacc;
     if (++nacc == 64) flush();
   }
+  // the low c bits of v (nothing above them set), c <= 64
+  __device__ __forceinline__ void put_bits(unsigned long long v, int c) {
+    if (c == 0) return;
+    acc |= v << nacc;
+    const int room = 64 - nacc;
+    if (c < room) {
+      nacc += c;
+      return;
+    }
+    nacc = 64;
+    flush();
+    if (c > room) {
+      acc = v >> room;
+      nacc = c - room;
+    }
+  }
 };
 
 struct BitReader {
   const unsigned long long* w;
   uint64_t pos;
-  unsigned long long buf = 0;
-  int avail = 0;
-  __device__ __forceinline__ unsigned get() {
-    if (avail == 0) {
-      const int s = (int)(pos & 63);
-      buf = w[pos >> 6] >> s;
-      avail = 64 - s;
-    }
-    const unsigned b = (unsigned)(buf & 1ull);
-    buf >>= 1;
-    --avail;
-    ++pos;
-    return b;
+  // the next c bits (c <= 64, all within the block), the first in bit 0
+  __device__ __forceinline__ unsigned long long peek(int c) const {
+    if (c == 0) return 0ull;
+    const uint64_t wi = pos >> 6;
+    const int s = (int)(pos & 63);
+    unsigned long long v = w[wi] >> s;
+    if (s + c > 64) v |= w[wi + 1] << (64 - s);
+    return c == 64 ? v : v & ((1ull << c) - 1ull);
   }
+  __device__ __forceinline__ unsigned long long get_bits(int c) {
+    const unsigned long long v = peek(c);
+    pos += (uint64_t)c;
+    return v;
+  }
+  __device__ __forceinline__ unsigned get() { return (unsigned)get_bits(1); }
 };
 
 template <typename T, int D>
@@ -256,34 +273,44 @@ __global__ __launch_bounds__(kZfpThreads) void k_zfp_encode(const T* __restrict_
     U u[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) u[i] = ((U)v[ord.p[i]] + Z::M) ^ Z::M;
+    // Runs of bits go out in one write each: the significant coefficients'
+    // bits of a plane, and for each group test the zeros up to the next one
+    // with that one (a run stops early where the budget ends).
     int m = 0, B = budget;
     for (int k = Z::P - 1; k >= 0 && B > 0; --k) {
       unsigned long long xm = 0;
 #pragma unroll
       for (int i = 0; i < n; ++i) xm |= (unsigned long long)((u[i] >> k) & 1u) << i;
       const int t = min(m, B);
-      for (int i = 0; i < t; ++i) bw.put((xm >> i) & 1ull);
+      bw.put_bits(t == 64 ? xm : xm & ((1ull << t) - 1ull), t);
       B -= t;
       if (t < m) break;
       xm = m < 64 ? xm >> m : 0ull;
       while (m < n && B > 0) {
-        const unsigned long long gbit = xm ? 1ull : 0ull;
-        bw.put(gbit);
-        --B;
-        if (!gbit) break;
-        while (true) {
-          if (m == n - 1) {  // the last coefficient's one is implied
-            xm >>= 1;
-            ++m;
-            break;
-          }
-          if (B == 0) break;
-          const unsigned long long bit = xm & 1ull;
-          bw.put(bit);
+        if (!xm) {
+          bw.put_bits(0ull, 1);
           --B;
-          xm >>= 1;
-          ++m;
-          if (bit) break;
+          break;
+        }
+        bw.put_bits(1ull, 1);
+        --B;
+        const int z = __builtin_ctzll(xm);  // the next one is coefficient m + z
+        if (m + z == n - 1) {               // the last coefficient: its one is implied
+          const int c = min(z, B);
+          bw.put_bits(0ull, c);
+          B -= c;
+          m += c < z ? c : z + 1;
+          break;
+        }
+        if (B >= z + 1) {
+          bw.put_bits(1ull << z, z + 1);
+          B -= z + 1;
+          m += z + 1;
+          xm = z + 1 < 64 ? xm >> (z + 1) : 0ull;
+        } else {
+          bw.put_bits(0ull, B);
+          m += B;
+          B = 0;
         }
       }
     }
@@ -328,27 +355,37 @@ __global__ __launch_bounds__(kZfpThreads) void k_zfp_decode(
     for (int i = 0; i < n; ++i) u[i] = 0;
     int m = 0, B = (int)maxbits - 1 - Z::EB;
     for (int k = Z::P - 1; k >= 0 && B > 0; --k) {
-      unsigned long long ym = 0;
       const int t = min(m, B);
-      for (int i = 0; i < t; ++i) ym |= (unsigned long long)br.get() << i;
+      unsigned long long ym = br.get_bits(t);
       B -= t;
-      bool stop = t < m;
+      const bool stop = t < m;
       while (!stop && m < n && B > 0) {
         const unsigned gbit = br.get();
         --B;
         if (!gbit) break;
-        while (true) {
+        if (m == n - 1) {  // the last coefficient's one is implied
+          ym |= 1ull << m;
+          ++m;
+          break;
+        }
+        // the next one within the budget and before the last coefficient
+        const int L = min(B, n - 1 - m);
+        const unsigned long long v = br.peek(L);
+        if (v) {
+          const int r = __builtin_ctzll(v);
+          br.pos += (uint64_t)(r + 1);
+          B -= r + 1;
+          ym |= 1ull << (m + r);
+          m += r + 1;
+        } else {
+          br.pos += (uint64_t)L;
+          B -= L;
+          m += L;
           if (m == n - 1) {
             ym |= 1ull << m;
             ++m;
-            break;
           }
-          if (B == 0) break;
-          const unsigned bit = br.get();
-          --B;
-          if (bit) ym |= 1ull << m;
-          ++m;
-          if (bit) break;
+          break;
         }
       }
 #pragma unroll
