@@ -238,7 +238,9 @@ void build_launches(BatchPlan& b, const int t[kTuneKinds], std::vector<JobBlock>
           const Plan& p = *b.plans[j];
           if (!at(j) || p.bit[axis] < 0 || cls(j) != c) return 0;
           const PlanLevel& v = p.lv[p.L - s];
-          if (axis == 2) return std::min<uint32_t>(ceil_div(v.nc[0] * v.nc[1], 4), 1024);
+          // (about four rows per wavefront: each wavefront loads its factors
+          // once and the next row while it solves one)
+          if (axis == 2) return std::min<uint32_t>(ceil_div(v.nc[0] * v.nc[1], 16), 1024);
           if (axis == 1) return ceil_div(v.nc[0] * v.nc[2], 64);
           return ceil_div(v.nc[1] * v.nc[2], 64);
         });
@@ -261,7 +263,12 @@ void build_launches(BatchPlan& b, const int t[kTuneKinds], std::vector<JobBlock>
     BLaunch L;
     L.kind = BK::Hist;
     L.name = "b_histogram";
-    mapped(L, [&](int j) { return live(j) ? hist_blocks(b.plans[j]->N) : 0u; });
+    // about 256K symbols per block: each block clears and flushes a
+    // 32K-bin LDS window, which small slices would pay per few symbols
+    mapped(L, [&](int j) {
+      return live(j) ? (uint32_t)std::min<int64_t>(256, std::max<int64_t>(1, (b.plans[j]->N + 262143) / 262144))
+                     : 0u;
+    });
   }
   per_job(BK::Codebook, "b_codebook");
   {
@@ -271,7 +278,7 @@ void build_launches(BatchPlan& b, const int t[kTuneKinds], std::vector<JobBlock>
     mapped(L, [&](int j) { return live(j) ? chunk_words_blocks(b.plans[j]->N, kChunk) : 0u; });
   }
   per_job(BK::Scan, "b_layout_scan");
-  per_job(BK::OSort, "b_outlier_sort");
+  per_job(BK::OSort, "b_outlier_order");
   {
     BLaunch L;
     L.kind = BK::Encode;
@@ -299,7 +306,7 @@ void launch_one(const BatchPlan& b, const BLaunch& L, const int t[kTuneKinds], h
     case BK::Codebook: launch_b_codebook(J, b.n, s); break;
     case BK::ChunkW: launch_b_chunk_words(J, m, L.nb, s); break;
     case BK::Scan: launch_b_layout_scan(J, b.n, s); break;
-    case BK::OSort: launch_b_outlier_sort(J, b.n, s); break;
+    case BK::OSort: launch_b_escape_order(J, b.n, s); break;
     case BK::Encode: launch_b_encode(J, m, L.nb, s); break;
     case BK::Header: launch_b_header(J, b.n, s); break;
   }
@@ -526,6 +533,9 @@ mgc_status mgc_compress_batched(mgc_ctx ctx, int n, const void* const* d_in, con
       J.ovA = w.ovA;
       J.okB = w.okB;
       J.ovB = w.ovB;
+      J.zc = w.zc;
+      J.zpre = w.zpre;
+      J.zl = w.zl;
       J.size_out = d_sizes + j;
       J.status_out = d_status + j;
       J.hdr = make_header(p, b.ndim[j], b.shape[j].data(), b.dt[j], bounds[j], norm, mode);

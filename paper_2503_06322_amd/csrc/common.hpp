@@ -188,6 +188,7 @@ struct Job {
   uint32_t* opos;
   int64_t* oval;
   uint32_t *okA, *ovA, *okB, *ovB;
+  uint32_t *zc, *zpre, *zl;  // escape counts per chunk, their prefix, lane masks
   uint64_t* size_out;       // result tables of the call (device)
   int32_t* status_out;
   Header hdr;               // template: request and shape fields

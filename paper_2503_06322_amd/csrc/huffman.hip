@@ -122,11 +122,31 @@ constexpr int kHistWin = kHistWindow;
 // values escape the dictionary, and then too contended for one global
 // counter); other symbols go to global atomics.
 __device__ __forceinline__ void hist_add(unsigned s, unsigned* h, unsigned* hist, unsigned lo,
-                                         unsigned hot) {
+                                         unsigned hot, unsigned cnt = 1u) {
   const unsigned d = s - lo;
-  if (d < (unsigned)kHistWin) atomicAdd(&h[d], 1u);
-  else if (s == hot) atomicAdd(&h[kHistWin], 1u);
-  else atomicAdd(&hist[s], 1u);
+  if (d < (unsigned)kHistWin) atomicAdd(&h[d], cnt);
+  else if (s == hot) atomicAdd(&h[kHistWin], cnt);
+  else atomicAdd(&hist[s], cnt);
+}
+
+// The eight symbols of a 16-byte word, equal neighbours counted together:
+// narrow distributions (most symbols equal) would otherwise send every lane
+// of a wavefront to the same LDS counter at once.
+__device__ __forceinline__ void hist_add8(const uint4& w, unsigned* h, unsigned* hist,
+                                          unsigned lo, unsigned hot) {
+  const unsigned a[4] = {w.x, w.y, w.z, w.w};
+  unsigned cur = a[0] & 0xFFFFu, cnt = 0u;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const unsigned s = (k & 1) ? (a[k >> 1] >> 16) : (a[k >> 1] & 0xFFFFu);
+    if (s != cur) {
+      hist_add(cur, h, hist, lo, hot, cnt);
+      cur = s;
+      cnt = 0u;
+    }
+    ++cnt;
+  }
+  hist_add(cur, h, hist, lo, hot, cnt);
 }
 
 __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ sym, int64_t n,
@@ -145,24 +165,9 @@ __device__ __forceinline__ void histogram_body(const uint16_t* __restrict__ sym,
 #pragma unroll
     for (int u = 0; u < 4; ++u) w[u] = sv[i + u * stride];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const unsigned a[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        hist_add(a[k] & 0xFFFFu, h, hist, lo, hot);
-        hist_add(a[k] >> 16, h, hist, lo, hot);
-      }
-    }
+    for (int u = 0; u < 4; ++u) hist_add8(w[u], h, hist, lo, hot);
   }
-  for (; i < nvec; i += stride) {
-    const uint4 w = sv[i];
-    const unsigned a[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      hist_add(a[k] & 0xFFFFu, h, hist, lo, hot);
-      hist_add(a[k] >> 16, h, hist, lo, hot);
-    }
-  }
+  for (; i < nvec; i += stride) hist_add8(sv[i], h, hist, lo, hot);
   for (int64_t i = nvec * 8 + (int64_t)blk * 1024 + threadIdx.x; i < n; i += stride)
     hist_add(sym[i], h, hist, lo, hot);
   __syncthreads();
@@ -2346,13 +2351,65 @@ __global__ __launch_bounds__(256) void kb_chunk_words(const Job* __restrict__ jo
   const JobBlock jb = map[blockIdx.x];
   const Job& J = jobs[jb.job];
   if (job_skipped_h(J)) return;
-  chunk_words_body(J.sym, J.N, (int)kChunkSyms, J.clen, J.cw, J.lay, jb.local, jb.count);
+  chunk_words_body(J.sym, J.N, (int)kChunkSyms, J.clen, J.cw, J.lay, jb.local, jb.count, J.zc,
+                   J.zl);
 }
 
 __global__ __launch_bounds__(1024) void kb_layout_scan(const Job* __restrict__ jobs) {
   const Job& J = jobs[blockIdx.x];
   if (job_skipped_h(J)) return;
   layout_scan_body(J.cw, (int64_t)J.n_chunks, J.out, job_cb_off(J), J.lay, J.n_out, J.cap, 0);
+}
+
+// Escaped values of one array in stream order, one block per array: the
+// exclusive prefix of the chunks' escape counts, then every record placed at
+// its rank (the escapes of the chunks before its own, of its chunk's earlier
+// lanes, and of its lane's symbols before it), as the plain path does.
+__global__ __launch_bounds__(1024) void kb_escape_order(const Job* __restrict__ jobs) {
+  const Job& J = jobs[blockIdx.x];
+  if (job_skipped_h(J) || J.lay->status) return;
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t carry;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint64_t nc = J.n_chunks;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (uint64_t t0 = 0; t0 < nc; t0 += 1024) {
+    const uint64_t i = t0 + tid;
+    const uint32_t v = i < nc ? J.zc[i] : 0u;
+    uint32_t incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = carry, all = 0;
+    for (int w = 0; w < 16; ++w) {
+      before += w < wave ? wsum[w] : 0u;
+      all += wsum[w];
+    }
+    if (i < nc) J.zpre[i] = before + incl - v;
+    __syncthreads();
+    if (tid == 0) carry += all;
+    __syncthreads();
+  }
+  const uint64_t n = J.lay->n_outliers;
+  uint64_t* op = reinterpret_cast<uint64_t*>(J.out + J.lay->opos);
+  int64_t* ov = reinterpret_cast<int64_t*>(J.out + J.lay->oval);
+  for (uint64_t i = tid; i < n; i += 1024) {
+    const uint32_t pos = J.opos[i];
+    const uint32_t chunk = pos >> 10, j = pos & 1023u;
+    const uint32_t e = J.zl[(size_t)chunk * 64 + (j >> 4)];
+    const uint32_t t = j & 15u;
+    const uint64_t rank = (uint64_t)J.zpre[chunk] + (e >> 16) + (uint32_t)__popc(e & ((1u << t) - 1u));
+    if (((e >> t) & 1u) == 0u || rank >= n) {
+      atomicOr(J.status, ST_INTERNAL);
+      continue;
+    }
+    op[rank] = pos;
+    ov[rank] = J.oval[i];
+  }
 }
 
 __global__ __launch_bounds__(1024) void kb_outlier_sort(const Job* __restrict__ jobs) {
@@ -2408,6 +2465,9 @@ void launch_b_chunk_words(const Job* jobs, const JobBlock* map, uint32_t nb, hip
 }
 void launch_b_layout_scan(const Job* jobs, int n, hipStream_t s) {
   hipLaunchKernelGGL(kb_layout_scan, dim3((unsigned)n), dim3(1024), 0, s, jobs);
+}
+void launch_b_escape_order(const Job* jobs, int n, hipStream_t s) {
+  hipLaunchKernelGGL(kb_escape_order, dim3((unsigned)n), dim3(1024), 0, s, jobs);
 }
 void launch_b_outlier_sort(const Job* jobs, int n, hipStream_t s) {
   hipLaunchKernelGGL(kb_outlier_sort, dim3((unsigned)n), dim3(1024), 0, s, jobs);

@@ -132,6 +132,8 @@ void launch_b_codebook(const Job* jobs, int n, hipStream_t s);
 void launch_b_chunk_words(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s);
 void launch_b_layout_scan(const Job* jobs, int n, hipStream_t s);
 void launch_b_outlier_sort(const Job* jobs, int n, hipStream_t s);
+// escaped values in stream order from the chunk escape counts and lane masks
+void launch_b_escape_order(const Job* jobs, int n, hipStream_t s);
 void launch_b_encode(const Job* jobs, const JobBlock* map, uint32_t nb, hipStream_t s);
 void launch_b_header(const Job* jobs, int n, hipStream_t s);
 // Blocks per array of the map-driven Huffman launches.
