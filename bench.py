@@ -535,7 +535,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rel", type=float, default=1e-3)
     ap.add_argument("--n", type=int, default=513)
-    ap.add_argument("--cpu-planes", type=int, default=129)
+    ap.add_argument("--cpu-planes", type=int, default=257)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
