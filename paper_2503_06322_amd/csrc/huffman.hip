@@ -93,14 +93,15 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Lanes of the wave whose `digit` (nbits bits) equals this lane's, among the
-// lanes with valid set.
+// Orders the wavefront's LDS accesses before the fence against those after.
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lanes of the wave whose `digit` (nbits bits) equals this lane's, among the
+// lanes with valid set.
 __device__ __forceinline__ uint64_t match_digit(unsigned digit, int nbits, bool valid) {
   uint64_t peers = __ballot(valid);
   for (int b = 0; b < nbits; ++b) {
@@ -343,26 +344,6 @@ struct CbSmem {
   unsigned wl[16][34];
 };
 
-// count of a[0..n) that are < w (strict) or <= w, a ascending
-__device__ __forceinline__ unsigned lower_count(const uint32_t* a, unsigned n, uint32_t w) {
-  unsigned lo = 0, hi = n;
-  while (lo < hi) {
-    const unsigned mid = (lo + hi) >> 1;
-    if (a[mid] < w) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-__device__ __forceinline__ unsigned upper_count(const uint32_t* a, unsigned n, uint32_t w) {
-  unsigned lo = 0, hi = n;
-  while (lo < hi) {
-    const unsigned mid = (lo + hi) >> 1;
-    if (a[mid] <= w) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 // For four keys at once: pos[u] = count of a[0..n) below w[u] (LE: at most
 // w[u]), a ascending, n >= 1.  Branch-free halving (the probe is always in
 // range and the trip count depends on n only), so the four probes of a step
@@ -387,6 +368,24 @@ __device__ __forceinline__ void lds_count4(const uint32_t* a, unsigned n, const 
   for (int u = 0; u < 4; ++u) pos[u] = b[u] + ((LE ? v[u] <= w[u] : v[u] < w[u]) ? 1u : 0u);
 }
 
+// Count of the entries <= t in a[lo, hi) (ascending), by the whole block:
+// one probe per thread at a stride S = ceil((hi - lo) / 1024) finds the
+// stride interval that holds the boundary, then one probe per thread inside
+// it (S <= 1024 for the queue lengths here, at most 2^17).
+__device__ unsigned block_count_le(const uint32_t* a, unsigned lo, unsigned hi,
+                                   unsigned long long t) {
+  const unsigned len = hi - lo, tid = threadIdx.x;
+  if (len == 0) return 0;
+  const unsigned S = (len + 1023) / 1024;
+  const unsigned p = tid * S;
+  const unsigned c1 = __syncthreads_count(p < len && (unsigned long long)a[lo + p] <= t);
+  if (c1 == 0) return 0;
+  const unsigned base = (c1 - 1) * S;  // a[lo + base] <= t < a[lo + base + S] (or the end)
+  const unsigned q = base + 1 + tid;
+  const unsigned c2 = __syncthreads_count(tid + 1 < S && q < len && (unsigned long long)a[lo + q] <= t);
+  return base + 1 + c2;
+}
+
 // Weight bound of a merge round: with m nodes taken (a pending first child
 // of weight lastw when m is odd), the next pair's weight; l0 <= l1 and
 // i0 <= i1 are the fronts of the leaf and internal queues (~0 when empty).
@@ -399,53 +398,6 @@ __device__ __forceinline__ unsigned long long merge_threshold(unsigned m, uint32
   const unsigned long long a = l0 < i0 ? l0 : i0;
   const unsigned long long b = l0 < i0 ? (l1 < i0 ? l1 : i0) : (l0 < i1 ? l0 : i1);
   return a + b;
-}
-
-// Stable rank of each item among items with the same small digit (< 34), in
-// item order.  For every item calls fn(i, digit, rank) where rank counts
-// earlier items with that digit.  Wavefront w takes a contiguous run of the
-// items in tiles of 64 (peers with the same digit found by ballots, one
-// lane per digit updating the wave's counter): a counting pass, a scan of
-// the per-wave counts over the wavefronts, then the ranking pass; two block
-// barriers in all.
-template <typename DigitFn, typename Fn>
-__device__ void stable_digit_ranks(unsigned n, DigitFn digit_of, Fn fn, CbSmem& sm) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const unsigned run = ((n + 16 * 64 - 1) / (16 * 64)) * 64;  // items per wavefront
-  const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
-  for (int d = lane; d < 34; d += 64) sm.wl[wave][d] = 0;
-  wave_lds_fence();
-  for (unsigned t = i0; t < i1; t += 64) {
-    const unsigned i = t + lane;
-    const bool valid = i < i1;
-    const unsigned d = valid ? digit_of(i) : 0u;
-    const uint64_t peers = match_digit(d, 6, valid);
-    if (valid && __popcll(peers & lanemask_lt()) == 0) sm.wl[wave][d] += __popcll(peers);
-    wave_lds_fence();
-  }
-  __syncthreads();
-  if (tid < 34) {
-    unsigned acc = 0;
-    for (int w = 0; w < 16; ++w) {
-      const unsigned c = sm.wl[w][tid];
-      sm.wl[w][tid] = acc;
-      acc += c;
-    }
-  }
-  __syncthreads();
-  for (unsigned t = i0; t < i1; t += 64) {
-    const unsigned i = t + lane;
-    const bool valid = i < i1;
-    const unsigned d = valid ? digit_of(i) : 0u;
-    const uint64_t peers = match_digit(d, 6, valid);
-    const unsigned r = __popcll(peers & lanemask_lt());
-    const unsigned base = valid ? sm.wl[wave][d] : 0u;
-    if (valid) fn(i, d, base + r);
-    wave_lds_fence();
-    if (valid && r == 0) sm.wl[wave][d] = base + __popcll(peers);
-    wave_lds_fence();
-  }
-  __syncthreads();
 }
 
 // 1. non-zero keys in ascending symbol order (each thread owns 64 symbols,
@@ -709,37 +661,60 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
         continue;
       }
       // global-memory round: leaves and internal nodes of weight <= t
-      // (prefixes of the sorted queues)
-      unsigned la = li, ib = ii;
-      bool more_l = true, more_i = true;
-      while (more_l || more_i) {
-        const unsigned xl = la + tid, xi = ib + tid;
-        const bool okl = more_l && xl < n && (unsigned long long)Lw[xl] <= t;
-        const bool oki = more_i && xi < nI && (unsigned long long)s.Iw[xi] <= t;
-        const int cl = __syncthreads_count(okl);
-        const int ci = __syncthreads_count(oki);
-        la += cl;
-        ib += ci;
-        more_l = more_l && cl == 1024;
-        more_i = more_i && ci == 1024;
-      }
+      // (prefixes of the sorted queues, found by a two-level block search),
+      // four nodes per thread in flight
+      const unsigned la = li + block_count_le(Lw, li, n, t);
+      const unsigned ib = ii + block_count_le(s.Iw, ii, nI, t);
       const unsigned nl2 = la - li, ni2 = ib - ii;
       const unsigned m_new = m + nl2 + ni2;
-      for (unsigned x = li + tid; x < la; x += 1024) {
-        const uint32_t w = Lw[x];
-        const unsigned pos = m + (x - li) + lower_count(s.Iw + ii, ni2, w);
-        s.Sw[pos] = w;
-        s.leafPar[x] = pos >> 1;
+      for (unsigned x0 = li + tid; x0 < la; x0 += 4096) {
+        uint32_t w[4];
+        unsigned pos[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = Lw[min(x0 + 1024u * u, la - 1)];
+        if (ni2) lds_count4<false>(s.Iw + ii, ni2, w, pos);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned x = x0 + 1024u * u;
+          if (x < la) {
+            const unsigned p = m + (x - li) + pos[u];
+            s.Sw[p] = w[u];
+            s.leafPar[x] = p >> 1;
+          }
+        }
       }
-      for (unsigned y = ii + tid; y < ib; y += 1024) {
-        const uint32_t w = s.Iw[y];
-        const unsigned pos = m + (y - ii) + upper_count(Lw + li, nl2, w);
-        s.Sw[pos] = w;
-        s.parA[y] = pos >> 1;
+      for (unsigned y0 = ii + tid; y0 < ib; y0 += 4096) {
+        uint32_t w[4];
+        unsigned pos[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = s.Iw[min(y0 + 1024u * u, ib - 1)];
+        if (nl2) lds_count4<true>(Lw + li, nl2, w, pos);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned y = y0 + 1024u * u;
+          if (y < ib) {
+            const unsigned p = m + (y - ii) + pos[u];
+            s.Sw[p] = w[u];
+            s.parA[y] = p >> 1;
+          }
+        }
       }
       __syncthreads();
-      for (unsigned j = nI + tid; j < m_new / 2; j += 1024)
-        s.Iw[j] = (2 * j + 1 == m ? lastw0 : s.Sw[2 * j]) + s.Sw[2 * j + 1];
+      const unsigned mh2 = m_new / 2;
+      for (unsigned j0 = nI + tid; j0 < mh2; j0 += 4096) {
+        uint32_t a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned j = min(j0 + 1024u * u, mh2 - 1);
+          a[u] = s.Sw[2 * j];
+          b[u] = s.Sw[2 * j + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned j = j0 + 1024u * u;
+          if (j < mh2) s.Iw[j] = (2 * j + 1 == m ? lastw0 : a[u]) + b[u];
+        }
+      }
       __syncthreads();
       if (tid == 0) {
         const unsigned long long INF = ~0ull;
@@ -762,40 +737,66 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
     //    that large only shows that the code must be flattened).  A node
     //    created in round r is taken in a later round, so its parent is
     //    created later still: walking the rounds backwards, each round's
-    //    nodes are resolved in parallel, the next round's parent indices
-    //    loaded while the current round is resolved.
+    //    nodes are resolved in parallel.  The parent indices of as many of
+    //    the remaining rounds as fit are first staged in LDS (over the length
+    //    bytes, written only later) in one copy, so the rounds of a batch
+    //    wait on LDS only; a round larger than the stage reads them directly.
     uint8_t* dep = reinterpret_cast<uint8_t*>(&big);  // [n - 1] internal nodes
     uint8_t* lenAsc = dep + kDict;                     // [n] lengths in symbol order
     const unsigned rounds = sm.rounds;
     if (rounds <= (unsigned)kMaxRounds) {
-      constexpr int PF = 8;
+      constexpr unsigned kStage = (unsigned)((sizeof(CbBig) - kDict) / 4);
+      uint32_t* pst = reinterpret_cast<uint32_t*>(lenAsc);
       auto round_hi = [&](int r) { return r + 1 < (int)rounds ? sm.round_lo[r + 1] : root + 1; };
-      uint32_t cur[PF], nxt[PF];
+      for (int r = (int)rounds - 1; r >= 0;) {
+        const unsigned bhi = round_hi(r);
+        int r0 = r;
+        while (r0 > 0 && bhi - sm.round_lo[r0 - 1] <= kStage) --r0;
+        const unsigned blo = sm.round_lo[r0];
+        if (bhi - blo <= kStage) {
+          for (unsigned y0 = blo + tid; y0 < bhi; y0 += 8192) {
+            uint32_t v[8];
 #pragma unroll
-      for (int u = 0; u < PF; ++u) {
-        const unsigned y = sm.round_lo[rounds - 1] + tid + 1024u * u;
-        cur[u] = y < root + 1 ? s.parA[min(y, root)] : 0u;
-      }
-      for (int r = (int)rounds - 1; r >= 0; --r) {
-        const unsigned lo = sm.round_lo[r], hi = round_hi(r);
-        if (r > 0) {
-          const unsigned lo1 = sm.round_lo[r - 1], hi1 = lo;
+            for (int u = 0; u < 8; ++u) v[u] = s.parA[min(y0 + 1024u * u, bhi - 1)];
 #pragma unroll
-          for (int u = 0; u < PF; ++u) {
-            const unsigned y = lo1 + tid + 1024u * u;
-            nxt[u] = s.parA[min(y, hi1 > 0 ? hi1 - 1 : 0u)];
+            for (int u = 0; u < 8; ++u)
+              if (y0 + 1024u * u < bhi) pst[y0 + 1024u * u - blo] = v[u];
           }
-        }
+          __syncthreads();
+          for (int rr = r; rr >= r0; --rr) {
+            const unsigned lo = sm.round_lo[rr], hi = round_hi(rr);
+            for (unsigned y0 = lo + tid; y0 < hi; y0 += 4096) {
+              uint32_t pv[4], dv[4];
 #pragma unroll
-        for (int u = 0; u < PF; ++u) {
-          const unsigned y = lo + tid + 1024u * u;
-          if (y < hi) dep[y] = y == root ? 0 : (uint8_t)min(dep[cur[u]] + 1u, 255u);
-        }
-        for (unsigned y = lo + tid + 1024u * PF; y < hi; y += 1024)
-          dep[y] = y == root ? 0 : (uint8_t)min(dep[s.parA[y]] + 1u, 255u);
-        __syncthreads();
+              for (int u = 0; u < 4; ++u) pv[u] = pst[min(y0 + 1024u * u, hi - 1) - blo];
 #pragma unroll
-        for (int u = 0; u < PF; ++u) cur[u] = nxt[u];
+              for (int u = 0; u < 4; ++u) dv[u] = dep[min(pv[u], root)];  // (the root has no parent)
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const unsigned y = y0 + 1024u * u;
+                if (y < hi) dep[y] = y == root ? 0 : (uint8_t)min(dv[u] + 1u, 255u);
+              }
+            }
+            __syncthreads();
+          }
+          r = r0 - 1;
+        } else {
+          const unsigned lo = sm.round_lo[r];
+          for (unsigned y0 = lo + tid; y0 < bhi; y0 += 8192) {
+            uint32_t pv[8], dv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) pv[u] = s.parA[min(y0 + 1024u * u, bhi - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) dv[u] = dep[min(pv[u], root)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const unsigned y = y0 + 1024u * u;
+              if (y < bhi) dep[y] = y == root ? 0 : (uint8_t)min(dv[u] + 1u, 255u);
+            }
+          }
+          __syncthreads();
+          r -= 1;
+        }
       }
     } else {
       // pointer jumping towards the root (global memory), then saturated
@@ -826,19 +827,19 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
       for (unsigned y = tid; y <= root; y += 1024) dep[y] = (uint8_t)min(da[y], 255u);
       __syncthreads();
     }
-    // 5. leaf lengths, stored by the leaf's position in symbol order (four
-    //    leaves per thread in flight)
+    // 5. leaf lengths, stored by the leaf's position in symbol order
+    //    (sixteen leaves per thread in flight)
     unsigned lmax = 0;
-    for (unsigned x0 = tid; x0 < n; x0 += 4096) {
-      uint32_t par[4], lx[4];
+    for (unsigned x0 = tid; x0 < n; x0 += 16384) {
+      uint32_t par[16], lx[16];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const unsigned x = min(x0 + 1024 * u, n - 1);
         par[u] = s.leafPar[x];
         lx[u] = Lx[x];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 16; ++u) {
         if (x0 + 1024 * u < n) {
           const unsigned l = min(dep[par[u]] + 1u, 255u);
           lenAsc[lx[u]] = (uint8_t)l;
@@ -852,47 +853,107 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
     __syncthreads();
   }
   // 6. canonical codes: count per length, first code per length, then the
-  //    rank of each symbol among equal lengths in ascending symbol order
+  //    rank of each symbol among equal lengths in ascending symbol order.
+  //    Wavefront w takes a contiguous run of the symbols in tiles of 64.  Its
+  //    running count of each length d sits in lane d; a tile is taken one
+  //    distinct length at a time (the lengths of neighbouring symbols mostly
+  //    agree, so a tile holds few): the first remaining lane names the
+  //    length, a ballot finds its peers, their ranks are the count read from
+  //    lane d plus their order in the tile, and lane d advances.  A counting
+  //    pass, the scan of the counts over the wavefronts (which also gives the
+  //    counts per length), then the ranking pass with eight tiles of loads in
+  //    flight.
   const uint8_t* lenAsc = reinterpret_cast<const uint8_t*>(&big) + kDict;
-  if (tid < 34) sm.lfirst[tid] = 0;
-  __syncthreads();
-  // one LDS add per distinct length in each wavefront's 64 symbols
-  for (unsigned t = tid & ~63u; t < n; t += 1024) {
-    const unsigned i = t + (tid & 63);
-    const bool valid = i < n;
-    const unsigned l = valid ? lenAsc[i] : 0u;
-    const uint64_t peers = match_digit(l, 6, valid);
-    if (valid && __popcll(peers & lanemask_lt()) == 0) atomicAdd(&sm.lfirst[l], __popcll(peers));
-  }
-  __syncthreads();
-  if (tid == 0) {
-    unsigned c = 0, ml = 0;
-    for (int l = 1; l <= kMaxCodeLen; ++l) {
-      const unsigned cntl = sm.lfirst[l];
-      if (cntl) ml = l;
-      sm.lfirst[l] = c;
-      s.pk[kDict + l] = c;  // first code of each length, for the encoder
-      c = (c + cntl) << 1;
+  {
+    constexpr int B = 8;
+    const int wave = tid >> 6, lane = tid & 63;
+    const unsigned run = ((n + 1023) / 1024) * 64;
+    const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
+    unsigned cnt = 0;  // lane d: symbols of length d so far
+    for (unsigned t = i0; t < i1; t += 64 * B) {
+      unsigned dl[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) dl[u] = lenAsc[min(t + u * 64 + lane, i1 - 1)];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        uint64_t rem = __ballot(t + u * 64 + lane < i1);
+        while (rem) {
+          const int ld = __ffsll((unsigned long long)rem) - 1;
+          const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dl[u], ld);
+          const uint64_t m = __ballot(dl[u] == d) & rem;
+          if (lane == (int)d) cnt += (unsigned)__popcll(m);
+          rem &= ~m;
+        }
+      }
     }
-    lay->max_len = ml;
+    if (lane < 34) sm.wl[wave][lane] = cnt;
+    __syncthreads();
+    if (tid < 34) {
+      unsigned acc = 0;
+      for (int w = 0; w < 16; ++w) {
+        const unsigned c = sm.wl[w][tid];
+        sm.wl[w][tid] = acc;
+        acc += c;
+      }
+      sm.lcount[tid] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned c = 0, ml = 0;
+      for (int l = 1; l <= kMaxCodeLen; ++l) {
+        const unsigned cntl = sm.lcount[l];
+        if (cntl) ml = l;
+        sm.lfirst[l] = c;
+        s.pk[kDict + l] = c;  // first code of each length, for the encoder
+        c = (c + cntl) << 1;
+      }
+      lay->max_len = ml;
+    }
+    __syncthreads();
+    // 7. per symbol: code, length, the packed (rank, length) word of the
+    //    encoder, and the codebook section (symbols ascending, then their
+    //    lengths)
+    cnt = lane < 34 ? sm.wl[wave][lane] : 0u;      // earlier wavefronts' symbols
+    const unsigned fst = lane < 34 ? sm.lfirst[lane] : 0u;
+    uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
+    for (unsigned t = i0; t < i1; t += 64 * B) {
+      unsigned dl[B], sy[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const unsigned i = min(t + u * 64 + lane, i1 - 1);
+        dl[u] = lenAsc[i];
+        sy[u] = s.symAsc[i];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const unsigned i = t + u * 64 + lane;
+        const bool valid = i < i1;
+        uint64_t rem = __ballot(valid);
+        unsigned rank = 0, first = 0;
+        while (rem) {
+          const int ld = __ffsll((unsigned long long)rem) - 1;
+          const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dl[u], ld);
+          const uint64_t m = __ballot(dl[u] == d) & rem;
+          const unsigned base = (unsigned)__builtin_amdgcn_readlane((int)cnt, (int)d);
+          const unsigned fd = (unsigned)__builtin_amdgcn_readlane((int)fst, (int)d);
+          if ((m >> lane) & 1u) {
+            rank = base + (unsigned)__popcll(m & lanemask_lt());
+            first = fd;
+          }
+          if (lane == (int)d) cnt += (unsigned)__popcll(m);
+          rem &= ~m;
+        }
+        if (valid) {
+          const unsigned d = dl[u];
+          code[sy[u]] = first + rank;
+          clen[sy[u]] = (uint8_t)d;
+          s.pk[sy[u]] = (rank << 6) | d;
+          cs[i] = (uint16_t)sy[u];
+          cb_out[2 * n + i] = (uint8_t)d;
+        }
+      }
+    }
   }
-  __syncthreads();
-  // 7. per symbol: code, length, the packed (rank, length) word of the
-  //    encoder, and the codebook section (symbols ascending, then their
-  //    lengths)
-  uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
-  stable_digit_ranks(
-      n, [&](unsigned i) { return (unsigned)lenAsc[i]; },
-      [&](unsigned i, unsigned d, unsigned rank) {
-        const unsigned sy = s.symAsc[i];
-        const unsigned c = sm.lfirst[d] + rank;
-        code[sy] = c;
-        clen[sy] = (uint8_t)d;
-        s.pk[sy] = (rank << 6) | d;
-        cs[i] = (uint16_t)sy;
-        cb_out[2 * n + i] = (uint8_t)d;
-      },
-      sm);
   if (tid == 0) lay->n_codes = n;
 }
 
