@@ -2054,20 +2054,30 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
   }
   if (bad) sm.flag = 1;
   // per-wave counts of each length: wavefront w takes a contiguous run of
-  // the section in tiles of 64 (the same runs rank the codes below)
+  // the section in tiles of 64 (the same runs rank the codes below); its
+  // count of length d sits in lane d, and a tile is taken one distinct
+  // length at a time (first remaining lane, then a ballot for its peers)
   const unsigned run = ((n + 16 * 64 - 1) / (16 * 64)) * 64;
   const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
-  for (int d = lane; d < 34; d += 64) sm.wl[wave][d] = 0;
   __syncthreads();  // lengths in LDS
-  // one LDS add per distinct length and tile (a wavefront's LDS atomics
-  // take effect in issue order, so the tiles need no fence between them)
-  for (unsigned t0 = i0; t0 < i1; t0 += 64) {
-    const unsigned i = t0 + lane;
-    const bool valid = i < i1;
-    const unsigned d = valid ? lenL[i] : 0u;
-    const uint64_t peers = match_digit(d, 6, valid);
-    if (valid && __popcll(peers & lanemask_lt()) == 0) atomicAdd(&sm.wl[wave][d], __popcll(peers));
+  unsigned cnt = 0;
+  for (unsigned t0 = i0; t0 < i1; t0 += 64 * 8) {
+    unsigned dl[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) dl[u] = lenL[min(t0 + 64 * u + lane, i1 - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      uint64_t rem = __ballot(t0 + 64 * u + lane < i1);
+      while (rem) {
+        const int ld = __ffsll((unsigned long long)rem) - 1;
+        const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dl[u], ld);
+        const uint64_t m = __ballot(dl[u] == d) & rem;
+        if (lane == (int)d) cnt += (unsigned)__popcll(m);
+        rem &= ~m;
+      }
+    }
   }
+  if (lane < 34) sm.wl[wave][lane] = cnt;
   __syncthreads();
   if (tid < 34) {
     unsigned c = 0;
@@ -2122,6 +2132,7 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
   }
   __syncthreads();
   constexpr int PF = 8;
+  cnt = lane < 34 ? sm.wl[wave][lane] : 0u;  // lane d: next slot of length d
   uint16_t cur[PF], nxt[PF];
 #pragma unroll
   for (int u = 0; u < PF; ++u) cur[u] = i0 < i1 ? syms[min(i0 + 64 * u + lane, i1 - 1)] : 0;
@@ -2133,18 +2144,23 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     }
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      // the lowest lane of each length takes the slots with one LDS
-      // add-and-return and hands the first slot to its peers
+      // per distinct length of the tile: its codes take the next slots of
+      // the length in lane order, and lane d advances
       const unsigned i = g + 64 * u + lane;
       const bool valid = i < i1;
-      const unsigned d = valid ? lenL[i] : 0u;
-      const uint64_t peers = match_digit(d, 6, valid);
-      const unsigned r = __popcll(peers & lanemask_lt());
-      unsigned first = 0;
-      if (valid && r == 0) first = atomicAdd(&sm.wl[wave][d], __popcll(peers));
-      const int leader = valid ? __ffsll((long long)peers) - 1 : lane;
-      const unsigned base = (unsigned)__shfl((int)first, leader, 64);
-      if (valid) t->sorted[base + r] = cur[u];
+      const unsigned dv = lenL[min(i, i1 - 1)];
+      uint64_t rem = __ballot(valid);
+      unsigned slot = 0;
+      while (rem) {
+        const int ld = __ffsll((unsigned long long)rem) - 1;
+        const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dv, ld);
+        const uint64_t m = __ballot(dv == d) & rem;
+        const unsigned base = (unsigned)__builtin_amdgcn_readlane((int)cnt, (int)d);
+        if ((m >> lane) & 1u) slot = base + (unsigned)__popcll(m & lanemask_lt());
+        if (lane == (int)d) cnt += (unsigned)__popcll(m);
+        rem &= ~m;
+      }
+      if (valid) t->sorted[slot] = cur[u];
     }
 #pragma unroll
     for (int u = 0; u < PF; ++u) cur[u] = nxt[u];
