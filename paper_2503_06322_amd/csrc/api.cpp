@@ -240,6 +240,24 @@ void solve_coarse(mgc_ctx ctx, const LevelGeom& g, double* x, const double* sub,
   }
 }
 
+// The levels 1..top that run in one workgroup with their grids in LDS (0:
+// none): the largest top whose levels all fit, their tables within the LDS
+// copy; *tt receives the copy's range and offsets.
+int tail_top(const Plan& p, TailTabArgs* tt) {
+  int top = 0;
+  const size_t t0 = p.lv.size() > 1 ? p.lv[1].t_wl[0] : 0;
+  for (int l = 1; l <= p.L && l < kTailLevels; ++l) {
+    const PlanLevel& v = p.lv[l];
+    const size_t end = v.t_Mt[2] + 3 * (size_t)v.nf[2];
+    if (!tail_level_fits(p.geom(l)) || end - t0 > tail_max_table()) break;
+    top = l;
+    tt->n = (uint32_t)(end - t0);
+    for (int k = 0; k < 3; ++k) tt->wl[l][k] = (uint32_t)(v.t_wl[k] - t0);
+  }
+  tt->src = p.d_tab + t0;
+  return top;
+}
+
 // rdev: device reciprocal bins r_0..r_L (quantising runs, sym != nullptr);
 // gate: the compression's status word (null: ungated).
 void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_f32,
@@ -248,7 +266,9 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
                           const unsigned* gate, hipStream_t s) {
   const void* Gcur = d_in;
   bool cur_f32 = in_f32;
-  for (int l = p.L; l >= 1; --l) {
+  TailTabArgs tt{};
+  const int top = tail_top(p, &tt);
+  for (int l = p.L; l > top; --l) {
     double* Gnext = ((p.L - l) % 2 == 0) ? gA : gB;
     const LevelGeom g = p.geom(l);
     {
@@ -259,6 +279,12 @@ void run_levels_decompose(mgc_ctx ctx, const Plan& p, const void* d_in, bool in_
     solve_coarse(ctx, g, Gnext, nullptr, l == p.L, true, s);
     Gcur = Gnext;
     cur_f32 = false;
+  }
+  if (top >= 1) {
+    StageScope sc(&ctx->prof, "dec_tail", s);
+    launch_dec_tail(Gcur, cur_f32, p.d_geo, top, tt, sym, raw, sym ? rdev : nullptr, ob, status,
+                    gate, s);
+    return;
   }
   StageScope sc(&ctx->prof, "level0", s);
   launch_level0(Gcur, cur_f32, p.points(0), sym, raw, sym ? rdev : nullptr, ob, status, gate,
@@ -288,13 +314,21 @@ void run_levels_recompose(mgc_ctx ctx, const Plan& p, const CoeffSrc& src,
       off += (size_t)p.points(l);
     }
   }
-  {
+  // (with levels requested every level's grid goes to memory: no tail)
+  TailTabArgs tt{};
+  const int top = levels ? 0 : tail_top(p, &tt);
+  if (top >= 1) {
+    StageScope sc(&ctx->prof, "rec_tail", s);
+    launch_rec_tail(src, coarse ? *coarse : src, coarse ? coarse_top : -1, q.data(), p.d_geo, top,
+                    tt, top == p.L ? d_out : (void*)slot[0], top == p.L && out_f32, s);
+    if (top == p.L) return;
+  } else {
     StageScope sc(&ctx->prof, "rec_level0", s);
     launch_rec_level0(src_of(0), p.points(0), q[0], slot[0], false, s);
   }
   double* Gprev = slot[0];
   double* F = gB;
-  for (int l = 1; l <= p.L; ++l) {
+  for (int l = top + 1; l <= p.L; ++l) {
     const LevelGeom g = p.geom(l);
     const bool fin = l == p.L;
     {

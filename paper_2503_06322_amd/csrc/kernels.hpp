@@ -97,6 +97,30 @@ void launch_dequant_prefix(const CoeffSrc& src, int64_t m, const LevelBins& lb, 
                            hipStream_t s);
 void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, bool out_f32,
                        hipStream_t s);
+// The smallest levels in one workgroup with their grids in LDS.  Level l
+// qualifies when its fine grid, coarse grid and coarse lines fit; the levels
+// 1..top taken must all qualify, with top < kTailLevels and their tables (a
+// prefix of the plan's table block) at most tail_max_table() doubles.
+constexpr int kTailLevels = 16;
+struct TailTabArgs {
+  const double* src;            // device: level 1's first table (axis 0 wl)
+  uint32_t n;                   // doubles up to the end of level top's tables
+  uint32_t wl[kTailLevels][3];  // offset of level l's axis-k wl from src
+};
+bool tail_level_fits(const LevelGeom& g);
+size_t tail_max_table();
+// Decomposition of levels top..1 and level 0 (as the level loop with
+// launch_dec_level, the solves and launch_level0): G is level top's grid;
+// d_geo the plan's device geometry (d_geo[l]).
+void launch_dec_tail(const void* G, bool g_is_f32, const LevelGeom* d_geo, int top,
+                     const TailTabArgs& tt, uint16_t* sym, double* raw, const double* rdev,
+                     const OutlierBuf& ob, unsigned* status, const unsigned* gate, hipStream_t s);
+// Recomposition of level 0 and levels 1..top (as launch_rec_level0 and the
+// level loop): out receives level top's grid; the coefficients of levels
+// <= coarse_top come from `coarse`, the others from src; q[0..top] host.
+void launch_rec_tail(const CoeffSrc& src, const CoeffSrc& coarse, int coarse_top,
+                     const double* q, const LevelGeom* d_geo, int top, const TailTabArgs& tt,
+                     void* out, bool out_f32, hipStream_t s);
 // Adjoint of recomposition, one level: Gc = P^T g (also copied to Gc_copy,
 // which the Thomas sweeps then turn into v = M_{l-1}^{-1} Gc); Pv on the fine
 // grid; cbar (stream order) = g - M_l P v at the level's new nodes.

@@ -2241,11 +2241,22 @@ __global__ __launch_bounds__(kThomasGridThreads) void k_thomas_grid(
     double* __restrict__ x, int64_t n0, int64_t n1, int64_t n2, const Thomas3Args a,
     const double* __restrict__ sub) {
   constexpr int NT = kThomasGridThreads;
+  constexpr int ML = kThomasGridMaxLine;
   extern __shared__ double gsm[];
+  // the factors of every active axis go to LDS with the grid, so that the
+  // sweeps' steps wait on LDS only
+  __shared__ double tab[3][3][ML];
   const int n = (int)(n0 * n1 * n2);
+  const int64_t nn[3] = {n0, n1, n2};
+  for (int i = threadIdx.x; i < 9 * ML; i += NT) {
+    const int axis = i / (3 * ML), k = (i / ML) % 3, j = i % ML;
+    if (a.active[axis] && j < (int)nn[axis]) {
+      const double* src = k == 0 ? a.ta[axis] : (k == 1 ? a.tm[axis] : a.tc[axis]);
+      tab[axis][k][j] = src[j];
+    }
+  }
   block_load_lds<NT>(x, gsm, n);
   __syncthreads();
-  const int64_t nn[3] = {n0, n1, n2};
   for (int axis = 2; axis >= 0; --axis) {
     if (!a.active[axis]) continue;
     const int L = (int)nn[axis];
@@ -2256,11 +2267,406 @@ __global__ __launch_bounds__(kThomasGridThreads) void k_thomas_grid(
       if (axis == 2) base = t * (int)n2;
       else if (axis == 1) base = (t / (int)n2) * (int)(n1 * n2) + t % (int)n2;
       else base = t;
-      lds_line_sweep(gsm + base, L, stride, a.ta[axis], a.tm[axis], a.tc[axis]);
+      lds_line_sweep(gsm + base, L, stride, tab[axis][0], tab[axis][1], tab[axis][2]);
     }
     __syncthreads();
   }
   block_store_lds<NT>(x, gsm, n, sub);
+}
+
+// ------------------------------------------------ the smallest levels, one block
+// The last levels of a hierarchy (fine grids of at most kTailMax points) run
+// in one workgroup with every grid in LDS: per level the cells (interpolation
+// and quantisation, or recomposition's interpolation plus coefficients), the
+// separable restriction (x, then y, then z) and the coarse solves (axes 2,
+// 1, 0), with block barriers where the level loop has launches.  Each value
+// is formed by the same operations in the same order as in the tiled level
+// kernels and the LDS-resident solve (k_thomas_grid), so the results agree
+// bit for bit.  The levels' operator tables are one contiguous range of the
+// plan's table block (level by level, axis by axis: wl, wr, W, ta, tm, tc and
+// the adjoint's tables), copied to LDS with the first grid and the levels'
+// geometry, so the kernel waits on memory once before its first level.
+constexpr int kTailMax = 4913;     // fine points of the largest level taken (17^3)
+constexpr int kTailCoarse = 2464;  // coarse points (and nf0 nc1 nc2) of that level at most
+constexpr int kTailLine = 128;     // longest active coarse line (one thread per line)
+constexpr int kTailTab = 2048;     // doubles of the table range
+constexpr int kTailThreads = 512;
+constexpr int kTailEsc = 1024;     // escaped values staged in LDS (the rest: direct)
+
+// Pointers into the LDS table copy for one level and axis.
+struct TailAxis {
+  const double *wl, *wr, *W, *ta;
+};
+__device__ __forceinline__ TailAxis tail_axis(const double* tab, const TailTabArgs& ta,
+                                              const LevelGeom& g, int l, int k) {
+  const double* b = tab + ta.wl[l][k];
+  const int nf = (int)g.nf[k], nc = (int)g.nc[k];
+  return TailAxis{b, b + nf, b + 2 * nf, b + 2 * nf + 5 * nc};
+}
+
+// Copies the table range and the geometry of levels 1..top (all loads of a
+// thread issued before its stores).  No barrier.
+__device__ __forceinline__ void tail_fetch(const TailTabArgs& ta, double* tab,
+                                           const LevelGeom* __restrict__ geo, int top,
+                                           LevelGeom* sgeo) {
+  const int tid = threadIdx.x;
+  if (tid >= 1 && tid <= top) sgeo[tid] = geo[tid];
+  for (uint32_t i0 = tid; i0 < ta.n; i0 += 8 * kTailThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ta.src[min(i0 + u * kTailThreads, ta.n - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u * kTailThreads < ta.n) tab[i0 + u * kTailThreads] = v[u];
+  }
+}
+
+// The separable restriction (x, then y, then z; taps clamped to the grid,
+// where out-of-grid taps have weight zero) of the fine grid F (dims nf) to
+// the coarse grid C (dims nc); A and B scratch (B may alias F).
+__device__ void tail_restrict(const double* F, double* A, double* B, double* C,
+                              const LevelGeom& g, const double* W0, const double* W1,
+                              const double* W2) {
+  const int tid = threadIdx.x;
+  const int nf0 = (int)g.nf[0], nf1 = (int)g.nf[1], nf2 = (int)g.nf[2];
+  const int nc0 = (int)g.nc[0], nc1 = (int)g.nc[1], nc2 = (int)g.nc[2];
+  const int nA = nf0 * nf1 * nc2;
+  for (int e = tid; e < nA; e += kTailThreads) {
+    const int cx = e % nc2, row = e / nc2;
+    const int p = (int)cpos32((uint32_t)cx, (uint32_t)nf2);
+    const double* r = F + row * nf2;
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) acc = fma(W2[5 * cx + d], r[min(max(p + d - 2, 0), nf2 - 1)], acc);
+    A[e] = acc;
+  }
+  __syncthreads();
+  const int nB = nf0 * nc1 * nc2;
+  for (int e = tid; e < nB; e += kTailThreads) {
+    const int cx = e % nc2, rest = e / nc2, cy = rest % nc1, z = rest / nc1;
+    const int p = (int)cpos32((uint32_t)cy, (uint32_t)nf1);
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+      acc = fma(W1[5 * cy + d], A[(z * nf1 + min(max(p + d - 2, 0), nf1 - 1)) * nc2 + cx], acc);
+    B[e] = acc;
+  }
+  __syncthreads();
+  const int nC = nc0 * nc1 * nc2;
+  for (int e = tid; e < nC; e += kTailThreads) {
+    const int cyx = e % (nc1 * nc2), cz = e / (nc1 * nc2);
+    const int p = (int)cpos32((uint32_t)cz, (uint32_t)nf0);
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < 5; ++d)
+      acc = fma(W0[5 * cz + d], B[min(max(p + d - 2, 0), nf0 - 1) * (nc1 * nc2) + cyx], acc);
+    C[e] = acc;
+  }
+  __syncthreads();
+}
+
+// The solves of the coarse grid C (dims nc) along its active axes, 2, then
+// 1, then 0, one thread per line (as k_thomas_grid).
+__device__ void tail_solve(double* C, const LevelGeom& g, const TailAxis (&ax)[3]) {
+  const int n0 = (int)g.nc[0], n1 = (int)g.nc[1], n2 = (int)g.nc[2];
+  const int n = n0 * n1 * n2;
+  const int nn[3] = {n0, n1, n2};
+  for (int axis = 2; axis >= 0; --axis) {
+    if (g.bit[axis] < 0) continue;
+    const int L = nn[axis];
+    const int lines = n / L;
+    const int stride = axis == 2 ? 1 : (axis == 1 ? n2 : n1 * n2);
+    const double* ta = ax[axis].ta;
+    for (int t = threadIdx.x; t < lines; t += kTailThreads) {
+      int base;
+      if (axis == 2) base = t * n2;
+      else if (axis == 1) base = (t / n2) * (n1 * n2) + t % n2;
+      else base = t;
+      lds_line_sweep(C + base, L, stride, ta, ta + L, ta + 2 * L);
+    }
+    __syncthreads();
+  }
+}
+
+struct DecTailSmem {
+  double X[kTailMax];     // fine grid of the level (or, alternately, its coarse grid)
+  double Y[kTailCoarse];  // coarse grid (or, alternately, the fine grid)
+  double A[kTailMax];     // restriction along x
+  double tab[kTailTab];
+  LevelGeom geo[kTailLevels];
+  uint32_t esc_pos[kTailEsc];
+  int64_t esc_val[kTailEsc];
+  unsigned n_esc;
+  unsigned long long esc_base;
+};
+
+// Decomposition of levels top..1 and level 0: G holds level top's grid.
+// Escaped values are staged in LDS (one reservation of outlier records for
+// the whole launch); beyond kTailEsc they take emit_q's direct path.
+template <typename Tin, bool QUANT>
+__global__ __launch_bounds__(kTailThreads) void k_dec_tail(
+    const Tin* __restrict__ G, const LevelGeom* __restrict__ geo, const int top,
+    const TailTabArgs tt, uint16_t* __restrict__ sym, double* __restrict__ raw,
+    const double* __restrict__ rdev, const OutlierBuf ob, unsigned* __restrict__ status,
+    const unsigned* __restrict__ gate) {
+  if (gate_closed(gate)) return;
+  __shared__ DecTailSmem sm;
+  const int tid = threadIdx.x;
+  if (tid == 0) sm.n_esc = 0;
+  {
+    // the grid's first loads in flight across the table copy
+    const int n = (int)(geo[top].nf[0] * geo[top].nf[1] * geo[top].nf[2]);
+    for (int i0 = tid, first = 1; i0 < n || first; i0 += 8 * kTailThreads, first = 0) {
+      Tin v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = G[min(i0 + u * kTailThreads, n - 1)];
+      if (first) tail_fetch(tt, sm.tab, geo, top, sm.geo);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u * kTailThreads < n) sm.X[i0 + u * kTailThreads] = (double)v[u];
+    }
+  }
+  __syncthreads();
+  auto emit = [&](uint32_t pos, double c, double r) {
+    if (!QUANT) {
+      raw[pos] = c;
+      return;
+    }
+    // the symbol and escape of emit_q; the escape's record staged in LDS
+    const double t = rint(c * r);
+    const bool esc = !(fabs(t) < 32768.0);
+    sym[pos] = (uint16_t)(int)((esc ? -32768.0 : t) + 32768.0);
+    const uint64_t m = __ballot(esc);
+    if (m == 0) return;
+    if (esc) {
+      int64_t k = 0;
+      if (fabs(t) < 4611686018427387904.0) k = (int64_t)t;
+      else atomicOr(status, ST_RANGE);
+      const int lane = (int)__lane_id();
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      unsigned base = 0;
+      if (lane == leader) base = atomicAdd(&sm.n_esc, (unsigned)__popcll(m));
+      base = (unsigned)__shfl((int)base, leader, 64);
+      const unsigned i = base + (unsigned)__popcll(m & ((1ull << lane) - 1));
+      if (i < (unsigned)kTailEsc) {
+        sm.esc_pos[i] = pos;
+        sm.esc_val[i] = k;
+      } else {
+        const unsigned long long j = atomicAdd(ob.count, 1ull);
+        if (j < ob.cap) {
+          ob.pos[j] = pos;
+          ob.val[j] = k;
+        }
+      }
+    }
+  };
+  double* F = sm.X;  // fine grid of the level
+  double* C = sm.Y;  // its coarse grid
+  for (int l = top; l >= 1; --l) {
+    const LevelGeom& g = sm.geo[l];
+    const TailAxis ax[3] = {tail_axis(sm.tab, tt, g, l, 0), tail_axis(sm.tab, tt, g, l, 1),
+                            tail_axis(sm.tab, tt, g, l, 2)};
+    const double r = QUANT ? rdev[l] : 0.0;
+    const uint32_t nf0 = (uint32_t)g.nf[0], nf1 = (uint32_t)g.nf[1], nf2 = (uint32_t)g.nf[2];
+    const uint32_t nc0 = (uint32_t)g.nc[0], nc1 = (uint32_t)g.nc[1], nc2 = (uint32_t)g.nc[2];
+    const uint32_t e1c = nc1, e1n = nf1 - nc1, e2c = nc2, e2n = nf2 - nc2;
+    const uint32_t lvl = (uint32_t)g.level_off;
+    const int m0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, m1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
+              m2 = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
+    uint32_t so[8];
+    subband_offsets(g, so);
+    auto T = [&](uint32_t z, uint32_t y, uint32_t x) { return F[(z * nf1 + y) * nf2 + x]; };
+    // cells: the new nodes' coefficients (the forms of lerp_cells)
+    const uint32_t ncell = nc0 * nc1 * nc2;
+    for (uint32_t e = tid; e < ncell; e += kTailThreads) {
+      const uint32_t J2 = e % nc2, rest = e / nc2, J1 = rest % nc1, J0 = rest / nc1;
+      const bool h0 = 2 * J0 + 1 < nf0 - 1, h1 = 2 * J1 + 1 < nf1 - 1, h2 = 2 * J2 + 1 < nf2 - 1;
+      if (!(h0 || h1 || h2)) continue;
+      const uint32_t p0 = cpos32(J0, nf0), p1 = cpos32(J1, nf1), p2 = cpos32(J2, nf2);
+      const uint32_t s0 = h0 ? p0 + 2 : p0, s1 = h1 ? p1 + 2 : p1, s2 = h2 ? p2 + 2 : p2;
+      const uint32_t q0 = h0 ? p0 + 1 : p0, q1 = h1 ? p1 + 1 : p1, q2 = h2 ? p2 + 1 : p2;
+      const double wz0 = ax[0].wl[q0], wz1 = ax[0].wr[q0];
+      const double wy0 = ax[1].wl[q1], wy1 = ax[1].wr[q1];
+      const double wx0 = ax[2].wl[q2], wx1 = ax[2].wr[q2];
+      const double c000 = T(p0, p1, p2), c001 = T(p0, p1, s2), c010 = T(p0, s1, p2),
+                   c011 = T(p0, s1, s2), c100 = T(s0, p1, p2), c101 = T(s0, p1, s2),
+                   c110 = T(s0, s1, p2), c111 = T(s0, s1, s2);
+      const double ix00 = lin2(wx0, c000, wx1, c001), ix01 = lin2(wx0, c010, wx1, c011);
+      const double ix10 = lin2(wx0, c100, wx1, c101), ix11 = lin2(wx0, c110, wx1, c111);
+      const uint32_t base_cc = (J0 * e1c + J1) * e2c + J2, base_cn = (J0 * e1c + J1) * e2n + J2;
+      const uint32_t base_nc = (J0 * e1n + J1) * e2c + J2, base_nn = (J0 * e1n + J1) * e2n + J2;
+      if (h2) emit(lvl + sel8(so, m2) + base_cn, T(p0, p1, q2) - ix00, r);
+      if (h1) emit(lvl + sel8(so, m1) + base_nc, T(p0, q1, p2) - (lin2(wy0, c000, wy1, c010)), r);
+      if (h1 && h2)
+        emit(lvl + sel8(so, m1 | m2) + base_nn, T(p0, q1, q2) - (lin2(wy0, ix00, wy1, ix01)), r);
+      if (h0) emit(lvl + sel8(so, m0) + base_cc, T(q0, p1, p2) - (lin2(wz0, c000, wz1, c100)), r);
+      if (h0 && h2)
+        emit(lvl + sel8(so, m0 | m2) + base_cn, T(q0, p1, q2) - (lin2(wz0, ix00, wz1, ix10)), r);
+      if (h0 && h1)
+        emit(lvl + sel8(so, m0 | m1) + base_nc,
+             T(q0, q1, p2) - (lin2(wz0, lin2(wy0, c000, wy1, c010), wz1, lin2(wy0, c100, wy1, c110))),
+             r);
+      if (h0 && h1 && h2)
+        emit(lvl + sel8(so, m0 | m1 | m2) + base_nn,
+             T(q0, q1, q2) - (lin2(wz0, lin2(wy0, ix00, wy1, ix01), wz1, lin2(wy0, ix10, wy1, ix11))),
+             r);
+    }
+    // (the restriction's first pass only reads F, as the cells do)
+    tail_restrict(F, sm.A, F, C, g, ax[0].W, ax[1].W, ax[2].W);
+    tail_solve(C, g, ax);
+    double* t = F;
+    F = C;
+    C = t;
+  }
+  // level 0: the coarsest grid's values at stream positions 0..
+  const LevelGeom& g1 = sm.geo[1];
+  const int n0 = (int)(g1.nc[0] * g1.nc[1] * g1.nc[2]);
+  const double r0 = QUANT ? rdev[0] : 0.0;
+  for (int i = tid; i < n0; i += kTailThreads) emit((uint32_t)i, F[i], r0);
+  if (QUANT) {
+    // the staged records: one reservation, then the copies
+    __syncthreads();
+    const unsigned ne = min(sm.n_esc, (unsigned)kTailEsc);
+    if (tid == 0) sm.esc_base = ne ? atomicAdd(ob.count, (unsigned long long)ne) : 0ull;
+    __syncthreads();
+    const unsigned long long b = sm.esc_base;
+    for (unsigned i = tid; i < ne; i += kTailThreads) {
+      if (b + i < ob.cap) {
+        ob.pos[b + i] = sm.esc_pos[i];
+        ob.val[b + i] = sm.esc_val[i];
+      }
+    }
+  }
+}
+
+struct TailQ {
+  double q[kTailLevels];
+};
+
+struct RecTailSmem {
+  double X[kTailMax];      // the level's coefficients on its fine grid
+  double Y[kTailCoarse];   // coarse grid
+  double A[kTailMax];      // restriction along x
+  double B[kTailCoarse];   // restriction along y
+  double Gp[kTailCoarse];  // the previous level's values (the coarse grid's)
+  double tab[kTailTab];
+  LevelGeom geo[kTailLevels];
+};
+
+// Recomposition of level 0 and levels 1..top: out receives level top's grid.
+// Coefficients of levels <= coarse_top come from `coarse` (FP64), the others
+// from src.
+template <typename Tout>
+__global__ __launch_bounds__(kTailThreads) void k_rec_tail(
+    const CoeffSrc src, const CoeffSrc coarse, const int coarse_top, const TailQ tq,
+    const LevelGeom* __restrict__ geo, const int top, const TailTabArgs tt,
+    Tout* __restrict__ out) {
+  __shared__ RecTailSmem sm;
+  const int tid = threadIdx.x;
+  auto coef = [&](int l, uint32_t pos) -> double {
+    const CoeffSrc& s = l <= coarse_top ? coarse : src;
+    if (s.raw) return s.raw[pos];
+    return dequant(s, s.sym[pos], pos, tq.q[l]);
+  };
+  {
+    // level 0 (as k_rec_level0), with the tables and geometry
+    const int n0 = (int)(geo[1].nc[0] * geo[1].nc[1] * geo[1].nc[2]);
+    for (int i0 = tid, first = 1; i0 < n0 || first; i0 += 8 * kTailThreads, first = 0) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = coef(0, (uint32_t)min(i0 + u * kTailThreads, n0 - 1));
+      if (first) tail_fetch(tt, sm.tab, geo, top, sm.geo);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u * kTailThreads < n0) sm.Gp[i0 + u * kTailThreads] = v[u];
+    }
+  }
+  __syncthreads();
+  for (int l = 1; l <= top; ++l) {
+    const LevelGeom& g = sm.geo[l];
+    const TailAxis ax[3] = {tail_axis(sm.tab, tt, g, l, 0), tail_axis(sm.tab, tt, g, l, 1),
+                            tail_axis(sm.tab, tt, g, l, 2)};
+    const uint32_t nf0 = (uint32_t)g.nf[0], nf1 = (uint32_t)g.nf[1], nf2 = (uint32_t)g.nf[2];
+    const uint32_t nc0 = (uint32_t)g.nc[0], nc1 = (uint32_t)g.nc[1], nc2 = (uint32_t)g.nc[2];
+    const uint32_t e1c = nc1, e1n = nf1 - nc1, e2c = nc2, e2n = nf2 - nc2;
+    const uint32_t lvl = (uint32_t)g.level_off;
+    const int m0 = g.bit[0] >= 0 ? 1 << g.bit[0] : 0, m1 = g.bit[1] >= 0 ? 1 << g.bit[1] : 0,
+              m2 = g.bit[2] >= 0 ? 1 << g.bit[2] : 0;
+    uint32_t so[8];
+    subband_offsets(g, so);
+    const uint32_t nfine = nf0 * nf1 * nf2, ncell = nc0 * nc1 * nc2;
+    auto fidx = [&](uint32_t i0, uint32_t i1, uint32_t i2) { return (i0 * nf1 + i1) * nf2 + i2; };
+    // 1. the coefficients on the fine grid (zero at the coarse nodes)
+    for (uint32_t i = tid; i < nfine; i += kTailThreads) sm.X[i] = 0.0;
+    __syncthreads();
+    for (uint32_t e = tid; e < ncell; e += kTailThreads) {
+      const uint32_t J2 = e % nc2, rest = e / nc2, J1 = rest % nc1, J0 = rest / nc1;
+      const bool h0 = 2 * J0 + 1 < nf0 - 1, h1 = 2 * J1 + 1 < nf1 - 1, h2 = 2 * J2 + 1 < nf2 - 1;
+      const uint32_t P0 = cpos32(J0, nf0), P1 = cpos32(J1, nf1), P2 = cpos32(J2, nf2);
+      const uint32_t bcc = (J0 * e1c + J1) * e2c + J2, bcn = (J0 * e1c + J1) * e2n + J2;
+      const uint32_t bnc = (J0 * e1n + J1) * e2c + J2, bnn = (J0 * e1n + J1) * e2n + J2;
+      double v[8];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        const bool nx = k & 1, ny = k & 2, nz = k & 4;
+        const bool ok = (!nx || h2) && (!ny || h1) && (!nz || h0);
+        const int m = (nz ? m0 : 0) | (ny ? m1 : 0) | (nx ? m2 : 0);
+        const uint32_t bse = ny ? (nx ? bnn : bnc) : (nx ? bcn : bcc);
+        v[k] = ok ? coef(l, lvl + sel8(so, m) + bse) : 0.0;
+      }
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        const bool nx = k & 1, ny = k & 2, nz = k & 4;
+        if ((!nx || h2) && (!ny || h1) && (!nz || h0))
+          sm.X[fidx(P0 + (nz ? 1 : 0), P1 + (ny ? 1 : 0), P2 + (nx ? 1 : 0))] = v[k];
+      }
+    }
+    __syncthreads();
+    // 2. restriction, solves, and sub - x with the previous level's values
+    tail_restrict(sm.X, sm.A, sm.B, sm.Y, g, ax[0].W, ax[1].W, ax[2].W);
+    tail_solve(sm.Y, g, ax);
+    for (uint32_t i = tid; i < ncell; i += kTailThreads) sm.Y[i] = sm.Gp[i] - sm.Y[i];
+    __syncthreads();
+    // 3. the level's values (the forms of rec_interp_body; the coefficients
+    //    from step 1)
+    auto Gc = [&](uint32_t a, uint32_t b, uint32_t c) { return sm.Y[(a * nc1 + b) * nc2 + c]; };
+    const bool last = l == top;
+    for (uint32_t e = tid; e < ncell; e += kTailThreads) {
+      const uint32_t J2 = e % nc2, rest = e / nc2, J1 = rest % nc1, J0 = rest / nc1;
+      const bool h0 = 2 * J0 + 1 < nf0 - 1, h1 = 2 * J1 + 1 < nf1 - 1, h2 = 2 * J2 + 1 < nf2 - 1;
+      const uint32_t P0 = cpos32(J0, nf0), P1 = cpos32(J1, nf1), P2 = cpos32(J2, nf2);
+      const uint32_t r0 = P0 + (h0 ? 1 : 0), r1 = P1 + (h1 ? 1 : 0), r2 = P2 + (h2 ? 1 : 0);
+      const double wz0 = ax[0].wl[r0], wz1 = ax[0].wr[r0], wy0 = ax[1].wl[r1], wy1 = ax[1].wr[r1];
+      const double wx0 = ax[2].wl[r2], wx1 = ax[2].wr[r2];
+      const uint32_t a1 = h0 ? J0 + 1 : J0, b1 = h1 ? J1 + 1 : J1, c1 = h2 ? J2 + 1 : J2;
+      const double c000 = Gc(J0, J1, J2), c001 = Gc(J0, J1, c1), c010 = Gc(J0, b1, J2),
+                   c011 = Gc(J0, b1, c1), c100 = Gc(a1, J1, J2), c101 = Gc(a1, J1, c1),
+                   c110 = Gc(a1, b1, J2), c111 = Gc(a1, b1, c1);
+      const double ix00 = lin2(wx0, c000, wx1, c001), ix01 = lin2(wx0, c010, wx1, c011);
+      const double ix10 = lin2(wx0, c100, wx1, c101), ix11 = lin2(wx0, c110, wx1, c111);
+      auto cf = [&](uint32_t i0, uint32_t i1, uint32_t i2) { return sm.X[fidx(i0, i1, i2)]; };
+      auto put = [&](uint32_t i0, uint32_t i1, uint32_t i2, double v) {
+        const uint32_t o = fidx(i0, i1, i2);
+        if (last) out[o] = (Tout)v;
+        else sm.Gp[o] = v;
+      };
+      put(P0, P1, P2, c000);
+      if (h2) put(P0, P1, P2 + 1, ix00 + cf(P0, P1, P2 + 1));
+      if (h1) put(P0, P1 + 1, P2, (lin2(wy0, c000, wy1, c010)) + cf(P0, P1 + 1, P2));
+      if (h1 && h2) put(P0, P1 + 1, P2 + 1, (lin2(wy0, ix00, wy1, ix01)) + cf(P0, P1 + 1, P2 + 1));
+      if (h0) put(P0 + 1, P1, P2, (lin2(wz0, c000, wz1, c100)) + cf(P0 + 1, P1, P2));
+      if (h0 && h2) put(P0 + 1, P1, P2 + 1, (lin2(wz0, ix00, wz1, ix10)) + cf(P0 + 1, P1, P2 + 1));
+      if (h0 && h1)
+        put(P0 + 1, P1 + 1, P2,
+            (lin2(wz0, lin2(wy0, c000, wy1, c010), wz1, lin2(wy0, c100, wy1, c110))) +
+                cf(P0 + 1, P1 + 1, P2));
+      if (h0 && h1 && h2)
+        put(P0 + 1, P1 + 1, P2 + 1,
+            (lin2(wz0, lin2(wy0, ix00, wy1, ix01), wz1, lin2(wy0, ix10, wy1, ix11))) +
+                cf(P0 + 1, P1 + 1, P2 + 1));
+    }
+    __syncthreads();
+  }
 }
 
 template <typename Tin, bool QUANT>
@@ -2872,6 +3278,52 @@ void launch_dequant_prefix(const CoeffSrc& src, int64_t m, const LevelBins& lb, 
     hipLaunchKernelGGL(k_dequant_escapes, dim3(bo), dim3(256), 0, s, src.opos, src.oval,
                        src.n_out, m, lb, raw);
   }
+}
+
+bool tail_level_fits(const LevelGeom& g) {
+  const int64_t nf = g.nf[0] * g.nf[1] * g.nf[2], nc = g.nc[0] * g.nc[1] * g.nc[2];
+  if (nf > kTailMax || nc > kTailCoarse || g.nf[0] * g.nc[1] * g.nc[2] > kTailCoarse) return false;
+  for (int k = 0; k < 3; ++k)
+    if (g.bit[k] >= 0 && g.nc[k] > kTailLine) return false;
+  return true;
+}
+size_t tail_max_table() { return kTailTab; }
+
+void launch_dec_tail(const void* G, bool g_is_f32, const LevelGeom* d_geo, int top,
+                     const TailTabArgs& tt, uint16_t* sym, double* raw, const double* rdev,
+                     const OutlierBuf& ob, unsigned* status, const unsigned* gate, hipStream_t s) {
+  if (top < 1 || top >= kTailLevels || tt.n > (uint32_t)kTailTab)
+    throw std::logic_error("launch_dec_tail: levels exceed the LDS tables");
+  const dim3 b(1), t(kTailThreads);
+  if (g_is_f32) {
+    if (sym) hipLaunchKernelGGL((k_dec_tail<float, true>), b, t, 0, s, static_cast<const float*>(G),
+                                d_geo, top, tt, sym, raw, rdev, ob, status, gate);
+    else hipLaunchKernelGGL((k_dec_tail<float, false>), b, t, 0, s, static_cast<const float*>(G),
+                            d_geo, top, tt, sym, raw, rdev, ob, status, gate);
+  } else {
+    if (sym) hipLaunchKernelGGL((k_dec_tail<double, true>), b, t, 0, s,
+                                static_cast<const double*>(G), d_geo, top, tt, sym, raw, rdev, ob,
+                                status, gate);
+    else hipLaunchKernelGGL((k_dec_tail<double, false>), b, t, 0, s,
+                            static_cast<const double*>(G), d_geo, top, tt, sym, raw, rdev, ob,
+                            status, gate);
+  }
+}
+
+void launch_rec_tail(const CoeffSrc& src, const CoeffSrc& coarse, int coarse_top,
+                     const double* q, const LevelGeom* d_geo, int top, const TailTabArgs& tt,
+                     void* out, bool out_f32, hipStream_t s) {
+  if (top < 1 || top >= kTailLevels || tt.n > (uint32_t)kTailTab)
+    throw std::logic_error("launch_rec_tail: levels exceed the LDS tables");
+  TailQ tq{};
+  for (int l = 0; l <= top; ++l) tq.q[l] = q[l];
+  const dim3 b(1), t(kTailThreads);
+  if (out_f32)
+    hipLaunchKernelGGL((k_rec_tail<float>), b, t, 0, s, src, coarse, coarse_top, tq, d_geo, top,
+                       tt, static_cast<float*>(out));
+  else
+    hipLaunchKernelGGL((k_rec_tail<double>), b, t, 0, s, src, coarse, coarse_top, tq, d_geo, top,
+                       tt, static_cast<double*>(out));
 }
 
 void launch_rec_level0(const CoeffSrc& src, int64_t m0, double q, void* out, bool out_f32,
