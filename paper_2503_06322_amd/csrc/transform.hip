@@ -2291,7 +2291,6 @@ constexpr int kTailCoarse = 2464;  // coarse points (and nf0 nc1 nc2) of that le
 constexpr int kTailLine = 128;     // longest active coarse line (one thread per line)
 constexpr int kTailTab = 2048;     // doubles of the table range
 constexpr int kTailThreads = 512;
-constexpr int kTailEsc = 1024;     // escaped values staged in LDS (the rest: direct)
 
 // Pointers into the LDS table copy for one level and axis.
 struct TailAxis {
@@ -2394,15 +2393,15 @@ struct DecTailSmem {
   double A[kTailMax];     // restriction along x
   double tab[kTailTab];
   LevelGeom geo[kTailLevels];
-  uint32_t esc_pos[kTailEsc];
-  int64_t esc_val[kTailEsc];
+  double r[kTailLevels];  // reciprocal bins
   unsigned n_esc;
-  unsigned long long esc_base;
 };
 
 // Decomposition of levels top..1 and level 0: G holds level top's grid.
-// Escaped values are staged in LDS (one reservation of outlier records for
-// the whole launch); beyond kTailEsc they take emit_q's direct path.
+// The launch is the only writer of the outlier records while it runs (the
+// compression's kernels run in stream order), so its escaped values take
+// the records after the count it finds, numbered by an LDS counter, and the
+// count is advanced once at the end.
 template <typename Tin, bool QUANT>
 __global__ __launch_bounds__(kTailThreads) void k_dec_tail(
     const Tin* __restrict__ G, const LevelGeom* __restrict__ geo, const int top,
@@ -2413,6 +2412,9 @@ __global__ __launch_bounds__(kTailThreads) void k_dec_tail(
   __shared__ DecTailSmem sm;
   const int tid = threadIdx.x;
   if (tid == 0) sm.n_esc = 0;
+  if (QUANT && tid <= top) sm.r[tid] = rdev[tid];
+  const unsigned long long ebase =
+      QUANT ? __hip_atomic_load(ob.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
   {
     // the grid's first loads in flight across the table copy
     const int n = (int)(geo[top].nf[0] * geo[top].nf[1] * geo[top].nf[2]);
@@ -2427,37 +2429,51 @@ __global__ __launch_bounds__(kTailThreads) void k_dec_tail(
     }
   }
   __syncthreads();
-  auto emit = [&](uint32_t pos, double c, double r) {
+  // Quantises up to seven values of a lane (emit_q's symbol and escape); the
+  // wavefront reserves its escapes' records with one LDS add.
+  auto emit_cell = [&](const uint32_t (&pos)[8], const double (&v)[8], const bool (&ok)[8],
+                       double r) {
     if (!QUANT) {
-      raw[pos] = c;
+#pragma unroll
+      for (int k = 1; k < 8; ++k)
+        if (ok[k]) raw[pos[k]] = v[k];
       return;
     }
-    // the symbol and escape of emit_q; the escape's record staged in LDS
-    const double t = rint(c * r);
-    const bool esc = !(fabs(t) < 32768.0);
-    sym[pos] = (uint16_t)(int)((esc ? -32768.0 : t) + 32768.0);
-    const uint64_t m = __ballot(esc);
-    if (m == 0) return;
-    if (esc) {
-      int64_t k = 0;
-      if (fabs(t) < 4611686018427387904.0) k = (int64_t)t;
+    double t[8];
+    bool esc[8];
+    unsigned ne = 0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      t[k] = rint(v[k] * r);
+      esc[k] = ok[k] && !(fabs(t[k]) < 32768.0);
+      if (ok[k]) sym[pos[k]] = (uint16_t)(int)((esc[k] ? -32768.0 : t[k]) + 32768.0);
+      ne += esc[k] ? 1u : 0u;
+    }
+    if (__ballot(ne != 0) == 0) return;
+    // exclusive prefix of ne (< 8) over the lanes, from its three bits
+    const uint64_t lt = (1ull << __lane_id()) - 1;
+    unsigned excl = 0, tot = 0;
+#pragma unroll
+    for (int bit = 0; bit < 3; ++bit) {
+      const uint64_t bm = __ballot((ne >> bit) & 1u);
+      excl += (unsigned)__popcll(bm & lt) << bit;
+      tot += (unsigned)__popcll(bm) << bit;
+    }
+    unsigned base = 0;
+    if (__lane_id() == 0) base = atomicAdd(&sm.n_esc, tot);
+    base = (unsigned)__shfl((int)base, 0, 64);
+    unsigned long long j = ebase + base + excl;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      if (!esc[k]) continue;
+      int64_t kv = 0;
+      if (fabs(t[k]) < 4611686018427387904.0) kv = (int64_t)t[k];
       else atomicOr(status, ST_RANGE);
-      const int lane = (int)__lane_id();
-      const int leader = __ffsll((unsigned long long)m) - 1;
-      unsigned base = 0;
-      if (lane == leader) base = atomicAdd(&sm.n_esc, (unsigned)__popcll(m));
-      base = (unsigned)__shfl((int)base, leader, 64);
-      const unsigned i = base + (unsigned)__popcll(m & ((1ull << lane) - 1));
-      if (i < (unsigned)kTailEsc) {
-        sm.esc_pos[i] = pos;
-        sm.esc_val[i] = k;
-      } else {
-        const unsigned long long j = atomicAdd(ob.count, 1ull);
-        if (j < ob.cap) {
-          ob.pos[j] = pos;
-          ob.val[j] = k;
-        }
+      if (j < ob.cap) {
+        ob.pos[j] = pos[k];
+        ob.val[j] = kv;
       }
+      ++j;
     }
   };
   double* F = sm.X;  // fine grid of the level
@@ -2466,7 +2482,7 @@ __global__ __launch_bounds__(kTailThreads) void k_dec_tail(
     const LevelGeom& g = sm.geo[l];
     const TailAxis ax[3] = {tail_axis(sm.tab, tt, g, l, 0), tail_axis(sm.tab, tt, g, l, 1),
                             tail_axis(sm.tab, tt, g, l, 2)};
-    const double r = QUANT ? rdev[l] : 0.0;
+    const double r = QUANT ? sm.r[l] : 0.0;
     const uint32_t nf0 = (uint32_t)g.nf[0], nf1 = (uint32_t)g.nf[1], nf2 = (uint32_t)g.nf[2];
     const uint32_t nc0 = (uint32_t)g.nc[0], nc1 = (uint32_t)g.nc[1], nc2 = (uint32_t)g.nc[2];
     const uint32_t e1c = nc1, e1n = nf1 - nc1, e2c = nc2, e2n = nf2 - nc2;
@@ -2476,12 +2492,14 @@ __global__ __launch_bounds__(kTailThreads) void k_dec_tail(
     uint32_t so[8];
     subband_offsets(g, so);
     auto T = [&](uint32_t z, uint32_t y, uint32_t x) { return F[(z * nf1 + y) * nf2 + x]; };
-    // cells: the new nodes' coefficients (the forms of lerp_cells)
+    // cells: the new nodes' coefficients (the forms of lerp_cells); every
+    // lane of a wavefront takes part in each round (for the reservation)
     const uint32_t ncell = nc0 * nc1 * nc2;
-    for (uint32_t e = tid; e < ncell; e += kTailThreads) {
+    for (uint32_t e0 = 0; e0 < ncell; e0 += kTailThreads) {
+      const uint32_t e = min(e0 + tid, ncell - 1);
+      const bool live = e0 + tid < ncell;
       const uint32_t J2 = e % nc2, rest = e / nc2, J1 = rest % nc1, J0 = rest / nc1;
       const bool h0 = 2 * J0 + 1 < nf0 - 1, h1 = 2 * J1 + 1 < nf1 - 1, h2 = 2 * J2 + 1 < nf2 - 1;
-      if (!(h0 || h1 || h2)) continue;
       const uint32_t p0 = cpos32(J0, nf0), p1 = cpos32(J1, nf1), p2 = cpos32(J2, nf2);
       const uint32_t s0 = h0 ? p0 + 2 : p0, s1 = h1 ? p1 + 2 : p1, s2 = h2 ? p2 + 2 : p2;
       const uint32_t q0 = h0 ? p0 + 1 : p0, q1 = h1 ? p1 + 1 : p1, q2 = h2 ? p2 + 1 : p2;
@@ -2495,21 +2513,36 @@ __global__ __launch_bounds__(kTailThreads) void k_dec_tail(
       const double ix10 = lin2(wx0, c100, wx1, c101), ix11 = lin2(wx0, c110, wx1, c111);
       const uint32_t base_cc = (J0 * e1c + J1) * e2c + J2, base_cn = (J0 * e1c + J1) * e2n + J2;
       const uint32_t base_nc = (J0 * e1n + J1) * e2c + J2, base_nn = (J0 * e1n + J1) * e2n + J2;
-      if (h2) emit(lvl + sel8(so, m2) + base_cn, T(p0, p1, q2) - ix00, r);
-      if (h1) emit(lvl + sel8(so, m1) + base_nc, T(p0, q1, p2) - (lin2(wy0, c000, wy1, c010)), r);
-      if (h1 && h2)
-        emit(lvl + sel8(so, m1 | m2) + base_nn, T(p0, q1, q2) - (lin2(wy0, ix00, wy1, ix01)), r);
-      if (h0) emit(lvl + sel8(so, m0) + base_cc, T(q0, p1, p2) - (lin2(wz0, c000, wz1, c100)), r);
-      if (h0 && h2)
-        emit(lvl + sel8(so, m0 | m2) + base_cn, T(q0, p1, q2) - (lin2(wz0, ix00, wz1, ix10)), r);
-      if (h0 && h1)
-        emit(lvl + sel8(so, m0 | m1) + base_nc,
-             T(q0, q1, p2) - (lin2(wz0, lin2(wy0, c000, wy1, c010), wz1, lin2(wy0, c100, wy1, c110))),
-             r);
-      if (h0 && h1 && h2)
-        emit(lvl + sel8(so, m0 | m1 | m2) + base_nn,
-             T(q0, q1, q2) - (lin2(wz0, lin2(wy0, ix00, wy1, ix01), wz1, lin2(wy0, ix10, wy1, ix11))),
-             r);
+      uint32_t pos[8];
+      double v[8];
+      bool ok[8];
+      pos[0] = 0;
+      v[0] = 0.0;
+      ok[0] = false;
+      pos[1] = lvl + sel8(so, m2) + base_cn;
+      v[1] = T(p0, p1, q2) - ix00;
+      ok[1] = live && h2;
+      pos[2] = lvl + sel8(so, m1) + base_nc;
+      v[2] = T(p0, q1, p2) - (lin2(wy0, c000, wy1, c010));
+      ok[2] = live && h1;
+      pos[3] = lvl + sel8(so, m1 | m2) + base_nn;
+      v[3] = T(p0, q1, q2) - (lin2(wy0, ix00, wy1, ix01));
+      ok[3] = live && h1 && h2;
+      pos[4] = lvl + sel8(so, m0) + base_cc;
+      v[4] = T(q0, p1, p2) - (lin2(wz0, c000, wz1, c100));
+      ok[4] = live && h0;
+      pos[5] = lvl + sel8(so, m0 | m2) + base_cn;
+      v[5] = T(q0, p1, q2) - (lin2(wz0, ix00, wz1, ix10));
+      ok[5] = live && h0 && h2;
+      pos[6] = lvl + sel8(so, m0 | m1) + base_nc;
+      v[6] = T(q0, q1, p2) -
+             (lin2(wz0, lin2(wy0, c000, wy1, c010), wz1, lin2(wy0, c100, wy1, c110)));
+      ok[6] = live && h0 && h1;
+      pos[7] = lvl + sel8(so, m0 | m1 | m2) + base_nn;
+      v[7] = T(q0, q1, q2) -
+             (lin2(wz0, lin2(wy0, ix00, wy1, ix01), wz1, lin2(wy0, ix10, wy1, ix11)));
+      ok[7] = live && h0 && h1 && h2;
+      emit_cell(pos, v, ok, r);
     }
     // (the restriction's first pass only reads F, as the cells do)
     tail_restrict(F, sm.A, F, C, g, ax[0].W, ax[1].W, ax[2].W);
@@ -2521,21 +2554,17 @@ __global__ __launch_bounds__(kTailThreads) void k_dec_tail(
   // level 0: the coarsest grid's values at stream positions 0..
   const LevelGeom& g1 = sm.geo[1];
   const int n0 = (int)(g1.nc[0] * g1.nc[1] * g1.nc[2]);
-  const double r0 = QUANT ? rdev[0] : 0.0;
-  for (int i = tid; i < n0; i += kTailThreads) emit((uint32_t)i, F[i], r0);
+  const double r0 = QUANT ? sm.r[0] : 0.0;
+  for (int i0 = 0; i0 < n0; i0 += kTailThreads) {
+    const int i = min(i0 + tid, n0 - 1);
+    uint32_t pos[8] = {0, (uint32_t)i, 0, 0, 0, 0, 0, 0};
+    double v[8] = {0.0, F[i], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool ok[8] = {false, i0 + tid < n0, false, false, false, false, false, false};
+    emit_cell(pos, v, ok, r0);
+  }
   if (QUANT) {
-    // the staged records: one reservation, then the copies
     __syncthreads();
-    const unsigned ne = min(sm.n_esc, (unsigned)kTailEsc);
-    if (tid == 0) sm.esc_base = ne ? atomicAdd(ob.count, (unsigned long long)ne) : 0ull;
-    __syncthreads();
-    const unsigned long long b = sm.esc_base;
-    for (unsigned i = tid; i < ne; i += kTailThreads) {
-      if (b + i < ob.cap) {
-        ob.pos[b + i] = sm.esc_pos[i];
-        ob.val[b + i] = sm.esc_val[i];
-      }
-    }
+    if (tid == 0 && sm.n_esc) atomicAdd(ob.count, (unsigned long long)sm.n_esc);
   }
 }
 
