@@ -430,10 +430,134 @@ __device__ unsigned compact_keys(const unsigned* __restrict__ hist, const Codebo
   return total;
 }
 
+// Canonical codes (RFC 1951 construction): count per length, first code per
+// length, then the rank of each symbol among equal lengths in ascending
+// symbol order.  A wavefront takes a contiguous run [i0, i1) of the symbols
+// in tiles of 64.  Its running count of each length d sits in lane d; a tile
+// is taken one distinct length at a time (the lengths of neighbouring
+// symbols mostly agree, so a tile holds few): the first remaining lane names
+// the length, a ballot finds its peers, their ranks are the count read from
+// lane d plus their order in the tile, and lane d advances.
+
+// Lane d: the run's symbols of length d.
+__device__ unsigned wave_len_counts(const uint8_t* lenAsc, unsigned i0, unsigned i1) {
+  constexpr int B = 8;
+  const int lane = threadIdx.x & 63;
+  unsigned cnt = 0;
+  for (unsigned t = i0; t < i1; t += 64 * B) {
+    unsigned dl[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) dl[u] = lenAsc[min(t + u * 64 + lane, i1 - 1)];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      uint64_t rem = __ballot(t + u * 64 + lane < i1);
+      while (rem) {
+        const int ld = __ffsll((unsigned long long)rem) - 1;
+        const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dl[u], ld);
+        const uint64_t m = __ballot(dl[u] == d) & rem;
+        if (lane == (int)d) cnt += (unsigned)__popcll(m);
+        rem &= ~m;
+      }
+    }
+  }
+  return cnt;
+}
+
+// The run's codes: lane d of cnt holds the symbols of length d before the
+// run, lane d of fst the first code of length d.  Writes code[], the packed
+// words s.pk and the codebook section (n symbols, then their lengths).
+__device__ void wave_len_ranks(const uint8_t* lenAsc, unsigned i0, unsigned i1, unsigned cnt,
+                               const unsigned fst, const CodebookScratch& s,
+                               uint32_t* __restrict__ code, uint8_t* __restrict__ cb_out,
+                               const unsigned n) {
+  constexpr int B = 8;
+  const int lane = threadIdx.x & 63;
+  uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
+  for (unsigned t = i0; t < i1; t += 64 * B) {
+    unsigned dl[B], sy[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const unsigned i = min(t + u * 64 + lane, i1 - 1);
+      dl[u] = lenAsc[i];
+      sy[u] = s.symAsc[i];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const unsigned i = t + u * 64 + lane;
+      const bool valid = i < i1;
+      uint64_t rem = __ballot(valid);
+      unsigned rank = 0, first = 0;
+      while (rem) {
+        const int ld = __ffsll((unsigned long long)rem) - 1;
+        const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dl[u], ld);
+        const uint64_t m = __ballot(dl[u] == d) & rem;
+        const unsigned base = (unsigned)__builtin_amdgcn_readlane((int)cnt, (int)d);
+        const unsigned fd = (unsigned)__builtin_amdgcn_readlane((int)fst, (int)d);
+        if ((m >> lane) & 1u) {
+          rank = base + (unsigned)__popcll(m & lanemask_lt());
+          first = fd;
+        }
+        if (lane == (int)d) cnt += (unsigned)__popcll(m);
+        rem &= ~m;
+      }
+      if (valid) {
+        const unsigned d = dl[u];
+        code[sy[u]] = first + rank;
+        s.pk[sy[u]] = (rank << 6) | d;
+        cs[i] = (uint16_t)sy[u];
+        cb_out[2 * n + i] = (uint8_t)d;
+      }
+    }
+  }
+}
+
+// First code of each length from the counts per length (tot[l]); with
+// write also stored behind the packed words, with lay->max_len.
+__device__ __forceinline__ void first_codes(const unsigned* tot, unsigned* first, uint32_t* pk,
+                                            Layout* lay, bool write) {
+  unsigned c = 0, ml = 0;
+  for (int l = 1; l <= kMaxCodeLen; ++l) {
+    const unsigned cntl = tot[l];
+    if (cntl) ml = l;
+    first[l] = c;
+    if (write) pk[kDict + l] = c;  // first code of each length, for the encoder
+    c = (c + cntl) << 1;
+  }
+  if (write) lay->max_len = ml;
+}
+
+// The canonical codes of n symbols in one block of 1024 threads (lengths in
+// symbol order in lenAsc): a counting pass, the scan of the counts over the
+// wavefronts (which also gives the counts per length), the ranking pass.
+__device__ void canonical_codes(const unsigned n, const uint8_t* lenAsc, const CodebookScratch& s,
+                                uint32_t* __restrict__ code, uint8_t* __restrict__ cb_out,
+                                Layout* __restrict__ lay, CbSmem& sm) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const unsigned run = ((n + 1023) / 1024) * 64;
+  const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
+  const unsigned cnt = wave_len_counts(lenAsc, i0, i1);
+  if (lane < 34) sm.wl[wave][lane] = cnt;
+  __syncthreads();
+  if (tid < 34) {
+    unsigned acc = 0;
+    for (int w = 0; w < 16; ++w) {
+      const unsigned c = sm.wl[w][tid];
+      sm.wl[w][tid] = acc;
+      acc += c;
+    }
+    sm.lcount[tid] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) first_codes(sm.lcount, sm.lfirst, s.pk, lay, true);
+  __syncthreads();
+  wave_len_ranks(lenAsc, i0, i1, lane < 34 ? sm.wl[wave][lane] : 0u,
+                 lane < 34 ? sm.lfirst[lane] : 0u, s, code, cb_out, n);
+}
+
 // PRESORTED: the leaf sort of the first round was done by the multi-block
 // sort (k_cbs_count / k_cbs_pass), which also wrote the non-zero keys in
 // symbol order; otherwise the block compacts and sorts them itself.
-template <bool PRESORTED>
+template <bool PRESORTED, bool CANON>
 __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
                                               const CodebookScratch& s,
                                               uint32_t* __restrict__ code,
@@ -441,12 +565,8 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
                                               uint8_t* __restrict__ cb_out,
                                               Layout* __restrict__ lay) {
   __shared__ CbSmem sm;
-  __shared__ CbBig big;
+  __shared__ __align__(16) CbBig big;
   const int tid = threadIdx.x;
-  for (unsigned i = tid; i < kDict; i += 1024) {
-    clen[i] = 0;
-    code[i] = 0;
-  }
   unsigned n, pre_passes = 0;
   if (PRESORTED) {
     // item count: every non-zero bin is counted once in the first pass's
@@ -465,6 +585,8 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
   __syncthreads();
 
   if (n == 0) {
+    uint4* clen4 = reinterpret_cast<uint4*>(clen);
+    for (unsigned i = tid; i < kDict / 16; i += 1024) clen4[i] = make_uint4(0u, 0u, 0u, 0u);
     if (tid == 0) {
       lay->n_codes = 0;
       lay->max_len = 0;
@@ -472,21 +594,12 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
     return;
   }
   if (n == 1) {
-    if (tid == 0) {
-      const unsigned sy = s.symAsc[0];
-      clen[sy] = 1;
-      code[sy] = 0;
-      s.pk[sy] = 1u;  // rank 0, one bit
-      s.pk[kDict + 1] = 0u;  // first code of length 1
-      reinterpret_cast<uint16_t*>(cb_out)[0] = (uint16_t)sy;
-      cb_out[2] = 1;
-      lay->n_codes = 1;
-      lay->max_len = 1;
-    }
-    return;
+    // one symbol: a one-bit code
+    if (tid == 0) reinterpret_cast<uint8_t*>(&big)[kDict] = 1;
+    __syncthreads();
   }
   const uint32_t root = n - 2;
-  for (int flatten = 0;; ++flatten) {
+  for (int flatten = 0; n >= 2; ++flatten) {
     if (flatten > 40) {  // 33 halvings bring every frequency to 1
       if (tid == 0) lay->status |= ST_INTERNAL;
       return;
@@ -852,109 +965,37 @@ __device__ __forceinline__ void codebook_body(const unsigned* __restrict__ hist,
     for (unsigned i = tid; i < n; i += 1024) s.freqAsc[i] = (s.freqAsc[i] + 1u) >> 1;
     __syncthreads();
   }
-  // 6. canonical codes: count per length, first code per length, then the
-  //    rank of each symbol among equal lengths in ascending symbol order.
-  //    Wavefront w takes a contiguous run of the symbols in tiles of 64.  Its
-  //    running count of each length d sits in lane d; a tile is taken one
-  //    distinct length at a time (the lengths of neighbouring symbols mostly
-  //    agree, so a tile holds few): the first remaining lane names the
-  //    length, a ballot finds its peers, their ranks are the count read from
-  //    lane d plus their order in the tile, and lane d advances.  A counting
-  //    pass, the scan of the counts over the wavefronts (which also gives the
-  //    counts per length), then the ranking pass with eight tiles of loads in
-  //    flight.
-  const uint8_t* lenAsc = reinterpret_cast<const uint8_t*>(&big) + kDict;
+  // 5b. the code length of every symbol (zero for absent ones) through an
+  //     LDS table over the depth bytes (dead now): cleared, filled from the
+  //     leaves, then stored whole with 16-byte stores
   {
-    constexpr int B = 8;
-    const int wave = tid >> 6, lane = tid & 63;
-    const unsigned run = ((n + 1023) / 1024) * 64;
-    const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
-    unsigned cnt = 0;  // lane d: symbols of length d so far
-    for (unsigned t = i0; t < i1; t += 64 * B) {
-      unsigned dl[B];
-#pragma unroll
-      for (int u = 0; u < B; ++u) dl[u] = lenAsc[min(t + u * 64 + lane, i1 - 1)];
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        uint64_t rem = __ballot(t + u * 64 + lane < i1);
-        while (rem) {
-          const int ld = __ffsll((unsigned long long)rem) - 1;
-          const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dl[u], ld);
-          const uint64_t m = __ballot(dl[u] == d) & rem;
-          if (lane == (int)d) cnt += (unsigned)__popcll(m);
-          rem &= ~m;
-        }
-      }
-    }
-    if (lane < 34) sm.wl[wave][lane] = cnt;
+    uint8_t* lenAsc = reinterpret_cast<uint8_t*>(&big) + kDict;
+    uint4* tab4 = reinterpret_cast<uint4*>(&big);
+    for (unsigned i = tid; i < kDict / 16; i += 1024) tab4[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
-    if (tid < 34) {
-      unsigned acc = 0;
-      for (int w = 0; w < 16; ++w) {
-        const unsigned c = sm.wl[w][tid];
-        sm.wl[w][tid] = acc;
-        acc += c;
-      }
-      sm.lcount[tid] = acc;
+    uint8_t* tab = reinterpret_cast<uint8_t*>(&big);
+    for (unsigned i0 = tid; i0 < n; i0 += 8192) {
+      unsigned sy[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sy[u] = s.symAsc[min(i0 + 1024u * u, n - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + 1024u * u < n) tab[sy[u]] = lenAsc[i0 + 1024u * u];
     }
     __syncthreads();
-    if (tid == 0) {
-      unsigned c = 0, ml = 0;
-      for (int l = 1; l <= kMaxCodeLen; ++l) {
-        const unsigned cntl = sm.lcount[l];
-        if (cntl) ml = l;
-        sm.lfirst[l] = c;
-        s.pk[kDict + l] = c;  // first code of each length, for the encoder
-        c = (c + cntl) << 1;
-      }
-      lay->max_len = ml;
-    }
-    __syncthreads();
-    // 7. per symbol: code, length, the packed (rank, length) word of the
-    //    encoder, and the codebook section (symbols ascending, then their
-    //    lengths)
-    cnt = lane < 34 ? sm.wl[wave][lane] : 0u;      // earlier wavefronts' symbols
-    const unsigned fst = lane < 34 ? sm.lfirst[lane] : 0u;
-    uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
-    for (unsigned t = i0; t < i1; t += 64 * B) {
-      unsigned dl[B], sy[B];
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const unsigned i = min(t + u * 64 + lane, i1 - 1);
-        dl[u] = lenAsc[i];
-        sy[u] = s.symAsc[i];
-      }
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        const unsigned i = t + u * 64 + lane;
-        const bool valid = i < i1;
-        uint64_t rem = __ballot(valid);
-        unsigned rank = 0, first = 0;
-        while (rem) {
-          const int ld = __ffsll((unsigned long long)rem) - 1;
-          const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dl[u], ld);
-          const uint64_t m = __ballot(dl[u] == d) & rem;
-          const unsigned base = (unsigned)__builtin_amdgcn_readlane((int)cnt, (int)d);
-          const unsigned fd = (unsigned)__builtin_amdgcn_readlane((int)fst, (int)d);
-          if ((m >> lane) & 1u) {
-            rank = base + (unsigned)__popcll(m & lanemask_lt());
-            first = fd;
-          }
-          if (lane == (int)d) cnt += (unsigned)__popcll(m);
-          rem &= ~m;
-        }
-        if (valid) {
-          const unsigned d = dl[u];
-          code[sy[u]] = first + rank;
-          clen[sy[u]] = (uint8_t)d;
-          s.pk[sy[u]] = (rank << 6) | d;
-          cs[i] = (uint16_t)sy[u];
-          cb_out[2 * n + i] = (uint8_t)d;
-        }
-      }
-    }
+    uint4* clen4 = reinterpret_cast<uint4*>(clen);
+    for (unsigned i = tid; i < kDict / 16; i += 1024) clen4[i] = tab4[i];
   }
   if (tid == 0) lay->n_codes = n;
+  if (CANON) {
+    // 6-7. canonical codes in this block (lengths in LDS)
+    canonical_codes(n, reinterpret_cast<const uint8_t*>(&big) + kDict, s, code, cb_out, lay, sm);
+  } else {
+    // lengths in symbol order for the canonical pass (k_canon), as bytes
+    // over the sort keys (dead now)
+    const uint32_t* len4 = reinterpret_cast<const uint32_t*>(&big) + kDict / 4;
+    for (unsigned i = tid; i < (n + 3) / 4; i += 1024) s.keyA[i] = len4[i];
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ hist,
@@ -964,7 +1005,66 @@ __global__ __launch_bounds__(1024) void k_codebook(const unsigned* __restrict__ 
                                                     Layout* __restrict__ lay,
                                                     const unsigned* __restrict__ gate) {
   if (gate_closed(gate)) return;
-  codebook_body<true>(hist, s, code, clen, cb_out, lay);
+  codebook_body<true, false>(hist, s, code, clen, cb_out, lay);
+}
+
+// The canonical codes of the codebook k_codebook built (its lengths in
+// symbol order as bytes over s.keyA) on kCanonBlocks blocks of four
+// wavefronts, each wavefront a contiguous run of the symbols: the counts per
+// length of every run (over s.valA), then the ranks, each block scanning the
+// runs' counts before its own.
+constexpr int kCanonBlocks = 64;
+constexpr int kCanonRuns = kCanonBlocks * 4;
+
+__device__ __forceinline__ void canon_run(unsigned n, unsigned& i0, unsigned& i1) {
+  const unsigned gw = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const unsigned run = ((n + 64 * kCanonRuns - 1) / (64 * kCanonRuns)) * 64;
+  i0 = min(n, gw * run);
+  i1 = min(n, i0 + run);
+}
+
+__global__ __launch_bounds__(256) void k_canon_count(CodebookScratch s, const Layout* __restrict__ lay,
+                                                      const unsigned* __restrict__ gate) {
+  if (gate_closed(gate) || lay->status) return;
+  const unsigned n = (unsigned)lay->n_codes;
+  if (n == 0) return;
+  unsigned i0, i1;
+  canon_run(n, i0, i1);
+  const unsigned cnt = wave_len_counts(reinterpret_cast<const uint8_t*>(s.keyA), i0, i1);
+  const int lane = threadIdx.x & 63;
+  if (lane < 34) s.valA[(blockIdx.x * 4 + (threadIdx.x >> 6)) * 34 + lane] = cnt;
+}
+
+__global__ __launch_bounds__(256) void k_canon_rank(CodebookScratch s, uint32_t* __restrict__ code,
+                                                     uint8_t* __restrict__ cb_out,
+                                                     Layout* __restrict__ lay,
+                                                     const unsigned* __restrict__ gate) {
+  if (gate_closed(gate) || lay->status) return;
+  const unsigned n = (unsigned)lay->n_codes;
+  if (n == 0) return;
+  __shared__ unsigned cw[kCanonRuns * 34];
+  __shared__ unsigned off[4][34], tot[34], first[34];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < kCanonRuns * 34; i += 256) cw[i] = s.valA[i];
+  __syncthreads();
+  if (tid < 34) {
+    // counts of length tid before each of this block's runs, and in all
+    const unsigned w0 = blockIdx.x * 4;
+    unsigned acc = 0;
+#pragma unroll 16
+    for (unsigned w = 0; w < (unsigned)kCanonRuns; ++w) {
+      if (w >= w0 && w < w0 + 4) off[w - w0][tid] = acc;
+      acc += cw[w * 34 + tid];
+    }
+    tot[tid] = acc;
+  }
+  __syncthreads();
+  if (tid == 0) first_codes(tot, first, s.pk, lay, blockIdx.x == 0);
+  __syncthreads();
+  unsigned i0, i1;
+  canon_run(n, i0, i1);
+  wave_len_ranks(reinterpret_cast<const uint8_t*>(s.keyA), i0, i1, lane < 34 ? off[wave][lane] : 0u,
+                 lane < 34 ? first[lane] : 0u, s, code, cb_out, n);
 }
 
 // ------------------------------------------------- multi-block leaf sort
@@ -2418,7 +2518,7 @@ __global__ __launch_bounds__(1024) void kb_histogram(const Job* __restrict__ job
 __global__ __launch_bounds__(1024) void kb_codebook(const Job* __restrict__ jobs) {
   const Job& J = jobs[blockIdx.x];
   if (job_skipped_h(J)) return;
-  codebook_body<false>(J.hist, J.cbs, J.code, J.clen, J.out + job_cb_off(J), J.lay);
+  codebook_body<false, true>(J.hist, J.cbs, J.code, J.clen, J.out + job_cb_off(J), J.lay);
 }
 
 __global__ __launch_bounds__(256) void kb_chunk_words(const Job* __restrict__ jobs,
@@ -2559,13 +2659,21 @@ void launch_b_header(const Job* jobs, int n, hipStream_t s) {
 
 void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
                      uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
-                     hipStream_t s, const unsigned* gate) {
+                     hipStream_t s, const unsigned* gate, bool canon) {
   hipLaunchKernelGGL(k_cbs_count, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
   hipLaunchKernelGGL(k_cbs_pass<0>, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
   hipLaunchKernelGGL(k_cbs_pass<1>, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
   hipLaunchKernelGGL(k_cbs_pass<2>, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
   hipLaunchKernelGGL(k_cbs_pass<3>, dim3(kSortTiles), dim3(256), 0, s, hist, sc, gate);
   hipLaunchKernelGGL(k_codebook, dim3(1), dim3(1024), 0, s, hist, sc, code, clen,
+                     cb_out_base + cb_off, lay, gate);
+  if (canon) launch_canon(sc, code, cb_out_base, cb_off, lay, s, gate);
+}
+
+void launch_canon(const CodebookScratch& sc, uint32_t* code, uint8_t* cb_out_base,
+                  uint64_t cb_off, Layout* lay, hipStream_t s, const unsigned* gate) {
+  hipLaunchKernelGGL(k_canon_count, dim3(kCanonBlocks), dim3(256), 0, s, sc, lay, gate);
+  hipLaunchKernelGGL(k_canon_rank, dim3(kCanonBlocks), dim3(256), 0, s, sc, code,
                      cb_out_base + cb_off, lay, gate);
 }
 

@@ -182,9 +182,16 @@ constexpr uint32_t kHistWinLo = kHalf - kHistWindow / 2;
 void launch_histogram(const uint16_t* sym, int64_t n, unsigned* hist, hipStream_t s,
                       const unsigned* gate = nullptr, uint32_t win_lo = kHistWinLo,
                       uint32_t hot = 0);
+// Code lengths (clen, and lay->n_codes), then, when canon is set, the
+// canonical codes (code, the packed words with the first codes behind them,
+// the codebook section, lay->max_len); with canon false the caller runs
+// launch_canon after the lengths (the chunk-size pass needs the lengths
+// only).
 void launch_codebook(const unsigned* hist, const CodebookScratch& sc, uint32_t* code,
                      uint8_t* clen, uint8_t* cb_out_base, uint64_t cb_off, Layout* lay,
-                     hipStream_t s, const unsigned* gate = nullptr);
+                     hipStream_t s, const unsigned* gate = nullptr, bool canon = true);
+void launch_canon(const CodebookScratch& sc, uint32_t* code, uint8_t* cb_out_base,
+                  uint64_t cb_off, Layout* lay, hipStream_t s, const unsigned* gate = nullptr);
 // zc / zl (optional, C = 1024): per-chunk escape counts and per-lane escape
 // masks with in-chunk prefix counts, for launch_escape_order.
 void launch_chunk_words(const uint16_t* sym, int64_t N, int C, const uint8_t* clen,
