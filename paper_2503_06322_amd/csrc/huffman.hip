@@ -58,6 +58,9 @@ struct DecodeTables {
   // the shortest and longest length under the prefix.
   uint32_t lut[1 << kLutBits];
   uint16_t sorted[kDict];       // symbols in (length, symbol) order
+  // construction scratch: per run of the section, its counts per length and
+  // (at 34) whether it holds an invalid length or symbol
+  uint32_t runs[256 * 36];
 };
 
 size_t decode_tables_bytes() { return sizeof(DecodeTables); }
@@ -463,23 +466,22 @@ __device__ unsigned wave_len_counts(const uint8_t* lenAsc, unsigned i0, unsigned
   return cnt;
 }
 
-// The run's codes: lane d of cnt holds the symbols of length d before the
-// run, lane d of fst the first code of length d.  Writes code[], the packed
-// words s.pk and the codebook section (n symbols, then their lengths).
-__device__ void wave_len_ranks(const uint8_t* lenAsc, unsigned i0, unsigned i1, unsigned cnt,
-                               const unsigned fst, const CodebookScratch& s,
-                               uint32_t* __restrict__ code, uint8_t* __restrict__ cb_out,
-                               const unsigned n) {
+// The ranking pass over the run: lane d of cnt holds the symbols of length d
+// before the run, lane d of fst a per-length value handed on (the first code
+// of length d).  Calls out(i, symbol, d, rank among length d, fst of d) for
+// each symbol i of the run; sym_of(i) loads symbol i.
+template <typename SymFn, typename OutFn>
+__device__ void wave_rank_pass(const uint8_t* lenAsc, unsigned i0, unsigned i1, unsigned cnt,
+                               const unsigned fst, SymFn sym_of, OutFn out) {
   constexpr int B = 8;
   const int lane = threadIdx.x & 63;
-  uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
   for (unsigned t = i0; t < i1; t += 64 * B) {
     unsigned dl[B], sy[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const unsigned i = min(t + u * 64 + lane, i1 - 1);
       dl[u] = lenAsc[i];
-      sy[u] = s.symAsc[i];
+      sy[u] = sym_of(i);
     }
 #pragma unroll
     for (int u = 0; u < B; ++u) {
@@ -500,15 +502,26 @@ __device__ void wave_len_ranks(const uint8_t* lenAsc, unsigned i0, unsigned i1, 
         if (lane == (int)d) cnt += (unsigned)__popcll(m);
         rem &= ~m;
       }
-      if (valid) {
-        const unsigned d = dl[u];
-        code[sy[u]] = first + rank;
-        s.pk[sy[u]] = (rank << 6) | d;
-        cs[i] = (uint16_t)sy[u];
-        cb_out[2 * n + i] = (uint8_t)d;
-      }
+      if (valid) out(i, sy[u], dl[u], rank, first);
     }
   }
+}
+
+// The run's codes (fst: first codes): code[], the packed words s.pk and the
+// codebook section (n symbols, then their lengths).
+__device__ void wave_len_ranks(const uint8_t* lenAsc, unsigned i0, unsigned i1, unsigned cnt,
+                               const unsigned fst, const CodebookScratch& s,
+                               uint32_t* __restrict__ code, uint8_t* __restrict__ cb_out,
+                               const unsigned n) {
+  uint16_t* cs = reinterpret_cast<uint16_t*>(cb_out);
+  wave_rank_pass(
+      lenAsc, i0, i1, cnt, fst, [&](unsigned i) { return s.symAsc[i]; },
+      [&](unsigned i, unsigned sy, unsigned d, unsigned rank, unsigned first) {
+        code[sy] = first + rank;
+        s.pk[sy] = (rank << 6) | d;
+        cs[i] = (uint16_t)sy;
+        cb_out[2 * n + i] = (uint8_t)d;
+      });
 }
 
 // First code of each length from the counts per length (tot[l]); with
@@ -1023,6 +1036,42 @@ __device__ __forceinline__ void canon_run(unsigned n, unsigned& i0, unsigned& i1
   i1 = min(n, i0 + run);
 }
 
+// Per length, the counts before each of this block's four runs (off) and in
+// all runs (tot), from the runs' counts (cw, `pitch` words per run): partial
+// sums over seven groups of runs, then each length's prefix up to the block.
+// All 256 threads; ends with a barrier.
+struct RunScan {
+  unsigned part[7][34];
+  unsigned off[4][34];
+  unsigned tot[34];
+};
+__device__ void run_offsets(const unsigned* cw, int pitch, RunScan& rs) {
+  constexpr int G = (kCanonRuns + 6) / 7;
+  const int tid = threadIdx.x;
+  if (tid < 7 * 34) {
+    const int d = tid % 34, g = tid / 34;
+    unsigned acc = 0;
+    for (int w = g * G; w < min((g + 1) * G, kCanonRuns); ++w) acc += cw[w * pitch + d];
+    rs.part[g][d] = acc;
+  }
+  __syncthreads();
+  if (tid < 34) {
+    const int w0 = blockIdx.x * 4, gb = w0 / G;
+    unsigned tot = 0, pre = 0;
+    for (int g = 0; g < 7; ++g) {
+      tot += rs.part[g][tid];
+      if (g < gb) pre += rs.part[g][tid];
+    }
+    for (int w = gb * G; w < w0; ++w) pre += cw[w * pitch + tid];
+    for (int k = 0; k < 4; ++k) {
+      rs.off[k][tid] = pre;
+      pre += cw[(w0 + k) * pitch + tid];
+    }
+    rs.tot[tid] = tot;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_canon_count(CodebookScratch s, const Layout* __restrict__ lay,
                                                       const unsigned* __restrict__ gate) {
   if (gate_closed(gate) || lay->status) return;
@@ -1043,28 +1092,19 @@ __global__ __launch_bounds__(256) void k_canon_rank(CodebookScratch s, uint32_t*
   const unsigned n = (unsigned)lay->n_codes;
   if (n == 0) return;
   __shared__ unsigned cw[kCanonRuns * 34];
-  __shared__ unsigned off[4][34], tot[34], first[34];
+  __shared__ RunScan rs;
+  __shared__ unsigned first[34];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int i = tid; i < kCanonRuns * 34; i += 256) cw[i] = s.valA[i];
   __syncthreads();
-  if (tid < 34) {
-    // counts of length tid before each of this block's runs, and in all
-    const unsigned w0 = blockIdx.x * 4;
-    unsigned acc = 0;
-#pragma unroll 16
-    for (unsigned w = 0; w < (unsigned)kCanonRuns; ++w) {
-      if (w >= w0 && w < w0 + 4) off[w - w0][tid] = acc;
-      acc += cw[w * 34 + tid];
-    }
-    tot[tid] = acc;
-  }
-  __syncthreads();
-  if (tid == 0) first_codes(tot, first, s.pk, lay, blockIdx.x == 0);
+  run_offsets(cw, 34, rs);
+  if (tid == 0) first_codes(rs.tot, first, s.pk, lay, blockIdx.x == 0);
   __syncthreads();
   unsigned i0, i1;
   canon_run(n, i0, i1);
-  wave_len_ranks(reinterpret_cast<const uint8_t*>(s.keyA), i0, i1, lane < 34 ? off[wave][lane] : 0u,
-                 lane < 34 ? first[lane] : 0u, s, code, cb_out, n);
+  wave_len_ranks(reinterpret_cast<const uint8_t*>(s.keyA), i0, i1,
+                 lane < 34 ? rs.off[wave][lane] : 0u, lane < 34 ? first[lane] : 0u, s, code, cb_out,
+                 n);
 }
 
 // ------------------------------------------------- multi-block leaf sort
@@ -2073,204 +2113,103 @@ __global__ void k_huff_header(uint8_t* __restrict__ out, uint32_t C, uint64_t N,
 }
 
 // ---------------------------------------------------------------- decoding
-__global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restrict__ cb,
-                                                         uint64_t n_codes,
-                                                         DecodeTables* __restrict__ t,
-                                                         unsigned* status) {
-  __shared__ CbSmem sm;
-  __shared__ uint8_t lenL[kDict];  // code lengths of the section, in its order
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+// The decoding tables from a stream's codebook section (n symbols ascending,
+// then their code lengths) on kCanonBlocks blocks of four wavefronts, each
+// wavefront a contiguous run of the section (as the codebook's canonical
+// pass): the runs' counts per length and validity, then the per-length
+// tables, the symbols in (length, symbol) order and the prefix table.
+static_assert(kCanonRuns == 256, "the tables' run scratch holds 256 runs");
+
+__global__ __launch_bounds__(256) void k_dt_count(const uint8_t* __restrict__ cb, uint32_t n,
+                                                   DecodeTables* __restrict__ t,
+                                                   unsigned* status) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (blockIdx.x == 0) {
+    if (tid < 4) status[tid] = 0u;  // the call's status words start here (first kernel)
+    if (tid == 0) t->valid = 0;
+  }
   const uint16_t* syms = reinterpret_cast<const uint16_t*>(cb);
-  const uint8_t* lens = cb + 2 * n_codes;
-  const unsigned n = (unsigned)n_codes;
-  if (tid < 34) sm.lcount[tid] = 0;
-  if (tid < 4) status[tid] = 0u;  // the call's status words start here (first kernel)
-  if (tid == 0) {
-    sm.flag = 0;
-    t->valid = 0;
-  }
-  // lengths into LDS and symbols checked for strict increase, both read as
-  // aligned 16-byte words covering the section (all of a thread's loads in
-  // flight at once)
+  const uint8_t* lens = cb + 2 * (size_t)n;
+  unsigned i0, i1;
+  canon_run(n, i0, i1);
+  // (invalid lengths count in lanes that are never read)
+  const unsigned cnt = wave_len_counts(lens, i0, i1);
   bool bad = false;
-  {
-    // (the aligned base is formed by pointer arithmetic so that the loads
-    // stay global-memory loads)
-    const unsigned lskip = (unsigned)(reinterpret_cast<uintptr_t>(lens) & 15);
-    const uint4* lw = reinterpret_cast<const uint4*>(lens - lskip);
-    const unsigned nlw = (lskip + n + 15) / 16;
-    for (unsigned w0 = tid; w0 < nlw; w0 += 4096) {
-      uint4 v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = lw[min(w0 + 1024 * u, nlw - 1)];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const unsigned w = w0 + 1024 * u;
-        if (w >= nlw) continue;
-        const uint32_t q[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-        for (int b = 0; b < 16; ++b) {
-          const int64_t i = (int64_t)w * 16 + b - lskip;  // section index of this byte
-          if (i >= 0 && i < (int64_t)n) {
-            const unsigned l = (q[b >> 2] >> (8 * (b & 3))) & 255u;
-            const bool out_of_range = l < 1 || l > (unsigned)kMaxCodeLen;
-            bad |= out_of_range;
-            // a rejected length is stored as 0 so that the per-length counts
-            // below (which run before the rejection is acted on) index in range
-            lenL[i] = out_of_range ? (uint8_t)0 : (uint8_t)l;
-          }
-        }
-      }
-    }
-    const unsigned sskip = (unsigned)(reinterpret_cast<uintptr_t>(syms) & 15) / 2;  // even address
-    const uint4* sw = reinterpret_cast<const uint4*>(syms - sskip);
-    const unsigned nsw = (sskip + n + 7) / 8;
-    for (unsigned w0 = tid; w0 < nsw; w0 += 4096) {
-      uint4 v[4];
-      unsigned prev[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const unsigned w = min(w0 + 1024 * u, nsw - 1);
-        v[u] = sw[w];
-        // the element before this word's first one (if it is in the section)
-        const int64_t i = (int64_t)w * 8 - sskip - 1;
-        prev[u] = i >= 0 ? syms[i] : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const unsigned w = w0 + 1024 * u;
-        if (w >= nsw) continue;
-        const uint32_t q[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-        int64_t i = (int64_t)w * 8 - sskip;
-        unsigned pv = prev[u];
-#pragma unroll
-        for (int e = 0; e < 8; ++e, ++i) {
-          const unsigned y = (q[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-          if (i >= 1 && i < (int64_t)n) bad |= y <= pv;
-          pv = y;
-        }
-      }
-    }
+  for (unsigned i = i0 + lane; i < i1; i += 64) {
+    const unsigned l = lens[i];
+    bad |= l < 1 || l > (unsigned)kMaxCodeLen;
+    if (i >= 1) bad |= syms[i] <= syms[i - 1];  // symbols strictly increasing
   }
-  if (bad) sm.flag = 1;
-  // per-wave counts of each length: wavefront w takes a contiguous run of
-  // the section in tiles of 64 (the same runs rank the codes below); its
-  // count of length d sits in lane d, and a tile is taken one distinct
-  // length at a time (first remaining lane, then a ballot for its peers)
-  const unsigned run = ((n + 16 * 64 - 1) / (16 * 64)) * 64;
-  const unsigned i0 = min(n, (unsigned)wave * run), i1 = min(n, i0 + run);
-  __syncthreads();  // lengths in LDS
-  unsigned cnt = 0;
-  for (unsigned t0 = i0; t0 < i1; t0 += 64 * 8) {
-    unsigned dl[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) dl[u] = lenL[min(t0 + 64 * u + lane, i1 - 1)];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      uint64_t rem = __ballot(t0 + 64 * u + lane < i1);
-      while (rem) {
-        const int ld = __ffsll((unsigned long long)rem) - 1;
-        const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dl[u], ld);
-        const uint64_t m = __ballot(dl[u] == d) & rem;
-        if (lane == (int)d) cnt += (unsigned)__popcll(m);
-        rem &= ~m;
-      }
-    }
-  }
-  if (lane < 34) sm.wl[wave][lane] = cnt;
-  __syncthreads();
-  if (tid < 34) {
-    unsigned c = 0;
-    for (int w = 0; w < 16; ++w) c += sm.wl[w][tid];
-    sm.lcount[tid] = c;
-  }
-  __syncthreads();
+  const bool any = __ballot(bad) != 0;
+  const unsigned gw = blockIdx.x * 4 + (tid >> 6);
+  if (lane < 34) t->runs[gw * 36 + lane] = cnt;
+  if (lane == 34) t->runs[gw * 36 + 34] = any ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_dt_rank(const uint8_t* __restrict__ cb, uint32_t n,
+                                                  DecodeTables* __restrict__ t,
+                                                  unsigned* status) {
+  __shared__ unsigned cw[kCanonRuns * 36];
+  __shared__ RunScan rs;
+  __shared__ unsigned lfirst[34], lbase[34];
   __shared__ unsigned long long llim[34];
-  __shared__ unsigned lmax;
+  __shared__ unsigned lmax, flag;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < kCanonRuns * 36; i += 256) cw[i] = t->runs[i];
+  if (tid == 0) flag = 0;
+  __syncthreads();
+  // validity of the runs (one thread per run)
+  if (cw[tid * 36 + 34]) flag = 1;
+  run_offsets(cw, 36, rs);
+  const unsigned* tot = rs.tot;
   if (tid == 0) {
     unsigned c = 0, idx = 0, maxlen = 0;
     unsigned long long kraft = 0;
     for (int l = 1; l <= kMaxCodeLen; ++l) {
-      const unsigned cnt = sm.lcount[l];
-      t->first[l] = c;
-      t->count[l] = cnt;
-      t->base[l] = idx;
-      t->limit[l] = ((unsigned long long)c + cnt) << (32 - l);
+      const unsigned cnt = tot[l];
       llim[l] = ((unsigned long long)c + cnt) << (32 - l);
-      sm.lfirst[l] = c;
-      sm.lbase[l] = idx;
+      lfirst[l] = c;
+      lbase[l] = idx;
       kraft += (unsigned long long)cnt << (32 - l);
       idx += cnt;
       c = (c + cnt) << 1;
       if (cnt) maxlen = l;
     }
-    t->maxlen = maxlen;
     lmax = maxlen;
-    if (kraft > (1ull << 32) || (n >= 2 && kraft != (1ull << 32))) sm.flag = 1;
+    if (kraft > (1ull << 32) || (n >= 2 && kraft != (1ull << 32))) flag = 1;
+    if (blockIdx.x == 0 && !flag) {
+      for (int l = 1; l <= kMaxCodeLen; ++l) {
+        t->first[l] = lfirst[l];
+        t->count[l] = tot[l];
+        t->base[l] = lbase[l];
+        t->limit[l] = llim[l];
+      }
+      t->maxlen = maxlen;
+    }
   }
   __syncthreads();
-  if (sm.flag) {
-    if (tid == 0) atomicOr(status, ST_FORMAT);
+  if (flag) {
+    if (blockIdx.x == 0 && tid == 0) atomicOr(status, ST_FORMAT);
     return;
   }
-  __shared__ unsigned lfirst[34], lbase[34];
-  if (tid < 34) {
-    lfirst[tid] = sm.lfirst[tid];
-    lbase[tid] = sm.lbase[tid];
+  // symbols in (length, symbol) order: slot = base of the length + rank
+  {
+    const uint16_t* syms = reinterpret_cast<const uint16_t*>(cb);
+    unsigned i0, i1;
+    canon_run(n, i0, i1);
+    wave_rank_pass(
+        cb + 2 * (size_t)n, i0, i1, lane < 34 ? rs.off[wave][lane] : 0u,
+        lane < 34 ? lbase[lane] : 0u, [&](unsigned i) { return (unsigned)syms[i]; },
+        [&](unsigned, unsigned sy, unsigned, unsigned rank, unsigned base) {
+          t->sorted[base + rank] = (uint16_t)sy;
+        });
   }
-  // symbols in (length, symbol) order: the stable rank of each code among
-  // the codes of its length, from the per-wave counts (scanned over the
-  // wavefronts) and a ranking pass over the same runs, whose symbol loads
-  // run eight tiles ahead of the tile being ranked.
-  if (tid < 34) {
-    unsigned acc = lbase[tid];
-    for (int w = 0; w < 16; ++w) {
-      const unsigned c = sm.wl[w][tid];
-      sm.wl[w][tid] = acc;
-      acc += c;
-    }
-  }
-  __syncthreads();
-  constexpr int PF = 8;
-  cnt = lane < 34 ? sm.wl[wave][lane] : 0u;  // lane d: next slot of length d
-  uint16_t cur[PF], nxt[PF];
-#pragma unroll
-  for (int u = 0; u < PF; ++u) cur[u] = i0 < i1 ? syms[min(i0 + 64 * u + lane, i1 - 1)] : 0;
-  for (unsigned g = i0; g < i1; g += 64 * PF) {
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const unsigned i = g + 64 * PF + 64 * u + lane;
-      nxt[u] = g + 64 * PF < i1 ? syms[min(i, i1 - 1)] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      // per distinct length of the tile: its codes take the next slots of
-      // the length in lane order, and lane d advances
-      const unsigned i = g + 64 * u + lane;
-      const bool valid = i < i1;
-      const unsigned dv = lenL[min(i, i1 - 1)];
-      uint64_t rem = __ballot(valid);
-      unsigned slot = 0;
-      while (rem) {
-        const int ld = __ffsll((unsigned long long)rem) - 1;
-        const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)dv, ld);
-        const uint64_t m = __ballot(dv == d) & rem;
-        const unsigned base = (unsigned)__builtin_amdgcn_readlane((int)cnt, (int)d);
-        if ((m >> lane) & 1u) slot = base + (unsigned)__popcll(m & lanemask_lt());
-        if (lane == (int)d) cnt += (unsigned)__popcll(m);
-        rem &= ~m;
-      }
-      if (valid) t->sorted[slot] = cur[u];
-    }
-#pragma unroll
-    for (int u = 0; u < PF; ++u) cur[u] = nxt[u];
-  }
-  __syncthreads();
   // prefix table: the code length at a left-aligned 32-bit window W is one
   // more than the number of lengths whose limit is <= W (limits do not
   // decrease with the length); a prefix's windows span [lo, hi]
+  constexpr unsigned kPer = (1u << kLutBits) / kCanonBlocks;
   const unsigned maxlen = lmax;
-  for (unsigned p = tid; p < (1u << kLutBits); p += 1024) {
+  for (unsigned p = blockIdx.x * kPer + tid; tid < kPer && p < (blockIdx.x + 1) * kPer; p += 256) {
     const uint64_t lo = (uint64_t)p << (32 - kLutBits);
     const uint64_t hi = lo + (1ull << (32 - kLutBits)) - 1;
     unsigned dlo = 1, dhi = 1;
@@ -2284,8 +2223,7 @@ __global__ __launch_bounds__(1024) void k_decode_tables(const uint8_t* __restric
     else e = kLutMixed | (dlo << 16) | (dhi << 22);
     t->lut[p] = e;
   }
-  __syncthreads();
-  if (tid == 0) t->valid = 1;
+  if (blockIdx.x == 0 && tid == 0) t->valid = 1;
 }
 
 // One thread per chunk, 64 chunks per wavefront, blockDim/64 wavefronts per
@@ -2790,7 +2728,10 @@ void launch_huff_header(uint8_t* out, uint32_t C, uint64_t N, uint64_t n_chunks,
 
 void launch_decode_tables(const uint8_t* cb, uint64_t n_codes, DecodeTables* t,
                           unsigned* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(1024), 0, s, cb, n_codes, t, status);
+  hipLaunchKernelGGL(k_dt_count, dim3(kCanonBlocks), dim3(256), 0, s, cb, (uint32_t)n_codes, t,
+                     status);
+  hipLaunchKernelGGL(k_dt_rank, dim3(kCanonBlocks), dim3(256), 0, s, cb, (uint32_t)n_codes, t,
+                     status);
 }
 
 namespace {
