@@ -15,8 +15,11 @@
 //    every available node of weight <= t is taken in this round by a parallel
 //    merge of the two sorted queues.  The threshold at least doubles every
 //    two rounds, so the round count is logarithmic in the total weight.
-//    Depths come from pointer jumping; lengths above 32 halve the
-//    frequencies and rebuild.  Codes are canonical (RFC 1951 construction).
+//    Depths come from walking the rounds backwards; lengths above 32 halve
+//    the frequencies and rebuild.  Codes are canonical (RFC 1951
+//    construction), assigned on many blocks (k_canon_count / k_canon_rank:
+//    each wavefront a run of the symbols with its count of each length in
+//    one lane; the batched form assigns them in its one workgroup).
 //  * chunk lengths and layout: one wavefront per chunk sums the code lengths
 //    (and, in a compression, counts the escape symbols per chunk and lane);
 //    an exclusive scan of the chunk word counts over many blocks gives the
@@ -27,6 +30,9 @@
 //    (k_encode).  A wave prefix scan of code lengths gives each lane its bit
 //    offset; codes are OR-ed MSB-first into the chunk's 32-bit words in LDS,
 //    then stored coalesced.
+//  * decoding tables: the same runs on many blocks (k_dt_count / k_dt_rank)
+//    validate the codebook section and build the per-length tables, the
+//    (length, symbol)-ordered symbols and the prefix table.
 //  * decode: one thread per chunk; a 12-bit prefix table in LDS gives the
 //    code length shared by all codes under a prefix (or the lengths to test
 //    against the canonical limits when several share it), and the code's
