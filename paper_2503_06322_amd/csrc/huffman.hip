@@ -345,11 +345,10 @@ static_assert(sizeof(CbBig) >= 2 * kDict, "depth and length bytes fit the merge 
 struct CbSmem {
   unsigned round_lo[kMaxRounds];
   unsigned sm32[16];
-  unsigned m, li, ii, nI, la, ib, n, flag, lastw, rounds, cntL, cntI;
+  unsigned m, li, ii, nI, lastw, rounds, cntL, cntI;
   unsigned long long t;
   unsigned lcount[34];
   unsigned lfirst[34];
-  unsigned lbase[34];
   unsigned wl[16][34];
 };
 
